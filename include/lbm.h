@@ -1,0 +1,224 @@
+/*
+ * lbm.h -- C ABI of the multiscale two-component D3Q19 lattice-Boltzmann step
+ * for AMD Instinct MI355X (gfx950).
+ *
+ * The model (paper: "Enhanced numerical models for two-component fluid flow in
+ * multiscale porous structures", Sec. II):
+ *   - LB equation on D3Q19 with a collision projected on the Hermite space and
+ *     the exact-difference force term, Eqs. (2)-(3);
+ *   - Shan-Chen pseudo-potential inter-component force;
+ *   - CSF surface-tension control, Eq. (4), in under-resolved (gray) voxels;
+ *   - the under-resolved-region force of Eq. (1): capillary term
+ *     -Pc(Sw) rho_r n H and Brinkman resistance rho nu / (K0(phi) Kr(Sw)) rho_r u,
+ *     taken semi-implicitly;
+ *   - residual-component model (Sec. II, Fig. 6): trapped water/oil amounts read
+ *     off the J-scaled (Eq. (5)) Pc-Sw curve at Pc^{ref,max} / Pc^{ref,min};
+ *   - tensorial resistivity, Eqs. (6)-(7), principal axes from the Hessian and
+ *     gradient of the porosity field.
+ *
+ * Conventions shared by every call
+ *   - Grid: nx * ny * nz voxels, periodic in all directions.  Linear voxel index
+ *     v = x + nx * (y + ny * z) (x fastest).  All host arrays are in that order.
+ *   - Components: 0 = water (w), 1 = oil (o).  ncomp = 1 runs water only.
+ *   - Voxel classes: LBM_PORE (resolved fluid, phi = 1), LBM_SOLID,
+ *     LBM_GRAY (under-resolved porous medium, 0 < phi < 1).
+ *   - Velocity set (D3Q19), direction order i = 0..18:
+ *       (0,0,0),
+ *       (+1,0,0) (-1,0,0) (0,+1,0) (0,-1,0) (0,0,+1) (0,0,-1),
+ *       (+1,+1,0) (-1,-1,0) (+1,-1,0) (-1,+1,0) (+1,0,+1) (-1,0,-1)
+ *       (+1,0,-1) (-1,0,+1) (0,+1,+1) (0,-1,-1) (0,+1,-1) (0,-1,+1);
+ *     directions 2k-1 and 2k are opposite.
+ *   - Every function returns an lbm_status (0 = LBM_OK).  No exception crosses
+ *     the ABI.  On error, lbm_last_error() describes the cause.  A handle is not
+ *     thread-safe; calls on one handle must not overlap.
+ *   - Device work is enqueued on params.stream (a hipStream_t; NULL = the null
+ *     stream).  Calls that hand data to the host synchronise that stream.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum lbm_status {
+  LBM_OK = 0,
+  LBM_E_INVAL = -1,       /* invalid argument (range, monotonicity, size) */
+  LBM_E_NOMEM = -2,       /* device allocation failed (hook returned NULL) */
+  LBM_E_DEVICE = -3,      /* HIP runtime error (launch, copy, no device) */
+  LBM_E_STATE = -4,       /* call out of order (e.g. step before init) */
+  LBM_E_NONFINITE = -5,   /* a diagnostic step found NaN/Inf in the state */
+  LBM_E_UNSUPPORTED = -6  /* valid request this build does not implement */
+} lbm_status;
+
+enum { LBM_PORE = 0, LBM_SOLID = 1, LBM_GRAY = 2 };
+enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1 };
+enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
+enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
+
+#define LBM_TABLE_N 1025 /* samples of every constitutive curve on [0, 1] */
+#define LBM_MAX_TYPES 256
+
+/* Model and run parameters.  Fill with lbm_params_default() first. */
+typedef struct lbm_params {
+  int32_t nx, ny, nz;     /* grid size, each >= 1 */
+  int32_t ncomp;          /* 1 or 2 */
+  int32_t precision;      /* LBM_PREC_F64 | LBM_PREC_F32: storage and arithmetic */
+  int32_t collision;      /* LBM_COLL_REGULARIZED (Hermite-projected) | LBM_COLL_BGK */
+  double tau[2];          /* relaxation times (water, oil), > 1/2; nu = (tau - 1/2) / 3 */
+  double G;               /* pseudo-potential coupling, F^a = -G rho^a sum_i w_i psi^b(x+c_i) c_i */
+  double g[2][3];         /* body acceleration per component, force = rho^a g^a */
+  double kappa;           /* CSF coefficient of Eq. (4) */
+  int32_t csf_region;     /* LBM_CSF_GRAY (paper) | LBM_CSF_ALL (calibration runs) */
+  int32_t tensor;         /* 1: tensorial resistivity, Eqs. (6)-(7); 0: scalar K0 */
+  double phi_max, phi_avg;/* characteristic values of Eq. (4) */
+  double m_minor;         /* bulk minority density (residual trap keeps rho^a >= m) */
+  double s_min, s_max;    /* saturation normalisation: S = clamp((s - s_min)/(s_max - s_min)) */
+  double wall_dpsi[2];    /* wettability: a solid neighbour enters the pseudo-potential
+                             sum with max(rho^b(x) + wall_dpsi[b], 0); (+, -) is water-wet */
+  double kr_min;          /* floor of Kr in the resistance */
+  double c_max, c_min;    /* Pc^{ref,max} = c_max Pc_PM, Pc^{ref,min} = c_min Pc_PM */
+  double hyst;            /* residual event hysteresis h: events at S >= 1/2+h / S <= 1/2-h */
+  double eps_n;           /* |grad rho| below which the CSF normal is zero */
+  double sigma_s;         /* Gaussian smoothing std of phi for the principal axes */
+  int32_t smooth_radius;  /* smoothing stencil radius (<= 8) */
+  int32_t outlet_x;       /* outlet flux plane between x_f and x_f + 1 (0 <= x_f < nx) */
+  double eps_g, eps_H;    /* isotropic gate: max|lambda| <= eps_H and |grad| <= eps_g */
+  double delta_tie;       /* tie-break: |l2| - |l1| <= delta_tie |l3| uses the gradient */
+  int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
+  int32_t track_flux;     /* 1: accumulate the outlet flux every step */
+  /* device allocator hook (NULL = hipMalloc/hipFree); ctx is passed through */
+  void *(*alloc)(size_t bytes, void *ctx);
+  void (*free)(void *ptr, void *ctx);
+  void *alloc_ctx;
+  void *stream;           /* hipStream_t the library enqueues on */
+} lbm_params;
+
+/* One pore type of the constitutive library (paper, Sec. I step ii; Appendix).
+ * Each curve holds LBM_TABLE_N uniform samples on [0, 1] and is evaluated by
+ * linear interpolation.  K0 is sampled in phi, the others in water saturation.
+ * Requirements (else LBM_E_INVAL): all finite, K0 > 0, Pc non-increasing,
+ * Krw non-decreasing, Kro non-increasing, Kr in [0, 1], 0 < phi_ref < 1,
+ * Pc_PM > 0, kd > 0. */
+typedef struct lbm_pore_table {
+  double K0[LBM_TABLE_N];
+  double Pc[LBM_TABLE_N];
+  double Krw[LBM_TABLE_N];
+  double Kro[LBM_TABLE_N];
+  double phi_ref;  /* reference porosity of the Pc curve (Leverett-J scaling, Eq. (5)) */
+  double Pc_PM;    /* critical (entry) pressure of the type */
+  double kd[3];    /* principal permeability multipliers a_k (K^D = a_k K0, Eq. (7)),
+                      first along the axis of least porosity curvature */
+} lbm_pore_table;
+
+/* Field output.  NULL pointers skip a field.  on_device = 0: host arrays of
+ * N doubles; on_device = 1: device arrays of N values of the storage type
+ * (double for LBM_PREC_F64, float for LBM_PREC_F32).  Values are at the current
+ * time level: densities, the velocity u = (rho I + R/2)^-1 (m + F_ex/2),
+ * residual-inclusive saturation S and residual amounts; zero in solid voxels. */
+typedef struct lbm_fields {
+  int32_t on_device;
+  void *rho_w, *rho_o, *ux, *uy, *uz, *S, *r_w, *r_o;
+} lbm_fields;
+
+/* Global diagnostics, reduced in fp64. */
+typedef struct lbm_diag {
+  double mass_w, mass_o;  /* mobile + residual mass per component */
+  double sw;              /* sum(phi S) / sum(phi) over fluid voxels */
+  double q_w, q_o;        /* outlet flux of the last step per component */
+  double q_acc_w, q_acc_o;/* outlet flux accumulated since init */
+  double max_u;           /* max |u| */
+  int64_t step;           /* steps taken since init */
+  int32_t nonfinite;      /* 1 if any population or velocity is NaN/Inf */
+  int32_t pad_;
+} lbm_diag;
+
+/* Per-kernel device time, recorded with HIP events when profiling is on. */
+typedef struct lbm_kernel_times {
+  double step_ms;   int64_t step_launches;   /* fused collide-stream kernel */
+  double aux_ms;    int64_t aux_launches;    /* density / normal passes */
+  double other_ms;  int64_t other_launches;  /* flux, diagnostics */
+} lbm_kernel_times;
+
+typedef struct lbm_handle lbm_handle;
+
+/* Fills p with the defaults (32^3, two components, fp64, regularised, tau = 1,
+ * G = 3, no force, kappa = 0, gray CSF region, scalar resistivity, the
+ * G = 3 coexistence constants, kr_min = 1e-4, c_max = 3.5, c_min = 0.575,
+ * h = 0.05, sigma_s = 1.5, radius 5, eps = 1e-6, delta_tie = 0.05, outlet at
+ * nx - 1, flux tracking on, no hooks, null stream).  Never fails. */
+void lbm_params_default(lbm_params *p);
+
+/* Host-only validation of p (no device call).  Writes a message to msg (may
+ * be NULL).  Returns LBM_OK or LBM_E_INVAL / LBM_E_UNSUPPORTED. */
+int lbm_validate_params(const lbm_params *p, char *msg, size_t msglen);
+
+/* Validates p, allocates the device state through the hook and returns a new
+ * handle in *out (NULL on failure).  The library owns its device memory until
+ * lbm_destroy.  Errors: LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE. */
+int lbm_create(const lbm_params *p, lbm_handle **out);
+
+/* Copies the geometry in (host arrays of N values owned by the caller):
+ * cls (LBM_PORE/LBM_SOLID/LBM_GRAY), phi (in (0,1) on gray voxels, ignored
+ * elsewhere), pore_type (< ntab on gray voxels) and ntab pore tables; then runs
+ * the per-voxel setup on the device: K0(phi), the Leverett-J factor
+ * s_J = sqrt((K0_ref/phi_ref) / (K0/phi)), the residual saturations theta_w,
+ * theta_o and, with tensor = 1, the inverse permeability tensors.
+ * Invalidates the fluid state (lbm_init_fluid is needed again).
+ * Errors: LBM_E_INVAL (codes, ranges, table shape), LBM_E_DEVICE. */
+int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double *phi,
+                     const uint8_t *pore_type, const lbm_pore_table *tabs, int32_t ntab);
+
+/* Sets every fluid voxel to the rest equilibrium of the given densities
+ * (host arrays of N doubles; rho_o ignored for ncomp = 1), clears the residual
+ * store, sets the side flag of gray voxels to [S >= 1/2] and the step counter
+ * and flux accumulators to zero.  Errors: LBM_E_STATE (no geometry),
+ * LBM_E_INVAL (non-finite or non-positive density on a fluid voxel). */
+int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *rho_o);
+
+/* Advances n >= 0 time steps, asynchronously on the stream.  Every
+ * params.diag_every steps it synchronises and returns LBM_E_NONFINITE if the
+ * state holds NaN/Inf.  Errors: LBM_E_STATE (no fluid state), LBM_E_DEVICE. */
+int lbm_step(lbm_handle *h, int64_t n);
+
+/* Evaluates the fields at the current time level (see lbm_fields) and writes
+ * them; synchronises the stream for host outputs. */
+int lbm_get_fields(lbm_handle *h, const lbm_fields *out);
+
+/* Computes the global diagnostics of the current state; synchronises. */
+int lbm_get_diagnostics(lbm_handle *h, lbm_diag *out);
+
+/* Per-voxel setup values (host arrays of N doubles, NULL skips): K0, s_J,
+ * theta_w, theta_o, and the inverse permeability as 6 arrays of N in the
+ * order xx, yy, zz, xy, xz, yz (K0inv6 may be NULL; zero outside gray). */
+int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
+                  double *theta_o, double *K0inv6);
+
+/* Checkpoint.  The state blob holds a header, the post-streaming populations
+ * f[a][i][v] (storage type), the residual amounts r[a][v] and the side flags
+ * (one byte per voxel).  lbm_state_size gives its size in bytes; get/set copy
+ * it to/from a host buffer of exactly that size.  Resuming is bitwise exact. */
+int lbm_state_size(const lbm_handle *h, size_t *bytes);
+int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
+int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
+
+/* Profiling: when on, each launch is bracketed by HIP events on the stream;
+ * lbm_get_kernel_times synchronises and returns the accumulated device time
+ * since the last reset.  Off by default. */
+int lbm_set_profiling(lbm_handle *h, int32_t on);
+int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset);
+
+/* Description of the last error on h (or of the last failed lbm_create when
+ * h is NULL).  Valid until the next call on h. */
+const char *lbm_last_error(const lbm_handle *h);
+
+/* Frees the device state (through the hook) and the handle.  NULL is a no-op. */
+void lbm_destroy(lbm_handle *h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

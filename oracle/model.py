@@ -12,7 +12,8 @@ post-streaming population set at time n.  One step (Eq. (2)) is:
 2. stencils      isotropic gradient grad X = (1/cs^2) sum_i w_i X(x+c_i) c_i with
                  a solid neighbour taking the value X(x); pseudo-potential
                  force F_SC^a = -G rho^a sum_i w_i psi^b(x+c_i) c_i (b the
-                 other component, psi = rho on fluid, psi_wall on solid);
+                 other component; psi = rho on fluid; a solid neighbour takes
+                 the local value plus a wetting offset, max(rho^b(x) + dpsi^b, 0));
                  CSF force of Eq. (4) with phi^a = rho^b, n^a = grad rho^b / |.|,
                  curvature -div n^a, in the configured region (gray);
 3. gray voxels   Eq. (1): capillary force -Pc(S) rho_r^a n H, read as
@@ -209,12 +210,12 @@ class Oracle:
             S_hat = np.where(fl, (rho[0] / safe - p.s_min) / span, 0.0)
             out.update(S=np.where(fl, S, 0.0), S_hat=S_hat, rhoT=tw + to)
             # pseudo-potential inter-component force
-            psi_wall = p.psi_wall
             for a in range(2):
                 b = 1 - a
                 acc = np.zeros((3,) + self.shape)
+                wall = np.maximum(rho[b] + p.wall_dpsi[b], 0.0)
                 for i in range(1, Q):
-                    psi = np.where(self.nb_solid[i], psi_wall[b], _sh(rho[b], C[i]))
+                    psi = np.where(self.nb_solid[i], wall, _sh(rho[b], C[i]))
                     for d in range(3):
                         if C[i, d]:
                             acc[d] += W[i] * C[i, d] * psi

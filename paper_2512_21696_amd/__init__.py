@@ -1,0 +1,338 @@
+"""Python binding of the gfx950 multiscale two-component D3Q19 library.
+
+Argument marshalling only: every step of the method runs in the HIP kernels of
+``liblbm.so`` behind the C ABI declared in ``include/lbm.h``.  PyTorch supplies
+device memory (its caching allocator is passed in as the allocator hook) and
+the stream (the current torch stream).  There is no CPU fallback: importing
+this package without the built library, or creating a handle without a GPU,
+raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblbm.so")
+
+LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, \
+    LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVICE",
+          -4: "LBM_E_STATE", -5: "LBM_E_NONFINITE", -6: "LBM_E_UNSUPPORTED"}
+PREC = {"f64": 0, "f32": 1}
+COLL = {"regularized": 0, "bgk": 1}
+REGION = {"gray": 0, "all": 1}
+TABLE_N = 1025
+
+ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p)
+
+
+class lbm_params(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+        ("ncomp", ctypes.c_int32), ("precision", ctypes.c_int32), ("collision", ctypes.c_int32),
+        ("tau", ctypes.c_double * 2), ("G", ctypes.c_double), ("g", (ctypes.c_double * 3) * 2),
+        ("kappa", ctypes.c_double), ("csf_region", ctypes.c_int32), ("tensor", ctypes.c_int32),
+        ("phi_max", ctypes.c_double), ("phi_avg", ctypes.c_double), ("m_minor", ctypes.c_double),
+        ("s_min", ctypes.c_double), ("s_max", ctypes.c_double), ("wall_dpsi", ctypes.c_double * 2),
+        ("kr_min", ctypes.c_double), ("c_max", ctypes.c_double), ("c_min", ctypes.c_double),
+        ("hyst", ctypes.c_double), ("eps_n", ctypes.c_double), ("sigma_s", ctypes.c_double),
+        ("smooth_radius", ctypes.c_int32), ("outlet_x", ctypes.c_int32),
+        ("eps_g", ctypes.c_double), ("eps_H", ctypes.c_double), ("delta_tie", ctypes.c_double),
+        ("diag_every", ctypes.c_int32), ("track_flux", ctypes.c_int32),
+        ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
+        ("stream", ctypes.c_void_p),
+    ]
+
+
+class lbm_pore_table(ctypes.Structure):
+    _fields_ = [("K0", ctypes.c_double * TABLE_N), ("Pc", ctypes.c_double * TABLE_N),
+                ("Krw", ctypes.c_double * TABLE_N), ("Kro", ctypes.c_double * TABLE_N),
+                ("phi_ref", ctypes.c_double), ("Pc_PM", ctypes.c_double),
+                ("kd", ctypes.c_double * 3)]
+
+
+class lbm_fields(ctypes.Structure):
+    _fields_ = [("on_device", ctypes.c_int32)] + [
+        (k, ctypes.c_void_p) for k in ("rho_w", "rho_o", "ux", "uy", "uz", "S", "r_w", "r_o")]
+
+
+class lbm_diag(ctypes.Structure):
+    _fields_ = [(k, ctypes.c_double) for k in ("mass_w", "mass_o", "sw", "q_w", "q_o", "q_acc_w",
+                                                "q_acc_o", "max_u")] + [
+        ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
+class lbm_kernel_times(ctypes.Structure):
+    _fields_ = [("step_ms", ctypes.c_double), ("step_launches", ctypes.c_int64),
+                ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
+                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64)]
+
+
+EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_geometry",
+           "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
+           "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
+           "lbm_get_kernel_times", "lbm_last_error", "lbm_destroy"]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Loads liblbm.so; raises when it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with __graft_entry__.build() or "
+                          f"python paper_2512_21696_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
+    dp, u8p = P(ctypes.c_double), P(ctypes.c_uint8)
+    sig = {
+        "lbm_params_default": (None, [P(lbm_params)]),
+        "lbm_validate_params": (ctypes.c_int, [P(lbm_params), ctypes.c_char_p, sz]),
+        "lbm_create": (ctypes.c_int, [P(lbm_params), P(vp)]),
+        "lbm_set_geometry": (ctypes.c_int, [vp, u8p, dp, u8p, P(lbm_pore_table), i32]),
+        "lbm_init_fluid": (ctypes.c_int, [vp, dp, dp]),
+        "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_get_fields": (ctypes.c_int, [vp, P(lbm_fields)]),
+        "lbm_get_diagnostics": (ctypes.c_int, [vp, P(lbm_diag)]),
+        "lbm_get_setup": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
+        "lbm_state_size": (ctypes.c_int, [vp, P(sz)]),
+        "lbm_get_state": (ctypes.c_int, [vp, vp, sz]),
+        "lbm_set_state": (ctypes.c_int, [vp, vp, sz]),
+        "lbm_set_profiling": (ctypes.c_int, [vp, i32]),
+        "lbm_get_kernel_times": (ctypes.c_int, [vp, P(lbm_kernel_times), i32]),
+        "lbm_last_error": (ctypes.c_char_p, [vp]),
+        "lbm_destroy": (None, [vp]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class LbmError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS.get(code, code)}: {msg}")
+        self.code = code
+
+
+def lbm_params_default() -> lbm_params:
+    p = lbm_params()
+    load_library().lbm_params_default(ctypes.byref(p))
+    return p
+
+
+def to_c_params(params) -> lbm_params:
+    """workloads.Params (or any object with the same attribute names) -> lbm_params."""
+    p = lbm_params_default()
+    p.nx, p.ny, p.nz = int(params.nx), int(params.ny), int(params.nz)
+    p.ncomp = int(params.ncomp)
+    p.precision = PREC[params.precision]
+    p.collision = COLL[params.collision]
+    for a in range(2):
+        p.tau[a] = float(params.tau[a] if a < len(params.tau) else 1.0)
+        for d in range(3):
+            p.g[a][d] = float(params.g[a][d])
+        p.wall_dpsi[a] = float(params.wall_dpsi[a])
+    p.G = float(params.G)
+    p.kappa = float(params.kappa)
+    p.csf_region = REGION[params.csf_region]
+    p.tensor = int(bool(params.tensor))
+    for k in ("phi_max", "phi_avg", "m_minor", "s_min", "s_max", "kr_min", "c_max", "c_min",
+              "hyst", "eps_n", "sigma_s", "eps_g", "eps_H", "delta_tie"):
+        setattr(p, k, float(getattr(params, k)))
+    p.smooth_radius = int(params.smooth_radius)
+    p.outlet_x = int(params.outlet_x)
+    p.diag_every = int(getattr(params, "diag_every", 0))
+    p.track_flux = int(getattr(params, "track_flux", 1))
+    return p
+
+
+def to_c_tables(tables):
+    arr = (lbm_pore_table * max(len(tables), 1))()
+    for k, t in enumerate(tables):
+        for name in ("K0", "Pc", "Krw", "Kro"):
+            a = np.ascontiguousarray(t[name], dtype=np.float64)
+            if a.shape != (TABLE_N,):
+                raise ValueError(f"table {k} curve {name} must hold {TABLE_N} samples")
+            ctypes.memmove(getattr(arr[k], name), a.ctypes.data, a.nbytes)
+        arr[k].phi_ref = float(t["phi_ref"])
+        arr[k].Pc_PM = float(t["Pc_PM"])
+        for d in range(3):
+            arr[k].kd[d] = float(t["kd"][d])
+    return arr
+
+
+class Lbm:
+    """A handle of the C library.  Methods carry the ABI's names without the
+    ``lbm_`` prefix and only marshal arguments."""
+
+    def __init__(self, params, use_torch_memory: bool = True):
+        import torch
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU: the library has no CPU path")
+        self.lib = load_library()
+        self.params = params
+        self.torch = torch
+        cp = to_c_params(params)
+        self.device = torch.cuda.current_device()
+        self.stream = torch.cuda.current_stream()
+        cp.stream = self.stream.cuda_stream
+        self._cbs = None
+        if use_torch_memory:
+            dev, st = self.device, self.stream.cuda_stream
+
+            def _alloc(nbytes, ctx):
+                try:
+                    return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, st))
+                except Exception:
+                    return None
+
+            def _free(ptr, ctx):
+                torch.cuda.caching_allocator_delete(int(ptr))
+
+            self._cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+            cp.alloc, cp.free = self._cbs
+        self.c_params = cp
+        h = ctypes.c_void_p()
+        rc = self.lib.lbm_create(ctypes.byref(cp), ctypes.byref(h))
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_last_error(None).decode())
+        self.h = h
+        self.N = int(params.nx) * int(params.ny) * int(params.nz)
+        self.shape = (int(params.nz), int(params.ny), int(params.nx))
+
+    def _check(self, rc):
+        if rc != LBM_OK:
+            raise LbmError(rc, self.lib.lbm_last_error(self.h).decode())
+
+    def destroy(self):
+        if getattr(self, "h", None):
+            self.lib.lbm_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ calls
+    def set_geometry(self, cls, phi, pore_type, tables):
+        cls = np.ascontiguousarray(cls, dtype=np.uint8).reshape(-1)
+        phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
+        pt = np.ascontiguousarray(pore_type, dtype=np.uint8).reshape(-1)
+        assert cls.size == self.N and phi.size == self.N and pt.size == self.N
+        tabs = to_c_tables(tables)
+        self._check(self.lib.lbm_set_geometry(
+            self.h, cls.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+            phi.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+            pt.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)), tabs, len(tables)))
+
+    def init_fluid(self, rho_w, rho_o=None):
+        rw = np.ascontiguousarray(rho_w, dtype=np.float64).reshape(-1)
+        ro = rw if rho_o is None else np.ascontiguousarray(rho_o, dtype=np.float64).reshape(-1)
+        assert rw.size == self.N and ro.size == self.N
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.lbm_init_fluid(self.h, rw.ctypes.data_as(dp), ro.ctypes.data_as(dp)))
+
+    def step(self, n=1):
+        self._check(self.lib.lbm_step(self.h, int(n)))
+
+    FIELD_NAMES = ("rho_w", "rho_o", "ux", "uy", "uz", "S", "r_w", "r_o")
+
+    def get_fields(self, names=FIELD_NAMES):
+        """Host fp64 arrays shaped [z, y, x]."""
+        out = {k: np.zeros(self.N, np.float64) for k in names}
+        f = lbm_fields()
+        f.on_device = 0
+        for k in self.FIELD_NAMES:
+            setattr(f, k, out[k].ctypes.data if k in out else None)
+        self._check(self.lib.lbm_get_fields(self.h, ctypes.byref(f)))
+        return {k: v.reshape(self.shape) for k, v in out.items()}
+
+    def get_fields_device(self, tensors: dict):
+        """Writes into caller device tensors (storage dtype, N elements each)."""
+        f = lbm_fields()
+        f.on_device = 1
+        for k in self.FIELD_NAMES:
+            t = tensors.get(k)
+            setattr(f, k, t.data_ptr() if t is not None else None)
+        self._check(self.lib.lbm_get_fields(self.h, ctypes.byref(f)))
+
+    def get_diagnostics(self) -> dict:
+        d = lbm_diag()
+        self._check(self.lib.lbm_get_diagnostics(self.h, ctypes.byref(d)))
+        return {k: getattr(d, k) for k, _ in lbm_diag._fields_ if k != "pad_"}
+
+    def get_setup(self):
+        arrs = [np.zeros(self.N) for _ in range(4)] + [np.zeros(6 * self.N)]
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.lbm_get_setup(self.h, *[a.ctypes.data_as(dp) for a in arrs]))
+        K0, sJ, thw, tho, Kinv = arrs
+        return dict(K0=K0.reshape(self.shape), sJ=sJ.reshape(self.shape),
+                    thw=thw.reshape(self.shape), tho=tho.reshape(self.shape),
+                    Kinv=Kinv.reshape((6,) + self.shape))
+
+    def state_size(self) -> int:
+        n = ctypes.c_size_t()
+        self._check(self.lib.lbm_state_size(self.h, ctypes.byref(n)))
+        return n.value
+
+    def get_state(self) -> bytes:
+        n = self.state_size()
+        buf = ctypes.create_string_buffer(n)
+        self._check(self.lib.lbm_get_state(self.h, buf, n))
+        return buf.raw
+
+    def set_state(self, blob: bytes):
+        buf = ctypes.create_string_buffer(blob, len(blob))
+        self._check(self.lib.lbm_set_state(self.h, buf, len(blob)))
+
+    def state_arrays(self, blob: bytes) -> dict:
+        """Splits a state blob into the post-streaming populations, residual
+        amounts and side flags (views on a copy)."""
+        hdr = 8 + 4 + 4 + 4 * 4 + 8 + 4 * 8
+        es = 8 if self.params.precision == "f64" else 4
+        dt = np.float64 if es == 8 else np.float32
+        nc = int(self.params.ncomp)
+        nf = nc * 19 * self.N
+        raw = np.frombuffer(blob, dtype=np.uint8)
+        f = raw[hdr:hdr + nf * es].view(dt).reshape((nc, 19) + self.shape)
+        off = hdr + nf * es
+        r = raw[off:off + 2 * self.N * es].view(dt).reshape((2,) + self.shape)
+        side = raw[off + 2 * self.N * es:].reshape(self.shape)
+        return dict(f=f, r=r, side=side)
+
+    def set_profiling(self, on: bool):
+        self._check(self.lib.lbm_set_profiling(self.h, int(bool(on))))
+
+    def get_kernel_times(self, reset=False) -> dict:
+        t = lbm_kernel_times()
+        self._check(self.lib.lbm_get_kernel_times(self.h, ctypes.byref(t), int(bool(reset))))
+        return {k: getattr(t, k) for k, _ in lbm_kernel_times._fields_}
+
+
+def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
+    return Lbm(params, use_torch_memory)
+
+
+def make_state_blob(lbm: Lbm, f, r, side, step=0, q_last=(0.0, 0.0), q_acc=(0.0, 0.0)) -> bytes:
+    """Builds a state blob (the ABI's checkpoint format) from post-streaming
+    populations f[a][i][z][y][x], residual amounts r[2][z][y][x] and side flags."""
+    import struct
+    p = lbm.params
+    dt = np.float64 if p.precision == "f64" else np.float32
+    hdr = struct.pack("<QIIiiiiq4d", 0x4C424D3251313953, 1, PREC[p.precision], int(p.nx),
+                      int(p.ny), int(p.nz), int(p.ncomp), int(step), q_last[0], q_last[1],
+                      q_acc[0], q_acc[1])
+    return (hdr + np.ascontiguousarray(f, dt).tobytes() + np.ascontiguousarray(r, dt).tobytes()
+            + np.ascontiguousarray(side, np.uint8).tobytes())

@@ -1,0 +1,53 @@
+// Internal declarations shared by the host runtime and the device kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <stddef.h>
+
+namespace lbm {
+
+constexpr int Q = 19;
+constexpr int TABLE_N = 1025;
+
+// per-voxel mask word: bit i (0..18) set when x + c_i is a solid voxel;
+// class code in bits 24..25.
+constexpr uint32_t CLASS_SHIFT = 24;
+constexpr uint32_t CLASS_MASK = 3u << CLASS_SHIFT;
+constexpr uint32_t SOLID_CODE = 1u;
+constexpr uint32_t GRAY_CODE = 2u;
+
+// Scalars of one run, converted once on the host.
+struct ModelConsts {
+  int nx, ny, nz;
+  long long N;
+  int ncomp, collision, csf_all, tensor;
+  double tau[2], omega[2], nu[2];
+  double G;
+  double g[2][3];
+  double kappa, csf_scale;  // csf_scale = 1 / (phi_avg phi_max)
+  double m_minor, s_min, inv_span;
+  double wall_dpsi[2];
+  double kr_min, hyst, eps_n;
+  int outlet_x;
+};
+
+// Device buffers of one run (storage type T is float or double).
+template <typename T>
+struct DevState {
+  T *f[2];           // populations, two copies; layout [a][i][v]
+  T *rho;            // densities at the current level [a][v]
+  T *nrm;            // CSF normals [a][3][v] (only when kappa != 0)
+  uint32_t *mask;    // neighbour-solid bits and class
+  uint8_t *ptype;    // pore type per voxel
+  T *K0, *sJ, *thw, *tho;  // gray constitutive values [v]
+  T *Kinv;           // inverse permeability [6][v] (tensor runs)
+  T *r;              // residual amounts [2][v]
+  T *phiT;           // porosity per voxel (1 pore, 0 solid) for diagnostics
+  uint8_t *side;     // residual side flag (1 = water)
+  T *tab;            // pore tables [type][curve][TABLE_N], curves Pc, Krw, Kro
+  double *partial;   // block partials for reductions
+  double *acc;       // device accumulators: q_last[2], q_acc[2]
+};
+
+}  // namespace lbm

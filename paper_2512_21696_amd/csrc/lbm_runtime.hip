@@ -1,0 +1,774 @@
+// Host runtime of the C ABI: handle, device memory through the allocator hook,
+// launch sequencing on the caller's stream, checkpoints and diagnostics.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_kernels.hip"
+#include "lbm_validate.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+constexpr uint64_t kStateMagic = 0x4C424D3251313953ull;  // "LBM2Q19S"
+constexpr uint32_t kStateVersion = 1;
+
+struct StateHeader {
+  uint64_t magic;
+  uint32_t version, precision;
+  int32_t nx, ny, nz, ncomp;
+  int64_t step;
+  double q_last[2], q_acc[2];
+};
+
+struct EventPair {
+  hipEvent_t a, b;
+  int kind;
+};
+
+}  // namespace
+
+struct lbm_handle {
+  lbm_params p{};
+  ModelConsts mc{};
+  hipStream_t st = nullptr;
+  std::string err;
+  size_t es = 8;
+  long long N = 0;
+  int cur = 0;
+  int ntab = 0;
+  bool has_geom = false, has_fluid = false, rho_valid = false;
+  int64_t step = 0;
+  DevState<double> sd{};
+  DevState<float> sf{};
+  std::vector<void *> geom_allocs;  // freed when a new geometry comes in
+  std::vector<void *> allocs;
+  std::vector<uint8_t> geom_cls;   // host copy of the classes (density validation)
+  // profiling
+  bool prof = false;
+  std::vector<EventPair> ev_pool, ev_live;
+  double t_ms[3] = {0, 0, 0};
+  int64_t t_n[3] = {0, 0, 0};
+};
+
+namespace {
+
+int set_err(lbm_handle *h, int code, const std::string &msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+int hip_check(lbm_handle *h, hipError_t e, const char *what) {
+  if (e == hipSuccess) return LBM_OK;
+  return set_err(h, LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+void *dev_alloc(lbm_handle *h, size_t bytes) {
+  if (bytes == 0) bytes = 256;
+  void *p = nullptr;
+  if (h->p.alloc) {
+    p = h->p.alloc(bytes, h->p.alloc_ctx);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  return p;
+}
+
+void dev_free(lbm_handle *h, void *p) {
+  if (!p) return;
+  if (h->p.free) h->p.free(p, h->p.alloc_ctx);
+  else (void)hipFree(p);
+}
+
+template <typename T>
+T *alloc_into(lbm_handle *h, std::vector<void *> &list, size_t count, bool *ok) {
+  void *p = dev_alloc(h, count * sizeof(T));
+  if (!p) {
+    *ok = false;
+    return nullptr;
+  }
+  list.push_back(p);
+  return (T *)p;
+}
+
+// ---- profiling helpers
+void fold_events(lbm_handle *h) {
+  if (h->ev_live.empty()) return;
+  (void)hipStreamSynchronize(h->st);
+  for (auto &e : h->ev_live) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, e.a, e.b) == hipSuccess) {
+      h->t_ms[e.kind] += ms;
+      h->t_n[e.kind] += 1;
+    }
+    h->ev_pool.push_back(e);
+  }
+  h->ev_live.clear();
+}
+
+struct Timed {
+  lbm_handle *h;
+  EventPair e{};
+  bool on;
+  Timed(lbm_handle *h_, int kind) : h(h_), on(h_->prof) {
+    if (!on) return;
+    if (h->ev_live.size() >= 4096) fold_events(h);
+    if (h->ev_pool.empty()) {
+      EventPair n{};
+      (void)hipEventCreate(&n.a);
+      (void)hipEventCreate(&n.b);
+      h->ev_pool.push_back(n);
+    }
+    e = h->ev_pool.back();
+    h->ev_pool.pop_back();
+    e.kind = kind;
+    (void)hipEventRecord(e.a, h->st);
+  }
+  ~Timed() {
+    if (!on) return;
+    (void)hipEventRecord(e.b, h->st);
+    h->ev_live.push_back(e);
+  }
+};
+enum { K_STEP = 0, K_AUX = 1, K_OTHER = 2 };
+
+template <typename T>
+DevState<T> &state(lbm_handle *h);
+template <>
+DevState<double> &state<double>(lbm_handle *h) { return h->sd; }
+template <>
+DevState<float> &state<float>(lbm_handle *h) { return h->sf; }
+
+unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+int alloc_state(lbm_handle *h) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  const int nc = h->p.ncomp;
+  bool ok = true;
+  auto &L = h->allocs;
+  s.f[0] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
+  s.f[1] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
+  s.rho = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+  s.nrm = (h->p.ncomp == 2 && h->p.kappa != 0.0) ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
+  s.mask = alloc_into<uint32_t>(h, L, (size_t)N, &ok);
+  s.ptype = alloc_into<uint8_t>(h, L, (size_t)N, &ok);
+  s.K0 = alloc_into<T>(h, L, (size_t)N, &ok);
+  s.sJ = alloc_into<T>(h, L, (size_t)N, &ok);
+  s.thw = alloc_into<T>(h, L, (size_t)N, &ok);
+  s.tho = alloc_into<T>(h, L, (size_t)N, &ok);
+  s.Kinv = h->p.tensor ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
+  s.r = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+  s.phiT = alloc_into<T>(h, L, (size_t)N, &ok);
+  s.side = alloc_into<uint8_t>(h, L, (size_t)N, &ok);
+  s.tab = nullptr;
+  long long nb = std::max<long long>(blocks(N), blocks((long long)h->p.ny * h->p.nz));
+  s.partial = alloc_into<double>(h, L, (size_t)nb * 6, &ok);
+  s.acc = alloc_into<double>(h, L, 16, &ok);
+  if (!ok) return set_err(h, LBM_E_NOMEM, "device allocation failed");
+  if (hipMemsetAsync(s.acc, 0, 16 * sizeof(double), h->st) != hipSuccess)
+    return set_err(h, LBM_E_DEVICE, "hipMemsetAsync failed");
+  return LBM_OK;
+}
+
+ModelConsts make_consts(const lbm_params &p) {
+  ModelConsts mc{};
+  mc.nx = p.nx;
+  mc.ny = p.ny;
+  mc.nz = p.nz;
+  mc.N = (long long)p.nx * p.ny * p.nz;
+  mc.ncomp = p.ncomp;
+  mc.collision = p.collision;
+  mc.csf_all = p.csf_region == LBM_CSF_ALL;
+  mc.tensor = p.tensor;
+  for (int a = 0; a < 2; ++a) {
+    double tau = (a < p.ncomp) ? p.tau[a] : 1.0;
+    mc.tau[a] = tau;
+    mc.omega[a] = 1.0 / tau;
+    mc.nu[a] = (1.0 / 3.0) * (tau - 0.5);
+    for (int d = 0; d < 3; ++d) mc.g[a][d] = p.g[a][d];
+    mc.wall_dpsi[a] = p.wall_dpsi[a];
+  }
+  mc.G = p.G;
+  mc.kappa = p.ncomp == 2 ? p.kappa : 0.0;
+  mc.csf_scale = 1.0 / (p.phi_avg * p.phi_max);
+  mc.m_minor = p.m_minor;
+  mc.s_min = p.s_min;
+  mc.inv_span = 1.0 / (p.s_max - p.s_min);
+  mc.kr_min = p.kr_min;
+  mc.hyst = p.hyst;
+  mc.eps_n = p.eps_n;
+  mc.outlet_x = p.outlet_x;
+  return mc;
+}
+
+// ------------------------------------------------------------------ geometry
+template <typename T>
+int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const uint8_t *pt,
+                   const lbm_pore_table *tabs, int ntab) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  hipStream_t st = h->st;
+  for (void *p : h->geom_allocs) dev_free(h, p);
+  h->geom_allocs.clear();
+  std::vector<void *> tmp;
+  bool ok = true;
+  uint8_t *cls_d = alloc_into<uint8_t>(h, tmp, N, &ok);
+  double *phi_d = alloc_into<double>(h, tmp, N, &ok);
+  double *K0d = alloc_into<double>(h, tmp, N, &ok);
+  const int nt = ntab > 0 ? ntab : 1;
+  double *dtabs = alloc_into<double>(h, tmp, (size_t)nt * 4 * TABLE_N, &ok);
+  double *dmeta = alloc_into<double>(h, tmp, (size_t)nt * 8, &ok);
+  s.tab = alloc_into<T>(h, h->geom_allocs, (size_t)nt * 3 * TABLE_N, &ok);
+  double *sm1 = nullptr, *sm2 = nullptr, *wts = nullptr;
+  if (h->p.tensor) {
+    sm1 = alloc_into<double>(h, tmp, N, &ok);
+    sm2 = alloc_into<double>(h, tmp, N, &ok);
+    wts = alloc_into<double>(h, tmp, 32, &ok);
+  }
+  auto cleanup = [&]() {
+    (void)hipStreamSynchronize(st);
+    for (void *p : tmp) dev_free(h, p);
+  };
+  if (!ok) {
+    cleanup();
+    return set_err(h, LBM_E_NOMEM, "device allocation failed in set_geometry");
+  }
+  // host staging of tables: fp64 (setup) and storage type (step)
+  std::vector<double> htab((size_t)nt * 4 * TABLE_N, 0.0), hmeta((size_t)nt * 8, 0.0);
+  std::vector<T> htabT((size_t)nt * 3 * TABLE_N, (T)0);
+  std::vector<double> phi0;
+  for (int t = 0; t < ntab; ++t) {
+    const lbm_pore_table &tb = tabs[t];
+    for (int i = 0; i < TABLE_N; ++i) {
+      htab[(size_t)t * 4 * TABLE_N + i] = tb.K0[i];
+      htab[(size_t)t * 4 * TABLE_N + TABLE_N + i] = tb.Pc[i];
+      htab[(size_t)t * 4 * TABLE_N + 2 * TABLE_N + i] = tb.Krw[i];
+      htab[(size_t)t * 4 * TABLE_N + 3 * TABLE_N + i] = tb.Kro[i];
+      htabT[(size_t)t * 3 * TABLE_N + i] = (T)tb.Pc[i];
+      htabT[(size_t)t * 3 * TABLE_N + TABLE_N + i] = (T)tb.Krw[i];
+      htabT[(size_t)t * 3 * TABLE_N + 2 * TABLE_N + i] = (T)tb.Kro[i];
+    }
+    hmeta[t * 8 + 0] = tb.phi_ref;
+    hmeta[t * 8 + 1] = tb.Pc_PM;
+    for (int d = 0; d < 3; ++d) hmeta[t * 8 + 2 + d] = tb.kd[d];
+  }
+  const double *phi_src = phi;
+  if (!phi) {
+    phi0.assign(N, 1.0);
+    phi_src = phi0.data();
+  }
+  std::vector<uint8_t> pt0;
+  const uint8_t *pt_src = pt;
+  if (!pt) {
+    pt0.assign(N, 0);
+    pt_src = pt0.data();
+  }
+  int rc = LBM_OK;
+#define CK(x, w) \
+  if (rc == LBM_OK) rc = hip_check(h, (x), w)
+  CK(hipMemcpyAsync(cls_d, cls, N, hipMemcpyHostToDevice, st), "copy cls");
+  CK(hipMemcpyAsync(phi_d, phi_src, N * sizeof(double), hipMemcpyHostToDevice, st), "copy phi");
+  CK(hipMemcpyAsync(s.ptype, pt_src, N, hipMemcpyHostToDevice, st), "copy pore type");
+  CK(hipMemcpyAsync(dtabs, htab.data(), htab.size() * sizeof(double), hipMemcpyHostToDevice, st),
+     "copy tables");
+  CK(hipMemcpyAsync(dmeta, hmeta.data(), hmeta.size() * sizeof(double), hipMemcpyHostToDevice, st),
+     "copy table metadata");
+  CK(hipMemcpyAsync(s.tab, htabT.data(), htabT.size() * sizeof(T), hipMemcpyHostToDevice, st),
+     "copy step tables");
+  if (rc == LBM_OK) {
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_mask, dim3(blocks(N)), dim3(256), 0, st, cls_d, s.mask, h->p.nx, h->p.ny,
+                       h->p.nz, N);
+    hipLaunchKernelGGL(k_setup_gray<T>, dim3(blocks(N)), dim3(256), 0, st, phi_d, s.ptype, s.mask,
+                       dtabs, dmeta, h->p.c_max, h->p.c_min, N, s.K0, s.sJ, s.thw, s.tho, K0d,
+                       s.phiT);
+    if (h->p.tensor) {
+      const int R = h->p.smooth_radius;
+      std::vector<double> w(2 * R + 1);
+      double sum = 0.0;
+      for (int j = -R; j <= R; ++j) {
+        w[j + R] = std::exp(-(double)(j * j) / (2.0 * h->p.sigma_s * h->p.sigma_s));
+        sum += w[j + R];
+      }
+      for (double &x : w) x /= sum;
+      CK(hipMemcpyAsync(wts, w.data(), w.size() * sizeof(double), hipMemcpyHostToDevice, st),
+         "copy smoothing weights");
+      hipLaunchKernelGGL(k_base_phi, dim3(blocks(N)), dim3(256), 0, st, s.mask, phi_d, sm1, N);
+      // z, then y, then x
+      hipLaunchKernelGGL(k_smooth, dim3(blocks(N)), dim3(256), 0, st, sm1, sm2, h->p.nx, h->p.ny,
+                         h->p.nz, N, 0, R, wts);
+      hipLaunchKernelGGL(k_smooth, dim3(blocks(N)), dim3(256), 0, st, sm2, sm1, h->p.nx, h->p.ny,
+                         h->p.nz, N, 1, R, wts);
+      hipLaunchKernelGGL(k_smooth, dim3(blocks(N)), dim3(256), 0, st, sm1, sm2, h->p.nx, h->p.ny,
+                         h->p.nz, N, 2, R, wts);
+      hipLaunchKernelGGL(k_axes<T>, dim3(blocks(N)), dim3(256), 0, st, sm2, s.mask, s.ptype, K0d,
+                         dmeta, h->p.nx, h->p.ny, h->p.nz, N, h->p.eps_g, h->p.eps_H,
+                         h->p.delta_tie, s.Kinv);
+    }
+    CK(hipGetLastError(), "setup kernels");
+  }
+  CK(hipStreamSynchronize(st), "setup");
+#undef CK
+  cleanup();
+  return rc;
+}
+
+// ------------------------------------------------------------------ stepping
+template <typename T>
+void ensure_aux(lbm_handle *h) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  if (!h->rho_valid) {
+    Timed tm(h, K_AUX);
+    if (h->p.ncomp == 2)
+      hipLaunchKernelGGL((k_moments<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
+                         s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+    else
+      hipLaunchKernelGGL((k_moments<T, 1>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
+                         s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+    if (s.nrm)
+      hipLaunchKernelGGL(k_normals<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.rho, s.nrm, s.mask,
+                         h->p.nx, h->p.ny, h->p.nz, N, h->p.eps_n);
+    h->rho_valid = true;
+  }
+}
+
+template <typename T, int MODE, typename O>
+void launch_step(lbm_handle *h, const FieldsOut &fo) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  const T *fin = s.f[h->cur];
+  T *fout = s.f[1 - h->cur];
+  Timed tm(h, MODE == MODE_STEP ? K_STEP : K_OTHER);
+  if (h->p.ncomp == 2)
+    hipLaunchKernelGGL((k_step<T, 2, MODE, O>), dim3(blocks(N)), dim3(256), 0, h->st, h->mc, fin,
+                       fout, s, fo);
+  else
+    hipLaunchKernelGGL((k_step<T, 1, MODE, O>), dim3(blocks(N)), dim3(256), 0, h->st, h->mc, fin,
+                       fout, s, fo);
+}
+
+template <typename T>
+int diag_t(lbm_handle *h, lbm_diag *out) {
+  DevState<T> &s = state<T>(h);
+  ensure_aux<T>(h);
+  FieldsOut fo{};
+  launch_step<T, MODE_DIAG, T>(h, fo);
+  {
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, h->st, s.partial, (int)blocks(h->N), 6, 1,
+                       s.acc + 4, 0);
+  }
+  double acc[10];
+  int rc = hip_check(h, hipMemcpyAsync(acc, s.acc, sizeof(acc), hipMemcpyDeviceToHost, h->st),
+                     "copy diagnostics");
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "diagnostics");
+  if (rc != LBM_OK) return rc;
+  out->q_w = acc[0];
+  out->q_o = acc[1];
+  out->q_acc_w = acc[2];
+  out->q_acc_o = acc[3];
+  out->mass_w = acc[4];
+  out->mass_o = acc[5];
+  out->sw = acc[7] > 0 ? acc[6] / acc[7] : 0.0;
+  out->nonfinite = acc[8] != 0.0 || !std::isfinite(acc[4]) || !std::isfinite(acc[5]);
+  out->max_u = acc[9];
+  out->step = h->step;
+  out->pad_ = 0;
+  return LBM_OK;
+}
+
+template <typename T>
+int step_t(lbm_handle *h, int64_t n) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
+  for (int64_t k = 0; k < n; ++k) {
+    ensure_aux<T>(h);
+    launch_step<T, MODE_STEP, T>(h, FieldsOut{});
+    h->cur = 1 - h->cur;
+    h->rho_valid = false;
+    h->step += 1;
+    if (h->p.track_flux) {
+      Timed tm(h, K_OTHER);
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask, s.partial);
+      else
+        hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask, s.partial);
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, h->st, s.partial, (int)fb, 2, 0, s.acc,
+                         1);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_check(h, e, "step launch");
+    if (h->p.diag_every > 0 && h->step % h->p.diag_every == 0) {
+      lbm_diag d{};
+      int rc = diag_t<T>(h, &d);
+      if (rc != LBM_OK) return rc;
+      if (d.nonfinite)
+        return set_err(h, LBM_E_NONFINITE,
+                       "non-finite state at step " + std::to_string((long long)h->step));
+    }
+  }
+  (void)N;
+  return LBM_OK;
+}
+
+template <typename T>
+int init_t(lbm_handle *h, const double *rw, const double *ro) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  std::vector<void *> tmp;
+  bool ok = true;
+  double *rw_d = alloc_into<double>(h, tmp, N, &ok);
+  double *ro_d = alloc_into<double>(h, tmp, N, &ok);
+  if (!ok) {
+    for (void *p : tmp) dev_free(h, p);
+    return set_err(h, LBM_E_NOMEM, "device allocation failed in init_fluid");
+  }
+  int rc = hip_check(h, hipMemcpyAsync(rw_d, rw, N * 8, hipMemcpyHostToDevice, h->st), "copy rho_w");
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(ro_d, ro ? ro : rw, N * 8, hipMemcpyHostToDevice, h->st),
+                   "copy rho_o");
+  if (rc == LBM_OK) {
+    Timed tm(h, K_OTHER);
+    T *C = s.f[1 - h->cur];
+    hipLaunchKernelGGL(k_equilibrium_rest<T>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d, ro_d, C,
+                       s.mask, N, h->p.ncomp);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur], s.mask,
+                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+  }
+  h->rho_valid = false;
+  if (rc == LBM_OK) {
+    ensure_aux<T>(h);
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_init_side<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.rho, s.mask, s.side,
+                       s.r, N, h->p.s_min, h->p.s_max - h->p.s_min);
+    rc = hip_check(h, hipMemsetAsync(s.acc, 0, 16 * sizeof(double), h->st), "clear accumulators");
+  }
+  if (rc == LBM_OK) rc = hip_check(h, hipGetLastError(), "init kernels");
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "init");
+  for (void *p : tmp) dev_free(h, p);
+  if (rc == LBM_OK) {
+    h->step = 0;
+    h->has_fluid = true;
+  }
+  return rc;
+}
+
+template <typename T>
+int fields_t(lbm_handle *h, const lbm_fields *out) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  ensure_aux<T>(h);
+  void *dst[8] = {out->rho_w, out->rho_o, out->ux, out->uy, out->uz, out->S, out->r_w, out->r_o};
+  if (out->on_device) {
+    FieldsOut fo{dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], dst[6], dst[7]};
+    launch_step<T, MODE_FIELDS, T>(h, fo);
+    return hip_check(h, hipGetLastError(), "fields kernel");
+  }
+  std::vector<void *> tmp;
+  bool ok = true;
+  void *d[8] = {nullptr};
+  for (int k = 0; k < 8; ++k)
+    if (dst[k]) d[k] = alloc_into<double>(h, tmp, N, &ok);
+  if (!ok) {
+    for (void *p : tmp) dev_free(h, p);
+    return set_err(h, LBM_E_NOMEM, "device allocation failed in get_fields");
+  }
+  FieldsOut fo{d[0], d[1], d[2], d[3], d[4], d[5], d[6], d[7]};
+  launch_step<T, MODE_FIELDS, double>(h, fo);
+  int rc = hip_check(h, hipGetLastError(), "fields kernel");
+  for (int k = 0; k < 8 && rc == LBM_OK; ++k)
+    if (dst[k])
+      rc = hip_check(h, hipMemcpyAsync(dst[k], d[k], N * 8, hipMemcpyDeviceToHost, h->st),
+                     "copy field");
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "fields");
+  for (void *p : tmp) dev_free(h, p);
+  return rc;
+}
+
+size_t state_bytes(const lbm_handle *h) {
+  const size_t N = (size_t)h->N;
+  return sizeof(StateHeader) + (size_t)h->p.ncomp * Q * N * h->es + 2 * N * h->es + N;
+}
+
+template <typename T>
+int get_state_t(lbm_handle *h, void *buf) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  T *C = s.f[1 - h->cur];
+  {
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_gather<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur], C, s.mask,
+                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+  }
+  StateHeader hd{};
+  hd.magic = kStateMagic;
+  hd.version = kStateVersion;
+  hd.precision = (uint32_t)h->p.precision;
+  hd.nx = h->p.nx;
+  hd.ny = h->p.ny;
+  hd.nz = h->p.nz;
+  hd.ncomp = h->p.ncomp;
+  hd.step = h->step;
+  double acc[4];
+  char *b = (char *)buf;
+  int rc = hip_check(h, hipMemcpyAsync(acc, s.acc, sizeof(acc), hipMemcpyDeviceToHost, h->st),
+                     "copy accumulators");
+  size_t off = sizeof(StateHeader);
+  const size_t fb = (size_t)h->p.ncomp * Q * N * sizeof(T);
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(b + off, C, fb, hipMemcpyDeviceToHost, h->st), "copy f");
+  off += fb;
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(b + off, s.r, 2 * N * sizeof(T), hipMemcpyDeviceToHost, h->st),
+                   "copy r");
+  off += 2 * N * sizeof(T);
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(b + off, s.side, N, hipMemcpyDeviceToHost, h->st), "copy side");
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "get_state");
+  if (rc != LBM_OK) return rc;
+  hd.q_last[0] = acc[0];
+  hd.q_last[1] = acc[1];
+  hd.q_acc[0] = acc[2];
+  hd.q_acc[1] = acc[3];
+  std::memcpy(b, &hd, sizeof(hd));
+  return LBM_OK;
+}
+
+template <typename T>
+int set_state_t(lbm_handle *h, const void *buf) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  StateHeader hd;
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (hd.magic != kStateMagic || hd.version != kStateVersion ||
+      hd.precision != (uint32_t)h->p.precision || hd.nx != h->p.nx || hd.ny != h->p.ny ||
+      hd.nz != h->p.nz || hd.ncomp != h->p.ncomp)
+    return set_err(h, LBM_E_INVAL, "state blob does not match this handle");
+  const char *b = (const char *)buf;
+  T *C = s.f[1 - h->cur];
+  size_t off = sizeof(StateHeader);
+  const size_t fb = (size_t)h->p.ncomp * Q * N * sizeof(T);
+  int rc = hip_check(h, hipMemcpyAsync(C, b + off, fb, hipMemcpyHostToDevice, h->st), "copy f");
+  off += fb;
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(s.r, b + off, 2 * N * sizeof(T), hipMemcpyHostToDevice, h->st),
+                   "copy r");
+  off += 2 * N * sizeof(T);
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(s.side, b + off, N, hipMemcpyHostToDevice, h->st), "copy side");
+  double acc[4] = {hd.q_last[0], hd.q_last[1], hd.q_acc[0], hd.q_acc[1]};
+  if (rc == LBM_OK)
+    rc = hip_check(h, hipMemcpyAsync(s.acc, acc, sizeof(acc), hipMemcpyHostToDevice, h->st),
+                   "copy accumulators");
+  if (rc == LBM_OK) {
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur], s.mask,
+                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    rc = hip_check(h, hipGetLastError(), "scatter");
+  }
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "set_state");
+  if (rc == LBM_OK) {
+    h->step = hd.step;
+    h->rho_valid = false;
+    h->has_fluid = true;
+  }
+  return rc;
+}
+
+template <typename T>
+int get_setup_t(lbm_handle *h, double *K0, double *sJ, double *thw, double *tho, double *Kinv) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  std::vector<T> buf(N);
+  const T *src[4] = {s.K0, s.sJ, s.thw, s.tho};
+  double *dst[4] = {K0, sJ, thw, tho};
+  for (int k = 0; k < 4; ++k) {
+    if (!dst[k]) continue;
+    int rc = hip_check(h, hipMemcpy(buf.data(), src[k], N * sizeof(T), hipMemcpyDeviceToHost),
+                       "copy setup");
+    if (rc != LBM_OK) return rc;
+    for (long long v = 0; v < N; ++v) dst[k][v] = (double)buf[v];
+  }
+  if (Kinv) {
+    if (!s.Kinv) {
+      std::memset(Kinv, 0, sizeof(double) * 6 * N);
+      return LBM_OK;
+    }
+    for (int k = 0; k < 6; ++k) {
+      int rc = hip_check(h, hipMemcpy(buf.data(), s.Kinv + (size_t)k * N, N * sizeof(T),
+                                      hipMemcpyDeviceToHost),
+                         "copy tensor");
+      if (rc != LBM_OK) return rc;
+      for (long long v = 0; v < N; ++v) Kinv[(size_t)k * N + v] = (double)buf[v];
+    }
+  }
+  return LBM_OK;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" int lbm_create(const lbm_params *p, lbm_handle **out) {
+  if (!out) return LBM_E_INVAL;
+  *out = nullptr;
+  char msg[256] = {0};
+  int rc = lbm_validate_params(p, msg, sizeof(msg));
+  if (rc != LBM_OK) {
+    g_create_error = msg;
+    return rc;
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) {
+    g_create_error = "no HIP device";
+    return LBM_E_DEVICE;
+  }
+  lbm_handle *h = new lbm_handle();
+  h->p = *p;
+  h->mc = make_consts(*p);
+  h->st = (hipStream_t)p->stream;
+  h->N = h->mc.N;
+  h->es = p->precision == LBM_PREC_F64 ? 8 : 4;
+  rc = p->precision == LBM_PREC_F64 ? alloc_state<double>(h) : alloc_state<float>(h);
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "create");
+  if (rc != LBM_OK) {
+    g_create_error = h->err;
+    lbm_destroy(h);
+    return rc;
+  }
+  *out = h;
+  return LBM_OK;
+}
+
+extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double *phi,
+                                const uint8_t *pore_type, const lbm_pore_table *tabs,
+                                int32_t ntab) {
+  if (!h) return LBM_E_INVAL;
+  char msg[256] = {0};
+  int rc = validate_tables(tabs, ntab, msg, sizeof(msg));
+  if (rc == LBM_OK) rc = validate_geometry(h->N, cls, phi, pore_type, ntab, msg, sizeof(msg));
+  if (rc != LBM_OK) return set_err(h, rc, msg);
+  h->has_geom = false;
+  h->has_fluid = false;
+  rc = h->p.precision == LBM_PREC_F64 ? set_geometry_t<double>(h, cls, phi, pore_type, tabs, ntab)
+                                      : set_geometry_t<float>(h, cls, phi, pore_type, tabs, ntab);
+  if (rc == LBM_OK) {
+    h->has_geom = true;
+    h->ntab = ntab;
+    h->geom_cls.assign(cls, cls + h->N);
+  }
+  return rc;
+}
+
+extern "C" int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *rho_o) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->has_geom) return set_err(h, LBM_E_STATE, "lbm_set_geometry must come first");
+  char msg[256] = {0};
+  int rc = validate_densities(h->N, h->geom_cls.data(), rho_w, rho_o, h->p.ncomp, msg, sizeof(msg));
+  if (rc != LBM_OK) return set_err(h, rc, msg);
+  return h->p.precision == LBM_PREC_F64 ? init_t<double>(h, rho_w, rho_o)
+                                        : init_t<float>(h, rho_w, rho_o);
+}
+
+extern "C" int lbm_step(lbm_handle *h, int64_t n) {
+  if (!h) return LBM_E_INVAL;
+  if (n < 0) return set_err(h, LBM_E_INVAL, "n must be >= 0");
+  if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
+  return h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n) : step_t<float>(h, n);
+}
+
+extern "C" int lbm_get_fields(lbm_handle *h, const lbm_fields *out) {
+  if (!h || !out) return LBM_E_INVAL;
+  if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
+  return h->p.precision == LBM_PREC_F64 ? fields_t<double>(h, out) : fields_t<float>(h, out);
+}
+
+extern "C" int lbm_get_diagnostics(lbm_handle *h, lbm_diag *out) {
+  if (!h || !out) return LBM_E_INVAL;
+  if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
+  return h->p.precision == LBM_PREC_F64 ? diag_t<double>(h, out) : diag_t<float>(h, out);
+}
+
+extern "C" int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
+                             double *theta_o, double *Kinv6) {
+  if (!h) return LBM_E_INVAL;
+  if (!h->has_geom) return set_err(h, LBM_E_STATE, "no geometry");
+  return h->p.precision == LBM_PREC_F64 ? get_setup_t<double>(h, K0, sJ, theta_w, theta_o, Kinv6)
+                                        : get_setup_t<float>(h, K0, sJ, theta_w, theta_o, Kinv6);
+}
+
+extern "C" int lbm_state_size(const lbm_handle *h, size_t *bytes) {
+  if (!h || !bytes) return LBM_E_INVAL;
+  *bytes = state_bytes(h);
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
+  if (!h || !host_buf) return LBM_E_INVAL;
+  if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
+  if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
+  return h->p.precision == LBM_PREC_F64 ? get_state_t<double>(h, host_buf)
+                                        : get_state_t<float>(h, host_buf);
+}
+
+extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
+  if (!h || !host_buf) return LBM_E_INVAL;
+  if (!h->has_geom) return set_err(h, LBM_E_STATE, "lbm_set_geometry must come first");
+  if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
+  return h->p.precision == LBM_PREC_F64 ? set_state_t<double>(h, host_buf)
+                                        : set_state_t<float>(h, host_buf);
+}
+
+extern "C" int lbm_set_profiling(lbm_handle *h, int32_t on) {
+  if (!h) return LBM_E_INVAL;
+  if (!on) fold_events(h);
+  h->prof = on != 0;
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset) {
+  if (!h || !out) return LBM_E_INVAL;
+  fold_events(h);
+  out->step_ms = h->t_ms[K_STEP];
+  out->step_launches = h->t_n[K_STEP];
+  out->aux_ms = h->t_ms[K_AUX];
+  out->aux_launches = h->t_n[K_AUX];
+  out->other_ms = h->t_ms[K_OTHER];
+  out->other_launches = h->t_n[K_OTHER];
+  if (reset) {
+    for (int k = 0; k < 3; ++k) {
+      h->t_ms[k] = 0;
+      h->t_n[k] = 0;
+    }
+  }
+  return LBM_OK;
+}
+
+extern "C" const char *lbm_last_error(const lbm_handle *h) {
+  return h ? h->err.c_str() : g_create_error.c_str();
+}
+
+extern "C" void lbm_destroy(lbm_handle *h) {
+  if (!h) return;
+  (void)hipStreamSynchronize(h->st);
+  fold_events(h);
+  for (auto &e : h->ev_pool) {
+    (void)hipEventDestroy(e.a);
+    (void)hipEventDestroy(e.b);
+  }
+  for (void *p : h->geom_allocs) dev_free(h, p);
+  for (void *p : h->allocs) dev_free(h, p);
+  delete h;
+}

@@ -109,7 +109,7 @@ class Brute:
                         if c == (0, 0, 0):
                             continue
                         n = nb(v, c)
-                        psi = p.psi_wall[b] if self.solid(n) else rho[b][n]
+                        psi = max(rho[b][v] + p.wall_dpsi[b], 0.0) if self.solid(n) else rho[b][n]
                         for d in range(3):
                             acc[d] += weight(c) * psi * c[d]
                     for d in range(3):

@@ -22,7 +22,7 @@ def run(G=3.0, n=64, steps=8000, m0=0.003):
     p.tau, p.G, p.g = (1.0, 1.0), G, ((0.0,) * 3, (0.0,) * 3)
     p.kappa, p.csf_region, p.phi_max, p.phi_avg = 0.0, "gray", 1.0, 0.5
     p.m_minor, p.s_min, p.s_max = m0, m0 / (1 + m0), 1 / (1 + m0)
-    p.psi_wall, p.kr_min, p.c_max, p.c_min, p.hyst = (1.0, m0), 1e-4, 3.5, 0.575, 0.05
+    p.wall_dpsi, p.kr_min, p.c_max, p.c_min, p.hyst = (0.1, -0.1), 1e-4, 3.5, 0.575, 0.05
     p.eps_n, p.tensor, p.collision, p.outlet_x = 1e-12, False, "regularized", n - 1
     o = Oracle(p)
     shape = (1, 1, n)

@@ -1,0 +1,217 @@
+"""GPU parity: the HIP path through the C ABI against the fp64 CPU oracle.
+
+FP64 runs must agree to 1e-12 (normalised max error per field, and relative
+error of every diagnostic scalar).  FP32 runs are compared at a tolerance
+derived from single-precision rounding accumulated over the run."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle, C, Q
+from gpu_common import (announce, gpu_run, oracle_run, field_errors, diag_errors, FIELDS)
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _check64(wl, steps, label):
+    announce(f"{label}: fp64 {steps} steps")
+    lb = gpu_run(wl, steps, "f64")
+    got = lb.get_fields()
+    dg = lb.get_diagnostics()
+    o = oracle_run(wl, steps)
+    ref = o.fields()
+    do = o.diagnostics()
+    fe = field_errors(got, ref, FIELDS if wl["params"].ncomp == 2 else ("rho_w", "ux", "uy", "uz"))
+    de = diag_errors(dg, do)
+    print(label, "field errors", {k: f"{v:.2e}" for k, v in fe.items()})
+    print(label, "diag errors", {k: f"{v:.2e}" for k, v in de.items()})
+    assert max(fe.values()) <= TOL64, fe
+    assert max(de.values()) <= TOL64, de
+    assert dg["step"] == steps and dg["nonfinite"] == 0
+    lb.destroy()
+    return o
+
+
+def test_droplet_slab_fp64_200_steps():
+    wl = W.droplet_slab()
+    o = _check64(wl, 200, "droplet_slab 32^3")
+    assert o.r.sum() > 0  # residual events happened on both sides
+
+
+def test_rock_mini_fp64():
+    wl = W.multiscale_rock(n=48, precision="f64")
+    _check64(wl, 60, "multiscale_rock 48^3")
+
+
+def test_fiber_mini_fp64():
+    wl = W.fiber_bundles(n=40, ncyl=4, precision="f64")
+    _check64(wl, 60, "fiber_bundles 40^3")
+
+
+def test_ragged_grid_fp64_bgk():
+    # N = 17*13*11 is not a multiple of the block size; solids, BGK, CSF in all
+    rng = np.random.default_rng(5)
+    n = (11, 13, 17)
+    p = W.Params(nx=17, ny=13, nz=11, ncomp=2, tau=(0.7, 1.2), G=3.0, kappa=-0.02,
+                 collision="bgk", csf_region="all", g=((1e-4, 0, 0), (0, -1e-4, 0)),
+                 outlet_x=5).filled()
+    cls = rng.choice([0, 0, 0, 1, 2], size=n).astype(np.uint8)
+    phi = np.where(cls == 2, rng.uniform(0.1, 0.4, n), 1.0)
+    pt = np.where(cls == 2, rng.integers(0, 2, n), 0).astype(np.uint8)
+    wl0 = W.multiscale_rock(n=8, precision="f64")
+    rw = np.where(rng.random(n) < 0.5, 1.0, p.m_minor)
+    wl = dict(params=p, cls=cls, phi=phi, ptype=pt, tables=wl0["tables"][:2], rho_w=rw,
+              rho_o=1.0 + p.m_minor - rw)
+    _check64(wl, 25, "ragged 17x13x11")
+
+
+def test_setup_parity_fp64():
+    wl = W.multiscale_rock(n=32, precision="f64")
+    announce("setup values 32^3 rock")
+    lb = gpu_run(wl, 0, "f64")
+    s = lb.get_setup()
+    o = Oracle(wl["params"])
+    o.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    for k, ref in (("K0", o.K0), ("sJ", o.sJ), ("thw", o.thw), ("tho", o.tho)):
+        err = np.abs(s[k] - ref).max() / max(np.abs(ref).max(), 1e-300)
+        assert err < 1e-14, (k, err)
+    assert (o.tho > 0).any() and (o.thw > 0).any()
+    lb.destroy()
+    wl = W.fiber_bundles(n=32, ncyl=3, precision="f64")
+    announce("setup values 32^3 fibers (tensor)")
+    lb = gpu_run(wl, 0, "f64")
+    s = lb.get_setup()
+    o = Oracle(wl["params"])
+    o.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    g = wl["cls"] == 2
+    scale = np.abs(o.Kinv).max()
+    err = np.abs(s["Kinv"] - o.Kinv)[:, g].max() / scale
+    print("tensor setup max error", err)
+    assert err < 1e-12
+    lb.destroy()
+
+
+def _random_state_case(ncomp, seed=11):
+    import test_oracle_brute as TB
+    p, cls, phi, ptype, tabs, rw, ro, rng = TB.tiny_case(ncomp, "regularized", seed=seed,
+                                                         n=(6, 7, 9))
+    o = Oracle(p)
+    o.set_geometry(cls, phi, ptype, tabs)
+    o.init_fluid(rw, ro)
+    TB.perturb(o, rng)
+    if ncomp == 2:
+        ev = o.evaluate()
+        flip = o.gray & (rng.random(o.shape) < 0.7)
+        o.side = np.where(flip, ev["S"] < 0.5, o.side)
+        o.r[0] = np.where(o.gray, 0.01 * rng.random(o.shape), 0.0)
+    return p, cls, phi, ptype, tabs, o
+
+
+@pytest.mark.parametrize("ncomp", [2, 1])
+def test_one_step_from_arbitrary_state(ncomp):
+    """Transplant a perturbed oracle state (with pending residual events) into
+    the GPU and compare the post-streaming populations after each step."""
+    import paper_2512_21696_amd as L
+    p, cls, phi, ptype, tabs, o = _random_state_case(ncomp)
+    announce(f"state transplant ncomp={ncomp}")
+    lb = L.lbm_create(p)
+    lb.set_geometry(cls, phi, ptype, tabs)
+    lb.set_state(L.make_state_blob(lb, o.f, o.r, o.side.astype(np.uint8)))
+    for k in range(3):
+        lb.step(1)
+        o.step(1)
+        st = lb.state_arrays(lb.get_state())
+        err = np.abs(st["f"] - o.f).max() / np.abs(o.f).max()
+        assert err < 1e-13, (k, err)
+        assert np.abs(st["r"] - o.r).max() < 1e-14
+        assert np.array_equal(st["side"].astype(bool), o.side)
+    lb.destroy()
+
+
+def test_checkpoint_resume_bitwise():
+    import paper_2512_21696_amd as L
+    wl = W.droplet_slab()
+    announce("checkpoint/resume droplet_slab fp64")
+    a = gpu_run(wl, 12, "f64")
+    blob = a.get_state()
+    a.step(12)
+    fa = a.get_state()
+    b = L.lbm_create(wl["params"])
+    b.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    b.set_state(blob)
+    b.step(12)
+    assert b.get_state() == fa
+    a.destroy()
+    b.destroy()
+
+
+def test_poiseuille_bgk_exact_on_gpu():
+    import math
+    tau = 0.5 + math.sqrt(3) / 4
+    H, g = 10, 1e-6
+    ny = H + 2
+    p = W.Params(nx=1, ny=ny, nz=1, ncomp=1, tau=(tau, tau), G=0.0, g=((g, 0, 0), (0, 0, 0)),
+                 collision="bgk").filled()
+    cls = np.zeros((1, ny, 1), np.uint8)
+    cls[:, 0, :] = 1
+    cls[:, -1, :] = 1
+    wl = dict(params=p, cls=cls, phi=np.ones(cls.shape), ptype=np.zeros(cls.shape, np.uint8),
+              tables=[], rho_w=np.ones(cls.shape), rho_o=np.ones(cls.shape))
+    announce("poiseuille 1x12x1 bgk")
+    lb = gpu_run(wl, 3000, "f64")
+    u = lb.get_fields()["ux"][0, :, 0]
+    nu = (tau - 0.5) / 3
+    y = np.arange(ny, dtype=float)
+    ex = g / (2 * nu) * (y - 0.5) * (H + 0.5 - y)
+    assert np.max(np.abs(u[1:-1] - ex[1:-1])) < 1e-10 * ex.max()
+    lb.destroy()
+
+
+def test_fp32_against_oracle():
+    """FP32 storage and arithmetic: 100 steps of the droplet case; single
+    precision rounding (6e-8) accumulated over 100 steps stays below 1e-4 of
+    each field's scale."""
+    wl = W.droplet_slab(precision="f32")
+    announce("droplet_slab fp32 100 steps")
+    lb = gpu_run(wl, 100, "f32")
+    got = lb.get_fields()
+    p64 = W.droplet_slab()["params"]
+    o = oracle_run(W.droplet_slab(), 100)
+    fe = field_errors(got, o.fields(), ("rho_w", "rho_o", "ux", "uy", "uz", "S"))
+    print("fp32 field errors", {k: f"{v:.2e}" for k, v in fe.items()})
+    assert max(fe.values()) < 1e-4, fe
+    lb.destroy()
+
+
+def test_errors_through_abi():
+    import paper_2512_21696_amd as L
+    p = W.Params(nx=4, ny=4, nz=4).filled()
+    announce("error paths")
+    lb = L.lbm_create(p)
+    with pytest.raises(L.LbmError) as e:
+        lb.step(1)
+    assert e.value.code == L.LBM_E_STATE
+    cls = np.full((4, 4, 4), 2, np.uint8)
+    wl = W.droplet_slab()
+    with pytest.raises(L.LbmError) as e:
+        lb.set_geometry(cls, np.full(cls.shape, 1.5), np.zeros(cls.shape, np.uint8), wl["tables"])
+    assert e.value.code == L.LBM_E_INVAL
+    bad = dict(wl["tables"][0])
+    bad["Pc"] = bad["Pc"][::-1].copy()
+    with pytest.raises(L.LbmError) as e:
+        lb.set_geometry(cls, np.full(cls.shape, 0.3), np.zeros(cls.shape, np.uint8), [bad])
+    assert e.value.code == L.LBM_E_INVAL
+    lb.set_geometry(cls, np.full(cls.shape, 0.3), np.zeros(cls.shape, np.uint8), wl["tables"])
+    with pytest.raises(L.LbmError) as e:
+        lb.init_fluid(np.full(cls.shape, -1.0), np.ones(cls.shape))
+    assert e.value.code == L.LBM_E_INVAL
+    lb.init_fluid(np.ones(cls.shape), np.full(cls.shape, p.m_minor))
+    # a non-finite state injected through the checkpoint path is detected
+    st = lb.state_arrays(lb.get_state())
+    f = st["f"].copy()
+    f[0, 3, 1, 1, 1] = np.nan
+    lb.set_state(L.make_state_blob(lb, f, st["r"], st["side"]))
+    assert lb.get_diagnostics()["nonfinite"] == 1
+    lb.destroy()

@@ -1,0 +1,75 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and validates arguments on the host."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2512_21696_amd as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    pat = r"^(?:int|void|const char \*)\s*(lbm_[a-z_]+)\s*\("
+    return sorted(set(re.findall(pat, src, flags=re.M)))
+
+
+def test_library_exports_every_declared_function():
+    lib = L.load_library()
+    names = header_functions()
+    assert set(names) == set(L.EXPORTS), names
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_defaults_validate():
+    p = L.lbm_params_default()
+    assert p.nx == 32 and p.ncomp == 2 and p.precision == 0 and p.track_flux == 1
+    assert abs(p.m_minor - 0.0029912221254390597) < 1e-18
+    msg = ctypes.create_string_buffer(256)
+    assert L.load_library().lbm_validate_params(ctypes.byref(p), msg, 256) == L.LBM_OK
+
+
+@pytest.mark.parametrize("field,value,code", [
+    ("tau", (0.5, 1.0), L.LBM_E_INVAL), ("ncomp", 3, L.LBM_E_INVAL), ("nx", 0, L.LBM_E_INVAL),
+    ("precision", 7, L.LBM_E_UNSUPPORTED), ("outlet_x", 32, L.LBM_E_INVAL),
+    ("hyst", 0.5, L.LBM_E_INVAL), ("kr_min", 0.0, L.LBM_E_INVAL)])
+def test_invalid_params_rejected_on_host(field, value, code):
+    lib = L.load_library()
+    p = L.lbm_params_default()
+    if field == "tau":
+        p.tau[0], p.tau[1] = value
+    else:
+        setattr(p, field, value)
+    msg = ctypes.create_string_buffer(256)
+    assert lib.lbm_validate_params(ctypes.byref(p), msg, 256) == code
+    assert len(msg.value) > 0
+    h = ctypes.c_void_p()
+    assert lib.lbm_create(ctypes.byref(p), ctypes.byref(h)) == code
+    assert not h.value
+    assert len(lib.lbm_last_error(None)) > 0
+
+
+def test_oversized_grid_unsupported():
+    p = L.lbm_params_default()
+    p.nx = p.ny = p.nz = 400
+    assert L.load_library().lbm_validate_params(ctypes.byref(p), None, 0) == L.LBM_E_UNSUPPORTED
+
+
+def test_null_handle_calls_fail_cleanly():
+    lib = L.load_library()
+    assert lib.lbm_step(None, 1) == L.LBM_E_INVAL
+    assert lib.lbm_init_fluid(None, None, None) == L.LBM_E_INVAL
+    lib.lbm_destroy(None)
+
+
+def test_binding_refuses_without_gpu():
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("GPU present")
+    import workloads as W
+    with pytest.raises(RuntimeError):
+        L.lbm_create(W.Params().filled())

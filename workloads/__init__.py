@@ -72,7 +72,7 @@ class Params:
     m_minor: float = 0.0            # filled from G when 0
     s_min: float = 0.0
     s_max: float = 0.0
-    psi_wall: tuple = (1.0, 0.0)    # (water, oil); oil filled with m when 0
+    wall_dpsi: tuple = (0.1, -0.1)  # wetting offsets of the solid pseudo-potential (w, o)
     kr_min: float = 1e-4
     c_max: float = 3.5
     c_min: float = 0.575
@@ -97,8 +97,6 @@ class Params:
             p.s_max = 1.0 / (1.0 + m)
         if p.phi_avg == 0.0:
             p.phi_avg = 0.5 * (1.0 + m)
-        if p.psi_wall[1] == 0.0:
-            p.psi_wall = (p.psi_wall[0], m)
         if p.eps_n == 0.0:
             p.eps_n = 1e-12 if p.precision == "f64" else 1e-7
         if p.outlet_x < 0:
@@ -210,9 +208,11 @@ def multiscale_rock(n: int = 256, seed: int = 2001, precision: str = "f32",
     rims) and 45 % pore; gray phi ~ U[0.05, 0.4]; pore type ~ U{0..3} with
     Brooks-Corey lambda in {0.5, 1, 2, 3} (Pc_e = 0.05, Swr = 0.1, Corey
     cubic Kr, Kozeny-Carman d = 2, phi_ref = 0.225).  An 8-voxel pore buffer
-    at x < 8 starts as water, the rest as oil; body acceleration gw on water
-    along +x; tau_w = 0.6, tau_o = 1.0 (viscosity ratio 1:5); G = 3."""
-    p = Params(nx=n, ny=n, nz=n, ncomp=2, precision=precision, tau=(0.6, 1.0), G=3.0,
+    at x < 8 starts as water (tanh edge), the rest as oil; body acceleration gw
+    on water along +x; tau_w = 1.0, tau_o = 1.5 (viscosity ratio 1:2; a 1:5
+    ratio, tau_w = 0.6 or tau_o = 3, drove densities negative within ~100
+    steps next to gray and solid voxels); G = 3."""
+    p = Params(nx=n, ny=n, nz=n, ncomp=2, precision=precision, tau=(1.0, 1.5), G=3.0,
                g=((gw, 0.0, 0.0), (0.0, 0.0, 0.0)), kappa=kappa).filled()
     f = gaussian_random_field((n, n, n), 6.0, seed)
     q35, q55 = np.quantile(f, [0.35, 0.55])
@@ -232,7 +232,14 @@ def multiscale_rock(n: int = 256, seed: int = 2001, precision: str = "f32",
         pc, krw, kro = brooks_corey_tables(0.05, lam, 0.1)
         tabs.append(pore_table(K0, pc, krw, kro, phi_ref=0.225, pc_pm=0.05))
     x, _, _ = _coords(n, n, n)
-    rw, ro = two_phase_densities(x < buffer, p.m_minor)
+    # water buffer x < buffer with a tanh edge of width 1.5 (periodic in x)
+    c = 0.5 * (buffer - 1)
+    d = np.abs(x - c)
+    d = np.minimum(d, n - d)
+    prof = 0.5 * (1.0 - np.tanh((d - 0.5 * buffer) / 1.5))
+    m = p.m_minor
+    rw = m + (1.0 - m) * prof
+    ro = 1.0 + m - rw
     return dict(name=f"multiscale_rock_{n}", params=p, cls=cls, phi=phi, ptype=ptype,
                 tables=tabs, rho_w=rw, rho_o=ro, steps=2000)
 
