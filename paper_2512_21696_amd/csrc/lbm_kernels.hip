@@ -476,16 +476,18 @@ struct FieldsOut {
 
 enum { MODE_STEP = 0, MODE_FIELDS = 1, MODE_DIAG = 2 };
 
+// One voxel of the step (MODE_STEP), of the field evaluation (MODE_FIELDS) or
+// of the diagnostics (MODE_DIAG: the voxel's contributions are left in dsum,
+// reduced by the caller once all lanes have converged).
 template <typename T, int NC, int MODE, typename O>
-__global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__restrict__ fin,
-                                              T *__restrict__ fout, const DevState<T> s,
-                                              const FieldsOut fo) {
+__device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__restrict__ fin,
+                                           T *__restrict__ fout, const DevState<T> &s,
+                                           const FieldsOut &fo, const long long v,
+                                           double (&dsum)[6]) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = v < N;
   uint32_t mk = active ? s.mask[v] : (SOLID_CODE << CLASS_SHIFT);
   const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
-  double dsum[6] = {0, 0, 0, 0, 0, 0};  // MODE_DIAG: mass_w, mass_o, phiS, phi, nonfinite, max|u|
   if (cl == SOLID_CODE) {
     if (MODE == MODE_FIELDS && active) {
       O *outs[8] = {(O *)fo.rho_w, (O *)fo.rho_o, (O *)fo.ux, (O *)fo.uy,
@@ -493,7 +495,6 @@ __global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__r
       for (int k = 0; k < 8; ++k)
         if (outs[k]) outs[k][v] = (O)0;
     }
-    if (MODE == MODE_DIAG) block_sum<6>(dsum, s.partial + (size_t)blockIdx.x * 6, true);
     return;
   }
   const bool gray = cl == GRAY_CODE;
@@ -696,7 +697,6 @@ __global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__r
     const double un = sqrt((double)u0 * u0 + (double)u1 * u1 + (double)u2 * u2);
     dsum[4] = isfinite(un) && isfinite(dsum[0]) && isfinite(dsum[1]) ? 0.0 : 1.0;
     dsum[5] = isfinite(un) ? un : 0.0;
-    block_sum<6>(dsum, s.partial + (size_t)blockIdx.x * 6, true);
     return;
   }
 
@@ -812,6 +812,16 @@ __global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__r
       fout[(size_t)(a * Q + i) * N + v] = post;
     }
   }
+}
+
+template <typename T, int NC, int MODE, typename O>
+__global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__restrict__ fin,
+                                              T *__restrict__ fout, const DevState<T> s,
+                                              const FieldsOut fo) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double dsum[6] = {0, 0, 0, 0, 0, 0};  // mass_w, mass_o, phi S, phi, nonfinite, max|u|
+  step_voxel<T, NC, MODE, O>(mc, fin, fout, s, fo, v, dsum);
+  if (MODE == MODE_DIAG) block_sum<6>(dsum, s.partial + (size_t)blockIdx.x * 6, true);
 }
 
 // Outlet flux through the plane x_f | x_f+1, counted per link from the
