@@ -1,0 +1,196 @@
+"""Benchmark of the multiscale two-component D3Q19 step on one MI355X.
+
+Workload: the 256^3 synthetic multiscale rock (Gaussian random field,
+35 % solid / 20 % gray / 45 % pore, four Brooks-Corey pore types, water driven
+in +x), fp32 storage and arithmetic.  A step is one full time step of the
+method: density pass, CSF normals, the fused collide-stream kernel (forces,
+constitutive update, residual transfer, collision, pull streaming) and the
+per-step outlet-flux reduction; diagnostics (fp64 reductions with the
+non-finite check) run every --diag-every steps inside the timed region.
+
+Prints ONE JSON line.  value = fluid-voxel updates per second / 1e6 over the
+timed steps (inputs resident in HBM); the roofline block prices the dominant
+kernel (the fused step) with its algorithmic bytes per fluid update divided
+by its mean launch time from HIP events on the library's stream.
+"""
+import argparse
+import hashlib
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "MLUPS (2-comp D3Q19) & % HBM peak; FP16-store vs FP32 MLUPS at stated error"
+
+
+def algorithmic_bytes(ncomp, es, gray_frac, tensor):
+    """Bytes the method must move per fluid voxel update: every population read
+    and written once, the class code, and the per-voxel inputs of gray voxels
+    (K0, s_J, theta_w, theta_o, pore type; residual amounts and side flag read
+    and written; the six inverse-permeability values for the tensor model)."""
+    pops = 2 * 19 * ncomp * es
+    gray = 0.0
+    if ncomp == 2:
+        gray = 4 * es + 1 + 2 * 2 * es + 2
+    else:
+        gray = es
+    if tensor:
+        gray += 6 * es
+    return pops + 1 + gray_frac * gray
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbm_kernels.hip", "lbm_runtime.hip"):
+        with open(os.path.join(ROOT, "paper_2512_21696_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload):
+    """HBM traffic per step-kernel launch from the committed rocprofv3 counter
+    summary, or None when the kernels changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "step_kernel_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh)
+    if rec.get("kernel_hash") != kernel_source_hash() or rec.get("workload") != workload:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(n_crop=64, steps=10):
+    """The fp64 CPU oracle on a bounded sample: an n_crop^3 multiscale rock of
+    the same recipe, a few steps, single thread."""
+    os.environ.setdefault("OMP_NUM_THREADS", "1")
+    import numpy as np
+    import workloads as W
+    from oracle import Oracle
+    wl = W.multiscale_rock(n=n_crop, precision="f64")
+    o = Oracle(wl["params"])
+    o.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    o.init_fluid(wl["rho_w"], wl["rho_o"])
+    o.step(1)
+    nfl = int(np.sum(wl["cls"] != 1))
+    t0 = time.perf_counter()
+    o.step(steps)
+    dt = time.perf_counter() - t0
+    return {"value": nfl * steps / dt / 1e6, "unit": "MLUPS (fluid voxels)", "cores": 1,
+            "kind": "oracle",
+            "sample": f"{n_crop}^3 multiscale rock of the same recipe, fp64, {steps} steps "
+                      f"after one warm-up step, single thread ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=300)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--diag-every", type=int, default=100)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
+              f"slab decomposition is a design, not a built path", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2512_21696_amd as L
+
+    torch.cuda.set_device(0)
+    t_gen = time.perf_counter()
+    wl = W.multiscale_rock(n=args.n, precision=args.precision)
+    p = wl["params"]
+    p.diag_every = args.diag_every
+    cls = wl["cls"]
+    n_fluid = int(np.sum(cls != 1))
+    n_gray = int(np.sum(cls == 2))
+    t_gen = time.perf_counter() - t_gen
+    print(f"[bench] generated {wl['name']} in {t_gen:.1f}s: fluid {n_fluid}, gray {n_gray}",
+          file=sys.stderr, flush=True)
+
+    lb = L.lbm_create(p)
+    t0 = time.perf_counter()
+    lb.set_geometry(cls, wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    lb.step(args.warmup)
+    torch.cuda.synchronize()
+    print(f"[bench] setup {t_setup:.2f}s, warm-up {args.warmup} steps done", file=sys.stderr,
+          flush=True)
+
+    lb.set_profiling(True)
+    lb.get_kernel_times(reset=True)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record(stream)
+    lb.step(args.steps)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    total_ms = e0.elapsed_time(e1)
+    kt = lb.get_kernel_times(reset=True)
+    lb.set_profiling(False)
+    diag = lb.get_diagnostics()
+    print(f"[bench] timed {args.steps} steps in {total_ms:.1f} ms; diag {diag}", file=sys.stderr,
+          flush=True)
+
+    ms_per_step = total_ms / args.steps
+    mlups = n_fluid * args.steps / (total_ms * 1e-3) / 1e6
+    es = 4 if args.precision == "f32" else 8
+    b_alg = algorithmic_bytes(2, es, n_gray / n_fluid, False)
+    step_ms = kt["step_ms"] / max(kt["step_launches"], 1)
+    achieved = b_alg * n_fluid / (step_ms * 1e-3) / 1e9
+    traffic = measured_traffic(wl["name"] + "_" + args.precision)
+    out = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": wl["name"], "grid": [args.n] * 3, "components": 2,
+                   "fluid_voxels": n_fluid, "gray_voxels": n_gray,
+                   "storage": args.precision, "diag_every": args.diag_every,
+                   "lups_counted_over": "fluid (pore + gray) voxels",
+                   "all_voxel_mlups": round(args.n ** 3 * args.steps / (total_ms * 1e-3) / 1e6, 2),
+                   "setup_s": round(t_setup, 3)},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": traffic,
+                     "kernel": "k_step (fused collide-stream)",
+                     "bytes_per_fluid_update": round(b_alg, 2),
+                     "kernel_ms": round(step_ms, 4),
+                     "step_time_share": round(kt["step_ms"] / total_ms, 4),
+                     "aux_ms_per_step": round(kt["aux_ms"] / args.steps, 4),
+                     "other_ms_per_step": round(kt["other_ms"] / args.steps, 4)},
+        "diagnostics": {k: diag[k] for k in ("mass_w", "mass_o", "sw", "max_u", "nonfinite",
+                                             "step")},
+    }
+    lb.destroy()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline()
+        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
