@@ -856,23 +856,36 @@ __global__ void k_flux(const ModelConsts mc, const T *__restrict__ post,
   block_sum<2>(val, partial + (size_t)blockIdx.x * 2, false);
 }
 
-// Fixed-order sum of block partials; NV values per block.
-__global__ void k_finalize(const double *__restrict__ partial, int nblocks, int nv, int maxlast,
-                           double *__restrict__ out, int accumulate) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// Fixed-order sum of block partials (nv values per block), one block of 256
+// threads: strided partial sums then a fixed tree, so results are
+// deterministic for a given launch shape.
+__global__ __launch_bounds__(256) void k_finalize(const double *__restrict__ partial, int nblocks,
+                                                  int nv, int maxlast, double *__restrict__ out,
+                                                  int accumulate) {
+  __shared__ double sh[256];
+  const int t = threadIdx.x;
   for (int k = 0; k < nv; ++k) {
-    bool mx = maxlast && k == nv - 1;
-    double x = mx ? 0.0 : 0.0;
-    for (int b = 0; b < nblocks; ++b) {
-      double y = partial[(size_t)b * nv + k];
+    const bool mx = maxlast && k == nv - 1;
+    double x = 0.0;
+    for (int b = t; b < nblocks; b += 256) {
+      const double y = partial[(size_t)b * nv + k];
       x = mx ? fmax(x, y) : x + y;
     }
-    if (accumulate) {  // out[0..nv) = last values, out[nv..2nv) += last values
-      out[k] = x;
-      out[nv + k] += x;
-    } else {
-      out[k] = x;
+    sh[t] = x;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+      if (t < w) sh[t] = mx ? fmax(sh[t], sh[t + w]) : sh[t] + sh[t + w];
+      __syncthreads();
     }
+    if (t == 0) {
+      if (accumulate) {  // out[0..nv) = last values, out[nv..2nv) += last values
+        out[k] = sh[0];
+        out[nv + k] += sh[0];
+      } else {
+        out[k] = sh[0];
+      }
+    }
+    __syncthreads();
   }
 }
 

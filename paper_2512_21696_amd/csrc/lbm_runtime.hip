@@ -9,6 +9,7 @@
 
 #include "../../include/lbm.h"
 #include "lbm_kernels.hip"
+#include "lbm_step_tiled.hip"
 #include "lbm_validate.hpp"
 
 using namespace lbm;
@@ -335,11 +336,33 @@ void ensure_aux(lbm_handle *h) {
     else
       hipLaunchKernelGGL((k_moments<T, 1>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
                          s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
-    if (s.nrm)
-      hipLaunchKernelGGL(k_normals<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.rho, s.nrm, s.mask,
-                         h->p.nx, h->p.ny, h->p.nz, N, h->p.eps_n);
     h->rho_valid = true;
   }
+}
+
+// CSF normals as a field (used by the field and diagnostics evaluations; the
+// step kernel computes them in LDS)
+template <typename T>
+void ensure_normals(lbm_handle *h) {
+  DevState<T> &s = state<T>(h);
+  ensure_aux<T>(h);
+  if (s.nrm) {
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_normals<T>, dim3(blocks(h->N)), dim3(256), 0, h->st, s.rho, s.nrm, s.mask,
+                       h->p.nx, h->p.ny, h->p.nz, h->N, h->p.eps_n);
+  }
+}
+
+template <typename T, int NC, bool REG>
+void launch_tiled(lbm_handle *h, const T *fin, T *fout) {
+  DevState<T> &s = state<T>(h);
+  const int tx = (h->p.nx + zm::TX - 1) / zm::TX;
+  const int ty = (h->p.ny + zm::TY - 1) / zm::TY;
+  const int tz = (h->p.nz + zm::ZC - 1) / zm::ZC;
+  const int nt = tx * ty * tz;
+  const int grid = (nt + 7) / 8 * 8;
+  hipLaunchKernelGGL((k_step_zm<T, NC, REG>), dim3(grid), dim3(zm::NT), 0, h->st,
+                     make_kc<T>(h->mc), fin, fout, s, tx, ty, tz, nt);
 }
 
 template <typename T, int MODE, typename O>
@@ -349,6 +372,17 @@ void launch_step(lbm_handle *h, const FieldsOut &fo) {
   const T *fin = s.f[h->cur];
   T *fout = s.f[1 - h->cur];
   Timed tm(h, MODE == MODE_STEP ? K_STEP : K_OTHER);
+  if (MODE == MODE_STEP) {
+    const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
+    if (h->p.ncomp == 2) {
+      if (reg) launch_tiled<T, 2, true>(h, fin, fout);
+      else launch_tiled<T, 2, false>(h, fin, fout);
+    } else {
+      if (reg) launch_tiled<T, 1, true>(h, fin, fout);
+      else launch_tiled<T, 1, false>(h, fin, fout);
+    }
+    return;
+  }
   if (h->p.ncomp == 2)
     hipLaunchKernelGGL((k_step<T, 2, MODE, O>), dim3(blocks(N)), dim3(256), 0, h->st, h->mc, fin,
                        fout, s, fo);
@@ -360,12 +394,12 @@ void launch_step(lbm_handle *h, const FieldsOut &fo) {
 template <typename T>
 int diag_t(lbm_handle *h, lbm_diag *out) {
   DevState<T> &s = state<T>(h);
-  ensure_aux<T>(h);
+  ensure_normals<T>(h);
   FieldsOut fo{};
   launch_step<T, MODE_DIAG, T>(h, fo);
   {
     Timed tm(h, K_OTHER);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, h->st, s.partial, (int)blocks(h->N), 6, 1,
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)blocks(h->N), 6, 1,
                        s.acc + 4, 0);
   }
   double acc[10];
@@ -406,7 +440,7 @@ int step_t(lbm_handle *h, int64_t n) {
       else
         hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
                            s.mask, s.partial);
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(64), 0, h->st, s.partial, (int)fb, 2, 0, s.acc,
+      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0, s.acc,
                          1);
     }
     hipError_t e = hipGetLastError();
@@ -470,7 +504,7 @@ template <typename T>
 int fields_t(lbm_handle *h, const lbm_fields *out) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
-  ensure_aux<T>(h);
+  ensure_normals<T>(h);
   void *dst[8] = {out->rho_w, out->rho_o, out->ux, out->uy, out->uz, out->S, out->r_w, out->r_o};
   if (out->on_device) {
     FieldsOut fo{dst[0], dst[1], dst[2], dst[3], dst[4], dst[5], dst[6], dst[7]};
