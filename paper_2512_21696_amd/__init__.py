@@ -197,7 +197,10 @@ class Lbm:
                     return None
 
             def _free(ptr, ctx):
-                torch.cuda.caching_allocator_delete(int(ptr))
+                try:
+                    torch.cuda.caching_allocator_delete(int(ptr))
+                except Exception:  # interpreter shutdown: torch already torn down
+                    pass
 
             self._cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
             cp.alloc, cp.free = self._cbs

@@ -1,50 +1,52 @@
 // The fused collide-stream kernel of one time step (gfx950).
 //
 // A block owns a column of 64 x 4 voxels (one wavefront per x-row, so every
-// population load and store of a wave is 256 contiguous bytes) and marches
-// along z through a chunk of ZC planes.  Rolling windows in LDS hold, per
-// plane, the densities of both components and the mobile saturation S_hat on
-// the column plus a radius-2 halo (periodic wrap), a solid flag per cell, and
-// the CSF normals n^a = grad rho^b / |grad rho^b| on the column plus a
-// radius-1 halo.  Each plane is staged once and used by three consecutive
-// voxel planes, so every stencil of the step (pseudo-potential sum,
-// grad rho^b, curvature -div n^a, grad S_hat) reads LDS only.  Blocks are
-// numbered so that the blocks resident on one XCD (dispatch is round-robin
-// over the 8 XCDs) cover neighbouring columns, keeping halo re-reads in that
-// XCD's L2.
+// population load and store of a wave covers 256 contiguous bytes) and
+// marches along z through a chunk of ZC planes.  Rolling windows in LDS hold,
+// per plane, (rho_w, rho_o, S_hat, solid flag) on the column plus a radius-2
+// halo (periodic wrap) and the CSF normals
+// n^a = grad rho^b / |grad rho^b| on the column plus a radius-1 halo.  Each
+// plane is staged once and serves three consecutive voxel planes, so every
+// stencil of the step (pseudo-potential sum, grad rho^b, curvature -div n^a,
+// grad S_hat) reads LDS only.  Blocks are numbered so that the blocks resident
+// on one XCD (dispatch is round-robin over the 8 XCDs) cover neighbouring
+// columns, which keeps halo re-reads inside that XCD's L2.
 //
 // Collision: with the Hermite-projected (regularised) operator the
 // post-collision set depends on the gathered populations only through their
 // first moments (rho, rho u, the second-moment tensor), so the pull
-// accumulates those ten moments per component on the fly.  Equilibrium,
-// projected non-equilibrium part and the force term of Eq. (3) are each a
-// quadratic form w_i (A + B.c_i + c_i^T C c_i), so the 19 outgoing
-// populations follow from ten coefficients per component.  The BGK variant
-// keeps the populations.
+// accumulates those ten moments per component on the fly (pairing opposite
+// directions).  Equilibrium, projected non-equilibrium part and the force term
+// of Eq. (3) are each a quadratic form w_i (A + B.c_i + c_i^T C c_i), so the
+// 19 outgoing populations follow from ten coefficients per component.  The
+// BGK variant keeps the populations.
+//
+// fp32 runs use the hardware reciprocal and reciprocal square root (1 ulp);
+// fp64 runs divide exactly.
 namespace lbm {
 namespace zm {
 constexpr int TX = 64, TY = 4;
 constexpr int NT = TX * TY;
 constexpr int R = 2;
 constexpr int HX = TX + 2 * R, HY = TY + 2 * R;
-constexpr int NH = HX * HY;          // density plane cells
+constexpr int NH = HX * HY;  // density plane cells
 constexpr int MX = TX + 2, MY = TY + 2;
-constexpr int NM = MX * MY;          // normal plane cells
-constexpr int RS = 4;                // density planes z-1 .. z+2
-constexpr int MS = 3;                // normal planes z-1 .. z+1
-constexpr int ZC = 32;               // planes per block
+constexpr int NM = MX * MY;  // normal plane cells
+constexpr int RS = 4;        // density planes z-1 .. z+2
+constexpr int MS = 3;        // normal planes z-1 .. z+1
+constexpr int ZC = 32;       // planes per block
 __host__ __device__ constexpr int hoff(int i) { return cx(i) + HX * cy(i); }
 __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 }  // namespace zm
 
 // Run constants pre-converted to the arithmetic type, so the kernel reads
-// them as scalar (SGPR) operands instead of converting inside the loop.
+// them as scalar operands instead of converting inside the loop.
 template <typename T>
 struct KC {
   int nx, ny, nz, csf_all, tensor, collision;
   long long N;
   T g[2][3], omega[2], nu[2], wall_dpsi[2];
-  T G, kappa, csf_den, s_min, span, kr_min, hyst, m_minor, eps_n;
+  T G, kappa, csf_fac, s_min, inv_span, kr_min, hyst, m_minor, eps_n2;
 };
 
 template <typename T>
@@ -58,11 +60,21 @@ KC<T> make_kc(const ModelConsts &m) {
     k.nu[a] = (T)m.nu[a];
     k.wall_dpsi[a] = (T)m.wall_dpsi[a];
   }
-  k.G = (T)m.G; k.kappa = (T)m.kappa; k.csf_den = (T)(1.0 / m.csf_scale);
-  k.s_min = (T)m.s_min; k.span = (T)(1.0 / m.inv_span); k.kr_min = (T)m.kr_min;
-  k.hyst = (T)m.hyst; k.m_minor = (T)m.m_minor; k.eps_n = (T)m.eps_n;
+  k.G = (T)m.G; k.kappa = (T)m.kappa;
+  k.csf_fac = (T)(m.kappa * m.csf_scale);  // kappa / (phi_avg phi_max)
+  k.s_min = (T)m.s_min; k.inv_span = (T)m.inv_span; k.kr_min = (T)m.kr_min;
+  k.hyst = (T)m.hyst; k.m_minor = (T)m.m_minor; k.eps_n2 = (T)(m.eps_n * m.eps_n);
   return k;
 }
+
+template <typename T> __device__ inline T rcp(T x);
+template <> __device__ inline float rcp<float>(float x) { return __builtin_amdgcn_rcpf(x); }
+template <> __device__ inline double rcp<double>(double x) { return 1.0 / x; }
+template <typename T> __device__ inline T rsq(T x);
+template <> __device__ inline float rsq<float>(float x) { return __builtin_amdgcn_rsqf(x); }
+template <> __device__ inline double rsq<double>(double x) { return 1.0 / sqrt(x); }
+
+template <typename T> struct vec4 { T x, y, z, w; };
 
 __device__ inline int wrapn(int v, int n) {
   v %= n;
@@ -81,23 +93,25 @@ __device__ inline float bload(rsrc_t r, uint32_t off, float) {
 __device__ inline double bload(rsrc_t r, uint32_t off, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
-__device__ inline void bstore(rsrc_t r, uint32_t off, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, off, 0, 0);
+__device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
 }
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
-__device__ inline void bstore(rsrc_t r, uint32_t off, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, off, 0, 0);
+__device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
 }
 
 __device__ inline int rslot(int z) { return (z + 8) & 3; }
 __device__ inline int mslot(int z) { return (z + 9) % 3; }
 
-// Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus keep*f_i
-// for BGK) of one component.
+// Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus
+// keep * sc * f_i for BGK) of one component; voff is the voxel's byte offset
+// within its plane, sbase the byte offset of the plane.
 template <typename T, bool REG>
-__device__ __forceinline__ void emit_post(rsrc_t out, uint32_t vox, uint32_t N, T A, T B0, T B1, T B2,
-                                          T Cxx, T Cyy, T Czz, T Cxy, T Cxz, T Cyz, T sc,
-                                          const T *fpop, T keep) {
+__device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sbase,
+                                          uint32_t Nbytes, T A, T B0, T B1, T B2, T Cxx, T Cyy,
+                                          T Czz, T Cxy, T Cxz, T Cyz, T sc, const T *fpop,
+                                          T keep) {
   const T w0 = (T)(1.0 / 3.0) * sc, w1 = (T)(1.0 / 18.0) * sc, w2 = (T)(1.0 / 36.0) * sc;
   T v[Q];
   v[0] = w0 * A;
@@ -108,25 +122,29 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t vox, uint32_t N, 
   v[4] = w1 * (ay - B1);
   v[5] = w1 * (az + B2);
   v[6] = w1 * (az - B2);
-  const T exy = A + Cxx + Cyy, exz = A + Cxx + Czz, eyz = A + Cyy + Czz;
+  const T exy = ax + Cyy, exz = ax + Czz, eyz = ay + Czz;
   const T dxy = (T)2 * Cxy, dxz = (T)2 * Cxz, dyz = (T)2 * Cyz;
-  v[7] = w2 * (exy + B0 + B1 + dxy);
-  v[8] = w2 * (exy - B0 - B1 + dxy);
-  v[9] = w2 * (exy + B0 - B1 - dxy);
-  v[10] = w2 * (exy - B0 + B1 - dxy);
-  v[11] = w2 * (exz + B0 + B2 + dxz);
-  v[12] = w2 * (exz - B0 - B2 + dxz);
-  v[13] = w2 * (exz + B0 - B2 - dxz);
-  v[14] = w2 * (exz - B0 + B2 - dxz);
-  v[15] = w2 * (eyz + B1 + B2 + dyz);
-  v[16] = w2 * (eyz - B1 - B2 + dyz);
-  v[17] = w2 * (eyz + B1 - B2 - dyz);
-  v[18] = w2 * (eyz - B1 + B2 - dyz);
+  const T pxy = exy + dxy, mxy = exy - dxy, pxz = exz + dxz, mxz = exz - dxz;
+  const T pyz = eyz + dyz, myz = eyz - dyz;
+  const T s01 = B0 + B1, d01 = B0 - B1, s02 = B0 + B2, d02 = B0 - B2, s12 = B1 + B2,
+          d12 = B1 - B2;
+  v[7] = w2 * (pxy + s01);
+  v[8] = w2 * (pxy - s01);
+  v[9] = w2 * (mxy + d01);
+  v[10] = w2 * (mxy - d01);
+  v[11] = w2 * (pxz + s02);
+  v[12] = w2 * (pxz - s02);
+  v[13] = w2 * (mxz + d02);
+  v[14] = w2 * (mxz - d02);
+  v[15] = w2 * (pyz + s12);
+  v[16] = w2 * (pyz - s12);
+  v[17] = w2 * (myz + d12);
+  v[18] = w2 * (myz - d12);
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     T val = v[i];
     if (!REG) val += keep * sc * fpop[i];
-    bstore(out, ((uint32_t)i * N + vox) * (uint32_t)sizeof(T), val);
+    bstore(out, voff, sbase + (uint32_t)i * Nbytes, val);
   }
 }
 
@@ -137,10 +155,9 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
                                                  const int chunks_z, const int ntiles) {
   using namespace zm;
   constexpr bool STENCIL = NC == 2;
-  __shared__ T srho[STENCIL ? RS : 1][NC][STENCIL ? NH : 1];
-  __shared__ T sS[STENCIL ? RS : 1][STENCIL ? NH : 1];
-  __shared__ uint8_t ssol[STENCIL ? RS : 1][STENCIL ? NH : 1];
-  __shared__ T snrm[STENCIL ? MS : 1][STENCIL ? 6 : 1][STENCIL ? NM : 1];
+  using T4 = vec4<T>;
+  __shared__ T4 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];     // rho_w, rho_o, S_hat, solid
+  __shared__ T4 snrm[STENCIL ? MS : 1][2][STENCIL ? NM : 1];  // n^w, n^o
   __shared__ int sxw[HX], syw[HY];
 
   const int nb = gridDim.x;
@@ -155,62 +172,67 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   const int tx = tid % TX, ty = tid / TX;
   const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
   const long long N = mc.N;
-  const long long nxy = (long long)nx * ny;
+  const uint32_t N32 = (uint32_t)N;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const int x0 = bx * TX, y0 = by * TY;
   const int zs = bzc * ZC;
   const int ze = zs + ZC < nz ? zs + ZC : nz;
   const bool csf = STENCIL && mc.kappa != (T)0;
-  const T span = mc.span;
+  constexpr uint32_t ES = (uint32_t)sizeof(T);
 
-  if (tid < HX) sxw[tid] = wrapn(x0 + tid - R, nx);
-  if (tid < HY) syw[tid] = wrapn(y0 + tid - R, ny);
-  __syncthreads();
+  if (STENCIL) {
+    if (tid < HX) sxw[tid] = wrapn(x0 + tid - R, nx);
+    if (tid < HY) syw[tid] = wrapn(y0 + tid - R, ny);
+    __syncthreads();
+  }
 
   // stage one density plane (global plane zz, periodic) into its ring slot
   auto load_rho = [&](int zz) {
     const int sl = rslot(zz);
-    const long long zoff = (long long)wrapn(zz, nz) * nxy;
+    const uint32_t zoff = (uint32_t)wrapn(zz, nz) * nxy;
     for (int k = tid; k < NH; k += NT) {
       const int lx = k % HX, ly = k / HX;
-      const long long g = zoff + sxw[lx] + (long long)nx * syw[ly];
+      const uint32_t g = zoff + (uint32_t)sxw[lx] + (uint32_t)nx * (uint32_t)syw[ly];
       const bool sol = ((s.mask[g] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
-      ssol[sl][k] = sol;
       const T rw = s.rho[g];
-      srho[sl][0][k] = rw;
-      if (NC == 2) {
-        const T ro = s.rho[N + g];
-        srho[sl][NC - 1][k] = ro;
-        sS[sl][k] = sol ? (T)0 : (rw / (rw + ro) - mc.s_min) / span;
-      }
+      const T ro = s.rho[N + g];
+      T4 e;
+      e.x = rw;
+      e.y = ro;
+      e.z = sol ? (T)0 : (rw * rcp(rw + ro) - mc.s_min) * mc.inv_span;
+      e.w = sol ? (T)1 : (T)0;
+      srho[sl][k] = e;
     }
   };
   // CSF normals of plane zz from the density planes zz-1 .. zz+1
   auto make_normals = [&](int zz) {
     const int ms = mslot(zz);
+    const int sc0 = rslot(zz);
     for (int k = tid; k < NM; k += NT) {
       const int mx_ = k % MX, my_ = k / MX;
       const int c = (mx_ + 1) + HX * (my_ + 1);
-      const int sc0 = rslot(zz);
-      const bool sol = ssol[sc0][c];
+      const T4 self = srho[sc0][c];
+      const bool sol = self.w != (T)0;
+      T gw0 = 0, gw1 = 0, gw2 = 0, go0 = 0, go1 = 0, go2 = 0;  // grad rho_w, grad rho_o
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const T self = srho[sc0][1 - a][c];
-        T g0 = 0, g1 = 0, g2 = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const int sl = rslot(zz + cz(i));
-          const int cc = c + hoff(i);
-          const T val = ssol[sl][cc] ? self : srho[sl][1 - a][cc];
-          if (cx(i)) g0 += (T)(gw(i) * cx(i)) * val;
-          if (cy(i)) g1 += (T)(gw(i) * cy(i)) * val;
-          if (cz(i)) g2 += (T)(gw(i) * cz(i)) * val;
-        }
-        const T n = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
-        const bool big = !sol && n > mc.eps_n;
-        snrm[ms][a * 3 + 0][k] = big ? g0 / n : (T)0;
-        snrm[ms][a * 3 + 1][k] = big ? g1 / n : (T)0;
-        snrm[ms][a * 3 + 2][k] = big ? g2 / n : (T)0;
+      for (int i = 1; i < Q; ++i) {
+        const T4 e = srho[rslot(zz + cz(i))][c + hoff(i)];
+        const bool ns = e.w != (T)0;
+        const T vw = ns ? self.x : e.x;
+        const T vo = ns ? self.y : e.y;
+        if (cx(i)) { gw0 += (T)(gw(i) * cx(i)) * vw; go0 += (T)(gw(i) * cx(i)) * vo; }
+        if (cy(i)) { gw1 += (T)(gw(i) * cy(i)) * vw; go1 += (T)(gw(i) * cy(i)) * vo; }
+        if (cz(i)) { gw2 += (T)(gw(i) * cz(i)) * vw; go2 += (T)(gw(i) * cz(i)) * vo; }
       }
+      // n^w follows grad rho_o, n^o follows grad rho_w
+      const T qo = go0 * go0 + go1 * go1 + go2 * go2;
+      const T qw = gw0 * gw0 + gw1 * gw1 + gw2 * gw2;
+      const bool bo = !sol && qo > mc.eps_n2;
+      const bool bw = !sol && qw > mc.eps_n2;
+      const T io = bo ? rsq(qo) : (T)0;
+      const T iw = bw ? rsq(qw) : (T)0;
+      snrm[ms][0][k] = T4{go0 * io, go1 * io, go2 * io, (T)0};
+      snrm[ms][1][k] = T4{gw0 * iw, gw1 * iw, gw2 * iw, (T)0};
     }
   };
 
@@ -227,15 +249,22 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   const bool inside = x < nx && y < ny;
   const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
   const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const int X3[3] = {xm, x, xp};
-  const int Y3[3] = {ym * nx, y * nx, yp * nx};
+  const uint32_t X3[3] = {(uint32_t)xm, (uint32_t)x, (uint32_t)xp};
+  const uint32_t Y3[3] = {(uint32_t)(ym * nx), (uint32_t)(y * nx), (uint32_t)(yp * nx)};
+  const uint32_t vxy = (uint32_t)x + (uint32_t)y * (uint32_t)nx;  // in-plane voxel index
   const int c = (tx + R) + HX * (ty + R);
   const int cn = (tx + 1) + MX * (ty + 1);
   const T cs2 = (T)CS2;
+  rsrc_t rin[NC], rout[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    rin[a] = make_rsrc(fin + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
+    rout[a] = make_rsrc(fout + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
+  }
 
   for (int z = zs; z < ze; ++z) {
     if (STENCIL) {
-      __syncthreads();  // previous plane done with the slot reused below
+      __syncthreads();  // the previous plane is done with the slot reused below
       load_rho(z + 2);
       __syncthreads();
       if (csf) {
@@ -244,47 +273,59 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
       }
     }
     if (!inside) continue;
-    const long long v = x + (long long)nx * y + (long long)z * nxy;
-    const uint32_t v32 = (uint32_t)v;
-    const uint32_t N32 = (uint32_t)N;
+    const uint32_t zoff = (uint32_t)z * nxy;
+    const uint32_t v = vxy + zoff;
     const uint32_t mk = s.mask[v];
     const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
     if (cl == SOLID_CODE) continue;
     const bool gray = cl == GRAY_CODE;
     const int zm1 = z == 0 ? nz - 1 : z - 1, zp1 = z == nz - 1 ? 0 : z + 1;
-    const uint32_t Z3[3] = {(uint32_t)(zm1 * nxy), (uint32_t)(z * nxy), (uint32_t)(zp1 * nxy)};
+    const uint32_t Z3[3] = {(uint32_t)zm1 * nxy, zoff, (uint32_t)zp1 * nxy};
 
-    // a1 + a2: pull with bounce-back, moments accumulated on the fly
-    T rho[NC], mom[NC][3], P[NC][6];
+    // a1 + a2: pull with bounce-back; moments accumulated over opposite pairs
+    T rho[NC], mom[NC][3], P[NC][6];  // P: xx, yy, zz, xy, xz, yz
     T f[REG ? 1 : NC][REG ? 1 : Q];
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-      const rsrc_t rin = make_rsrc(fin + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
-      T r = 0, m0 = 0, m1 = 0, m2 = 0, pxx = 0, pyy = 0, pzz = 0, pxy = 0, pxz = 0, pyz = 0;
+      const T f0 = bload(rin[a], v * ES, (T)0);
+      if (!REG) f[REG ? 0 : a][0] = f0;
+      rho[a] = f0;
+      mom[a][0] = mom[a][1] = mom[a][2] = 0;
 #pragma unroll
-      for (int i = 0; i < Q; ++i) {
-        const int j = opp(i);
-        const uint32_t e = ((mk >> j) & 1u)
-                               ? (uint32_t)j * N32 + v32
-                               : (uint32_t)i * N32 + (uint32_t)(X3[1 - cx(i)] + Y3[1 - cy(i)]) +
-                                     Z3[1 - cz(i)];
-        const T val = bload(rin, e * (uint32_t)sizeof(T), (T)0);
-        if (!REG) f[REG ? 0 : a][REG ? 0 : i] = val;
-        r += val;
-        if (cx(i)) { m0 += (T)cx(i) * val; pxx += val; }
-        if (cy(i)) { m1 += (T)cy(i) * val; pyy += val; }
-        if (cz(i)) { m2 += (T)cz(i) * val; pzz += val; }
-        if (cx(i) && cy(i)) pxy += (T)(cx(i) * cy(i)) * val;
-        if (cx(i) && cz(i)) pxz += (T)(cx(i) * cz(i)) * val;
-        if (cy(i) && cz(i)) pyz += (T)(cy(i) * cz(i)) * val;
-      }
-      rho[a] = r;
-      mom[a][0] = m0; mom[a][1] = m1; mom[a][2] = m2;
-      P[a][0] = pxx; P[a][1] = pyy; P[a][2] = pzz; P[a][3] = pxy; P[a][4] = pxz; P[a][5] = pyz;
+      for (int d = 0; d < 6; ++d) P[a][d] = 0;
     }
-    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const int j = i + 1;  // opposite of i
+      // pull source of i is x - c_i, of j is x + c_i; bounce-back takes the
+      // opposite population of this voxel when the source is solid
+      const uint32_t oi = ((mk >> j) & 1u)
+                              ? (uint32_t)j * N32 + v
+                              : (uint32_t)i * N32 + X3[1 - cx(i)] + Y3[1 - cy(i)] + Z3[1 - cz(i)];
+      const uint32_t oj = ((mk >> i) & 1u)
+                              ? (uint32_t)i * N32 + v
+                              : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        const T fi = bload(rin[a], oi * ES, (T)0);
+        const T fj = bload(rin[a], oj * ES, (T)0);
+        if (!REG) {
+          f[REG ? 0 : a][i] = fi;
+          f[REG ? 0 : a][j] = fj;
+        }
+        const T sm = fi + fj, df = fi - fj;
+        rho[a] += sm;
+        if (cx(i)) { mom[a][0] += cx(i) > 0 ? df : -df; P[a][0] += sm; }
+        if (cy(i)) { mom[a][1] += cy(i) > 0 ? df : -df; P[a][1] += sm; }
+        if (cz(i)) { mom[a][2] += cz(i) > 0 ? df : -df; P[a][2] += sm; }
+        if (cx(i) && cy(i)) P[a][3] += cx(i) * cy(i) > 0 ? sm : -sm;
+        if (cx(i) && cz(i)) P[a][4] += cx(i) * cz(i) > 0 ? sm : -sm;
+        if (cy(i) && cz(i)) P[a][5] += cy(i) * cz(i) > 0 ? sm : -sm;
+      }
+    }
     T rt = rho[0];
     if (NC == 2) rt = rho[0] + rho[1];
+    const T irt = rcp(rt);
 
     T Fex[NC][3];
 #pragma unroll
@@ -299,65 +340,80 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
         ro_res = s.r[N + v];
       }
       const T tw = rho[0] + rw_res, to = rho[1] + ro_res;
-      const T sat = tw / (tw + to);
-      S = (sat - mc.s_min) / span;
-      S = S < (T)0 ? (T)0 : (S > (T)1 ? (T)1 : S);
       rhoT = tw + to;
-      // a3: pseudo-potential force (solid neighbours: local density + wetting offset)
+      S = (tw * rcp(rhoT) - mc.s_min) * mc.inv_span;
+      S = S < (T)0 ? (T)0 : (S > (T)1 ? (T)1 : S);
+      // a3: pseudo-potential sums acc_b = sum_i w_i c_i psi_b(x + c_i); a solid
+      // neighbour enters with the local density plus the wetting offset
+      T pw[2];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) {
-        const int bb = 1 - a;
-        T pw = rho[bb] + mc.wall_dpsi[bb];
-        pw = pw > (T)0 ? pw : (T)0;
-        T acc0 = 0, acc1 = 0, acc2 = 0;
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const T psi = ((mk >> i) & 1u) ? pw : srho[rslot(z + cz(i))][bb][c + hoff(i)];
-          if (cx(i)) acc0 += (T)(wq(i) * cx(i)) * psi;
-          if (cy(i)) acc1 += (T)(wq(i) * cy(i)) * psi;
-          if (cz(i)) acc2 += (T)(wq(i) * cz(i)) * psi;
-        }
-        const T k = -mc.G * rho[a];
-        Fex[a][0] += k * acc0;
-        Fex[a][1] += k * acc1;
-        Fex[a][2] += k * acc2;
-        __builtin_amdgcn_sched_barrier(0);
+      for (int bb = 0; bb < 2; ++bb) {
+        const T p_ = rho[bb] + mc.wall_dpsi[bb];
+        pw[bb] = p_ > (T)0 ? p_ : (T)0;
       }
-      // a3: CSF surface-tension control, Eq. (4)
-      if (csf && (gray || mc.csf_all)) {
+      T aw0 = 0, aw1 = 0, aw2 = 0, ao0 = 0, ao1 = 0, ao2 = 0;
 #pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const T self = rho[1 - a];
-          const int m0s = mslot(z);
-          T gr0 = 0, gr1 = 0, gr2 = 0, dv = 0;
+      for (int i = 1; i < Q; ++i) {
+        const T4 e = srho[rslot(z + cz(i))][c + hoff(i)];
+        const bool sol = (mk >> i) & 1u;
+        const T vw = sol ? pw[0] : e.x;
+        const T vo = sol ? pw[1] : e.y;
+        if (cx(i)) { aw0 += (T)(wq(i) * cx(i)) * vw; ao0 += (T)(wq(i) * cx(i)) * vo; }
+        if (cy(i)) { aw1 += (T)(wq(i) * cy(i)) * vw; ao1 += (T)(wq(i) * cy(i)) * vo; }
+        if (cz(i)) { aw2 += (T)(wq(i) * cz(i)) * vw; ao2 += (T)(wq(i) * cz(i)) * vo; }
+      }
+      {
+        const T kw = -mc.G * rho[0], ko = -mc.G * rho[1];
+        Fex[0][0] += kw * ao0; Fex[0][1] += kw * ao1; Fex[0][2] += kw * ao2;
+        Fex[1][0] += ko * aw0; Fex[1][1] += ko * aw1; Fex[1][2] += ko * aw2;
+      }
+      // a3: CSF surface-tension control, Eq. (4).  The Neumann gradient of
+      // rho_b differs from 3 acc_b only through the solid links.
+      if (csf && (gray || mc.csf_all)) {
+        T sw0 = 0, sw1 = 0, sw2 = 0;  // sum over solid links of w_i c_i
+        if (mk & 0x7fffeu) {
 #pragma unroll
           for (int i = 1; i < Q; ++i) {
-            const bool sol = (mk >> i) & 1u;
-            const T val = sol ? self : srho[rslot(z + cz(i))][1 - a][c + hoff(i)];
-            const int ms = sol ? m0s : mslot(z + cz(i));
-            const int u = sol ? cn : cn + moff(i);
-            if (cx(i)) gr0 += (T)(gw(i) * cx(i)) * val;
-            if (cy(i)) gr1 += (T)(gw(i) * cy(i)) * val;
-            if (cz(i)) gr2 += (T)(gw(i) * cz(i)) * val;
-            if (cx(i)) dv += (T)(gw(i) * cx(i)) * snrm[ms][a * 3 + 0][u];
-            if (cy(i)) dv += (T)(gw(i) * cy(i)) * snrm[ms][a * 3 + 1][u];
-            if (cz(i)) dv += (T)(gw(i) * cz(i)) * snrm[ms][a * 3 + 2][u];
+            const T on = ((mk >> i) & 1u) ? (T)wq(i) : (T)0;
+            if (cx(i)) sw0 += (T)cx(i) * on;
+            if (cy(i)) sw1 += (T)cy(i) * on;
+            if (cz(i)) sw2 += (T)cz(i) * on;
           }
-          const T k = mc.kappa * (-dv);
-          const T sc = mc.csf_den;
-          Fex[a][0] += k * gr0 * rho[a] / sc;
-          Fex[a][1] += k * gr1 * rho[a] / sc;
-          Fex[a][2] += k * gr2 * rho[a] / sc;
-          __builtin_amdgcn_sched_barrier(0);
         }
+        const T dw = pw[0] - rho[0], dox = pw[1] - rho[1];
+        const T grw0 = (T)3 * (aw0 - dw * sw0), grw1 = (T)3 * (aw1 - dw * sw1),
+                grw2 = (T)3 * (aw2 - dw * sw2);
+        const T gro0 = (T)3 * (ao0 - dox * sw0), gro1 = (T)3 * (ao1 - dox * sw1),
+                gro2 = (T)3 * (ao2 - dox * sw2);
+        const int m0s = mslot(z);
+        T dvw = 0, dvo = 0;  // div n^w, div n^o
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const bool sol = (mk >> i) & 1u;
+          const int ms = sol ? m0s : mslot(z + cz(i));
+          const int u = sol ? cn : cn + moff(i);
+          const T4 nw = snrm[ms][0][u];
+          const T4 no = snrm[ms][1][u];
+          const T k = (T)gw(i);
+          T tw_ = 0, to_ = 0;
+          if (cx(i)) { tw_ += (T)cx(i) * nw.x; to_ += (T)cx(i) * no.x; }
+          if (cy(i)) { tw_ += (T)cy(i) * nw.y; to_ += (T)cy(i) * no.y; }
+          if (cz(i)) { tw_ += (T)cz(i) * nw.z; to_ += (T)cz(i) * no.z; }
+          dvw += k * tw_;
+          dvo += k * to_;
+        }
+        // F_csf^a = kappa (-div n^a) grad rho^b rho^a / (phi_avg phi_max)
+        const T kw = -mc.csf_fac * dvw * rho[0], ko = -mc.csf_fac * dvo * rho[1];
+        Fex[0][0] += kw * gro0; Fex[0][1] += kw * gro1; Fex[0][2] += kw * gro2;
+        Fex[1][0] += ko * grw0; Fex[1][1] += ko * grw1; Fex[1][2] += ko * grw2;
       }
       // a4: capillary term of Eq. (1) and the resistance coefficient
       if (gray) {
-        const T shat0 = (rho[0] / rt - mc.s_min) / span;
+        const T shat0 = (rho[0] * irt - mc.s_min) * mc.inv_span;
         T g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          const T val = ((mk >> i) & 1u) ? shat0 : sS[rslot(z + cz(i))][c + hoff(i)];
+          const T val = ((mk >> i) & 1u) ? shat0 : srho[rslot(z + cz(i))][c + hoff(i)].z;
           if (cx(i)) g0 += (T)(gw(i) * cx(i)) * val;
           if (cy(i)) g1 += (T)(gw(i) * cy(i)) * val;
           if (cz(i)) g2 += (T)(gw(i) * cz(i)) * val;
@@ -367,17 +423,13 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
         const T Pc = s.sJ[v] * lerp_tab<T>(tb, S);
         const T krw = lerp_tab<T>(tb + TABLE_N, S);
         const T kro = lerp_tab<T>(tb + 2 * TABLE_N, S);
-#pragma unroll
-        for (int a = 0; a < 2; ++a) {
-          const T k = -Pc * (rho[a] / rt);
-          Fex[a][0] += k * g0;
-          Fex[a][1] += k * g1;
-          Fex[a][2] += k * g2;
-        }
+        const T kw = -Pc * rho[0] * irt, ko = -Pc * rho[1] * irt;
+        Fex[0][0] += kw * g0; Fex[0][1] += kw * g1; Fex[0][2] += kw * g2;
+        Fex[1][0] += ko * g0; Fex[1][1] += ko * g1; Fex[1][2] += ko * g2;
         const T Sw = S, So = (T)1 - S;
         const T krmin = mc.kr_min;
-        const T cw = Sw > (T)0 ? rt * Sw * mc.nu[0] / (krw > krmin ? krw : krmin) : (T)0;
-        const T co = So > (T)0 ? rt * So * mc.nu[1] / (kro > krmin ? kro : krmin) : (T)0;
+        const T cw = Sw > (T)0 ? rt * Sw * mc.nu[0] * rcp(krw > krmin ? krw : krmin) : (T)0;
+        const T co = So > (T)0 ? rt * So * mc.nu[1] * rcp(kro > krmin ? kro : krmin) : (T)0;
         cR = cw + co;
       }
     } else if (gray) {
@@ -406,19 +458,19 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
               c02 = a01 * a12 - a02 * a11;
       const T c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12,
               c22 = a00 * a11 - a01 * a01;
-      const T det = a00 * c00 + a01 * c01 + a02 * c02;
-      const T u0 = (c00 * b0 + c01 * b1 + c02 * b2) / det;
-      const T u1 = (c01 * b0 + c11 * b1 + c12 * b2) / det;
-      const T u2 = (c02 * b0 + c12 * b1 + c22 * b2) / det;
+      const T idet = rcp(a00 * c00 + a01 * c01 + a02 * c02);
+      const T u0 = (c00 * b0 + c01 * b1 + c02 * b2) * idet;
+      const T u1 = (c01 * b0 + c11 * b1 + c12 * b2) * idet;
+      const T u2 = (c02 * b0 + c12 * b1 + c22 * b2) * idet;
       Ru0 = Rxx * u0 + Rxy * u1 + Rxz * u2;
       Ru1 = Rxy * u0 + Ryy * u1 + Ryz * u2;
       Ru2 = Rxz * u0 + Ryz * u1 + Rzz * u2;
     } else if (gray) {
-      const T Rs = cR / s.K0[v];
-      const T den = rt + (T)0.5 * Rs;
-      Ru0 = Rs * (b0 / den);
-      Ru1 = Rs * (b1 / den);
-      Ru2 = Rs * (b2 / den);
+      const T Rs = cR * rcp(s.K0[v]);
+      const T q = Rs * rcp(rt + (T)0.5 * Rs);
+      Ru0 = q * b0;
+      Ru1 = q * b1;
+      Ru2 = q * b2;
     }
 
     // a6: Shan-Chen common velocity u'
@@ -429,7 +481,8 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
       den += rho[a] * om;
       up0 += mom[a][0] * om; up1 += mom[a][1] * om; up2 += mom[a][2] * om;
     }
-    up0 /= den; up1 /= den; up2 /= den;
+    const T iden = rcp(den);
+    up0 *= iden; up1 *= iden; up2 *= iden;
     const T usq = up0 * up0 + up1 * up1 + up2 * up2;
 
     // a7: residual transfer (gray voxels) as per-component scale factors
@@ -467,20 +520,20 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       const T ra = rho[a];
-      const T kr = rho[a] / rt;
+      const T kr = ra * irt;
       const T Fa0 = Fex[a][0] - kr * Ru0, Fa1 = Fex[a][1] - kr * Ru1, Fa2 = Fex[a][2] - kr * Ru2;
-      const T h2 = (T)2 * ra;
-      const T ua0 = up0 + Fa0 / h2, ua1 = up1 + Fa1 / h2, ua2 = up2 + Fa2 / h2;
+      const T ih2 = (T)0.5 * rcp(ra);
+      const T ua0 = up0 + Fa0 * ih2, ua1 = up1 + Fa1 * ih2, ua2 = up2 + Fa2 * ih2;
       const T uF = ua0 * Fa0 + ua1 * Fa1 + ua2 * Fa2;
       const T om = mc.omega[a];
       const T keep = (T)1 - om;
-      // equilibrium part (weight omega for BGK, 1 for the projected form)
-      const T we = REG ? (T)1 : om;
-      T A = we * ra * ((T)1 - (T)1.5 * usq) - (T)3 * uF;
-      T B0 = (T)3 * (we * ra * up0 + Fa0);
-      T B1 = (T)3 * (we * ra * up1 + Fa1);
-      T B2 = (T)3 * (we * ra * up2 + Fa2);
-      const T er = (T)4.5 * we * ra;
+      const T we = REG ? (T)1 : om;  // weight of the equilibrium part
+      const T wr = we * ra;
+      T A = wr * ((T)1 - (T)1.5 * usq) - (T)3 * uF;
+      T B0 = (T)3 * (wr * up0 + Fa0);
+      T B1 = (T)3 * (wr * up1 + Fa1);
+      T B2 = (T)3 * (wr * up2 + Fa2);
+      const T er = (T)4.5 * wr;
       T Cxx = er * up0 * up0 + (T)9 * ua0 * Fa0;
       T Cyy = er * up1 * up1 + (T)9 * ua1 * Fa1;
       T Czz = er * up2 * up2 + (T)9 * ua2 * Fa2;
@@ -503,9 +556,8 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
         Cxy += k45 * qxy; Cxz += k45 * qxz; Cyz += k45 * qyz;
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
-      const rsrc_t rout = make_rsrc(fout + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
-      emit_post<T, REG>(rout, v32, N32, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy, Cxz, Cyz, sc,
-                        f[REG ? 0 : a], keep);
+      emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy,
+                        Cxz, Cyz, sc, f[REG ? 0 : a], keep);
     }
   }
 }

@@ -61,7 +61,13 @@ def test_ragged_grid_fp64_bgk():
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, n), 1.0)
     pt = np.where(cls == 2, rng.integers(0, 2, n), 0).astype(np.uint8)
     wl0 = W.multiscale_rock(n=8, precision="f64")
-    rw = np.where(rng.random(n) < 0.5, 1.0, p.m_minor)
+    # two smooth water blobs; the minority density dips slightly below zero
+    # near them, which a sign-coded solid marker once confused
+    z, y, x = np.meshgrid(np.arange(11), np.arange(13), np.arange(17), indexing="ij")
+    r1 = np.sqrt((x - 5) ** 2 + (y - 6) ** 2 + (z - 5) ** 2)
+    r2 = np.sqrt((x - 13) ** 2 + (y - 3) ** 2 + (z - 8) ** 2)
+    prof = 0.5 * (1 - np.tanh((r1 - 3.5) / 1.5)) + 0.5 * (1 - np.tanh((r2 - 2.5) / 1.5))
+    rw = p.m_minor + (1 - p.m_minor) * np.clip(prof, 0, 1)
     wl = dict(params=p, cls=cls, phi=phi, ptype=pt, tables=wl0["tables"][:2], rho_w=rw,
               rho_o=1.0 + p.m_minor - rw)
     _check64(wl, 25, "ragged 17x13x11")
@@ -93,10 +99,10 @@ def test_setup_parity_fp64():
     lb.destroy()
 
 
-def _random_state_case(ncomp, seed=11):
+def _random_state_case(ncomp, seed=11, collision="regularized", region="gray"):
     import test_oracle_brute as TB
-    p, cls, phi, ptype, tabs, rw, ro, rng = TB.tiny_case(ncomp, "regularized", seed=seed,
-                                                         n=(6, 7, 9))
+    p, cls, phi, ptype, tabs, rw, ro, rng = TB.tiny_case(ncomp, collision, seed=seed,
+                                                         n=(6, 7, 9), region=region)
     o = Oracle(p)
     o.set_geometry(cls, phi, ptype, tabs)
     o.init_fluid(rw, ro)
@@ -109,13 +115,16 @@ def _random_state_case(ncomp, seed=11):
     return p, cls, phi, ptype, tabs, o
 
 
-@pytest.mark.parametrize("ncomp", [2, 1])
-def test_one_step_from_arbitrary_state(ncomp):
+@pytest.mark.parametrize("ncomp,collision,region", [(2, "regularized", "gray"),
+                                                    (1, "regularized", "gray"),
+                                                    (2, "bgk", "all"), (1, "bgk", "gray"),
+                                                    (2, "regularized", "all")])
+def test_one_step_from_arbitrary_state(ncomp, collision, region):
     """Transplant a perturbed oracle state (with pending residual events) into
     the GPU and compare the post-streaming populations after each step."""
     import paper_2512_21696_amd as L
-    p, cls, phi, ptype, tabs, o = _random_state_case(ncomp)
-    announce(f"state transplant ncomp={ncomp}")
+    p, cls, phi, ptype, tabs, o = _random_state_case(ncomp, collision=collision, region=region)
+    announce(f"state transplant ncomp={ncomp} {collision} csf region {region}")
     lb = L.lbm_create(p)
     lb.set_geometry(cls, phi, ptype, tabs)
     lb.set_state(L.make_state_blob(lb, o.f, o.r, o.side.astype(np.uint8)))
