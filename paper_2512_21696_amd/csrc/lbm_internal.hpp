@@ -36,7 +36,8 @@ struct ModelConsts {
 template <typename T>
 struct DevState {
   T *f[2];           // populations, two copies; layout [a][i][v]
-  T *rho;            // densities at the current level [a][v]
+  T *rho;            // densities at the current level [a][v] (field evaluation)
+  T *rho2;           // the same, interleaved [v][a] (fused step)
   T *nrm;            // CSF normals [a][3][v] (only when kappa != 0)
   uint32_t *mask;    // neighbour-solid bits and class
   uint8_t *ptype;    // pore type per voxel

@@ -45,7 +45,7 @@ struct lbm_handle {
   long long N = 0;
   int cur = 0;
   int ntab = 0;
-  bool has_geom = false, has_fluid = false, rho_valid = false;
+  bool has_geom = false, has_fluid = false, rho_valid = false, rho2_valid = false;
   int64_t step = 0;
   DevState<double> sd{};
   DevState<float> sf{};
@@ -159,6 +159,7 @@ int alloc_state(lbm_handle *h) {
   s.f[0] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
   s.f[1] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
   s.rho = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+  s.rho2 = alloc_into<T>(h, L, (size_t)2 * N, &ok);
   s.nrm = (h->p.ncomp == 2 && h->p.kappa != 0.0) ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
   s.mask = alloc_into<uint32_t>(h, L, (size_t)N, &ok);
   s.ptype = alloc_into<uint8_t>(h, L, (size_t)N, &ok);
@@ -329,7 +330,7 @@ void ensure_aux(lbm_handle *h) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
   if (!h->rho_valid) {
-    Timed tm(h, K_AUX);
+    Timed tm(h, K_OTHER);
     if (h->p.ncomp == 2)
       hipLaunchKernelGGL((k_moments<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
                          s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
@@ -337,6 +338,20 @@ void ensure_aux(lbm_handle *h) {
       hipLaunchKernelGGL((k_moments<T, 1>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
                          s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
     h->rho_valid = true;
+  }
+}
+
+// Interleaved densities for the fused step (only the two-component model
+// reads neighbour densities)
+template <typename T>
+void ensure_density(lbm_handle *h) {
+  DevState<T> &s = state<T>(h);
+  const long long N = h->N;
+  if (h->p.ncomp == 2 && !h->rho2_valid) {
+    Timed tm(h, K_AUX);
+    hipLaunchKernelGGL((k_density<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
+                       s.rho2, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+    h->rho2_valid = true;
   }
 }
 
@@ -427,10 +442,11 @@ int step_t(lbm_handle *h, int64_t n) {
   const long long N = h->N;
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
   for (int64_t k = 0; k < n; ++k) {
-    ensure_aux<T>(h);
+    ensure_density<T>(h);
     launch_step<T, MODE_STEP, T>(h, FieldsOut{});
     h->cur = 1 - h->cur;
     h->rho_valid = false;
+    h->rho2_valid = false;
     h->step += 1;
     if (h->p.track_flux) {
       Timed tm(h, K_OTHER);
@@ -483,6 +499,7 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
                        h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
   }
   h->rho_valid = false;
+  h->rho2_valid = false;
   if (rc == LBM_OK) {
     ensure_aux<T>(h);
     Timed tm(h, K_OTHER);
@@ -617,6 +634,7 @@ int set_state_t(lbm_handle *h, const void *buf) {
   if (rc == LBM_OK) {
     h->step = hd.step;
     h->rho_valid = false;
+    h->rho2_valid = false;
     h->has_fluid = true;
   }
   return rc;

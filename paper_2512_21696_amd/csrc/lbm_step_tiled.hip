@@ -32,7 +32,7 @@ constexpr int HX = TX + 2 * R, HY = TY + 2 * R;
 constexpr int NH = HX * HY;  // density plane cells
 constexpr int MX = TX + 2, MY = TY + 2;
 constexpr int NM = MX * MY;  // normal plane cells
-constexpr int RS = 4;        // density planes z-1 .. z+2
+constexpr int RS = 5;        // density planes z-2 .. z+2
 constexpr int MS = 3;        // normal planes z-1 .. z+1
 constexpr int ZC = 32;       // planes per block
 __host__ __device__ constexpr int hoff(int i) { return cx(i) + HX * cy(i); }
@@ -75,6 +75,7 @@ template <> __device__ inline float rsq<float>(float x) { return __builtin_amdgc
 template <> __device__ inline double rsq<double>(double x) { return 1.0 / sqrt(x); }
 
 template <typename T> struct vec4 { T x, y, z, w; };
+template <typename T> struct alignas(2 * sizeof(T)) vec2 { T x, y; };
 
 __device__ inline int wrapn(int v, int n) {
   v %= n;
@@ -101,7 +102,7 @@ __device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) 
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
 }
 
-__device__ inline int rslot(int z) { return (z + 8) & 3; }
+__device__ inline int rslot(int z) { return (z + 10) % 5; }
 __device__ inline int mslot(int z) { return (z + 9) % 3; }
 
 // Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus
@@ -111,7 +112,7 @@ template <typename T, bool REG>
 __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sbase,
                                           uint32_t Nbytes, T A, T B0, T B1, T B2, T Cxx, T Cyy,
                                           T Czz, T Cxy, T Cxz, T Cyz, T sc, const T *fpop,
-                                          T keep) {
+                                          T keep, bool zero) {
   const T w0 = (T)(1.0 / 3.0) * sc, w1 = (T)(1.0 / 18.0) * sc, w2 = (T)(1.0 / 36.0) * sc;
   T v[Q];
   v[0] = w0 * A;
@@ -144,8 +145,56 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
   for (int i = 0; i < Q; ++i) {
     T val = v[i];
     if (!REG) val += keep * sc * fpop[i];
-    bstore(out, voff, sbase + (uint32_t)i * Nbytes, val);
+    bstore(out, voff, sbase + (uint32_t)i * Nbytes, zero ? (T)0 : val);
   }
+}
+
+// Densities of the current level for the fused step: the pull of every
+// population (bounce-back at solid sources) summed per component, written
+// interleaved [v][rho_w, rho_o].  Solid voxels get zero.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_density(const T *__restrict__ fin, T *__restrict__ rho2,
+                                                 const uint32_t *__restrict__ mask, int nx, int ny,
+                                                 int nz, long long N) {
+  const uint32_t v = blockIdx.x * 256u + threadIdx.x;
+  if (v >= (uint32_t)N) return;
+  const uint32_t mk = mask[v];
+  vec2<T> *out = reinterpret_cast<vec2<T> *>(rho2);
+  if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) {
+    out[v] = vec2<T>{(T)0, (T)0};
+    return;
+  }
+  const uint32_t N32 = (uint32_t)N;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const uint32_t z = v / nxy;
+  const uint32_t rem = v - z * nxy;
+  const uint32_t y = rem / (uint32_t)nx;
+  const uint32_t x = rem - y * (uint32_t)nx;
+  const uint32_t X3[3] = {x == 0 ? nx - 1 : x - 1, x, x == (uint32_t)nx - 1 ? 0 : x + 1};
+  const uint32_t Y3[3] = {(y == 0 ? ny - 1 : y - 1) * nx, y * nx,
+                          (y == (uint32_t)ny - 1 ? 0 : y + 1) * nx};
+  const uint32_t Z3[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy,
+                          (z == (uint32_t)nz - 1 ? 0 : z + 1) * nxy};
+  constexpr uint32_t ES = (uint32_t)sizeof(T);
+  T r[2] = {0, 0};
+#pragma unroll
+  for (int a = 0; a < NC; ++a) {
+    const rsrc_t rin = make_rsrc(fin + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
+    T acc = bload(rin, v * ES, (T)0);
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const int j = i + 1;
+      const uint32_t oi = ((mk >> j) & 1u)
+                              ? (uint32_t)j * N32 + v
+                              : (uint32_t)i * N32 + X3[1 - cx(i)] + Y3[1 - cy(i)] + Z3[1 - cz(i)];
+      const uint32_t oj = ((mk >> i) & 1u)
+                              ? (uint32_t)i * N32 + v
+                              : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
+      acc += bload(rin, oi * ES, (T)0) + bload(rin, oj * ES, (T)0);
+    }
+    r[a] = acc;
+  }
+  out[v] = vec2<T>{r[0], r[1]};
 }
 
 template <typename T, int NC, bool REG>
@@ -156,8 +205,10 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   using namespace zm;
   constexpr bool STENCIL = NC == 2;
   using T4 = vec4<T>;
-  __shared__ T4 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];     // rho_w, rho_o, S_hat, solid
-  __shared__ T4 snrm[STENCIL ? MS : 1][2][STENCIL ? NM : 1];  // n^w, n^o
+  using T2 = vec2<T>;
+  __shared__ T2 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];        // rho_w, rho_o
+  __shared__ uint8_t ssol[STENCIL ? RS : 1][STENCIL ? NH : 1];   // solid flag
+  __shared__ T2 snrm[STENCIL ? MS : 1][3][STENCIL ? NM : 1];     // (n^w_d, n^o_d), d = x,y,z
   __shared__ int sxw[HX], syw[HY];
 
   const int nb = gridDim.x;
@@ -179,29 +230,47 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   const int ze = zs + ZC < nz ? zs + ZC : nz;
   const bool csf = STENCIL && mc.kappa != (T)0;
   constexpr uint32_t ES = (uint32_t)sizeof(T);
+  const T2 *rho2 = reinterpret_cast<const T2 *>(s.rho2);
 
+  // Staging of one density plane: each thread owns up to 3 cells of the
+  // (64+4) x (4+4) plane; the global loads are issued one plane ahead into
+  // registers and written to LDS after the barrier-free voxel work.
+  constexpr int CPT = (NH + NT - 1) / NT;
+  uint32_t cell_g[CPT];  // in-plane voxel index of each owned cell
+  T2 pre_r[CPT];
+  uint32_t pre_m[CPT];
   if (STENCIL) {
     if (tid < HX) sxw[tid] = wrapn(x0 + tid - R, nx);
     if (tid < HY) syw[tid] = wrapn(y0 + tid - R, ny);
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int k = tid + q * NT;
+      const int kk = k < NH ? k : 0;
+      const int lx = kk % HX, ly = kk / HX;
+      cell_g[q] = (uint32_t)sxw[lx] + (uint32_t)nx * (uint32_t)syw[ly];
+    }
   }
-
-  // stage one density plane (global plane zz, periodic) into its ring slot
-  auto load_rho = [&](int zz) {
-    const int sl = rslot(zz);
+  auto fetch_rho = [&](int zz) {
     const uint32_t zoff = (uint32_t)wrapn(zz, nz) * nxy;
-    for (int k = tid; k < NH; k += NT) {
-      const int lx = k % HX, ly = k / HX;
-      const uint32_t g = zoff + (uint32_t)sxw[lx] + (uint32_t)nx * (uint32_t)syw[ly];
-      const bool sol = ((s.mask[g] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
-      const T rw = s.rho[g];
-      const T ro = s.rho[N + g];
-      T4 e;
-      e.x = rw;
-      e.y = ro;
-      e.z = sol ? (T)0 : (rw * rcp(rw + ro) - mc.s_min) * mc.inv_span;
-      e.w = sol ? (T)1 : (T)0;
-      srho[sl][k] = e;
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      if (tid + q * NT < NH) {
+        const uint32_t g = zoff + cell_g[q];
+        pre_m[q] = s.mask[g];
+        pre_r[q] = rho2[g];
+      }
+    }
+  };
+  auto store_rho = [&](int zz) {
+    const int sl = rslot(zz);
+#pragma unroll
+    for (int q = 0; q < CPT; ++q) {
+      const int k = tid + q * NT;
+      if (k < NH) {
+        srho[sl][k] = pre_r[q];
+        ssol[sl][k] = ((pre_m[q] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+      }
     }
   };
   // CSF normals of plane zz from the density planes zz-1 .. zz+1
@@ -211,13 +280,14 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
     for (int k = tid; k < NM; k += NT) {
       const int mx_ = k % MX, my_ = k / MX;
       const int c = (mx_ + 1) + HX * (my_ + 1);
-      const T4 self = srho[sc0][c];
-      const bool sol = self.w != (T)0;
+      const T2 self = srho[sc0][c];
+      const bool sol = ssol[sc0][c];
       T gw0 = 0, gw1 = 0, gw2 = 0, go0 = 0, go1 = 0, go2 = 0;  // grad rho_w, grad rho_o
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const T4 e = srho[rslot(zz + cz(i))][c + hoff(i)];
-        const bool ns = e.w != (T)0;
+        const int sl = rslot(zz + cz(i));
+        const T2 e = srho[sl][c + hoff(i)];
+        const bool ns = ssol[sl][c + hoff(i)];
         const T vw = ns ? self.x : e.x;
         const T vo = ns ? self.y : e.y;
         if (cx(i)) { gw0 += (T)(gw(i) * cx(i)) * vw; go0 += (T)(gw(i) * cx(i)) * vo; }
@@ -227,22 +297,25 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
       // n^w follows grad rho_o, n^o follows grad rho_w
       const T qo = go0 * go0 + go1 * go1 + go2 * go2;
       const T qw = gw0 * gw0 + gw1 * gw1 + gw2 * gw2;
-      const bool bo = !sol && qo > mc.eps_n2;
-      const bool bw = !sol && qw > mc.eps_n2;
-      const T io = bo ? rsq(qo) : (T)0;
-      const T iw = bw ? rsq(qw) : (T)0;
-      snrm[ms][0][k] = T4{go0 * io, go1 * io, go2 * io, (T)0};
-      snrm[ms][1][k] = T4{gw0 * iw, gw1 * iw, gw2 * iw, (T)0};
+      const T io = (!sol && qo > mc.eps_n2) ? rsq(qo) : (T)0;
+      const T iw = (!sol && qw > mc.eps_n2) ? rsq(qw) : (T)0;
+      snrm[ms][0][k] = T2{go0 * io, gw0 * iw};
+      snrm[ms][1][k] = T2{go1 * io, gw1 * iw};
+      snrm[ms][2][k] = T2{go2 * io, gw2 * iw};
     }
   };
 
   if (STENCIL) {
-    for (int zz = zs - 2; zz <= zs + 1; ++zz) load_rho(zz);
+    for (int zz = zs - 2; zz <= zs + 1; ++zz) {
+      fetch_rho(zz);
+      store_rho(zz);
+    }
     __syncthreads();
     if (csf) {
       make_normals(zs - 1);
       make_normals(zs);
     }
+    fetch_rho(zs + 2);
   }
 
   const int x = x0 + tx, y = y0 + ty;
@@ -264,20 +337,23 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
 
   for (int z = zs; z < ze; ++z) {
     if (STENCIL) {
-      __syncthreads();  // the previous plane is done with the slot reused below
-      load_rho(z + 2);
+      // plane z+2 reuses the slot of plane z-3, which no wave still reads
+      store_rho(z + 2);
       __syncthreads();
-      if (csf) {
-        make_normals(z + 1);
-        __syncthreads();
-      }
+      if (csf) make_normals(z + 1);
+      __syncthreads();
+      if (z + 1 < ze) fetch_rho(z + 3);
     }
     if (!inside) continue;
     const uint32_t zoff = (uint32_t)z * nxy;
     const uint32_t v = vxy + zoff;
     const uint32_t mk = s.mask[v];
     const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
-    if (cl == SOLID_CODE) continue;
+    // Solid lanes of a wave that also holds fluid voxels run along (their
+    // results are discarded) and store zeros, so that every population store
+    // of the wave writes whole cache lines instead of partial ones.
+    const bool solid = cl == SOLID_CODE;
+    if (__all(solid)) continue;
     const bool gray = cl == GRAY_CODE;
     const int zm1 = z == 0 ? nz - 1 : z - 1, zp1 = z == nz - 1 ? 0 : z + 1;
     const uint32_t Z3[3] = {(uint32_t)zm1 * nxy, zoff, (uint32_t)zp1 * nxy};
@@ -354,7 +430,7 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
       T aw0 = 0, aw1 = 0, aw2 = 0, ao0 = 0, ao1 = 0, ao2 = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const T4 e = srho[rslot(z + cz(i))][c + hoff(i)];
+        const T2 e = srho[rslot(z + cz(i))][c + hoff(i)];
         const bool sol = (mk >> i) & 1u;
         const T vw = sol ? pw[0] : e.x;
         const T vo = sol ? pw[1] : e.y;
@@ -392,15 +468,10 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
           const bool sol = (mk >> i) & 1u;
           const int ms = sol ? m0s : mslot(z + cz(i));
           const int u = sol ? cn : cn + moff(i);
-          const T4 nw = snrm[ms][0][u];
-          const T4 no = snrm[ms][1][u];
           const T k = (T)gw(i);
-          T tw_ = 0, to_ = 0;
-          if (cx(i)) { tw_ += (T)cx(i) * nw.x; to_ += (T)cx(i) * no.x; }
-          if (cy(i)) { tw_ += (T)cy(i) * nw.y; to_ += (T)cy(i) * no.y; }
-          if (cz(i)) { tw_ += (T)cz(i) * nw.z; to_ += (T)cz(i) * no.z; }
-          dvw += k * tw_;
-          dvo += k * to_;
+          if (cx(i)) { const T2 n = snrm[ms][0][u]; dvw += k * (T)cx(i) * n.x; dvo += k * (T)cx(i) * n.y; }
+          if (cy(i)) { const T2 n = snrm[ms][1][u]; dvw += k * (T)cy(i) * n.x; dvo += k * (T)cy(i) * n.y; }
+          if (cz(i)) { const T2 n = snrm[ms][2][u]; dvw += k * (T)cz(i) * n.x; dvo += k * (T)cz(i) * n.y; }
         }
         // F_csf^a = kappa (-div n^a) grad rho^b rho^a / (phi_avg phi_max)
         const T kw = -mc.csf_fac * dvw * rho[0], ko = -mc.csf_fac * dvo * rho[1];
@@ -413,7 +484,11 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
         T g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          const T val = ((mk >> i) & 1u) ? shat0 : srho[rslot(z + cz(i))][c + hoff(i)].z;
+          T val = shat0;
+          if (!((mk >> i) & 1u)) {
+            const T2 e = srho[rslot(z + cz(i))][c + hoff(i)];
+            val = (e.x * rcp(e.x + e.y) - mc.s_min) * mc.inv_span;
+          }
           if (cx(i)) g0 += (T)(gw(i) * cx(i)) * val;
           if (cy(i)) g1 += (T)(gw(i) * cy(i)) * val;
           if (cz(i)) g2 += (T)(gw(i) * cz(i)) * val;
@@ -557,7 +632,7 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
       emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy,
-                        Cxz, Cyz, sc, f[REG ? 0 : a], keep);
+                        Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid);
     }
   }
 }
