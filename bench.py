@@ -46,7 +46,7 @@ def algorithmic_bytes(ncomp, es, gray_frac, tensor):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_runtime.hip"):
+    for f in ("lbm_kernels.hip", "lbm_step_tiled.hip", "lbm_runtime.hip", "lbm_internal.hpp"):
         with open(os.path.join(ROOT, "paper_2512_21696_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -87,6 +87,50 @@ def cpu_baseline(n_crop=64, steps=10):
                       f"after one warm-up step, single thread ({dt:.1f} s)"}
 
 
+def calibrate_copy(mib=1024, narr=38, reps=5):
+    """Yardsticks from libhbmprobe.so: plain copies of a known size (4-byte and
+    16-byte accesses per lane), and a read and a write of 38 arrays of 256^3
+    floats at the same index, one thread per index (the structure-of-arrays population pattern, 2.55
+    GB at 256^3 in fp32).  Their counter readings convert FETCH_SIZE and
+    WRITE_SIZE into bytes; their rates are the practical HBM ceiling."""
+    import ctypes
+    import torch
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_2512_21696_amd", "libhbmprobe.so"))
+    lib.hbm_probe.argtypes = [ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t,
+                              ctypes.c_int, ctypes.c_void_p]
+    torch.cuda.set_device(0)
+    nbytes = mib << 20
+    a = torch.arange(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    arr_bytes = narr * (256 ** 3) * 4
+    big = torch.ones(arr_bytes // 4, dtype=torch.float32, device="cuda")
+    out = torch.empty(256 ** 3, dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    res = {}
+    cases = [("copy_b32", 0, a, b, nbytes, 2 * nbytes), ("copy_b128", 1, a, b, nbytes, 2 * nbytes),
+             ("read_38_arrays", 2, big, out, arr_bytes, arr_bytes),
+             ("write_38_arrays", 3, None, big, arr_bytes, arr_bytes)]
+    for name, kind, src, dst, size, moved in cases:
+        ms = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            rc = lib.hbm_probe(kind, src.data_ptr() if src is not None else None, dst.data_ptr(),
+                               size, narr, ctypes.c_void_p(st.cuda_stream))
+            e1.record(st)
+            if rc != 0:
+                raise RuntimeError(f"hbm_probe {name} failed: {rc}")
+            torch.cuda.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        best = min(ms[1:]) if len(ms) > 1 else ms[0]
+        res[name] = {"bytes_read": size if kind != 3 else 0,
+                     "bytes_written": size if kind in (0, 1) else (size if kind == 3 else 0),
+                     "ms_best": round(best, 4), "gb_per_s": round(moved / (best * 1e-3) / 1e9, 1)}
+    assert torch.equal(a, b)
+    print(json.dumps({"yardsticks": res, "reps": reps}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,11 +140,16 @@ def main():
     ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only time a plain 1 GiB device copy (counter yardstick) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
               f"slab decomposition is a design, not a built path", file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        calibrate_copy()
+        return
 
     import numpy as np
     import torch

@@ -6,6 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
+PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["lbm_runtime.hip", "lbm_validate.cpp"]
@@ -14,12 +15,18 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Wno-unused-result"]
 
 
-def build(verbose: bool = False) -> str:
-    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+def _compile(sources, out, verbose):
+    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", out + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
-    os.replace(LIB + ".tmp", LIB)
+    os.replace(out + ".tmp", out)
+
+
+def build(verbose: bool = False) -> str:
+    """Compiles the method's library and the bandwidth yardstick library."""
+    _compile(SOURCES, LIB, verbose)
+    _compile(["hbm_probe.hip"], PROBE_LIB, verbose)
     return LIB
 
 
