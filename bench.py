@@ -11,7 +11,10 @@ non-finite check) run every --diag-every steps inside the timed region.
 Prints ONE JSON line.  value = fluid-voxel updates per second / 1e6 over the
 timed steps (inputs resident in HBM); the roofline block prices the dominant
 kernel (the fused step) with its algorithmic bytes per fluid update divided
-by its mean launch time from HIP events on the library's stream.
+by its mean launch time from HIP events on the library's stream.  Unless
+--no-compare, the same workload also runs with fp64, fp32, fp16 and bf16
+population storage: "storage_comparison" gives each one's MLUPS and its field
+errors against the fp64 run after the same number of steps.
 """
 import argparse
 import hashlib
@@ -25,15 +28,21 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+COMPARED = ("rho_w", "rho_o", "ux", "uy", "uz", "S")
 METRIC = "MLUPS (2-comp D3Q19) & % HBM peak; FP16-store vs FP32 MLUPS at stated error"
 
 
-def algorithmic_bytes(ncomp, es, gray_frac, tensor):
+def algorithmic_bytes(ncomp, es, gray_frac, tensor, pop_es=None):
     """Bytes the method must move per fluid voxel update: every population read
     and written once, the class code, and the per-voxel inputs of gray voxels
     (K0, s_J, theta_w, theta_o, pore type; residual amounts and side flag read
-    and written; the six inverse-permeability values for the tensor model)."""
-    pops = 2 * 19 * ncomp * es
+    and written; the six inverse-permeability values for the tensor model).
+    With 16-bit storage (pop_es = 2) a two-component voxel also reads its two
+    fp32 reference densities."""
+    pop_es = es if pop_es is None else pop_es
+    pops = 2 * 19 * ncomp * pop_es
+    if pop_es == 2 and ncomp == 2:
+        pops += 2 * es
     gray = 0.0
     if ncomp == 2:
         gray = 4 * es + 1 + 2 * 2 * es + 2
@@ -137,9 +146,11 @@ def main():
     ap.add_argument("--steps", type=int, default=300)
     ap.add_argument("--warmup", type=int, default=20)
     ap.add_argument("--n", type=int, default=256)
-    ap.add_argument("--precision", default="f32", choices=["f32", "f64"])
+    ap.add_argument("--precision", default="f32", choices=["f32", "f64", "f16", "bf16"])
     ap.add_argument("--diag-every", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the runs of the other storage precisions")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only time a plain 1 GiB device copy (counter yardstick) and exit")
     args = ap.parse_args()
@@ -159,8 +170,6 @@ def main():
     torch.cuda.set_device(0)
     t_gen = time.perf_counter()
     wl = W.multiscale_rock(n=args.n, precision=args.precision)
-    p = wl["params"]
-    p.diag_every = args.diag_every
     cls = wl["cls"]
     n_fluid = int(np.sum(cls != 1))
     n_gray = int(np.sum(cls == 2))
@@ -168,38 +177,54 @@ def main():
     print(f"[bench] generated {wl['name']} in {t_gen:.1f}s: fluid {n_fluid}, gray {n_gray}",
           file=sys.stderr, flush=True)
 
-    lb = L.lbm_create(p)
-    t0 = time.perf_counter()
-    lb.set_geometry(cls, wl["phi"], wl["ptype"], wl["tables"])
-    lb.init_fluid(wl["rho_w"], wl["rho_o"])
-    torch.cuda.synchronize()
-    t_setup = time.perf_counter() - t0
-    lb.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] setup {t_setup:.2f}s, warm-up {args.warmup} steps done", file=sys.stderr,
-          flush=True)
+    def run_leg(precision, keep_fields):
+        """Setup, warm-up and the timed steps of one storage precision; the
+        fields after the last step stay on the device when asked for."""
+        p = wl["params"]
+        p.precision = precision
+        p.eps_n = 1e-12 if precision == "f64" else 1e-7
+        p.diag_every = args.diag_every
+        lb = L.lbm_create(p)
+        t0 = time.perf_counter()
+        lb.set_geometry(cls, wl["phi"], wl["ptype"], wl["tables"])
+        lb.init_fluid(wl["rho_w"], wl["rho_o"])
+        torch.cuda.synchronize()
+        t_setup = time.perf_counter() - t0
+        lb.step(args.warmup)
+        torch.cuda.synchronize()
+        lb.set_profiling(True)
+        lb.get_kernel_times(reset=True)
+        stream = torch.cuda.current_stream()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record(stream)
+        lb.step(args.steps)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        total_ms = e0.elapsed_time(e1)
+        kt = lb.get_kernel_times(reset=True)
+        lb.set_profiling(False)
+        diag = lb.get_diagnostics()
+        fields = None
+        if keep_fields:
+            dt = torch.float64 if precision == "f64" else torch.float32
+            fields = {k: torch.empty(cls.size, dtype=dt, device="cuda") for k in COMPARED}
+            lb.get_fields_device(fields)
+            torch.cuda.synchronize()
+        lb.destroy()
+        print(f"[bench] {precision}: setup {t_setup:.2f}s, {args.steps} steps in "
+              f"{total_ms:.1f} ms; diag {diag}", file=sys.stderr, flush=True)
+        return dict(total_ms=total_ms, kt=kt, diag=diag, fields=fields, t_setup=t_setup)
 
-    lb.set_profiling(True)
-    lb.get_kernel_times(reset=True)
-    stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record(stream)
-    lb.step(args.steps)
-    e1.record(stream)
-    torch.cuda.synchronize()
-    total_ms = e0.elapsed_time(e1)
-    kt = lb.get_kernel_times(reset=True)
-    lb.set_profiling(False)
-    diag = lb.get_diagnostics()
-    print(f"[bench] timed {args.steps} steps in {total_ms:.1f} ms; diag {diag}", file=sys.stderr,
-          flush=True)
-
+    compare = not args.no_compare
+    main_leg = run_leg(args.precision, compare)
+    total_ms, kt, diag = main_leg["total_ms"], main_leg["kt"], main_leg["diag"]
     ms_per_step = total_ms / args.steps
     mlups = n_fluid * args.steps / (total_ms * 1e-3) / 1e6
-    es = 4 if args.precision == "f32" else 8
-    b_alg = algorithmic_bytes(2, es, n_gray / n_fluid, False)
+    es = 8 if args.precision == "f64" else 4
+    pop_es = 2 if args.precision in ("f16", "bf16") else es
+    b_alg = algorithmic_bytes(2, es, n_gray / n_fluid, False, pop_es)
     step_ms = kt["step_ms"] / max(kt["step_launches"], 1)
     achieved = b_alg * n_fluid / (step_ms * 1e-3) / 1e9
     traffic = measured_traffic(wl["name"] + "_" + args.precision)
@@ -221,11 +246,11 @@ def main():
                    "storage": args.precision, "diag_every": args.diag_every,
                    "lups_counted_over": "fluid (pore + gray) voxels",
                    "all_voxel_mlups": round(args.n ** 3 * args.steps / (total_ms * 1e-3) / 1e6, 2),
-                   "setup_s": round(t_setup, 3)},
+                   "setup_s": round(main_leg["t_setup"], 3)},
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": traffic,
-                     "kernel": "k_step (fused collide-stream)",
+                     "kernel": "k_step_zm (fused collide-stream)",
                      "bytes_per_fluid_update": round(b_alg, 2),
                      "kernel_ms": round(step_ms, 4),
                      "step_time_share": round(kt["step_ms"] / total_ms, 4),
@@ -234,7 +259,49 @@ def main():
         "diagnostics": {k: diag[k] for k in ("mass_w", "mass_o", "sw", "max_u", "nonfinite",
                                              "step")},
     }
-    lb.destroy()
+    if compare:
+        # the other storage precisions on the same workload and step count, and
+        # their field errors against the fp64 run (itself held to 1e-12 of the
+        # oracle by the parity tests) after warm-up + timed steps
+        legs = {args.precision: main_leg}
+        for prec in ("f64", "f32", "f16", "bf16"):
+            if prec not in legs:
+                legs[prec] = run_leg(prec, True)
+        ref = legs["f64"]["fields"]
+        mass0 = legs["f64"]["diag"]
+        comp = {}
+        for prec in ("f32", "f16", "bf16", "f64"):
+            lg = legs[prec]
+            t = lg["total_ms"]
+            k = lg["kt"]
+            e = {}
+            if prec != "f64":
+                for name in COMPARED:
+                    r = ref[name]
+                    d = (lg["fields"][name].double() - r).abs().max().item()
+                    sc = r.abs().max().item()
+                    e[name] = d / sc if sc > 0 else d
+                e["mass_w"] = abs(lg["diag"]["mass_w"] - mass0["mass_w"]) / mass0["mass_w"]
+                e["mass_o"] = abs(lg["diag"]["mass_o"] - mass0["mass_o"]) / mass0["mass_o"]
+            comp[prec] = {
+                "value": round(n_fluid * args.steps / (t * 1e-3) / 1e6, 2),
+                "ms_per_step": round(t / args.steps, 4),
+                "kernel_ms": round(k["step_ms"] / max(k["step_launches"], 1), 4),
+                "aux_ms_per_step": round(k["aux_ms"] / args.steps, 4),
+                "speedup_vs_f32": None,
+                "err_vs_f64_after_steps": args.warmup + args.steps,
+                "err_vs_f64": {n: float(f"{v:.3e}") for n, v in e.items()},
+            }
+        for prec in comp:
+            comp[prec]["speedup_vs_f32"] = round(comp["f32"]["ms_per_step"] /
+                                                 comp[prec]["ms_per_step"], 3)
+        out["storage_comparison"] = {
+            "note": "same workload and steps per storage precision; err = max|X - X_f64| / "
+                    "max|X_f64| per field after warm-up + timed steps, mass = relative "
+                    "difference of total component mass",
+            "legs": comp}
+        for lg in legs.values():
+            lg["fields"] = None
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()

@@ -55,7 +55,15 @@ typedef enum lbm_status {
 } lbm_status;
 
 enum { LBM_PORE = 0, LBM_SOLID = 1, LBM_GRAY = 2 };
-enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1 };
+/* Precision.  F64 and F32: populations and arithmetic in that type.  F16 and
+ * BF16: populations stored in 16 bits, every other array and all arithmetic in
+ * fp32.  A stored population is the offset h = f_i / w_i - rho_ref from the
+ * equilibrium weight w_i, where rho_ref is the density (of the same component)
+ * of the voxel that will read it, taken at the level the population was
+ * written; two-component runs keep rho_ref per voxel in fp32, one-component
+ * runs use rho_ref = 1.  In the bulk of either component h is small, so the
+ * 16-bit rounding acts on the deviation from equilibrium rather than on f. */
+enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1, LBM_PREC_F16 = 2, LBM_PREC_BF16 = 3 };
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
 
@@ -66,7 +74,7 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
 typedef struct lbm_params {
   int32_t nx, ny, nz;     /* grid size, each >= 1 */
   int32_t ncomp;          /* 1 or 2 */
-  int32_t precision;      /* LBM_PREC_F64 | LBM_PREC_F32: storage and arithmetic */
+  int32_t precision;      /* LBM_PREC_F64 | LBM_PREC_F32 | LBM_PREC_F16 | LBM_PREC_BF16 */
   int32_t collision;      /* LBM_COLL_REGULARIZED (Hermite-projected) | LBM_COLL_BGK */
   double tau[2];          /* relaxation times (water, oil), > 1/2; nu = (tau - 1/2) / 3 */
   double G;               /* pseudo-potential coupling, F^a = -G rho^a sum_i w_i psi^b(x+c_i) c_i */
@@ -115,8 +123,8 @@ typedef struct lbm_pore_table {
 } lbm_pore_table;
 
 /* Field output.  NULL pointers skip a field.  on_device = 0: host arrays of
- * N doubles; on_device = 1: device arrays of N values of the storage type
- * (double for LBM_PREC_F64, float for LBM_PREC_F32).  Values are at the current
+ * N doubles; on_device = 1: device arrays of N values of the arithmetic type
+ * (double for LBM_PREC_F64, float otherwise).  Values are at the current
  * time level: densities, the velocity u = (rho I + R/2)^-1 (m + F_ex/2),
  * residual-inclusive saturation S and residual amounts; zero in solid voxels. */
 typedef struct lbm_fields {
@@ -198,9 +206,12 @@ int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
                   double *theta_o, double *K0inv6);
 
 /* Checkpoint.  The state blob holds a header, the post-streaming populations
- * f[a][i][v] (storage type), the residual amounts r[a][v] and the side flags
- * (one byte per voxel).  lbm_state_size gives its size in bytes; get/set copy
- * it to/from a host buffer of exactly that size.  Resuming is bitwise exact. */
+ * f[a][i][v] (storage type; for F16/BF16 the 16-bit offsets h, followed for
+ * two components by the fp32 reference densities rho_ref[v][a] they are
+ * relative to), the residual amounts r[a][v] (arithmetic type) and the side
+ * flags (one byte per voxel).  lbm_state_size gives its size in bytes; get/set
+ * copy it to/from a host buffer of exactly that size.  Resuming is bitwise
+ * exact. */
 int lbm_state_size(const lbm_handle *h, size_t *bytes);
 int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);

@@ -21,7 +21,8 @@ LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, \
     LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
 STATUS = {0: "LBM_OK", -1: "LBM_E_INVAL", -2: "LBM_E_NOMEM", -3: "LBM_E_DEVICE",
           -4: "LBM_E_STATE", -5: "LBM_E_NONFINITE", -6: "LBM_E_UNSUPPORTED"}
-PREC = {"f64": 0, "f32": 1}
+PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
+STORE16 = ("f16", "bf16")
 COLL = {"regularized": 0, "bgk": 1}
 REGION = {"gray": 0, "all": 1}
 TABLE_N = 1025
@@ -263,7 +264,8 @@ class Lbm:
         return {k: v.reshape(self.shape) for k, v in out.items()}
 
     def get_fields_device(self, tensors: dict):
-        """Writes into caller device tensors (storage dtype, N elements each)."""
+        """Writes into caller device tensors (arithmetic dtype: float64 for f64
+        runs, float32 otherwise; N elements each)."""
         f = lbm_fields()
         f.on_device = 1
         for k in self.FIELD_NAMES:
@@ -301,19 +303,31 @@ class Lbm:
         self._check(self.lib.lbm_set_state(self.h, buf, len(blob)))
 
     def state_arrays(self, blob: bytes) -> dict:
-        """Splits a state blob into the post-streaming populations, residual
-        amounts and side flags (views on a copy)."""
+        """Splits a state blob into its sections (views on the blob): the
+        post-streaming populations ``f`` (f64/f32 runs) or their raw 16-bit
+        offsets ``codes`` plus the reference densities ``ref`` [z][y][x][a]
+        (two-component f16/bf16 runs), the residual amounts ``r`` and the side
+        flags ``side``."""
         hdr = 8 + 4 + 4 + 4 * 4 + 8 + 4 * 8
-        es = 8 if self.params.precision == "f64" else 4
+        prec = self.params.precision
+        es = 8 if prec == "f64" else 4
         dt = np.float64 if es == 8 else np.float32
         nc = int(self.params.ncomp)
         nf = nc * 19 * self.N
         raw = np.frombuffer(blob, dtype=np.uint8)
-        f = raw[hdr:hdr + nf * es].view(dt).reshape((nc, 19) + self.shape)
-        off = hdr + nf * es
-        r = raw[off:off + 2 * self.N * es].view(dt).reshape((2,) + self.shape)
-        side = raw[off + 2 * self.N * es:].reshape(self.shape)
-        return dict(f=f, r=r, side=side)
+        out = {}
+        if prec in STORE16:
+            out["codes"] = raw[hdr:hdr + nf * 2].view(np.uint16).reshape((nc, 19) + self.shape)
+            off = hdr + nf * 2
+            if nc == 2:
+                out["ref"] = raw[off:off + 2 * self.N * es].view(dt).reshape(self.shape + (2,))
+                off += 2 * self.N * es
+        else:
+            out["f"] = raw[hdr:hdr + nf * es].view(dt).reshape((nc, 19) + self.shape)
+            off = hdr + nf * es
+        out["r"] = raw[off:off + 2 * self.N * es].view(dt).reshape((2,) + self.shape)
+        out["side"] = raw[off + 2 * self.N * es:].reshape(self.shape)
+        return out
 
     def set_profiling(self, on: bool):
         self._check(self.lib.lbm_set_profiling(self.h, int(bool(on))))
@@ -328,14 +342,25 @@ def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
     return Lbm(params, use_torch_memory)
 
 
-def make_state_blob(lbm: Lbm, f, r, side, step=0, q_last=(0.0, 0.0), q_acc=(0.0, 0.0)) -> bytes:
+def make_state_blob(lbm: Lbm, f, r, side, step=0, q_last=(0.0, 0.0), q_acc=(0.0, 0.0),
+                    ref=None) -> bytes:
     """Builds a state blob (the ABI's checkpoint format) from post-streaming
-    populations f[a][i][z][y][x], residual amounts r[2][z][y][x] and side flags."""
+    populations f[a][i][z][y][x], residual amounts r[2][z][y][x] and side flags.
+    For f16/bf16 runs ``f`` holds the raw 16-bit offsets (uint16) and ``ref``
+    the reference densities [z][y][x][a] (two components)."""
     import struct
     p = lbm.params
     dt = np.float64 if p.precision == "f64" else np.float32
     hdr = struct.pack("<QIIiiiiq4d", 0x4C424D3251313953, 1, PREC[p.precision], int(p.nx),
                       int(p.ny), int(p.nz), int(p.ncomp), int(step), q_last[0], q_last[1],
                       q_acc[0], q_acc[1])
-    return (hdr + np.ascontiguousarray(f, dt).tobytes() + np.ascontiguousarray(r, dt).tobytes()
+    if p.precision in STORE16:
+        body = np.ascontiguousarray(f, np.uint16).tobytes()
+        if int(p.ncomp) == 2:
+            if ref is None:
+                raise ValueError("16-bit two-component blobs need the reference densities")
+            body += np.ascontiguousarray(ref, np.float32).tobytes()
+    else:
+        body = np.ascontiguousarray(f, dt).tobytes()
+    return (hdr + body + np.ascontiguousarray(r, dt).tobytes()
             + np.ascontiguousarray(side, np.uint8).tobytes())

@@ -32,10 +32,19 @@ struct ModelConsts {
   int outlet_x;
 };
 
-// Device buffers of one run (storage type T is float or double).
+// Population storage: the arithmetic type itself, or 16-bit offsets
+// h = f_i / w_i - rho_ref (fp16 or bf16) with fp32 arithmetic.
+enum : int { SK_NATIVE = 0, SK_F16 = 2, SK_BF16 = 3 };
+
+// Device buffers of one run (arithmetic type T is float or double).
 template <typename T>
 struct DevState {
-  T *f[2];           // populations, two copies; layout [a][i][v]
+  T *f[2];           // populations, two copies; layout [a][i][v].  16-bit runs:
+                     // f[0] is an fp32 decode of the stored set (field
+                     // evaluation, initialisation), f[1] is unused
+  uint16_t *fc[2];   // 16-bit runs: stored offsets, two copies, layout [a][i][v]
+  T *rhoE;           // 16-bit two-component runs: reference densities [v][a]
+                     // of the stored offsets (the reader's density)
   T *rho;            // densities at the current level [a][v] (field evaluation)
   T *rho2;           // the same, interleaved [v][a] (fused step)
   T *nrm;            // CSF normals [a][3][v] (only when kappa != 0)

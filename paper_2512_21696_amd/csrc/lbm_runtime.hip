@@ -5,6 +5,8 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
+#include <utility>
 #include <vector>
 
 #include "../../include/lbm.h"
@@ -41,7 +43,10 @@ struct lbm_handle {
   ModelConsts mc{};
   hipStream_t st = nullptr;
   std::string err;
-  size_t es = 8;
+  size_t es = 8;   // arithmetic type size
+  size_t pes = 8;  // stored population size
+  int sk = SK_NATIVE;
+  bool dec_valid = false;  // 16-bit runs: f[0] holds the decode of the stored set
   long long N = 0;
   int cur = 0;
   int ntab = 0;
@@ -157,7 +162,14 @@ int alloc_state(lbm_handle *h) {
   bool ok = true;
   auto &L = h->allocs;
   s.f[0] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
-  s.f[1] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
+  s.f[1] = h->sk == SK_NATIVE ? alloc_into<T>(h, L, (size_t)nc * Q * N, &ok) : nullptr;
+  s.fc[0] = s.fc[1] = nullptr;
+  s.rhoE = nullptr;
+  if (h->sk != SK_NATIVE) {
+    s.fc[0] = alloc_into<uint16_t>(h, L, (size_t)nc * Q * N, &ok);
+    s.fc[1] = alloc_into<uint16_t>(h, L, (size_t)nc * Q * N, &ok);
+    if (nc == 2) s.rhoE = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+  }
   s.rho = alloc_into<T>(h, L, (size_t)2 * N, &ok);
   s.rho2 = alloc_into<T>(h, L, (size_t)2 * N, &ok);
   s.nrm = (h->p.ncomp == 2 && h->p.kappa != 0.0) ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
@@ -325,18 +337,42 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
 }
 
 // ------------------------------------------------------------------ stepping
+// Stored populations in the arithmetic type, slot layout, for the field and
+// diagnostics evaluations: the stored set itself, or (16-bit runs) its decode.
+template <typename T>
+const T *eval_pops(lbm_handle *h) {
+  DevState<T> &s = state<T>(h);
+  if (h->sk == SK_NATIVE) return s.f[h->cur];
+  if constexpr (std::is_same<T, float>::value) {
+    if (!h->dec_valid) {
+      Timed tm(h, K_OTHER);
+      if (h->sk == SK_F16)
+        hipLaunchKernelGGL(k_decode<SK_F16>, dim3(blocks(h->N)), dim3(256), 0, h->st,
+                           s.fc[h->cur], s.rhoE, s.mask, s.f[0], h->p.nx, h->p.ny, h->p.nz, h->N,
+                           h->p.ncomp);
+      else
+        hipLaunchKernelGGL(k_decode<SK_BF16>, dim3(blocks(h->N)), dim3(256), 0, h->st,
+                           s.fc[h->cur], s.rhoE, s.mask, s.f[0], h->p.nx, h->p.ny, h->p.nz, h->N,
+                           h->p.ncomp);
+      h->dec_valid = true;
+    }
+  }
+  return s.f[0];
+}
+
 template <typename T>
 void ensure_aux(lbm_handle *h) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
   if (!h->rho_valid) {
+    const T *fin = eval_pops<T>(h);
     Timed tm(h, K_OTHER);
     if (h->p.ncomp == 2)
-      hipLaunchKernelGGL((k_moments<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
-                         s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+      hipLaunchKernelGGL((k_moments<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, fin, s.rho,
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, N);
     else
-      hipLaunchKernelGGL((k_moments<T, 1>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
-                         s.rho, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+      hipLaunchKernelGGL((k_moments<T, 1>), dim3(blocks(N)), dim3(256), 0, h->st, fin, s.rho,
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, N);
     h->rho_valid = true;
   }
 }
@@ -349,8 +385,20 @@ void ensure_density(lbm_handle *h) {
   const long long N = h->N;
   if (h->p.ncomp == 2 && !h->rho2_valid) {
     Timed tm(h, K_AUX);
-    hipLaunchKernelGGL((k_density<T, 2>), dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
-                       s.rho2, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
+    if (h->sk == SK_NATIVE) {
+      hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE>), dim3(blocks(N)), dim3(256), 0, h->st,
+                         (const void *)s.f[h->cur], s.rho2, (const T *)nullptr, s.mask, h->p.nx,
+                         h->p.ny, h->p.nz, N);
+    } else if constexpr (std::is_same<T, float>::value) {
+      if (h->sk == SK_F16)
+        hipLaunchKernelGGL((k_density<float, 2, SK_F16>), dim3(blocks(N)), dim3(256), 0, h->st,
+                           (const void *)s.fc[h->cur], s.rho2, s.rhoE, s.mask, h->p.nx, h->p.ny,
+                           h->p.nz, N);
+      else
+        hipLaunchKernelGGL((k_density<float, 2, SK_BF16>), dim3(blocks(N)), dim3(256), 0, h->st,
+                           (const void *)s.fc[h->cur], s.rho2, s.rhoE, s.mask, h->p.nx, h->p.ny,
+                           h->p.nz, N);
+    }
     h->rho2_valid = true;
   }
 }
@@ -369,35 +417,49 @@ void ensure_normals(lbm_handle *h) {
 }
 
 template <typename T, int NC, bool REG>
-void launch_tiled(lbm_handle *h, const T *fin, T *fout) {
+void launch_tiled(lbm_handle *h) {
   DevState<T> &s = state<T>(h);
   const int tx = (h->p.nx + zm::TX - 1) / zm::TX;
   const int ty = (h->p.ny + zm::TY - 1) / zm::TY;
   const int tz = (h->p.nz + zm::ZC - 1) / zm::ZC;
   const int nt = tx * ty * tz;
   const int grid = (nt + 7) / 8 * 8;
-  hipLaunchKernelGGL((k_step_zm<T, NC, REG>), dim3(grid), dim3(zm::NT), 0, h->st,
-                     make_kc<T>(h->mc), fin, fout, s, tx, ty, tz, nt);
+  if (h->sk == SK_NATIVE) {
+    hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE>), dim3(grid), dim3(zm::NT), 0, h->st,
+                       make_kc<T>(h->mc), (const void *)s.f[h->cur], (void *)s.f[1 - h->cur], s,
+                       tx, ty, tz, nt);
+  } else if constexpr (std::is_same<T, float>::value) {
+    const void *fin = s.fc[h->cur];
+    void *fout = s.fc[1 - h->cur];
+    if (h->sk == SK_F16)
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16>), dim3(grid), dim3(zm::NT), 0, h->st,
+                         make_kc<float>(h->mc), fin, fout, s, tx, ty, tz, nt);
+    else
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16>), dim3(grid), dim3(zm::NT), 0,
+                         h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, tz, nt);
+  }
 }
 
 template <typename T, int MODE, typename O>
 void launch_step(lbm_handle *h, const FieldsOut &fo) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
-  const T *fin = s.f[h->cur];
-  T *fout = s.f[1 - h->cur];
-  Timed tm(h, MODE == MODE_STEP ? K_STEP : K_OTHER);
   if (MODE == MODE_STEP) {
+    Timed tm(h, K_STEP);
     const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
     if (h->p.ncomp == 2) {
-      if (reg) launch_tiled<T, 2, true>(h, fin, fout);
-      else launch_tiled<T, 2, false>(h, fin, fout);
+      if (reg) launch_tiled<T, 2, true>(h);
+      else launch_tiled<T, 2, false>(h);
     } else {
-      if (reg) launch_tiled<T, 1, true>(h, fin, fout);
-      else launch_tiled<T, 1, false>(h, fin, fout);
+      if (reg) launch_tiled<T, 1, true>(h);
+      else launch_tiled<T, 1, false>(h);
     }
     return;
   }
+  // field / diagnostics evaluation: no populations are written
+  const T *fin = eval_pops<T>(h);
+  T *fout = nullptr;
+  Timed tm(h, K_OTHER);
   if (h->p.ncomp == 2)
     hipLaunchKernelGGL((k_step<T, 2, MODE, O>), dim3(blocks(N)), dim3(256), 0, h->st, h->mc, fin,
                        fout, s, fo);
@@ -445,17 +507,40 @@ int step_t(lbm_handle *h, int64_t n) {
     ensure_density<T>(h);
     launch_step<T, MODE_STEP, T>(h, FieldsOut{});
     h->cur = 1 - h->cur;
+    // 16-bit runs: the new offsets are relative to the densities of the level
+    // just left, which the density pass wrote into rho2
+    if (h->sk != SK_NATIVE && h->p.ncomp == 2) std::swap(s.rhoE, s.rho2);
     h->rho_valid = false;
     h->rho2_valid = false;
+    h->dec_valid = false;
     h->step += 1;
     if (h->p.track_flux) {
       Timed tm(h, K_OTHER);
-      if (h->p.ncomp == 2)
-        hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                           s.mask, s.partial);
-      else
-        hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                           s.mask, s.partial);
+      if (h->sk == SK_NATIVE) {
+        if (h->p.ncomp == 2)
+          hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                             s.mask, s.partial);
+        else
+          hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                             s.mask, s.partial);
+      } else if constexpr (std::is_same<T, float>::value) {
+        const uint16_t *c = s.fc[h->cur];
+        if (h->sk == SK_F16) {
+          if (h->p.ncomp == 2)
+            hipLaunchKernelGGL((k_flux16<SK_F16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                               s.rhoE, s.mask, s.partial);
+          else
+            hipLaunchKernelGGL((k_flux16<SK_F16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                               s.rhoE, s.mask, s.partial);
+        } else {
+          if (h->p.ncomp == 2)
+            hipLaunchKernelGGL((k_flux16<SK_BF16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                               s.rhoE, s.mask, s.partial);
+          else
+            hipLaunchKernelGGL((k_flux16<SK_BF16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                               s.rhoE, s.mask, s.partial);
+        }
+      }
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0, s.acc,
                          1);
     }
@@ -492,14 +577,32 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
                    "copy rho_o");
   if (rc == LBM_OK) {
     Timed tm(h, K_OTHER);
-    T *C = s.f[1 - h->cur];
-    hipLaunchKernelGGL(k_equilibrium_rest<T>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d, ro_d, C,
-                       s.mask, N, h->p.ncomp);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur], s.mask,
-                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    if (h->sk == SK_NATIVE) {
+      T *C = s.f[1 - h->cur];
+      hipLaunchKernelGGL(k_equilibrium_rest<T>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d, ro_d,
+                         C, s.mask, N, h->p.ncomp);
+      hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur],
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    } else if constexpr (std::is_same<T, float>::value) {
+      float *C = s.f[0];
+      hipLaunchKernelGGL(k_equilibrium_rest<float>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d,
+                         ro_d, C, s.mask, N, h->p.ncomp);
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL(k_ref_canonical, dim3(blocks(N)), dim3(256), 0, h->st, C, s.rhoE,
+                           s.mask, N);
+      if (h->sk == SK_F16)
+        hipLaunchKernelGGL(k_scatter_enc<SK_F16>, dim3(blocks(N)), dim3(256), 0, h->st, C,
+                           s.fc[h->cur], s.rhoE, s.mask, h->p.nx, h->p.ny, h->p.nz, N,
+                           h->p.ncomp);
+      else
+        hipLaunchKernelGGL(k_scatter_enc<SK_BF16>, dim3(blocks(N)), dim3(256), 0, h->st, C,
+                           s.fc[h->cur], s.rhoE, s.mask, h->p.nx, h->p.ny, h->p.nz, N,
+                           h->p.ncomp);
+    }
   }
   h->rho_valid = false;
   h->rho2_valid = false;
+  h->dec_valid = false;
   if (rc == LBM_OK) {
     ensure_aux<T>(h);
     Timed tm(h, K_OTHER);
@@ -551,18 +654,25 @@ int fields_t(lbm_handle *h, const lbm_fields *out) {
 
 size_t state_bytes(const lbm_handle *h) {
   const size_t N = (size_t)h->N;
-  return sizeof(StateHeader) + (size_t)h->p.ncomp * Q * N * h->es + 2 * N * h->es + N;
+  const size_t refs = (h->sk != SK_NATIVE && h->p.ncomp == 2) ? 2 * N * h->es : 0;
+  return sizeof(StateHeader) + (size_t)h->p.ncomp * Q * N * h->pes + refs + 2 * N * h->es + N;
 }
 
 template <typename T>
 int get_state_t(lbm_handle *h, void *buf) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
-  T *C = s.f[1 - h->cur];
+  // canonical (post-streaming) order; 16-bit offsets are already relative to
+  // the reader, so their gather is a plain permutation
+  const void *C = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur] : (const void *)s.fc[1 - h->cur];
   {
     Timed tm(h, K_OTHER);
-    hipLaunchKernelGGL(k_gather<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur], C, s.mask,
-                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    if (h->sk == SK_NATIVE)
+      hipLaunchKernelGGL(k_gather<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
+                         s.f[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    else
+      hipLaunchKernelGGL(k_gather<uint16_t>, dim3(blocks(N)), dim3(256), 0, h->st, s.fc[h->cur],
+                         s.fc[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
   }
   StateHeader hd{};
   hd.magic = kStateMagic;
@@ -578,10 +688,17 @@ int get_state_t(lbm_handle *h, void *buf) {
   int rc = hip_check(h, hipMemcpyAsync(acc, s.acc, sizeof(acc), hipMemcpyDeviceToHost, h->st),
                      "copy accumulators");
   size_t off = sizeof(StateHeader);
-  const size_t fb = (size_t)h->p.ncomp * Q * N * sizeof(T);
+  const size_t fb = (size_t)h->p.ncomp * Q * N * h->pes;
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemcpyAsync(b + off, C, fb, hipMemcpyDeviceToHost, h->st), "copy f");
   off += fb;
+  if (h->sk != SK_NATIVE && h->p.ncomp == 2) {
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemcpyAsync(b + off, s.rhoE, 2 * N * sizeof(T), hipMemcpyDeviceToHost,
+                                       h->st),
+                     "copy reference densities");
+    off += 2 * N * sizeof(T);
+  }
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemcpyAsync(b + off, s.r, 2 * N * sizeof(T), hipMemcpyDeviceToHost, h->st),
                    "copy r");
@@ -609,11 +726,18 @@ int set_state_t(lbm_handle *h, const void *buf) {
       hd.nz != h->p.nz || hd.ncomp != h->p.ncomp)
     return set_err(h, LBM_E_INVAL, "state blob does not match this handle");
   const char *b = (const char *)buf;
-  T *C = s.f[1 - h->cur];
+  void *C = h->sk == SK_NATIVE ? (void *)s.f[1 - h->cur] : (void *)s.fc[1 - h->cur];
   size_t off = sizeof(StateHeader);
-  const size_t fb = (size_t)h->p.ncomp * Q * N * sizeof(T);
+  const size_t fb = (size_t)h->p.ncomp * Q * N * h->pes;
   int rc = hip_check(h, hipMemcpyAsync(C, b + off, fb, hipMemcpyHostToDevice, h->st), "copy f");
   off += fb;
+  if (h->sk != SK_NATIVE && h->p.ncomp == 2) {
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemcpyAsync(s.rhoE, b + off, 2 * N * sizeof(T), hipMemcpyHostToDevice,
+                                       h->st),
+                     "copy reference densities");
+    off += 2 * N * sizeof(T);
+  }
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemcpyAsync(s.r, b + off, 2 * N * sizeof(T), hipMemcpyHostToDevice, h->st),
                    "copy r");
@@ -626,8 +750,13 @@ int set_state_t(lbm_handle *h, const void *buf) {
                    "copy accumulators");
   if (rc == LBM_OK) {
     Timed tm(h, K_OTHER);
-    hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur], s.mask,
-                       h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    if (h->sk == SK_NATIVE)
+      hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, (const T *)C,
+                         s.f[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+    else
+      hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(blocks(N)), dim3(256), 0, h->st,
+                         (const uint16_t *)C, s.fc[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N,
+                         h->p.ncomp);
     rc = hip_check(h, hipGetLastError(), "scatter");
   }
   if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "set_state");
@@ -635,6 +764,7 @@ int set_state_t(lbm_handle *h, const void *buf) {
     h->step = hd.step;
     h->rho_valid = false;
     h->rho2_valid = false;
+    h->dec_valid = false;
     h->has_fluid = true;
   }
   return rc;
@@ -693,6 +823,8 @@ extern "C" int lbm_create(const lbm_params *p, lbm_handle **out) {
   h->st = (hipStream_t)p->stream;
   h->N = h->mc.N;
   h->es = p->precision == LBM_PREC_F64 ? 8 : 4;
+  h->sk = p->precision == LBM_PREC_F16 ? SK_F16 : (p->precision == LBM_PREC_BF16 ? SK_BF16 : SK_NATIVE);
+  h->pes = h->sk == SK_NATIVE ? h->es : 2;
   rc = p->precision == LBM_PREC_F64 ? alloc_state<double>(h) : alloc_state<float>(h);
   if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "create");
   if (rc != LBM_OK) {

@@ -23,6 +23,15 @@
 //
 // fp32 runs use the hardware reciprocal and reciprocal square root (1 ulp);
 // fp64 runs divide exactly.
+//
+// 16-bit storage (fp16 or bf16, fp32 arithmetic): a stored population is the
+// offset h = f_i / w_i - rho_ref, rho_ref being the density of the voxel that
+// reads it (the destination of the pull, or the voxel itself under
+// bounce-back) at the level it was written.  The reader therefore decodes
+// every pulled value with its own reference, f_i = w_i (rho_ref + h), and the
+// writer encodes with the destination densities it already holds in LDS.  The
+// moments are accumulated from the offsets with the reference added exactly
+// once, so the fp32 weights never multiply the bulk density.
 namespace lbm {
 namespace zm {
 constexpr int TX = 64, TY = 4;
@@ -102,6 +111,35 @@ __device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) 
   __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
 }
 
+__device__ inline uint32_t bload16(rsrc_t r, uint32_t off) {
+  return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+__device__ inline void bstore16(rsrc_t r, uint32_t voff, uint32_t soff, uint16_t v) {
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
+}
+template <int SK> __device__ inline float dec16(uint32_t bits);
+template <> __device__ inline float dec16<SK_F16>(uint32_t bits) {
+  return (float)__builtin_bit_cast(_Float16, (uint16_t)bits);
+}
+template <> __device__ inline float dec16<SK_BF16>(uint32_t bits) {
+  return __builtin_bit_cast(float, bits << 16);
+}
+// round to nearest even
+template <int SK> __device__ inline uint16_t enc16(float x);
+template <> __device__ inline uint16_t enc16<SK_F16>(float x) {
+  return __builtin_bit_cast(uint16_t, (_Float16)x);
+}
+template <> __device__ inline uint16_t enc16<SK_BF16>(float x) {
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
+}
+// One pulled value: the population itself (native storage) or its stored
+// offset h (16-bit storage).  off is the element index within the component.
+template <typename T, int SK>
+__device__ inline T pull_value(rsrc_t r, uint32_t off) {
+  if constexpr (SK == SK_NATIVE) return bload(r, off * (uint32_t)sizeof(T), (T)0);
+  else return (T)dec16<SK>(bload16(r, off * 2u));
+}
+
 __device__ inline int rslot(int z) { return (z + 10) % 5; }
 __device__ inline int mslot(int z) { return (z + 9) % 3; }
 
@@ -149,11 +187,58 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
   }
 }
 
+// 16-bit variant: stores enc(c_i(A + B.c_i + c_i^T C c_i) sc - ref_i) where
+// ref_i is the reference density of the voxel that reads slot i (plus
+// keep * sc * g_i, g_i = f_i / w_i, for BGK).
+template <int SK, bool REG>
+__device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t sbase,
+                                            uint32_t Nbytes, float A, float B0, float B1,
+                                            float B2, float Cxx, float Cyy, float Czz, float Cxy,
+                                            float Cxz, float Cyz, float sc, const float *gpop,
+                                            float keep, bool zero, const float *ref) {
+  float v[Q];
+  v[0] = A;
+  const float ax = A + Cxx, ay = A + Cyy, az = A + Czz;
+  v[1] = ax + B0;
+  v[2] = ax - B0;
+  v[3] = ay + B1;
+  v[4] = ay - B1;
+  v[5] = az + B2;
+  v[6] = az - B2;
+  const float exy = ax + Cyy, exz = ax + Czz, eyz = ay + Czz;
+  const float dxy = 2.f * Cxy, dxz = 2.f * Cxz, dyz = 2.f * Cyz;
+  const float pxy = exy + dxy, mxy = exy - dxy, pxz = exz + dxz, mxz = exz - dxz;
+  const float pyz = eyz + dyz, myz = eyz - dyz;
+  const float s01 = B0 + B1, d01 = B0 - B1, s02 = B0 + B2, d02 = B0 - B2, s12 = B1 + B2,
+              d12 = B1 - B2;
+  v[7] = pxy + s01;
+  v[8] = pxy - s01;
+  v[9] = mxy + d01;
+  v[10] = mxy - d01;
+  v[11] = pxz + s02;
+  v[12] = pxz - s02;
+  v[13] = mxz + d02;
+  v[14] = mxz - d02;
+  v[15] = pyz + s12;
+  v[16] = pyz - s12;
+  v[17] = myz + d12;
+  v[18] = myz - d12;
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    float val = v[i] * sc;
+    if (!REG) val += keep * sc * gpop[i];
+    val -= ref[i];
+    bstore16(out, voff, sbase + (uint32_t)i * Nbytes, zero ? (uint16_t)0 : enc16<SK>(val));
+  }
+}
+
 // Densities of the current level for the fused step: the pull of every
 // population (bounce-back at solid sources) summed per component, written
-// interleaved [v][rho_w, rho_o].  Solid voxels get zero.
-template <typename T, int NC>
-__global__ __launch_bounds__(256) void k_density(const T *__restrict__ fin, T *__restrict__ rho2,
+// interleaved [v][rho_w, rho_o].  Solid voxels get zero.  With 16-bit storage
+// rho = rho_ref + sum_i w_i h_i, rho_ref from rhoE.
+template <typename T, int NC, int SK>
+__global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
+                                                 T *__restrict__ rho2, const T *__restrict__ rhoE,
                                                  const uint32_t *__restrict__ mask, int nx, int ny,
                                                  int nz, long long N) {
   const uint32_t v = blockIdx.x * 256u + threadIdx.x;
@@ -175,12 +260,19 @@ __global__ __launch_bounds__(256) void k_density(const T *__restrict__ fin, T *_
                           (y == (uint32_t)ny - 1 ? 0 : y + 1) * nx};
   const uint32_t Z3[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy,
                           (z == (uint32_t)nz - 1 ? 0 : z + 1) * nxy};
-  constexpr uint32_t ES = (uint32_t)sizeof(T);
+  constexpr uint32_t ES = SK == SK_NATIVE ? (uint32_t)sizeof(T) : 2u;
+  T ref[2] = {0, 0};
+  if constexpr (SK != SK_NATIVE) {
+    const vec2<T> e = reinterpret_cast<const vec2<T> *>(rhoE)[v];
+    ref[0] = e.x;
+    ref[1] = e.y;
+  }
   T r[2] = {0, 0};
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
-    const rsrc_t rin = make_rsrc(fin + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
-    T acc = bload(rin, v * ES, (T)0);
+    const rsrc_t rin = make_rsrc((const char *)fin + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
+    const T v0 = pull_value<T, SK>(rin, v);
+    T axis = 0, diag = 0;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
       const int j = i + 1;
@@ -190,16 +282,19 @@ __global__ __launch_bounds__(256) void k_density(const T *__restrict__ fin, T *_
       const uint32_t oj = ((mk >> i) & 1u)
                               ? (uint32_t)i * N32 + v
                               : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
-      acc += bload(rin, oi * ES, (T)0) + bload(rin, oj * ES, (T)0);
+      const T pair = pull_value<T, SK>(rin, oi) + pull_value<T, SK>(rin, oj);
+      if (i < 7) axis += pair;
+      else diag += pair;
     }
-    r[a] = acc;
+    if constexpr (SK == SK_NATIVE) r[a] = v0 + axis + diag;
+    else r[a] = ref[a] + (T)(1.0 / 3.0) * v0 + (T)(1.0 / 18.0) * axis + (T)(1.0 / 36.0) * diag;
   }
   out[v] = vec2<T>{r[0], r[1]};
 }
 
-template <typename T, int NC, bool REG>
-__global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__restrict__ fin,
-                                                 T *__restrict__ fout, const DevState<T> s,
+template <typename T, int NC, bool REG, int SK>
+__global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
+                                                 void *__restrict__ fout, const DevState<T> s,
                                                  const int tiles_x, const int tiles_y,
                                                  const int chunks_z, const int ntiles) {
   using namespace zm;
@@ -229,7 +324,8 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   const int zs = bzc * ZC;
   const int ze = zs + ZC < nz ? zs + ZC : nz;
   const bool csf = STENCIL && mc.kappa != (T)0;
-  constexpr uint32_t ES = (uint32_t)sizeof(T);
+  constexpr uint32_t ES = SK == SK_NATIVE ? (uint32_t)sizeof(T) : 2u;  // population element
+  constexpr bool S16 = SK != SK_NATIVE;
   const T2 *rho2 = reinterpret_cast<const T2 *>(s.rho2);
 
   // Staging of one density plane: each thread owns up to 3 cells of the
@@ -331,8 +427,8 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
   rsrc_t rin[NC], rout[NC];
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
-    rin[a] = make_rsrc(fin + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
-    rout[a] = make_rsrc(fout + (size_t)a * Q * N, (uint32_t)(Q * N * sizeof(T)));
+    rin[a] = make_rsrc((const char *)fin + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
+    rout[a] = make_rsrc((char *)fout + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
   }
 
   for (int z = zs; z < ze; ++z) {
@@ -358,17 +454,29 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
     const int zm1 = z == 0 ? nz - 1 : z - 1, zp1 = z == nz - 1 ? 0 : z + 1;
     const uint32_t Z3[3] = {(uint32_t)zm1 * nxy, zoff, (uint32_t)zp1 * nxy};
 
-    // a1 + a2: pull with bounce-back; moments accumulated over opposite pairs
+    // a1 + a2: pull with bounce-back; moments accumulated over opposite pairs.
+    // 16-bit storage: the pulled offsets are weighted as they arrive and the
+    // reference enters rho and the diagonal of P once.
     T rho[NC], mom[NC][3], P[NC][6];  // P: xx, yy, zz, xy, xz, yz
-    T f[REG ? 1 : NC][REG ? 1 : Q];
+    T f[REG ? 1 : NC][REG ? 1 : Q];   // BGK: f_i (native) or f_i / w_i (16-bit)
+    T refo[NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) refo[a] = (T)1;
+    if constexpr (S16) {
+      if (NC == 2) {
+        const T2 e = reinterpret_cast<const T2 *>(s.rhoE)[v];
+        refo[0] = e.x;
+        refo[NC - 1] = e.y;
+      }
+    }
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
-      const T f0 = bload(rin[a], v * ES, (T)0);
-      if (!REG) f[REG ? 0 : a][0] = f0;
-      rho[a] = f0;
+      const T f0 = pull_value<T, SK>(rin[a], v);
+      if (!REG) f[REG ? 0 : a][0] = S16 ? refo[a] + f0 : f0;
+      rho[a] = S16 ? refo[a] + (T)(1.0 / 3.0) * f0 : f0;
       mom[a][0] = mom[a][1] = mom[a][2] = 0;
 #pragma unroll
-      for (int d = 0; d < 6; ++d) P[a][d] = 0;
+      for (int d = 0; d < 6; ++d) P[a][d] = (S16 && d < 3) ? refo[a] * cs2 : (T)0;
     }
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
@@ -383,11 +491,16 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
                               : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        const T fi = bload(rin[a], oi * ES, (T)0);
-        const T fj = bload(rin[a], oj * ES, (T)0);
+        T fi = pull_value<T, SK>(rin[a], oi);
+        T fj = pull_value<T, SK>(rin[a], oj);
         if (!REG) {
-          f[REG ? 0 : a][i] = fi;
-          f[REG ? 0 : a][j] = fj;
+          f[REG ? 0 : a][i] = S16 ? refo[a] + fi : fi;
+          f[REG ? 0 : a][j] = S16 ? refo[a] + fj : fj;
+        }
+        if (S16) {
+          const T w = i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0);
+          fi *= w;
+          fj *= w;
         }
         const T sm = fi + fj, df = fi - fj;
         rho[a] += sm;
@@ -631,10 +744,151 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const T *__rest
         Cxy += k45 * qxy; Cxz += k45 * qxz; Cyz += k45 * qyz;
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
-      emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy,
-                        Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid);
+      if constexpr (!S16) {
+        emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz,
+                          Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid);
+      } else {
+        // reference of each outgoing slot: the destination's density of this
+        // level, or this voxel's own under bounce-back (exactly the values
+        // the density pass wrote, so the reader decodes with the same floats)
+        float ref[Q];
+        if (NC == 2) {
+          const float own = reinterpret_cast<const float *>(&srho[rslot(z)][c])[a];
+#pragma unroll
+          for (int i = 0; i < Q; ++i)
+            ref[i] = (i > 0 && !((mk >> i) & 1u))
+                         ? reinterpret_cast<const float *>(
+                               &srho[rslot(z + cz(i))][c + hoff(i)])[a]
+                         : own;
+        } else {
+#pragma unroll
+          for (int i = 0; i < Q; ++i) ref[i] = 1.f;
+        }
+        emit_post16<SK, REG>(rout[a], vxy * 2u, zoff * 2u, N32 * 2u, A, B0, B1, B2, Cxx, Cyy, Czz,
+                             Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, ref);
+      }
     }
   }
+}
+
+// ---------------------------------------------------------------------------
+// 16-bit storage: conversions between the stored offsets and fp32 populations
+// (field evaluation, initialisation) and the per-step outlet flux.
+
+// Reference density of component a for the voxel that reads slot (v, i).
+__device__ inline float slot_ref(const float *rhoE, const Nbr &nb, uint32_t mk, long long v,
+                                 int i, int a, int nc) {
+  if (nc == 1) return 1.f;
+  const long long rd = (i > 0 && !((mk >> i) & 1u)) ? (long long)nb.at(cx(i), cy(i), cz(i)) : v;
+  return rhoE[2 * rd + a];
+}
+
+// stored offsets (slot layout) -> fp32 populations f = w_i (rho_ref + h)
+template <int SK>
+__global__ __launch_bounds__(256) void k_decode(const uint16_t *__restrict__ codes,
+                                                const float *__restrict__ rhoE,
+                                                const uint32_t *__restrict__ mask,
+                                                float *__restrict__ out, int nx, int ny, int nz,
+                                                long long N, int nc) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  const bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  const Nbr nb((int)v, nx, ny, nz);
+  for (int a = 0; a < nc; ++a) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const size_t k = (size_t)(a * Q + i) * N + v;
+      float val = 0.f;
+      if (!solid) val = (float)wq(i) * (slot_ref(rhoE, nb, mk, v, i, a, nc) + dec16<SK>(codes[k]));
+      out[k] = val;
+    }
+  }
+}
+
+// reference densities of a canonical (post-streaming) fp32 set: rho = sum_i f_i
+__global__ __launch_bounds__(256) void k_ref_canonical(const float *__restrict__ C,
+                                                       float *__restrict__ rhoE,
+                                                       const uint32_t *__restrict__ mask,
+                                                       long long N) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const bool solid = ((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  for (int a = 0; a < 2; ++a) {
+    float r = 0.f;
+    if (!solid) {
+#pragma unroll
+      for (int i = 0; i < Q; ++i) r += C[(size_t)(a * Q + i) * N + v];
+    }
+    rhoE[2 * v + a] = r;
+  }
+}
+
+// canonical fp32 set -> stored offsets (the streaming of k_scatter, encoded
+// against the reader's reference)
+template <int SK>
+__global__ __launch_bounds__(256) void k_scatter_enc(const float *__restrict__ C,
+                                                     uint16_t *__restrict__ codes,
+                                                     const float *__restrict__ rhoE,
+                                                     const uint32_t *__restrict__ mask, int nx,
+                                                     int ny, int nz, long long N, int nc) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  const bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  const Nbr nb((int)v, nx, ny, nz);
+  for (int a = 0; a < nc; ++a) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      uint16_t code = 0;
+      if (!solid) {
+        const bool bb = i > 0 && ((mk >> i) & 1u);
+        const float val = bb ? C[(size_t)(a * Q + opp(i)) * N + v]
+                             : C[(size_t)(a * Q + i) * N + nb.at(cx(i), cy(i), cz(i))];
+        const float inv_w = i == 0 ? 3.f : (i < 7 ? 18.f : 36.f);
+        code = enc16<SK>(val * inv_w - slot_ref(rhoE, nb, mk, v, i, a, nc));
+      }
+      codes[(size_t)(a * Q + i) * N + v] = code;
+    }
+  }
+}
+
+// per-link outlet flux through the plane x_f | x_f + 1 from the stored offsets
+template <int SK, int NC>
+__global__ void k_flux16(const ModelConsts mc, const uint16_t *__restrict__ codes,
+                         const float *__restrict__ rhoE, const uint32_t *__restrict__ mask,
+                         double *__restrict__ partial) {
+  const long long N = mc.N;
+  const int nyz = mc.ny * mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  double val[2] = {0.0, 0.0};
+  if (k < nyz) {
+    const int x0 = mc.outlet_x;
+    const int x1 = x0 + 1 == mc.nx ? 0 : x0 + 1;
+    const long long base = (long long)k * mc.nx;
+    const long long v0 = base + x0, v1 = base + x1;
+    const uint32_t m0 = mask[v0], m1 = mask[v1];
+    const bool f0 = ((m0 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    const Nbr n0((int)v0, mc.nx, mc.ny, mc.nz), n1((int)v1, mc.nx, mc.ny, mc.nz);
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      double q = 0.0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) {
+          const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v0]);
+          q += (double)((float)wq(i) * (slot_ref(rhoE, n0, m0, v0, i, a, NC) + h));
+        }
+        if (cx(i) == -1 && f1 && !((m1 >> i) & 1u)) {
+          const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v1]);
+          q -= (double)((float)wq(i) * (slot_ref(rhoE, n1, m1, v1, i, a, NC) + h));
+        }
+      }
+      val[a] = q;
+    }
+  }
+  block_sum<2>(val, partial + (size_t)blockIdx.x * 2, false);
 }
 
 }  // namespace lbm

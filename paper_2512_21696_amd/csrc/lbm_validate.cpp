@@ -61,11 +61,15 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
   if (N * 2 * 19 >= 2147483647.0)
     return fail(msg, len, LBM_E_UNSUPPORTED, "grid too large: 2*19*N must stay below 2^31");
   if (p->ncomp != 1 && p->ncomp != 2) return fail(msg, len, LBM_E_INVAL, "ncomp must be 1 or 2");
+  if (p->precision != LBM_PREC_F64 && p->precision != LBM_PREC_F32 &&
+      p->precision != LBM_PREC_F16 && p->precision != LBM_PREC_BF16)
+    return fail(msg, len, LBM_E_UNSUPPORTED,
+                "precision must be LBM_PREC_F64, LBM_PREC_F32, LBM_PREC_F16 or LBM_PREC_BF16");
+  // the arithmetic-type arrays (and, in fp64/fp32 runs, the populations) are
+  // addressed with 32-bit byte offsets per component
   if (N * 19 * (p->precision == LBM_PREC_F64 ? 8 : 4) >= 4294967295.0)
     return fail(msg, len, LBM_E_UNSUPPORTED,
                 "grid too large: one component's populations must stay below 4 GiB");
-  if (p->precision != LBM_PREC_F64 && p->precision != LBM_PREC_F32)
-    return fail(msg, len, LBM_E_UNSUPPORTED, "precision must be LBM_PREC_F64 or LBM_PREC_F32");
   if (p->collision != LBM_COLL_REGULARIZED && p->collision != LBM_COLL_BGK)
     return fail(msg, len, LBM_E_INVAL, "unknown collision model");
   for (int a = 0; a < p->ncomp; ++a)

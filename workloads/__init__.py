@@ -60,7 +60,7 @@ class Params:
     ny: int = 32
     nz: int = 32
     ncomp: int = 2
-    precision: str = "f64"          # "f64" | "f32"
+    precision: str = "f64"          # "f64" | "f32" | "f16" | "bf16" (16-bit population storage)
     collision: str = "regularized"  # "regularized" | "bgk"
     tau: tuple = (1.0, 1.0)         # (water, oil)
     G: float = 3.0
