@@ -2,13 +2,15 @@
 //
 // A block owns a column of 64 x 4 voxels (one wavefront per x-row, so every
 // population load and store of a wave covers 256 contiguous bytes) and
-// marches along z through a chunk of ZC planes.  Rolling windows in LDS hold,
-// per plane, (rho_w, rho_o, S_hat, solid flag) on the column plus a radius-2
-// halo (periodic wrap) and the CSF normals
+// marches along z through a chunk of ZC planes.  A rolling window in LDS holds
+// five planes of (rho_w, rho_o) on the column plus a radius-2 halo (periodic
+// wrap; +inf marks a solid cell), and one plane of the CSF normals
 // n^a = grad rho^b / |grad rho^b| on the column plus a radius-1 halo.  Each
-// plane is staged once and serves three consecutive voxel planes, so every
-// stencil of the step (pseudo-potential sum, grad rho^b, curvature -div n^a,
-// grad S_hat) reads LDS only.  Blocks are numbered so that the blocks resident
+// density plane is staged once and serves every stencil of the step
+// (pseudo-potential sum, grad rho^b, the normals, grad S_hat); each normal
+// plane is consumed as soon as it is made, its contributions to the
+// curvature -div n^a of the voxels on the planes below, on and above it
+// summed in registers.  Blocks are numbered so that the blocks resident
 // on one XCD (dispatch is round-robin over the 8 XCDs) cover neighbouring
 // columns, which keeps halo re-reads inside that XCD's L2.
 //
@@ -32,6 +34,8 @@
 // writer encodes with the destination densities it already holds in LDS.  The
 // moments are accumulated from the offsets with the reference added exactly
 // once, so the fp32 weights never multiply the bulk density.
+#include <type_traits>
+
 namespace lbm {
 namespace zm {
 constexpr int TX = 64, TY = 4;
@@ -42,7 +46,6 @@ constexpr int NH = HX * HY;  // density plane cells
 constexpr int MX = TX + 2, MY = TY + 2;
 constexpr int NM = MX * MY;  // normal plane cells
 constexpr int RS = 5;        // density planes z-2 .. z+2
-constexpr int MS = 3;        // normal planes z-1 .. z+1
 constexpr int ZC = 32;       // planes per block
 __host__ __device__ constexpr int hoff(int i) { return cx(i) + HX * cy(i); }
 __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
@@ -140,8 +143,38 @@ __device__ inline T pull_value(rsrc_t r, uint32_t off) {
   else return (T)dec16<SK>(bload16(r, off * 2u));
 }
 
+// Raw pulled value (the population, or the 16-bit offset's bits) and its
+// conversion to the arithmetic type, split so the loads can be issued a plane
+// ahead of their use.
+template <typename T, int SK>
+__device__ inline auto pull_raw(rsrc_t r, uint32_t off) {
+  if constexpr (SK == SK_NATIVE) return bload(r, off * (uint32_t)sizeof(T), (T)0);
+  else return bload16(r, off * 2u);
+}
+// The same with the population array's start as a scalar byte offset.
+template <typename T, int SK>
+__device__ inline auto pull_raw_s(rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (SK == SK_NATIVE) {
+    if constexpr (sizeof(T) == 4)
+      return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+    else
+      return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else {
+    return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+  }
+}
+// Keeps a running scalar offset in one SGPR: the compiler may not fold the
+// per-direction offsets into 19 loop-invariant registers (which it would then
+// spill into vector lanes and reload on every use).
+__device__ inline void keep_scalar(uint32_t &so) { asm volatile("" : "+s"(so)); }
+
+template <typename T, int SK, typename L>
+__device__ inline T pull_decode(L raw) {
+  if constexpr (SK == SK_NATIVE) return raw;
+  else return (T)dec16<SK>(raw);
+}
+
 __device__ inline int rslot(int z) { return (z + 10) % 5; }
-__device__ inline int mslot(int z) { return (z + 9) % 3; }
 
 // Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus
 // keep * sc * f_i for BGK) of one component; voff is the voxel's byte offset
@@ -179,11 +212,14 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
   v[16] = w2 * (pyz - s12);
   v[17] = w2 * (myz + d12);
   v[18] = w2 * (myz - d12);
+  uint32_t so = sbase;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     T val = v[i];
     if (!REG) val += keep * sc * fpop[i];
-    bstore(out, voff, sbase + (uint32_t)i * Nbytes, zero ? (T)0 : val);
+    bstore(out, voff, so, zero ? (T)0 : val);
+    so += Nbytes;
+    keep_scalar(so);
   }
 }
 
@@ -223,18 +259,23 @@ __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t 
   v[16] = pyz - s12;
   v[17] = myz + d12;
   v[18] = myz - d12;
+  uint32_t so = sbase;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     float val = v[i] * sc;
     if (!REG) val += keep * sc * gpop[i];
     val -= ref[i];
-    bstore16(out, voff, sbase + (uint32_t)i * Nbytes, zero ? (uint16_t)0 : enc16<SK>(val));
+    bstore16(out, voff, so, zero ? (uint16_t)0 : enc16<SK>(val));
+    so += Nbytes;
+    keep_scalar(so);
   }
 }
 
 // Densities of the current level for the fused step: the pull of every
 // population (bounce-back at solid sources) summed per component, written
-// interleaved [v][rho_w, rho_o].  Solid voxels get zero.  With 16-bit storage
+// interleaved [v][rho_w, rho_o].  Solid voxels get +inf in both slots: the
+// fused step recognises solid halo cells by it (a fluid density is finite),
+// and never uses the value itself.  With 16-bit storage
 // rho = rho_ref + sum_i w_i h_i, rho_ref from rhoE.
 template <typename T, int NC, int SK>
 __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
@@ -246,7 +287,7 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
   const uint32_t mk = mask[v];
   vec2<T> *out = reinterpret_cast<vec2<T> *>(rho2);
   if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) {
-    out[v] = vec2<T>{(T)0, (T)0};
+    out[v] = vec2<T>{(T)INFINITY, (T)INFINITY};
     return;
   }
   const uint32_t N32 = (uint32_t)N;
@@ -293,7 +334,7 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
 }
 
 template <typename T, int NC, bool REG, int SK>
-__global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
                                                  void *__restrict__ fout, const DevState<T> s,
                                                  const int tiles_x, const int tiles_y,
                                                  const int chunks_z, const int ntiles) {
@@ -301,9 +342,8 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
   constexpr bool STENCIL = NC == 2;
   using T4 = vec4<T>;
   using T2 = vec2<T>;
-  __shared__ T2 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];        // rho_w, rho_o
-  __shared__ uint8_t ssol[STENCIL ? RS : 1][STENCIL ? NH : 1];   // solid flag
-  __shared__ T2 snrm[STENCIL ? MS : 1][3][STENCIL ? NM : 1];     // (n^w_d, n^o_d), d = x,y,z
+  __shared__ T2 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];  // rho_w, rho_o (+inf: solid)
+  __shared__ T2 snrm[3][STENCIL ? NM : 1];                  // (n^w_d, n^o_d) of one plane
   __shared__ int sxw[HX], syw[HY];
 
   const int nb = gridDim.x;
@@ -334,7 +374,6 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
   constexpr int CPT = (NH + NT - 1) / NT;
   uint32_t cell_g[CPT];  // in-plane voxel index of each owned cell
   T2 pre_r[CPT];
-  uint32_t pre_m[CPT];
   if (STENCIL) {
     if (tid < HX) sxw[tid] = wrapn(x0 + tid - R, nx);
     if (tid < HY) syw[tid] = wrapn(y0 + tid - R, ny);
@@ -350,40 +389,31 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
   auto fetch_rho = [&](int zz) {
     const uint32_t zoff = (uint32_t)wrapn(zz, nz) * nxy;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q) {
-      if (tid + q * NT < NH) {
-        const uint32_t g = zoff + cell_g[q];
-        pre_m[q] = s.mask[g];
-        pre_r[q] = rho2[g];
-      }
-    }
+    for (int q = 0; q < CPT; ++q)
+      if (tid + q * NT < NH) pre_r[q] = rho2[zoff + cell_g[q]];
   };
   auto store_rho = [&](int zz) {
     const int sl = rslot(zz);
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int k = tid + q * NT;
-      if (k < NH) {
-        srho[sl][k] = pre_r[q];
-        ssol[sl][k] = ((pre_m[q] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
-      }
+      if (k < NH) srho[sl][k] = pre_r[q];
     }
   };
-  // CSF normals of plane zz from the density planes zz-1 .. zz+1
+  // CSF normals of plane zz from the density planes zz-1 .. zz+1 (a solid
+  // neighbour takes the cell's own density; solid cells get a zero normal)
   auto make_normals = [&](int zz) {
-    const int ms = mslot(zz);
     const int sc0 = rslot(zz);
     for (int k = tid; k < NM; k += NT) {
       const int mx_ = k % MX, my_ = k / MX;
       const int c = (mx_ + 1) + HX * (my_ + 1);
       const T2 self = srho[sc0][c];
-      const bool sol = ssol[sc0][c];
+      const bool sol = __builtin_isinf(self.x);
       T gw0 = 0, gw1 = 0, gw2 = 0, go0 = 0, go1 = 0, go2 = 0;  // grad rho_w, grad rho_o
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const int sl = rslot(zz + cz(i));
-        const T2 e = srho[sl][c + hoff(i)];
-        const bool ns = ssol[sl][c + hoff(i)];
+        const T2 e = srho[rslot(zz + cz(i))][c + hoff(i)];
+        const bool ns = __builtin_isinf(e.x);
         const T vw = ns ? self.x : e.x;
         const T vo = ns ? self.y : e.y;
         if (cx(i)) { gw0 += (T)(gw(i) * cx(i)) * vw; go0 += (T)(gw(i) * cx(i)) * vo; }
@@ -393,14 +423,81 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
       // n^w follows grad rho_o, n^o follows grad rho_w
       const T qo = go0 * go0 + go1 * go1 + go2 * go2;
       const T qw = gw0 * gw0 + gw1 * gw1 + gw2 * gw2;
-      const T io = (!sol && qo > mc.eps_n2) ? rsq(qo) : (T)0;
-      const T iw = (!sol && qw > mc.eps_n2) ? rsq(qw) : (T)0;
-      snrm[ms][0][k] = T2{go0 * io, gw0 * iw};
-      snrm[ms][1][k] = T2{go1 * io, gw1 * iw};
-      snrm[ms][2][k] = T2{go2 * io, gw2 * iw};
+      const T io = qo > mc.eps_n2 ? rsq(qo) : (T)0;
+      const T iw = qw > mc.eps_n2 ? rsq(qw) : (T)0;
+      snrm[0][k] = sol ? T2{0, 0} : T2{go0 * io, gw0 * iw};
+      snrm[1][k] = sol ? T2{0, 0} : T2{go1 * io, gw1 * iw};
+      snrm[2][k] = sol ? T2{0, 0} : T2{go2 * io, gw2 * iw};
     }
   };
 
+  const int x = x0 + tx, y = y0 + ty;
+  const bool inside = x < nx && y < ny;
+  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
+  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
+  // byte offsets of the 3 x 3 in-plane neighbours (x - 1 .. x + 1, y - 1 .. y + 1)
+  uint32_t XYE[3][3];
+#pragma unroll
+  for (int bb = 0; bb < 3; ++bb)
+#pragma unroll
+    for (int aa = 0; aa < 3; ++aa)
+      XYE[bb][aa] = ((uint32_t)(aa == 0 ? xm : (aa == 1 ? x : xp)) +
+                     (uint32_t)(bb == 0 ? ym : (bb == 1 ? y : yp)) * (uint32_t)nx) * ES;
+  const uint32_t vxy = (uint32_t)x + (uint32_t)y * (uint32_t)nx;  // in-plane voxel index
+  const int c = (tx + R) + HX * (ty + R);
+  const int cn = (tx + 1) + MX * (ty + 1);
+  const T cs2 = (T)CS2;
+
+  // Masks of this thread's voxel on planes z, z+1, z+2, and the CSF
+  // curvature sums -div n^a of those planes, accumulated as the normal
+  // planes arrive: the normals of plane p serve the voxels of planes p-1, p,
+  // p+1 through the directions with c_z = p - (their plane); a solid link
+  // takes the voxel's own normal.
+  uint32_t M[3] = {0u, 0u, 0u};
+  T Dw[3] = {0, 0, 0}, Do[3] = {0, 0, 0};
+  auto mask_at = [&](int zz) -> uint32_t {
+    return inside ? s.mask[vxy + (uint32_t)wrapn(zz, nz) * nxy] : 0u;
+  };
+  auto accum = [&](auto BASE) {  // BASE: plane of the normals minus z
+    constexpr int base = decltype(BASE)::value;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const int o = base - cz(i);  // target plane minus z
+      if (o < 0 || o > 2) continue;
+      const T k = ((M[o] >> i) & 1u) ? (T)0 : (T)gw(i);
+      const int u = cn + moff(i);
+      if (cx(i)) { const T2 n = snrm[0][u]; Dw[o] += k * (T)cx(i) * n.x; Do[o] += k * (T)cx(i) * n.y; }
+      if (cy(i)) { const T2 n = snrm[1][u]; Dw[o] += k * (T)cy(i) * n.x; Do[o] += k * (T)cy(i) * n.y; }
+      if (cz(i)) { const T2 n = snrm[2][u]; Dw[o] += k * (T)cz(i) * n.x; Do[o] += k * (T)cz(i) * n.y; }
+    }
+    if constexpr (base >= 0 && base <= 2) {
+      const uint32_t mk = M[base];
+      if (mk & 0x7fffeu) {
+        T s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+        for (int i = 1; i < Q; ++i) {
+          const T on = ((mk >> i) & 1u) ? (T)gw(i) : (T)0;
+          if (cx(i)) s0 += (T)cx(i) * on;
+          if (cy(i)) s1 += (T)cy(i) * on;
+          if (cz(i)) s2 += (T)cz(i) * on;
+        }
+        const T2 n0 = snrm[0][cn], n1 = snrm[1][cn], n2 = snrm[2][cn];
+        Dw[base] += s0 * n0.x + s1 * n1.x + s2 * n2.x;
+        Do[base] += s0 * n0.y + s1 * n1.y + s2 * n2.y;
+      }
+    }
+  };
+  auto advance = [&](int znext) {  // shift the windows to plane znext
+    M[0] = M[1];
+    M[1] = M[2];
+    M[2] = mask_at(znext + 2);
+    Dw[0] = Dw[1]; Dw[1] = Dw[2]; Dw[2] = 0;
+    Do[0] = Do[1]; Do[1] = Do[2]; Do[2] = 0;
+  };
+
+  M[0] = mask_at(zs);
+  M[1] = mask_at(zs + 1);
+  M[2] = mask_at(zs + 2);
   if (STENCIL) {
     for (int zz = zs - 2; zz <= zs + 1; ++zz) {
       fetch_rho(zz);
@@ -409,21 +506,16 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
     __syncthreads();
     if (csf) {
       make_normals(zs - 1);
+      __syncthreads();
+      accum(std::integral_constant<int, -1>{});
+      __syncthreads();
       make_normals(zs);
+      __syncthreads();
+      accum(std::integral_constant<int, 0>{});
     }
     fetch_rho(zs + 2);
   }
 
-  const int x = x0 + tx, y = y0 + ty;
-  const bool inside = x < nx && y < ny;
-  const int xm = x == 0 ? nx - 1 : x - 1, xp = x == nx - 1 ? 0 : x + 1;
-  const int ym = y == 0 ? ny - 1 : y - 1, yp = y == ny - 1 ? 0 : y + 1;
-  const uint32_t X3[3] = {(uint32_t)xm, (uint32_t)x, (uint32_t)xp};
-  const uint32_t Y3[3] = {(uint32_t)(ym * nx), (uint32_t)(y * nx), (uint32_t)(yp * nx)};
-  const uint32_t vxy = (uint32_t)x + (uint32_t)y * (uint32_t)nx;  // in-plane voxel index
-  const int c = (tx + R) + HX * (ty + R);
-  const int cn = (tx + 1) + MX * (ty + 1);
-  const T cs2 = (T)CS2;
   rsrc_t rin[NC], rout[NC];
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
@@ -431,87 +523,124 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
     rout[a] = make_rsrc((char *)fout + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
   }
 
-  for (int z = zs; z < ze; ++z) {
+
+  // The pull of plane z+1 is issued while plane z computes, so each wave keeps
+  // its next plane's loads in flight (and ahead of its own stores).
+  using LT = typename std::conditional<S16, uint32_t, T>::type;
+  LT pf[NC][Q];
+  T pfref[NC];
+  auto issue = [&](int zz, uint32_t mkz) {
+    const uint32_t zo = (uint32_t)zz * nxy;
+    const uint32_t vv = vxy + zo;
+    const int zm1 = zz == 0 ? nz - 1 : zz - 1, zp1 = zz == nz - 1 ? 0 : zz + 1;
+    const uint32_t NE = N32 * ES;
+    const uint32_t ZE[3] = {(uint32_t)zm1 * nxy * ES, zo * ES, (uint32_t)zp1 * nxy * ES};
+    const uint32_t vE = vv * ES;
+#pragma unroll
+    for (int a = 0; a < NC; ++a) pf[a][0] = pull_raw_s<T, SK>(rin[a], vE, 0u);
+    // pair (i, j = i + 1) of opposite directions, both addressed from the
+    // scalar start i N of array i: pull source of i is x - c_i (array i), of
+    // j is x + c_i (array j = i + 1, one N further); bounce-back takes the
+    // opposite population of this voxel when the source is solid
+    uint32_t so = NE;
+#pragma unroll
+    for (int i = 1; i < Q; i += 2) {
+      const int j = i + 1;
+      const uint32_t oi = ((mkz >> j) & 1u) ? vE + NE : XYE[1 - cy(i)][1 - cx(i)] + ZE[1 - cz(i)];
+      const uint32_t oj = ((mkz >> i) & 1u) ? vE : XYE[1 + cy(i)][1 + cx(i)] + ZE[1 + cz(i)] + NE;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        pf[a][i] = pull_raw_s<T, SK>(rin[a], oi, so);
+        pf[a][j] = pull_raw_s<T, SK>(rin[a], oj, so);
+      }
+      so += 2 * NE;
+      keep_scalar(so);
+    }
+    if constexpr (S16) {
+      if (NC == 2) {
+        const T2 e = reinterpret_cast<const T2 *>(s.rhoE)[vv];
+        pfref[0] = e.x;
+        pfref[NC - 1] = e.y;
+      }
+    }
+  };
+  auto all_solid = [](uint32_t mkz) { return __all(((mkz >> CLASS_SHIFT) & 3u) == SOLID_CODE); };
+  if (inside && !all_solid(M[0])) issue(zs, M[0]);
+
+  for (int z = zs; z < ze; advance(++z)) {
     if (STENCIL) {
-      // plane z+2 reuses the slot of plane z-3, which no wave still reads
+      // plane z+2 reuses the slot of plane z-3, which no wave still reads;
+      // the barrier also ends every read of the previous normal plane
       store_rho(z + 2);
       __syncthreads();
-      if (csf) make_normals(z + 1);
-      __syncthreads();
+      if (csf) {
+        make_normals(z + 1);
+        __syncthreads();
+        accum(std::integral_constant<int, 1>{});
+      }
       if (z + 1 < ze) fetch_rho(z + 3);
     }
     if (!inside) continue;
     const uint32_t zoff = (uint32_t)z * nxy;
     const uint32_t v = vxy + zoff;
-    const uint32_t mk = s.mask[v];
+    const uint32_t mk = M[0];
     const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
     // Solid lanes of a wave that also holds fluid voxels run along (their
     // results are discarded) and store zeros, so that every population store
     // of the wave writes whole cache lines instead of partial ones.
     const bool solid = cl == SOLID_CODE;
-    if (__all(solid)) continue;
+    const bool skip = all_solid(mk);
+    const bool skip_next = z + 1 >= ze || all_solid(M[1]);
     const bool gray = cl == GRAY_CODE;
-    const int zm1 = z == 0 ? nz - 1 : z - 1, zp1 = z == nz - 1 ? 0 : z + 1;
-    const uint32_t Z3[3] = {(uint32_t)zm1 * nxy, zoff, (uint32_t)zp1 * nxy};
 
-    // a1 + a2: pull with bounce-back; moments accumulated over opposite pairs.
-    // 16-bit storage: the pulled offsets are weighted as they arrive and the
-    // reference enters rho and the diagonal of P once.
+    // a1 + a2: the pulled populations of this plane (bounce-back resolved at
+    // issue) summed into moments over opposite pairs.  16-bit storage: the
+    // offsets are weighted as they arrive and the reference enters rho and
+    // the diagonal of P once.
     T rho[NC], mom[NC][3], P[NC][6];  // P: xx, yy, zz, xy, xz, yz
     T f[REG ? 1 : NC][REG ? 1 : Q];   // BGK: f_i (native) or f_i / w_i (16-bit)
     T refo[NC];
+    if (!skip) {
 #pragma unroll
-    for (int a = 0; a < NC; ++a) refo[a] = (T)1;
-    if constexpr (S16) {
-      if (NC == 2) {
-        const T2 e = reinterpret_cast<const T2 *>(s.rhoE)[v];
-        refo[0] = e.x;
-        refo[NC - 1] = e.y;
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < NC; ++a) {
-      const T f0 = pull_value<T, SK>(rin[a], v);
-      if (!REG) f[REG ? 0 : a][0] = S16 ? refo[a] + f0 : f0;
-      rho[a] = S16 ? refo[a] + (T)(1.0 / 3.0) * f0 : f0;
-      mom[a][0] = mom[a][1] = mom[a][2] = 0;
-#pragma unroll
-      for (int d = 0; d < 6; ++d) P[a][d] = (S16 && d < 3) ? refo[a] * cs2 : (T)0;
-    }
-#pragma unroll
-    for (int i = 1; i < Q; i += 2) {
-      const int j = i + 1;  // opposite of i
-      // pull source of i is x - c_i, of j is x + c_i; bounce-back takes the
-      // opposite population of this voxel when the source is solid
-      const uint32_t oi = ((mk >> j) & 1u)
-                              ? (uint32_t)j * N32 + v
-                              : (uint32_t)i * N32 + X3[1 - cx(i)] + Y3[1 - cy(i)] + Z3[1 - cz(i)];
-      const uint32_t oj = ((mk >> i) & 1u)
-                              ? (uint32_t)i * N32 + v
-                              : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
+      for (int a = 0; a < NC; ++a) refo[a] = (S16 && NC == 2) ? pfref[a] : (T)1;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        T fi = pull_value<T, SK>(rin[a], oi);
-        T fj = pull_value<T, SK>(rin[a], oj);
-        if (!REG) {
-          f[REG ? 0 : a][i] = S16 ? refo[a] + fi : fi;
-          f[REG ? 0 : a][j] = S16 ? refo[a] + fj : fj;
+        const T f0 = pull_decode<T, SK>(pf[a][0]);
+        if (!REG) f[REG ? 0 : a][0] = S16 ? refo[a] + f0 : f0;
+        rho[a] = S16 ? refo[a] + (T)(1.0 / 3.0) * f0 : f0;
+        mom[a][0] = mom[a][1] = mom[a][2] = 0;
+#pragma unroll
+        for (int d = 0; d < 6; ++d) P[a][d] = (S16 && d < 3) ? refo[a] * cs2 : (T)0;
+      }
+#pragma unroll
+      for (int i = 1; i < Q; i += 2) {
+        const int j = i + 1;
+#pragma unroll
+        for (int a = 0; a < NC; ++a) {
+          T fi = pull_decode<T, SK>(pf[a][i]);
+          T fj = pull_decode<T, SK>(pf[a][j]);
+          if (!REG) {
+            f[REG ? 0 : a][i] = S16 ? refo[a] + fi : fi;
+            f[REG ? 0 : a][j] = S16 ? refo[a] + fj : fj;
+          }
+          if (S16) {
+            const T w = i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0);
+            fi *= w;
+            fj *= w;
+          }
+          const T sm = fi + fj, df = fi - fj;
+          rho[a] += sm;
+          if (cx(i)) { mom[a][0] += cx(i) > 0 ? df : -df; P[a][0] += sm; }
+          if (cy(i)) { mom[a][1] += cy(i) > 0 ? df : -df; P[a][1] += sm; }
+          if (cz(i)) { mom[a][2] += cz(i) > 0 ? df : -df; P[a][2] += sm; }
+          if (cx(i) && cy(i)) P[a][3] += cx(i) * cy(i) > 0 ? sm : -sm;
+          if (cx(i) && cz(i)) P[a][4] += cx(i) * cz(i) > 0 ? sm : -sm;
+          if (cy(i) && cz(i)) P[a][5] += cy(i) * cz(i) > 0 ? sm : -sm;
         }
-        if (S16) {
-          const T w = i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0);
-          fi *= w;
-          fj *= w;
-        }
-        const T sm = fi + fj, df = fi - fj;
-        rho[a] += sm;
-        if (cx(i)) { mom[a][0] += cx(i) > 0 ? df : -df; P[a][0] += sm; }
-        if (cy(i)) { mom[a][1] += cy(i) > 0 ? df : -df; P[a][1] += sm; }
-        if (cz(i)) { mom[a][2] += cz(i) > 0 ? df : -df; P[a][2] += sm; }
-        if (cx(i) && cy(i)) P[a][3] += cx(i) * cy(i) > 0 ? sm : -sm;
-        if (cx(i) && cz(i)) P[a][4] += cx(i) * cz(i) > 0 ? sm : -sm;
-        if (cy(i) && cz(i)) P[a][5] += cy(i) * cz(i) > 0 ? sm : -sm;
       }
     }
+    if (!skip_next) issue(z + 1, M[1]);
+    if (skip) continue;
     T rt = rho[0];
     if (NC == 2) rt = rho[0] + rho[1];
     const T irt = rcp(rt);
@@ -574,18 +703,7 @@ __global__ __launch_bounds__(256) void k_step_zm(const KC<T> mc, const void *__r
                 grw2 = (T)3 * (aw2 - dw * sw2);
         const T gro0 = (T)3 * (ao0 - dox * sw0), gro1 = (T)3 * (ao1 - dox * sw1),
                 gro2 = (T)3 * (ao2 - dox * sw2);
-        const int m0s = mslot(z);
-        T dvw = 0, dvo = 0;  // div n^w, div n^o
-#pragma unroll
-        for (int i = 1; i < Q; ++i) {
-          const bool sol = (mk >> i) & 1u;
-          const int ms = sol ? m0s : mslot(z + cz(i));
-          const int u = sol ? cn : cn + moff(i);
-          const T k = (T)gw(i);
-          if (cx(i)) { const T2 n = snrm[ms][0][u]; dvw += k * (T)cx(i) * n.x; dvo += k * (T)cx(i) * n.y; }
-          if (cy(i)) { const T2 n = snrm[ms][1][u]; dvw += k * (T)cy(i) * n.x; dvo += k * (T)cy(i) * n.y; }
-          if (cz(i)) { const T2 n = snrm[ms][2][u]; dvw += k * (T)cz(i) * n.x; dvo += k * (T)cz(i) * n.y; }
-        }
+        const T dvw = Dw[0], dvo = Do[0];  // div n^w, div n^o
         // F_csf^a = kappa (-div n^a) grad rho^b rho^a / (phi_avg phi_max)
         const T kw = -mc.csf_fac * dvw * rho[0], ko = -mc.csf_fac * dvo * rho[1];
         Fex[0][0] += kw * gro0; Fex[0][1] += kw * gro1; Fex[0][2] += kw * gro2;
