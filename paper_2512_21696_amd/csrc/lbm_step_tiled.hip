@@ -4,7 +4,8 @@
 // population load and store of a wave covers 256 contiguous bytes) and
 // marches along z through a chunk of ZC planes.  A rolling window in LDS holds
 // five planes of (rho_w, rho_o) on the column plus a radius-2 halo (periodic
-// wrap; +inf marks a solid cell), and one plane of the CSF normals
+// wrap; +inf marks a solid cell) with the mobile saturation S_hat of each
+// cell, and one plane of the CSF normals
 // n^a = grad rho^b / |grad rho^b| on the column plus a radius-1 halo.  Each
 // density plane is staged once and serves every stencil of the step
 // (pseudo-potential sum, grad rho^b, the normals, grad S_hat); each normal
@@ -343,6 +344,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   using T4 = vec4<T>;
   using T2 = vec2<T>;
   __shared__ T2 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];  // rho_w, rho_o (+inf: solid)
+  __shared__ T sshat[STENCIL ? RS : 1][STENCIL ? NH : 1];  // mobile saturation S_hat
   __shared__ T2 snrm[3][STENCIL ? NM : 1];                  // (n^w_d, n^o_d) of one plane
   __shared__ int sxw[HX], syw[HY];
 
@@ -397,7 +399,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int q = 0; q < CPT; ++q) {
       const int k = tid + q * NT;
-      if (k < NH) srho[sl][k] = pre_r[q];
+      if (k < NH) {
+        const T2 e = pre_r[q];
+        srho[sl][k] = e;
+        sshat[sl][k] = __builtin_isinf(e.x) ? (T)0 : (e.x * rcp(e.x + e.y) - mc.s_min) * mc.inv_span;
+      }
     }
   };
   // CSF normals of plane zz from the density planes zz-1 .. zz+1 (a solid
@@ -715,11 +721,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         T g0 = 0, g1 = 0, g2 = 0;
 #pragma unroll
         for (int i = 1; i < Q; ++i) {
-          T val = shat0;
-          if (!((mk >> i) & 1u)) {
-            const T2 e = srho[rslot(z + cz(i))][c + hoff(i)];
-            val = (e.x * rcp(e.x + e.y) - mc.s_min) * mc.inv_span;
-          }
+          const T val = ((mk >> i) & 1u) ? shat0 : sshat[rslot(z + cz(i))][c + hoff(i)];
           if (cx(i)) g0 += (T)(gw(i) * cx(i)) * val;
           if (cy(i)) g1 += (T)(gw(i) * cy(i)) * val;
           if (cz(i)) g2 += (T)(gw(i) * cz(i)) * val;
