@@ -1,0 +1,128 @@
+"""Parity at the benchmark's full size and launch configuration: the 256^3
+multiscale rock in fp32 (and with fp16 storage), run through the C ABI, then
+one more step compared voxel by voxel on sampled voxels against the fp64
+oracle.
+
+The oracle cannot run 16.7 M voxels, but the update of one voxel depends only
+on the post-streaming populations within three voxels of it (pull: radius 1;
+pseudo-potential and grad S_hat: densities at radius 1 of the neighbours that
+are pulled from; CSF: normals at radius 1, each from densities at radius 1,
+of those neighbours).  So each sampled voxel is checked on a periodic 9^3
+crop centred on it (radius 4, one spare layer): the oracle steps the crop
+once and the centre's new post-streaming populations, residual amounts and
+side flag must match the GPU's.
+
+Tolerances: one fp32 step from the same state differs from the fp64 oracle
+only by fp32 rounding, a few ulps of the largest operands (densities O(1)):
+1e-5 of each voxel's largest f_i / w_i.  fp16 storage adds one rounding of
+the stored offset, at most 2^-11 of |h| <= 1: 1e-3 in f_i / w_i."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle, W as WQ
+from gpu_common import announce
+
+pytestmark = pytest.mark.gpu
+
+N_SIDE = 256
+R = 4
+
+
+def _categories(cls, rng, per=24):
+    """Seeded sample of fluid voxels: gray and pore voxels, each in the
+    interior and next to a solid."""
+    solid = cls == W.SOLID
+    near = np.zeros_like(solid)
+    for ax in range(3):
+        for sh in (-1, 1):
+            near |= np.roll(solid, sh, axis=ax)
+    picks = []
+    for name, sel in (("gray interior", (cls == W.GRAY) & ~near),
+                      ("gray at solid", (cls == W.GRAY) & near),
+                      ("pore interior", (cls == W.PORE) & ~near),
+                      ("pore at solid", (cls == W.PORE) & near)):
+        idx = np.flatnonzero(sel)
+        take = rng.choice(idx, size=min(per, idx.size), replace=False)
+        picks += [(name, int(t)) for t in take]
+    return picks
+
+
+def _crop(a, c, lead):
+    """Periodic (2R+1)^3 crop of a [..., z, y, x] array around c = (z, y, x)."""
+    idx = [np.arange(ci - R, ci + R + 1) % N_SIDE for ci in c]
+    return a[(slice(None),) * lead + np.ix_(*idx)]
+
+
+def _states(prec, steps):
+    import paper_2512_21696_amd as L
+    wl = W.multiscale_rock(n=N_SIDE, precision=prec)
+    p = wl["params"]
+    announce(f"multiscale_rock 256^3 {prec}: {steps} steps, state, one step, state")
+    lb = L.lbm_create(p)
+    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    lb.step(steps)
+    d0 = lb.get_diagnostics()
+    s0 = lb.state_arrays(lb.get_state())
+    lb.step(1)
+    d1 = lb.get_diagnostics()
+    s1 = lb.state_arrays(lb.get_state())
+    lb.destroy()
+    return wl, s0, s1, d0, d1
+
+
+def _decoded_crop(st, prec, c):
+    """f / w_i (float64) of the (2R+1)^3 crop of a state around c; 16-bit
+    offsets decode as rho_ref + h, solid voxels as 0."""
+    w = WQ.reshape((1, 19, 1, 1, 1))
+    if prec == "f32":
+        return _crop(st["f"], c, 2).astype(np.float64) / w
+    bits = _crop(st["codes"], c, 2)
+    if prec == "f16":
+        h = bits.view(np.float16).astype(np.float64)
+    else:
+        h = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    ref = np.moveaxis(_crop(np.moveaxis(st["ref"], -1, 0), c, 1), 0, 0).astype(np.float64)
+    return np.where(np.isfinite(ref)[:, None], ref[:, None] + h, 0.0)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 1e-3)])
+def test_rock256_sampled_step_matches_oracle(prec, tol):
+    wl, s0, s1, d0, d1 = _states(prec, 20)
+    cls = wl["cls"]
+    w = WQ.reshape((1, 19, 1, 1, 1))
+    picks = _categories(cls, np.random.default_rng(7))
+    p = W.Params(**{**wl["params"].as_dict(), "nx": 2 * R + 1, "ny": 2 * R + 1,
+                    "nz": 2 * R + 1, "precision": "f64", "outlet_x": 0})
+    hy = p.hyst
+    worst, skipped = {}, 0
+    for name, flat in picks:
+        c = np.unravel_index(flat, cls.shape)
+        o = Oracle(p)
+        o.set_geometry(_crop(cls, c, 0), _crop(wl["phi"], c, 0), _crop(wl["ptype"], c, 0),
+                       wl["tables"])
+        o.set_state(dict(f=_decoded_crop(s0, prec, c) * w,
+                         r=_crop(s0["r"], c, 1).astype(np.float64),
+                         side=_crop(s0["side"], c, 0).astype(bool), step=0,
+                         Q_acc=np.zeros(2), Q_last=np.zeros(2)))
+        S0 = float(o.evaluate()["S"][R, R, R])
+        if min(abs(S0 - 0.5 - hy), abs(S0 - 0.5 + hy)) < 1e-4:
+            skipped += 1  # a residual-event switch this close to its threshold may go either way
+            continue
+        o.step(1)
+        got = _decoded_crop(s1, prec, c)[:, :, R, R, R]
+        ref = o.f[:, :, R, R, R] / WQ[None, :]
+        err = np.abs(got - ref).max() / np.abs(ref).max()
+        worst[name] = max(worst.get(name, 0.0), err)
+        assert err < tol, (name, c, err)
+        r_got = s1["r"][(slice(None),) + c].astype(np.float64)
+        assert np.abs(r_got - o.r[:, R, R, R]).max() < tol, (name, c, r_got, o.r[:, R, R, R])
+        assert bool(s1["side"][c]) == bool(o.side[R, R, R]), (name, c)
+    print(prec, "worst relative error per category", {k: f"{v:.2e}" for k, v in worst.items()},
+          "skipped near a threshold:", skipped)
+    assert len(worst) == 4
+    # a property of the whole grid: mass per component (mobile + residual) is
+    # carried through the step up to rounding
+    for k in ("mass_w", "mass_o"):
+        assert abs(d1[k] - d0[k]) / d0[k] < 1e-6, (k, d0[k], d1[k])
