@@ -2,7 +2,8 @@
 
 Workload: the 256^3 synthetic multiscale rock (Gaussian random field,
 35 % solid / 20 % gray / 45 % pore, four Brooks-Corey pore types, water driven
-in +x), fp32 storage and arithmetic.  A step is one full time step of the
+in +x, CSF control at half the kappa = 0 surface tension), fp32 storage and
+arithmetic.  A step is one full time step of the
 method: density pass, CSF normals, the fused collide-stream kernel (forces,
 constitutive update, residual transfer, collision, pull streaming) and the
 per-step outlet-flux reduction; diagnostics (fp64 reductions with the
@@ -14,7 +15,8 @@ kernel (the fused step) with its algorithmic bytes per fluid update divided
 by its mean launch time from HIP events on the library's stream.  Unless
 --no-compare, the same workload also runs with fp64, fp32, fp16 and bf16
 population storage: "storage_comparison" gives each one's MLUPS and its field
-errors against the fp64 run after the same number of steps.
+errors against the fp64 run after the same number of steps; "fiber_tensor"
+times the one-component tensorial-resistivity workload (192^3 fibre bundles).
 """
 import argparse
 import hashlib
@@ -177,9 +179,10 @@ def main():
     print(f"[bench] generated {wl['name']} in {t_gen:.1f}s: fluid {n_fluid}, gray {n_gray}",
           file=sys.stderr, flush=True)
 
-    def run_leg(precision, keep_fields):
+    def run_leg(precision, keep_fields, wl=wl):
         """Setup, warm-up and the timed steps of one storage precision; the
         fields after the last step stay on the device when asked for."""
+        cls = wl["cls"]
         p = wl["params"]
         p.precision = precision
         p.eps_n = 1e-12 if precision == "f64" else 1e-7
@@ -243,6 +246,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": wl["name"], "grid": [args.n] * 3, "components": 2,
                    "fluid_voxels": n_fluid, "gray_voxels": n_gray,
+                   "sigma_scale": 0.5, "kappa": wl["params"].kappa,
                    "storage": args.precision, "diag_every": args.diag_every,
                    "lups_counted_over": "fluid (pore + gray) voxels",
                    "all_voxel_mlups": round(args.n ** 3 * args.steps / (total_ms * 1e-3) / 1e6, 2),
@@ -302,6 +306,33 @@ def main():
             "legs": comp}
         for lg in legs.values():
             lg["fields"] = None
+        # the same rock with the surface tension doubled by the CSF control
+        w2 = W.multiscale_rock(n=args.n, precision="f32", sigma_scale=2.0)
+        l2 = run_leg("f32", False, wl=w2)
+        out["sigma_2x"] = {"kappa": w2["params"].kappa, "storage": "f32",
+                           "value": round(n_fluid * args.steps / (l2["total_ms"] * 1e-3) / 1e6, 2),
+                           "ms_per_step": round(l2["total_ms"] / args.steps, 4),
+                           "kernel_ms": round(l2["kt"]["step_ms"] /
+                                              max(l2["kt"]["step_launches"], 1), 4),
+                           "diagnostics": {k: l2["diag"][k] for k in ("mass_w", "mass_o", "sw",
+                                                                       "max_u", "nonfinite")}}
+        # the tensorial-resistivity workload: 192^3 gray fibre bundles, one
+        # component, principal axes from the smoothed porosity
+        wf = W.fiber_bundles(n=192, precision="f32")
+        nf_fl = int(np.sum(wf["cls"] != 1))
+        nf_gr = int(np.sum(wf["cls"] == 2))
+        lf = run_leg("f32", False, wl=wf)
+        kf = lf["kt"]
+        fms = kf["step_ms"] / max(kf["step_launches"], 1)
+        bf = algorithmic_bytes(1, 4, nf_gr / nf_fl, True)
+        out["fiber_tensor"] = {
+            "workload": wf["name"], "components": 1, "tensor": True, "storage": "f32",
+            "fluid_voxels": nf_fl, "gray_voxels": nf_gr,
+            "value": round(nf_fl * args.steps / (lf["total_ms"] * 1e-3) / 1e6, 2),
+            "unit": "MLUPS", "ms_per_step": round(lf["total_ms"] / args.steps, 4),
+            "kernel_ms": round(fms, 4), "bytes_per_fluid_update": round(bf, 2),
+            "achieved_gbs": round(bf * nf_fl / (fms * 1e-3) / 1e9, 1),
+            "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()

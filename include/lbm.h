@@ -10,7 +10,7 @@
  *   - CSF surface-tension control, Eq. (4), in under-resolved (gray) voxels;
  *   - the under-resolved-region force of Eq. (1): capillary term
  *     -Pc(Sw) rho_r n H and Brinkman resistance rho nu / (K0(phi) Kr(Sw)) rho_r u,
- *     taken semi-implicitly;
+ *     taken semi-implicitly (default) or implicitly (lbm_params.resistance);
  *   - residual-component model (Sec. II, Fig. 6): trapped water/oil amounts read
  *     off the J-scaled (Eq. (5)) Pc-Sw curve at Pc^{ref,max} / Pc^{ref,min};
  *   - tensorial resistivity, Eqs. (6)-(7), principal axes from the Hessian and
@@ -66,6 +66,18 @@ enum { LBM_PORE = 0, LBM_SOLID = 1, LBM_GRAY = 2 };
 enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1, LBM_PREC_F16 = 2, LBM_PREC_BF16 = 3 };
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
+/* Time discretisation of the Brinkman resistance of Eq. (1) (paper silent).
+ * SEMI_IMPLICIT: R u with u = (rho I + R/2)^-1 (m + F_ex/2), the half-force
+ *   (trapezoidal) velocity: second order, the uniform Darcy state exact, and at
+ *   rest a force is carried entirely by pressure; the momentum of a voxel with
+ *   R >> rho reverses every step.
+ * IMPLICIT: R u* with u* = (rho I + R)^-1 (m + F_ex), the velocity after the
+ *   force (backward Euler): the uniform Darcy state exact and the momentum of a
+ *   strongly resisting voxel decays (L-stable), first order in R/rho; at rest
+ *   pressure carries only 2 rho / (2 rho + R) of a force inside a gray voxel.
+ * Either way F_res^a = -(rho^a / rho) R u and the reported velocity is
+ * (m + sum_a F^a / 2) / rho. */
+enum { LBM_RES_SEMI_IMPLICIT = 0, LBM_RES_IMPLICIT = 1 };
 
 #define LBM_TABLE_N 1025 /* samples of every constitutive curve on [0, 1] */
 #define LBM_MAX_TYPES 256
@@ -98,6 +110,7 @@ typedef struct lbm_params {
   double delta_tie;       /* tie-break: |l2| - |l1| <= delta_tie |l3| uses the gradient */
   int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
   int32_t track_flux;     /* 1: accumulate the outlet flux every step */
+  int32_t resistance;     /* LBM_RES_SEMI_IMPLICIT (default) | LBM_RES_IMPLICIT */
   /* device allocator hook (NULL = hipMalloc/hipFree); ctx is passed through */
   void *(*alloc)(size_t bytes, void *ctx);
   void (*free)(void *ptr, void *ctx);
@@ -125,7 +138,8 @@ typedef struct lbm_pore_table {
 /* Field output.  NULL pointers skip a field.  on_device = 0: host arrays of
  * N doubles; on_device = 1: device arrays of N values of the arithmetic type
  * (double for LBM_PREC_F64, float otherwise).  Values are at the current
- * time level: densities, the velocity u = (rho I + R/2)^-1 (m + F_ex/2),
+ * time level: densities, the velocity u = (m + sum_a F^a / 2) / rho with the
+ * total force (for the semi-implicit resistance, u = (rho I + R/2)^-1 (m + F_ex/2)),
  * residual-inclusive saturation S and residual amounts; zero in solid voxels. */
 typedef struct lbm_fields {
   int32_t on_device;

@@ -21,8 +21,11 @@ post-streaming population set at time n.  One step (Eq. (2)) is:
                  coefficient c_R = sum_b rho S^b nu^b / max(Kr^b, Kr_min) and
                  resistivity R = c_R K^-1 (scalar K0 or the tensor of
                  Eqs. (6)-(7));
-4. velocity      u = (rho I + R/2)^-1 (m + sum_a F_ex^a / 2) (semi-implicit),
-                 F_res^a = -(rho^a/rho) R u, F^a = F_ex^a + F_res^a;
+4. velocity      the resistance acts on u = (rho I + h R)^-1 (m + h sum_a F_ex^a),
+                 h = 1/2 (semi-implicit, the default) or h = 1 (implicit,
+                 backward Euler); F_res^a = -(rho^a/rho) R u,
+                 F^a = F_ex^a + F_res^a; the reported velocity is
+                 (m + sum_a F^a / 2) / rho (equal to u when h = 1/2);
 5. collision     equilibrium at the Shan-Chen common velocity
                  u' = sum(m^a/tau^a) / sum(rho^a/tau^a); non-equilibrium part
                  projected on Hermite orders 1-2 (regularised; BGK optional);
@@ -255,11 +258,13 @@ class Oracle:
             cR = np.where(self.gray, rho_t * nu, 0.0)
             out.update(S=np.where(fl, 1.0, 0.0), S_hat=np.where(fl, 1.0, 0.0), rhoT=rho_t)
         out["cR"] = cR
-        # semi-implicit velocity with the resistance of Eq. (1)
-        b = mom.sum(axis=0) + 0.5 * F_ex.sum(axis=0)
+        # velocity the resistance of Eq. (1) acts on: trapezoidal (h = 1/2)
+        # or backward Euler (h = 1) in the resistance
+        h = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
+        b = mom.sum(axis=0) + h * F_ex.sum(axis=0)
         if self.Kinv is None:
             Rs = np.where(self.gray, cR / np.where(self.gray, self.K0, 1.0), 0.0)
-            u = b / (safe + 0.5 * Rs)
+            u = b / (safe + h * Rs)
             Ru = Rs * u
         else:
             K = self.Kinv
@@ -268,17 +273,19 @@ class Oracle:
             for (i, j), k in idx.items():
                 Rm[i, j] = cR * K[k]
                 Rm[j, i] = cR * K[k]
-            A = 0.5 * Rm
+            A = h * Rm
             for d in range(3):
                 A[d, d] += safe
             Am = np.moveaxis(A, (0, 1), (-2, -1))
             bm = np.moveaxis(b, 0, -1)[..., None]
             u = np.moveaxis(np.linalg.solve(Am, bm)[..., 0], -1, 0)
             Ru = np.einsum("ij...,j...->i...", Rm, u)
-        u = np.where(fl, u, 0.0)
         F = np.empty_like(F_ex)
         for a in range(nc):
             F[a] = F_ex[a] - (rho[a] / safe) * Ru
+        if h != 0.5:
+            u = (mom.sum(axis=0) + 0.5 * F.sum(axis=0)) / safe
+        u = np.where(fl, u, 0.0)
         den = sum(rho[a] / self.tau[a] for a in range(nc))
         up = sum(mom[a] / self.tau[a] for a in range(nc)) / np.where(fl, den, 1.0)
         out.update(F_ex=F_ex, F=F, u=u, up=np.where(fl, up, 0.0), Ru=Ru)

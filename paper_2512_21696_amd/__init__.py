@@ -25,6 +25,7 @@ PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 STORE16 = ("f16", "bf16")
 COLL = {"regularized": 0, "bgk": 1}
 REGION = {"gray": 0, "all": 1}
+RESIST = {"semi_implicit": 0, "implicit": 1}
 TABLE_N = 1025
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -44,6 +45,7 @@ class lbm_params(ctypes.Structure):
         ("smooth_radius", ctypes.c_int32), ("outlet_x", ctypes.c_int32),
         ("eps_g", ctypes.c_double), ("eps_H", ctypes.c_double), ("delta_tie", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("track_flux", ctypes.c_int32),
+        ("resistance", ctypes.c_int32),
         ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
     ]
@@ -146,6 +148,7 @@ def to_c_params(params) -> lbm_params:
     p.G = float(params.G)
     p.kappa = float(params.kappa)
     p.csf_region = REGION[params.csf_region]
+    p.resistance = RESIST[getattr(params, "resistance", "semi_implicit")]
     p.tensor = int(bool(params.tensor))
     for k in ("phi_max", "phi_avg", "m_minor", "s_min", "s_max", "kr_min", "c_max", "c_min",
               "hyst", "eps_n", "sigma_s", "eps_g", "eps_H", "delta_tie"):

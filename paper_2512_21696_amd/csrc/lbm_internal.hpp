@@ -22,6 +22,7 @@ struct ModelConsts {
   int nx, ny, nz;
   long long N;
   int ncomp, collision, csf_all, tensor;
+  int res_implicit;  // 1: backward-Euler resistance, 0: semi-implicit
   double tau[2], omega[2], nu[2];
   double G;
   double g[2][3];

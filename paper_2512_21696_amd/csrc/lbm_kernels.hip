@@ -640,16 +640,20 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
     cR = rt * (T)mc.nu[0];
   }
 
-  // a5: semi-implicit velocity u = (rho I + R/2)^-1 (m + sum F_ex / 2)
+  // a5: velocity the resistance acts on, u = (rho I + h R)^-1 (m + h sum F_ex)
+  // with h = 1/2 (semi-implicit) or 1 (implicit); the reported velocity is
+  // (m + sum F / 2) / rho with the total force
+  const T h = mc.res_implicit ? (T)1 : (T)0.5;
   T b0 = 0, b1 = 0, b2 = 0, e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     b0 += mom[a][0]; b1 += mom[a][1]; b2 += mom[a][2];
     e0 += Fex[a][0]; e1 += Fex[a][1]; e2 += Fex[a][2];
   }
-  b0 = b0 + (T)0.5 * e0;
-  b1 = b1 + (T)0.5 * e1;
-  b2 = b2 + (T)0.5 * e2;
+  const T m0 = b0, m1 = b1, m2 = b2;
+  b0 = b0 + h * e0;
+  b1 = b1 + h * e1;
+  b2 = b2 + h * e2;
   T u0, u1, u2, Ru0 = 0, Ru1 = 0, Ru2 = 0;
   if (gray && mc.tensor) {
     const T *K = s.Kinv;
@@ -657,7 +661,6 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
     const T kxy = K[3 * N + v], kxz = K[4 * N + v], kyz = K[5 * N + v];
     const T Rxx = cR * kxx, Ryy = cR * kyy, Rzz = cR * kzz;
     const T Rxy = cR * kxy, Rxz = cR * kxz, Ryz = cR * kyz;
-    const T h = (T)0.5;
     const T a00 = rt + h * Rxx, a11 = rt + h * Ryy, a22 = rt + h * Rzz;
     const T a01 = h * Rxy, a02 = h * Rxz, a12 = h * Ryz;
     // symmetric 3x3 solve by the adjugate
@@ -672,9 +675,14 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
     Ru2 = Rxz * u0 + Ryz * u1 + Rzz * u2;
   } else {
     const T Rs = gray ? cR / s.K0[v] : (T)0;
-    const T den = rt + (T)0.5 * Rs;
+    const T den = rt + h * Rs;
     u0 = b0 / den; u1 = b1 / den; u2 = b2 / den;
     Ru0 = Rs * u0; Ru1 = Rs * u1; Ru2 = Rs * u2;
+  }
+  if (mc.res_implicit) {  // report (m + sum F / 2) / rho
+    u0 = (m0 + (T)0.5 * (e0 - Ru0)) / rt;
+    u1 = (m1 + (T)0.5 * (e1 - Ru1)) / rt;
+    u2 = (m2 + (T)0.5 * (e2 - Ru2)) / rt;
   }
 
   if (MODE == MODE_FIELDS) {

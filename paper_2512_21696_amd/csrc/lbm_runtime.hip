@@ -203,6 +203,7 @@ ModelConsts make_consts(const lbm_params &p) {
   mc.collision = p.collision;
   mc.csf_all = p.csf_region == LBM_CSF_ALL;
   mc.tensor = p.tensor;
+  mc.res_implicit = p.resistance == LBM_RES_IMPLICIT;
   for (int a = 0; a < 2; ++a) {
     double tau = (a < p.ncomp) ? p.tau[a] : 1.0;
     mc.tau[a] = tau;

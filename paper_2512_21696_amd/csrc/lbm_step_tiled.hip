@@ -56,7 +56,7 @@ __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 // them as scalar operands instead of converting inside the loop.
 template <typename T>
 struct KC {
-  int nx, ny, nz, csf_all, tensor, collision;
+  int nx, ny, nz, csf_all, tensor, collision, res_implicit;
   long long N;
   T g[2][3], omega[2], nu[2], wall_dpsi[2];
   T G, kappa, csf_fac, s_min, inv_span, kr_min, hyst, m_minor, eps_n2;
@@ -67,6 +67,7 @@ KC<T> make_kc(const ModelConsts &m) {
   KC<T> k{};
   k.nx = m.nx; k.ny = m.ny; k.nz = m.nz; k.N = m.N;
   k.csf_all = m.csf_all; k.tensor = m.tensor; k.collision = m.collision;
+  k.res_implicit = m.res_implicit;
   for (int a = 0; a < 2; ++a) {
     for (int d = 0; d < 3; ++d) k.g[a][d] = (T)m.g[a][d];
     k.omega[a] = (T)m.omega[a];
@@ -744,22 +745,23 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       cR = rt * mc.nu[0];
     }
 
-    // a5: semi-implicit velocity u = (rho I + R/2)^-1 (m + sum F_ex / 2)
+    // a5: velocity the resistance acts on, u = (rho I + h R)^-1 (m + h sum F_ex)
+    // with h = 1/2 (semi-implicit) or 1 (implicit)
+    const T h = mc.res_implicit ? (T)1 : (T)0.5;
     T b0 = 0, b1 = 0, b2 = 0, e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       b0 += mom[a][0]; b1 += mom[a][1]; b2 += mom[a][2];
       e0 += Fex[a][0]; e1 += Fex[a][1]; e2 += Fex[a][2];
     }
-    b0 = b0 + (T)0.5 * e0;
-    b1 = b1 + (T)0.5 * e1;
-    b2 = b2 + (T)0.5 * e2;
+    b0 = b0 + h * e0;
+    b1 = b1 + h * e1;
+    b2 = b2 + h * e2;
     T Ru0 = 0, Ru1 = 0, Ru2 = 0;
     if (gray && mc.tensor) {
       const T *K = s.Kinv;
       const T Rxx = cR * K[v], Ryy = cR * K[N + v], Rzz = cR * K[2 * N + v];
       const T Rxy = cR * K[3 * N + v], Rxz = cR * K[4 * N + v], Ryz = cR * K[5 * N + v];
-      const T h = (T)0.5;
       const T a00 = rt + h * Rxx, a11 = rt + h * Ryy, a22 = rt + h * Rzz;
       const T a01 = h * Rxy, a02 = h * Rxz, a12 = h * Ryz;
       const T c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22,
@@ -775,7 +777,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       Ru2 = Rxz * u0 + Ryz * u1 + Rzz * u2;
     } else if (gray) {
       const T Rs = cR * rcp(s.K0[v]);
-      const T q = Rs * rcp(rt + (T)0.5 * Rs);
+      const T q = Rs * rcp(rt + h * Rs);
       Ru0 = q * b0;
       Ru1 = q * b1;
       Ru2 = q * b2;

@@ -148,8 +148,9 @@ class Brute:
                 else:
                     cR = rt * cs2 * (p.tau[0] - 0.5)
                 R = cR / self.K0[z][y][x]
-            u = [(sum(mom[a][v][d] for a in range(nc)) + 0.5 * sum(Fex[a][d] for a in range(nc)))
-                 / (rt + 0.5 * R) for d in range(3)]
+            hh = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
+            u = [(sum(mom[a][v][d] for a in range(nc)) + hh * sum(Fex[a][d] for a in range(nc)))
+                 / (rt + hh * R) for d in range(3)]
             Ftot = [[Fex[a][d] - rho[a][v] / rt * R * u[d] for d in range(3)] for a in range(nc)]
             den = sum(rho[a][v] / p.tau[a] for a in range(nc))
             up = [sum(mom[a][v][d] / p.tau[a] for a in range(nc)) / den for d in range(3)]

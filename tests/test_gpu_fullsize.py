@@ -31,7 +31,9 @@ R = 4
 
 def _categories(cls, rng, per=24):
     """Seeded sample of fluid voxels: gray and pore voxels, each in the
-    interior and next to a solid."""
+    interior and next to a solid, and voxels on the fused kernel's tile edges
+    (x = 64 k - 1, 64 k; y = 4 k - 1, 4 k; z = 32 k - 1, 32 k) and on the
+    periodic wrap."""
     solid = cls == W.SOLID
     near = np.zeros_like(solid)
     for ax in range(3):
@@ -45,6 +47,19 @@ def _categories(cls, rng, per=24):
         idx = np.flatnonzero(sel)
         take = rng.choice(idx, size=min(per, idx.size), replace=False)
         picks += [(name, int(t)) for t in take]
+    fluid = cls != W.SOLID
+    n = cls.shape[0]
+    edge_x = np.array([0, 1, 63, 64, 127, 128, 191, 192, n - 2, n - 1])
+    edge_y = np.array([0, 3, 4, 127, 128, n - 1])
+    edge_z = np.array([0, 31, 32, 95, 96, n - 1])
+    got = 0
+    while got < 2 * per:
+        z = int(rng.choice(edge_z) if rng.random() < 0.5 else rng.integers(n))
+        y = int(rng.choice(edge_y) if rng.random() < 0.5 else rng.integers(n))
+        x = int(rng.choice(edge_x))
+        if fluid[z, y, x]:
+            picks.append(("tile edges and wrap", int(np.ravel_multi_index((z, y, x), cls.shape))))
+            got += 1
     return picks
 
 
@@ -121,7 +136,7 @@ def test_rock256_sampled_step_matches_oracle(prec, tol):
         assert bool(s1["side"][c]) == bool(o.side[R, R, R]), (name, c)
     print(prec, "worst relative error per category", {k: f"{v:.2e}" for k, v in worst.items()},
           "skipped near a threshold:", skipped)
-    assert len(worst) == 4
+    assert len(worst) == 5
     # a property of the whole grid: mass per component (mobile + residual) is
     # carried through the step up to rounding
     for k in ("mass_w", "mass_o"):

@@ -68,6 +68,18 @@ def test_csf_lowers_surface_tension_only(base_runs):
     assert abs(u1 / u0 - 1) < 0.15    # spurious current kept (measured 10 %)
 
 
+def test_kappa_calibration(base_runs):
+    """The stored CSF coefficients (tests/golden/make_kappa.py) still scale the
+    droplet's surface tension to 0.5 and 2 times its kappa = 0 value."""
+    with open(os.path.join(HERE, "golden", "kappa.json")) as fh:
+        gold = json.load(fh)
+    dp0 = base_runs[7][0]
+    for target, kappa in W.KAPPA_SIGMA_SCALE.items():
+        assert kappa == gold["targets"][str(target)]["kappa"]
+        dp = droplet2d(7, kappa)[0]
+        assert abs(dp / dp0 / target - 1) < 0.01, (target, dp / dp0)
+
+
 def test_coexistence_constant():
     with open(os.path.join(HERE, "golden", "coexistence.json")) as fh:
         gold = json.load(fh)
