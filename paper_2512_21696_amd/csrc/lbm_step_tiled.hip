@@ -108,19 +108,23 @@ __device__ inline float bload(rsrc_t r, uint32_t off, float) {
 __device__ inline double bload(rsrc_t r, uint32_t off, double) {
   return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
 }
+// Population stores are marked non-temporal (cache-policy bit 1, NT): the
+// new set is not read again within the step, and streaming it past the L2
+// leaves the L2 to the pulled lines that neighbouring tiles share.
+constexpr int kStoreNT = 2;
 __device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, float v) {
-  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, kStoreNT);
 }
 typedef unsigned int u32x2_t __attribute__((ext_vector_type(2)));
 __device__ inline void bstore(rsrc_t r, uint32_t voff, uint32_t soff, double v) {
-  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2_t, v), r, voff, soff, kStoreNT);
 }
 
 __device__ inline uint32_t bload16(rsrc_t r, uint32_t off) {
   return (uint32_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
 }
 __device__ inline void bstore16(rsrc_t r, uint32_t voff, uint32_t soff, uint16_t v) {
-  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, 0);
+  __builtin_amdgcn_raw_buffer_store_b16(v, r, voff, soff, kStoreNT);
 }
 template <int SK> __device__ inline float dec16(uint32_t bits);
 template <> __device__ inline float dec16<SK_F16>(uint32_t bits) {

@@ -109,6 +109,7 @@ def test_checkpoint_resume_bitwise_16bit(prec):
     b.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
     b.set_state(blob)
     b.step(12)
-    assert b.get_state() == fa
+    same = b.get_state() == fa  # (a bare assert would diff megabytes on failure)
+    assert same, "resumed run differs from the continuous run"
     a.destroy()
     b.destroy()
