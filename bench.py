@@ -255,7 +255,9 @@ def precision_drift(n, steps, every=100):
                     runs[prec].get_fields_device({name: t})
                     r = ref[name]
                     sc = r.abs().max().item()
-                    e[name] = float(f"{(t.double() - r).abs().max().item() / sc:.3e}")
+                    d = t.double() - r
+                    e[name] = float(f"{d.abs().max().item() / sc:.3e}")
+                    e[name + "_rms"] = float(f"{d.square().mean().sqrt().item() / sc:.3e}")
                 errs[prec][str(done)] = e
             del ref
             print(f"[drift] step {done}: " + json.dumps({p: errs[p].get(str(done)) for p in errs}),
@@ -263,7 +265,8 @@ def precision_drift(n, steps, every=100):
     for lb in runs.values():
         lb.destroy()
     print(json.dumps({"workload": wl["name"], "steps": steps, "compared_to": "f64 storage",
-                      "error": "max |X - X_f64| / max |X_f64| per field",
+                      "error": "max |X - X_f64| / max |X_f64| per field; *_rms: root mean "
+                               "square of X - X_f64 over all voxels / max |X_f64|",
                       "err_vs_f64": errs, "series_every": every, "series": series}),
           flush=True)
 

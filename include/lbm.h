@@ -59,10 +59,12 @@ enum { LBM_PORE = 0, LBM_SOLID = 1, LBM_GRAY = 2 };
  * BF16: populations stored in 16 bits, every other array and all arithmetic in
  * fp32.  A stored population is the offset h = f_i / w_i - rho_ref from the
  * equilibrium weight w_i, where rho_ref is the density (of the same component)
- * of the voxel that will read it, taken at the level the population was
- * written; two-component runs keep rho_ref per voxel in fp32, one-component
- * runs use rho_ref = 1.  In the bulk of either component h is small, so the
- * 16-bit rounding acts on the deviation from equilibrium rather than on f. */
+ * of the voxel that wrote it (the post-collision set of a voxel is close to
+ * its own equilibrium), taken at the level the population was written;
+ * two-component runs keep rho_ref per voxel in fp32, one-component runs use
+ * rho_ref = 1.  h is then of the order of the local velocity and
+ * non-equilibrium part, also next to an interface, so the 16-bit rounding acts
+ * on the deviation from the writer's equilibrium rather than on f. */
 enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1, LBM_PREC_F16 = 2, LBM_PREC_BF16 = 3 };
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
@@ -221,8 +223,10 @@ int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
 
 /* Checkpoint.  The state blob holds a header, the post-streaming populations
  * f[a][i][v] (storage type; for F16/BF16 the 16-bit offsets h, followed for
- * two components by the fp32 reference densities rho_ref[v][a] they are
- * relative to), the residual amounts r[a][v] (arithmetic type) and the side
+ * two components by the fp32 reference densities rho_ref[v][a]: the offset
+ * pulled by voxel v in direction i decodes as w_i (rho_ref[s] + h) with s the
+ * voxel it was pulled from, v - c_i, or v itself when v - c_i is solid), the
+ * residual amounts r[a][v] (arithmetic type) and the side
  * flags (one byte per voxel).  lbm_state_size gives its size in bytes; get/set
  * copy it to/from a host buffer of exactly that size.  Resuming is bitwise
  * exact. */

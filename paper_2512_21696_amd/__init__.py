@@ -309,8 +309,9 @@ class Lbm:
         """Splits a state blob into its sections (views on the blob): the
         post-streaming populations ``f`` (f64/f32 runs) or their raw 16-bit
         offsets ``codes`` plus the reference densities ``ref`` [z][y][x][a]
-        (two-component f16/bf16 runs), the residual amounts ``r`` and the side
-        flags ``side``."""
+        (two-component f16/bf16 runs; codes[a][i] at voxel d decodes as
+        w_i (ref[s][a] + h), s = d - c_i, or d itself when d - c_i is solid),
+        the residual amounts ``r`` and the side flags ``side``."""
         hdr = 8 + 4 + 4 + 4 * 4 + 8 + 4 * 8
         prec = self.params.precision
         es = 8 if prec == "f64" else 4

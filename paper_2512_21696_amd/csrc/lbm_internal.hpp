@@ -48,6 +48,9 @@ struct DevState {
                      // of the stored offsets (the reader's density)
   T *rho;            // densities at the current level [a][v] (field evaluation)
   T *rho2;           // the same, interleaved [v][a] (fused step)
+  T *rhoS;           // 16-bit two-component runs: sum_i w_i rho_ref(s_i) over the
+                     // sources s_i of each voxel's next pulls [v][a], written by
+                     // the fused step for the density pass that follows it
   T *nrm;            // CSF normals [a][3][v] (only when kappa != 0)
   uint32_t *mask;    // neighbour-solid bits and class
   uint8_t *ptype;    // pore type per voxel

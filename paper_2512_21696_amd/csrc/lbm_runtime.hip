@@ -51,6 +51,7 @@ struct lbm_handle {
   int cur = 0;
   int ntab = 0;
   bool has_geom = false, has_fluid = false, rho_valid = false, rho2_valid = false;
+  bool rhoS_valid = false;  // 16-bit runs: rhoS belongs to the stored set
   int64_t step = 0;
   DevState<double> sd{};
   DevState<float> sf{};
@@ -164,11 +165,14 @@ int alloc_state(lbm_handle *h) {
   s.f[0] = alloc_into<T>(h, L, (size_t)nc * Q * N, &ok);
   s.f[1] = h->sk == SK_NATIVE ? alloc_into<T>(h, L, (size_t)nc * Q * N, &ok) : nullptr;
   s.fc[0] = s.fc[1] = nullptr;
-  s.rhoE = nullptr;
+  s.rhoE = s.rhoS = nullptr;
   if (h->sk != SK_NATIVE) {
     s.fc[0] = alloc_into<uint16_t>(h, L, (size_t)nc * Q * N, &ok);
     s.fc[1] = alloc_into<uint16_t>(h, L, (size_t)nc * Q * N, &ok);
-    if (nc == 2) s.rhoE = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+    if (nc == 2) {
+      s.rhoE = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+      s.rhoS = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+    }
   }
   s.rho = alloc_into<T>(h, L, (size_t)2 * N, &ok);
   s.rho2 = alloc_into<T>(h, L, (size_t)2 * N, &ok);
@@ -387,18 +391,29 @@ void ensure_density(lbm_handle *h) {
   if (h->p.ncomp == 2 && !h->rho2_valid) {
     Timed tm(h, K_AUX);
     if (h->sk == SK_NATIVE) {
-      hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE>), dim3(blocks(N)), dim3(256), 0, h->st,
-                         (const void *)s.f[h->cur], s.rho2, (const T *)nullptr, s.mask, h->p.nx,
-                         h->p.ny, h->p.nz, N);
+      hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE, false>), dim3(blocks(N)), dim3(256), 0, h->st,
+                         (const void *)s.f[h->cur], s.rho2, (const T *)nullptr,
+                         (const T *)nullptr, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
     } else if constexpr (std::is_same<T, float>::value) {
-      if (h->sk == SK_F16)
-        hipLaunchKernelGGL((k_density<float, 2, SK_F16>), dim3(blocks(N)), dim3(256), 0, h->st,
-                           (const void *)s.fc[h->cur], s.rho2, s.rhoE, s.mask, h->p.nx, h->p.ny,
-                           h->p.nz, N);
-      else
-        hipLaunchKernelGGL((k_density<float, 2, SK_BF16>), dim3(blocks(N)), dim3(256), 0, h->st,
-                           (const void *)s.fc[h->cur], s.rho2, s.rhoE, s.mask, h->p.nx, h->p.ny,
-                           h->p.nz, N);
+      // the reference sums of the last step, unless the stored set came from
+      // elsewhere (initialisation, a state blob) or a checkpoint was taken
+      const void *fc = s.fc[h->cur];
+      const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
+      if (h->sk == SK_F16) {
+        if (h->rhoS_valid)
+          hipLaunchKernelGGL((k_density<float, 2, SK_F16, false>), dim3(blocks(N)), dim3(256), 0,
+                             h->st, fc, s.rho2, s.rhoE, s.rhoS, s.mask, nx, ny, nz, N);
+        else
+          hipLaunchKernelGGL((k_density<float, 2, SK_F16, true>), dim3(blocks(N)), dim3(256), 0,
+                             h->st, fc, s.rho2, s.rhoE, s.rhoS, s.mask, nx, ny, nz, N);
+      } else {
+        if (h->rhoS_valid)
+          hipLaunchKernelGGL((k_density<float, 2, SK_BF16, false>), dim3(blocks(N)), dim3(256), 0,
+                             h->st, fc, s.rho2, s.rhoE, s.rhoS, s.mask, nx, ny, nz, N);
+        else
+          hipLaunchKernelGGL((k_density<float, 2, SK_BF16, true>), dim3(blocks(N)), dim3(256), 0,
+                             h->st, fc, s.rho2, s.rhoE, s.rhoS, s.mask, nx, ny, nz, N);
+      }
     }
     h->rho2_valid = true;
   }
@@ -511,6 +526,7 @@ int step_t(lbm_handle *h, int64_t n) {
     // 16-bit runs: the new offsets are relative to the densities of the level
     // just left, which the density pass wrote into rho2
     if (h->sk != SK_NATIVE && h->p.ncomp == 2) std::swap(s.rhoE, s.rho2);
+    h->rhoS_valid = h->sk != SK_NATIVE && h->p.ncomp == 2;
     h->rho_valid = false;
     h->rho2_valid = false;
     h->dec_valid = false;
@@ -603,6 +619,7 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
   }
   h->rho_valid = false;
   h->rho2_valid = false;
+  h->rhoS_valid = false;
   h->dec_valid = false;
   if (rc == LBM_OK) {
     ensure_aux<T>(h);
@@ -663,6 +680,9 @@ template <typename T>
 int get_state_t(lbm_handle *h, void *buf) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
+  // 16-bit runs: the next density pass gathers the reference sums itself, as
+  // a run resumed from this blob will, so the two continue bitwise alike
+  h->rhoS_valid = false;
   // canonical (post-streaming) order; 16-bit offsets are already relative to
   // the reader, so their gather is a plain permutation
   const void *C = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur] : (const void *)s.fc[1 - h->cur];
@@ -765,6 +785,7 @@ int set_state_t(lbm_handle *h, const void *buf) {
     h->step = hd.step;
     h->rho_valid = false;
     h->rho2_valid = false;
+    h->rhoS_valid = false;
     h->dec_valid = false;
     h->has_fluid = true;
   }

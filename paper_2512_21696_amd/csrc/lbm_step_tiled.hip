@@ -29,12 +29,12 @@
 //
 // 16-bit storage (fp16 or bf16, fp32 arithmetic): a stored population is the
 // offset h = f_i / w_i - rho_ref, rho_ref being the density of the voxel that
-// reads it (the destination of the pull, or the voxel itself under
-// bounce-back) at the level it was written.  The reader therefore decodes
-// every pulled value with its own reference, f_i = w_i (rho_ref + h), and the
-// writer encodes with the destination densities it already holds in LDS.  The
-// moments are accumulated from the offsets with the reference added exactly
-// once, so the fp32 weights never multiply the bulk density.
+// wrote it, at the level it was written.  A voxel's post-collision set is close
+// to its own equilibrium, so h is of the order of its velocity and
+// non-equilibrium part even where the neighbour that pulls it lies across an
+// interface.  The writer encodes with its own density; the reader decodes each
+// pulled value with the reference of the voxel it came from, which the block
+// stages in LDS (three planes of the previous level's densities).
 #include <type_traits>
 
 namespace lbm {
@@ -229,15 +229,15 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
   }
 }
 
-// 16-bit variant: stores enc(c_i(A + B.c_i + c_i^T C c_i) sc - ref_i) where
-// ref_i is the reference density of the voxel that reads slot i (plus
-// keep * sc * g_i, g_i = f_i / w_i, for BGK).
+// 16-bit variant: stores enc((A + B.c_i + c_i^T C c_i) sc - ref) where ref
+// is the writing voxel's density (plus keep * sc * g_i, g_i = f_i / w_i, for
+// BGK).
 template <int SK, bool REG>
 __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t sbase,
                                             uint32_t Nbytes, float A, float B0, float B1,
                                             float B2, float Cxx, float Cyy, float Czz, float Cxy,
                                             float Cxz, float Cyz, float sc, const float *gpop,
-                                            float keep, bool zero, const float *ref) {
+                                            float keep, bool zero, float ref) {
   float v[Q];
   v[0] = A;
   const float ax = A + Cxx, ay = A + Cyy, az = A + Czz;
@@ -270,7 +270,7 @@ __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t 
   for (int i = 0; i < Q; ++i) {
     float val = v[i] * sc;
     if (!REG) val += keep * sc * gpop[i];
-    val -= ref[i];
+    val -= ref;
     bstore16(out, voff, so, zero ? (uint16_t)0 : enc16<SK>(val));
     so += Nbytes;
     keep_scalar(so);
@@ -282,10 +282,12 @@ __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t 
 // interleaved [v][rho_w, rho_o].  Solid voxels get +inf in both slots: the
 // fused step recognises solid halo cells by it (a fluid density is finite),
 // and never uses the value itself.  With 16-bit storage
-// rho = rho_ref + sum_i w_i h_i, rho_ref from rhoE.
-template <typename T, int NC, int SK>
+// rho = sum_i w_i (rho_ref(s_i) + h_i), s_i the voxel the offset was pulled
+// from (its writer) and rho_ref from rhoE.
+template <typename T, int NC, int SK, bool GATHER>
 __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
                                                  T *__restrict__ rho2, const T *__restrict__ rhoE,
+                                                 const T *__restrict__ rhoS,
                                                  const uint32_t *__restrict__ mask, int nx, int ny,
                                                  int nz, long long N) {
   const uint32_t v = blockIdx.x * 256u + threadIdx.x;
@@ -308,33 +310,39 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
   const uint32_t Z3[3] = {(z == 0 ? nz - 1 : z - 1) * nxy, z * nxy,
                           (z == (uint32_t)nz - 1 ? 0 : z + 1) * nxy};
   constexpr uint32_t ES = SK == SK_NATIVE ? (uint32_t)sizeof(T) : 2u;
-  T ref[2] = {0, 0};
-  if constexpr (SK != SK_NATIVE) {
-    const vec2<T> e = reinterpret_cast<const vec2<T> *>(rhoE)[v];
-    ref[0] = e.x;
-    ref[1] = e.y;
-  }
   T r[2] = {0, 0};
+  // 16-bit storage: the reference part sum_i w_i rho_ref(s_i) comes from
+  // the step that wrote the set (rhoS), or is gathered here (GATHER)
+  constexpr bool gather = SK != SK_NATIVE && GATHER;
+  T q[2] = {0, 0};
+  if constexpr (SK != SK_NATIVE && !GATHER) {
+    const vec2<T> e = reinterpret_cast<const vec2<T> *>(rhoS)[v];
+    q[0] = e.x;
+    q[1] = e.y;
+  }
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     const rsrc_t rin = make_rsrc((const char *)fin + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
-    const T v0 = pull_value<T, SK>(rin, v);
+    T v0 = pull_value<T, SK>(rin, v);
+    if constexpr (gather) v0 += rhoE[2 * v + a];
     T axis = 0, diag = 0;
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
       const int j = i + 1;
-      const uint32_t oi = ((mk >> j) & 1u)
-                              ? (uint32_t)j * N32 + v
-                              : (uint32_t)i * N32 + X3[1 - cx(i)] + Y3[1 - cy(i)] + Z3[1 - cz(i)];
-      const uint32_t oj = ((mk >> i) & 1u)
-                              ? (uint32_t)i * N32 + v
-                              : (uint32_t)j * N32 + X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
-      const T pair = pull_value<T, SK>(rin, oi) + pull_value<T, SK>(rin, oj);
+      // sources: x - c_i for i, x + c_i for j; this voxel under bounce-back
+      const bool bi = (mk >> j) & 1u, bj = (mk >> i) & 1u;
+      const uint32_t si = bi ? v : X3[1 - cx(i)] + Y3[1 - cy(i)] + Z3[1 - cz(i)];
+      const uint32_t sj = bj ? v : X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
+      const uint32_t oi = bi ? (uint32_t)j * N32 + v : (uint32_t)i * N32 + si;
+      const uint32_t oj = bj ? (uint32_t)i * N32 + v : (uint32_t)j * N32 + sj;
+      T pair = pull_value<T, SK>(rin, oi) + pull_value<T, SK>(rin, oj);
+      // 16-bit: each offset decodes with its writer's reference density
+      if constexpr (gather) pair += rhoE[2 * si + a] + rhoE[2 * sj + a];
       if (i < 7) axis += pair;
       else diag += pair;
     }
     if constexpr (SK == SK_NATIVE) r[a] = v0 + axis + diag;
-    else r[a] = ref[a] + (T)(1.0 / 3.0) * v0 + (T)(1.0 / 18.0) * axis + (T)(1.0 / 36.0) * diag;
+    else r[a] = q[a] + ((T)(1.0 / 3.0) * v0 + (T)(1.0 / 18.0) * axis + (T)(1.0 / 36.0) * diag);
   }
   out[v] = vec2<T>{r[0], r[1]};
 }
@@ -352,6 +360,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ T sshat[STENCIL ? RS : 1][STENCIL ? NH : 1];  // mobile saturation S_hat
   __shared__ T2 snrm[3][STENCIL ? NM : 1];                  // (n^w_d, n^o_d) of one plane
   __shared__ int sxw[HX], syw[HY];
+  // 16-bit storage, two components: reference densities (the writers'
+  // densities of the previous level) of planes z-1 .. z+1 on the tile plus a
+  // radius-1 halo, in a ring of three planes
+  constexpr bool REFS = SK != SK_NATIVE && NC == 2;
+  __shared__ T2 sref[REFS ? 3 : 1][REFS ? NM : 1];
 
   const int nb = gridDim.x;
   const int b = blockIdx.x;
@@ -411,6 +424,34 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
   };
+  // staging of one reference plane (same pattern on the 66 x 6 normal tile)
+  constexpr int CPE = (NM + NT - 1) / NT;
+  uint32_t ecell_g[CPE];
+  T2 pre_e[CPE];
+  if (REFS) {
+#pragma unroll
+    for (int q = 0; q < CPE; ++q) {
+      const int k = tid + q * NT;
+      const int kk = k < NM ? k : 0;
+      const int lx = kk % MX, ly = kk / MX;
+      ecell_g[q] = (uint32_t)sxw[lx + 1] + (uint32_t)nx * (uint32_t)syw[ly + 1];
+    }
+  }
+  auto fetch_ref = [&](int zz) {
+    const uint32_t zoff = (uint32_t)wrapn(zz, nz) * nxy;
+#pragma unroll
+    for (int q = 0; q < CPE; ++q)
+      if (tid + q * NT < NM) pre_e[q] = reinterpret_cast<const T2 *>(s.rhoE)[zoff + ecell_g[q]];
+  };
+  auto store_ref = [&](int zz) {
+    const int sl = (zz + 3) % 3;
+#pragma unroll
+    for (int q = 0; q < CPE; ++q) {
+      const int k = tid + q * NT;
+      if (k < NM) sref[sl][k] = pre_e[q];
+    }
+  };
+
   // CSF normals of plane zz from the density planes zz-1 .. zz+1 (a solid
   // neighbour takes the cell's own density; solid cells get a zero normal)
   auto make_normals = [&](int zz) {
@@ -514,6 +555,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       fetch_rho(zz);
       store_rho(zz);
     }
+    if (REFS) {
+      for (int zz = zs - 1; zz <= zs; ++zz) {
+        fetch_ref(zz);
+        store_ref(zz);
+      }
+    }
     __syncthreads();
     if (csf) {
       make_normals(zs - 1);
@@ -525,6 +572,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       accum(std::integral_constant<int, 0>{});
     }
     fetch_rho(zs + 2);
+    if (REFS) fetch_ref(zs + 1);
   }
 
   rsrc_t rin[NC], rout[NC];
@@ -539,7 +587,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // its next plane's loads in flight (and ahead of its own stores).
   using LT = typename std::conditional<S16, uint32_t, T>::type;
   LT pf[NC][Q];
-  T pfref[NC];
   auto issue = [&](int zz, uint32_t mkz) {
     const uint32_t zo = (uint32_t)zz * nxy;
     const uint32_t vv = vxy + zo;
@@ -567,13 +614,6 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       so += 2 * NE;
       keep_scalar(so);
     }
-    if constexpr (S16) {
-      if (NC == 2) {
-        const T2 e = reinterpret_cast<const T2 *>(s.rhoE)[vv];
-        pfref[0] = e.x;
-        pfref[NC - 1] = e.y;
-      }
-    }
   };
   auto all_solid = [](uint32_t mkz) { return __all(((mkz >> CLASS_SHIFT) & 3u) == SOLID_CODE); };
   if (inside && !all_solid(M[0])) issue(zs, M[0]);
@@ -584,12 +624,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       // the barrier also ends every read of the previous normal plane
       store_rho(z + 2);
       __syncthreads();
+      if (REFS) {
+        // plane z+1 takes the slot of plane z-2, whose last reader (plane
+        // z-1's pulls) finished before the barrier above; the next barrier
+        // orders it before this plane's pulls
+        store_ref(z + 1);
+        if (!csf) __syncthreads();
+      }
       if (csf) {
         make_normals(z + 1);
         __syncthreads();
         accum(std::integral_constant<int, 1>{});
       }
-      if (z + 1 < ze) fetch_rho(z + 3);
+      if (z + 1 < ze) {
+        fetch_rho(z + 3);
+        if (REFS) fetch_ref(z + 2);
+      }
     }
     if (!inside) continue;
     const uint32_t zoff = (uint32_t)z * nxy;
@@ -605,34 +655,50 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const bool gray = cl == GRAY_CODE;
 
     // a1 + a2: the pulled populations of this plane (bounce-back resolved at
-    // issue) summed into moments over opposite pairs.  16-bit storage: the
-    // offsets are weighted as they arrive and the reference enters rho and
-    // the diagonal of P once.
+    // issue) summed into moments over opposite pairs.  16-bit storage: each
+    // pulled offset decodes with the reference density of the voxel it came
+    // from (this voxel's own under bounce-back), g = ref + h = f_i / w_i.
     T rho[NC], mom[NC][3], P[NC][6];  // P: xx, yy, zz, xy, xz, yz
     T f[REG ? 1 : NC][REG ? 1 : Q];   // BGK: f_i (native) or f_i / w_i (16-bit)
-    T refo[NC];
     if (!skip) {
+      T Ro[NC];  // this voxel's reference densities
+      const int e0 = (z + 3) % 3;
 #pragma unroll
-      for (int a = 0; a < NC; ++a) refo[a] = (S16 && NC == 2) ? pfref[a] : (T)1;
+      for (int a = 0; a < NC; ++a)
+        Ro[a] = REFS ? reinterpret_cast<const T *>(&sref[e0][cn])[a] : (T)1;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
-        const T f0 = pull_decode<T, SK>(pf[a][0]);
-        if (!REG) f[REG ? 0 : a][0] = S16 ? refo[a] + f0 : f0;
-        rho[a] = S16 ? refo[a] + (T)(1.0 / 3.0) * f0 : f0;
+        T g0 = pull_decode<T, SK>(pf[a][0]);
+        if (S16) g0 += Ro[a];
+        if (!REG) f[REG ? 0 : a][0] = g0;
+        rho[a] = S16 ? (T)(1.0 / 3.0) * g0 : g0;
         mom[a][0] = mom[a][1] = mom[a][2] = 0;
 #pragma unroll
-        for (int d = 0; d < 6; ++d) P[a][d] = (S16 && d < 3) ? refo[a] * cs2 : (T)0;
+        for (int d = 0; d < 6; ++d) P[a][d] = 0;
       }
 #pragma unroll
       for (int i = 1; i < Q; i += 2) {
         const int j = i + 1;
+        // pull of i from x - c_i, of j from x + c_i; bounce-back when solid
+        const bool bbi = (mk >> j) & 1u, bbj = (mk >> i) & 1u;
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
           T fi = pull_decode<T, SK>(pf[a][i]);
           T fj = pull_decode<T, SK>(pf[a][j]);
+          if (S16) {
+            T Ri = Ro[a], Rj = Ro[a];
+            if (REFS) {
+              if (!bbi)
+                Ri = reinterpret_cast<const T *>(&sref[(z - cz(i) + 3) % 3][cn - moff(i)])[a];
+              if (!bbj)
+                Rj = reinterpret_cast<const T *>(&sref[(z + cz(i) + 3) % 3][cn + moff(i)])[a];
+            }
+            fi += Ri;
+            fj += Rj;
+          }
           if (!REG) {
-            f[REG ? 0 : a][i] = S16 ? refo[a] + fi : fi;
-            f[REG ? 0 : a][j] = S16 ? refo[a] + fj : fj;
+            f[REG ? 0 : a][i] = fi;
+            f[REG ? 0 : a][j] = fj;
           }
           if (S16) {
             const T w = i < 7 ? (T)(1.0 / 18.0) : (T)(1.0 / 36.0);
@@ -681,6 +747,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         pw[bb] = p_ > (T)0 ? p_ : (T)0;
       }
       T aw0 = 0, aw1 = 0, aw2 = 0, ao0 = 0, ao1 = 0, ao2 = 0;
+      // 16-bit storage: the reference part sum_i w_i rho_ref(s_i) of the next
+      // level's densities (this level's densities are the next references;
+      // a solid neighbour means bounce-back, whose writer is this voxel)
+      const T2 eown = srho[rslot(z)][c];
+      T qw = (T)(1.0 / 3.0) * eown.x, qo = (T)(1.0 / 3.0) * eown.y;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
         const T2 e = srho[rslot(z + cz(i))][c + hoff(i)];
@@ -690,7 +761,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (cx(i)) { aw0 += (T)(wq(i) * cx(i)) * vw; ao0 += (T)(wq(i) * cx(i)) * vo; }
         if (cy(i)) { aw1 += (T)(wq(i) * cy(i)) * vw; ao1 += (T)(wq(i) * cy(i)) * vo; }
         if (cz(i)) { aw2 += (T)(wq(i) * cz(i)) * vw; ao2 += (T)(wq(i) * cz(i)) * vo; }
+        if (S16) {
+          qw += (T)wq(i) * (sol ? eown.x : e.x);
+          qo += (T)wq(i) * (sol ? eown.y : e.y);
+        }
       }
+      if (S16) reinterpret_cast<T2 *>(s.rhoS)[v] = T2{qw, qo};
       {
         const T kw = -mc.G * rho[0], ko = -mc.G * rho[1];
         Fex[0][0] += kw * ao0; Fex[0][1] += kw * ao1; Fex[0][2] += kw * ao2;
@@ -874,22 +950,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz,
                           Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid);
       } else {
-        // reference of each outgoing slot: the destination's density of this
-        // level, or this voxel's own under bounce-back (exactly the values
-        // the density pass wrote, so the reader decodes with the same floats)
-        float ref[Q];
-        if (NC == 2) {
-          const float own = reinterpret_cast<const float *>(&srho[rslot(z)][c])[a];
-#pragma unroll
-          for (int i = 0; i < Q; ++i)
-            ref[i] = (i > 0 && !((mk >> i) & 1u))
-                         ? reinterpret_cast<const float *>(
-                               &srho[rslot(z + cz(i))][c + hoff(i)])[a]
-                         : own;
-        } else {
-#pragma unroll
-          for (int i = 0; i < Q; ++i) ref[i] = 1.f;
-        }
+        // reference of every outgoing slot: this voxel's density of this
+        // level (exactly the value the density pass wrote, which becomes the
+        // readers' reference array)
+        const float ref = NC == 2 ? reinterpret_cast<const float *>(&srho[rslot(z)][c])[a] : 1.f;
         emit_post16<SK, REG>(rout[a], vxy * 2u, zoff * 2u, N32 * 2u, A, B0, B1, B2, Cxx, Cyy, Czz,
                              Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, ref);
       }
@@ -901,12 +965,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // 16-bit storage: conversions between the stored offsets and fp32 populations
 // (field evaluation, initialisation) and the per-step outlet flux.
 
-// Reference density of component a for the voxel that reads slot (v, i).
-__device__ inline float slot_ref(const float *rhoE, const Nbr &nb, uint32_t mk, long long v,
-                                 int i, int a, int nc) {
-  if (nc == 1) return 1.f;
-  const long long rd = (i > 0 && !((mk >> i) & 1u)) ? (long long)nb.at(cx(i), cy(i), cz(i)) : v;
-  return rhoE[2 * rd + a];
+// Reference density of component a of the slots stored at voxel v: the
+// density of v (their writer) at the level they were written.
+__device__ inline float writer_ref(const float *rhoE, long long v, int a, int nc) {
+  return nc == 1 ? 1.f : rhoE[2 * v + a];
 }
 
 // stored offsets (slot layout) -> fp32 populations f = w_i (rho_ref + h)
@@ -920,13 +982,13 @@ __global__ __launch_bounds__(256) void k_decode(const uint16_t *__restrict__ cod
   if (v >= N) return;
   const uint32_t mk = mask[v];
   const bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
-  const Nbr nb((int)v, nx, ny, nz);
   for (int a = 0; a < nc; ++a) {
+    const float ref = solid ? 0.f : writer_ref(rhoE, v, a, nc);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const size_t k = (size_t)(a * Q + i) * N + v;
       float val = 0.f;
-      if (!solid) val = (float)wq(i) * (slot_ref(rhoE, nb, mk, v, i, a, nc) + dec16<SK>(codes[k]));
+      if (!solid) val = (float)wq(i) * (ref + dec16<SK>(codes[k]));
       out[k] = val;
     }
   }
@@ -972,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_scatter_enc(const float *__restrict__ C
         const float val = bb ? C[(size_t)(a * Q + opp(i)) * N + v]
                              : C[(size_t)(a * Q + i) * N + nb.at(cx(i), cy(i), cz(i))];
         const float inv_w = i == 0 ? 3.f : (i < 7 ? 18.f : 36.f);
-        code = enc16<SK>(val * inv_w - slot_ref(rhoE, nb, mk, v, i, a, nc));
+        code = enc16<SK>(val * inv_w - writer_ref(rhoE, v, a, nc));
       }
       codes[(size_t)(a * Q + i) * N + v] = code;
     }
@@ -996,7 +1058,6 @@ __global__ void k_flux16(const ModelConsts mc, const uint16_t *__restrict__ code
     const uint32_t m0 = mask[v0], m1 = mask[v1];
     const bool f0 = ((m0 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
-    const Nbr n0((int)v0, mc.nx, mc.ny, mc.nz), n1((int)v1, mc.nx, mc.ny, mc.nz);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double q = 0.0;
@@ -1004,11 +1065,11 @@ __global__ void k_flux16(const ModelConsts mc, const uint16_t *__restrict__ code
       for (int i = 1; i < Q; ++i) {
         if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) {
           const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v0]);
-          q += (double)((float)wq(i) * (slot_ref(rhoE, n0, m0, v0, i, a, NC) + h));
+          q += (double)((float)wq(i) * (writer_ref(rhoE, v0, a, NC) + h));
         }
         if (cx(i) == -1 && f1 && !((m1 >> i) & 1u)) {
           const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v1]);
-          q -= (double)((float)wq(i) * (slot_ref(rhoE, n1, m1, v1, i, a, NC) + h));
+          q -= (double)((float)wq(i) * (writer_ref(rhoE, v1, a, NC) + h));
         }
       }
       val[a] = q;

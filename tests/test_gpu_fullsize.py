@@ -20,7 +20,7 @@ import numpy as np
 import pytest
 
 import workloads as W
-from oracle import Oracle, W as WQ
+from oracle import Oracle, W as WQ, C as CQ
 from gpu_common import announce
 
 pytestmark = pytest.mark.gpu
@@ -87,9 +87,11 @@ def _states(prec, steps):
     return wl, s0, s1, d0, d1
 
 
-def _decoded_crop(st, prec, c):
-    """f / w_i (float64) of the (2R+1)^3 crop of a state around c; 16-bit
-    offsets decode as rho_ref + h, solid voxels as 0."""
+def _decoded_crop(st, prec, c, cls):
+    """f / w_i (float64) of the (2R+1)^3 crop of a state around c; a 16-bit
+    offset pulled by voxel d in direction i decodes as rho_ref(s) + h with s
+    the voxel it came from (d - c_i, or d itself when d - c_i is solid);
+    solid voxels decode as 0."""
     w = WQ.reshape((1, 19, 1, 1, 1))
     if prec == "f32":
         return _crop(st["f"], c, 2).astype(np.float64) / w
@@ -98,8 +100,17 @@ def _decoded_crop(st, prec, c):
         h = bits.view(np.float16).astype(np.float64)
     else:
         h = (bits.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
-    ref = np.moveaxis(_crop(np.moveaxis(st["ref"], -1, 0), c, 1), 0, 0).astype(np.float64)
-    return np.where(np.isfinite(ref)[:, None], ref[:, None] + h, 0.0)
+    ref_full = np.moveaxis(st["ref"], -1, 0)  # [a][z][y][x]
+    own = _crop(ref_full, c, 1).astype(np.float64)
+    refs = np.empty(h.shape)
+    for i in range(19):
+        shift = (int(CQ[i, 2]), int(CQ[i, 1]), int(CQ[i, 0]))  # (c_z, c_y, c_x)
+        idx = [(np.arange(ci - R, ci + R + 1) - d) % N_SIDE for ci, d in zip(c, shift)]
+        src = ref_full[(slice(None),) + np.ix_(*idx)].astype(np.float64)
+        src_solid = cls[np.ix_(*idx)] == W.SOLID
+        refs[:, i] = np.where(src_solid[None], own, src)
+    solid = _crop(cls, c, 0) == W.SOLID
+    return np.where(solid[None, None], 0.0, refs + h)
 
 
 @pytest.mark.parametrize("prec,tol", [("f32", 1e-5), ("f16", 1e-3)])
@@ -117,7 +128,7 @@ def test_rock256_sampled_step_matches_oracle(prec, tol):
         o = Oracle(p)
         o.set_geometry(_crop(cls, c, 0), _crop(wl["phi"], c, 0), _crop(wl["ptype"], c, 0),
                        wl["tables"])
-        o.set_state(dict(f=_decoded_crop(s0, prec, c) * w,
+        o.set_state(dict(f=_decoded_crop(s0, prec, c, cls) * w,
                          r=_crop(s0["r"], c, 1).astype(np.float64),
                          side=_crop(s0["side"], c, 0).astype(bool), step=0,
                          Q_acc=np.zeros(2), Q_last=np.zeros(2)))
@@ -126,7 +137,7 @@ def test_rock256_sampled_step_matches_oracle(prec, tol):
             skipped += 1  # a residual-event switch this close to its threshold may go either way
             continue
         o.step(1)
-        got = _decoded_crop(s1, prec, c)[:, :, R, R, R]
+        got = _decoded_crop(s1, prec, c, cls)[:, :, R, R, R]
         ref = o.f[:, :, R, R, R] / WQ[None, :]
         err = np.abs(got - ref).max() / np.abs(ref).max()
         worst[name] = max(worst.get(name, 0.0), err)

@@ -3,9 +3,9 @@ fp32 arithmetic) through the C ABI, against the fp64 oracle.
 
 Tolerances.  Every step rounds each stored offset once, to p = 11 (fp16) or
 p = 8 (bf16) significant bits: an absolute error of at most 2^-p |h| in f_i / w_i.
-|h| is the deviation of f_i / w_i from the reader's density: O(|u|/cs^2) in the
-bulk of either component and at most about 1 across an interface (densities
-are O(1)).  Over n steps the independent roundings add up like a random walk,
+|h| is the deviation of f_i / w_i from the writer's density: O(|u|/cs^2) plus the
+non-equilibrium part after a collision, and at most about 1 (densities are
+O(1)) for the sets written from a canonical state at initialisation.  Over n steps the independent roundings add up like a random walk,
 about 2^-p sqrt(n) in density (weights sum to 1); momentum collects at most
 1/6 of it (sum over c_x > 0 of w_i).  The bounds below are twice that, in
 absolute terms (densities and saturation on the scale 1, velocities in lattice
