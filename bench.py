@@ -193,6 +193,48 @@ def calibrate_copy(mib=1024, narr=38, reps=5):
     print(json.dumps({"yardsticks": res, "reps": reps}), flush=True)
 
 
+def rev_library(steps=400):
+    """The batched permeability library: 96 sphere-pack domains of edge 24..96
+    (workloads.rev_domains) run together in fp32.  Fixed work first (`steps`
+    steps, timed against a zero-step call, so the per-step time excludes
+    packing and set-up), then a run to convergence for the K values."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2512_21696_amd as L
+    wr = W.rev_domains()
+    doms = [d["cls"] for d in wr]
+    nvox = sum(c.size for c in doms)
+    npore = sum(int(np.count_nonzero(c == 0)) for c in doms)
+    kw = dict(tau=1.0, g=1e-5, axis=0, precision="f32", check_every=100)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    L.rev_permeability(doms, max_steps=0, tol=0.0, **kw)
+    t0 = time.perf_counter() - t0
+    t1 = time.perf_counter()
+    L.rev_permeability(doms, max_steps=steps, tol=0.0, **kw)
+    t1 = time.perf_counter() - t1
+    ms = (t1 - t0) / steps * 1e3
+    t2 = time.perf_counter()
+    conv = L.rev_permeability(doms, max_steps=20000, tol=1e-6, **kw)
+    t2 = time.perf_counter() - t2
+    K = np.array([r["K"] for r in conv])
+    b = 2 * 19 * 4 + 4  # populations read and written, the mask word
+    return {"workload": f"rev_domains_{len(doms)}", "domains": len(doms), "voxels": nvox,
+            "pore_voxels": npore, "storage": "f32", "collision": "regularized", "tau": 1.0,
+            "steps": steps, "ms_per_step": round(ms, 4),
+            "value": round(npore / (ms * 1e-3) / 1e6, 1), "unit": "MLUPS (pore voxels)",
+            "all_voxel_mlups": round(nvox / (ms * 1e-3) / 1e6, 1),
+            "bytes_per_pore_update": b,
+            "achieved_gbs": round(b * npore / (ms * 1e-3) / 1e9, 1),
+            "frac": round(b * npore / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "to_convergence": {"tol": 1e-6, "seconds": round(t2, 2),
+                               "converged": int(sum(r["converged"] for r in conv)),
+                               "steps_max": int(max(r["steps"] for r in conv)),
+                               "K_min": float(K.min()), "K_median": float(np.median(K)),
+                               "K_max": float(K.max())}}
+
+
 def precision_drift(n, steps, every=100):
     """The rock run in fp64, fp32, fp16 and bf16 storage side by side from the
     same initial state: per-field error against fp64 (max |X - X_f64| /
@@ -474,6 +516,8 @@ def main():
             "kernel_ms": round(fms, 4), "bytes_per_fluid_update": round(bf, 2),
             "achieved_gbs": round(bf * nf_fl / (fms * 1e-3) / 1e9, 1),
             "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if compare:
+        out["rev_library"] = rev_library()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()

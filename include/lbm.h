@@ -240,8 +240,75 @@ int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 int lbm_set_profiling(lbm_handle *h, int32_t on);
 int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset);
 
-/* Description of the last error on h (or of the last failed lbm_create when
- * h is NULL).  Valid until the next call on h. */
+/* ---------------------------------------------------------------------------
+ * Batched single-phase permeability of many small domains.
+ *
+ * The paper's workflow tabulates K0(phi) per pore type from single-phase runs
+ * on fully resolved sub-volumes driven by a body force, with K = phi <u> nu / g
+ * (Appendix: the domain mirrored along the force and periodic in that
+ * direction, the four other sides closed by walls).  lbm_rev_permeability runs
+ * any number of such domains of different sizes together: their voxels are
+ * packed into one array (each domain padded to a multiple of 256 voxels) and
+ * one launch per time step updates all of them.  Each domain is periodic on
+ * its own box (or walled on the sides and mirrored, as flags); the model is the
+ * one-component case of lbm_step without gray voxels (D3Q19, halfway
+ * bounce-back at solid voxels, the regularised or BGK collision, the force
+ * term of Eq. (3) for the body force rho g), started from rest at density 1.
+ *
+ * Every check_every steps the mean velocity along the force is evaluated per
+ * domain (velocity (m + F/2)/rho at the post-streaming level, fp64 sums in a
+ * fixed order); a domain has converged when it changed by at most tol times
+ * its magnitude since the previous check.  The run stops when every domain
+ * has converged or after max_steps; tol = 0 runs exactly max_steps.
+ */
+typedef struct {
+  int32_t nx, ny, nz;   /* box (each >= 1) */
+  int32_t pad_;
+  const uint8_t *cls;   /* host [z][y][x]: LBM_PORE or LBM_SOLID; caller-owned, read once */
+  double *u_out;        /* optional host [z][y][x] of the given box (the first half
+                           when mirrored): final velocity along the force (0 on solid
+                           voxels); NULL skips */
+} lbm_rev_domain;
+
+typedef struct {
+  double tau;           /* relaxation time, > 1/2 */
+  double g;             /* body acceleration along axis, > 0 */
+  int32_t axis;         /* 0 = x, 1 = y, 2 = z */
+  int32_t collision;    /* LBM_COLL_REGULARIZED or LBM_COLL_BGK */
+  int32_t precision;    /* LBM_PREC_F64 or LBM_PREC_F32 (storage and arithmetic) */
+  int32_t side_walls;   /* 1: the four box faces parallel to the force are walls
+                           (bounce-back) instead of periodic */
+  int32_t mirror;       /* 1: each domain is run joined to its mirror image along the
+                           force (twice the length, periodic across both joints) */
+  int32_t pad_;
+  int64_t max_steps;    /* >= 0 */
+  int64_t check_every;  /* >= 1 */
+  double tol;           /* >= 0 */
+  void *stream;         /* hipStream_t; NULL is the default stream */
+} lbm_rev_params;
+
+typedef struct {
+  double K;             /* permeability phi <u> nu / g, nu = (tau - 1/2) / 3 */
+  double phi;           /* pore fraction of the box */
+  double u_mean;        /* mean velocity along the force over the pore voxels */
+  int64_t steps;        /* steps at the check where it converged, or all steps run */
+  int32_t converged;    /* 1 when the tol criterion was met */
+  int32_t pad_;
+} lbm_rev_result;
+
+/* Runs the domains doms[0 .. ndom-1] and writes out[0 .. ndom-1] (caller-owned
+ * host arrays).  Device memory is allocated and freed inside the call, which
+ * returns after the last result is on the host.  Errors: LBM_E_INVAL for an
+ * argument out of range (nothing runs), LBM_E_UNSUPPORTED for another
+ * precision or more than 2^31 / 19 packed voxels, LBM_E_NOMEM, LBM_E_DEVICE,
+ * LBM_E_NONFINITE when a domain's mean velocity is not finite at a check.  The
+ * message is lbm_last_error(NULL). */
+int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
+                         lbm_rev_result *out);
+
+/* Description of the last error on h (or, when h is NULL, of the last failed
+ * call without a handle: lbm_create, lbm_rev_permeability).  Valid until the
+ * next call on h. */
 const char *lbm_last_error(const lbm_handle *h);
 
 /* Frees the device state (through the hook) and the handle.  NULL is a no-op. */

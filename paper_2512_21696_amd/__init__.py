@@ -69,6 +69,25 @@ class lbm_diag(ctypes.Structure):
         ("step", ctypes.c_int64), ("nonfinite", ctypes.c_int32), ("pad_", ctypes.c_int32)]
 
 
+class lbm_rev_domain(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("cls", ctypes.c_void_p), ("u_out", ctypes.c_void_p)]
+
+
+class lbm_rev_params(ctypes.Structure):
+    _fields_ = [("tau", ctypes.c_double), ("g", ctypes.c_double), ("axis", ctypes.c_int32),
+                ("collision", ctypes.c_int32), ("precision", ctypes.c_int32),
+                ("side_walls", ctypes.c_int32), ("mirror", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("max_steps", ctypes.c_int64),
+                ("check_every", ctypes.c_int64), ("tol", ctypes.c_double),
+                ("stream", ctypes.c_void_p)]
+
+
+class lbm_rev_result(ctypes.Structure):
+    _fields_ = [("K", ctypes.c_double), ("phi", ctypes.c_double), ("u_mean", ctypes.c_double),
+                ("steps", ctypes.c_int64), ("converged", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+
+
 class lbm_kernel_times(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_double), ("step_launches", ctypes.c_int64),
                 ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
@@ -78,7 +97,7 @@ class lbm_kernel_times(ctypes.Structure):
 EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_geometry",
            "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
-           "lbm_get_kernel_times", "lbm_last_error", "lbm_destroy"]
+           "lbm_get_kernel_times", "lbm_rev_permeability", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -91,6 +110,10 @@ def load_library(path: str = LIB_PATH):
     if not os.path.exists(path):
         raise ImportError(f"{path} is missing: build it with __graft_entry__.build() or "
                           f"python paper_2512_21696_amd/build.py")
+    try:  # torch first, so that the library binds to the HIP runtime torch loaded
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(path)
     P = ctypes.POINTER
     vp, i32, i64, sz = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t
@@ -110,6 +133,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_state": (ctypes.c_int, [vp, vp, sz]),
         "lbm_set_profiling": (ctypes.c_int, [vp, i32]),
         "lbm_get_kernel_times": (ctypes.c_int, [vp, P(lbm_kernel_times), i32]),
+        "lbm_rev_permeability": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain), i32,
+                                                P(lbm_rev_result)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_destroy": (None, [vp]),
     }
@@ -344,6 +369,47 @@ class Lbm:
 
 def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
     return Lbm(params, use_torch_memory)
+
+
+def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
+                     precision="f32", side_walls=False, mirror=False, max_steps=2000,
+                     check_every=100, tol=1e-6, want_u=False, stream=None):
+    """Single-phase permeability K = phi <u> nu / g of every domain (a list of
+    uint8 class arrays [z][y][x], 0 pore / 1 solid), all run together by
+    lbm_rev_permeability.  Returns one dict per domain (K, phi, u_mean, steps,
+    converged, and with want_u the final velocity field along the force)."""
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                stream = torch.cuda.current_stream().cuda_stream
+        except ImportError:
+            stream = None
+    lib = load_library()
+    arrs = [np.ascontiguousarray(c, dtype=np.uint8) for c in domains]
+    outs = [np.zeros(a.shape) if want_u else None for a in arrs]
+    doms = (lbm_rev_domain * len(arrs))()
+    for k, a in enumerate(arrs):
+        if a.ndim != 3:
+            raise ValueError("each domain is a 3-D class array [z][y][x]")
+        doms[k].nz, doms[k].ny, doms[k].nx = a.shape
+        doms[k].cls = a.ctypes.data
+        doms[k].u_out = outs[k].ctypes.data if want_u else None
+    p = lbm_rev_params(tau=float(tau), g=float(g), axis=int(axis), collision=COLL[collision],
+                       precision=PREC[precision], side_walls=int(bool(side_walls)),
+                       mirror=int(bool(mirror)), max_steps=int(max_steps),
+                       check_every=int(check_every), tol=float(tol), stream=stream)
+    res = (lbm_rev_result * len(arrs))()
+    rc = lib.lbm_rev_permeability(ctypes.byref(p), doms, len(arrs), res)
+    if rc != LBM_OK:
+        raise LbmError(rc, lib.lbm_last_error(None).decode())
+    out = []
+    for k in range(len(arrs)):
+        r = {n: getattr(res[k], n) for n in ("K", "phi", "u_mean", "steps", "converged")}
+        if want_u:
+            r["u"] = outs[k]
+        out.append(r)
+    return out
 
 
 def make_state_blob(lbm: Lbm, f, r, side, step=0, q_last=(0.0, 0.0), q_acc=(0.0, 0.0),

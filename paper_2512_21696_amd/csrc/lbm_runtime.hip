@@ -978,3 +978,6 @@ extern "C" void lbm_destroy(lbm_handle *h) {
   for (void *p : h->allocs) dev_free(h, p);
   delete h;
 }
+
+// Batched single-phase permeability runs (own kernels and entry point).
+#include "lbm_rev.hip"

@@ -328,3 +328,46 @@ def uniform_gray(n=(8, 8, 8), phi=0.3, ncomp=1, tau=1.0, g=(1e-5, 0.0, 0.0), kd=
 
 WORKLOADS = {"droplet_slab": droplet_slab, "multiscale_rock": multiscale_rock,
              "fiber_bundles": fiber_bundles}
+
+
+def sphere_pack(shape: tuple, porosity: float, seed: int, rmin: float = 3.0,
+                rmax: float = 8.0) -> np.ndarray:
+    """Periodic box [z][y][x] of class codes: solid spheres (centre uniform in
+    the box, radius ~ U[rmin, rmax], voxel centres at integer coordinates) are
+    added, overlapping, until the pore fraction falls to `porosity` or below."""
+    nz, ny, nx = shape
+    if 2 * math.ceil(rmax) + 2 > min(shape):
+        raise ValueError("box too small for the sphere radius")
+    rng = np.random.default_rng(seed)
+    cls = np.zeros(shape, np.uint8)
+    target = (1.0 - porosity) * cls.size
+    solid = 0
+    while solid < target:
+        c = rng.uniform(0.0, 1.0, 3) * np.array([nz, ny, nx])
+        r = rng.uniform(rmin, rmax)
+        R = int(math.ceil(r))
+        idx = [np.arange(int(math.floor(ci)) - R, int(math.floor(ci)) + R + 2) for ci in c]
+        dz, dy, dx = np.meshgrid(idx[0] - c[0], idx[1] - c[1], idx[2] - c[2], indexing="ij")
+        ball = dz * dz + dy * dy + dx * dx <= r * r
+        sel = np.ix_(idx[0] % nz, idx[1] % ny, idx[2] % nx)
+        sub = cls[sel]
+        solid += int(np.count_nonzero(ball & (sub == PORE)))
+        sub[ball] = SOLID
+        cls[sel] = sub
+    return cls
+
+
+def rev_domains(count: int = 96, seed: int = 4001, lmin: int = 24, lmax: int = 96,
+                phi_range: tuple = (0.20, 0.45), rmin: float = 3.0, rmax: float = 8.0) -> list:
+    """The batch of the permeability library: `count` cubic sphere packs, edge
+    ~ U{lmin..lmax} and target porosity ~ U[phi_range] (seed), each packed by
+    sphere_pack with its own seed.  Returns a list of dicts (cls, edge,
+    target porosity)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        n = int(rng.integers(lmin, lmax + 1))
+        phi = float(rng.uniform(*phi_range))
+        out.append(dict(cls=sphere_pack((n, n, n), phi, seed * 1000 + k, rmin, rmax), edge=n,
+                        target_porosity=phi))
+    return out
