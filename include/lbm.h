@@ -80,6 +80,18 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
  * Either way F_res^a = -(rho^a / rho) R u and the reported velocity is
  * (m + sum_a F^a / 2) / rho. */
 enum { LBM_RES_SEMI_IMPLICIT = 0, LBM_RES_IMPLICIT = 1 };
+/* Boundaries of the x faces.  PERIODIC: the grid wraps.  PRESSURE: the paper's
+ * pressure inlet and outlet (Sec. III.B-D; it gives no equations): beyond
+ * x = 0 and x = nx - 1 lie reservoirs of prescribed densities rho_in and
+ * rho_out per component.  A reservoir cell is fluid: it enters the
+ * pseudo-potential sum of a boundary voxel with its density, and the
+ * populations it sends into the domain are the equilibrium at its density and
+ * at the mixture velocity of the adjacent boundary voxel's post-collision set
+ * (zero next to a solid voxel).  Gray voxels and, with kappa != 0, the CSF
+ * region must stay two voxels away from both faces (LBM_CSF_GRAY required; a
+ * gray voxel at x in {0, 1, nx-2, nx-1} is rejected by lbm_set_geometry), so
+ * no other stencil reaches a reservoir.  Not with 16-bit storage. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1 };
 
 #define LBM_TABLE_N 1025 /* samples of every constitutive curve on [0, 1] */
 #define LBM_MAX_TYPES 256
@@ -107,12 +119,16 @@ typedef struct lbm_params {
   double eps_n;           /* |grad rho| below which the CSF normal is zero */
   double sigma_s;         /* Gaussian smoothing std of phi for the principal axes */
   int32_t smooth_radius;  /* smoothing stencil radius (<= 8) */
-  int32_t outlet_x;       /* outlet flux plane between x_f and x_f + 1 (0 <= x_f < nx) */
+  int32_t outlet_x;       /* outlet flux plane between x_f and x_f + 1 (0 <= x_f < nx;
+                             x_f <= nx - 2 with LBM_BC_PRESSURE) */
   double eps_g, eps_H;    /* isotropic gate: max|lambda| <= eps_H and |grad| <= eps_g */
   double delta_tie;       /* tie-break: |l2| - |l1| <= delta_tie |l3| uses the gradient */
   int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
   int32_t track_flux;     /* 1: accumulate the outlet flux every step */
   int32_t resistance;     /* LBM_RES_SEMI_IMPLICIT (default) | LBM_RES_IMPLICIT */
+  int32_t bc_x;           /* LBM_BC_PERIODIC (default) | LBM_BC_PRESSURE */
+  double rho_in[2];       /* LBM_BC_PRESSURE: reservoir densities (water, oil) beyond x = 0 */
+  double rho_out[2];      /* LBM_BC_PRESSURE: reservoir densities beyond x = nx - 1 */
   /* device allocator hook (NULL = hipMalloc/hipFree); ctx is passed through */
   void *(*alloc)(size_t bytes, void *ctx);
   void (*free)(void *ptr, void *ctx);

@@ -12,7 +12,11 @@ residual events; momentum conservation of the pseudo-potential force;
 uniform-Darcy steady state (scalar and tensorial); Poiseuille flow with
 halfway bounce-back; Brinkman channel convergence; Laplace's law; the
 flat-interface capillary jump; J-scaling and residual-saturation closed forms;
-tensor reductions; brute-force nested-loop equality on tiny grids.
+tensor reductions; brute-force nested-loop equality on tiny grids; open x
+faces (a reservoir at the rest state is neutral, steady pressure-driven flow
+conserves mass through every plane and is Poiseuille-shaped); the single-phase
+permeability run (uniform acceleration of an open box, the exact discrete
+permeability of a BGK slit).
 
 Parity unpinned: the coupled transient of the two-component dynamics with CSF,
 capillary and residual terms acting together has no closed form; it is bounded

@@ -34,6 +34,16 @@ post-streaming population set at time n.  One step (Eq. (2)) is:
 6. residual      trap / release on a saturation crossing (gray voxels);
 7. outlet flux   per-link count through the plane x_f | x_f + 1;
 8. streaming     pull with halfway bounce-back at solid neighbours, periodic.
+
+Open x faces (bc_x = "pressure"; the pressure inlet and outlet of the paper's
+Sec. III.B-D protocols, whose equations it does not give): beyond x = 0 and
+x = nx - 1 lie reservoirs of prescribed densities rho_in, rho_out per
+component.  A reservoir cell is fluid; it enters the pseudo-potential sum of a
+boundary voxel with its density, and the populations it sends into the domain
+are the equilibrium at its density and at the mixture velocity of the adjacent
+boundary voxel's post-collision set (0 next to a solid voxel).  Gray voxels
+and the CSF region must keep two voxels away from both faces, so the other
+stencils never reach a reservoir.
 """
 from __future__ import annotations
 
@@ -68,6 +78,7 @@ class Oracle:
         self.Q_last = np.zeros(2)
         self.Q_acc = np.zeros(2)
         self.f = None
+        self.open_x = getattr(p, "bc_x", "periodic") == "pressure"
 
     # ------------------------------------------------------------------ setup
     def set_geometry(self, cls, phi, ptype, tables):
@@ -97,6 +108,22 @@ class Oracle:
         # solid flags of x + c_i and of x - c_i
         self.nb_solid = np.stack([_sh(self.solid, C[i]) for i in range(Q)])
         self.src_solid = np.stack([_sh(self.solid, C[i], -1) for i in range(Q)])
+        if self.open_x:
+            # x + c_i (nb) or x - c_i (src) beyond an x face: a reservoir cell,
+            # which is fluid
+            x = np.arange(self.nx)[None, None, :]
+            hi, lo = x == self.nx - 1, x == 0
+            self.cross_nb = np.stack([np.broadcast_to(hi if C[i, 0] > 0 else (lo if C[i, 0] < 0
+                                      else np.zeros_like(lo)), self.shape) for i in range(Q)])
+            self.cross_src = np.stack([np.broadcast_to(lo if C[i, 0] > 0 else (hi if C[i, 0] < 0
+                                       else np.zeros_like(lo)), self.shape) for i in range(Q)])
+            self.nb_solid = self.nb_solid & ~self.cross_nb
+            self.src_solid = self.src_solid & ~self.cross_src
+            near = np.zeros(self.nx, bool)
+            near[[0, min(1, self.nx - 1), max(self.nx - 2, 0), self.nx - 1]] = True
+            if np.any(gray[:, :, near]) or (p.kappa != 0.0 and p.csf_region != "gray"):
+                raise ValueError("with open x faces, gray voxels and the CSF region keep two "
+                                 "voxels away from both faces")
 
     def init_fluid(self, rho_w, rho_o=None):
         rho = [np.asarray(rho_w, np.float64).reshape(self.shape)]
@@ -219,6 +246,9 @@ class Oracle:
                 wall = np.maximum(rho[b] + p.wall_dpsi[b], 0.0)
                 for i in range(1, Q):
                     psi = np.where(self.nb_solid[i], wall, _sh(rho[b], C[i]))
+                    if self.open_x and C[i, 0] != 0:
+                        ghost = p.rho_out[b] if C[i, 0] > 0 else p.rho_in[b]
+                        psi = np.where(self.cross_nb[i], ghost, psi)
                     for d in range(3):
                         if C[i, d]:
                             acc[d] += W[i] * C[i, d] * psi
@@ -315,6 +345,8 @@ class Oracle:
         if self.ncomp == 2:
             self._residual(post, ev)
         self._outlet_flux(post)
+        if self.open_x:
+            self._reservoirs(post)
         new = np.empty_like(post)
         for a in range(self.ncomp):
             for i in range(Q):
@@ -351,6 +383,29 @@ class Oracle:
         new_rw = np.where(to_o, rw + d_w, new_rw)
         self.r[0], self.r[1] = new_rw, new_ro
         self.side = np.where(to_w, True, np.where(to_o, False, self.side))
+
+    def _reservoirs(self, post):
+        """Open x faces: the populations the reservoir cells send into the
+        domain, written where the pull reads them (the slots across the
+        periodic wrap, whose own populations leave the domain)."""
+        p = self.p
+        ends = []
+        for x in (0, self.nx - 1):  # boundary planes: mixture velocity of the post set
+            rho = post[:, :, :, :, x].sum(axis=(0, 1))
+            mom = np.stack([np.einsum("i,aizy->zy", C[:, d].astype(float), post[:, :, :, :, x])
+                            for d in range(3)])
+            fl = self.fluid[:, :, x]
+            ends.append(np.where(fl, mom / np.where(fl, rho, 1.0), 0.0))
+        u_in, u_out = ends
+        plane = (self.nz, self.ny)
+        for a in range(self.ncomp):
+            feq_in = self.equilibrium(np.full(plane, p.rho_in[a]), u_in)
+            feq_out = self.equilibrium(np.full(plane, p.rho_out[a]), u_out)
+            for i in range(Q):
+                if C[i, 0] > 0:  # read by the voxels at x = 0 across the wrap
+                    post[a, i][:, :, self.nx - 1] = feq_in[i]
+                elif C[i, 0] < 0:  # read by the voxels at x = nx - 1
+                    post[a, i][:, :, 0] = feq_out[i]
 
     def _outlet_flux(self, post):
         xf = int(self.p.outlet_x)

@@ -48,11 +48,11 @@ __device__ inline int wrapc(int v, int n) {
 // Wrapped coordinates of x-2..x+2 (and y, z) for stencils up to radius 2.
 struct Nbr {
   int X[5], Y[5], Z[5];
-  int nx, nxy;
+  int nx, nxy, x;
   __device__ Nbr(int v, int nx_, int ny, int nz) {
     nx = nx_;
     nxy = nx_ * ny;
-    int x = v % nx_;
+    x = v % nx_;
     int t = v / nx_;
     int y = t % ny;
     int z = t / ny;
@@ -109,16 +109,67 @@ __device__ inline void block_sum(double (&val)[NV], double *out_row, bool maxlas
 }
 
 // ------------------------------------------------------------------ setup
+// With open x faces (pressure boundaries) a neighbour beyond a face is a
+// reservoir cell, which is fluid.
 __global__ void k_mask(const uint8_t *__restrict__ cls, uint32_t *__restrict__ mask, int nx,
-                       int ny, int nz, long long N) {
+                       int ny, int nz, long long N, int open_x) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   Nbr nb((int)v, nx, ny, nz);
+  const int x = (int)(v % nx);
   uint32_t m = (uint32_t)cls[v] << CLASS_SHIFT;
 #pragma unroll
-  for (int i = 1; i < Q; ++i)
-    if (cls[nb.at(cx(i), cy(i), cz(i))] == SOLID_CODE) m |= 1u << i;
+  for (int i = 1; i < Q; ++i) {
+    const bool beyond = open_x && (x + cx(i) < 0 || x + cx(i) >= nx);
+    if (!beyond && cls[nb.at(cx(i), cy(i), cz(i))] == SOLID_CODE) m |= 1u << i;
+  }
   mask[v] = m;
+}
+
+// Open x faces: the populations the reservoir cells send into the domain,
+// written into the slots that the boundary voxels pull across the periodic
+// wrap (slots whose own populations leave the domain): the equilibrium at the
+// reservoir density and at the mixture velocity of the adjacent boundary
+// voxel's post-collision set.  One thread per (y, z) row.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_reservoirs(const ModelConsts mc, T *__restrict__ post,
+                                                    const uint32_t *__restrict__ mask) {
+  const long long N = mc.N;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mc.ny * mc.nz) return;
+  const long long v0 = (long long)k * mc.nx, v1 = v0 + mc.nx - 1;
+  T u[2][3];
+  const long long vb[2] = {v0, v1};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const bool fluid = ((mask[vb[e]] >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    T rho = 0, m0 = 0, m1 = 0, m2 = 0;
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const T f = post[(size_t)(a * Q + i) * N + vb[e]];
+        rho += f;
+        m0 += (T)cx(i) * f;
+        m1 += (T)cy(i) * f;
+        m2 += (T)cz(i) * f;
+      }
+    const T ir = fluid ? (T)1 / rho : (T)0;
+    u[e][0] = m0 * ir;
+    u[e][1] = m1 * ir;
+    u[e][2] = m2 * ir;
+  }
+  for (int a = 0; a < NC; ++a) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (cx(i) == 0) continue;
+      const int e = cx(i) > 0 ? 0 : 1;  // inlet reservoir sends c_x = +1, outlet c_x = -1
+      const T r = (T)(e == 0 ? mc.rho_in[a] : mc.rho_out[a]);
+      const T cu = (T)cx(i) * u[e][0] + (T)cy(i) * u[e][1] + (T)cz(i) * u[e][2];
+      const T usq = u[e][0] * u[e][0] + u[e][1] * u[e][1] + u[e][2] * u[e][2];
+      const T feq = (T)wq(i) * r * ((T)1 + (T)3 * cu + (T)4.5 * cu * cu - (T)1.5 * usq);
+      post[(size_t)(a * Q + i) * N + (e == 0 ? v1 : v0)] = feq;
+    }
+  }
 }
 
 // Per gray voxel (fp64): K0 = lerp(K0_tab, phi), s_J (Leverett-J, Eq. (5)),
@@ -334,7 +385,7 @@ __global__ void k_axes(const double *__restrict__ ps, const uint32_t *__restrict
 template <typename T>
 __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
                           const uint32_t *__restrict__ mask, int nx, int ny, int nz, long long N,
-                          int ncomp) {
+                          int ncomp, int open_x) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   uint32_t mk = mask[v];
@@ -344,9 +395,15 @@ __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       T val = 0;
+      const int rd = nb.at(cx(i), cy(i), cz(i));  // the voxel that pulls slot i
       if (!solid) {
         if ((mk >> i) & 1u) val = C[(size_t)(a * Q + opp(i)) * N + v];
-        else val = C[(size_t)(a * Q + i) * N + nb.at(cx(i), cy(i), cz(i))];
+        else val = C[(size_t)(a * Q + i) * N + rd];
+      } else if (open_x && cx(i) != 0 && (nb.x + cx(i) < 0 || nb.x + cx(i) >= nx) &&
+                 ((mask[rd] >> CLASS_SHIFT) & 3u) != SOLID_CODE) {
+        // open x faces: a fluid boundary voxel pulls this slot of a solid
+        // voxel across the wrap (its reservoir population)
+        val = C[(size_t)(a * Q + i) * N + rd];
       }
       B[(size_t)(a * Q + i) * N + v] = val;
     }
@@ -560,7 +617,12 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
       T acc0 = 0, acc1 = 0, acc2 = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const T psi = ((mk >> i) & 1u) ? pw : rb[nb.at(cx(i), cy(i), cz(i))];
+        T psi = ((mk >> i) & 1u) ? pw : rb[nb.at(cx(i), cy(i), cz(i))];
+        if (mc.open_x && cx(i) != 0) {  // a reservoir cell beyond an x face
+          const int xn = nb.x + cx(i);
+          if (xn < 0) psi = (T)mc.rho_in[b];
+          else if (xn >= mc.nx) psi = (T)mc.rho_out[b];
+        }
         if (cx(i)) acc0 += (T)(wq(i) * cx(i)) * psi;
         if (cy(i)) acc1 += (T)(wq(i) * cy(i)) * psi;
         if (cz(i)) acc2 += (T)(wq(i) * cz(i)) * psi;

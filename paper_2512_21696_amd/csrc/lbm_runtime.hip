@@ -208,6 +208,11 @@ ModelConsts make_consts(const lbm_params &p) {
   mc.csf_all = p.csf_region == LBM_CSF_ALL;
   mc.tensor = p.tensor;
   mc.res_implicit = p.resistance == LBM_RES_IMPLICIT;
+  mc.open_x = p.bc_x == LBM_BC_PRESSURE;
+  for (int a = 0; a < 2; ++a) {
+    mc.rho_in[a] = p.rho_in[a];
+    mc.rho_out[a] = p.rho_out[a];
+  }
   for (int a = 0; a < 2; ++a) {
     double tau = (a < p.ncomp) ? p.tau[a] : 1.0;
     mc.tau[a] = tau;
@@ -306,7 +311,7 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
   if (rc == LBM_OK) {
     Timed tm(h, K_OTHER);
     hipLaunchKernelGGL(k_mask, dim3(blocks(N)), dim3(256), 0, st, cls_d, s.mask, h->p.nx, h->p.ny,
-                       h->p.nz, N);
+                       h->p.nz, N, h->mc.open_x);
     hipLaunchKernelGGL(k_setup_gray<T>, dim3(blocks(N)), dim3(256), 0, st, phi_d, s.ptype, s.mask,
                        dtabs, dmeta, h->p.c_max, h->p.c_min, N, s.K0, s.sJ, s.thw, s.tho, K0d,
                        s.phiT);
@@ -523,6 +528,15 @@ int step_t(lbm_handle *h, int64_t n) {
     ensure_density<T>(h);
     launch_step<T, MODE_STEP, T>(h, FieldsOut{});
     h->cur = 1 - h->cur;
+    if (h->mc.open_x) {
+      Timed tm(h, K_OTHER);
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL((k_reservoirs<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask);
+      else
+        hipLaunchKernelGGL((k_reservoirs<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask);
+    }
     // 16-bit runs: the new offsets are relative to the densities of the level
     // just left, which the density pass wrote into rho2
     if (h->sk != SK_NATIVE && h->p.ncomp == 2) std::swap(s.rhoE, s.rho2);
@@ -599,7 +613,7 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
       hipLaunchKernelGGL(k_equilibrium_rest<T>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d, ro_d,
                          C, s.mask, N, h->p.ncomp);
       hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur],
-                         s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp, h->mc.open_x);
     } else if constexpr (std::is_same<T, float>::value) {
       float *C = s.f[0];
       hipLaunchKernelGGL(k_equilibrium_rest<float>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d,
@@ -773,11 +787,12 @@ int set_state_t(lbm_handle *h, const void *buf) {
     Timed tm(h, K_OTHER);
     if (h->sk == SK_NATIVE)
       hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, (const T *)C,
-                         s.f[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
-    else
+                         s.f[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp,
+                         h->mc.open_x);
+    else  // (open x faces need native storage)
       hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(blocks(N)), dim3(256), 0, h->st,
                          (const uint16_t *)C, s.fc[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N,
-                         h->p.ncomp);
+                         h->p.ncomp, 0);
     rc = hip_check(h, hipGetLastError(), "scatter");
   }
   if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "set_state");
@@ -866,6 +881,15 @@ extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double 
   int rc = validate_tables(tabs, ntab, msg, sizeof(msg));
   if (rc == LBM_OK) rc = validate_geometry(h->N, cls, phi, pore_type, ntab, msg, sizeof(msg));
   if (rc != LBM_OK) return set_err(h, rc, msg);
+  if (h->p.bc_x == LBM_BC_PRESSURE) {
+    // reservoirs: no gray voxel within two voxels of either x face
+    const int nx = h->p.nx;
+    for (long long r = 0; r < (long long)h->p.ny * h->p.nz; ++r)
+      for (int x : {0, 1, nx - 2, nx - 1})
+        if (x >= 0 && x < nx && cls[r * nx + x] == LBM_GRAY)
+          return set_err(h, LBM_E_INVAL,
+                         "pressure boundaries: a gray voxel lies within two voxels of an x face");
+  }
   h->has_geom = false;
   h->has_fluid = false;
   rc = h->p.precision == LBM_PREC_F64 ? set_geometry_t<double>(h, cls, phi, pore_type, tabs, ntab)

@@ -56,9 +56,9 @@ __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 // them as scalar operands instead of converting inside the loop.
 template <typename T>
 struct KC {
-  int nx, ny, nz, csf_all, tensor, collision, res_implicit;
+  int nx, ny, nz, csf_all, tensor, collision, res_implicit, open_x;
   long long N;
-  T g[2][3], omega[2], nu[2], wall_dpsi[2];
+  T g[2][3], omega[2], nu[2], wall_dpsi[2], rho_in[2], rho_out[2];
   T G, kappa, csf_fac, s_min, inv_span, kr_min, hyst, m_minor, eps_n2;
 };
 
@@ -68,7 +68,10 @@ KC<T> make_kc(const ModelConsts &m) {
   k.nx = m.nx; k.ny = m.ny; k.nz = m.nz; k.N = m.N;
   k.csf_all = m.csf_all; k.tensor = m.tensor; k.collision = m.collision;
   k.res_implicit = m.res_implicit;
+  k.open_x = m.open_x;
   for (int a = 0; a < 2; ++a) {
+    k.rho_in[a] = (T)m.rho_in[a];
+    k.rho_out[a] = (T)m.rho_out[a];
     for (int d = 0; d < 3; ++d) k.g[a][d] = (T)m.g[a][d];
     k.omega[a] = (T)m.omega[a];
     k.nu[a] = (T)m.nu[a];
@@ -360,6 +363,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   __shared__ T sshat[STENCIL ? RS : 1][STENCIL ? NH : 1];  // mobile saturation S_hat
   __shared__ T2 snrm[3][STENCIL ? NM : 1];                  // (n^w_d, n^o_d) of one plane
   __shared__ int sxw[HX], syw[HY];
+  __shared__ int sxg[HX];  // open x faces: 1 beyond x = 0, 2 beyond x = nx-1 (reservoir cells)
   // 16-bit storage, two components: reference densities (the writers'
   // densities of the previous level) of planes z-1 .. z+1 on the tile plus a
   // radius-1 halo, in a ring of three planes
@@ -393,9 +397,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   // registers and written to LDS after the barrier-free voxel work.
   constexpr int CPT = (NH + NT - 1) / NT;
   uint32_t cell_g[CPT];  // in-plane voxel index of each owned cell
+  uint32_t cell_res = 0;  // 2 bits per owned cell: reservoir cell (open x faces)
   T2 pre_r[CPT];
   if (STENCIL) {
-    if (tid < HX) sxw[tid] = wrapn(x0 + tid - R, nx);
+    if (tid < HX) {
+      const int xu = x0 + tid - R;
+      sxw[tid] = wrapn(xu, nx);
+      sxg[tid] = mc.open_x ? (xu < 0 ? 1 : (xu >= nx ? 2 : 0)) : 0;
+    }
     if (tid < HY) syw[tid] = wrapn(y0 + tid - R, ny);
     __syncthreads();
 #pragma unroll
@@ -404,13 +413,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const int kk = k < NH ? k : 0;
       const int lx = kk % HX, ly = kk / HX;
       cell_g[q] = (uint32_t)sxw[lx] + (uint32_t)nx * (uint32_t)syw[ly];
+      cell_res |= (uint32_t)sxg[lx] << (2 * q);
     }
   }
   auto fetch_rho = [&](int zz) {
     const uint32_t zoff = (uint32_t)wrapn(zz, nz) * nxy;
 #pragma unroll
-    for (int q = 0; q < CPT; ++q)
-      if (tid + q * NT < NH) pre_r[q] = rho2[zoff + cell_g[q]];
+    for (int q = 0; q < CPT; ++q) {
+      if (tid + q * NT < NH) {
+        const uint32_t rc = (cell_res >> (2 * q)) & 3u;
+        if (rc == 0u) pre_r[q] = rho2[zoff + cell_g[q]];
+        else pre_r[q] = rc == 1u ? T2{mc.rho_in[0], mc.rho_in[1]} : T2{mc.rho_out[0], mc.rho_out[1]};
+      }
+    }
   };
   auto store_rho = [&](int zz) {
     const int sl = rslot(zz);

@@ -51,6 +51,9 @@ extern "C" void lbm_params_default(lbm_params *p) {
   p->delta_tie = 0.05;
   p->diag_every = 0;
   p->track_flux = 1;
+  p->bc_x = LBM_BC_PERIODIC;
+  p->rho_in[0] = p->rho_out[0] = 1.0;
+  p->rho_in[1] = p->rho_out[1] = 0.0;
 }
 
 extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
@@ -104,6 +107,20 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
   if (p->diag_every < 0) return fail(msg, len, LBM_E_INVAL, "diag_every must be >= 0");
   if (p->resistance != LBM_RES_SEMI_IMPLICIT && p->resistance != LBM_RES_IMPLICIT)
     return fail(msg, len, LBM_E_INVAL, "unknown resistance scheme");
+  if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_PRESSURE)
+    return fail(msg, len, LBM_E_INVAL, "unknown x boundary");
+  if (p->bc_x == LBM_BC_PRESSURE) {
+    if (p->precision == LBM_PREC_F16 || p->precision == LBM_PREC_BF16)
+      return fail(msg, len, LBM_E_UNSUPPORTED, "pressure boundaries need F64 or F32 storage");
+    if (p->outlet_x > p->nx - 2)
+      return fail(msg, len, LBM_E_INVAL, "with pressure boundaries outlet_x must be <= nx - 2");
+    if (p->kappa != 0.0 && p->csf_region != LBM_CSF_GRAY)
+      return fail(msg, len, LBM_E_INVAL, "pressure boundaries need the CSF region in gray voxels");
+    for (int a = 0; a < 2; ++a)
+      if (!(p->rho_in[a] >= 0) || !(p->rho_out[a] >= 0) || !std::isfinite(p->rho_in[a]) ||
+          !std::isfinite(p->rho_out[a]))
+        return fail(msg, len, LBM_E_INVAL, "reservoir densities must be finite and >= 0");
+  }
   if ((p->alloc == nullptr) != (p->free == nullptr))
     return fail(msg, len, LBM_E_INVAL, "alloc and free hooks must be given together");
   return LBM_OK;
