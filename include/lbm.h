@@ -310,6 +310,8 @@ typedef struct {
   int64_t steps;        /* steps at the check where it converged, or all steps run */
   int32_t converged;    /* 1 when the tol criterion was met */
   int32_t pad_;
+  double step_ms;       /* mean device time of one batched step of all domains (HIP
+                           events around the step launches; the same in every result) */
 } lbm_rev_result;
 
 /* Runs the domains doms[0 .. ndom-1] and writes out[0 .. ndom-1] (caller-owned

@@ -87,7 +87,8 @@ class lbm_rev_params(ctypes.Structure):
 
 class lbm_rev_result(ctypes.Structure):
     _fields_ = [("K", ctypes.c_double), ("phi", ctypes.c_double), ("u_mean", ctypes.c_double),
-                ("steps", ctypes.c_int64), ("converged", ctypes.c_int32), ("pad_", ctypes.c_int32)]
+                ("steps", ctypes.c_int64), ("converged", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("step_ms", ctypes.c_double)]
 
 
 class lbm_kernel_times(ctypes.Structure):
@@ -411,7 +412,8 @@ def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
         raise LbmError(rc, lib.lbm_last_error(None).decode())
     out = []
     for k in range(len(arrs)):
-        r = {n: getattr(res[k], n) for n in ("K", "phi", "u_mean", "steps", "converged")}
+        r = {n: getattr(res[k], n) for n in ("K", "phi", "u_mean", "steps", "converged",
+                                             "step_ms")}
         if want_u:
             r["u"] = outs[k]
         out.append(r)

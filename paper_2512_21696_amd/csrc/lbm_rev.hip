@@ -217,10 +217,18 @@ __global__ void k_rev_reduce(const Dom *__restrict__ doms, int ndom,
   usum[d] = s;
 }
 
-struct DevBuf {  // device allocations of one call, freed on every exit path
+struct DevBuf {  // device allocations and events of one call, freed on every exit path
   std::vector<void *> ptrs;
+  std::vector<hipEvent_t> events;
   ~DevBuf() {
     for (void *p : ptrs) (void)hipFree(p);
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+  hipEvent_t event() {
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    events.push_back(e);
+    return e;
   }
   template <typename U>
   U *get(size_t n) {
@@ -300,6 +308,9 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   double *usum = mem.get<double>(ndom);
   if (!ddom || !dblk || !dcls || !dmask || !fa || !fb || (want_u && !uf) || !partial || !usum)
     return fail(LBM_E_NOMEM, "device allocation failed");
+  hipEvent_t ev0 = mem.event(), ev1 = mem.event();
+  if (!ev0 || !ev1) return fail(LBM_E_DEVICE, "hipEventCreate failed");
+  double step_ms_total = 0.0;
   int rc = check(hipMemcpyAsync(ddom, hd.data(), ndom * sizeof(Dom), hipMemcpyHostToDevice, st),
                  "copy domains");
   if (rc == LBM_OK)
@@ -350,6 +361,8 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     have_prev = true;
     if (all || done >= p->max_steps) break;
     const int64_t k = std::min<int64_t>(p->check_every, p->max_steps - done);
+    rc = check(hipEventRecord(ev0, st), "event");
+    if (rc != LBM_OK) return rc;
     for (int64_t s = 0; s < k; ++s) {
       if (reg)
         hipLaunchKernelGGL((k_rev_step<T, true>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, fb,
@@ -360,7 +373,12 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
       std::swap(fa, fb);
     }
     rc = check(hipGetLastError(), "step launch");
+    if (rc == LBM_OK) rc = check(hipEventRecord(ev1, st), "event");
+    if (rc == LBM_OK) rc = check(hipEventSynchronize(ev1), "step");
+    float ms = 0.f;
+    if (rc == LBM_OK) rc = check(hipEventElapsedTime(&ms, ev0, ev1), "event time");
     if (rc != LBM_OK) return rc;
+    step_ms_total += ms;
     done += k;
   }
   if (want_u) {
@@ -389,6 +407,7 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     out[d].steps = conv_step[d] >= 0 ? conv_step[d] : done;
     out[d].converged = conv_step[d] >= 0;
     out[d].pad_ = 0;
+    out[d].step_ms = done > 0 ? step_ms_total / (double)done : 0.0;
   }
   return LBM_OK;
 }
