@@ -115,6 +115,11 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
   // nothing to do; solid lanes of mixed waves store zeros so that every store
   // covers whole lines
   if (__all(solid)) return;
+  // solid lanes store zeros only when their 128-byte line holds a fluid voxel
+  constexpr int LPL = 128 / (int)sizeof(T);
+  const uint64_t live = __ballot(!solid);
+  const int lane = threadIdx.x & 63;
+  const bool dead_line = solid && ((live >> (lane / LPL * LPL)) & ((1ull << LPL) - 1ull)) == 0ull;
   const uint32_t Vt = (uint32_t)Vtot;
   T f[Q];  // the pulled set
   if (!solid) {
@@ -171,7 +176,7 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
     T val = (T)wq(i) * (A + B0 * c0 + B1 * c1 + B2 * c2 + Cxx * c0 * c0 + Cyy * c1 * c1 +
                         Czz * c2 * c2 + (T)2 * (Cxy * c0 * c1 + Cxz * c0 * c2 + Cyz * c1 * c2));
     if (!REG) val += keep * f[i];
-    fout[(size_t)i * Vtot + V] = solid ? (T)0 : val;
+    if (!dead_line) fout[(size_t)i * Vtot + V] = solid ? (T)0 : val;
   }
 }
 
