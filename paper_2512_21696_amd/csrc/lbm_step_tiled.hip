@@ -676,11 +676,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     T rho[NC], mom[NC][3], P[NC][6];  // P: xx, yy, zz, xy, xz, yz
     T f[REG ? 1 : NC][REG ? 1 : Q];   // BGK: f_i (native) or f_i / w_i (16-bit)
     if (!skip) {
-      T Ro[NC];  // this voxel's reference densities
-      const int e0 = (z + 3) % 3;
-#pragma unroll
-      for (int a = 0; a < NC; ++a)
-        Ro[a] = REFS ? reinterpret_cast<const T *>(&sref[e0][cn])[a] : (T)1;
+      // reference planes z-1, z, z+1 in the ring, and this voxel's references
+      const int es[3] = {(z + 2) % 3, z % 3, (z + 1) % 3};
+      T2 Ro2 = T2{(T)1, (T)1};
+      if (REFS) Ro2 = sref[es[1]][cn];
+      const T Ro[2] = {Ro2.x, Ro2.y};
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         T g0 = pull_decode<T, SK>(pf[a][0]);
@@ -696,20 +696,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         const int j = i + 1;
         // pull of i from x - c_i, of j from x + c_i; bounce-back when solid
         const bool bbi = (mk >> j) & 1u, bbj = (mk >> i) & 1u;
+        // 16-bit: the references of both sources, both components in one read
+        T2 Ri2 = Ro2, Rj2 = Ro2;
+        if (REFS) {
+          if (!bbi) Ri2 = sref[es[1 - cz(i)]][cn - moff(i)];
+          if (!bbj) Rj2 = sref[es[1 + cz(i)]][cn + moff(i)];
+        }
 #pragma unroll
         for (int a = 0; a < NC; ++a) {
           T fi = pull_decode<T, SK>(pf[a][i]);
           T fj = pull_decode<T, SK>(pf[a][j]);
           if (S16) {
-            T Ri = Ro[a], Rj = Ro[a];
-            if (REFS) {
-              if (!bbi)
-                Ri = reinterpret_cast<const T *>(&sref[(z - cz(i) + 3) % 3][cn - moff(i)])[a];
-              if (!bbj)
-                Rj = reinterpret_cast<const T *>(&sref[(z + cz(i) + 3) % 3][cn + moff(i)])[a];
-            }
-            fi += Ri;
-            fj += Rj;
+            fi += a == 0 ? Ri2.x : Ri2.y;
+            fj += a == 0 ? Rj2.x : Rj2.y;
           }
           if (!REG) {
             f[REG ? 0 : a][i] = fi;
