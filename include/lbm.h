@@ -250,6 +250,13 @@ int lbm_state_size(const lbm_handle *h, size_t *bytes);
 int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 
+/* Pressure boundaries (bc_x = LBM_BC_PRESSURE): replaces the reservoir densities
+ * (water, oil) beyond x = 0 and x = nx - 1 from the next step on, as the
+ * quasi-static capillary-pressure protocols of the paper's Appendix step the
+ * reservoir pressures.  Enqueues nothing.  LBM_E_STATE on a handle with
+ * periodic x faces; LBM_E_INVAL for a negative or non-finite density. */
+int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_out[2]);
+
 /* Profiling: when on, each launch is bracketed by HIP events on the stream;
  * lbm_get_kernel_times synchronises and returns the accumulated device time
  * since the last reset.  Off by default. */

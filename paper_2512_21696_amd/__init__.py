@@ -100,7 +100,8 @@ class lbm_kernel_times(ctypes.Structure):
 EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_geometry",
            "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
-           "lbm_get_kernel_times", "lbm_rev_permeability", "lbm_last_error", "lbm_destroy"]
+           "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
+           "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -136,6 +137,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_state": (ctypes.c_int, [vp, vp, sz]),
         "lbm_set_profiling": (ctypes.c_int, [vp, i32]),
         "lbm_get_kernel_times": (ctypes.c_int, [vp, P(lbm_kernel_times), i32]),
+        "lbm_set_reservoirs": (ctypes.c_int, [vp, dp, dp]),
         "lbm_rev_permeability": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain), i32,
                                                 P(lbm_rev_result)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
@@ -270,6 +272,7 @@ class Lbm:
         phi = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1)
         pt = np.ascontiguousarray(pore_type, dtype=np.uint8).reshape(-1)
         assert cls.size == self.N and phi.size == self.N and pt.size == self.N
+        self._fluid = (cls != 1).reshape(self.shape)
         tabs = to_c_tables(tables)
         self._check(self.lib.lbm_set_geometry(
             self.h, cls.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
@@ -365,6 +368,11 @@ class Lbm:
         out["side"] = raw[off + 2 * self.N * es:].reshape(self.shape)
         return out
 
+    def set_reservoirs(self, rho_in, rho_out):
+        a = (ctypes.c_double * 2)(*[float(v) for v in rho_in])
+        b = (ctypes.c_double * 2)(*[float(v) for v in rho_out])
+        self._check(self.lib.lbm_set_reservoirs(self.h, a, b))
+
     def set_profiling(self, on: bool):
         self._check(self.lib.lbm_set_profiling(self.h, int(bool(on))))
 
@@ -376,6 +384,12 @@ class Lbm:
 
 def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
     return Lbm(params, use_torch_memory)
+
+
+def reservoir_pressure(rho, G):
+    """Bulk pressure of a reservoir (water, oil densities) in the
+    two-component pseudo-potential model: cs^2 (rho_w + rho_o) + cs^2 G rho_w rho_o."""
+    return (rho[0] + rho[1] + G * rho[0] * rho[1]) / 3.0
 
 
 def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",

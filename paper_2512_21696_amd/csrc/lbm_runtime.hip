@@ -961,6 +961,21 @@ extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) 
                                         : set_state_t<float>(h, host_buf);
 }
 
+extern "C" int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_out[2]) {
+  if (!h || !rho_in || !rho_out) return LBM_E_INVAL;
+  if (h->p.bc_x != LBM_BC_PRESSURE)
+    return set_err(h, LBM_E_STATE, "set_reservoirs: the x faces are periodic");
+  for (int a = 0; a < 2; ++a)
+    if (!(rho_in[a] >= 0) || !(rho_out[a] >= 0) || !std::isfinite(rho_in[a]) ||
+        !std::isfinite(rho_out[a]))
+      return set_err(h, LBM_E_INVAL, "reservoir densities must be finite and >= 0");
+  for (int a = 0; a < 2; ++a) {
+    h->p.rho_in[a] = h->mc.rho_in[a] = rho_in[a];
+    h->p.rho_out[a] = h->mc.rho_out[a] = rho_out[a];
+  }
+  return LBM_OK;
+}
+
 extern "C" int lbm_set_profiling(lbm_handle *h, int32_t on) {
   if (!h) return LBM_E_INVAL;
   if (!on) fold_events(h);

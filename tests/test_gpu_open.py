@@ -95,3 +95,34 @@ def test_open_faces_reject_gray_next_to_a_face_and_16bit():
     with pytest.raises(L.LbmError) as e:
         L.lbm_create(p)
     assert e.value.code == L.LBM_E_UNSUPPORTED
+
+
+def test_reservoir_step_matches_oracle():
+    """lbm_set_reservoirs between steps (a pressure step of a quasi-static
+    protocol) against the oracle with the same change."""
+    import copy
+    wl = displacement()
+    announce("open x faces: reservoir densities stepped after 30 steps, fp64")
+    lb = gpu_run(wl, 30, "f64")
+    m = wl["params"].m_minor
+    new_in, new_out = (1.05, m), (m, 0.98)
+    lb.set_reservoirs(new_in, new_out)
+    lb.step(30)
+    got = lb.get_fields()
+    p = copy.deepcopy(displacement()["params"])
+    wl64 = displacement()
+    wl64["params"] = p
+    o = oracle_run(wl64, 30)
+    p.rho_in, p.rho_out = new_in, new_out
+    o.step(30)
+    fe = field_errors(got, o.fields(), ("rho_w", "rho_o", "ux", "uy", "uz", "S"))
+    print("reservoir step field errors", {k: f"{v:.2e}" for k, v in fe.items()})
+    assert max(fe.values()) < 1e-12
+    lb.destroy()
+    import paper_2512_21696_amd as L
+    per = W.droplet_slab()
+    lb = L.lbm_create(per["params"])
+    with pytest.raises(L.LbmError) as e:
+        lb.set_reservoirs(new_in, new_out)
+    assert e.value.code == L.LBM_E_STATE
+    lb.destroy()
