@@ -1,0 +1,158 @@
+"""Reference gradients of the outlet-flux history with respect to the gray
+porosity, for the one-component model (pore, gray and solid voxels, scalar
+K0(phi), regularised or BGK collision, semi-implicit or implicit resistance,
+body force).  TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark
+baseline).
+
+The step is the one of model.Oracle with one component, transcribed into plain
+PyTorch CPU fp64 operations so that torch's reverse-mode autograd gives the
+exact gradient of this discrete forward map; tests pin the transcription to
+model.Oracle (same fluxes and populations) and the gradient to central finite
+differences of model.Oracle.  It serves as the oracle of the GPU library's
+hand-written discrete adjoint.
+
+Loss convention: the caller supplies dL/dQ(n) for the outlet fluxes
+Q(1..N) of N steps (Q(n) measured on the post-collision set of step n, as
+model.Oracle does); the result is dL/dphi on every voxel (zero off gray).
+"""
+from __future__ import annotations
+
+import numpy as np
+import torch
+
+from .lattice import C, W, OPP, Q, CS2
+
+PORE, SOLID, GRAY = 0, 1, 2
+
+
+def _sh(a, c, sign=1):
+    """a evaluated at x + sign*c (periodic); a is [..., z, y, x]."""
+    cx, cy, cz = (int(v) * sign for v in c)
+    return torch.roll(a, (-cz, -cy, -cx), dims=(-3, -2, -1))
+
+
+def _lerp(tab, v):
+    """Linear interpolation of a 1025-sample table at v (differentiable in v)."""
+    tab = torch.as_tensor(np.asarray(tab, np.float64))
+    n = tab.shape[0] - 1
+    t = v * n
+    k = torch.clamp(torch.floor(t.detach()), 0, n - 1).long()
+    return tab[k] + (t - k) * (tab[k + 1] - tab[k])
+
+
+def _equilibrium(rho, u):
+    usq = u[0] ** 2 + u[1] ** 2 + u[2] ** 2
+    out = []
+    for i in range(Q):
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        out.append(W[i] * rho * (1.0 + cu / CS2 + cu * cu / (2 * CS2 * CS2) - usq / (2 * CS2)))
+    return torch.stack(out)
+
+
+def _force_term(u, F):
+    uF = u[0] * F[0] + u[1] * F[1] + u[2] * F[2]
+    out = []
+    for i in range(Q):
+        cF = C[i, 0] * F[0] + C[i, 1] * F[1] + C[i, 2] * F[2]
+        cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
+        out.append(W[i] * (cF / CS2 + (2.0 * cu * cF - 2.0 * CS2 * uF) / (2 * CS2 * CS2)))
+    return torch.stack(out)
+
+
+def _hermite(fneq):
+    j = [sum(C[i, a] * fneq[i] for i in range(Q) if C[i, a]) for a in range(3)]
+    Pi = [[sum(C[i, a] * C[i, b] * fneq[i] for i in range(Q) if C[i, a] and C[i, b])
+           for b in range(3)] for a in range(3)]
+    trace = Pi[0][0] + Pi[1][1] + Pi[2][2]
+    out = []
+    for i in range(Q):
+        cj = C[i, 0] * j[0] + C[i, 1] * j[1] + C[i, 2] * j[2]
+        pcc = sum(Pi[a][b] * float(C[i, a] * C[i, b]) for a in range(3) for b in range(3)
+                  if C[i, a] and C[i, b])
+        out.append(W[i] * (cj / CS2 + (pcc - CS2 * trace) / (2 * CS2 * CS2)))
+    return torch.stack(out)
+
+
+class OneComponent:
+    """The one-component step in torch; `phi` is a leaf tensor when gradients
+    are wanted."""
+
+    def __init__(self, params, cls, ptype, tables):
+        p = params
+        self.p = p
+        self.cls = np.asarray(cls, np.uint8)
+        self.shape = self.cls.shape
+        self.solid = torch.as_tensor(self.cls == SOLID)
+        self.fluid = ~self.solid
+        self.gray = torch.as_tensor(self.cls == GRAY)
+        self.ptype = np.asarray(ptype, np.uint8)
+        self.tables = tables
+        self.tau = float(p.tau[0])
+        self.g = [float(v) for v in p.g[0]]
+        self.h = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
+        self.src_solid = [_sh(self.solid, C[i], -1) for i in range(Q)]
+        fl = self.fluid.numpy()
+        xf = int(p.outlet_x)
+        x1 = (xf + 1) % self.shape[2]
+        # outlet-flux links through x_f | x_f + 1 with both ends fluid: weight
+        # +1 on post_i(x_f) for c_x = +1, -1 on post_i(x_f + 1) for c_x = -1
+        self.flux_w = torch.zeros((Q,) + self.shape, dtype=torch.float64)
+        for i in range(Q):
+            cx, cy, cz = (int(v) for v in C[i])
+            if cx == 0:
+                continue
+            src, dst = (xf, x1) if cx == 1 else (x1, xf)
+            ok = fl[:, :, src] & np.roll(fl[:, :, dst], (-cz, -cy), axis=(0, 1))
+            self.flux_w[i][:, :, src] = torch.as_tensor(cx * ok.astype(np.float64))
+
+    def K0(self, phi):
+        K0 = torch.zeros(self.shape, dtype=torch.float64)
+        for t, tab in enumerate(self.tables):
+            sel = torch.as_tensor((self.cls == GRAY) & (self.ptype == t))
+            if bool(sel.any()):
+                K0 = torch.where(sel, _lerp(tab["K0"], phi), K0)
+        return K0
+
+    def step(self, f, K0):
+        """One step from the post-streaming set f; returns (new f, Q)."""
+        p = self.p
+        fl = self.fluid
+        rho = f.sum(0)
+        mom = [sum(C[i, d] * f[i] for i in range(Q) if C[i, d]) for d in range(3)]
+        safe = torch.where(fl, rho, torch.ones_like(rho))
+        F_ex = [rho * self.g[d] for d in range(3)]
+        nu = CS2 * (self.tau - 0.5)
+        cR = torch.where(self.gray, rho * nu, torch.zeros_like(rho))
+        Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
+                         torch.zeros_like(rho))
+        u = [(mom[d] + self.h * F_ex[d]) / (safe + self.h * Rs) for d in range(3)]
+        F = [F_ex[d] - Rs * u[d] for d in range(3)]
+        up = [torch.where(fl, mom[d] / safe, torch.zeros_like(rho)) for d in range(3)]
+        feq = _equilibrium(rho, up)
+        fneq = f - feq
+        f1 = _hermite(fneq) if p.collision == "regularized" else fneq
+        ua = [up[d] + F[d] / (2.0 * safe) for d in range(3)]
+        post = feq + (1.0 - 1.0 / self.tau) * f1 + _force_term(ua, F)
+        post = torch.where(fl, post, torch.zeros_like(post))
+        Qn = (self.flux_w * post).sum()
+        new = torch.stack([torch.where(self.src_solid[i], post[OPP[i]], _sh(post[i], C[i], -1))
+                           for i in range(Q)])
+        return torch.where(fl, new, torch.zeros_like(new)), Qn
+
+
+def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
+    """Runs `steps` steps from the post-streaming set f0 [Q, z, y, x] and
+    returns (Q history [steps], dL/dphi [z, y, x]) for L = sum_n dL_dQ[n] Q(n)."""
+    model = OneComponent(params, cls, ptype, tables)
+    ph = torch.tensor(np.asarray(phi, np.float64), requires_grad=True)
+    K0 = model.K0(ph)
+    f = torch.as_tensor(np.asarray(f0, np.float64))
+    hist = []
+    for _ in range(int(steps)):
+        f, Qn = model.step(f, K0)
+        hist.append(Qn)
+    hist = torch.stack(hist)
+    L = (hist * torch.as_tensor(np.asarray(dL_dQ, np.float64))).sum()
+    L.backward()
+    g = ph.grad.detach().numpy()
+    return hist.detach().numpy(), np.where(np.asarray(cls) == GRAY, g, 0.0), f.detach().numpy()

@@ -1,0 +1,81 @@
+"""Pins of the reference gradient (oracle/adjoint.py): its torch forward
+reproduces model.Oracle's one-component run (fluxes and populations), and its
+autograd gradient of L = sum_n a_n Q(n) with respect to the gray porosity
+matches central finite differences of model.Oracle itself."""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import Oracle
+from oracle import adjoint as A
+
+
+def case(collision="regularized", resistance="semi_implicit", seed=5):
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 5, 6, 8
+    r = rng.random((nz, ny, nx))
+    cls = np.where(r < 0.15, 1, np.where(r < 0.6, 2, 0)).astype(np.uint8)
+    phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
+    K0 = W.kozeny_carman_table(2.0)
+    tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, collision=collision,
+                 resistance=resistance, g=((1e-4, 2e-5, 0.0), (0.0, 0.0, 0.0))).filled()
+    return p, cls, phi, np.zeros(cls.shape, np.uint8), tabs
+
+
+def oracle_history(p, cls, phi, pt, tabs, steps):
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(np.ones(cls.shape))
+    f0 = o.f[0].copy()
+    qs = []
+    for _ in range(steps):
+        o.step(1)
+        qs.append(o.Q_last[0])
+    return f0, np.array(qs), o.f[0]
+
+
+@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
+                                                  ("bgk", "implicit")])
+def test_torch_forward_equals_oracle(collision, resistance):
+    p, cls, phi, pt, tabs = case(collision, resistance)
+    f0, qs, fN = oracle_history(p, cls, phi, pt, tabs, 15)
+    hist, _, f_t = A.flux_gradient(p, cls, phi, pt, tabs, f0, 15, np.ones(15))
+    # Q is a signed sum of O(100) populations of size ~0.1: rounding order alone
+    # leaves ~1e-15 absolute
+    assert np.abs(hist - qs).max() < 1e-14
+    assert np.abs(f_t - fN).max() < 1e-14
+
+
+@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
+                                                  ("bgk", "implicit")])
+def test_gradient_matches_oracle_finite_differences(collision, resistance):
+    p, cls, phi, pt, tabs = case(collision, resistance)
+    steps = 12
+    a = np.linspace(1.0, 2.0, steps)            # L = sum_n a_n Q(n)
+    f0, _, _ = oracle_history(p, cls, phi, pt, tabs, 1)
+    _, grad, _ = A.flux_gradient(p, cls, phi, pt, tabs, f0, steps, a)
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(9)
+    # L carries ~1e-15 of rounding noise against a sensitivity of ~1e-6, so
+    # eps = 1e-4 (a tenth of a table interval); knots are kept out of reach
+    eps = 1e-4
+    checked = 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue  # a table knot within reach of the perturbation
+        Ls = []
+        for s in (1, -1):
+            ph = phi.copy()
+            ph[v] += s * eps
+            _, qs, _ = oracle_history(p, cls, ph, pt, tabs, steps)
+            Ls.append(float((a * qs).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        assert abs(grad[v] - fd) < 2e-5 * abs(fd) + 1e-12, (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
+    assert np.all(grad[cls != 2] == 0)
