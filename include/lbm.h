@@ -181,6 +181,7 @@ typedef struct lbm_kernel_times {
   double step_ms;   int64_t step_launches;   /* fused collide-stream kernel */
   double aux_ms;    int64_t aux_launches;    /* density / normal passes */
   double other_ms;  int64_t other_launches;  /* flux, diagnostics */
+  double adjoint_ms; int64_t adjoint_launches; /* reverse-step kernels of lbm_adjoint_flux */
 } lbm_kernel_times;
 
 typedef struct lbm_handle lbm_handle;
@@ -330,6 +331,48 @@ typedef struct {
  * message is lbm_last_error(NULL). */
 int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
                          lbm_rev_result *out);
+
+/* ---------------------------------------------------------------------------
+ * Discrete adjoint of the outlet flux with respect to the gray porosity.
+ *
+ * The gray-region resistance of Eq. (1) makes the flow depend on phi through
+ * K0(phi), the per-pore-type table; calibrating phi (or the tables) against an
+ * observed flux needs dL/dphi.  For the one-component model (ncomp = 1, scalar
+ * K0: tensor = 0, periodic x faces, native fp64 or fp32 storage) and a loss
+ * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
+ * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
+ * post-collision populations of step n crossing outlet_x | outlet_x + 1),
+ * lbm_adjoint_flux runs those steps and returns dL/dK0 and dL/dphi on every
+ * voxel: the exact gradient of the discrete forward map (the step in exact
+ * arithmetic, evaluated at the stored states).  Any differentiable loss of the
+ * flux history is handled by passing its gradient at the forward history (run
+ * the forward first, e.g. with lbm_step and lbm_get_diagnostics, or take
+ * Q_out of a first call with zero dL_dQ).
+ *
+ * Method: a forward sweep of nsteps ordinary steps with the stored set copied
+ * to a checkpoint every checkpoint_every steps, then a reverse sweep segment by
+ * segment: each segment's stored sets are recomputed from its checkpoint, and
+ * one reverse-step kernel per step applies the transposed streaming (a gather
+ * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
+ * weights and the transposed collision Jacobian, and accumulates dL/dK0 in
+ * fp64.  dL/dphi multiplies it by the K0(phi) table's slope on the lookup's
+ * cell (the right-hand slope on a table knot).
+ *
+ * Arguments: nsteps >= 1; dL_dQ a host array of nsteps finite doubles;
+ * checkpoint_every >= 1, or 0 for ceil(sqrt(nsteps)); Q_out (nsteps), dL_dK0 and
+ * dL_dphi (N each, [z][y][x], zero off gray voxels) host arrays owned by the
+ * caller, each may be NULL.  Device memory, allocated through the hook and
+ * freed before returning: (ceil(nsteps / K) + K - 1) population sets of the
+ * storage type (19 N values each, K = checkpoint_every) plus 2 x 19 N + 2 N
+ * doubles.  The handle ends nsteps steps on, exactly as after lbm_step(nsteps)
+ * (step counter and flux accumulators included).  Synchronises the stream.
+ * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
+ * fluid state), LBM_E_UNSUPPORTED (two components, tensorial resistivity,
+ * pressure x faces or 16-bit storage), LBM_E_NOMEM, LBM_E_DEVICE,
+ * LBM_E_NONFINITE (from a forward step's diagnostics). */
+int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
+                     int64_t checkpoint_every, double *Q_out, double *dL_dK0,
+                     double *dL_dphi);
 
 /* Description of the last error on h (or, when h is NULL, of the last failed
  * call without a handle: lbm_create, lbm_rev_permeability).  Valid until the

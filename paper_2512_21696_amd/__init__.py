@@ -94,14 +94,15 @@ class lbm_rev_result(ctypes.Structure):
 class lbm_kernel_times(ctypes.Structure):
     _fields_ = [("step_ms", ctypes.c_double), ("step_launches", ctypes.c_int64),
                 ("aux_ms", ctypes.c_double), ("aux_launches", ctypes.c_int64),
-                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64)]
+                ("other_ms", ctypes.c_double), ("other_launches", ctypes.c_int64),
+                ("adjoint_ms", ctypes.c_double), ("adjoint_launches", ctypes.c_int64)]
 
 
 EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_geometry",
            "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
            "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
-           "lbm_last_error", "lbm_destroy"]
+           "lbm_adjoint_flux", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -140,6 +141,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_reservoirs": (ctypes.c_int, [vp, dp, dp]),
         "lbm_rev_permeability": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain), i32,
                                                 P(lbm_rev_result)]),
+        "lbm_adjoint_flux": (ctypes.c_int, [vp, i64, dp, i64, dp, dp, dp]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_destroy": (None, [vp]),
     }
@@ -372,6 +374,25 @@ class Lbm:
         a = (ctypes.c_double * 2)(*[float(v) for v in rho_in])
         b = (ctypes.c_double * 2)(*[float(v) for v in rho_out])
         self._check(self.lib.lbm_set_reservoirs(self.h, a, b))
+
+    def adjoint_flux(self, nsteps, dL_dQ, checkpoint_every=0):
+        """Runs nsteps steps from the current state and returns, for the loss
+        L = sum_n dL_dQ[n] Q(n) on their outlet fluxes, a dict with the flux
+        history "Q" [nsteps] and the gradients "dL_dK0" and "dL_dphi" as host
+        fp64 arrays [z, y, x].  The handle ends nsteps steps on, as after
+        step(nsteps)."""
+        n = int(nsteps)
+        a = np.ascontiguousarray(dL_dQ, dtype=np.float64).reshape(-1)
+        if a.size != n:
+            raise ValueError("dL_dQ needs one value per step")
+        q = np.zeros(n, np.float64)
+        gk = np.zeros(self.N, np.float64)
+        gp = np.zeros(self.N, np.float64)
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._check(self.lib.lbm_adjoint_flux(self.h, n, a.ctypes.data_as(dp), int(checkpoint_every),
+                                              q.ctypes.data_as(dp), gk.ctypes.data_as(dp),
+                                              gp.ctypes.data_as(dp)))
+        return {"Q": q, "dL_dK0": gk.reshape(self.shape), "dL_dphi": gp.reshape(self.shape)}
 
     def set_profiling(self, on: bool):
         self._check(self.lib.lbm_set_profiling(self.h, int(bool(on))))

@@ -1,0 +1,48 @@
+"""torch.autograd binding of the library's discrete adjoint: the outlet-flux
+history of a one-component run as a differentiable function of the gray
+porosity field.  Argument marshalling only; the forward steps and the reverse
+sweep run in the HIP library."""
+import numpy as np
+import torch
+
+from . import lbm_create
+
+
+class FluxHistory(torch.autograd.Function):
+    """Q = FluxHistory.apply(phi, run) with phi a float64 tensor [z, y, x]
+    (read on gray voxels) and run a dict holding the one-component "params",
+    "cls", "ptype", "tables", the initial density "rho" [z, y, x], "steps"
+    and optionally "checkpoint_every".  Returns the outlet flux of every step,
+    a float64 CPU tensor [steps].  The backward pass restarts from the same
+    initial state and calls the library's adjoint with the incoming dL/dQ."""
+
+    @staticmethod
+    def forward(ctx, phi, run):
+        ph = phi.detach().to("cpu", torch.float64).numpy()
+        lb = lbm_create(run["params"])
+        try:
+            lb.set_geometry(run["cls"], ph, run["ptype"], run["tables"])
+            lb.init_fluid(run["rho"])
+            start = lb.get_state()
+            q = np.zeros(int(run["steps"]), np.float64)
+            for n in range(q.size):
+                lb.step(1)
+                q[n] = lb.get_diagnostics()["q_w"]
+        except Exception:
+            lb.destroy()
+            raise
+        ctx.lb, ctx.start, ctx.run = lb, start, run
+        ctx.phi_device, ctx.phi_dtype = phi.device, phi.dtype
+        return torch.from_numpy(q)
+
+    @staticmethod
+    def backward(ctx, grad_q):
+        lb = ctx.lb
+        try:
+            lb.set_state(ctx.start)
+            out = lb.adjoint_flux(int(ctx.run["steps"]), grad_q.detach().cpu().numpy(),
+                                  ctx.run.get("checkpoint_every", 0))
+        finally:
+            lb.destroy()
+        g = torch.from_numpy(np.ascontiguousarray(out["dL_dphi"]))
+        return g.to(ctx.phi_device, ctx.phi_dtype), None

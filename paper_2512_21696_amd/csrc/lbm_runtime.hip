@@ -58,11 +58,13 @@ struct lbm_handle {
   std::vector<void *> geom_allocs;  // freed when a new geometry comes in
   std::vector<void *> allocs;
   std::vector<uint8_t> geom_cls;   // host copy of the classes (density validation)
+  double *geom_phi = nullptr;      // device copies of the porosity [v] and of the fp64
+  double *geom_tabs = nullptr;     // pore tables [type][K0, Pc, Krw, Kro][TABLE_N]
   // profiling
   bool prof = false;
   std::vector<EventPair> ev_pool, ev_live;
-  double t_ms[3] = {0, 0, 0};
-  int64_t t_n[3] = {0, 0, 0};
+  double t_ms[4] = {0, 0, 0, 0};
+  int64_t t_n[4] = {0, 0, 0, 0};
 };
 
 namespace {
@@ -144,7 +146,7 @@ struct Timed {
     h->ev_live.push_back(e);
   }
 };
-enum { K_STEP = 0, K_AUX = 1, K_OTHER = 2 };
+enum { K_STEP = 0, K_AUX = 1, K_OTHER = 2, K_ADJ = 3 };
 
 template <typename T>
 DevState<T> &state(lbm_handle *h);
@@ -246,10 +248,12 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
   std::vector<void *> tmp;
   bool ok = true;
   uint8_t *cls_d = alloc_into<uint8_t>(h, tmp, N, &ok);
-  double *phi_d = alloc_into<double>(h, tmp, N, &ok);
+  double *phi_d = alloc_into<double>(h, h->geom_allocs, N, &ok);
   double *K0d = alloc_into<double>(h, tmp, N, &ok);
   const int nt = ntab > 0 ? ntab : 1;
-  double *dtabs = alloc_into<double>(h, tmp, (size_t)nt * 4 * TABLE_N, &ok);
+  double *dtabs = alloc_into<double>(h, h->geom_allocs, (size_t)nt * 4 * TABLE_N, &ok);
+  h->geom_phi = phi_d;
+  h->geom_tabs = dtabs;
   double *dmeta = alloc_into<double>(h, tmp, (size_t)nt * 8, &ok);
   s.tab = alloc_into<T>(h, h->geom_allocs, (size_t)nt * 3 * TABLE_N, &ok);
   double *sm1 = nullptr, *sm2 = nullptr, *wts = nullptr;
@@ -437,8 +441,10 @@ void ensure_normals(lbm_handle *h) {
   }
 }
 
+// The fused step from the stored copy into the other one, or (native storage)
+// from fin into fout when given.
 template <typename T, int NC, bool REG>
-void launch_tiled(lbm_handle *h) {
+void launch_tiled(lbm_handle *h, const T *fin_ = nullptr, T *fout_ = nullptr) {
   DevState<T> &s = state<T>(h);
   const int tx = (h->p.nx + zm::TX - 1) / zm::TX;
   const int ty = (h->p.ny + zm::TY - 1) / zm::TY;
@@ -446,9 +452,10 @@ void launch_tiled(lbm_handle *h) {
   const int nt = tx * ty * tz;
   const int grid = (nt + 7) / 8 * 8;
   if (h->sk == SK_NATIVE) {
+    const T *fin = fin_ ? fin_ : s.f[h->cur];
+    T *fout = fout_ ? fout_ : s.f[1 - h->cur];
     hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE>), dim3(grid), dim3(zm::NT), 0, h->st,
-                       make_kc<T>(h->mc), (const void *)s.f[h->cur], (void *)s.f[1 - h->cur], s,
-                       tx, ty, tz, nt);
+                       make_kc<T>(h->mc), (const void *)fin, (void *)fout, s, tx, ty, tz, nt);
   } else if constexpr (std::is_same<T, float>::value) {
     const void *fin = s.fc[h->cur];
     void *fout = s.fc[1 - h->cur];
@@ -992,8 +999,10 @@ extern "C" int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_
   out->aux_launches = h->t_n[K_AUX];
   out->other_ms = h->t_ms[K_OTHER];
   out->other_launches = h->t_n[K_OTHER];
+  out->adjoint_ms = h->t_ms[K_ADJ];
+  out->adjoint_launches = h->t_n[K_ADJ];
   if (reset) {
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < 4; ++k) {
       h->t_ms[k] = 0;
       h->t_n[k] = 0;
     }
@@ -1020,3 +1029,6 @@ extern "C" void lbm_destroy(lbm_handle *h) {
 
 // Batched single-phase permeability runs (own kernels and entry point).
 #include "lbm_rev.hip"
+
+// Discrete adjoint of the one-component step (own kernels and entry point).
+#include "lbm_adjoint.hip"

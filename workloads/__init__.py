@@ -376,3 +376,35 @@ def rev_domains(count: int = 96, seed: int = 4001, lmin: int = 24, lmax: int = 9
         out.append(dict(cls=sphere_pack((n, n, n), phi, seed * 1000 + k, rmin, rmax), edge=n,
                         target_porosity=phi))
     return out
+
+
+def adjoint_rock(n: int = 96, seed: int = 5001, precision: str = "f32", steps: int = 800,
+                 window: int = 200, tau: float = 1.0, g: float = 1e-5,
+                 collision: str = "regularized", resistance: str = "implicit") -> dict:
+    """The porosity-gradient workload: the multiscale-rock geometry generator
+    (Gaussian random field, correlation length 6, quantiles 35 % solid, 20 %
+    gray, 45 % pore; gray phi ~ U[0.05, 0.4], pore type ~ U{0..3}) on an n^3
+    box, run with one component (the fluid the library's adjoint covers) from
+    rest at density 1, body acceleration g along +x, tau = 1, implicit
+    resistance, outlet at x = n / 2.  Loss: L = sum over steps n >= window of
+    (Q(n) - Q*(n))^2 with a fixed seeded target: `target(q_base)` returns
+    Q*(n) = 1.1 mean(q_base over the window) (1 + 0.02 xi_n), xi ~ N(0, 1)
+    (seed + 1), from a base run's history; `loss_grad(q, target)` returns
+    (L, dL/dQ)."""
+    base = multiscale_rock(n=n, seed=seed, precision=precision, buffer=0)
+    p = Params(nx=n, ny=n, nz=n, ncomp=1, precision=precision, tau=(tau, tau), G=0.0,
+               collision=collision, resistance=resistance, g=((g, 0.0, 0.0), (0.0, 0.0, 0.0)),
+               kappa=0.0, outlet_x=n // 2).filled()
+    xi = np.random.default_rng(seed + 1).standard_normal(steps)
+    inside = np.arange(steps) >= window
+
+    def target(q_base):
+        return 1.1 * float(np.mean(np.asarray(q_base)[inside])) * (1.0 + 0.02 * xi)
+
+    def loss_grad(q, tgt):
+        d = np.where(inside, np.asarray(q, np.float64) - tgt, 0.0)
+        return float(np.sum(d * d)), 2.0 * d
+
+    return dict(name=f"adjoint_rock_{n}", params=p, cls=base["cls"], phi=base["phi"],
+                ptype=base["ptype"], tables=base["tables"], rho_w=np.ones((n, n, n)),
+                rho_o=None, steps=steps, target=target, loss_grad=loss_grad)
