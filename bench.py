@@ -233,6 +233,76 @@ def rev_library(steps=400):
                                "K_max": float(K.max())}}
 
 
+def adjoint_gradient(n=96, steps=800, every=50, precision="f32"):
+    """The porosity gradient of a flux-misfit loss (workloads.adjoint_rock: the
+    rock generator at n^3, one component, `steps` steps, squared misfit over
+    steps 200..steps): an untimed forward run for the flux history and dL/dQ,
+    then lbm_adjoint_flux with checkpoints every `every` steps, timed on the
+    host around the call (forward sweep, recomputation, reverse sweep, copies)
+    and per kernel with the library's HIP events.  Beside it the plain forward
+    run of the same steps."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2512_21696_amd as L
+    wl = W.adjoint_rock(n=n, steps=steps, precision=precision)
+    cls = wl["cls"]
+    n_fluid = int(np.sum(cls != 1))
+    gray_frac = float(np.sum(cls == 2)) / n_fluid
+    lb = L.lbm_create(wl["params"])
+    lb.set_geometry(cls, wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"])
+    start = lb.get_state()
+    q = np.zeros(steps)
+    for k in range(steps):
+        lb.step(1)
+        q[k] = lb.get_diagnostics()["q_w"]
+    loss, dLdQ = wl["loss_grad"](q, wl["target"](q))
+    # forward alone
+    lb.set_state(start)
+    torch.cuda.synchronize()
+    lb.set_profiling(True)
+    lb.get_kernel_times(reset=True)
+    t0 = time.perf_counter()
+    lb.step(steps)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    kf = lb.get_kernel_times(reset=True)
+    # gradient
+    lb.set_state(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = lb.adjoint_flux(steps, dLdQ, checkpoint_every=every)
+    t_adj = time.perf_counter() - t0
+    ka = lb.get_kernel_times(reset=True)
+    lb.set_profiling(False)
+    lb.destroy()
+    es = 8 if precision == "f64" else 4
+    # per fluid voxel: the recomputed set pulled, the adjoint set gathered and
+    # written (storage type), the mask word; gray voxels read K0 and update
+    # their fp64 dL/dK0
+    b = 19 * es + 2 * 19 * es + 4 + gray_frac * (es + 16)
+    adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
+    achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
+    g = out["dL_dphi"]
+    return {"workload": wl["name"], "storage": precision, "components": 1, "steps": steps,
+            "checkpoint_every": every, "fluid_voxels": n_fluid,
+            "gray_voxels": int(np.sum(cls == 2)), "loss": loss,
+            "flux_history_equal": bool(np.array_equal(out["Q"], q)),
+            "forward_seconds": round(t_fwd, 4), "gradient_seconds": round(t_adj, 4),
+            "gradient_over_forward": round(t_adj / t_fwd, 2),
+            "step_kernel_ms": round(kf["step_ms"] / max(kf["step_launches"], 1), 4),
+            "reverse_kernel_ms": round(adj_ms, 4),
+            "reverse_kernel_launches": int(ka["adjoint_launches"]),
+            "recompute_and_forward_step_launches": int(ka["step_launches"]),
+            "roofline": {"kernel": "k_adj_step", "bound": "hbm",
+                         "bytes_per_fluid_update": round(b, 2),
+                         "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(achieved / HBM_PEAK_GBS, 4)},
+            "dL_dphi_max_abs": float(np.abs(g).max()),
+            "dL_dphi_nonzero": int(np.count_nonzero(g))}
+
+
 def precision_drift(n, steps, every=100):
     """The rock run in fp64, fp32, fp16 and bf16 storage side by side from the
     same initial state: per-field error against fp64 (max |X - X_f64| /
@@ -327,6 +397,8 @@ def main():
     ap.add_argument("--record-traffic", metavar="PREFIX",
                     help="only turn the rocprofv3 counter passes PREFIX_{fetch,write,cfetch,"
                          "cwrite} into the traffic record of --precision's workload (no GPU)")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="only run the porosity-gradient section and print its JSON, then exit")
     ap.add_argument("--drift", type=int, default=0, metavar="STEPS",
                     help="only run the storage precisions side by side for STEPS steps and "
                          "print their field errors against fp64 at checkpoints, then exit")
@@ -343,6 +415,11 @@ def main():
         return
     if args.drift:
         precision_drift(args.n, args.drift)
+        return
+    if args.adjoint:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"adjoint_gradient": adjoint_gradient()}), flush=True)
         return
 
     import numpy as np
@@ -516,6 +593,7 @@ def main():
             "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if compare:
         out["rev_library"] = rev_library()
+        out["adjoint_gradient"] = adjoint_gradient()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()

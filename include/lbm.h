@@ -354,17 +354,18 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * segment: each segment's stored sets are recomputed from its checkpoint, and
  * one reverse-step kernel per step applies the transposed streaming (a gather
  * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
- * weights and the transposed collision Jacobian, and accumulates dL/dK0 in
- * fp64.  dL/dphi multiplies it by the K0(phi) table's slope on the lookup's
+ * weights and the transposed collision Jacobian, and accumulates dL/dK0.  dL/dphi multiplies it by the K0(phi) table's slope on the lookup's
  * cell (the right-hand slope on a table knot).
  *
  * Arguments: nsteps >= 1; dL_dQ a host array of nsteps finite doubles;
  * checkpoint_every >= 1, or 0 for ceil(sqrt(nsteps)); Q_out (nsteps), dL_dK0 and
  * dL_dphi (N each, [z][y][x], zero off gray voxels) host arrays owned by the
  * caller, each may be NULL.  Device memory, allocated through the hook and
- * freed before returning: (ceil(nsteps / K) + K - 1) population sets of the
- * storage type (19 N values each, K = checkpoint_every) plus 2 x 19 N + 2 N
- * doubles.  The handle ends nsteps steps on, exactly as after lbm_step(nsteps)
+ * freed before returning: ceil(nsteps / K) + K + 1 population-sized sets of
+ * the storage type (19 N values each, K = checkpoint_every: checkpoints, the
+ * recomputed levels of one segment, two adjoint sets) plus 2 N doubles.  The
+ * adjoint populations are kept in the storage type, the reverse arithmetic and
+ * the dL/dK0 accumulation in fp64.  The handle ends nsteps steps on, exactly as after lbm_step(nsteps)
  * (step counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
  * fluid state), LBM_E_UNSUPPORTED (two components, tensorial resistivity,

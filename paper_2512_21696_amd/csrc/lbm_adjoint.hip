@@ -37,11 +37,13 @@
 namespace lbm {
 namespace adj {
 
+// The adjoint populations are stored in the state's type (fp64 or fp32); the
+// arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.
 template <typename T, bool REG>
 __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
                                                   const T *__restrict__ post,
-                                                  const double *__restrict__ lin,
-                                                  double *__restrict__ lout,
+                                                  const T *__restrict__ lin,
+                                                  T *__restrict__ lout,
                                                   const uint32_t *__restrict__ mask,
                                                   const T *__restrict__ K0,
                                                   double *__restrict__ gK0, const double a) {
@@ -67,7 +69,8 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
                                    ? post[(size_t)j * N + v]
                                    : post[(size_t)i * N + nb.at(-cx(i), -cy(i), -cz(i))]);
     const bool wall = (mk >> i) & 1u;
-    double l = wall ? lin[(size_t)j * N + v] : lin[(size_t)i * N + nb.at(cx(i), cy(i), cz(i))];
+    double l = (double)(wall ? lin[(size_t)j * N + v]
+                             : lin[(size_t)i * N + nb.at(cx(i), cy(i), cz(i))]);
     if (!wall && at0 && cx(i) == 1) l += a;
     if (!wall && at1 && cx(i) == -1) l -= a;
     lp[i] = l;
@@ -178,7 +181,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
     } else {
       l += keep * lp[k];
     }
-    lout[(size_t)k * N + v] = l;
+    lout[(size_t)k * N + v] = (T)l;
   }
   if (gray) gK0[v] += -(r / k0) * (rho * Rsb);
 }
@@ -211,7 +214,7 @@ __global__ __launch_bounds__(256) void k_adj_phi(const double *__restrict__ gK0,
 namespace {
 
 template <typename T>
-void launch_adj_step(lbm_handle *h, const T *post, const double *lin, double *lout, double *gk,
+void launch_adj_step(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk,
                      double a) {
   DevState<T> &s = state<T>(h);
   Timed tm(h, K_ADJ);
@@ -249,7 +252,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   bool ok = true;
   T *ck = alloc_into<T>(h, tmp, (size_t)nseg * QN, &ok);
   T *ring = K > 1 ? alloc_into<T>(h, tmp, (size_t)(K - 1) * QN, &ok) : nullptr;
-  double *lam = alloc_into<double>(h, tmp, 2 * QN, &ok);
+  T *lam = alloc_into<T>(h, tmp, 2 * QN, &ok);
   double *gk = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *gp = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *qh = alloc_into<double>(h, tmp, (size_t)2 * n, &ok);
@@ -279,7 +282,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   }
   // reverse sweep; the loss does not depend on the set after the last step
   if (rc == LBM_OK)
-    rc = hip_check(h, hipMemsetAsync(lam, 0, 2 * QN * sizeof(double), h->st), "clear adjoint");
+    rc = hip_check(h, hipMemsetAsync(lam, 0, 2 * QN * sizeof(T), h->st), "clear adjoint");
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemsetAsync(gk, 0, (size_t)N * sizeof(double), h->st), "clear gradient");
   int cl = 0;

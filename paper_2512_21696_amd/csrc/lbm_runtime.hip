@@ -448,23 +448,27 @@ void launch_tiled(lbm_handle *h, const T *fin_ = nullptr, T *fout_ = nullptr) {
   DevState<T> &s = state<T>(h);
   const int tx = (h->p.nx + zm::TX - 1) / zm::TX;
   const int ty = (h->p.ny + zm::TY - 1) / zm::TY;
-  const int tz = (h->p.nz + zm::ZC - 1) / zm::ZC;
+  // z chunks of ZC planes, halved while the grid has fewer than 1024 tiles (4
+  // blocks per CU), down to 4 planes
+  int zc = zm::ZC;
+  while (zc > 4 && (long long)tx * ty * ((h->p.nz + zc - 1) / zc) < 1024) zc /= 2;
+  const int tz = (h->p.nz + zc - 1) / zc;
   const int nt = tx * ty * tz;
   const int grid = (nt + 7) / 8 * 8;
   if (h->sk == SK_NATIVE) {
     const T *fin = fin_ ? fin_ : s.f[h->cur];
     T *fout = fout_ ? fout_ : s.f[1 - h->cur];
     hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE>), dim3(grid), dim3(zm::NT), 0, h->st,
-                       make_kc<T>(h->mc), (const void *)fin, (void *)fout, s, tx, ty, tz, nt);
+                       make_kc<T>(h->mc), (const void *)fin, (void *)fout, s, tx, ty, zc, nt);
   } else if constexpr (std::is_same<T, float>::value) {
     const void *fin = s.fc[h->cur];
     void *fout = s.fc[1 - h->cur];
     if (h->sk == SK_F16)
       hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16>), dim3(grid), dim3(zm::NT), 0, h->st,
-                         make_kc<float>(h->mc), fin, fout, s, tx, ty, tz, nt);
+                         make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
     else
       hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16>), dim3(grid), dim3(zm::NT), 0,
-                         h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, tz, nt);
+                         h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
   }
 }
 

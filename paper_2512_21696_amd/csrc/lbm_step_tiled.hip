@@ -47,7 +47,7 @@ constexpr int NH = HX * HY;  // density plane cells
 constexpr int MX = TX + 2, MY = TY + 2;
 constexpr int NM = MX * MY;  // normal plane cells
 constexpr int RS = 5;        // density planes z-2 .. z+2
-constexpr int ZC = 32;       // planes per block
+constexpr int ZC = 32;       // planes per block (fewer on grids too small to fill the chip)
 __host__ __device__ constexpr int hoff(int i) { return cx(i) + HX * cy(i); }
 __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 }  // namespace zm
@@ -354,7 +354,7 @@ template <typename T, int NC, bool REG, int SK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
                                                  void *__restrict__ fout, const DevState<T> s,
                                                  const int tiles_x, const int tiles_y,
-                                                 const int chunks_z, const int ntiles) {
+                                                 const int zc, const int ntiles) {
   using namespace zm;
   constexpr bool STENCIL = NC == 2;
   using T4 = vec4<T>;
@@ -385,8 +385,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const uint32_t N32 = (uint32_t)N;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const int x0 = bx * TX, y0 = by * TY;
-  const int zs = bzc * ZC;
-  const int ze = zs + ZC < nz ? zs + ZC : nz;
+  const int zs = bzc * zc;
+  const int ze = zs + zc < nz ? zs + zc : nz;
   const bool csf = STENCIL && mc.kappa != (T)0;
   constexpr uint32_t ES = SK == SK_NATIVE ? (uint32_t)sizeof(T) : 2u;  // population element
   constexpr bool S16 = SK != SK_NATIVE;
