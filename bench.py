@@ -275,6 +275,14 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32"):
     out = lb.adjoint_flux(steps, dLdQ, checkpoint_every=every)
     t_adj = time.perf_counter() - t0
     ka = lb.get_kernel_times(reset=True)
+    # every level kept (checkpoint_every = steps: no recomputation, steps
+    # population sets of HBM)
+    lb.set_state(start)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out_all = lb.adjoint_flux(steps, dLdQ, checkpoint_every=steps)
+    t_all = time.perf_counter() - t0
+    lb.get_kernel_times(reset=True)
     lb.set_profiling(False)
     lb.destroy()
     es = 8 if precision == "f64" else 4
@@ -291,6 +299,11 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32"):
             "flux_history_equal": bool(np.array_equal(out["Q"], q)),
             "forward_seconds": round(t_fwd, 4), "gradient_seconds": round(t_adj, 4),
             "gradient_over_forward": round(t_adj / t_fwd, 2),
+            "all_levels_kept": {"gradient_seconds": round(t_all, 4),
+                                "gradient_over_forward": round(t_all / t_fwd, 2),
+                                "population_sets": steps + 2,
+                                "same_gradient": bool(np.array_equal(out_all["dL_dphi"],
+                                                                     out["dL_dphi"]))},
             "step_kernel_ms": round(kf["step_ms"] / max(kf["step_launches"], 1), 4),
             "reverse_kernel_ms": round(adj_ms, 4),
             "reverse_kernel_launches": int(ka["adjoint_launches"]),

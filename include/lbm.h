@@ -351,7 +351,9 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  *
  * Method: a forward sweep of nsteps ordinary steps with the stored set copied
  * to a checkpoint every checkpoint_every steps, then a reverse sweep segment by
- * segment: each segment's stored sets are recomputed from its checkpoint, and
+ * segment: each segment's stored sets are recomputed from its checkpoint (the
+ * last segment keeps them from the forward sweep, so checkpoint_every =
+ * nsteps stores every level and recomputes nothing), and
  * one reverse-step kernel per step applies the transposed streaming (a gather
  * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
  * weights and the transposed collision Jacobian, and accumulates dL/dK0.  dL/dphi multiplies it by the K0(phi) table's slope on the lookup's
@@ -370,7 +372,8 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
  * fluid state), LBM_E_UNSUPPORTED (two components, tensorial resistivity,
  * pressure x faces or 16-bit storage), LBM_E_NOMEM, LBM_E_DEVICE,
- * LBM_E_NONFINITE (from a forward step's diagnostics). */
+ * LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
+ * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
                      int64_t checkpoint_every, double *Q_out, double *dL_dK0,
                      double *dL_dphi);

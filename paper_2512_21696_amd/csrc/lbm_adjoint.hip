@@ -38,7 +38,11 @@ namespace lbm {
 namespace adj {
 
 // The adjoint populations are stored in the state's type (fp64 or fp32); the
-// arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.
+// arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.  One thread
+// per voxel; the grid is a multiple of 8 blocks and block b takes the voxel
+// range (b % 8) * (grid / 8) + b / 8, so that each XCD (blocks are dealt to
+// the 8 XCDs round-robin) sweeps one contiguous z slab and the y and z
+// neighbours of its gathers stay in its own L2.
 template <typename T, bool REG>
 __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
                                                   const T *__restrict__ post,
@@ -48,7 +52,9 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
                                                   const T *__restrict__ K0,
                                                   double *__restrict__ gK0, const double a) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int per = gridDim.x / 8;
+  const long long blk = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const long long v = blk * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const uint32_t mk = mask[v];
   const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
@@ -218,12 +224,13 @@ void launch_adj_step(lbm_handle *h, const T *post, const T *lin, T *lout, double
                      double a) {
   DevState<T> &s = state<T>(h);
   Timed tm(h, K_ADJ);
+  const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
   if (h->p.collision == LBM_COLL_REGULARIZED)
-    hipLaunchKernelGGL((adj::k_adj_step<T, true>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
-                       post, lin, lout, s.mask, s.K0, gk, a);
+    hipLaunchKernelGGL((adj::k_adj_step<T, true>), dim3(nb), dim3(256), 0, h->st, h->mc, post, lin,
+                       lout, s.mask, s.K0, gk, a);
   else
-    hipLaunchKernelGGL((adj::k_adj_step<T, false>), dim3(blocks(h->N)), dim3(256), 0, h->st,
-                       h->mc, post, lin, lout, s.mask, s.K0, gk, a);
+    hipLaunchKernelGGL((adj::k_adj_step<T, false>), dim3(nb), dim3(256), 0, h->st, h->mc, post,
+                       lin, lout, s.mask, s.K0, gk, a);
 }
 
 template <typename T>
@@ -264,13 +271,20 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   if (!ok) return finish(set_err(h, LBM_E_NOMEM, "device allocation failed in adjoint_flux"));
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
   int rc = LBM_OK;
-  // forward sweep
+  // forward sweep.  The last segment keeps its levels: each of its steps but
+  // the last writes its new set straight into the ring (the handle's buffer
+  // pointers are swapped for it and put back at the end), so that segment is
+  // not recomputed, and checkpoint_every = nsteps recomputes nothing.
+  T *const own0 = s.f[0], *const own1 = s.f[1];
   for (int64_t sg = 0; sg < nseg && rc == LBM_OK; ++sg) {
     rc = hip_check(h, hipMemcpyAsync(ck + sg * QN, s.f[h->cur], QN * sizeof(T),
                                      hipMemcpyDeviceToDevice, h->st),
                    "checkpoint copy");
     const int64_t m = std::min<int64_t>(K, n - sg * K);
+    const bool keep = sg == nseg - 1;
+    T *const spare = s.f[1 - h->cur];
     for (int64_t k = 0; k < m && rc == LBM_OK; ++k) {
+      if (keep) s.f[1 - h->cur] = k < m - 1 ? ring + k * QN : spare;
       rc = step_t<T>(h, 1);
       if (rc != LBM_OK) break;
       Timed tm(h, K_OTHER);
@@ -278,6 +292,15 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
                          s.mask, s.partial);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0,
                          qh + 2 * (sg * K + k), 0);
+    }
+    if (keep) {
+      if (rc == LBM_OK) {  // the final set is in `spare`, one of the handle's buffers
+        s.f[1 - h->cur] = s.f[h->cur] == own0 ? own1 : own0;
+      } else {  // a failed step: the handle's buffers come back, the state is lost
+        s.f[0] = own0;
+        s.f[1] = own1;
+        h->has_fluid = false;
+      }
     }
   }
   // reverse sweep; the loss does not depend on the set after the last step
@@ -289,7 +312,8 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   for (int64_t sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
     const int64_t m = std::min<int64_t>(K, n - sg * K);
     auto level = [&](int64_t k) -> T * { return k == 0 ? ck + sg * QN : ring + (k - 1) * QN; };
-    for (int64_t k = 1; k < m; ++k) launch_recompute<T>(h, level(k - 1), level(k));
+    if (sg < nseg - 1)
+      for (int64_t k = 1; k < m; ++k) launch_recompute<T>(h, level(k - 1), level(k));
     for (int64_t k = m - 1; k >= 0; --k) {
       launch_adj_step<T>(h, level(k), lam + cl * QN, lam + (1 - cl) * QN, gk, dLdQ[sg * K + k]);
       cl = 1 - cl;
