@@ -1,15 +1,18 @@
 """Reference gradients of the outlet-flux history with respect to the gray
 porosity, for the one-component model (pore, gray and solid voxels, scalar
-K0(phi), regularised or BGK collision, semi-implicit or implicit resistance,
-body force).  TEST INFRASTRUCTURE ONLY (tests, smoke check, benchmark
-baseline).
+K0(phi) or the tensorial resistivity of Eqs. (6)-(7), regularised or BGK
+collision, semi-implicit or implicit resistance, body force).  TEST
+INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline).
 
-The step is the one of model.Oracle with one component, transcribed into plain
-PyTorch CPU fp64 operations so that torch's reverse-mode autograd gives the
-exact gradient of this discrete forward map; tests pin the transcription to
-model.Oracle (same fluxes and populations) and the gradient to central finite
-differences of model.Oracle.  It serves as the oracle of the GPU library's
-hand-written discrete adjoint.
+The step is the one of model.Oracle with one component, and the tensor set-up
+the one of tensor.inverse_permeability (smoothing, gradient and Hessian,
+eigen-decomposition, ordering by |lambda|, gate and tie-break, Eq. (7)),
+transcribed into plain PyTorch CPU fp64 operations so that torch's reverse-mode
+autograd gives the exact gradient of this discrete forward map (through the
+eigenvectors with torch.linalg.eigh's derivative); tests pin the transcription
+to model.Oracle and tensor.inverse_permeability (same fluxes, populations and
+K^-1) and the gradient to central finite differences of model.Oracle.  It
+serves as the oracle of the GPU library's hand-written discrete adjoint.
 
 Loss convention: the caller supplies dL/dQ(n) for the outlet fluxes
 Q(1..N) of N steps (Q(n) measured on the post-collision set of step n, as
@@ -73,6 +76,76 @@ def _hermite(fneq):
     return torch.stack(out)
 
 
+def _roll(a, dx=0, dy=0, dz=0):
+    """a at (x+dx, y+dy, z+dz), periodic, for [z, y, x] arrays."""
+    return torch.roll(a, (-dz, -dy, -dx), dims=(0, 1, 2))
+
+
+def _smooth(a, sigma, radius):
+    """Periodic separable Gaussian (weights normalised to 1), z then y then x."""
+    j = np.arange(-radius, radius + 1, dtype=np.float64)
+    w = np.exp(-j * j / (2.0 * sigma * sigma))
+    w = w / w.sum()
+    out = a
+    for dim in (0, 1, 2):
+        acc = torch.zeros_like(out)
+        for jj, wj in zip(range(-radius, radius + 1), w):
+            acc = acc + float(wj) * torch.roll(out, -jj, dims=dim)
+        out = acc
+    return out
+
+
+def inverse_permeability(phi, cls, ptype, K0, tables, p):
+    """K^-1 [6, z, y, x] (xx, yy, zz, xy, xz, yz; zero off gray) as a function
+    of the porosity tensor phi and the K0 field: the smoothed porosity (solid
+    0, pore 1), its central-difference gradient and Hessian, the eigenpairs
+    of the Hessian ordered by ascending |lambda|, the isotropic gate, the
+    tie-break that turns the second axis along the gradient's part normal to
+    the third, and K^-1 = sum_k e_k e_k^T / (a_k K0)."""
+    gray = torch.as_tensor(cls == GRAY)
+    base = torch.where(gray, phi, torch.as_tensor(np.where(cls == PORE, 1.0, 0.0)))
+    ps = _smooth(base, float(p.sigma_s), int(p.smooth_radius))
+    off = [(1, 0, 0), (0, 1, 0), (0, 0, 1)]
+    g = [0.5 * (_roll(ps, *off[a]) - _roll(ps, *[-v for v in off[a]])) for a in range(3)]
+    H = [[None] * 3 for _ in range(3)]
+    for a in range(3):
+        H[a][a] = _roll(ps, *off[a]) - 2.0 * ps + _roll(ps, *[-v for v in off[a]])
+        for b in range(a + 1, 3):
+            ea, eb = off[a], off[b]
+            pp = _roll(ps, *[u + v for u, v in zip(ea, eb)])
+            pm = _roll(ps, *[u - v for u, v in zip(ea, eb)])
+            mp = _roll(ps, *[-u + v for u, v in zip(ea, eb)])
+            mm = _roll(ps, *[-u - v for u, v in zip(ea, eb)])
+            H[a][b] = H[b][a] = 0.25 * (pp - pm - mp + mm)
+    idx = np.nonzero(cls == GRAY)
+    H3 = torch.stack([torch.stack([H[a][b][idx] for b in range(3)], -1) for a in range(3)], -2)
+    g3 = torch.stack([g[a][idx] for a in range(3)], -1)
+    lam, vec = torch.linalg.eigh(H3)
+    order = torch.argsort(lam.detach().abs(), dim=-1, stable=True)
+    lam = torch.gather(lam, -1, order)
+    E = torch.gather(vec, -1, order[:, None, :].expand(-1, 3, -1))
+    al = lam.abs()
+    e3 = E[:, :, 2]
+    pv = g3 - (g3 * e3).sum(-1, keepdim=True) * e3
+    pn = pv.norm(dim=-1)
+    tie = ((al[:, 1] - al[:, 0]) <= float(p.delta_tie) * al[:, 2]) & (pn > float(p.eps_g))
+    e2t = pv / torch.where(tie, pn, torch.ones_like(pn))[:, None]
+    e1t = torch.linalg.cross(e3, e2t, dim=-1)
+    e1t = e1t / torch.where(tie, e1t.norm(dim=-1), torch.ones_like(pn))[:, None]
+    E = torch.stack([torch.where(tie[:, None], e1t, E[:, :, 0]),
+                     torch.where(tie[:, None], e2t, E[:, :, 1]), e3], -1)
+    iso = (al.max(-1).values <= float(p.eps_H)) & (g3.norm(dim=-1) <= float(p.eps_g))
+    kd = torch.as_tensor(np.array([tables[int(t)]["kd"] for t in ptype[idx]], np.float64))
+    k0 = K0[idx]
+    M = sum(E[:, :, k, None] * E[:, None, :, k] / (kd[:, k] * k0)[:, None, None]
+            for k in range(3))
+    M = torch.where(iso[:, None, None], torch.eye(3, dtype=torch.float64) / k0[:, None, None], M)
+    out = torch.zeros((6,) + cls.shape, dtype=torch.float64)
+    comps = [(0, 0), (1, 1), (2, 2), (0, 1), (0, 2), (1, 2)]
+    return torch.stack([out[c].index_put(tuple(torch.as_tensor(i) for i in idx), M[:, a, b])
+                        for c, (a, b) in enumerate(comps)])
+
+
 class OneComponent:
     """The one-component step in torch; `phi` is a leaf tensor when gradients
     are wanted."""
@@ -90,6 +163,7 @@ class OneComponent:
         self.tau = float(p.tau[0])
         self.g = [float(v) for v in p.g[0]]
         self.h = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
+        self.tensor = bool(getattr(p, "tensor", False))
         self.src_solid = [_sh(self.solid, C[i], -1) for i in range(Q)]
         fl = self.fluid.numpy()
         xf = int(p.outlet_x)
@@ -113,8 +187,12 @@ class OneComponent:
                 K0 = torch.where(sel, _lerp(tab["K0"], phi), K0)
         return K0
 
-    def step(self, f, K0):
-        """One step from the post-streaming set f; returns (new f, Q)."""
+    def Kinv(self, phi, K0):
+        return inverse_permeability(phi, self.cls, self.ptype, K0, self.tables, self.p)
+
+    def step(self, f, K0, Kinv=None):
+        """One step from the post-streaming set f; returns (new f, Q).  With
+        the tensorial resistivity Kinv is K^-1 [6, z, y, x]."""
         p = self.p
         fl = self.fluid
         rho = f.sum(0)
@@ -123,10 +201,19 @@ class OneComponent:
         F_ex = [rho * self.g[d] for d in range(3)]
         nu = CS2 * (self.tau - 0.5)
         cR = torch.where(self.gray, rho * nu, torch.zeros_like(rho))
-        Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
-                         torch.zeros_like(rho))
-        u = [(mom[d] + self.h * F_ex[d]) / (safe + self.h * Rs) for d in range(3)]
-        F = [F_ex[d] - Rs * u[d] for d in range(3)]
+        b = [mom[d] + self.h * F_ex[d] for d in range(3)]
+        if Kinv is None:
+            Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
+                             torch.zeros_like(rho))
+            Ru = [Rs * (b[d] / (safe + self.h * Rs)) for d in range(3)]
+        else:
+            comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}
+            R = [[cR * Kinv[comp[(min(a, c), max(a, c))]] for c in range(3)] for a in range(3)]
+            A = torch.stack([torch.stack([self.h * R[a][c] + (safe if a == c else 0.0)
+                                          for c in range(3)], -1) for a in range(3)], -2)
+            u = torch.linalg.solve(A, torch.stack(b, -1)[..., None])[..., 0]
+            Ru = [sum(R[a][c] * u[..., c] for c in range(3)) for a in range(3)]
+        F = [F_ex[d] - Ru[d] for d in range(3)]
         up = [torch.where(fl, mom[d] / safe, torch.zeros_like(rho)) for d in range(3)]
         feq = _equilibrium(rho, up)
         fneq = f - feq
@@ -146,10 +233,11 @@ def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
     model = OneComponent(params, cls, ptype, tables)
     ph = torch.tensor(np.asarray(phi, np.float64), requires_grad=True)
     K0 = model.K0(ph)
+    Kinv = model.Kinv(ph, K0) if model.tensor else None
     f = torch.as_tensor(np.asarray(f0, np.float64))
     hist = []
     for _ in range(int(steps)):
-        f, Qn = model.step(f, K0)
+        f, Qn = model.step(f, K0, Kinv)
         hist.append(Qn)
     hist = torch.stack(hist)
     L = (hist * torch.as_tensor(np.asarray(dL_dQ, np.float64))).sum()

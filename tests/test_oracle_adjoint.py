@@ -79,3 +79,79 @@ def test_gradient_matches_oracle_finite_differences(collision, resistance):
             break
     assert checked == 3
     assert np.all(grad[cls != 2] == 0)
+
+
+def tensor_case():
+    """14^3 gray fibre bundles (3 cylinders), one component, tensorial
+    resistivity with multipliers (1, 0.1, 0.1), a skewed body force."""
+    wl = W.fiber_bundles(n=14, ncyl=3, precision="f64")
+    p = wl["params"]
+    p.outlet_x = 6
+    p.g = ((1e-4, 3e-5, -2e-5), (0.0, 0.0, 0.0))
+    return p, wl["cls"], wl["phi"], wl["ptype"], wl["tables"], wl["rho_w"]
+
+
+def test_tensor_setup_and_forward_equal_oracle():
+    import torch
+    from oracle.tensor import inverse_permeability
+    p, cls, phi, pt, tabs, rho = tensor_case()
+    m = A.OneComponent(p, cls, pt, tabs)
+    ph = torch.tensor(phi)
+    K0 = m.K0(ph)
+    Ki = m.Kinv(ph, K0).numpy()
+    ref, aux = inverse_permeability(phi, cls, pt, K0.numpy(), tabs, p.sigma_s, p.smooth_radius,
+                                    p.eps_g, p.eps_H, p.delta_tie)
+    assert np.abs(Ki - ref).max() < 1e-13 * np.abs(ref).max()
+    # the case exercises anisotropic axes (not only the isotropic gate)
+    assert sum(not iso for iso, _ in aux["axes"].values()) > 100
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rho)
+    f0 = o.f[0].copy()
+    qs = []
+    for _ in range(10):
+        o.step(1)
+        qs.append(o.Q_last[0])
+    hist, _, fN = A.flux_gradient(p, cls, phi, pt, tabs, f0, 10, np.ones(10))
+    assert np.abs(hist - np.array(qs)).max() < 1e-14
+    assert np.abs(fN - o.f[0]).max() < 1e-14
+
+
+def test_tensor_gradient_matches_oracle_finite_differences():
+    """dL/dphi through K0(phi) and through K^-1(phi) (smoothing, Hessian,
+    eigenvectors): perturbing one voxel moves K^-1 of every gray voxel within
+    the smoothing radius."""
+    p, cls, phi, pt, tabs, rho = tensor_case()
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rho)
+    _, grad, _ = A.flux_gradient(p, cls, phi, pt, tabs, o.f[0].copy(), steps, a)
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(3)
+    eps = 1e-4
+    checked = 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue
+        Ls = []
+        for s in (1, -1):
+            ph = phi.copy()
+            ph[v] += s * eps
+            oo = Oracle(p)
+            oo.set_geometry(cls, ph, pt, tabs)
+            oo.init_fluid(rho)
+            q = []
+            for _ in range(steps):
+                oo.step(1)
+                q.append(oo.Q_last[0])
+            Ls.append(float((a * np.array(q)).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        assert abs(grad[v] - fd) < 1e-4 * abs(fd) + 1e-12, (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
