@@ -356,8 +356,15 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * nsteps stores every level and recomputes nothing), and
  * one reverse-step kernel per step applies the transposed streaming (a gather
  * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
- * weights and the transposed collision Jacobian, and accumulates dL/dK0.  dL/dphi multiplies it by the K0(phi) table's slope on the lookup's
- * cell (the right-hand slope on a table knot).
+ * weights and the transposed collision Jacobian, and accumulates dL/dK0 (or,
+ * with the tensor, dL/dK^-1 per gray voxel).  The tensor's dL/dK^-1 goes back
+ * through the set-up: first-order perturbation of the Hessian's eigenvectors
+ * (and of the tie-break's gradient-aligned axis), the transposed gradient and
+ * Hessian stencils and the transposed Gaussian smoothing; the derivative is
+ * that of the branch each voxel took (isotropic gate, |lambda| ordering, tie
+ * test), exact away from those switches.  dL/dphi adds dL/dK0 times the
+ * K0(phi) table's slope on the lookup's cell (the right-hand slope on a table
+ * knot).
  *
  * Arguments: nsteps >= 1; dL_dQ a host array of nsteps finite doubles;
  * checkpoint_every >= 1, or 0 for ceil(sqrt(nsteps)); Q_out (nsteps), dL_dK0 and
@@ -365,13 +372,14 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * caller, each may be NULL.  Device memory, allocated through the hook and
  * freed before returning: ceil(nsteps / K) + K + 1 population-sized sets of
  * the storage type (19 N values each, K = checkpoint_every: checkpoints, the
- * recomputed levels of one segment, two adjoint sets) plus 2 N doubles.  The
- * adjoint populations are kept in the storage type, the reverse arithmetic and
- * the dL/dK0 accumulation in fp64.  The handle ends nsteps steps on, exactly as after lbm_step(nsteps)
- * (step counter and flux accumulators included).  Synchronises the stream.
+ * recomputed levels of one segment, two adjoint sets) plus 2 N doubles (scalar
+ * K0) or 20 N doubles (tensor).  The adjoint populations are kept in the
+ * storage type, the reverse arithmetic and the gradient accumulation in fp64.
+ * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
+ * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
- * fluid state), LBM_E_UNSUPPORTED (two components, tensorial resistivity,
- * pressure x faces or 16-bit storage), LBM_E_NOMEM, LBM_E_DEVICE,
+ * fluid state), LBM_E_UNSUPPORTED (two components, pressure x faces or 16-bit
+ * storage), LBM_E_NOMEM, LBM_E_DEVICE,
  * LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,

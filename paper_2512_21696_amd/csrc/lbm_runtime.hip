@@ -60,6 +60,7 @@ struct lbm_handle {
   std::vector<uint8_t> geom_cls;   // host copy of the classes (density validation)
   double *geom_phi = nullptr;      // device copies of the porosity [v] and of the fp64
   double *geom_tabs = nullptr;     // pore tables [type][K0, Pc, Krw, Kro][TABLE_N]
+  double *geom_meta = nullptr;     // and their metadata [type][8] (kept for the adjoint)
   // profiling
   bool prof = false;
   std::vector<EventPair> ev_pool, ev_live;
@@ -254,7 +255,8 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
   double *dtabs = alloc_into<double>(h, h->geom_allocs, (size_t)nt * 4 * TABLE_N, &ok);
   h->geom_phi = phi_d;
   h->geom_tabs = dtabs;
-  double *dmeta = alloc_into<double>(h, tmp, (size_t)nt * 8, &ok);
+  double *dmeta = alloc_into<double>(h, h->geom_allocs, (size_t)nt * 8, &ok);
+  h->geom_meta = dmeta;
   s.tab = alloc_into<T>(h, h->geom_allocs, (size_t)nt * 3 * TABLE_N, &ok);
   double *sm1 = nullptr, *sm2 = nullptr, *wts = nullptr;
   if (h->p.tensor) {

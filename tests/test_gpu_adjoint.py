@@ -255,3 +255,78 @@ def test_fullsize_fp32_gradient_against_fp64():
     # shows at a few 1e-4 in it; the gradient is of the same order
     assert eq < 1e-3
     assert eg < 1e-2
+
+
+def fiber_case(n=14, ncyl=3, precision="f64", collision="regularized", resistance="semi_implicit"):
+    """Gray fibre bundles, one component, tensorial resistivity (1, 0.1, 0.1),
+    a few solid voxels added (seed 33), skewed body force."""
+    wl = W.fiber_bundles(n=n, ncyl=ncyl, precision=precision)
+    p = wl["params"]
+    p.outlet_x = n // 2 - 1
+    p.collision = collision
+    p.resistance = resistance
+    p.g = ((1e-4, 3e-5, -2e-5), (0.0, 0.0, 0.0))
+    rng = np.random.default_rng(33)
+    cls = wl["cls"].copy()
+    cls[(rng.random(cls.shape) < 0.05) & (cls == 0)] = 1
+    phi = np.where(cls == 1, 0.0, wl["phi"])
+    return dict(params=p, cls=cls, phi=phi, ptype=wl["ptype"], tables=wl["tables"],
+                rho=wl["rho_w"])
+
+
+@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
+                                                  ("bgk", "implicit")])
+def test_tensor_adjoint_matches_oracle_fp64(collision, resistance):
+    announce(f"tensor adjoint 14^3 fibres fp64 {collision} {resistance}, 10 steps")
+    c = fiber_case(collision=collision, resistance=resistance)
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    qo, go = oracle_gradient(c, steps, a)
+    lb = gpu_handle(c)
+    out = lb.adjoint_flux(steps, a, checkpoint_every=4)
+    lb.destroy()
+    gray = c["cls"] == 2
+    assert np.count_nonzero(go[gray]) > 0.5 * gray.sum()
+    assert np.abs(out["Q"] - qo).max() < 1e-13
+    e = norm_err(out["dL_dphi"], go)
+    print(f"tensor dL/dphi normalised error {e:.2e}")
+    assert e < 1e-9
+    assert np.all(out["dL_dphi"][~gray] == 0)
+
+
+def test_tensor_gradient_against_gpu_finite_differences():
+    """64^3 fibre bundles (8 cylinders), fp64, 300 steps, linear flux loss:
+    the adjoint against central differences of the GPU forward run on 4 gray
+    voxels (seed 5003)."""
+    import paper_2512_21696_amd as L
+    c = fiber_case(n=64, ncyl=8)
+    steps = 300
+    a = np.where(np.arange(steps) >= 100, 1.0, 0.0)
+    announce(f"tensor adjoint 64^3 fibres fp64 {steps} steps")
+    lb = gpu_handle(c)
+    out = lb.adjoint_flux(steps, a, checkpoint_every=20)
+    lb.destroy()
+    g = out["dL_dphi"]
+    gray = np.argwhere(c["cls"] == 2)
+    t = c["phi"][tuple(gray.T)] * 1024
+    cand = gray[np.minimum(t - np.floor(t), np.ceil(t) - t) > 0.2]
+    rng = np.random.default_rng(5003)
+    mag = np.abs(g[tuple(cand.T)])
+    top = cand[np.argsort(mag)[-50:]]
+    picks = [tuple(v) for v in top[rng.choice(50, 2, replace=False)]]
+    picks += [tuple(v) for v in cand[rng.choice(len(cand), 2, replace=False)]]
+    gmax = np.abs(g).max()
+    eps = 1e-4
+    for v in picks:
+        announce(f"tensor 64^3 finite difference at {v}")
+        Ls = []
+        for sgn in (1, -1):
+            ph = c["phi"].copy()
+            ph[v] += sgn * eps
+            lb = gpu_handle(dict(c, phi=ph))
+            Ls.append(float(np.sum(a * lb.adjoint_flux(steps, np.zeros(steps),
+                                                       checkpoint_every=steps)["Q"])))
+            lb.destroy()
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        print(f"voxel {v}: adjoint {g[v]:.6e} fd {fd:.6e}")
+        assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
