@@ -233,19 +233,28 @@ def rev_library(steps=400):
                                "K_max": float(K.max())}}
 
 
-def adjoint_gradient(n=96, steps=800, every=50, precision="f32"):
-    """The porosity gradient of a flux-misfit loss (workloads.adjoint_rock: the
-    rock generator at n^3, one component, `steps` steps, squared misfit over
-    steps 200..steps): an untimed forward run for the flux history and dL/dQ,
-    then lbm_adjoint_flux with checkpoints every `every` steps, timed on the
-    host around the call (forward sweep, recomputation, reverse sweep, copies)
-    and per kernel with the library's HIP events.  Beside it the plain forward
-    run of the same steps."""
+def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
+    """The porosity gradient of a flux loss.  kind "rock": workloads.adjoint_rock
+    (the rock generator at n^3, one component, `steps` steps, squared misfit
+    over steps 200..steps); kind "fiber": the n^3 gray fibre bundles with the
+    tensorial resistivity, L = sum of Q(n) over steps 200..steps.  An untimed
+    forward run for the flux history and dL/dQ, then lbm_adjoint_flux with
+    checkpoints every `every` steps, timed on the host around the call
+    (forward sweep, recomputation, reverse sweep, copies) and per kernel with
+    the library's HIP events.  Beside it the plain forward run of the same
+    steps."""
     import numpy as np
     import torch
     import workloads as W
     import paper_2512_21696_amd as L
-    wl = W.adjoint_rock(n=n, steps=steps, precision=precision)
+    if kind == "rock":
+        wl = W.adjoint_rock(n=n, steps=steps, precision=precision)
+    else:
+        wl = W.fiber_bundles(n=n, precision=precision)
+        wl["params"].outlet_x = n // 2
+        lin = np.where(np.arange(steps) >= 200, 1.0, 0.0)
+        wl["target"] = lambda q: None
+        wl["loss_grad"] = lambda q, t: (float(np.sum(lin * q)), lin)
     cls = wl["cls"]
     n_fluid = int(np.sum(cls != 1))
     gray_frac = float(np.sum(cls == 2)) / n_fluid
@@ -276,34 +285,37 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32"):
     t_adj = time.perf_counter() - t0
     ka = lb.get_kernel_times(reset=True)
     # every level kept (checkpoint_every = steps: no recomputation, steps
-    # population sets of HBM)
-    lb.set_state(start)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    out_all = lb.adjoint_flux(steps, dLdQ, checkpoint_every=steps)
-    t_all = time.perf_counter() - t0
+    # population sets of HBM), when that fits in 150 GB
+    es = 8 if precision == "f64" else 4
+    all_levels = None
+    if (steps + 2) * 19 * cls.size * es < 150e9:
+        lb.set_state(start)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out_all = lb.adjoint_flux(steps, dLdQ, checkpoint_every=steps)
+        t_all = time.perf_counter() - t0
+        all_levels = {"gradient_seconds": round(t_all, 4),
+                      "gradient_over_forward": round(t_all / t_fwd, 2),
+                      "population_sets": steps + 2,
+                      "same_gradient": bool(np.array_equal(out_all["dL_dphi"], out["dL_dphi"]))}
     lb.get_kernel_times(reset=True)
     lb.set_profiling(False)
     lb.destroy()
-    es = 8 if precision == "f64" else 4
     # per fluid voxel: the recomputed set pulled, the adjoint set gathered and
     # written (storage type), the mask word; gray voxels read K0 and update
-    # their fp64 dL/dK0
-    b = 19 * es + 2 * 19 * es + 4 + gray_frac * (es + 16)
+    # their fp64 dL/dK0, or (tensor) read K^-1 and update dL/dK^-1
+    b = 19 * es + 2 * 19 * es + 4 + gray_frac * ((es + 16) if kind == "rock" else (6 * es + 96))
     adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
     achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
     g = out["dL_dphi"]
     return {"workload": wl["name"], "storage": precision, "components": 1, "steps": steps,
+            "tensor": kind != "rock",
             "checkpoint_every": every, "fluid_voxels": n_fluid,
             "gray_voxels": int(np.sum(cls == 2)), "loss": loss,
             "flux_history_equal": bool(np.array_equal(out["Q"], q)),
             "forward_seconds": round(t_fwd, 4), "gradient_seconds": round(t_adj, 4),
             "gradient_over_forward": round(t_adj / t_fwd, 2),
-            "all_levels_kept": {"gradient_seconds": round(t_all, 4),
-                                "gradient_over_forward": round(t_all / t_fwd, 2),
-                                "population_sets": steps + 2,
-                                "same_gradient": bool(np.array_equal(out_all["dL_dphi"],
-                                                                     out["dL_dphi"]))},
+            "all_levels_kept": all_levels,
             "step_kernel_ms": round(kf["step_ms"] / max(kf["step_launches"], 1), 4),
             "reverse_kernel_ms": round(adj_ms, 4),
             "reverse_kernel_launches": int(ka["adjoint_launches"]),
@@ -432,7 +444,10 @@ def main():
     if args.adjoint:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps({"adjoint_gradient": adjoint_gradient()}), flush=True)
+        print(json.dumps({"adjoint_gradient": adjoint_gradient(),
+                          "adjoint_gradient_tensor": adjoint_gradient(n=192, steps=1000,
+                                                                      kind="fiber")}),
+              flush=True)
         return
 
     import numpy as np
@@ -607,6 +622,7 @@ def main():
     if compare:
         out["rev_library"] = rev_library()
         out["adjoint_gradient"] = adjoint_gradient()
+        out["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
