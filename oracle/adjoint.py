@@ -244,3 +244,149 @@ def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
     L.backward()
     g = ph.grad.detach().numpy()
     return hist.detach().numpy(), np.where(np.asarray(cls) == GRAY, g, 0.0), f.detach().numpy()
+
+
+class TwoComponent(OneComponent):
+    """The two-component step in torch (Sec. II without the CSF control, kappa
+    = 0, and for horizons without residual events, which are switches with no
+    derivative): the pseudo-potential force with wall virtual densities, the
+    capillary term of Eq. (1) with P_c = s_J(phi) P_c(S) and the gradient of
+    the mobile saturation, the resistance c_R = sum_b rho S^b nu^b / max(Kr^b,
+    Kr_min) with K0(phi) or K^-1(phi), the common velocity u' and per-component
+    collision with the force term at u' + F^a / (2 rho^a).  r [2, z, y, x]
+    holds the residual amounts, constant over such a horizon."""
+
+    def __init__(self, params, cls, ptype, tables, r):
+        super().__init__(params, cls, ptype, tables)
+        p = params
+        if float(getattr(p, "kappa", 0.0)) != 0.0:
+            raise ValueError("the reference gradient covers kappa = 0")
+        self.taus = [float(t) for t in p.tau]
+        self.gs = [[float(v) for v in p.g[a]] for a in range(2)]
+        self.r = torch.as_tensor(np.asarray(r, np.float64))
+        self.nb_solid = [_sh(self.solid, C[i]) for i in range(Q)]
+
+    def sJ(self, phi, K0):
+        out = torch.zeros(self.shape, dtype=torch.float64)
+        for t, tab in enumerate(self.tables):
+            sel = torch.as_tensor((self.cls == GRAY) & (self.ptype == t))
+            if bool(sel.any()):
+                ref = torch.tensor(float(tab["phi_ref"]), dtype=torch.float64)
+                k0ref = _lerp(tab["K0"], ref).item()
+                safe_k = torch.where(sel, K0, torch.ones_like(K0))
+                ph_ = torch.where(sel, phi, torch.ones_like(phi))
+                val = torch.sqrt((k0ref / tab["phi_ref"]) / (safe_k / ph_))
+                out = torch.where(sel, val, out)
+        return out
+
+    def _nb(self, X, i):
+        return torch.where(self.nb_solid[i], X, _sh(X, C[i]))
+
+    def step2(self, f, K0, sJ, Kinv=None):
+        """One step from the post-streaming sets f [2, Q, z, y, x]; returns
+        (new f, Q^w)."""
+        p = self.p
+        fl = self.fluid
+        rho = [f[a].sum(0) for a in range(2)]
+        mom = [[sum(C[i, d] * f[a][i] for i in range(Q) if C[i, d]) for d in range(3)]
+               for a in range(2)]
+        rho_t = rho[0] + rho[1]
+        safe = torch.where(fl, rho_t, torch.ones_like(rho_t))
+        F_ex = [[rho[a] * self.gs[a][d] for d in range(3)] for a in range(2)]
+        span = p.s_max - p.s_min
+        tw, to = rho[0] + self.r[0], rho[1] + self.r[1]
+        s = torch.where(fl, tw / torch.where(fl, tw + to, torch.ones_like(tw)), torch.zeros_like(tw))
+        S = torch.clamp((s - p.s_min) / span, 0.0, 1.0)
+        S_hat = torch.where(fl, (rho[0] / safe - p.s_min) / span, torch.zeros_like(tw))
+        for a in range(2):
+            b = 1 - a
+            wall = torch.clamp(rho[b] + p.wall_dpsi[b], min=0.0)
+            acc = [0.0, 0.0, 0.0]
+            for i in range(1, Q):
+                psi = torch.where(self.nb_solid[i], wall, _sh(rho[b], C[i]))
+                for d in range(3):
+                    if C[i, d]:
+                        acc[d] = acc[d] + W[i] * C[i, d] * psi
+            for d in range(3):
+                F_ex[a][d] = F_ex[a][d] - p.G * rho[a] * acc[d]
+        gS = [0.0, 0.0, 0.0]
+        for i in range(1, Q):
+            v = self._nb(S_hat, i)
+            for d in range(3):
+                if C[i, d]:
+                    gS[d] = gS[d] + (W[i] * C[i, d] / CS2) * v
+        Pc = torch.zeros(self.shape, dtype=torch.float64)
+        Krw = torch.zeros(self.shape, dtype=torch.float64)
+        Kro = torch.zeros(self.shape, dtype=torch.float64)
+        for t, tab in enumerate(self.tables):
+            sel = torch.as_tensor((self.cls == GRAY) & (self.ptype == t))
+            if bool(sel.any()):
+                Pc = torch.where(sel, sJ * _lerp(tab["Pc"], S), Pc)
+                Krw = torch.where(sel, _lerp(tab["Krw"], S), Krw)
+                Kro = torch.where(sel, _lerp(tab["Kro"], S), Kro)
+        for a in range(2):
+            for d in range(3):
+                F_ex[a][d] = F_ex[a][d] + torch.where(self.gray, -Pc * (rho[a] / safe) * gS[d],
+                                                      torch.zeros_like(Pc))
+        nu = [CS2 * (t - 0.5) for t in self.taus]
+        Sw, So = S, 1.0 - S
+        cw = torch.where(Sw > 0, rho_t * Sw * nu[0] / torch.clamp(Krw, min=p.kr_min),
+                         torch.zeros_like(S))
+        co = torch.where(So > 0, rho_t * So * nu[1] / torch.clamp(Kro, min=p.kr_min),
+                         torch.zeros_like(S))
+        cR = torch.where(self.gray, cw + co, torch.zeros_like(S))
+        b = [mom[0][d] + mom[1][d] + self.h * (F_ex[0][d] + F_ex[1][d]) for d in range(3)]
+        if Kinv is None:
+            Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
+                             torch.zeros_like(S))
+            Ru = [Rs * (b[d] / (safe + self.h * Rs)) for d in range(3)]
+        else:
+            comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}
+            R = [[cR * Kinv[comp[(min(a, c), max(a, c))]] for c in range(3)] for a in range(3)]
+            A = torch.stack([torch.stack([self.h * R[a][c] + (safe if a == c else 0.0)
+                                          for c in range(3)], -1) for a in range(3)], -2)
+            u = torch.linalg.solve(A, torch.stack(b, -1)[..., None])[..., 0]
+            Ru = [sum(R[a][c] * u[..., c] for c in range(3)) for a in range(3)]
+        F = [[F_ex[a][d] - (rho[a] / safe) * Ru[d] for d in range(3)] for a in range(2)]
+        den = rho[0] / self.taus[0] + rho[1] / self.taus[1]
+        den = torch.where(fl, den, torch.ones_like(den))
+        up = [torch.where(fl, (mom[0][d] / self.taus[0] + mom[1][d] / self.taus[1]) / den,
+                          torch.zeros_like(den)) for d in range(3)]
+        posts = []
+        for a in range(2):
+            feq = _equilibrium(rho[a], up)
+            fneq = f[a] - feq
+            f1 = _hermite(fneq) if p.collision == "regularized" else fneq
+            ra = torch.where(fl, 2.0 * rho[a], torch.ones_like(rho[a]))
+            ua = [up[d] + F[a][d] / ra for d in range(3)]
+            post = feq + (1.0 - 1.0 / self.taus[a]) * f1 + _force_term(ua, F[a])
+            posts.append(torch.where(fl, post, torch.zeros_like(post)))
+        Qn = (self.flux_w * posts[0]).sum()
+        new = []
+        for a in range(2):
+            na = torch.stack([torch.where(self.src_solid[i], posts[a][OPP[i]],
+                                          _sh(posts[a][i], C[i], -1)) for i in range(Q)])
+            new.append(torch.where(fl, na, torch.zeros_like(na)))
+        return torch.stack(new), Qn
+
+
+def flux_gradient2(params, cls, phi, ptype, tables, f0, r, steps, dL_dQ):
+    """Two components: runs `steps` steps from the post-streaming sets f0
+    [2, Q, z, y, x] with residual amounts r [2, z, y, x] and returns (Q^w
+    history, dL/dphi, final f) for L = sum_n dL_dQ[n] Q^w(n), through K0(phi)
+    (or K^-1(phi)) in the resistance and s_J(phi) in the capillary term."""
+    model = TwoComponent(params, cls, ptype, tables, r)
+    ph = torch.tensor(np.asarray(phi, np.float64), requires_grad=True)
+    K0 = model.K0(ph)
+    sJ = model.sJ(ph, K0)
+    Kinv = model.Kinv(ph, K0) if model.tensor else None
+    f = torch.as_tensor(np.asarray(f0, np.float64))
+    hist = []
+    for _ in range(int(steps)):
+        f, Qn = model.step2(f, K0, sJ, Kinv)
+        hist.append(Qn)
+    hist = torch.stack(hist)
+    L = (hist * torch.as_tensor(np.asarray(dL_dQ, np.float64))).sum()
+    L.backward()
+    g = ph.grad.detach().numpy()
+    return hist.detach().numpy(), np.where(np.asarray(cls) == GRAY, g, 0.0), f.detach().numpy()

@@ -155,3 +155,77 @@ def test_tensor_gradient_matches_oracle_finite_differences():
         if checked == 3:
             break
     assert checked == 3
+
+
+def two_case(collision="regularized", resistance="implicit", seed=7):
+    """20 x 8 x 6, two components (water in x < 10, oil beyond), random pore /
+    solid / gray voxels with two pore types, kappa = 0, skewed body forces."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 6, 8, 20
+    r = rng.random((nz, ny, nx))
+    cls = np.where(r < 0.15, 1, np.where(r < 0.5, 2, 0)).astype(np.uint8)
+    phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
+    pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
+    K0 = W.kozeny_carman_table(2.0)
+    tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
+            for lam in (1.0, 2.0)]
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
+                 collision=collision, resistance=resistance,
+                 g=((1e-4, 2e-5, 0.0), (0.0, 0.0, -1e-5)), outlet_x=9).filled()
+    m = p.m_minor
+    x = np.arange(nx)[None, None, :]
+    rw = np.where(x < 10, 1.0, m) + 0.005 * rng.random(cls.shape)
+    return p, cls, phi, pt, tabs, rw, 1.0 + m - rw
+
+
+def _two_history(p, cls, phi, pt, tabs, rw, ro, steps):
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rw, ro)
+    f0, r0, side0 = o.f.copy(), o.r.copy(), o.side.copy()
+    q = []
+    for _ in range(steps):
+        o.step(1)
+        q.append(o.Q_last[0])
+    events = int(np.sum(o.side != side0)) + int(np.sum(o.r != r0))
+    return f0, r0, np.array(q), o.f, events
+
+
+def test_two_component_forward_equals_oracle():
+    p, cls, phi, pt, tabs, rw, ro = two_case()
+    f0, r0, q, fN, events = _two_history(p, cls, phi, pt, tabs, rw, ro, 10)
+    assert events == 0  # the horizon has no residual event
+    hist, _, f_t = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r0, 10, np.ones(10))
+    assert np.abs(hist - q).max() < 1e-14
+    assert np.abs(f_t - fN).max() < 1e-14
+
+
+def test_two_component_gradient_matches_oracle_finite_differences():
+    """Through K0(phi) in the resistance and s_J(phi) in the capillary term."""
+    p, cls, phi, pt, tabs, rw, ro = two_case()
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    f0, r0, _, _, _ = _two_history(p, cls, phi, pt, tabs, rw, ro, 1)
+    _, grad, _ = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r0, steps, a)
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(3)
+    eps = 1e-4
+    checked = 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue
+        Ls = []
+        for s in (1, -1):
+            ph = phi.copy()
+            ph[v] += s * eps
+            _, _, q, _, ev = _two_history(p, cls, ph, pt, tabs, rw, ro, steps)
+            assert ev == 0
+            Ls.append(float((a * q).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        assert abs(grad[v] - fd) < 1e-4 * abs(fd) + 1e-12, (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
