@@ -273,25 +273,500 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   if (gray && !tens) gk[v] += -(r / k0) * (rho * Rsb);
 }
 
-// dL/dphi = dL/dK0 * dK0/dphi on gray voxels: the slope of the linear
-// interpolation in the K0(phi) table, on the same table cell as the lookup.
-__global__ __launch_bounds__(256) void k_adj_phi(const double *__restrict__ gK0,
-                                                 const double *__restrict__ phi,
-                                                 const uint8_t *__restrict__ pt,
+// ---------------------------------------------------------------------------
+// Two components (Sec. II without the CSF control, and for horizons without
+// residual events).  Forward quantities at a fluid voxel x, per component a
+// (b = 1 - a), with rho_t = rho^w + rho^o:
+//   F_ex^a = rho^a g^a - G rho^a sum_i w_i c_i psi^b(x + c_i)   (psi = rho, or
+//            max(rho^b(x) + dpsi^b, 0) across a solid link)
+//          - P_c (rho^a / rho_t) grad S_hat                       (gray voxels)
+//   S_hat = (rho^w / rho_t - s_min) / span (own value across a solid link),
+//   S = clamp(((rho^w + r^w) / (rho_t + r^w + r^o) - s_min) / span, 0, 1),
+//   P_c = s_J P_c(S), c_R = rho_t S nu^w / max(Kr^w(S), Kr_min)
+//                         + rho_t (1 - S) nu^o / max(Kr^o(S), Kr_min),
+//   u = (rho_t I + h c_R K^-1)^-1 (m^w + m^o + h (F_ex^w + F_ex^o)),
+//   F^a = F_ex^a - (rho^a / rho_t) c_R K^-1 u,
+//   u' = (omega^w m^w + omega^o m^o) / (omega^w rho^w + omega^o rho^o),
+//   post^a = w_i (A^a + B^a.c_i + c_i^T C^a c_i) as for one component, with
+//   feq(rho^a, u'), the force term at u' + F^a / (2 rho^a) and, regularised,
+//   the first-order part j^a = m^a - rho^a u' of the non-equilibrium.
+// The reverse of the force's neighbour reads is split off: k_adj_step2 keeps
+// dL/d(acc^a) and dL/d(grad S_hat) of each voxel (stash[9][v]), k_adj_nl2
+// gathers them into the neighbours' dL/drho^a (rnl[v][2]), which the next
+// reverse step adds to every population of those voxels as it gathers.
+template <typename T, bool REG, bool TENS>
+__global__ __launch_bounds__(256) void k_adj_step2(
+    const ModelConsts mc, const T *__restrict__ post, const T *__restrict__ rho2,
+    const T *__restrict__ rres, const T *__restrict__ lin, const T *__restrict__ rnl,
+    T *__restrict__ lout, T *__restrict__ stash, const uint32_t *__restrict__ mask,
+    const T *__restrict__ K0, const T *__restrict__ Kinv, const T *__restrict__ sJ,
+    const uint8_t *__restrict__ ptype, const T *__restrict__ tab, double *__restrict__ gk,
+    double *__restrict__ gsj, const double an) {
+  const long long N = mc.N;
+  const int per = gridDim.x / 8;
+  const long long blk = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
+  const long long v = blk * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
+  if (cl == SOLID_CODE) return;
+  const bool gray = cl == GRAY_CODE;
+  const bool tens = TENS && gray;
+  const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+  const int x1 = mc.outlet_x + 1 == mc.nx ? 0 : mc.outlet_x + 1;
+  const bool at0 = nb.x == mc.outlet_x, at1 = nb.x == x1;
+  const double cs2 = CS2, cs4 = CS2 * CS2;
+
+  // pulls, moments and the gathered adjoint of the post-collision sets
+  double rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
+  double lp[REG ? 1 : 2][REG ? 1 : Q];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const T *pa = post + (size_t)a * Q * N;
+    const T *la = lin + (size_t)a * Q * N;
+    rho[a] = 0; L0[a] = 0;
+    for (int d = 0; d < 3; ++d) { m[a][d] = 0; L1[a][d] = 0; }
+    for (int d = 0; d < 6; ++d) M2[a][d] = 0;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const int j = opp(i);
+      const double fi = (double)(((mk >> j) & 1u) ? pa[(size_t)j * N + v]
+                                                  : pa[(size_t)i * N + nb.at(-cx(i), -cy(i), -cz(i))]);
+      rho[a] += fi;
+      if (cx(i)) m[a][0] += cx(i) * fi;
+      if (cy(i)) m[a][1] += cy(i) * fi;
+      if (cz(i)) m[a][2] += cz(i) * fi;
+      const bool wall = (mk >> i) & 1u;
+      double l;
+      if (wall) {
+        l = (double)la[(size_t)j * N + v] + (double)rnl[2 * v + a];
+      } else {
+        const int y = nb.at(cx(i), cy(i), cz(i));
+        l = (double)la[(size_t)i * N + y] + (double)rnl[2 * (size_t)y + a];
+        if (a == 0 && at0 && cx(i) == 1) l += an;
+        if (a == 0 && at1 && cx(i) == -1) l -= an;
+      }
+      if (!REG) lp[REG ? 0 : a][REG ? 0 : i] = l;
+      const double wl = wq(i) * l;
+      L0[a] += wl;
+      if (cx(i)) { L1[a][0] += cx(i) * wl; M2[a][0] += wl; }
+      if (cy(i)) { L1[a][1] += cy(i) * wl; M2[a][1] += wl; }
+      if (cz(i)) { L1[a][2] += cz(i) * wl; M2[a][2] += wl; }
+      if (cx(i) && cy(i)) M2[a][3] += (cx(i) * cy(i)) * wl;
+      if (cx(i) && cz(i)) M2[a][4] += (cx(i) * cz(i)) * wl;
+      if (cy(i) && cz(i)) M2[a][5] += (cy(i) * cz(i)) * wl;
+    }
+  }
+
+  // forward quantities
+  const double rt = rho[0] + rho[1], irt = 1.0 / rt;
+  const double h = mc.res_implicit ? 1.0 : 0.5;
+  const double span = 1.0 / mc.inv_span;
+  double Fex[2][3], acc[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int b = 1 - a;
+    double pw = rho[b] + mc.wall_dpsi[b];
+    pw = pw > 0.0 ? pw : 0.0;
+    double s0 = 0, s1 = 0, s2 = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const double psi = ((mk >> i) & 1u) ? pw : (double)rho2[2 * (size_t)nb.at(cx(i), cy(i), cz(i)) + b];
+      if (cx(i)) s0 += wq(i) * cx(i) * psi;
+      if (cy(i)) s1 += wq(i) * cy(i) * psi;
+      if (cz(i)) s2 += wq(i) * cz(i) * psi;
+    }
+    acc[a][0] = s0; acc[a][1] = s1; acc[a][2] = s2;
+    for (int d = 0; d < 3; ++d) Fex[a][d] = rho[a] * mc.g[a][d] - mc.G * rho[a] * acc[a][d];
+  }
+  // gray: saturation, tables, capillary force, resistance coefficient
+  double S = 0, Sraw = 0, tw = 0, to = 0, gS[3] = {0, 0, 0}, Pct = 0, dPct = 0, Krw = 0,
+         dKrw = 0, Kro = 0, dKro = 0, sj = 0, Pc = 0, kw = 1, ko = 1, cR = 0;
+  const double shat0 = (rho[0] * irt - mc.s_min) / span;
+  if (gray) {
+    tw = rho[0] + (double)rres[v];
+    to = rho[1] + (double)rres[N + v];
+    Sraw = (tw / (tw + to) - mc.s_min) / span;
+    S = Sraw < 0.0 ? 0.0 : (Sraw > 1.0 ? 1.0 : Sraw);
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      double val = shat0;
+      if (!((mk >> i) & 1u)) {
+        const size_t u = 2 * (size_t)nb.at(cx(i), cy(i), cz(i));
+        const double aw = (double)rho2[u], ao = (double)rho2[u + 1];
+        val = (aw / (aw + ao) - mc.s_min) / span;
+      }
+      if (cx(i)) gS[0] += gw(i) * cx(i) * val;
+      if (cy(i)) gS[1] += gw(i) * cy(i) * val;
+      if (cz(i)) gS[2] += gw(i) * cz(i) * val;
+    }
+    const T *tb = tab + (size_t)ptype[v] * 3 * TABLE_N;
+    const double t = S * (double)(TABLE_N - 1);
+    int k = (int)floor(t);
+    k = k > TABLE_N - 2 ? TABLE_N - 2 : (k < 0 ? 0 : k);
+    const double fr = t - (double)k;
+    auto lookup = [&](const T *c, double &val, double &slope) {
+      const double lo = (double)c[k], hi = (double)c[k + 1];
+      val = lo + fr * (hi - lo);
+      slope = (hi - lo) * (double)(TABLE_N - 1);
+    };
+    lookup(tb, Pct, dPct);
+    lookup(tb + TABLE_N, Krw, dKrw);
+    lookup(tb + 2 * TABLE_N, Kro, dKro);
+    sj = (double)sJ[v];
+    Pc = sj * Pct;
+    for (int a = 0; a < 2; ++a)
+      for (int d = 0; d < 3; ++d) Fex[a][d] += -Pc * (rho[a] * irt) * gS[d];
+    kw = Krw > mc.kr_min ? Krw : mc.kr_min;
+    ko = Kro > mc.kr_min ? Kro : mc.kr_min;
+    const double cw = S > 0.0 ? rt * S * mc.nu[0] / kw : 0.0;
+    const double co = 1.0 - S > 0.0 ? rt * (1.0 - S) * mc.nu[1] / ko : 0.0;
+    cR = cw + co;
+  }
+  // resistance
+  double bvec[3], u[3], Ru[3], K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+                                  Ai[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, wv[3] = {0, 0, 0};
+  for (int d = 0; d < 3; ++d) bvec[d] = m[0][d] + m[1][d] + h * (Fex[0][d] + Fex[1][d]);
+  double k0 = 1.0, Rs = 0.0, den = rt;
+  if (tens) {
+    K[0][0] = (double)Kinv[v];
+    K[1][1] = (double)Kinv[N + v];
+    K[2][2] = (double)Kinv[2 * N + v];
+    K[0][1] = K[1][0] = (double)Kinv[3 * N + v];
+    K[0][2] = K[2][0] = (double)Kinv[4 * N + v];
+    K[1][2] = K[2][1] = (double)Kinv[5 * N + v];
+    const double hc = h * cR;
+    const double a00 = rt + hc * K[0][0], a11 = rt + hc * K[1][1], a22 = rt + hc * K[2][2];
+    const double a01 = hc * K[0][1], a02 = hc * K[0][2], a12 = hc * K[1][2];
+    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22,
+                 c02 = a01 * a12 - a02 * a11;
+    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12,
+                 c22 = a00 * a11 - a01 * a01;
+    const double idet = 1.0 / (a00 * c00 + a01 * c01 + a02 * c02);
+    Ai[0][0] = c00 * idet; Ai[1][1] = c11 * idet; Ai[2][2] = c22 * idet;
+    Ai[0][1] = Ai[1][0] = c01 * idet;
+    Ai[0][2] = Ai[2][0] = c02 * idet;
+    Ai[1][2] = Ai[2][1] = c12 * idet;
+    for (int i = 0; i < 3; ++i) u[i] = Ai[i][0] * bvec[0] + Ai[i][1] * bvec[1] + Ai[i][2] * bvec[2];
+    for (int i = 0; i < 3; ++i) {
+      wv[i] = K[i][0] * u[0] + K[i][1] * u[1] + K[i][2] * u[2];
+      Ru[i] = cR * wv[i];
+    }
+  } else {
+    if (gray) {
+      k0 = (double)K0[v];
+      Rs = cR / k0;
+    }
+    den = rt + h * Rs;
+    for (int d = 0; d < 3; ++d) {
+      u[d] = bvec[d] / den;
+      Ru[d] = Rs * u[d];
+    }
+  }
+  double F[2][3];
+  for (int a = 0; a < 2; ++a)
+    for (int d = 0; d < 3; ++d) F[a][d] = Fex[a][d] - (rho[a] * irt) * Ru[d];
+  const double om[2] = {mc.omega[0], mc.omega[1]};
+  const double D = om[0] * rho[0] + om[1] * rho[1];
+  double up[3];
+  for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) / D;
+  const double usq = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
+
+  // reverse sweep
+  double rb[2] = {0, 0}, mb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Pb[2][6];
+  double upb[3] = {0, 0, 0}, usqb = 0, Fb[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a];
+    const double ra = rho[a], ir2 = 0.5 / ra;
+    double ua[3];
+    for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * ir2;
+    const double *Mv = M2[a];
+    const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
+    double Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0};
+    rb[a] += e * (1.0 - usq / (2 * cs2)) * L0[a];
+    usqb += -e * ra / (2 * cs2) * L0[a];
+    const double uFb = -L0[a] / cs2;
+    double pl = 0, pMp = 0;
+    for (int d = 0; d < 3; ++d) pl += up[d] * L1[a][d];
+    rb[a] += e * pl / cs2;
+    for (int d = 0; d < 3; ++d) {
+      upb[d] += e * ra * L1[a][d] / cs2;
+      Fbar[d] += L1[a][d] / cs2;
+    }
+    for (int i = 0; i < 3; ++i) {
+      const double Mu = Mm[i][0] * up[0] + Mm[i][1] * up[1] + Mm[i][2] * up[2];
+      pMp += up[i] * Mu;
+      upb[i] += e * ra * Mu / cs4;
+      uab[i] += (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) / cs4;
+      Fbar[i] += (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) / cs4;
+    }
+    rb[a] += e * pMp / (2 * cs4);
+    for (int d = 0; d < 6; ++d) Pb[a][d] = 0;
+    if (REG) {
+      const double c = keep / (2 * cs4), dd = -keep / (2 * cs2) * L0[a];
+      double B[3][3];
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) B[i][j] = c * Mm[i][j] + (i == j ? dd : 0.0);
+      Pb[a][0] = B[0][0]; Pb[a][1] = B[1][1]; Pb[a][2] = B[2][2];
+      Pb[a][3] = B[0][1]; Pb[a][4] = B[0][2]; Pb[a][5] = B[1][2];
+      double pBp = 0;
+      for (int i = 0; i < 3; ++i) {
+        const double Bu = B[i][0] * up[0] + B[i][1] * up[1] + B[i][2] * up[2];
+        pBp += up[i] * Bu;
+        upb[i] += -2.0 * ra * Bu;
+      }
+      rb[a] += -cs2 * (B[0][0] + B[1][1] + B[2][2]) - pBp;
+      // first-order part j^a = m^a - rho^a u'
+      double pj = 0;
+      for (int d = 0; d < 3; ++d) {
+        const double jb = keep * L1[a][d] / cs2;
+        mb[a][d] += jb;
+        pj += up[d] * jb;
+        upb[d] += -ra * jb;
+      }
+      rb[a] += -pj;
+    }
+    double abF = 0;
+    for (int d = 0; d < 3; ++d) {
+      uab[d] += F[a][d] * uFb;
+      Fbar[d] += ua[d] * uFb;
+      upb[d] += uab[d];
+      Fbar[d] += uab[d] * ir2;
+      abF += uab[d] * F[a][d];
+    }
+    rb[a] += -abF * ir2 / ra;
+    for (int d = 0; d < 3; ++d) Fb[a][d] = Fbar[d];
+  }
+  for (int d = 0; d < 3; ++d) upb[d] += 2.0 * up[d] * usqb;
+  {
+    double pu = 0;
+    for (int d = 0; d < 3; ++d) pu += upb[d] * up[d];
+    for (int a = 0; a < 2; ++a) {
+      for (int d = 0; d < 3; ++d) mb[a][d] += om[a] * upb[d] / D;
+      rb[a] += -om[a] * pu / D;
+    }
+  }
+  // F^a = F_ex^a - (rho^a / rho_t) R u
+  double Rub[3] = {0, 0, 0}, rtb = 0, Fexb[2][3];
+  for (int a = 0; a < 2; ++a) {
+    double FR = 0;
+    for (int d = 0; d < 3; ++d) {
+      Fexb[a][d] = Fb[a][d];
+      Rub[d] += -(rho[a] * irt) * Fb[a][d];
+      FR += Fb[a][d] * Ru[d];
+    }
+    rb[a] += -FR * irt;
+    rtb += rho[a] * FR * irt * irt;
+  }
+  double cRb = 0, bb[3];
+  if (tens) {
+    cRb = Rub[0] * wv[0] + Rub[1] * wv[1] + Rub[2] * wv[2];
+    double wb[3], ub[3], Kb[3][3];
+    for (int i = 0; i < 3; ++i) wb[i] = cR * Rub[i];
+    for (int i = 0; i < 3; ++i) {
+      ub[i] = K[i][0] * wb[0] + K[i][1] * wb[1] + K[i][2] * wb[2];
+      for (int j = 0; j < 3; ++j) Kb[i][j] = wb[i] * u[j];
+    }
+    for (int i = 0; i < 3; ++i) bb[i] = Ai[i][0] * ub[0] + Ai[i][1] * ub[1] + Ai[i][2] * ub[2];
+    double AK = 0;
+    for (int i = 0; i < 3; ++i)
+      for (int j = 0; j < 3; ++j) {
+        const double Ab = -bb[i] * u[j];
+        AK += Ab * K[i][j];
+        Kb[i][j] += h * cR * Ab;
+        if (i == j) rtb += Ab;
+      }
+    cRb += h * AK;
+    gk[v] += Kb[0][0];
+    gk[N + v] += Kb[1][1];
+    gk[2 * N + v] += Kb[2][2];
+    gk[3 * N + v] += Kb[0][1] + Kb[1][0];
+    gk[4 * N + v] += Kb[0][2] + Kb[2][0];
+    gk[5 * N + v] += Kb[1][2] + Kb[2][1];
+  } else {
+    double Rsb = 0, ub[3];
+    for (int d = 0; d < 3; ++d) {
+      Rsb += u[d] * Rub[d];
+      ub[d] = Rs * Rub[d];
+    }
+    const double idn = 1.0 / den;
+    double denb = 0;
+    for (int d = 0; d < 3; ++d) {
+      bb[d] = ub[d] * idn;
+      denb += -ub[d] * u[d] * idn;
+    }
+    rtb += denb;
+    Rsb += h * denb;
+    if (gray) {
+      cRb = Rsb / k0;
+      gk[v] += -Rsb * cR / (k0 * k0);
+    }
+  }
+  for (int a = 0; a < 2; ++a)
+    for (int d = 0; d < 3; ++d) {
+      mb[a][d] += bb[d];
+      Fexb[a][d] += h * bb[d];
+    }
+  // F_ex: body force, pseudo-potential force (own part; the neighbours'
+  // part is stashed), capillary term
+  double gSb[3] = {0, 0, 0}, Pcb = 0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int b = 1 - a;
+    double gF = 0, aF = 0, gFS = 0;
+    for (int d = 0; d < 3; ++d) {
+      gF += mc.g[a][d] * Fexb[a][d];
+      aF += acc[a][d] * Fexb[a][d];
+      gFS += gS[d] * Fexb[a][d];
+    }
+    rb[a] += gF - mc.G * aF;
+    const double accb[3] = {-mc.G * rho[a] * Fexb[a][0], -mc.G * rho[a] * Fexb[a][1],
+                            -mc.G * rho[a] * Fexb[a][2]};
+    for (int d = 0; d < 3; ++d) stash[(size_t)(3 * a + d) * N + v] = (T)accb[d];
+    if (rho[b] + mc.wall_dpsi[b] > 0.0) {  // solid links read max(rho^b + dpsi^b, 0)
+      double wsum = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (!((mk >> i) & 1u)) continue;
+        wsum += wq(i) * (cx(i) * accb[0] + cy(i) * accb[1] + cz(i) * accb[2]);
+      }
+      rb[b] += wsum;
+    }
+    if (gray) {
+      Pcb += -(rho[a] * irt) * gFS;
+      rb[a] += -Pc * gFS * irt;
+      rtb += Pc * rho[a] * gFS * irt * irt;
+      for (int d = 0; d < 3; ++d) gSb[d] += -Pc * (rho[a] * irt) * Fexb[a][d];
+    }
+  }
+  if (gray) {
+    for (int d = 0; d < 3; ++d) stash[(size_t)(6 + d) * N + v] = (T)gSb[d];
+    // c_R
+    double Sb = 0;
+    if (S > 0.0) {
+      rtb += cRb * S * mc.nu[0] / kw;
+      Sb += cRb * rt * mc.nu[0] / kw;
+      if (Krw > mc.kr_min) Sb += -cRb * rt * S * mc.nu[0] / (kw * kw) * dKrw;
+    }
+    if (1.0 - S > 0.0) {
+      rtb += cRb * (1.0 - S) * mc.nu[1] / ko;
+      Sb += -cRb * rt * mc.nu[1] / ko;
+      if (Kro > mc.kr_min) Sb += -cRb * rt * (1.0 - S) * mc.nu[1] / (ko * ko) * dKro;
+    }
+    // P_c = s_J P_c(S)
+    gsj[v] += Pcb * Pct;
+    Sb += Pcb * sj * dPct;
+    if (Sraw > 0.0 && Sraw < 1.0) {
+      const double tt = tw + to, sb = Sb / span;
+      rb[0] += sb * to / (tt * tt);
+      rb[1] += -sb * tw / (tt * tt);
+    }
+    // grad S_hat: the links to solid neighbours read this voxel's S_hat
+    double shb = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (!((mk >> i) & 1u)) continue;
+      shb += gw(i) * (cx(i) * gSb[0] + cy(i) * gSb[1] + cz(i) * gSb[2]);
+    }
+    rb[0] += shb / span * rho[1] * irt * irt;
+    rb[1] += -shb / span * rho[0] * irt * irt;
+  }
+  rb[0] += rtb;
+  rb[1] += rtb;
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    T *lo = lout + (size_t)a * Q * N;
+#pragma unroll
+    for (int k = 0; k < Q; ++k) {
+      double l = rb[a];
+      if (cx(k)) l += cx(k) * mb[a][0];
+      if (cy(k)) l += cy(k) * mb[a][1];
+      if (cz(k)) l += cz(k) * mb[a][2];
+      if (REG) {
+        if (cx(k)) l += Pb[a][0];
+        if (cy(k)) l += Pb[a][1];
+        if (cz(k)) l += Pb[a][2];
+        if (cx(k) && cy(k)) l += (2 * cx(k) * cy(k)) * Pb[a][3];
+        if (cx(k) && cz(k)) l += (2 * cx(k) * cz(k)) * Pb[a][4];
+        if (cy(k) && cz(k)) l += (2 * cy(k) * cz(k)) * Pb[a][5];
+      } else {
+        l += (1.0 - om[a]) * lp[REG ? 0 : a][REG ? 0 : k];
+      }
+      lo[(size_t)k * N + v] = (T)l;
+    }
+  }
+}
+
+// The neighbours' part of the force's reverse: dL/drho^b(y) from the
+// pseudo-potential reads of every fluid voxel x = y - c_i, and dL/drho^w,o(y)
+// through S_hat(y) from the saturation-gradient reads of gray voxels.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
+                                                 const T *__restrict__ rho2,
+                                                 const T *__restrict__ stash,
                                                  const uint32_t *__restrict__ mask,
-                                                 const double *__restrict__ tabs, long long N,
-                                                 double *__restrict__ out) {
+                                                 T *__restrict__ rnl) {
+  const long long N = mc.N;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;  // stays zero
+  const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+  double r0 = 0, r1 = 0, shb = 0;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const size_t x = (size_t)nb.at(-cx(i), -cy(i), -cz(i));
+    auto dot = [&](int c0) {
+      double s = 0;
+      if (cx(i)) s += cx(i) * (double)stash[(size_t)c0 * N + x];
+      if (cy(i)) s += cy(i) * (double)stash[(size_t)(c0 + 1) * N + x];
+      if (cz(i)) s += cz(i) * (double)stash[(size_t)(c0 + 2) * N + x];
+      return s;
+    };
+    r1 += wq(i) * dot(0);  // water's force reads psi^o
+    r0 += wq(i) * dot(3);  // oil's force reads psi^w
+    shb += gw(i) * dot(6);
+  }
+  const double aw = (double)rho2[2 * v], ao = (double)rho2[2 * v + 1];
+  const double tt = aw + ao, span = 1.0 / mc.inv_span;
+  rnl[2 * v] = (T)(r0 + shb / span * ao / (tt * tt));
+  rnl[2 * v + 1] = (T)(r1 - shb / span * aw / (tt * tt));
+}
+
+// dL/dphi on gray voxels: dL/dK0 times the K0(phi) table's slope on the
+// lookup's cell, plus (two components) dL/ds_J through
+// s_J = sqrt((K0_ref / phi_ref) phi / K0(phi)), plus (tensor) the transposed
+// smoothing's result gbase (the porosity field the smoothing read is phi
+// there).  gbase and gsj may be null.
+__global__ __launch_bounds__(256) void k_adj_phi2(const double *__restrict__ gbase,
+                                                  const double *__restrict__ gK0,
+                                                  const double *__restrict__ gsj,
+                                                  const double *__restrict__ phi,
+                                                  const uint8_t *__restrict__ pt,
+                                                  const uint32_t *__restrict__ mask,
+                                                  const double *__restrict__ tabs,
+                                                  const double *__restrict__ tabmeta, long long N,
+                                                  double *__restrict__ out) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   if (((mask[v] >> CLASS_SHIFT) & 3u) != GRAY_CODE) {
     out[v] = 0.0;
     return;
   }
-  const double *tab = tabs + (size_t)pt[v] * 4 * TABLE_N;  // curve 0 of each type is K0
-  const double t = phi[v] * (double)(TABLE_N - 1);
+  const int ty = pt[v];
+  const double *tab = tabs + (size_t)ty * 4 * TABLE_N;
+  const double ph = phi[v];
+  const double t = ph * (double)(TABLE_N - 1);
   int k = (int)floor(t);
   k = k > TABLE_N - 2 ? TABLE_N - 2 : (k < 0 ? 0 : k);
-  out[v] = gK0[v] * (tab[k + 1] - tab[k]) * (double)(TABLE_N - 1);
+  const double slope = (tab[k + 1] - tab[k]) * (double)(TABLE_N - 1);
+  const double k0 = lerp_tab<double>(tab, ph);
+  const double phi_ref = tabmeta[ty * 8 + 0];
+  const double k0ref = lerp_tab<double>(tab, phi_ref);
+  const double sj = sqrt((k0ref / phi_ref) / (k0 / ph));
+  const double dsj = 0.5 * sj * (1.0 / ph - slope / k0);
+  out[v] = (gbase ? gbase[v] : 0.0) + gK0[v] * slope + (gsj ? gsj[v] * dsj : 0.0);
 }
 
 // ---------------------------------------------------------------------------
@@ -487,29 +962,6 @@ __global__ __launch_bounds__(256) void k_adj_hess_t(const double *__restrict__ h
   out[v] = acc;
 }
 
-// dL/dphi on gray voxels with the tensor: the transposed smoothing's result
-// (the porosity field the smoothing read is phi there) plus dL/dK0 times the
-// K0 table's slope.
-__global__ __launch_bounds__(256) void k_adj_phi_tensor(const double *__restrict__ gbase,
-                                                        const double *__restrict__ gK0,
-                                                        const double *__restrict__ phi,
-                                                        const uint8_t *__restrict__ pt,
-                                                        const uint32_t *__restrict__ mask,
-                                                        const double *__restrict__ tabs,
-                                                        long long N, double *__restrict__ out) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= N) return;
-  if (((mask[v] >> CLASS_SHIFT) & 3u) != GRAY_CODE) {
-    out[v] = 0.0;
-    return;
-  }
-  const double *tab = tabs + (size_t)pt[v] * 4 * TABLE_N;
-  const double t = phi[v] * (double)(TABLE_N - 1);
-  int k = (int)floor(t);
-  k = k > TABLE_N - 2 ? TABLE_N - 2 : (k < 0 ? 0 : k);
-  out[v] = gbase[v] + gK0[v] * (tab[k + 1] - tab[k]) * (double)(TABLE_N - 1);
-}
-
 }  // namespace adj
 }  // namespace lbm
 
@@ -525,34 +977,105 @@ void launch_adj_step_t(lbm_handle *h, const T *post, const T *lin, T *lout, doub
                      lin, lout, s.mask, s.K0, (const T *)s.Kinv, gk, a);
 }
 
-template <typename T>
-void launch_adj_step(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk,
-                     double a) {
-  Timed tm(h, K_ADJ);
-  const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
-  if (h->p.tensor) {
-    if (reg) launch_adj_step_t<T, true, true>(h, post, lin, lout, gk, a);
-    else launch_adj_step_t<T, false, true>(h, post, lin, lout, gk, a);
-  } else {
-    if (reg) launch_adj_step_t<T, true, false>(h, post, lin, lout, gk, a);
-    else launch_adj_step_t<T, false, false>(h, post, lin, lout, gk, a);
-  }
+template <typename T, bool REG, bool TENS>
+void launch_adj_step2_t(lbm_handle *h, const T *post, const T *dens, const T *lin,
+                        const T *rnl, T *lout, T *stash, double *gk, double *gsj, double a) {
+  DevState<T> &s = state<T>(h);
+  const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
+  hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS>), dim3(nb), dim3(256), 0, h->st, h->mc,
+                     post, dens, (const T *)s.r, lin, rnl, lout, stash, s.mask, s.K0,
+                     (const T *)s.Kinv, s.sJ, s.ptype, s.tab, gk, gsj, a);
 }
 
-// dL/dK^-1 (tensor runs) back to dL/dK0 and dL/dphi: the smoothed porosity is
-// rebuilt with the set-up's own kernels, the axes kernel turns dL/dK^-1 into
-// dL/dH, dL/dg and dL/dK0, then the transposed stencils and the transposed
-// smoothing (a symmetric periodic convolution per axis, applied in the reverse
-// axis order) carry dL/dH and dL/dg back to the porosity.
+// One reverse step: one component, or (two components) the density pass of
+// the level, the local reverse and the gather of the neighbours' part.
 template <typename T>
-int tensor_gradient(lbm_handle *h, const double *gKi, double *gK0, double *gphi,
+void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk, double a,
+                    T *dens, const T *rnl_in, T *rnl_out, T *stash, double *gsj) {
+  DevState<T> &s = state<T>(h);
+  const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
+  const bool ten = h->p.tensor != 0;
+  if (h->p.ncomp == 1) {
+    Timed tm(h, K_ADJ);
+    if (ten) {
+      if (reg) launch_adj_step_t<T, true, true>(h, post, lin, lout, gk, a);
+      else launch_adj_step_t<T, false, true>(h, post, lin, lout, gk, a);
+    } else {
+      if (reg) launch_adj_step_t<T, true, false>(h, post, lin, lout, gk, a);
+      else launch_adj_step_t<T, false, false>(h, post, lin, lout, gk, a);
+    }
+    return;
+  }
+  {
+    Timed tm(h, K_AUX);
+    hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE, false>), dim3(blocks(h->N)), dim3(256), 0,
+                       h->st, (const void *)post, dens, (const T *)nullptr, (const T *)nullptr,
+                       s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
+  }
+  Timed tm(h, K_ADJ);
+  if (ten) {
+    if (reg) launch_adj_step2_t<T, true, true>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+    else launch_adj_step2_t<T, false, true>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+  } else {
+    if (reg) launch_adj_step2_t<T, true, false>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+    else launch_adj_step2_t<T, false, false>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+  }
+  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc, dens,
+                     stash, s.mask, rnl_out);
+}
+
+// The fused step from fin into fout (two components: after the density pass
+// of fin into the handle's density buffer).
+template <typename T>
+void launch_recompute(lbm_handle *h, const T *fin, T *fout) {
+  DevState<T> &s = state<T>(h);
+  const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
+  if (h->p.ncomp == 2) {
+    {
+      Timed tm(h, K_AUX);
+      hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE, false>), dim3(blocks(h->N)), dim3(256), 0,
+                         h->st, (const void *)fin, s.rho2, (const T *)nullptr, (const T *)nullptr,
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
+    }
+    Timed tm(h, K_STEP);
+    if (reg) launch_tiled<T, 2, true>(h, fin, fout);
+    else launch_tiled<T, 2, false>(h, fin, fout);
+    return;
+  }
+  Timed tm(h, K_STEP);
+  if (reg) launch_tiled<T, 1, true>(h, fin, fout);
+  else launch_tiled<T, 1, false>(h, fin, fout);
+}
+
+// 1 where the residual amounts or side flags of two copies differ (block
+// partials, summed by k_finalize): residual events happened in between.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_diff(const T *__restrict__ r0,
+                                                  const T *__restrict__ r1,
+                                                  const uint8_t *__restrict__ s0,
+                                                  const uint8_t *__restrict__ s1, long long N,
+                                                  double *__restrict__ partial) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  double val[1] = {0.0};
+  if (v < N)
+    val[0] = (r0[v] != r1[v] || r0[N + v] != r1[N + v] || s0[v] != s1[v]) ? 1.0 : 0.0;
+  block_sum<1>(val, partial + blockIdx.x, false);
+}
+
+// dL/dK^-1 (tensor runs) back to dL/dK0 and to the porosity through the
+// set-up: the smoothed porosity is rebuilt with the set-up's own kernels, the
+// axes kernel turns dL/dK^-1 into dL/dH, dL/dg and dL/dK0, then the transposed
+// stencils and the transposed smoothing (a symmetric periodic convolution per
+// axis, applied in the reverse axis order) carry dL/dH and dL/dg back to the
+// porosity field (gbase).
+template <typename T>
+int tensor_gradient(lbm_handle *h, const double *gKi, double *gK0, double *gbase,
                     std::vector<void *> &tmp) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
   const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
   bool ok = true;
   double *sm1 = alloc_into<double>(h, tmp, (size_t)N, &ok);
-  double *sm2 = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *hb = alloc_into<double>(h, tmp, (size_t)9 * N, &ok);
   double *wts = alloc_into<double>(h, tmp, 32, &ok);
   if (!ok) return set_err(h, LBM_E_NOMEM, "device allocation failed in adjoint_flux");
@@ -569,6 +1092,7 @@ int tensor_gradient(lbm_handle *h, const double *gKi, double *gK0, double *gphi,
                      "copy smoothing weights");
   if (rc != LBM_OK) return rc;
   const dim3 gr(blocks(N)), bl(256);
+  double *sm2 = gbase;
   Timed tm(h, K_OTHER);
   hipLaunchKernelGGL(k_base_phi, gr, bl, 0, h->st, s.mask, h->geom_phi, sm1, N);
   hipLaunchKernelGGL(k_smooth, gr, bl, 0, h->st, sm1, sm2, nx, ny, nz, N, 0, R, wts);
@@ -581,16 +1105,7 @@ int tensor_gradient(lbm_handle *h, const double *gKi, double *gK0, double *gphi,
   hipLaunchKernelGGL(k_smooth, gr, bl, 0, h->st, sm1, sm2, nx, ny, nz, N, 2, R, wts);
   hipLaunchKernelGGL(k_smooth, gr, bl, 0, h->st, sm2, sm1, nx, ny, nz, N, 1, R, wts);
   hipLaunchKernelGGL(k_smooth, gr, bl, 0, h->st, sm1, sm2, nx, ny, nz, N, 0, R, wts);
-  hipLaunchKernelGGL(adj::k_adj_phi_tensor, gr, bl, 0, h->st, sm2, gK0, h->geom_phi, s.ptype,
-                     s.mask, h->geom_tabs, N, gphi);
   return hip_check(h, hipGetLastError(), "tensor gradient kernels");
-}
-
-template <typename T>
-void launch_recompute(lbm_handle *h, const T *fin, T *fout) {
-  Timed tm(h, K_STEP);
-  if (h->p.collision == LBM_COLL_REGULARIZED) launch_tiled<T, 1, true>(h, fin, fout);
-  else launch_tiled<T, 1, false>(h, fin, fout);
 }
 
 // Forward sweep: nsteps ordinary steps of the handle, the stored set copied
@@ -604,20 +1119,34 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
               double *gK0_out, double *gphi_out) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
-  const size_t QN = (size_t)Q * N;
+  const int nc = h->p.ncomp;
+  const size_t SN = (size_t)nc * Q * N;  // one population set
   if (K <= 0) K = std::max<int64_t>(1, (int64_t)std::ceil(std::sqrt((double)n)));
   K = std::min<int64_t>(K, n);
   const int64_t nseg = (n + K - 1) / K;
   std::vector<void *> tmp;
   bool ok = true;
-  T *ck = alloc_into<T>(h, tmp, (size_t)nseg * QN, &ok);
-  T *ring = K > 1 ? alloc_into<T>(h, tmp, (size_t)(K - 1) * QN, &ok) : nullptr;
-  T *lam = alloc_into<T>(h, tmp, 2 * QN, &ok);
+  T *ck = alloc_into<T>(h, tmp, (size_t)nseg * SN, &ok);
+  T *ring = K > 1 ? alloc_into<T>(h, tmp, (size_t)(K - 1) * SN, &ok) : nullptr;
+  T *lam = alloc_into<T>(h, tmp, 2 * SN, &ok);
   const size_t ngk = h->p.tensor ? (size_t)6 * N : (size_t)N;  // dL/dK^-1 or dL/dK0
   double *gk = alloc_into<double>(h, tmp, ngk, &ok);
   double *gk0 = h->p.tensor ? alloc_into<double>(h, tmp, (size_t)N, &ok) : gk;
+  double *gbase = h->p.tensor ? alloc_into<double>(h, tmp, (size_t)N, &ok) : nullptr;
   double *gp = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *qh = alloc_into<double>(h, tmp, (size_t)2 * n, &ok);
+  T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *r0 = nullptr;
+  double *gsj = nullptr, *flag = nullptr;
+  uint8_t *side0 = nullptr;
+  if (nc == 2) {
+    dens = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
+    stash = alloc_into<T>(h, tmp, (size_t)9 * N, &ok);
+    rnl = alloc_into<T>(h, tmp, (size_t)4 * N, &ok);
+    r0 = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
+    side0 = alloc_into<uint8_t>(h, tmp, (size_t)N, &ok);
+    gsj = alloc_into<double>(h, tmp, (size_t)N, &ok);
+    flag = alloc_into<double>(h, tmp, 1, &ok);
+  }
   auto finish = [&](int rc) {
     (void)hipStreamSynchronize(h->st);
     for (void *p : tmp) dev_free(h, p);
@@ -626,25 +1155,37 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   if (!ok) return finish(set_err(h, LBM_E_NOMEM, "device allocation failed in adjoint_flux"));
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
   int rc = LBM_OK;
+  if (nc == 2) {
+    rc = hip_check(h, hipMemcpyAsync(r0, s.r, (size_t)2 * N * sizeof(T), hipMemcpyDeviceToDevice,
+                                     h->st),
+                   "copy residual amounts");
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemcpyAsync(side0, s.side, (size_t)N, hipMemcpyDeviceToDevice, h->st),
+                     "copy side flags");
+  }
   // forward sweep.  The last segment keeps its levels: each of its steps but
   // the last writes its new set straight into the ring (the handle's buffer
   // pointers are swapped for it and put back at the end), so that segment is
   // not recomputed, and checkpoint_every = nsteps recomputes nothing.
   T *const own0 = s.f[0], *const own1 = s.f[1];
   for (int64_t sg = 0; sg < nseg && rc == LBM_OK; ++sg) {
-    rc = hip_check(h, hipMemcpyAsync(ck + sg * QN, s.f[h->cur], QN * sizeof(T),
+    rc = hip_check(h, hipMemcpyAsync(ck + sg * SN, s.f[h->cur], SN * sizeof(T),
                                      hipMemcpyDeviceToDevice, h->st),
                    "checkpoint copy");
     const int64_t m = std::min<int64_t>(K, n - sg * K);
     const bool keep = sg == nseg - 1;
     T *const spare = s.f[1 - h->cur];
     for (int64_t k = 0; k < m && rc == LBM_OK; ++k) {
-      if (keep) s.f[1 - h->cur] = k < m - 1 ? ring + k * QN : spare;
+      if (keep) s.f[1 - h->cur] = k < m - 1 ? ring + k * SN : spare;
       rc = step_t<T>(h, 1);
       if (rc != LBM_OK) break;
       Timed tm(h, K_OTHER);
-      hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                         s.mask, s.partial);
+      if (nc == 2)
+        hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask, s.partial);
+      else
+        hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                           s.mask, s.partial);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0,
                          qh + 2 * (sg * K + k), 0);
     }
@@ -658,29 +1199,59 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       }
     }
   }
+  // two components: the reverse sweep holds for a horizon without residual
+  // events (switches with no derivative)
+  if (rc == LBM_OK && nc == 2) {
+    const unsigned nbk = blocks(N);
+    hipLaunchKernelGGL((k_adj_diff<T>), dim3(nbk), dim3(256), 0, h->st, r0, (const T *)s.r, side0,
+                       (const uint8_t *)s.side, N, s.partial);
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)nbk, 1, 0, flag,
+                       0);
+    double changed = 0.0;
+    rc = hip_check(h, hipMemcpyAsync(&changed, flag, sizeof(double), hipMemcpyDeviceToHost, h->st),
+                   "copy event flag");
+    if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "event check");
+    if (rc == LBM_OK && changed != 0.0)
+      rc = set_err(h, LBM_E_UNSUPPORTED,
+                   "adjoint_flux: residual events within the horizon (" +
+                       std::to_string((long long)changed) +
+                       " voxels); the handle has advanced the steps");
+  }
   // reverse sweep; the loss does not depend on the set after the last step
   if (rc == LBM_OK)
-    rc = hip_check(h, hipMemsetAsync(lam, 0, 2 * QN * sizeof(T), h->st), "clear adjoint");
+    rc = hip_check(h, hipMemsetAsync(lam, 0, 2 * SN * sizeof(T), h->st), "clear adjoint");
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemsetAsync(gk, 0, ngk * sizeof(double), h->st), "clear gradient");
+  if (rc == LBM_OK && nc == 2) {
+    rc = hip_check(h, hipMemsetAsync(rnl, 0, (size_t)4 * N * sizeof(T), h->st), "clear");
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemsetAsync(stash, 0, (size_t)9 * N * sizeof(T), h->st), "clear");
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemsetAsync(gsj, 0, (size_t)N * sizeof(double), h->st), "clear");
+  }
   int cl = 0;
   for (int64_t sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
     const int64_t m = std::min<int64_t>(K, n - sg * K);
-    auto level = [&](int64_t k) -> T * { return k == 0 ? ck + sg * QN : ring + (k - 1) * QN; };
+    auto level = [&](int64_t k) -> T * { return k == 0 ? ck + sg * SN : ring + (k - 1) * SN; };
     if (sg < nseg - 1)
       for (int64_t k = 1; k < m; ++k) launch_recompute<T>(h, level(k - 1), level(k));
     for (int64_t k = m - 1; k >= 0; --k) {
-      launch_adj_step<T>(h, level(k), lam + cl * QN, lam + (1 - cl) * QN, gk, dLdQ[sg * K + k]);
+      T *rin = rnl ? rnl + (size_t)cl * 2 * N : nullptr;
+      T *rout = rnl ? rnl + (size_t)(1 - cl) * 2 * N : nullptr;
+      launch_reverse<T>(h, level(k), lam + cl * SN, lam + (1 - cl) * SN, gk, dLdQ[sg * K + k],
+                        dens, rin, rout, stash, gsj);
       cl = 1 - cl;
     }
     rc = hip_check(h, hipGetLastError(), "adjoint launches");
   }
-  if (rc == LBM_OK && h->p.tensor) {
-    rc = tensor_gradient<T>(h, gk, gk0, gp, tmp);
-  } else if (rc == LBM_OK) {
+  // the recomputation used the handle's density buffer
+  h->rho2_valid = false;
+  if (rc == LBM_OK && h->p.tensor) rc = tensor_gradient<T>(h, gk, gk0, gbase, tmp);
+  if (rc == LBM_OK) {
     Timed tm(h, K_OTHER);
-    hipLaunchKernelGGL(adj::k_adj_phi, dim3(blocks(N)), dim3(256), 0, h->st, gk, h->geom_phi,
-                       s.ptype, s.mask, h->geom_tabs, N, gp);
+    hipLaunchKernelGGL(adj::k_adj_phi2, dim3(blocks(N)), dim3(256), 0, h->st,
+                       (const double *)gbase, (const double *)gk0, (const double *)gsj,
+                       h->geom_phi, s.ptype, s.mask, h->geom_tabs, h->geom_meta, N, gp);
     rc = hip_check(h, hipGetLastError(), "gradient kernel");
   }
   std::vector<double> qv;
@@ -715,9 +1286,10 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
   for (int64_t k = 0; k < nsteps; ++k)
     if (!std::isfinite(dL_dQ[k]))
       return set_err(h, LBM_E_INVAL, "adjoint_flux: non-finite dL_dQ");
-  if (h->p.ncomp != 1 || h->mc.open_x || h->sk != SK_NATIVE)
+  if (h->mc.open_x || h->sk != SK_NATIVE || (h->p.ncomp == 2 && h->p.kappa != 0.0))
     return set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: one component, periodic x faces and native storage only");
+                   "adjoint_flux: periodic x faces, native storage and (two components) "
+                   "kappa = 0 only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
   return h->es == 8 ? adjoint_t<double>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi)
                     : adjoint_t<float>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi);

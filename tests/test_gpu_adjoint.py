@@ -330,3 +330,64 @@ def test_tensor_gradient_against_gpu_finite_differences():
         fd = (Ls[0] - Ls[1]) / (2 * eps)
         print(f"voxel {v}: adjoint {g[v]:.6e} fd {fd:.6e}")
         assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
+
+
+def two_gpu_case(collision="regularized", resistance="implicit", tensor=False):
+    from test_oracle_adjoint import two_case
+    p, cls, phi, pt, tabs, rw, ro = two_case(collision, resistance)
+    p.tensor = tensor
+    return p, cls, phi, pt, tabs, rw, ro
+
+
+@pytest.mark.parametrize("collision,resistance,tensor", [("regularized", "implicit", False),
+                                                         ("bgk", "semi_implicit", False),
+                                                         ("regularized", "implicit", True)])
+def test_two_component_adjoint_matches_oracle(collision, resistance, tensor):
+    """20 x 8 x 6, water and oil, pore / solid / gray voxels with two pore
+    types, kappa = 0, 10 steps without residual events: dL/dphi through K0 (or
+    K^-1) in the resistance and s_J in the capillary term, fp64."""
+    import paper_2512_21696_amd as L
+    announce(f"two-component adjoint 20x8x6 fp64 {collision} {resistance} tensor={tensor}")
+    p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision, resistance, tensor)
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rw, ro)
+    qo, go, _ = A.flux_gradient2(p, cls, phi, pt, tabs, o.f.copy(), o.r.copy(), steps, a)
+    lb = L.lbm_create(p)
+    lb.set_geometry(cls, phi, pt, tabs)
+    lb.init_fluid(rw, ro)
+    out = lb.adjoint_flux(steps, a, checkpoint_every=4)
+    lb.destroy()
+    gray = cls == 2
+    assert np.count_nonzero(go[gray]) > 0.5 * gray.sum()
+    assert np.abs(out["Q"] - qo).max() < 1e-13
+    e = norm_err(out["dL_dphi"], go)
+    print(f"two-component dL/dphi normalised error {e:.2e}")
+    assert e < 1e-9
+
+
+def test_two_component_adjoint_rejects_csf_and_residual_events():
+    import paper_2512_21696_amd as L
+    announce("two-component adjoint: kappa != 0 and a horizon with residual events")
+    wl = W.droplet_slab(n=16, radius=4.0, slab=4)
+    lb = L.lbm_create(wl["params"])
+    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    with pytest.raises(L.LbmError) as ei:
+        lb.adjoint_flux(2, np.ones(2))
+    assert ei.value.code == L.LBM_E_UNSUPPORTED
+    lb.destroy()
+    wl = W.droplet_slab()
+    p = wl["params"]
+    p.kappa = 0.0
+    lb = L.lbm_create(p)
+    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    with pytest.raises(L.LbmError) as ei:
+        lb.adjoint_flux(200, np.ones(200), checkpoint_every=20)
+    assert ei.value.code == L.LBM_E_UNSUPPORTED and "residual events" in str(ei.value)
+    # the handle still advanced the steps
+    assert lb.get_diagnostics()["step"] == 200
+    lb.destroy()

@@ -174,7 +174,8 @@ def two_case(collision="regularized", resistance="implicit", seed=7):
                  g=((1e-4, 2e-5, 0.0), (0.0, 0.0, -1e-5)), outlet_x=9).filled()
     m = p.m_minor
     x = np.arange(nx)[None, None, :]
-    rw = np.where(x < 10, 1.0, m) + 0.005 * rng.random(cls.shape)
+    noise = 0.005 * rng.random(cls.shape)
+    rw = np.where(x < 10, 1.0 - noise, m + noise)
     return p, cls, phi, pt, tabs, rw, 1.0 + m - rw
 
 
