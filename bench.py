@@ -56,10 +56,21 @@ def algorithmic_bytes(ncomp, es, gray_frac, tensor, pop_es=None):
 
 
 def kernel_source_hash():
+    """Hash of what decides the step kernels' traffic: their sources and the
+    runtime's launch functions for them (launch_tiled, ensure_density)."""
+    import re
     h = hashlib.sha256()
-    for f in ("lbm_kernels.hip", "lbm_step_tiled.hip", "lbm_runtime.hip", "lbm_internal.hpp"):
-        with open(os.path.join(ROOT, "paper_2512_21696_amd", "csrc", f), "rb") as fh:
+    csrc = os.path.join(ROOT, "paper_2512_21696_amd", "csrc")
+    for f in ("lbm_kernels.hip", "lbm_step_tiled.hip", "lbm_internal.hpp"):
+        with open(os.path.join(csrc, f), "rb") as fh:
             h.update(fh.read())
+    with open(os.path.join(csrc, "lbm_runtime.hip")) as fh:
+        rt = fh.read()
+    for name in ("ensure_density", "launch_tiled"):
+        m = re.search(r"\n[^\n]*\b" + name + r"\(lbm_handle \*h[^{]*\{.*?\n\}\n", rt, re.S)
+        if m is None:
+            raise RuntimeError(f"{name} not found in lbm_runtime.hip")
+        h.update(m.group(0).encode())
     return h.hexdigest()[:16]
 
 
@@ -424,6 +435,8 @@ def main():
                          "cwrite} into the traffic record of --precision's workload (no GPU)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the porosity-gradient section and print its JSON, then exit")
+    ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "both"],
+                    help="with --adjoint: which workload(s) to run")
     ap.add_argument("--drift", type=int, default=0, metavar="STEPS",
                     help="only run the storage precisions side by side for STEPS steps and "
                          "print their field errors against fp64 at checkpoints, then exit")
@@ -444,10 +457,12 @@ def main():
     if args.adjoint:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps({"adjoint_gradient": adjoint_gradient(),
-                          "adjoint_gradient_tensor": adjoint_gradient(n=192, steps=1000,
-                                                                      kind="fiber")}),
-              flush=True)
+        res = {}
+        if args.adjoint_case in ("rock", "both"):
+            res["adjoint_gradient"] = adjoint_gradient()
+        if args.adjoint_case in ("fiber", "both"):
+            res["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
+        print(json.dumps(res), flush=True)
         return
 
     import numpy as np
