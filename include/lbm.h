@@ -336,12 +336,17 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * Discrete adjoint of the outlet flux with respect to the gray porosity.
  *
  * The gray-region resistance of Eq. (1) makes the flow depend on phi through
- * K0(phi), the per-pore-type table; calibrating phi (or the tables) against an
- * observed flux needs dL/dphi.  For the one-component model (ncomp = 1, scalar
- * K0: tensor = 0, periodic x faces, native fp64 or fp32 storage) and a loss
+ * K0(phi), the per-pore-type table, and, with the tensorial resistivity,
+ * through the principal axes of the smoothed porosity (Eqs. (6)-(7)); with two
+ * components phi also enters the capillary term through the Leverett-J factor
+ * s_J(phi) (Eq. (5)).  Calibrating phi (or the tables) against an observed flux
+ * needs dL/dphi.  For one component, or two components without the CSF control
+ * (kappa = 0) over a horizon without residual events (scalar K0 or tensor = 1,
+ * periodic x faces, native fp64 or fp32 storage) and a loss
  * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
  * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
- * post-collision populations of step n crossing outlet_x | outlet_x + 1),
+ * first component's post-collision populations of step n crossing
+ * outlet_x | outlet_x + 1),
  * lbm_adjoint_flux runs those steps and returns dL/dK0 and dL/dphi on every
  * voxel: the exact gradient of the discrete forward map (the step in exact
  * arithmetic, evaluated at the stored states).  Any differentiable loss of the
@@ -357,30 +362,36 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * one reverse-step kernel per step applies the transposed streaming (a gather
  * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
  * weights and the transposed collision Jacobian, and accumulates dL/dK0 (or,
- * with the tensor, dL/dK^-1 per gray voxel).  The tensor's dL/dK^-1 goes back
+ * with the tensor, dL/dK^-1 per gray voxel; with two components also dL/ds_J,
+ * and the reverse of the neighbours' pseudo-potential and saturation-gradient
+ * reads runs as a second, gathering kernel).  The tensor's dL/dK^-1 goes back
  * through the set-up: first-order perturbation of the Hessian's eigenvectors
  * (and of the tie-break's gradient-aligned axis), the transposed gradient and
  * Hessian stencils and the transposed Gaussian smoothing; the derivative is
  * that of the branch each voxel took (isotropic gate, |lambda| ordering, tie
  * test), exact away from those switches.  dL/dphi adds dL/dK0 times the
  * K0(phi) table's slope on the lookup's cell (the right-hand slope on a table
- * knot).
+ * knot) and dL/ds_J times ds_J/dphi.  Residual events are switches with no
+ * derivative: a two-component call checks after the forward sweep that no
+ * residual amount or side flag changed, else returns LBM_E_UNSUPPORTED.
  *
  * Arguments: nsteps >= 1; dL_dQ a host array of nsteps finite doubles;
  * checkpoint_every >= 1, or 0 for ceil(sqrt(nsteps)); Q_out (nsteps), dL_dK0 and
  * dL_dphi (N each, [z][y][x], zero off gray voxels) host arrays owned by the
  * caller, each may be NULL.  Device memory, allocated through the hook and
  * freed before returning: ceil(nsteps / K) + K + 1 population-sized sets of
- * the storage type (19 N values each, K = checkpoint_every: checkpoints, the
+ * the storage type (19 N values per component, K = checkpoint_every: checkpoints, the
  * recomputed levels of one segment, two adjoint sets) plus 2 N doubles (scalar
- * K0) or 20 N doubles (tensor).  The adjoint populations are kept in the
- * storage type, the reverse arithmetic and the gradient accumulation in fp64.
+ * K0) or 20 N doubles (tensor), and for two components 15 N values of the
+ * storage type, N bytes and N doubles more.  The adjoint populations are kept
+ * in the storage type, the reverse arithmetic and the gradient accumulation in
+ * fp64.
  * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
  * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
- * fluid state), LBM_E_UNSUPPORTED (two components, pressure x faces or 16-bit
- * storage), LBM_E_NOMEM, LBM_E_DEVICE,
- * LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
+ * fluid state), LBM_E_UNSUPPORTED (pressure x faces, 16-bit storage, two
+ * components with kappa != 0 or with residual events within the horizon),
+ * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
                      int64_t checkpoint_every, double *Q_out, double *dL_dK0,
