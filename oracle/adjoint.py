@@ -248,13 +248,16 @@ def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
 
 class TwoComponent(OneComponent):
     """The two-component step in torch (Sec. II without the CSF control, kappa
-    = 0, and for horizons without residual events, which are switches with no
-    derivative): the pseudo-potential force with wall virtual densities, the
+    = 0): the pseudo-potential force with wall virtual densities, the
     capillary term of Eq. (1) with P_c = s_J(phi) P_c(S) and the gradient of
     the mobile saturation, the resistance c_R = sum_b rho S^b nu^b / max(Kr^b,
     Kr_min) with K0(phi) or K^-1(phi), the common velocity u' and per-component
-    collision with the force term at u' + F^a / (2 rho^a).  r [2, z, y, x]
-    holds the residual amounts, constant over such a horizon."""
+    collision with the force term at u' + F^a / (2 rho^a), then the residual
+    transfer on a saturation crossing (trap and release, with theta_w and
+    theta_o the crossings of s_J(phi) P_c with c_max Pc_PM and c_min Pc_PM).
+    The events are switches: the gradient is that of the branch each voxel
+    takes (the crossing test is made on detached values).  r [2, z, y, x]
+    holds the residual amounts at the start."""
 
     def __init__(self, params, cls, ptype, tables, r):
         super().__init__(params, cls, ptype, tables)
@@ -282,10 +285,52 @@ class TwoComponent(OneComponent):
     def _nb(self, X, i):
         return torch.where(self.nb_solid[i], X, _sh(X, C[i]))
 
-    def step2(self, f, K0, sJ, Kinv=None):
-        """One step from the post-streaming sets f [2, Q, z, y, x]; returns
-        (new f, Q^w)."""
+    def thetas(self, sJ):
+        """theta_w, theta_o of the gray voxels as functions of s_J: the smallest
+        S where the non-increasing s_J P_c(S) equals c Pc_PM (0 when it never
+        does), theta_w at c_max, theta_o = 1 - S at c_min."""
         p = self.p
+        thw = torch.zeros(self.shape, dtype=torch.float64)
+        tho = torch.zeros(self.shape, dtype=torch.float64)
+        sj_d = sJ.detach().numpy()
+        for t, tab in enumerate(self.tables):
+            sel = (self.cls == GRAY) & (self.ptype == t)
+            if not sel.any():
+                continue
+            pc = np.asarray(tab["Pc"], np.float64)
+            n = len(pc) - 1
+            for c, is_w in ((p.c_max, True), (p.c_min, False)):
+                target = c * tab["Pc_PM"]
+                kk = np.zeros(self.shape, np.int64)
+                found = np.zeros(self.shape, bool)
+                for idx in zip(*np.nonzero(sel)):
+                    y = sj_d[idx] * pc
+                    if y[0] < target or y[n] > target:
+                        continue
+                    found[idx] = True
+                    kk[idx] = int(np.argmax(y <= target))
+                km = np.maximum(kk, 1)
+                a = sJ * torch.as_tensor(pc[km - 1])
+                b = sJ * torch.as_tensor(pc[km])
+                sstar = ((torch.as_tensor(km - 1, dtype=torch.float64)
+                          + (a - target) / torch.where(torch.as_tensor(found), a - b,
+                                                       torch.ones_like(a))) / n)
+                sstar = torch.where(torch.as_tensor(found & (kk > 0)), sstar, torch.zeros_like(a))
+                val = sstar if is_w else 1.0 - sstar
+                val = torch.where(torch.as_tensor(found), val, torch.zeros_like(a))
+                if is_w:
+                    thw = torch.where(torch.as_tensor(sel), val, thw)
+                else:
+                    tho = torch.where(torch.as_tensor(sel), val, tho)
+        return thw, tho
+
+    def step2(self, f, K0, sJ, Kinv=None, r=None, side=None, thw=None, tho=None):
+        """One step from the post-streaming sets f [2, Q, z, y, x] with
+        residual amounts r and side flags side; returns (new f, Q^w, new r,
+        new side).  Without side flags no residual transfer is made."""
+        p = self.p
+        if r is None:
+            r = self.r
         fl = self.fluid
         rho = [f[a].sum(0) for a in range(2)]
         mom = [[sum(C[i, d] * f[a][i] for i in range(Q) if C[i, d]) for d in range(3)]
@@ -294,7 +339,7 @@ class TwoComponent(OneComponent):
         safe = torch.where(fl, rho_t, torch.ones_like(rho_t))
         F_ex = [[rho[a] * self.gs[a][d] for d in range(3)] for a in range(2)]
         span = p.s_max - p.s_min
-        tw, to = rho[0] + self.r[0], rho[1] + self.r[1]
+        tw, to = rho[0] + r[0], rho[1] + r[1]
         s = torch.where(fl, tw / torch.where(fl, tw + to, torch.ones_like(tw)), torch.zeros_like(tw))
         S = torch.clamp((s - p.s_min) / span, 0.0, 1.0)
         S_hat = torch.where(fl, (rho[0] / safe - p.s_min) / span, torch.zeros_like(tw))
@@ -361,29 +406,63 @@ class TwoComponent(OneComponent):
             ua = [up[d] + F[a][d] / ra for d in range(3)]
             post = feq + (1.0 - 1.0 / self.taus[a]) * f1 + _force_term(ua, F[a])
             posts.append(torch.where(fl, post, torch.zeros_like(post)))
+        if side is not None:
+            Sd = S.detach()
+            g = torch.as_tensor(self.cls == GRAY)
+            to_w = g & ~side & (Sd >= 0.5 + p.hyst)
+            to_o = g & side & (Sd <= 0.5 - p.hyst)
+            rhoT = tw + to
+            m = p.m_minor
+            sw_ = torch.where(fl, rho[0], torch.ones_like(rho[0]))
+            so_ = torch.where(fl, rho[1], torch.ones_like(rho[1]))
+            # oil -> water: release residual water, trap theta_o of the total as oil
+            sc_w = (rho[0] + r[0]) / sw_
+            d_o = torch.clamp(torch.minimum(tho * rhoT - r[1], rho[1] - m), min=0.0)
+            sc_o = 1.0 - d_o / so_
+            # water -> oil: release residual oil, trap theta_w of the total as water
+            sc_o2 = (rho[1] + r[1]) / so_
+            d_w = torch.clamp(torch.minimum(thw * rhoT - r[0], rho[0] - m), min=0.0)
+            sc_w2 = 1.0 - d_w / sw_
+            s0 = torch.where(to_w, sc_w, torch.where(to_o, sc_w2, torch.ones_like(sc_w)))
+            s1 = torch.where(to_w, sc_o, torch.where(to_o, sc_o2, torch.ones_like(sc_o)))
+            posts = [posts[0] * s0, posts[1] * s1]
+            r = torch.stack([torch.where(to_w, torch.zeros_like(r[0]),
+                                         torch.where(to_o, r[0] + d_w, r[0])),
+                             torch.where(to_w, r[1] + d_o,
+                                         torch.where(to_o, torch.zeros_like(r[1]), r[1]))])
+            side = torch.where(to_w, torch.ones_like(side), torch.where(to_o, torch.zeros_like(side),
+                                                                        side))
         Qn = (self.flux_w * posts[0]).sum()
         new = []
         for a in range(2):
             na = torch.stack([torch.where(self.src_solid[i], posts[a][OPP[i]],
                                           _sh(posts[a][i], C[i], -1)) for i in range(Q)])
             new.append(torch.where(fl, na, torch.zeros_like(na)))
-        return torch.stack(new), Qn
+        return torch.stack(new), Qn, r, side
 
 
-def flux_gradient2(params, cls, phi, ptype, tables, f0, r, steps, dL_dQ):
+def flux_gradient2(params, cls, phi, ptype, tables, f0, r, steps, dL_dQ, side=None):
     """Two components: runs `steps` steps from the post-streaming sets f0
-    [2, Q, z, y, x] with residual amounts r [2, z, y, x] and returns (Q^w
-    history, dL/dphi, final f) for L = sum_n dL_dQ[n] Q^w(n), through K0(phi)
-    (or K^-1(phi)) in the resistance and s_J(phi) in the capillary term."""
+    [2, Q, z, y, x] with residual amounts r [2, z, y, x] (and, when side
+    flags are given, the residual transfer) and returns (Q^w history, dL/dphi,
+    final f) for L = sum_n dL_dQ[n] Q^w(n), through K0(phi) (or K^-1(phi)) in
+    the resistance, s_J(phi) in the capillary term and theta_w, theta_o(s_J)
+    in the residual transfer."""
     model = TwoComponent(params, cls, ptype, tables, r)
     ph = torch.tensor(np.asarray(phi, np.float64), requires_grad=True)
     K0 = model.K0(ph)
     sJ = model.sJ(ph, K0)
     Kinv = model.Kinv(ph, K0) if model.tensor else None
+    thw = tho = None
+    rr = torch.as_tensor(np.asarray(r, np.float64))
+    sd = None
+    if side is not None:
+        thw, tho = model.thetas(sJ)
+        sd = torch.as_tensor(np.asarray(side, bool))
     f = torch.as_tensor(np.asarray(f0, np.float64))
     hist = []
     for _ in range(int(steps)):
-        f, Qn = model.step2(f, K0, sJ, Kinv)
+        f, Qn, rr, sd = model.step2(f, K0, sJ, Kinv, rr, sd, thw, tho)
         hist.append(Qn)
     hist = torch.stack(hist)
     L = (hist * torch.as_tensor(np.asarray(dL_dQ, np.float64))).sum()

@@ -230,3 +230,82 @@ def test_two_component_gradient_matches_oracle_finite_differences():
         if checked == 3:
             break
     assert checked == 3
+
+
+def event_state(p, cls, phi, pt, tabs, rw, ro):
+    """The two-component case with half of the gray voxels' side flags turned
+    (seed 11) and some residual amounts, so that residual transfers fire."""
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rw, ro)
+    S = o.evaluate()["S"]
+    gray = cls == 2
+    rng = np.random.default_rng(11)
+    flip = gray & (rng.random(cls.shape) < 0.5)
+    side = o.side.copy()
+    side[flip] = ~side[flip]
+    r = np.zeros((2,) + cls.shape)
+    r[0] = np.where(gray & ~side & (S > 0.5), 0.01, 0.0)
+    r[1] = np.where(gray & side & (S < 0.5), 0.02, 0.0)
+    return side, r
+
+
+def _event_history(p, cls, phi, pt, tabs, rw, ro, side, r, steps):
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rw, ro)
+    o.side, o.r = side.copy(), r.copy()
+    f0 = o.f.copy()
+    q, events = [], 0
+    for _ in range(steps):
+        s0 = o.side.copy()
+        o.step(1)
+        q.append(o.Q_last[0])
+        events += int(np.sum(o.side != s0))
+    return f0, np.array(q), o.f, o.r, events
+
+
+def test_two_component_with_residual_events():
+    """Residual transfers (trap and release) fire in this horizon: the torch
+    transcription follows the numpy oracle through them (theta_w, theta_o as
+    functions of s_J equal the set-up's crossings), and its gradient, that of
+    the branch each voxel took, matches central finite differences of the
+    oracle at voxels whose perturbed runs take the same branches."""
+    import torch
+    p, cls, phi, pt, tabs, rw, ro = two_case()
+    side, r = event_state(p, cls, phi, pt, tabs, rw, ro)
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    f0, q, fN, rN, events = _event_history(p, cls, phi, pt, tabs, rw, ro, side, r, steps)
+    assert events > 100 and rN.max() > 0
+    m = A.TwoComponent(p, cls, pt, tabs, r)
+    ph = torch.tensor(phi)
+    thw, tho = m.thetas(m.sJ(ph, m.K0(ph)))
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    assert np.abs(thw.numpy() - o.thw).max() < 1e-14 and np.abs(tho.numpy() - o.tho).max() < 1e-14
+    assert o.tho.max() > 0  # both transfers trap something
+    hist, grad, fT = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r, steps, a, side=side)
+    assert np.abs(hist - q).max() < 1e-14 and np.abs(fT - fN).max() < 1e-14
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(5)
+    eps, checked = 1e-4, 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue
+        Ls = []
+        for s in (1, -1):
+            ph2 = phi.copy()
+            ph2[v] += s * eps
+            _, qq, _, _, ev = _event_history(p, cls, ph2, pt, tabs, rw, ro, side, r, steps)
+            assert ev == events
+            Ls.append(float((a * qq).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        # L carries ~1e-15 of rounding: 1e-11 of finite-difference noise
+        assert abs(grad[v] - fd) < 1e-4 * abs(fd) + 1e-6 * np.abs(grad).max(), (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
