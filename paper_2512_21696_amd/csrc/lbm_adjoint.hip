@@ -294,14 +294,25 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
 // dL/d(acc^a) and dL/d(grad S_hat) of each voxel (stash[9][v]), k_adj_nl2
 // gathers them into the neighbours' dL/drho^a (rnl[v][2]), which the next
 // reverse step adds to every population of those voxels as it gathers.
+// Residual transfer (gray voxels; the branch the forward state takes): on a
+// crossing the post-collision sets are scaled, post^a <- s^a post^a, with
+//   oil -> water (side 0, S >= 1/2 + h): s^w = (rho^w + r^w) / rho^w,
+//     d = max(min(theta_o rho_T - r^o, rho^o - m), 0), s^o = 1 - d / rho^o,
+//     r^w <- 0, r^o <- r^o + d;
+//   water -> oil (side 1, S <= 1/2 - h): the mirror with theta_w;
+// rho_T = rho^w + r^w + rho^o + r^o.  The residual amounts are state: lr[2][v]
+// carries dL/dr from step to step (updated in place), and gth[2][v]
+// accumulates dL/dtheta_w, dL/dtheta_o.
 template <typename T, bool REG, bool TENS>
 __global__ __launch_bounds__(256) void k_adj_step2(
     const ModelConsts mc, const T *__restrict__ post, const T *__restrict__ rho2,
-    const T *__restrict__ rres, const T *__restrict__ lin, const T *__restrict__ rnl,
-    T *__restrict__ lout, T *__restrict__ stash, const uint32_t *__restrict__ mask,
-    const T *__restrict__ K0, const T *__restrict__ Kinv, const T *__restrict__ sJ,
+    const T *__restrict__ rres, const uint8_t *__restrict__ side, const T *__restrict__ lin,
+    const T *__restrict__ rnl, T *__restrict__ lout, T *__restrict__ stash,
+    const uint32_t *__restrict__ mask, const T *__restrict__ K0, const T *__restrict__ Kinv,
+    const T *__restrict__ sJ, const T *__restrict__ thw, const T *__restrict__ tho,
     const uint8_t *__restrict__ ptype, const T *__restrict__ tab, double *__restrict__ gk,
-    double *__restrict__ gsj, const double an) {
+    double *__restrict__ gsj, double *__restrict__ lr, double *__restrict__ gth,
+    const double an) {
   const long long N = mc.N;
   const int per = gridDim.x / 8;
   const long long blk = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -319,14 +330,15 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 
   // pulls, moments and the gathered adjoint of the post-collision sets
   double rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
+  double Pi[2][6], lf[2];  // second moments (regularised), sum_i lam_i f_i (BGK)
   double lp[REG ? 1 : 2][REG ? 1 : Q];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const T *pa = post + (size_t)a * Q * N;
     const T *la = lin + (size_t)a * Q * N;
-    rho[a] = 0; L0[a] = 0;
+    rho[a] = 0; L0[a] = 0; lf[a] = 0;
     for (int d = 0; d < 3; ++d) { m[a][d] = 0; L1[a][d] = 0; }
-    for (int d = 0; d < 6; ++d) M2[a][d] = 0;
+    for (int d = 0; d < 6; ++d) { M2[a][d] = 0; Pi[a][d] = 0; }
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int j = opp(i);
@@ -336,6 +348,14 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       if (cx(i)) m[a][0] += cx(i) * fi;
       if (cy(i)) m[a][1] += cy(i) * fi;
       if (cz(i)) m[a][2] += cz(i) * fi;
+      if (REG) {
+        if (cx(i)) Pi[a][0] += fi;
+        if (cy(i)) Pi[a][1] += fi;
+        if (cz(i)) Pi[a][2] += fi;
+        if (cx(i) && cy(i)) Pi[a][3] += (cx(i) * cy(i)) * fi;
+        if (cx(i) && cz(i)) Pi[a][4] += (cx(i) * cz(i)) * fi;
+        if (cy(i) && cz(i)) Pi[a][5] += (cy(i) * cz(i)) * fi;
+      }
       const bool wall = (mk >> i) & 1u;
       double l;
       if (wall) {
@@ -346,7 +366,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         if (a == 0 && at0 && cx(i) == 1) l += an;
         if (a == 0 && at1 && cx(i) == -1) l -= an;
       }
-      if (!REG) lp[REG ? 0 : a][REG ? 0 : i] = l;
+      if (!REG) {
+        lp[REG ? 0 : a][REG ? 0 : i] = l;
+        lf[a] += l * fi;
+      }
       const double wl = wq(i) * l;
       L0[a] += wl;
       if (cx(i)) { L1[a][0] += cx(i) * wl; M2[a][0] += wl; }
@@ -472,6 +495,81 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) / D;
   const double usq = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
 
+  // residual transfer: which branch, the scale factors, and dL/ds^a =
+  // sum_i lam_post_i post_i of the unscaled set; the adjoint of the unscaled
+  // set is s^a times the gathered one
+  int ev = 0;  // 1: oil -> water, 2: water -> oil
+  double sc[2] = {1.0, 1.0}, scb[2] = {0.0, 0.0}, dtr = 0.0, rw0 = 0.0, ro0 = 0.0;
+  if (gray) {
+    const bool sd = side[v] != 0;
+    if (!sd && S >= 0.5 + mc.hyst) ev = 1;
+    else if (sd && S <= 0.5 - mc.hyst) ev = 2;
+  }
+  if (ev) {
+    rw0 = (double)rres[v];
+    ro0 = (double)rres[N + v];
+    const double rhoT = tw + to, mm = mc.m_minor;
+    if (ev == 1) {
+      sc[0] = (rho[0] + rw0) / rho[0];
+      double d = (double)tho[v] * rhoT - ro0;
+      const double cap = rho[1] - mm;
+      d = d < cap ? d : cap;
+      dtr = d > 0.0 ? d : 0.0;
+      sc[1] = 1.0 - dtr / rho[1];
+    } else {
+      sc[1] = (rho[1] + ro0) / rho[1];
+      double d = (double)thw[v] * rhoT - rw0;
+      const double cap = rho[0] - mm;
+      d = d < cap ? d : cap;
+      dtr = d > 0.0 ? d : 0.0;
+      sc[0] = 1.0 - dtr / rho[0];
+    }
+    for (int a = 0; a < 2; ++a) {
+      const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a], ra = rho[a];
+      double ua[3];
+      for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * 0.5 / ra;
+      double uF = 0, pl = 0, FL = 0;
+      for (int d = 0; d < 3; ++d) {
+        uF += ua[d] * F[a][d];
+        pl += up[d] * L1[a][d];
+        FL += F[a][d] * L1[a][d];
+      }
+      const double *Mv = M2[a];
+      const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
+      double uMu = 0, aMF = 0;
+      for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) {
+          uMu += up[i] * Mm[i][j] * up[j];
+          aMF += ua[i] * Mm[i][j] * F[a][j];
+        }
+      // equilibrium and force parts of A L0 + B.L1 + C:M
+      double phi_a = e * ra * (1.0 - usq / (2 * cs2)) * L0[a] - uF / cs2 * L0[a] +
+                     e * ra * pl / cs2 + FL / cs2 + e * ra * uMu / (2 * cs4) + aMF / cs4;
+      if (REG) {
+        const double *P = Pi[a];
+        const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
+        double tr = 0, PM = 0, jl = 0;
+        for (int i = 0; i < 3; ++i) {
+          for (int j = 0; j < 3; ++j) {
+            const double pn = Pm[i][j] - (i == j ? ra * cs2 : 0.0) - ra * up[i] * up[j];
+            PM += pn * Mm[i][j];
+            if (i == j) tr += pn;
+          }
+          jl += (m[a][i] - ra * up[i]) * L1[a][i];
+        }
+        phi_a += keep * (-tr / (2 * cs2) * L0[a] + jl / cs2 + PM / (2 * cs4));
+      } else {
+        phi_a += keep * lf[a];
+      }
+      scb[a] = phi_a;
+      L0[a] *= sc[a];
+      for (int d = 0; d < 3; ++d) L1[a][d] *= sc[a];
+      for (int d = 0; d < 6; ++d) M2[a][d] *= sc[a];
+      if (!REG)
+        for (int i = 0; i < Q; ++i) lp[REG ? 0 : a][REG ? 0 : i] *= sc[a];
+    }
+  }
+
   // reverse sweep
   double rb[2] = {0, 0}, mb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Pb[2][6];
   double upb[3] = {0, 0, 0}, usqb = 0, Fb[2][3];
@@ -548,7 +646,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   }
   // F^a = F_ex^a - (rho^a / rho_t) R u
-  double Rub[3] = {0, 0, 0}, rtb = 0, Fexb[2][3];
+  double Rub[3] = {0, 0, 0}, rtb = 0, Fexb[2][3], twb = 0, tob = 0;
   for (int a = 0; a < 2; ++a) {
     double FR = 0;
     for (int d = 0; d < 3; ++d) {
@@ -659,8 +757,8 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     Sb += Pcb * sj * dPct;
     if (Sraw > 0.0 && Sraw < 1.0) {
       const double tt = tw + to, sb = Sb / span;
-      rb[0] += sb * to / (tt * tt);
-      rb[1] += -sb * tw / (tt * tt);
+      twb += sb * to / (tt * tt);
+      tob += -sb * tw / (tt * tt);
     }
     // grad S_hat: the links to solid neighbours read this voxel's S_hat
     double shb = 0;
@@ -674,6 +772,56 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   }
   rb[0] += rtb;
   rb[1] += rtb;
+  if (gray) {
+    // residual amounts: dL/dr after the step comes in, dL/dr before it goes out
+    double rbw = 0.0, rbo = 0.0;
+    const double lw = lr[v], lo_ = lr[N + v];
+    if (ev) {
+      const double rhoT = tw + to;
+      double db = 0.0, rTb = 0.0;
+      if (ev == 1) {
+        rb[0] += scb[0] * (-rw0 / (rho[0] * rho[0]));
+        rbw += scb[0] / rho[0];
+        db += -scb[1] / rho[1];
+        rb[1] += scb[1] * dtr / (rho[1] * rho[1]);
+        rbo += lo_;  // r^o <- r^o + d; r^w <- 0
+        db += lo_;
+        const double raw = (double)tho[v] * rhoT - ro0, cap = rho[1] - mc.m_minor;
+        if (raw < cap && raw > 0.0) {
+          gth[N + v] += db * rhoT;
+          rTb += db * (double)tho[v];
+          rbo -= db;
+        } else if (raw >= cap && cap > 0.0) {
+          rb[1] += db;
+        }
+      } else {
+        rb[1] += scb[1] * (-ro0 / (rho[1] * rho[1]));
+        rbo += scb[1] / rho[1];
+        db += -scb[0] / rho[0];
+        rb[0] += scb[0] * dtr / (rho[0] * rho[0]);
+        rbw += lw;  // r^w <- r^w + d; r^o <- 0
+        db += lw;
+        const double raw = (double)thw[v] * rhoT - rw0, cap = rho[0] - mc.m_minor;
+        if (raw < cap && raw > 0.0) {
+          gth[v] += db * rhoT;
+          rTb += db * (double)thw[v];
+          rbw -= db;
+        } else if (raw >= cap && cap > 0.0) {
+          rb[0] += db;
+        }
+      }
+      twb += rTb;
+      tob += rTb;
+    } else {
+      rbw += lw;
+      rbo += lo_;
+    }
+    // t_w = rho^w + r^w, t_o = rho^o + r^o
+    rb[0] += twb;
+    rb[1] += tob;
+    lr[v] = rbw + twb;
+    lr[N + v] = rbo + tob;
+  }
 
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -734,19 +882,40 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
   rnl[2 * v + 1] = (T)(r1 - shb / span * aw / (tt * tt));
 }
 
+// d theta / d s_J of a residual saturation: theta is the smallest S* where
+// s_J P_c(S*) = target on the piecewise-linear table, so on the crossed cell
+// (k-1, k) dS*/ds_J = target / (s_J^2 (P_c[k-1] - P_c[k])) / (TABLE_N - 1);
+// zero where the curve never reaches the target or already starts below it.
+__device__ inline double dcross_dsj(const double *pc, double sj, double target) {
+  const int n = TABLE_N - 1;
+  if (sj * pc[0] < target || sj * pc[n] > target) return 0.0;
+  int lo = 0, hi = n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (sj * pc[mid] <= target) hi = mid;
+    else lo = mid + 1;
+  }
+  if (lo == 0) return 0.0;
+  return target / (sj * sj * (pc[lo - 1] - pc[lo])) / (double)n;
+}
+
 // dL/dphi on gray voxels: dL/dK0 times the K0(phi) table's slope on the
-// lookup's cell, plus (two components) dL/ds_J through
+// lookup's cell, plus (two components) dL/ds_J, with the residual
+// saturations' dL/dtheta_w (at c_max Pc_PM) and dL/dtheta_o (at c_min Pc_PM,
+// theta_o = 1 - S*) carried to s_J, through
 // s_J = sqrt((K0_ref / phi_ref) phi / K0(phi)), plus (tensor) the transposed
 // smoothing's result gbase (the porosity field the smoothing read is phi
-// there).  gbase and gsj may be null.
+// there).  gbase, gsj and gth may be null.
 __global__ __launch_bounds__(256) void k_adj_phi2(const double *__restrict__ gbase,
                                                   const double *__restrict__ gK0,
                                                   const double *__restrict__ gsj,
+                                                  const double *__restrict__ gth,
                                                   const double *__restrict__ phi,
                                                   const uint8_t *__restrict__ pt,
                                                   const uint32_t *__restrict__ mask,
                                                   const double *__restrict__ tabs,
-                                                  const double *__restrict__ tabmeta, long long N,
+                                                  const double *__restrict__ tabmeta,
+                                                  double c_max, double c_min, long long N,
                                                   double *__restrict__ out) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
@@ -766,7 +935,13 @@ __global__ __launch_bounds__(256) void k_adj_phi2(const double *__restrict__ gba
   const double k0ref = lerp_tab<double>(tab, phi_ref);
   const double sj = sqrt((k0ref / phi_ref) / (k0 / ph));
   const double dsj = 0.5 * sj * (1.0 / ph - slope / k0);
-  out[v] = (gbase ? gbase[v] : 0.0) + gK0[v] * slope + (gsj ? gsj[v] * dsj : 0.0);
+  double gs = gsj ? gsj[v] : 0.0;
+  if (gth) {
+    const double pcpm = tabmeta[ty * 8 + 1];
+    const double *pc = tab + TABLE_N;
+    gs += gth[v] * dcross_dsj(pc, sj, c_max * pcpm) - gth[N + v] * dcross_dsj(pc, sj, c_min * pcpm);
+  }
+  out[v] = (gbase ? gbase[v] : 0.0) + gK0[v] * slope + gs * dsj;
 }
 
 // ---------------------------------------------------------------------------
@@ -977,21 +1152,33 @@ void launch_adj_step_t(lbm_handle *h, const T *post, const T *lin, T *lout, doub
                      lin, lout, s.mask, s.K0, (const T *)s.Kinv, gk, a);
 }
 
+// Buffers of the two-component reverse: the level's density field, residual
+// amounts and side flags, the neighbour-part stash and gathers, dL/dr, and the
+// s_J and theta accumulators.
+template <typename T>
+struct Rev2 {
+  T *dens, *stash, *rnl_in, *rnl_out;
+  const T *r;
+  const uint8_t *side;
+  double *gsj, *lr, *gth;
+};
+
 template <typename T, bool REG, bool TENS>
-void launch_adj_step2_t(lbm_handle *h, const T *post, const T *dens, const T *lin,
-                        const T *rnl, T *lout, T *stash, double *gk, double *gsj, double a) {
+void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk,
+                        double a, const Rev2<T> &b) {
   DevState<T> &s = state<T>(h);
   const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
   hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS>), dim3(nb), dim3(256), 0, h->st, h->mc,
-                     post, dens, (const T *)s.r, lin, rnl, lout, stash, s.mask, s.K0,
-                     (const T *)s.Kinv, s.sJ, s.ptype, s.tab, gk, gsj, a);
+                     post, (const T *)b.dens, b.r, b.side, lin, (const T *)b.rnl_in, lout,
+                     b.stash, s.mask, s.K0, (const T *)s.Kinv, s.sJ, (const T *)s.thw,
+                     (const T *)s.tho, s.ptype, s.tab, gk, b.gsj, b.lr, b.gth, a);
 }
 
 // One reverse step: one component, or (two components) the density pass of
 // the level, the local reverse and the gather of the neighbours' part.
 template <typename T>
 void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk, double a,
-                    T *dens, const T *rnl_in, T *rnl_out, T *stash, double *gsj) {
+                    const Rev2<T> &b) {
   DevState<T> &s = state<T>(h);
   const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
   const bool ten = h->p.tensor != 0;
@@ -1009,25 +1196,29 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
   {
     Timed tm(h, K_AUX);
     hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE, false>), dim3(blocks(h->N)), dim3(256), 0,
-                       h->st, (const void *)post, dens, (const T *)nullptr, (const T *)nullptr,
+                       h->st, (const void *)post, b.dens, (const T *)nullptr, (const T *)nullptr,
                        s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
   }
   Timed tm(h, K_ADJ);
   if (ten) {
-    if (reg) launch_adj_step2_t<T, true, true>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
-    else launch_adj_step2_t<T, false, true>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+    if (reg) launch_adj_step2_t<T, true, true>(h, post, lin, lout, gk, a, b);
+    else launch_adj_step2_t<T, false, true>(h, post, lin, lout, gk, a, b);
   } else {
-    if (reg) launch_adj_step2_t<T, true, false>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
-    else launch_adj_step2_t<T, false, false>(h, post, dens, lin, rnl_in, lout, stash, gk, gsj, a);
+    if (reg) launch_adj_step2_t<T, true, false>(h, post, lin, lout, gk, a, b);
+    else launch_adj_step2_t<T, false, false>(h, post, lin, lout, gk, a, b);
   }
-  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc, dens,
-                     stash, s.mask, rnl_out);
+  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
+                     (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
 }
 
 // The fused step from fin into fout (two components: after the density pass
 // of fin into the handle's density buffer).
+// Two components: the residual amounts and side flags of the new level (rout,
+// sout, which hold a copy of the old level's on entry) are updated in place by
+// the step, through the handle's state pointers swapped for the launch.
 template <typename T>
-void launch_recompute(lbm_handle *h, const T *fin, T *fout) {
+void launch_recompute(lbm_handle *h, const T *fin, T *fout, T *rout = nullptr,
+                      uint8_t *sout = nullptr) {
   DevState<T> &s = state<T>(h);
   const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
   if (h->p.ncomp == 2) {
@@ -1037,29 +1228,22 @@ void launch_recompute(lbm_handle *h, const T *fin, T *fout) {
                          h->st, (const void *)fin, s.rho2, (const T *)nullptr, (const T *)nullptr,
                          s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
     }
-    Timed tm(h, K_STEP);
-    if (reg) launch_tiled<T, 2, true>(h, fin, fout);
-    else launch_tiled<T, 2, false>(h, fin, fout);
+    T *const r_own = s.r;
+    uint8_t *const s_own = s.side;
+    s.r = rout;
+    s.side = sout;
+    {
+      Timed tm(h, K_STEP);
+      if (reg) launch_tiled<T, 2, true>(h, fin, fout);
+      else launch_tiled<T, 2, false>(h, fin, fout);
+    }
+    s.r = r_own;
+    s.side = s_own;
     return;
   }
   Timed tm(h, K_STEP);
   if (reg) launch_tiled<T, 1, true>(h, fin, fout);
   else launch_tiled<T, 1, false>(h, fin, fout);
-}
-
-// 1 where the residual amounts or side flags of two copies differ (block
-// partials, summed by k_finalize): residual events happened in between.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_diff(const T *__restrict__ r0,
-                                                  const T *__restrict__ r1,
-                                                  const uint8_t *__restrict__ s0,
-                                                  const uint8_t *__restrict__ s1, long long N,
-                                                  double *__restrict__ partial) {
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  double val[1] = {0.0};
-  if (v < N)
-    val[0] = (r0[v] != r1[v] || r0[N + v] != r1[N + v] || s0[v] != s1[v]) ? 1.0 : 0.0;
-  block_sum<1>(val, partial + blockIdx.x, false);
 }
 
 // dL/dK^-1 (tensor runs) back to dL/dK0 and to the porosity through the
@@ -1135,17 +1319,24 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   double *gbase = h->p.tensor ? alloc_into<double>(h, tmp, (size_t)N, &ok) : nullptr;
   double *gp = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *qh = alloc_into<double>(h, tmp, (size_t)2 * n, &ok);
-  T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *r0 = nullptr;
-  double *gsj = nullptr, *flag = nullptr;
-  uint8_t *side0 = nullptr;
+  // two components: the residual amounts and side flags of every kept level
+  // (checkpoints and ring, like the populations), the reverse's buffers
+  T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *ckR = nullptr, *ringR = nullptr;
+  uint8_t *ckS = nullptr, *ringS = nullptr;
+  double *gsj = nullptr, *lr = nullptr, *gth = nullptr;
   if (nc == 2) {
     dens = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
     stash = alloc_into<T>(h, tmp, (size_t)9 * N, &ok);
     rnl = alloc_into<T>(h, tmp, (size_t)4 * N, &ok);
-    r0 = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
-    side0 = alloc_into<uint8_t>(h, tmp, (size_t)N, &ok);
+    ckR = alloc_into<T>(h, tmp, (size_t)nseg * 2 * N, &ok);
+    ckS = alloc_into<uint8_t>(h, tmp, (size_t)nseg * N, &ok);
+    if (K > 1) {
+      ringR = alloc_into<T>(h, tmp, (size_t)(K - 1) * 2 * N, &ok);
+      ringS = alloc_into<uint8_t>(h, tmp, (size_t)(K - 1) * N, &ok);
+    }
     gsj = alloc_into<double>(h, tmp, (size_t)N, &ok);
-    flag = alloc_into<double>(h, tmp, 1, &ok);
+    lr = alloc_into<double>(h, tmp, (size_t)2 * N, &ok);
+    gth = alloc_into<double>(h, tmp, (size_t)2 * N, &ok);
   }
   auto finish = [&](int rc) {
     (void)hipStreamSynchronize(h->st);
@@ -1155,14 +1346,15 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   if (!ok) return finish(set_err(h, LBM_E_NOMEM, "device allocation failed in adjoint_flux"));
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
   int rc = LBM_OK;
-  if (nc == 2) {
-    rc = hip_check(h, hipMemcpyAsync(r0, s.r, (size_t)2 * N * sizeof(T), hipMemcpyDeviceToDevice,
-                                     h->st),
-                   "copy residual amounts");
-    if (rc == LBM_OK)
-      rc = hip_check(h, hipMemcpyAsync(side0, s.side, (size_t)N, hipMemcpyDeviceToDevice, h->st),
-                     "copy side flags");
-  }
+  const size_t RB = (size_t)2 * N * sizeof(T);  // residual amounts of one level
+  auto copy_rs = [&](T *rdst, uint8_t *sdst, const T *rsrc, const uint8_t *ssrc) {
+    int e = hip_check(h, hipMemcpyAsync(rdst, rsrc, RB, hipMemcpyDeviceToDevice, h->st),
+                      "copy residual amounts");
+    if (e == LBM_OK)
+      e = hip_check(h, hipMemcpyAsync(sdst, ssrc, (size_t)N, hipMemcpyDeviceToDevice, h->st),
+                    "copy side flags");
+    return e;
+  };
   // forward sweep.  The last segment keeps its levels: each of its steps but
   // the last writes its new set straight into the ring (the handle's buffer
   // pointers are swapped for it and put back at the end), so that segment is
@@ -1172,6 +1364,8 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
     rc = hip_check(h, hipMemcpyAsync(ck + sg * SN, s.f[h->cur], SN * sizeof(T),
                                      hipMemcpyDeviceToDevice, h->st),
                    "checkpoint copy");
+    if (rc == LBM_OK && nc == 2)
+      rc = copy_rs(ckR + (size_t)sg * 2 * N, ckS + (size_t)sg * N, s.r, s.side);
     const int64_t m = std::min<int64_t>(K, n - sg * K);
     const bool keep = sg == nseg - 1;
     T *const spare = s.f[1 - h->cur];
@@ -1188,6 +1382,8 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
                            s.mask, s.partial);
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0,
                          qh + 2 * (sg * K + k), 0);
+      if (keep && nc == 2 && k < m - 1)
+        rc = copy_rs(ringR + (size_t)k * 2 * N, ringS + (size_t)k * N, s.r, s.side);
     }
     if (keep) {
       if (rc == LBM_OK) {  // the final set is in `spare`, one of the handle's buffers
@@ -1198,24 +1394,6 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
         h->has_fluid = false;
       }
     }
-  }
-  // two components: the reverse sweep holds for a horizon without residual
-  // events (switches with no derivative)
-  if (rc == LBM_OK && nc == 2) {
-    const unsigned nbk = blocks(N);
-    hipLaunchKernelGGL((k_adj_diff<T>), dim3(nbk), dim3(256), 0, h->st, r0, (const T *)s.r, side0,
-                       (const uint8_t *)s.side, N, s.partial);
-    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)nbk, 1, 0, flag,
-                       0);
-    double changed = 0.0;
-    rc = hip_check(h, hipMemcpyAsync(&changed, flag, sizeof(double), hipMemcpyDeviceToHost, h->st),
-                   "copy event flag");
-    if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "event check");
-    if (rc == LBM_OK && changed != 0.0)
-      rc = set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: residual events within the horizon (" +
-                       std::to_string((long long)changed) +
-                       " voxels); the handle has advanced the steps");
   }
   // reverse sweep; the loss does not depend on the set after the last step
   if (rc == LBM_OK)
@@ -1228,18 +1406,44 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       rc = hip_check(h, hipMemsetAsync(stash, 0, (size_t)9 * N * sizeof(T), h->st), "clear");
     if (rc == LBM_OK)
       rc = hip_check(h, hipMemsetAsync(gsj, 0, (size_t)N * sizeof(double), h->st), "clear");
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemsetAsync(lr, 0, (size_t)2 * N * sizeof(double), h->st), "clear");
+    if (rc == LBM_OK)
+      rc = hip_check(h, hipMemsetAsync(gth, 0, (size_t)2 * N * sizeof(double), h->st), "clear");
   }
   int cl = 0;
   for (int64_t sg = nseg - 1; sg >= 0 && rc == LBM_OK; --sg) {
     const int64_t m = std::min<int64_t>(K, n - sg * K);
     auto level = [&](int64_t k) -> T * { return k == 0 ? ck + sg * SN : ring + (k - 1) * SN; };
+    auto levelR = [&](int64_t k) -> T * {
+      return k == 0 ? ckR + (size_t)sg * 2 * N : ringR + (size_t)(k - 1) * 2 * N;
+    };
+    auto levelS = [&](int64_t k) -> uint8_t * {
+      return k == 0 ? ckS + (size_t)sg * N : ringS + (size_t)(k - 1) * N;
+    };
     if (sg < nseg - 1)
-      for (int64_t k = 1; k < m; ++k) launch_recompute<T>(h, level(k - 1), level(k));
-    for (int64_t k = m - 1; k >= 0; --k) {
-      T *rin = rnl ? rnl + (size_t)cl * 2 * N : nullptr;
-      T *rout = rnl ? rnl + (size_t)(1 - cl) * 2 * N : nullptr;
-      launch_reverse<T>(h, level(k), lam + cl * SN, lam + (1 - cl) * SN, gk, dLdQ[sg * K + k],
-                        dens, rin, rout, stash, gsj);
+      for (int64_t k = 1; k < m && rc == LBM_OK; ++k) {
+        if (nc == 2) {
+          rc = copy_rs(levelR(k), levelS(k), levelR(k - 1), levelS(k - 1));
+          launch_recompute<T>(h, level(k - 1), level(k), levelR(k), levelS(k));
+        } else {
+          launch_recompute<T>(h, level(k - 1), level(k));
+        }
+      }
+    for (int64_t k = m - 1; k >= 0 && rc == LBM_OK; --k) {
+      Rev2<T> b{};
+      if (nc == 2) {
+        b.dens = dens;
+        b.stash = stash;
+        b.rnl_in = rnl + (size_t)cl * 2 * N;
+        b.rnl_out = rnl + (size_t)(1 - cl) * 2 * N;
+        b.r = levelR(k);
+        b.side = levelS(k);
+        b.gsj = gsj;
+        b.lr = lr;
+        b.gth = gth;
+      }
+      launch_reverse<T>(h, level(k), lam + cl * SN, lam + (1 - cl) * SN, gk, dLdQ[sg * K + k], b);
       cl = 1 - cl;
     }
     rc = hip_check(h, hipGetLastError(), "adjoint launches");
@@ -1251,7 +1455,8 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
     Timed tm(h, K_OTHER);
     hipLaunchKernelGGL(adj::k_adj_phi2, dim3(blocks(N)), dim3(256), 0, h->st,
                        (const double *)gbase, (const double *)gk0, (const double *)gsj,
-                       h->geom_phi, s.ptype, s.mask, h->geom_tabs, h->geom_meta, N, gp);
+                       (const double *)gth, h->geom_phi, s.ptype, s.mask, h->geom_tabs,
+                       h->geom_meta, h->p.c_max, h->p.c_min, N, gp);
     rc = hip_check(h, hipGetLastError(), "gradient kernel");
   }
   std::vector<double> qv;
