@@ -418,3 +418,107 @@ def test_two_component_adjoint_through_residual_events(collision, resistance):
     assert e < 1e-9
     same = np.array_equal(outs[0]["dL_dphi"], outs[1]["dL_dphi"])
     assert same
+
+
+def _fd_history2(L, wl, phi, steps):
+    lb = L.lbm_create(wl["params"])
+    lb.set_geometry(wl["cls"], phi, wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    q = np.zeros(steps)
+    for n in range(steps):
+        lb.step(1)
+        q[n] = lb.get_diagnostics()["q_w"]
+    side = lb.state_arrays(lb.get_state())["side"].copy()
+    lb.destroy()
+    return q, side
+
+
+def test_fullsize_two_component_gradient_against_gpu_finite_differences():
+    """96^3 two-component rock (the benchmark's generator, kappa = 0), fp64,
+    300 steps with residual transfers firing, squared water-flux misfit over
+    steps 100..300, checkpoints every 50: the adjoint's dL/dphi against
+    central differences of the GPU forward run, 3 gray voxels of large
+    gradient and 2 random (seed 5003).  With thousands of transfers a
+    perturbation can move one to another step (a switch the gradient does not
+    see; eps = 1e-4 does that at one of these voxels), so a voxel counts only
+    when its perturbed runs end with the base run's side flags and two step
+    sizes (1e-5, 5e-6) agree."""
+    import paper_2512_21696_amd as L
+    wl = W.adjoint_rock2(n=96, precision="f64", steps=300, window=100)
+    steps = wl["steps"]
+    announce(f"adjoint_rock2 96^3 fp64 {steps} steps: base run")
+    q0, side0 = _fd_history2(L, wl, wl["phi"], steps)
+    tgt = wl["target"](q0)
+    _, dLdQ = wl["loss_grad"](q0, tgt)
+    announce("adjoint_rock2 96^3 fp64: adjoint")
+    lb = L.lbm_create(wl["params"])
+    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    side_start = lb.state_arrays(lb.get_state())["side"].copy()
+    out = lb.adjoint_flux(steps, dLdQ, checkpoint_every=50)
+    lb.destroy()
+    assert np.array_equal(out["Q"], q0)
+    assert np.count_nonzero(side0 != side_start) > 100  # residual transfers fired
+    g = out["dL_dphi"]
+    gray = np.argwhere(wl["cls"] == 2)
+    t = wl["phi"][tuple(gray.T)] * 1024
+    cand = gray[np.minimum(t - np.floor(t), np.ceil(t) - t) > 0.2]
+    rng = np.random.default_rng(5003)
+    top = cand[np.argsort(np.abs(g[tuple(cand.T)]))[-60:]]
+    gmax = np.abs(g).max()
+    checked = {"top": 0, "random": 0}
+    order = [("top", tuple(v)) for v in top[rng.permutation(60)]]
+    order += [("random", tuple(v)) for v in cand[rng.permutation(len(cand))[:40]]]
+    for kind, v in order:
+        if checked[kind] >= (3 if kind == "top" else 2):
+            continue
+        announce(f"adjoint_rock2 96^3 finite difference at {v} ({kind})")
+        fds, same = [], True
+        for eps in (1e-5, 5e-6):
+            Ls = []
+            for sgn in (1, -1):
+                ph = wl["phi"].copy()
+                ph[v] += sgn * eps
+                q, sd = _fd_history2(L, wl, ph, steps)
+                same = same and np.array_equal(sd, side0)
+                Ls.append(wl["loss_grad"](q, tgt)[0])
+            fds.append((Ls[0] - Ls[1]) / (2 * eps))
+        fd = fds[0]
+        if not same or abs(fds[0] - fds[1]) > 1e-3 * abs(fd) + 1e-6 * gmax:
+            continue  # a residual transfer switched within reach
+        print(f"voxel {v}: adjoint {g[v]:.6e} fd {fd:.6e}")
+        assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
+        checked[kind] += 1
+        if checked["top"] >= 3 and checked["random"] >= 2:
+            break
+    assert checked["top"] >= 3 and checked["random"] >= 2
+
+
+
+def test_rock24_two_component_adjoint_with_events_matches_oracle():
+    """24^3 from the benchmark's rock generator (two components, kappa = 0),
+    fp64, 60 steps in which residual transfers fire, checkpoints every 7:
+    the gradient against the oracle's, element by element."""
+    import paper_2512_21696_amd as L
+    wl = W.adjoint_rock2(n=24, precision="f64", steps=60, window=20)
+    p = wl["params"]
+    a = np.linspace(1.0, 2.0, 60)
+    announce("adjoint_rock2 24^3 fp64 60 steps: oracle gradient (CPU)")
+    o = Oracle(p)
+    o.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    o.init_fluid(wl["rho_w"], wl["rho_o"])
+    qo, go, _ = A.flux_gradient2(p, wl["cls"], wl["phi"], wl["ptype"], wl["tables"], o.f.copy(),
+                                 o.r.copy(), 60, a, side=o.side.copy())
+    announce("adjoint_rock2 24^3 fp64 60 steps: GPU")
+    lb = L.lbm_create(p)
+    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    s0 = lb.state_arrays(lb.get_state())["side"].copy()
+    out = lb.adjoint_flux(60, a, checkpoint_every=7)
+    s1 = lb.state_arrays(lb.get_state())["side"]
+    lb.destroy()
+    assert np.count_nonzero(s1 != s0) > 10
+    assert np.abs(out["Q"] - qo).max() < 1e-13
+    e = norm_err(out["dL_dphi"], go)
+    print(f"rock 24^3 dL/dphi normalised error {e:.2e}")
+    assert e < 1e-9

@@ -378,6 +378,23 @@ def rev_domains(count: int = 96, seed: int = 4001, lmin: int = 24, lmax: int = 9
     return out
 
 
+def _flux_misfit(seed: int, steps: int, window: int):
+    """(target, loss_grad) of the squared flux misfit over steps >= window:
+    Q*(n) = 1.1 mean(q_base over the window) (1 + 0.02 xi_n), xi ~ N(0, 1)
+    (seed), and L = sum (Q - Q*)^2 with its gradient."""
+    xi = np.random.default_rng(seed).standard_normal(steps)
+    inside = np.arange(steps) >= window
+
+    def target(q_base):
+        return 1.1 * float(np.mean(np.asarray(q_base)[inside])) * (1.0 + 0.02 * xi)
+
+    def loss_grad(q, tgt):
+        d = np.where(inside, np.asarray(q, np.float64) - tgt, 0.0)
+        return float(np.sum(d * d)), 2.0 * d
+
+    return target, loss_grad
+
+
 def adjoint_rock(n: int = 96, seed: int = 5001, precision: str = "f32", steps: int = 800,
                  window: int = 200, tau: float = 1.0, g: float = 1e-5,
                  collision: str = "regularized", resistance: str = "implicit") -> dict:
@@ -395,16 +412,24 @@ def adjoint_rock(n: int = 96, seed: int = 5001, precision: str = "f32", steps: i
     p = Params(nx=n, ny=n, nz=n, ncomp=1, precision=precision, tau=(tau, tau), G=0.0,
                collision=collision, resistance=resistance, g=((g, 0.0, 0.0), (0.0, 0.0, 0.0)),
                kappa=0.0, outlet_x=n // 2).filled()
-    xi = np.random.default_rng(seed + 1).standard_normal(steps)
-    inside = np.arange(steps) >= window
-
-    def target(q_base):
-        return 1.1 * float(np.mean(np.asarray(q_base)[inside])) * (1.0 + 0.02 * xi)
-
-    def loss_grad(q, tgt):
-        d = np.where(inside, np.asarray(q, np.float64) - tgt, 0.0)
-        return float(np.sum(d * d)), 2.0 * d
-
+    target, loss_grad = _flux_misfit(seed + 1, steps, window)
     return dict(name=f"adjoint_rock_{n}", params=p, cls=base["cls"], phi=base["phi"],
                 ptype=base["ptype"], tables=base["tables"], rho_w=np.ones((n, n, n)),
                 rho_o=None, steps=steps, target=target, loss_grad=loss_grad)
+
+
+
+def adjoint_rock2(n: int = 96, seed: int = 5001, precision: str = "f32", steps: int = 800,
+                  window: int = 200) -> dict:
+    """The two-component porosity-gradient workload: the multiscale rock of
+    `multiscale_rock` at n^3 (seed) without the CSF control (kappa = 0; the
+    library's adjoint does not cover it), water buffer and body force as
+    there, outlet at x = n / 2; loss L = sum over steps n >= window of
+    (Q^w(n) - Q*(n))^2 with the seeded target of `adjoint_rock`
+    (`target(q_base)`, `loss_grad(q, target)`)."""
+    base = multiscale_rock(n=n, seed=seed, precision=precision, kappa=0.0)
+    p = base["params"]
+    p.outlet_x = n // 2
+    target, loss_grad = _flux_misfit(seed + 1, steps, window)
+    return dict(base, name=f"adjoint_rock2_{n}", params=p, steps=steps, target=target,
+                loss_grad=loss_grad)
