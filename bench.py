@@ -260,6 +260,8 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     import paper_2512_21696_amd as L
     if kind == "rock":
         wl = W.adjoint_rock(n=n, steps=steps, precision=precision)
+    elif kind == "rock2":
+        wl = W.adjoint_rock2(n=n, steps=steps, precision=precision)
     else:
         wl = W.fiber_bundles(n=n, precision=precision)
         wl["params"].outlet_x = n // 2
@@ -271,7 +273,7 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     gray_frac = float(np.sum(cls == 2)) / n_fluid
     lb = L.lbm_create(wl["params"])
     lb.set_geometry(cls, wl["phi"], wl["ptype"], wl["tables"])
-    lb.init_fluid(wl["rho_w"])
+    lb.init_fluid(wl["rho_w"], wl.get("rho_o"))
     start = lb.get_state()
     q = np.zeros(steps)
     for k in range(steps):
@@ -315,12 +317,23 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     # per fluid voxel: the recomputed set pulled, the adjoint set gathered and
     # written (storage type), the mask word; gray voxels read K0 and update
     # their fp64 dL/dK0, or (tensor) read K^-1 and update dL/dK^-1
-    b = 19 * es + 2 * 19 * es + 4 + gray_frac * ((es + 16) if kind == "rock" else (6 * es + 96))
+    nc = int(wl["params"].ncomp)
+    if nc == 1:
+        b = 19 * es + 2 * 19 * es + 4 + gray_frac * ((es + 16) if kind == "rock" else (6 * es + 96))
+    else:
+        # two components, the reverse step's two kernels (timed together):
+        # both sets pulled, both adjoint sets gathered and written (3 x 38),
+        # the level's densities read twice (2 + 2), the neighbour part read
+        # and written (2 + 2), the stash written and gathered (9 + 9), the
+        # mask twice; gray voxels read r (2), K0, s_J, theta (2), side flag and
+        # pore type, and update dL/dr and the dL/dK0, dL/ds_J accumulators
+        # (4 doubles read and written)
+        b = 2 * 19 * es * 3 + 26 * es + 8 + gray_frac * (6 * es + 2 + 64)
     adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
     achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
     g = out["dL_dphi"]
-    return {"workload": wl["name"], "storage": precision, "components": 1, "steps": steps,
-            "tensor": kind != "rock",
+    return {"workload": wl["name"], "storage": precision, "components": nc, "steps": steps,
+            "tensor": kind == "fiber",
             "checkpoint_every": every, "fluid_voxels": n_fluid,
             "gray_voxels": int(np.sum(cls == 2)), "loss": loss,
             "flux_history_equal": bool(np.array_equal(out["Q"], q)),
@@ -435,7 +448,7 @@ def main():
                          "cwrite} into the traffic record of --precision's workload (no GPU)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the porosity-gradient section and print its JSON, then exit")
-    ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "both"],
+    ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "rock2", "both"],
                     help="with --adjoint: which workload(s) to run")
     ap.add_argument("--drift", type=int, default=0, metavar="STEPS",
                     help="only run the storage precisions side by side for STEPS steps and "
@@ -462,6 +475,8 @@ def main():
             res["adjoint_gradient"] = adjoint_gradient()
         if args.adjoint_case in ("fiber", "both"):
             res["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
+        if args.adjoint_case in ("rock2", "both"):
+            res["adjoint_gradient_two_component"] = adjoint_gradient(kind="rock2")
         print(json.dumps(res), flush=True)
         return
 
@@ -638,6 +653,7 @@ def main():
         out["rev_library"] = rev_library()
         out["adjoint_gradient"] = adjoint_gradient()
         out["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
+        out["adjoint_gradient_two_component"] = adjoint_gradient(kind="rock2")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
         out["cpu_baseline"]["host"] = platform.processor() or platform.machine()

@@ -341,8 +341,8 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * components phi also enters the capillary term through the Leverett-J factor
  * s_J(phi) (Eq. (5)).  Calibrating phi (or the tables) against an observed flux
  * needs dL/dphi.  For one component, or two components without the CSF control
- * (kappa = 0) over a horizon without residual events (scalar K0 or tensor = 1,
- * periodic x faces, native fp64 or fp32 storage) and a loss
+ * (kappa = 0) (scalar K0 or tensor = 1, periodic x faces, native fp64 or fp32
+ * storage) and a loss
  * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
  * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
  * first component's post-collision populations of step n crossing
@@ -371,9 +371,11 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * that of the branch each voxel took (isotropic gate, |lambda| ordering, tie
  * test), exact away from those switches.  dL/dphi adds dL/dK0 times the
  * K0(phi) table's slope on the lookup's cell (the right-hand slope on a table
- * knot) and dL/ds_J times ds_J/dphi.  Residual events are switches with no
- * derivative: a two-component call checks after the forward sweep that no
- * residual amount or side flag changed, else returns LBM_E_UNSUPPORTED.
+ * knot) and dL/ds_J times ds_J/dphi.  The residual transfers are switches: the
+ * gradient is that of the branch each voxel took at each step (the scale
+ * factors and trapped amounts differentiated on it, dL/dr carried between
+ * steps, dL/dtheta_w and dL/dtheta_o taken to s_J through the crossings of
+ * s_J P_c), which is what finite differences see when no transfer moves.
  *
  * Arguments: nsteps >= 1; dL_dQ a host array of nsteps finite doubles;
  * checkpoint_every >= 1, or 0 for ceil(sqrt(nsteps)); Q_out (nsteps), dL_dK0 and
@@ -382,15 +384,16 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * freed before returning: ceil(nsteps / K) + K + 1 population-sized sets of
  * the storage type (19 N values per component, K = checkpoint_every: checkpoints, the
  * recomputed levels of one segment, two adjoint sets) plus 2 N doubles (scalar
- * K0) or 20 N doubles (tensor), and for two components 15 N values of the
- * storage type, N bytes and N doubles more.  The adjoint populations are kept
+ * K0) or 20 N doubles (tensor), and for two components, per kept level, the
+ * residual amounts and side flags (2 N values of the storage type and N
+ * bytes), plus 15 N values of the storage type and 5 N doubles.  The adjoint populations are kept
  * in the storage type, the reverse arithmetic and the gradient accumulation in
  * fp64.
  * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
  * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
  * fluid state), LBM_E_UNSUPPORTED (pressure x faces, 16-bit storage, two
- * components with kappa != 0 or with residual events within the horizon),
+ * components with kappa != 0),
  * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
