@@ -10,10 +10,11 @@ from . import lbm_create
 
 class FluxHistory(torch.autograd.Function):
     """Q = FluxHistory.apply(phi, run) with phi a float64 tensor [z, y, x]
-    (read on gray voxels) and run a dict holding the one-component "params",
-    "cls", "ptype", "tables", the initial density "rho" [z, y, x], "steps"
-    and optionally "checkpoint_every".  Returns the outlet flux of every step,
-    a float64 CPU tensor [steps].  The backward pass restarts from the same
+    (read on gray voxels) and run a dict holding "params", "cls", "ptype",
+    "tables", the initial density "rho" [z, y, x] (the water density, with
+    "rho_o" the oil density for two components), "steps" and optionally
+    "checkpoint_every".  Returns the (water) outlet flux of every step, a
+    float64 CPU tensor [steps].  The backward pass restarts from the same
     initial state and calls the library's adjoint with the incoming dL/dQ."""
 
     @staticmethod
@@ -22,7 +23,7 @@ class FluxHistory(torch.autograd.Function):
         lb = lbm_create(run["params"])
         try:
             lb.set_geometry(run["cls"], ph, run["ptype"], run["tables"])
-            lb.init_fluid(run["rho"])
+            lb.init_fluid(run["rho"], run.get("rho_o"))
             start = lb.get_state()
             q = np.zeros(int(run["steps"]), np.float64)
             for n in range(q.size):
