@@ -326,12 +326,14 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
   const int x1 = mc.outlet_x + 1 == mc.nx ? 0 : mc.outlet_x + 1;
   const bool at0 = nb.x == mc.outlet_x, at1 = nb.x == x1;
-  const double cs2 = CS2, cs4 = CS2 * CS2;
+  const double cs2 = CS2;
+  constexpr double ics2 = 3.0, ics4 = 9.0;  // 1 / c_s^2, 1 / c_s^4
 
   // pulls, moments and the gathered adjoint of the post-collision sets
   double rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
   double Pi[2][6], lf[2];  // second moments (regularised), sum_i lam_i f_i (BGK)
   double lp[REG ? 1 : 2][REG ? 1 : Q];
+  const uint32_t N32 = (uint32_t)N, v32 = (uint32_t)v;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const T *pa = post + (size_t)a * Q * N;
@@ -342,8 +344,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const int j = opp(i);
-      const double fi = (double)(((mk >> j) & 1u) ? pa[(size_t)j * N + v]
-                                                  : pa[(size_t)i * N + nb.at(-cx(i), -cy(i), -cz(i))]);
+      const uint32_t src = ((mk >> j) & 1u) ? (uint32_t)j * N32 + v32
+                                            : (uint32_t)i * N32 + (uint32_t)nb.at(-cx(i), -cy(i), -cz(i));
+      const double fi = (double)pa[src];
       rho[a] += fi;
       if (cx(i)) m[a][0] += cx(i) * fi;
       if (cy(i)) m[a][1] += cy(i) * fi;
@@ -357,15 +360,11 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         if (cy(i) && cz(i)) Pi[a][5] += (cy(i) * cz(i)) * fi;
       }
       const bool wall = (mk >> i) & 1u;
-      double l;
-      if (wall) {
-        l = (double)la[(size_t)j * N + v] + (double)rnl[2 * v + a];
-      } else {
-        const int y = nb.at(cx(i), cy(i), cz(i));
-        l = (double)la[(size_t)i * N + y] + (double)rnl[2 * (size_t)y + a];
-        if (a == 0 && at0 && cx(i) == 1) l += an;
-        if (a == 0 && at1 && cx(i) == -1) l -= an;
-      }
+      const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
+      const uint32_t li = wall ? (uint32_t)j * N32 + v32 : (uint32_t)i * N32 + y;
+      double l = (double)la[li] + (double)rnl[2 * y + a];
+      if (a == 0 && cx(i) == 1 && at0 && !wall) l += an;
+      if (a == 0 && cx(i) == -1 && at1 && !wall) l -= an;
       if (!REG) {
         lp[REG ? 0 : a][REG ? 0 : i] = l;
         lf[a] += l * fi;
@@ -383,8 +382,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 
   // forward quantities
   const double rt = rho[0] + rho[1], irt = 1.0 / rt;
+  const double irho[2] = {1.0 / rho[0], 1.0 / rho[1]};
   const double h = mc.res_implicit ? 1.0 : 0.5;
-  const double span = 1.0 / mc.inv_span;
+  const double ispan = mc.inv_span;
   double Fex[2][3], acc[2][3];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -394,7 +394,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     double s0 = 0, s1 = 0, s2 = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const double psi = ((mk >> i) & 1u) ? pw : (double)rho2[2 * (size_t)nb.at(cx(i), cy(i), cz(i)) + b];
+      const bool wall = (mk >> i) & 1u;
+      const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
+      const double nbv = (double)rho2[2 * y + b];  // this voxel's own entry across a wall
+      const double psi = wall ? pw : nbv;
       if (cx(i)) s0 += wq(i) * cx(i) * psi;
       if (cy(i)) s1 += wq(i) * cy(i) * psi;
       if (cz(i)) s2 += wq(i) * cz(i) * psi;
@@ -404,21 +407,19 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   }
   // gray: saturation, tables, capillary force, resistance coefficient
   double S = 0, Sraw = 0, tw = 0, to = 0, gS[3] = {0, 0, 0}, Pct = 0, dPct = 0, Krw = 0,
-         dKrw = 0, Kro = 0, dKro = 0, sj = 0, Pc = 0, kw = 1, ko = 1, cR = 0;
-  const double shat0 = (rho[0] * irt - mc.s_min) / span;
+         dKrw = 0, Kro = 0, dKro = 0, sj = 0, Pc = 0, kw = 1, ko = 1, ikw = 1, iko = 1, cR = 0;
+  const double shat0 = (rho[0] * irt - mc.s_min) * ispan;
   if (gray) {
     tw = rho[0] + (double)rres[v];
     to = rho[1] + (double)rres[N + v];
-    Sraw = (tw / (tw + to) - mc.s_min) / span;
+    Sraw = (tw / (tw + to) - mc.s_min) * ispan;
     S = Sraw < 0.0 ? 0.0 : (Sraw > 1.0 ? 1.0 : Sraw);
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      double val = shat0;
-      if (!((mk >> i) & 1u)) {
-        const size_t u = 2 * (size_t)nb.at(cx(i), cy(i), cz(i));
-        const double aw = (double)rho2[u], ao = (double)rho2[u + 1];
-        val = (aw / (aw + ao) - mc.s_min) / span;
-      }
+      const bool wall = (mk >> i) & 1u;
+      const uint32_t u = 2 * (wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i)));
+      const double aw = (double)rho2[u], ao = (double)rho2[u + 1];
+      const double val = wall ? shat0 : (aw / (aw + ao) - mc.s_min) * mc.inv_span;
       if (cx(i)) gS[0] += gw(i) * cx(i) * val;
       if (cy(i)) gS[1] += gw(i) * cy(i) * val;
       if (cz(i)) gS[2] += gw(i) * cz(i) * val;
@@ -442,8 +443,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       for (int d = 0; d < 3; ++d) Fex[a][d] += -Pc * (rho[a] * irt) * gS[d];
     kw = Krw > mc.kr_min ? Krw : mc.kr_min;
     ko = Kro > mc.kr_min ? Kro : mc.kr_min;
-    const double cw = S > 0.0 ? rt * S * mc.nu[0] / kw : 0.0;
-    const double co = 1.0 - S > 0.0 ? rt * (1.0 - S) * mc.nu[1] / ko : 0.0;
+    ikw = 1.0 / kw;
+    iko = 1.0 / ko;
+    const double cw = S > 0.0 ? rt * S * mc.nu[0] * ikw : 0.0;
+    const double co = 1.0 - S > 0.0 ? rt * (1.0 - S) * mc.nu[1] * iko : 0.0;
     cR = cw + co;
   }
   // resistance
@@ -478,11 +481,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   } else {
     if (gray) {
       k0 = (double)K0[v];
-      Rs = cR / k0;
+      Rs = cR / k0;  // once per voxel
     }
     den = rt + h * Rs;
+    const double idn0 = 1.0 / den;
     for (int d = 0; d < 3; ++d) {
-      u[d] = bvec[d] / den;
+      u[d] = bvec[d] * idn0;
       Ru[d] = Rs * u[d];
     }
   }
@@ -490,9 +494,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   for (int a = 0; a < 2; ++a)
     for (int d = 0; d < 3; ++d) F[a][d] = Fex[a][d] - (rho[a] * irt) * Ru[d];
   const double om[2] = {mc.omega[0], mc.omega[1]};
-  const double D = om[0] * rho[0] + om[1] * rho[1];
+  const double D = om[0] * rho[0] + om[1] * rho[1], iD = 1.0 / D;
   double up[3];
-  for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) / D;
+  for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) * iD;
   const double usq = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
 
   // residual transfer: which branch, the scale factors, and dL/ds^a =
@@ -510,24 +514,24 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     ro0 = (double)rres[N + v];
     const double rhoT = tw + to, mm = mc.m_minor;
     if (ev == 1) {
-      sc[0] = (rho[0] + rw0) / rho[0];
+      sc[0] = (rho[0] + rw0) * irho[0];
       double d = (double)tho[v] * rhoT - ro0;
       const double cap = rho[1] - mm;
       d = d < cap ? d : cap;
       dtr = d > 0.0 ? d : 0.0;
-      sc[1] = 1.0 - dtr / rho[1];
+      sc[1] = 1.0 - dtr * irho[1];
     } else {
-      sc[1] = (rho[1] + ro0) / rho[1];
+      sc[1] = (rho[1] + ro0) * irho[1];
       double d = (double)thw[v] * rhoT - rw0;
       const double cap = rho[0] - mm;
       d = d < cap ? d : cap;
       dtr = d > 0.0 ? d : 0.0;
-      sc[0] = 1.0 - dtr / rho[0];
+      sc[0] = 1.0 - dtr * irho[0];
     }
     for (int a = 0; a < 2; ++a) {
       const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a], ra = rho[a];
       double ua[3];
-      for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * 0.5 / ra;
+      for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * 0.5 * irho[a];
       double uF = 0, pl = 0, FL = 0;
       for (int d = 0; d < 3; ++d) {
         uF += ua[d] * F[a][d];
@@ -543,8 +547,8 @@ __global__ __launch_bounds__(256) void k_adj_step2(
           aMF += ua[i] * Mm[i][j] * F[a][j];
         }
       // equilibrium and force parts of A L0 + B.L1 + C:M
-      double phi_a = e * ra * (1.0 - usq / (2 * cs2)) * L0[a] - uF / cs2 * L0[a] +
-                     e * ra * pl / cs2 + FL / cs2 + e * ra * uMu / (2 * cs4) + aMF / cs4;
+      double phi_a = e * ra * (1.0 - usq * (0.5 * ics2)) * L0[a] - uF * ics2 * L0[a] +
+                     e * ra * pl * ics2 + FL * ics2 + e * ra * uMu * (0.5 * ics4) + aMF * ics4;
       if (REG) {
         const double *P = Pi[a];
         const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
@@ -557,7 +561,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
           }
           jl += (m[a][i] - ra * up[i]) * L1[a][i];
         }
-        phi_a += keep * (-tr / (2 * cs2) * L0[a] + jl / cs2 + PM / (2 * cs4));
+        phi_a += keep * (-tr * (0.5 * ics2) * L0[a] + jl * ics2 + PM * (0.5 * ics4));
       } else {
         phi_a += keep * lf[a];
       }
@@ -576,33 +580,33 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a];
-    const double ra = rho[a], ir2 = 0.5 / ra;
+    const double ra = rho[a], ir2 = 0.5 * irho[a];
     double ua[3];
     for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * ir2;
     const double *Mv = M2[a];
     const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
     double Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0};
-    rb[a] += e * (1.0 - usq / (2 * cs2)) * L0[a];
-    usqb += -e * ra / (2 * cs2) * L0[a];
-    const double uFb = -L0[a] / cs2;
+    rb[a] += e * (1.0 - usq * (0.5 * ics2)) * L0[a];
+    usqb += -e * ra * (0.5 * ics2) * L0[a];
+    const double uFb = -L0[a] * ics2;
     double pl = 0, pMp = 0;
     for (int d = 0; d < 3; ++d) pl += up[d] * L1[a][d];
-    rb[a] += e * pl / cs2;
+    rb[a] += e * pl * ics2;
     for (int d = 0; d < 3; ++d) {
-      upb[d] += e * ra * L1[a][d] / cs2;
-      Fbar[d] += L1[a][d] / cs2;
+      upb[d] += e * ra * L1[a][d] * ics2;
+      Fbar[d] += L1[a][d] * ics2;
     }
     for (int i = 0; i < 3; ++i) {
       const double Mu = Mm[i][0] * up[0] + Mm[i][1] * up[1] + Mm[i][2] * up[2];
       pMp += up[i] * Mu;
-      upb[i] += e * ra * Mu / cs4;
-      uab[i] += (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) / cs4;
-      Fbar[i] += (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) / cs4;
+      upb[i] += e * ra * Mu * ics4;
+      uab[i] += (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) * ics4;
+      Fbar[i] += (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) * ics4;
     }
-    rb[a] += e * pMp / (2 * cs4);
+    rb[a] += e * pMp * (0.5 * ics4);
     for (int d = 0; d < 6; ++d) Pb[a][d] = 0;
     if (REG) {
-      const double c = keep / (2 * cs4), dd = -keep / (2 * cs2) * L0[a];
+      const double c = keep * (0.5 * ics4), dd = -keep * (0.5 * ics2) * L0[a];
       double B[3][3];
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) B[i][j] = c * Mm[i][j] + (i == j ? dd : 0.0);
@@ -618,7 +622,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       // first-order part j^a = m^a - rho^a u'
       double pj = 0;
       for (int d = 0; d < 3; ++d) {
-        const double jb = keep * L1[a][d] / cs2;
+        const double jb = keep * L1[a][d] * ics2;
         mb[a][d] += jb;
         pj += up[d] * jb;
         upb[d] += -ra * jb;
@@ -633,7 +637,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       Fbar[d] += uab[d] * ir2;
       abF += uab[d] * F[a][d];
     }
-    rb[a] += -abF * ir2 / ra;
+    rb[a] += -abF * ir2 * irho[a];
     for (int d = 0; d < 3; ++d) Fb[a][d] = Fbar[d];
   }
   for (int d = 0; d < 3; ++d) upb[d] += 2.0 * up[d] * usqb;
@@ -641,8 +645,8 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     double pu = 0;
     for (int d = 0; d < 3; ++d) pu += upb[d] * up[d];
     for (int a = 0; a < 2; ++a) {
-      for (int d = 0; d < 3; ++d) mb[a][d] += om[a] * upb[d] / D;
-      rb[a] += -om[a] * pu / D;
+      for (int d = 0; d < 3; ++d) mb[a][d] += om[a] * upb[d] * iD;
+      rb[a] += -om[a] * pu * iD;
     }
   }
   // F^a = F_ex^a - (rho^a / rho_t) R u
@@ -697,8 +701,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     rtb += denb;
     Rsb += h * denb;
     if (gray) {
-      cRb = Rsb / k0;
-      gk[v] += -Rsb * cR / (k0 * k0);
+      const double ik0 = 1.0 / k0;
+      cRb = Rsb * ik0;
+      gk[v] += -Rsb * cR * ik0 * ik0;
     }
   }
   for (int a = 0; a < 2; ++a)
@@ -726,8 +731,8 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       double wsum = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        if (!((mk >> i) & 1u)) continue;
-        wsum += wq(i) * (cx(i) * accb[0] + cy(i) * accb[1] + cz(i) * accb[2]);
+        const double t = wq(i) * (cx(i) * accb[0] + cy(i) * accb[1] + cz(i) * accb[2]);
+        wsum += ((mk >> i) & 1u) ? t : 0.0;
       }
       rb[b] += wsum;
     }
@@ -743,32 +748,32 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     // c_R
     double Sb = 0;
     if (S > 0.0) {
-      rtb += cRb * S * mc.nu[0] / kw;
-      Sb += cRb * rt * mc.nu[0] / kw;
-      if (Krw > mc.kr_min) Sb += -cRb * rt * S * mc.nu[0] / (kw * kw) * dKrw;
+      rtb += cRb * S * mc.nu[0] * ikw;
+      Sb += cRb * rt * mc.nu[0] * ikw;
+      if (Krw > mc.kr_min) Sb += -cRb * rt * S * mc.nu[0] * ikw * ikw * dKrw;
     }
     if (1.0 - S > 0.0) {
-      rtb += cRb * (1.0 - S) * mc.nu[1] / ko;
-      Sb += -cRb * rt * mc.nu[1] / ko;
-      if (Kro > mc.kr_min) Sb += -cRb * rt * (1.0 - S) * mc.nu[1] / (ko * ko) * dKro;
+      rtb += cRb * (1.0 - S) * mc.nu[1] * iko;
+      Sb += -cRb * rt * mc.nu[1] * iko;
+      if (Kro > mc.kr_min) Sb += -cRb * rt * (1.0 - S) * mc.nu[1] * iko * iko * dKro;
     }
     // P_c = s_J P_c(S)
     gsj[v] += Pcb * Pct;
     Sb += Pcb * sj * dPct;
     if (Sraw > 0.0 && Sraw < 1.0) {
-      const double tt = tw + to, sb = Sb / span;
-      twb += sb * to / (tt * tt);
-      tob += -sb * tw / (tt * tt);
+      const double itt = 1.0 / (tw + to), sb = Sb * ispan;
+      twb += sb * to * itt * itt;
+      tob += -sb * tw * itt * itt;
     }
     // grad S_hat: the links to solid neighbours read this voxel's S_hat
     double shb = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      if (!((mk >> i) & 1u)) continue;
-      shb += gw(i) * (cx(i) * gSb[0] + cy(i) * gSb[1] + cz(i) * gSb[2]);
+      const double t = gw(i) * (cx(i) * gSb[0] + cy(i) * gSb[1] + cz(i) * gSb[2]);
+      shb += ((mk >> i) & 1u) ? t : 0.0;
     }
-    rb[0] += shb / span * rho[1] * irt * irt;
-    rb[1] += -shb / span * rho[0] * irt * irt;
+    rb[0] += shb * ispan * rho[1] * irt * irt;
+    rb[1] += -shb * ispan * rho[0] * irt * irt;
   }
   rb[0] += rtb;
   rb[1] += rtb;
@@ -780,10 +785,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       const double rhoT = tw + to;
       double db = 0.0, rTb = 0.0;
       if (ev == 1) {
-        rb[0] += scb[0] * (-rw0 / (rho[0] * rho[0]));
-        rbw += scb[0] / rho[0];
-        db += -scb[1] / rho[1];
-        rb[1] += scb[1] * dtr / (rho[1] * rho[1]);
+        rb[0] += scb[0] * (-rw0 * irho[0] * irho[0]);
+        rbw += scb[0] * irho[0];
+        db += -scb[1] * irho[1];
+        rb[1] += scb[1] * dtr * irho[1] * irho[1];
         rbo += lo_;  // r^o <- r^o + d; r^w <- 0
         db += lo_;
         const double raw = (double)tho[v] * rhoT - ro0, cap = rho[1] - mc.m_minor;
@@ -795,10 +800,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
           rb[1] += db;
         }
       } else {
-        rb[1] += scb[1] * (-ro0 / (rho[1] * rho[1]));
-        rbo += scb[1] / rho[1];
-        db += -scb[0] / rho[0];
-        rb[0] += scb[0] * dtr / (rho[0] * rho[0]);
+        rb[1] += scb[1] * (-ro0 * irho[1] * irho[1]);
+        rbo += scb[1] * irho[1];
+        db += -scb[0] * irho[0];
+        rb[0] += scb[0] * dtr * irho[0] * irho[0];
         rbw += lw;  // r^w <- r^w + d; r^o <- 0
         db += lw;
         const double raw = (double)thw[v] * rhoT - rw0, cap = rho[0] - mc.m_minor;
