@@ -79,14 +79,16 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const int j = opp(i);
-    const double fi = (double)(((mk >> j) & 1u)
-                                   ? post[(size_t)j * N + v]
-                                   : post[(size_t)i * N + nb.at(-cx(i), -cy(i), -cz(i))]);
+    const uint32_t N32 = (uint32_t)N, v32 = (uint32_t)v;
+    const uint32_t src = ((mk >> j) & 1u) ? (uint32_t)j * N32 + v32
+                                          : (uint32_t)i * N32 + (uint32_t)nb.at(-cx(i), -cy(i), -cz(i));
+    const double fi = (double)post[src];
     const bool wall = (mk >> i) & 1u;
-    double l = (double)(wall ? lin[(size_t)j * N + v]
-                             : lin[(size_t)i * N + nb.at(cx(i), cy(i), cz(i))]);
-    if (!wall && at0 && cx(i) == 1) l += a;
-    if (!wall && at1 && cx(i) == -1) l -= a;
+    const uint32_t li = wall ? (uint32_t)j * N32 + v32
+                             : (uint32_t)i * N32 + (uint32_t)nb.at(cx(i), cy(i), cz(i));
+    double l = (double)lin[li];
+    if (cx(i) == 1 && at0 && !wall) l += a;
+    if (cx(i) == -1 && at1 && !wall) l -= a;
     lp[i] = l;
     rho += fi;
     if (cx(i)) m0 += cx(i) * fi;
@@ -103,7 +105,8 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   }
 
   // forward quantities of the voxel
-  const double cs2 = CS2, cs4 = CS2 * CS2;
+  const double cs2 = CS2;
+  constexpr double ics2 = 3.0, ics4 = 9.0;  // 1 / c_s^2, 1 / c_s^4
   const double om = mc.omega[0], keep = 1.0 - om, e = REG ? 1.0 : om;
   const double h = mc.res_implicit ? 1.0 : 0.5;
   const double g0 = mc.g[0][0], g1 = mc.g[0][1], g2 = mc.g[0][2];
@@ -157,29 +160,29 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   // reverse sweep of Phi
   double rb = 0, pb0 = 0, pb1 = 0, pb2 = 0, Fb0 = 0, Fb1 = 0, Fb2 = 0, ab0 = 0, ab1 = 0, ab2 = 0;
   // A terms
-  rb += e * (1.0 - usq / (2 * cs2)) * L0;
-  const double usqb = -e * rho / (2 * cs2) * L0;
-  const double uFb = -L0 / cs2;
+  rb += e * (1.0 - usq * (0.5 * ics2)) * L0;
+  const double usqb = -e * rho * (0.5 * ics2) * L0;
+  const double uFb = -L0 * ics2;
   // B terms
-  rb += e * (p0 * L1x + p1 * L1y + p2 * L1z) / cs2;
-  pb0 += e * rho * L1x / cs2; pb1 += e * rho * L1y / cs2; pb2 += e * rho * L1z / cs2;
-  Fb0 += L1x / cs2; Fb1 += L1y / cs2; Fb2 += L1z / cs2;
+  rb += e * (p0 * L1x + p1 * L1y + p2 * L1z) * ics2;
+  pb0 += e * rho * L1x * ics2; pb1 += e * rho * L1y * ics2; pb2 += e * rho * L1z * ics2;
+  Fb0 += L1x * ics2; Fb1 += L1y * ics2; Fb2 += L1z * ics2;
   // C terms (M = Lambda2, symmetric)
   const double Mp0 = Mxx * p0 + Mxy * p1 + Mxz * p2;
   const double Mp1 = Mxy * p0 + Myy * p1 + Myz * p2;
   const double Mp2 = Mxz * p0 + Myz * p1 + Mzz * p2;
-  rb += e * (p0 * Mp0 + p1 * Mp1 + p2 * Mp2) / (2 * cs4);
-  pb0 += e * rho * Mp0 / cs4; pb1 += e * rho * Mp1 / cs4; pb2 += e * rho * Mp2 / cs4;
-  ab0 += (Mxx * F0 + Mxy * F1 + Mxz * F2) / cs4;
-  ab1 += (Mxy * F0 + Myy * F1 + Myz * F2) / cs4;
-  ab2 += (Mxz * F0 + Myz * F1 + Mzz * F2) / cs4;
-  Fb0 += (Mxx * a0 + Mxy * a1 + Mxz * a2) / cs4;
-  Fb1 += (Mxy * a0 + Myy * a1 + Myz * a2) / cs4;
-  Fb2 += (Mxz * a0 + Myz * a1 + Mzz * a2) / cs4;
+  rb += e * (p0 * Mp0 + p1 * Mp1 + p2 * Mp2) * (0.5 * ics4);
+  pb0 += e * rho * Mp0 * ics4; pb1 += e * rho * Mp1 * ics4; pb2 += e * rho * Mp2 * ics4;
+  ab0 += (Mxx * F0 + Mxy * F1 + Mxz * F2) * ics4;
+  ab1 += (Mxy * F0 + Myy * F1 + Myz * F2) * ics4;
+  ab2 += (Mxz * F0 + Myz * F1 + Mzz * F2) * ics4;
+  Fb0 += (Mxx * a0 + Mxy * a1 + Mxz * a2) * ics4;
+  Fb1 += (Mxy * a0 + Myy * a1 + Myz * a2) * ics4;
+  Fb2 += (Mxz * a0 + Myz * a1 + Mzz * a2) * ics4;
   // regularised non-equilibrium: dPhi/dP, which is also dPhi/dPi
   double Bxx = 0, Byy = 0, Bzz = 0, Bxy = 0, Bxz = 0, Byz = 0;
   if (REG) {
-    const double c = keep / (2 * cs4), d = -keep / (2 * cs2) * L0;
+    const double c = keep * (0.5 * ics4), d = -keep * (0.5 * ics2) * L0;
     Bxx = c * Mxx + d; Byy = c * Myy + d; Bzz = c * Mzz + d;
     Bxy = c * Mxy; Bxz = c * Mxz; Byz = c * Myz;
     const double Bp0 = Bxx * p0 + Bxy * p1 + Bxz * p2;
