@@ -13,7 +13,8 @@ class FluxHistory(torch.autograd.Function):
     (read on gray voxels) and run a dict holding "params", "cls", "ptype",
     "tables", the initial density "rho" [z, y, x] (the water density, with
     "rho_o" the oil density for two components), "steps" and optionally
-    "checkpoint_every".  Returns the (water) outlet flux of every step, a
+    "checkpoint_every" and "start_state" (a state blob loaded after the
+    initialisation, e.g. residual amounts and side flags of a running job).  Returns the (water) outlet flux of every step, a
     float64 CPU tensor [steps].  The backward pass restarts from the same
     initial state and calls the library's adjoint with the incoming dL/dQ."""
 
@@ -24,6 +25,8 @@ class FluxHistory(torch.autograd.Function):
         try:
             lb.set_geometry(run["cls"], ph, run["ptype"], run["tables"])
             lb.init_fluid(run["rho"], run.get("rho_o"))
+            if run.get("start_state") is not None:
+                lb.set_state(run["start_state"])
             start = lb.get_state()
             q = np.zeros(int(run["steps"]), np.float64)
             for n in range(q.size):
