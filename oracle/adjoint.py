@@ -247,8 +247,10 @@ def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
 
 
 class TwoComponent(OneComponent):
-    """The two-component step in torch (Sec. II without the CSF control, kappa
-    = 0): the pseudo-potential force with wall virtual densities, the
+    """The two-component step in torch (Sec. II): the pseudo-potential force
+    with wall virtual densities, the CSF surface-tension control of Eq. (4)
+    (normals of the other component's density gradient, curvature as their
+    divergence, both with the voxel's own value across a solid link), the
     capillary term of Eq. (1) with P_c = s_J(phi) P_c(S) and the gradient of
     the mobile saturation, the resistance c_R = sum_b rho S^b nu^b / max(Kr^b,
     Kr_min) with K0(phi) or K^-1(phi), the common velocity u' and per-component
@@ -262,8 +264,7 @@ class TwoComponent(OneComponent):
     def __init__(self, params, cls, ptype, tables, r):
         super().__init__(params, cls, ptype, tables)
         p = params
-        if float(getattr(p, "kappa", 0.0)) != 0.0:
-            raise ValueError("the reference gradient covers kappa = 0")
+        self.region = torch.as_tensor(self.cls == GRAY) if p.csf_region == "gray" else self.fluid
         self.taus = [float(t) for t in p.tau]
         self.gs = [[float(v) for v in p.g[a]] for a in range(2)]
         self.r = torch.as_tensor(np.asarray(r, np.float64))
@@ -284,6 +285,16 @@ class TwoComponent(OneComponent):
 
     def _nb(self, X, i):
         return torch.where(self.nb_solid[i], X, _sh(X, C[i]))
+
+    def _grad(self, X):
+        """Isotropic gradient with the voxel's own value across a solid link."""
+        g = [0.0, 0.0, 0.0]
+        for i in range(1, Q):
+            v = self._nb(X, i)
+            for d in range(3):
+                if C[i, d]:
+                    g[d] = g[d] + (W[i] * C[i, d] / CS2) * v
+        return g
 
     def thetas(self, sJ):
         """theta_w, theta_o of the gray voxels as functions of s_J: the smallest
@@ -354,6 +365,23 @@ class TwoComponent(OneComponent):
                         acc[d] = acc[d] + W[i] * C[i, d] * psi
             for d in range(3):
                 F_ex[a][d] = F_ex[a][d] - p.G * rho[a] * acc[d]
+        if p.kappa != 0.0:
+            for a in range(2):
+                b = 1 - a
+                gr = self._grad(rho[b])
+                nrm = torch.sqrt(gr[0] ** 2 + gr[1] ** 2 + gr[2] ** 2)
+                big = nrm > p.eps_n
+                safe_n = torch.where(big, nrm, torch.ones_like(nrm))
+                nhat = [torch.where(big, gr[d] / safe_n, torch.zeros_like(nrm)) for d in range(3)]
+                div = 0.0
+                for i in range(1, Q):
+                    for d in range(3):
+                        if C[i, d]:
+                            div = div + (W[i] * C[i, d] / CS2) * self._nb(nhat[d], i)
+                curv = -div
+                for d in range(3):
+                    fc = p.kappa * curv * gr[d] * rho[a] / (p.phi_avg * p.phi_max)
+                    F_ex[a][d] = F_ex[a][d] + torch.where(self.region, fc, torch.zeros_like(fc))
         gS = [0.0, 0.0, 0.0]
         for i in range(1, Q):
             v = self._nb(S_hat, i)

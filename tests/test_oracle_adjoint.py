@@ -265,14 +265,17 @@ def _event_history(p, cls, phi, pt, tabs, rw, ro, side, r, steps):
     return f0, np.array(q), o.f, o.r, events
 
 
-def test_two_component_with_residual_events():
-    """Residual transfers (trap and release) fire in this horizon: the torch
-    transcription follows the numpy oracle through them (theta_w, theta_o as
-    functions of s_J equal the set-up's crossings), and its gradient, that of
-    the branch each voxel took, matches central finite differences of the
-    oracle at voxels whose perturbed runs take the same branches."""
+@pytest.mark.parametrize("kappa,region", [(0.0, "gray"), (-0.05, "gray"), (0.03, "all")])
+def test_two_component_with_residual_events(kappa, region):
+    """Residual transfers (trap and release) fire in this horizon, with and
+    without the CSF control: the torch transcription follows the numpy oracle
+    through them (theta_w, theta_o as functions of s_J equal the set-up's
+    crossings), and its gradient, that of the branch each voxel took, matches
+    central finite differences of the oracle at voxels whose perturbed runs
+    take the same branches."""
     import torch
     p, cls, phi, pt, tabs, rw, ro = two_case()
+    p.kappa, p.csf_region = kappa, region
     side, r = event_state(p, cls, phi, pt, tabs, rw, ro)
     steps = 10
     a = np.linspace(1.0, 2.0, steps)
