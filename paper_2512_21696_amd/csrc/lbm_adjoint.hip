@@ -309,8 +309,9 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
 template <typename T, bool REG, bool TENS>
 __global__ __launch_bounds__(256) void k_adj_step2(
     const ModelConsts mc, const T *__restrict__ post, const T *__restrict__ rho2,
-    const T *__restrict__ rres, const uint8_t *__restrict__ side, const T *__restrict__ lin,
-    const T *__restrict__ rnl, T *__restrict__ lout, T *__restrict__ stash,
+    const T *__restrict__ rres, const uint8_t *__restrict__ side, const T *__restrict__ nrmb,
+    const T *__restrict__ lin, const T *__restrict__ rnl, T *__restrict__ lout,
+    T *__restrict__ stash,
     const uint32_t *__restrict__ mask, const T *__restrict__ K0, const T *__restrict__ Kinv,
     const T *__restrict__ sJ, const T *__restrict__ thw, const T *__restrict__ tho,
     const uint8_t *__restrict__ ptype, const T *__restrict__ tab, double *__restrict__ gk,
@@ -407,6 +408,29 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
     acc[a][0] = s0; acc[a][1] = s1; acc[a][2] = s2;
     for (int d = 0; d < 3; ++d) Fex[a][d] = rho[a] * mc.g[a][d] - mc.G * rho[a] * acc[a][d];
+  }
+  // CSF control, Eq. (4), on the region's voxels: g^a = grad rho^b and the
+  // normals n^a = g^a / |g^a| of the level (nrmb rows 6a..6a+2: g, 6a+3..: n),
+  // curv^a = -div n^a (own normal across a solid link), F^a += kap curv g rho^a
+  const bool csfv = mc.kappa != 0.0 && (gray || mc.csf_all);
+  const double kap = mc.kappa * mc.csf_scale;
+  double cg[2][3] = {{0, 0, 0}, {0, 0, 0}}, curv[2] = {0, 0};
+  if (csfv) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      for (int d = 0; d < 3; ++d) cg[a][d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
+      double dv = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const bool wall = (mk >> i) & 1u;
+        const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
+        if (cx(i)) dv += gw(i) * cx(i) * (double)nrmb[(size_t)(6 * a + 3) * N + y];
+        if (cy(i)) dv += gw(i) * cy(i) * (double)nrmb[(size_t)(6 * a + 4) * N + y];
+        if (cz(i)) dv += gw(i) * cz(i) * (double)nrmb[(size_t)(6 * a + 5) * N + y];
+      }
+      curv[a] = -dv;
+      for (int d = 0; d < 3; ++d) Fex[a][d] += kap * curv[a] * cg[a][d] * rho[a];
+    }
   }
   // gray: saturation, tables, capillary force, resistance coefficient
   double S = 0, Sraw = 0, tw = 0, to = 0, gS[3] = {0, 0, 0}, Pct = 0, dPct = 0, Krw = 0,
@@ -714,6 +738,22 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       mb[a][d] += bb[d];
       Fexb[a][d] += h * bb[d];
     }
+  // CSF: this voxel's part; dL/dcurv^a and dL/dg^a of the force term are
+  // stashed (rows 9, 10 and 11..16) for the normals' and gradients' reverse
+  if (mc.kappa != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double cb = 0.0, gb[3] = {0, 0, 0};
+      if (csfv) {
+        const double gFc = cg[a][0] * Fexb[a][0] + cg[a][1] * Fexb[a][1] + cg[a][2] * Fexb[a][2];
+        rb[a] += kap * curv[a] * gFc;
+        cb = kap * rho[a] * gFc;
+        for (int d = 0; d < 3; ++d) gb[d] = kap * curv[a] * rho[a] * Fexb[a][d];
+      }
+      stash[(size_t)(9 + a) * N + v] = (T)cb;
+      for (int d = 0; d < 3; ++d) stash[(size_t)(11 + 3 * a + d) * N + v] = (T)gb[d];
+    }
+  }
   // F_ex: body force, pseudo-potential force (own part; the neighbours'
   // part is stashed), capillary term
   double gSb[3] = {0, 0, 0}, Pcb = 0;
@@ -855,9 +895,95 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   }
 }
 
+// The CSF normals of a level from its density field: per component a the
+// gradient g^a of rho^b (b = 1 - a; the voxel's own value across a solid link)
+// and n^a = g^a / |g^a| (0 when |g^a| <= eps_n), rows 6a..6a+2 and 6a+3..6a+5.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_normals(const ModelConsts mc,
+                                                     const T *__restrict__ rho2,
+                                                     const uint32_t *__restrict__ mask,
+                                                     T *__restrict__ nrmb) {
+  const long long N = mc.N;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int b = 1 - a;
+    double g0 = 0, g1 = 0, g2 = 0;
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const bool wall = (mk >> i) & 1u;
+      const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
+      const double r = (double)rho2[2 * y + b];
+      if (cx(i)) g0 += gw(i) * cx(i) * r;
+      if (cy(i)) g1 += gw(i) * cy(i) * r;
+      if (cz(i)) g2 += gw(i) * cz(i) * r;
+    }
+    const double n2 = g0 * g0 + g1 * g1 + g2 * g2;
+    const double in = n2 > mc.eps_n * mc.eps_n ? 1.0 / sqrt(n2) : 0.0;
+    const double g[3] = {g0, g1, g2};
+    for (int d = 0; d < 3; ++d) {
+      nrmb[(size_t)(6 * a + d) * N + v] = (T)g[d];
+      nrmb[(size_t)(6 * a + 3 + d) * N + v] = (T)(g[d] * in);
+    }
+  }
+}
+
+// CSF normals' reverse at a fluid voxel y: dL/dn^a(y) gathered from the
+// curvature reads of the voxels x = y - c_i (and of y itself across its solid
+// links), carried to dL/dg^a(y) through n = g / |g|, added to the force
+// term's own dL/dg^a(y) (stash rows 11..16, updated in place).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
+                                                         const T *__restrict__ nrmb,
+                                                         const uint32_t *__restrict__ mask,
+                                                         T *__restrict__ stash) {
+  const long long N = mc.N;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    double nbar[3] = {0, 0, 0};
+    const double cbv = (double)stash[(size_t)(9 + a) * N + v];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      const bool wall = (mk >> i) & 1u;
+      // the voxel x = y - c_i read n(y) through its link i; y's own solid
+      // links read its own normal
+      const double cb_nb = (double)stash[(size_t)(9 + a) * N + nb.at(-cx(i), -cy(i), -cz(i))];
+      const double c = cb_nb + (wall ? cbv : 0.0);
+      if (cx(i)) nbar[0] += -gw(i) * cx(i) * c;
+      if (cy(i)) nbar[1] += -gw(i) * cy(i) * c;
+      if (cz(i)) nbar[2] += -gw(i) * cz(i) * c;
+    }
+    double g[3], n[3];
+    for (int d = 0; d < 3; ++d) {
+      g[d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
+      n[d] = (double)nrmb[(size_t)(6 * a + 3 + d) * N + v];
+    }
+    const double n2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    if (n2 > mc.eps_n * mc.eps_n) {
+      const double in = 1.0 / sqrt(n2);
+      const double nn = n[0] * nbar[0] + n[1] * nbar[1] + n[2] * nbar[2];
+      for (int d = 0; d < 3; ++d) {
+        T *sg = stash + (size_t)(11 + 3 * a + d) * N + v;
+        *sg = (T)((double)*sg + (nbar[d] - nn * n[d]) * in);
+      }
+    }
+  }
+}
+
 // The neighbours' part of the force's reverse: dL/drho^b(y) from the
-// pseudo-potential reads of every fluid voxel x = y - c_i, and dL/drho^w,o(y)
-// through S_hat(y) from the saturation-gradient reads of gray voxels.
+// pseudo-potential reads of every fluid voxel x = y - c_i, dL/drho^w,o(y)
+// through S_hat(y) from the saturation-gradient reads of gray voxels, and
+// (CSF) dL/drho^b(y) from the density-gradient reads behind the normals and
+// the force term (own value across a solid link).
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
                                                  const T *__restrict__ rho2,
@@ -868,21 +994,30 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;  // stays zero
+  const uint32_t mk = mask[v];
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+  const bool csf = mc.kappa != 0.0;
   double r0 = 0, r1 = 0, shb = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const size_t x = (size_t)nb.at(-cx(i), -cy(i), -cz(i));
-    auto dot = [&](int c0) {
+    auto dot = [&](int c0, size_t at) {
       double s = 0;
-      if (cx(i)) s += cx(i) * (double)stash[(size_t)c0 * N + x];
-      if (cy(i)) s += cy(i) * (double)stash[(size_t)(c0 + 1) * N + x];
-      if (cz(i)) s += cz(i) * (double)stash[(size_t)(c0 + 2) * N + x];
+      if (cx(i)) s += cx(i) * (double)stash[(size_t)c0 * N + at];
+      if (cy(i)) s += cy(i) * (double)stash[(size_t)(c0 + 1) * N + at];
+      if (cz(i)) s += cz(i) * (double)stash[(size_t)(c0 + 2) * N + at];
       return s;
     };
-    r1 += wq(i) * dot(0);  // water's force reads psi^o
-    r0 += wq(i) * dot(3);  // oil's force reads psi^w
-    shb += gw(i) * dot(6);
+    r1 += wq(i) * dot(0, x);  // water's force reads psi^o
+    r0 += wq(i) * dot(3, x);  // oil's force reads psi^w
+    shb += gw(i) * dot(6, x);
+    if (csf) {
+      // g^w = grad rho^o, g^o = grad rho^w; a solid link of this voxel reads
+      // its own density
+      const bool wall = (mk >> i) & 1u;
+      r1 += gw(i) * (dot(11, x) + (wall ? dot(11, (size_t)v) : 0.0));
+      r0 += gw(i) * (dot(14, x) + (wall ? dot(14, (size_t)v) : 0.0));
+    }
   }
   const double aw = (double)rho2[2 * v], ao = (double)rho2[2 * v + 1];
   const double tt = aw + ao, span = 1.0 / mc.inv_span;
@@ -1165,7 +1300,7 @@ void launch_adj_step_t(lbm_handle *h, const T *post, const T *lin, T *lout, doub
 // s_J and theta accumulators.
 template <typename T>
 struct Rev2 {
-  T *dens, *stash, *rnl_in, *rnl_out;
+  T *dens, *stash, *rnl_in, *rnl_out, *nrmb;
   const T *r;
   const uint8_t *side;
   double *gsj, *lr, *gth;
@@ -1177,7 +1312,8 @@ void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, dou
   DevState<T> &s = state<T>(h);
   const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
   hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS>), dim3(nb), dim3(256), 0, h->st, h->mc,
-                     post, (const T *)b.dens, b.r, b.side, lin, (const T *)b.rnl_in, lout,
+                     post, (const T *)b.dens, b.r, b.side, (const T *)b.nrmb, lin,
+                     (const T *)b.rnl_in, lout,
                      b.stash, s.mask, s.K0, (const T *)s.Kinv, s.sJ, (const T *)s.thw,
                      (const T *)s.tho, s.ptype, s.tab, gk, b.gsj, b.lr, b.gth, a);
 }
@@ -1207,6 +1343,11 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
                        h->st, (const void *)post, b.dens, (const T *)nullptr, (const T *)nullptr,
                        s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
   }
+  if (h->p.kappa != 0.0) {
+    Timed tm(h, K_AUX);
+    hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
+                       (const T *)b.dens, s.mask, b.nrmb);
+  }
   Timed tm(h, K_ADJ);
   if (ten) {
     if (reg) launch_adj_step2_t<T, true, true>(h, post, lin, lout, gk, a, b);
@@ -1215,6 +1356,9 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
     if (reg) launch_adj_step2_t<T, true, false>(h, post, lin, lout, gk, a, b);
     else launch_adj_step2_t<T, false, false>(h, post, lin, lout, gk, a, b);
   }
+  if (h->p.kappa != 0.0)
+    hipLaunchKernelGGL((adj::k_adj_normals_rev<T>), dim3(blocks(h->N)), dim3(256), 0, h->st,
+                       h->mc, (const T *)b.nrmb, s.mask, b.stash);
   hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
                      (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
 }
@@ -1329,12 +1473,15 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   double *qh = alloc_into<double>(h, tmp, (size_t)2 * n, &ok);
   // two components: the residual amounts and side flags of every kept level
   // (checkpoints and ring, like the populations), the reverse's buffers
-  T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *ckR = nullptr, *ringR = nullptr;
+  T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *ckR = nullptr, *ringR = nullptr,
+    *nrmb = nullptr;
+  const int nstash = h->p.kappa != 0.0 ? 17 : 9;
   uint8_t *ckS = nullptr, *ringS = nullptr;
   double *gsj = nullptr, *lr = nullptr, *gth = nullptr;
   if (nc == 2) {
     dens = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
-    stash = alloc_into<T>(h, tmp, (size_t)9 * N, &ok);
+    stash = alloc_into<T>(h, tmp, (size_t)nstash * N, &ok);
+    if (h->p.kappa != 0.0) nrmb = alloc_into<T>(h, tmp, (size_t)12 * N, &ok);
     rnl = alloc_into<T>(h, tmp, (size_t)4 * N, &ok);
     ckR = alloc_into<T>(h, tmp, (size_t)nseg * 2 * N, &ok);
     ckS = alloc_into<uint8_t>(h, tmp, (size_t)nseg * N, &ok);
@@ -1411,7 +1558,9 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   if (rc == LBM_OK && nc == 2) {
     rc = hip_check(h, hipMemsetAsync(rnl, 0, (size_t)4 * N * sizeof(T), h->st), "clear");
     if (rc == LBM_OK)
-      rc = hip_check(h, hipMemsetAsync(stash, 0, (size_t)9 * N * sizeof(T), h->st), "clear");
+      rc = hip_check(h, hipMemsetAsync(stash, 0, (size_t)nstash * N * sizeof(T), h->st), "clear");
+    if (rc == LBM_OK && nrmb)
+      rc = hip_check(h, hipMemsetAsync(nrmb, 0, (size_t)12 * N * sizeof(T), h->st), "clear");
     if (rc == LBM_OK)
       rc = hip_check(h, hipMemsetAsync(gsj, 0, (size_t)N * sizeof(double), h->st), "clear");
     if (rc == LBM_OK)
@@ -1443,6 +1592,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       if (nc == 2) {
         b.dens = dens;
         b.stash = stash;
+        b.nrmb = nrmb;
         b.rnl_in = rnl + (size_t)cl * 2 * N;
         b.rnl_out = rnl + (size_t)(1 - cl) * 2 * N;
         b.r = levelR(k);
@@ -1499,10 +1649,9 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
   for (int64_t k = 0; k < nsteps; ++k)
     if (!std::isfinite(dL_dQ[k]))
       return set_err(h, LBM_E_INVAL, "adjoint_flux: non-finite dL_dQ");
-  if (h->mc.open_x || h->sk != SK_NATIVE || (h->p.ncomp == 2 && h->p.kappa != 0.0))
+  if (h->mc.open_x || h->sk != SK_NATIVE)
     return set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: periodic x faces, native storage and (two components) "
-                   "kappa = 0 only");
+                   "adjoint_flux: periodic x faces and native storage only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
   return h->es == 8 ? adjoint_t<double>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi)
                     : adjoint_t<float>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi);

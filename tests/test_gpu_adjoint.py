@@ -368,11 +368,14 @@ def test_two_component_adjoint_matches_oracle(collision, resistance, tensor):
     assert e < 1e-9
 
 
-def test_two_component_adjoint_rejects_csf():
+def test_adjoint_rejects_16bit_storage():
     import paper_2512_21696_amd as L
-    announce("two-component adjoint: kappa != 0 is rejected")
+    announce("adjoint: 16-bit storage is rejected")
     wl = W.droplet_slab(n=16, radius=4.0, slab=4)
-    lb = L.lbm_create(wl["params"])
+    p = wl["params"]
+    p.precision = "f16"
+    p.eps_n = 1e-7
+    lb = L.lbm_create(p)
     lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
     lb.init_fluid(wl["rho_w"], wl["rho_o"])
     with pytest.raises(L.LbmError) as ei:
@@ -381,9 +384,12 @@ def test_two_component_adjoint_rejects_csf():
     lb.destroy()
 
 
-@pytest.mark.parametrize("collision,resistance", [("regularized", "implicit"),
-                                                  ("bgk", "semi_implicit")])
-def test_two_component_adjoint_through_residual_events(collision, resistance):
+@pytest.mark.parametrize("collision,resistance,kappa,region",
+                         [("regularized", "implicit", 0.0, "gray"),
+                          ("bgk", "semi_implicit", 0.0, "gray"),
+                          ("regularized", "implicit", -0.05, "gray"),
+                          ("bgk", "implicit", 0.03, "all")])
+def test_two_component_adjoint_through_residual_events(collision, resistance, kappa, region):
     """The 20 x 8 x 6 two-component case with half of the gray voxels' side
     flags turned and some residual amounts (loaded through a state blob), so
     that trap and release fire: the gradient through the branch each voxel
@@ -391,8 +397,10 @@ def test_two_component_adjoint_through_residual_events(collision, resistance):
     unchanged."""
     import paper_2512_21696_amd as L
     from test_oracle_adjoint import event_state
-    announce(f"two-component adjoint with residual events 20x8x6 fp64 {collision} {resistance}")
+    announce(f"two-component adjoint with residual events 20x8x6 fp64 {collision} {resistance} "
+             f"kappa={kappa} region={region}")
     p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision, resistance)
+    p.kappa, p.csf_region = kappa, region
     side, r = event_state(p, cls, phi, pt, tabs, rw, ro)
     steps = 10
     a = np.linspace(1.0, 2.0, steps)
@@ -434,7 +442,7 @@ def _fd_history2(L, wl, phi, steps):
 
 
 def test_fullsize_two_component_gradient_against_gpu_finite_differences():
-    """96^3 two-component rock (the benchmark's generator, kappa = 0), fp64,
+    """96^3 two-component rock (the benchmark's generator with its CSF control), fp64,
     300 steps with residual transfers firing, squared water-flux misfit over
     steps 100..300, checkpoints every 50: the adjoint's dL/dphi against
     central differences of the GPU forward run, 3 gray voxels of large
@@ -444,7 +452,7 @@ def test_fullsize_two_component_gradient_against_gpu_finite_differences():
     when its perturbed runs end with the base run's side flags and two step
     sizes (1e-5, 5e-6) agree."""
     import paper_2512_21696_amd as L
-    wl = W.adjoint_rock2(n=96, precision="f64", steps=300, window=100)
+    wl = W.adjoint_rock2(n=96, precision="f64", steps=300, window=100)  # with its CSF control
     steps = wl["steps"]
     announce(f"adjoint_rock2 96^3 fp64 {steps} steps: base run")
     q0, side0 = _fd_history2(L, wl, wl["phi"], steps)
@@ -495,12 +503,14 @@ def test_fullsize_two_component_gradient_against_gpu_finite_differences():
 
 
 
-def test_rock24_two_component_adjoint_with_events_matches_oracle():
-    """24^3 from the benchmark's rock generator (two components, kappa = 0),
-    fp64, 60 steps in which residual transfers fire, checkpoints every 7:
-    the gradient against the oracle's, element by element."""
+@pytest.mark.parametrize("kappa", [0.0, None])
+def test_rock24_two_component_adjoint_with_events_matches_oracle(kappa):
+    """24^3 from the benchmark's rock generator (two components, without and
+    with its CSF control in the gray voxels), fp64, 60 steps in which residual
+    transfers fire, checkpoints every 7: the gradient against the oracle's,
+    element by element."""
     import paper_2512_21696_amd as L
-    wl = W.adjoint_rock2(n=24, precision="f64", steps=60, window=20)
+    wl = W.adjoint_rock2(n=24, precision="f64", steps=60, window=20, kappa=kappa)
     p = wl["params"]
     a = np.linspace(1.0, 2.0, 60)
     announce("adjoint_rock2 24^3 fp64 60 steps: oracle gradient (CPU)")

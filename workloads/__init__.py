@@ -420,14 +420,14 @@ def adjoint_rock(n: int = 96, seed: int = 5001, precision: str = "f32", steps: i
 
 
 def adjoint_rock2(n: int = 96, seed: int = 5001, precision: str = "f32", steps: int = 800,
-                  window: int = 200) -> dict:
+                  window: int = 200, kappa: float = None) -> dict:
     """The two-component porosity-gradient workload: the multiscale rock of
-    `multiscale_rock` at n^3 (seed) without the CSF control (kappa = 0; the
-    library's adjoint does not cover it), water buffer and body force as
-    there, outlet at x = n / 2; loss L = sum over steps n >= window of
-    (Q^w(n) - Q*(n))^2 with the seeded target of `adjoint_rock`
-    (`target(q_base)`, `loss_grad(q, target)`)."""
-    base = multiscale_rock(n=n, seed=seed, precision=precision, kappa=0.0)
+    `multiscale_rock` at n^3 (seed), with its CSF control in the gray voxels
+    (kappa of the 0.5x surface tension unless given), water buffer and body
+    force as there, outlet at x = n / 2; loss L = sum over steps n >= window
+    of (Q^w(n) - Q*(n))^2 with a seeded target (`target(q_base)`,
+    `loss_grad(q, target)`, as in `adjoint_rock`)."""
+    base = multiscale_rock(n=n, seed=seed, precision=precision, kappa=kappa)
     p = base["params"]
     p.outlet_x = n // 2
     target, loss_grad = _flux_misfit(seed + 1, steps, window)
