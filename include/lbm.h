@@ -340,9 +340,9 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * through the principal axes of the smoothed porosity (Eqs. (6)-(7)); with two
  * components phi also enters the capillary term through the Leverett-J factor
  * s_J(phi) (Eq. (5)).  Calibrating phi (or the tables) against an observed flux
- * needs dL/dphi.  For one component, or two components without the CSF control
- * (kappa = 0) (scalar K0 or tensor = 1, periodic x faces, native fp64 or fp32
- * storage) and a loss
+ * needs dL/dphi.  For one or two components (with the CSF control of Eq. (4)
+ * and the residual transfer; scalar K0 or tensor = 1; periodic x faces; native
+ * fp64 or fp32 storage) and a loss
  * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
  * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
  * first component's post-collision populations of step n crossing
@@ -363,8 +363,8 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * from x + c_i, bounce-back links mapped to the opposite slot), adds the flux
  * weights and the transposed collision Jacobian, and accumulates dL/dK0 (or,
  * with the tensor, dL/dK^-1 per gray voxel; with two components also dL/ds_J,
- * and the reverse of the neighbours' pseudo-potential and saturation-gradient
- * reads runs as a second, gathering kernel).  The tensor's dL/dK^-1 goes back
+ * and the reverse of the neighbours' pseudo-potential, saturation-gradient and
+ * (CSF) density-gradient and normal reads runs as gathering kernels).  The tensor's dL/dK^-1 goes back
  * through the set-up: first-order perturbation of the Hessian's eigenvectors
  * (and of the tie-break's gradient-aligned axis), the transposed gradient and
  * Hessian stencils and the transposed Gaussian smoothing; the derivative is
@@ -386,14 +386,14 @@ int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, in
  * recomputed levels of one segment, two adjoint sets) plus 2 N doubles (scalar
  * K0) or 20 N doubles (tensor), and for two components, per kept level, the
  * residual amounts and side flags (2 N values of the storage type and N
- * bytes), plus 15 N values of the storage type and 5 N doubles.  The adjoint populations are kept
+ * bytes), plus 15 N (kappa != 0: 35 N) values of the storage type and 5 N
+ * doubles.  The adjoint populations are kept
  * in the storage type, the reverse arithmetic and the gradient accumulation in
  * fp64.
  * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
  * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
- * fluid state), LBM_E_UNSUPPORTED (pressure x faces, 16-bit storage, two
- * components with kappa != 0),
+ * fluid state), LBM_E_UNSUPPORTED (pressure x faces, 16-bit storage),
  * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
