@@ -329,6 +329,12 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
         # pore type, and update dL/dr and the dL/dK0, dL/ds_J accumulators
         # (4 doubles read and written)
         b = 2 * 19 * es * 3 + 26 * es + 8 + gray_frac * (6 * es + 2 + 64)
+        if wl["params"].kappa != 0.0:
+            # CSF: the level's gradients and normals read (12), the curvature
+            # and gradient adjoints stashed, gathered and updated (8 + 2 + 6 +
+            # 12 + 6) and the normals read again by their reverse (6); the
+            # normals pass itself is timed apart
+            b += 52 * es
     adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
     achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
     g = out["dL_dphi"]

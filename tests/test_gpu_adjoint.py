@@ -139,10 +139,15 @@ def test_adjoint_rejects_unsupported_runs():
         lb.adjoint_flux(3, np.ones(3), checkpoint_every=-1)
     assert ei.value.code == L.LBM_E_INVAL
     lb.destroy()
-    wl = W.droplet_slab(n=16, radius=4.0, slab=4)
-    lb = L.lbm_create(wl["params"])
-    lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
-    lb.init_fluid(wl["rho_w"], wl["rho_o"])
+    # open x faces (pressure reservoirs) have no adjoint
+    p = W.Params(nx=16, ny=6, nz=4, ncomp=1, tau=(0.8, 0.8), G=0.0, kappa=0.0,
+                 bc_x="pressure", rho_in=(1.01, 0.0), rho_out=(1.0, 0.0)).filled()
+    shape = (4, 6, 16)
+    tabs = [W.pore_table(W.kozeny_carman_table(2.0), *W.brooks_corey_tables(0.05, 2.0, 0.1),
+                         phi_ref=0.225, pc_pm=0.05)]
+    lb = L.lbm_create(p)
+    lb.set_geometry(np.zeros(shape, np.uint8), np.ones(shape), np.zeros(shape, np.uint8), tabs)
+    lb.init_fluid(np.ones(shape))
     with pytest.raises(L.LbmError) as ei:
         lb.adjoint_flux(2, np.ones(2))
     assert ei.value.code == L.LBM_E_UNSUPPORTED
