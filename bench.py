@@ -321,20 +321,21 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     if nc == 1:
         b = 19 * es + 2 * 19 * es + 4 + gray_frac * ((es + 16) if kind == "rock" else (6 * es + 96))
     else:
-        # two components, the reverse step's two kernels (timed together):
-        # both sets pulled, both adjoint sets gathered and written (3 x 38),
-        # the level's densities read twice (2 + 2), the neighbour part read
-        # and written (2 + 2), the stash written and gathered (9 + 9), the
-        # mask twice; gray voxels read r (2), K0, s_J, theta (2), side flag and
-        # pore type, and update dL/dr and the dL/dK0, dL/ds_J accumulators
-        # (4 doubles read and written)
-        b = 2 * 19 * es * 3 + 26 * es + 8 + gray_frac * (6 * es + 2 + 64)
+        # two components, the reverse step's kernels (timed together; the
+        # density, normals and neighbour-sum passes of the level are timed
+        # apart): both sets pulled, both adjoint sets gathered and written
+        # (3 x 38); the level's neighbour sums read (9), the neighbour part
+        # read and written (2 + 2), the stash written and gathered (9 + 9),
+        # the densities (2), the mask twice; gray voxels read r (2), K0, s_J,
+        # theta (2), side flag and pore type, and update dL/dr and the dL/dK0,
+        # dL/ds_J accumulators (4 doubles read and written)
+        b = 2 * 19 * es * 3 + 33 * es + 8 + gray_frac * (6 * es + 2 + 64)
         if wl["params"].kappa != 0.0:
-            # CSF: the level's gradients and normals read (12), the curvature
-            # and gradient adjoints stashed, gathered and updated (8 + 2 + 6 +
-            # 12 + 6) and the normals read again by their reverse (6); the
-            # normals pass itself is timed apart
-            b += 52 * es
+            # CSF: curvature (2) and own gradient (3) read, the curvature and
+            # gradient adjoints stashed (8), the normals' reverse reading the
+            # curvature adjoints (2), normals and gradients (12) and updating
+            # the gradient adjoints (12), the gather reading them (6)
+            b += 45 * es
     adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
     achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
     g = out["dL_dphi"]

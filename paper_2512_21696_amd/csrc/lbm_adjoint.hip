@@ -310,7 +310,7 @@ template <typename T, bool REG, bool TENS>
 __global__ __launch_bounds__(256) void k_adj_step2(
     const ModelConsts mc, const T *__restrict__ post, const T *__restrict__ rho2,
     const T *__restrict__ rres, const uint8_t *__restrict__ side, const T *__restrict__ nrmb,
-    const T *__restrict__ lin, const T *__restrict__ rnl, T *__restrict__ lout,
+    const T *__restrict__ inb, const T *__restrict__ lin, const T *__restrict__ rnl, T *__restrict__ lout,
     T *__restrict__ stash,
     const uint32_t *__restrict__ mask, const T *__restrict__ K0, const T *__restrict__ Kinv,
     const T *__restrict__ sJ, const T *__restrict__ thw, const T *__restrict__ tho,
@@ -395,16 +395,15 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     const int b = 1 - a;
     double pw = rho[b] + mc.wall_dpsi[b];
     pw = pw > 0.0 ? pw : 0.0;
-    double s0 = 0, s1 = 0, s2 = 0;
+    // the fluid links' sum comes from the inputs pass, the solid links read pw
+    double s0 = (double)inb[(size_t)(3 * a) * N + v], s1 = (double)inb[(size_t)(3 * a + 1) * N + v],
+           s2 = (double)inb[(size_t)(3 * a + 2) * N + v];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const bool wall = (mk >> i) & 1u;
-      const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
-      const double nbv = (double)rho2[2 * y + b];  // this voxel's own entry across a wall
-      const double psi = wall ? pw : nbv;
-      if (cx(i)) s0 += wq(i) * cx(i) * psi;
-      if (cy(i)) s1 += wq(i) * cy(i) * psi;
-      if (cz(i)) s2 += wq(i) * cz(i) * psi;
+      const double w = ((mk >> i) & 1u) ? wq(i) * pw : 0.0;
+      if (cx(i)) s0 += cx(i) * w;
+      if (cy(i)) s1 += cy(i) * w;
+      if (cz(i)) s2 += cz(i) * w;
     }
     acc[a][0] = s0; acc[a][1] = s1; acc[a][2] = s2;
     for (int d = 0; d < 3; ++d) Fex[a][d] = rho[a] * mc.g[a][d] - mc.G * rho[a] * acc[a][d];
@@ -419,16 +418,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       for (int d = 0; d < 3; ++d) cg[a][d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
-      double dv = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const bool wall = (mk >> i) & 1u;
-        const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
-        if (cx(i)) dv += gw(i) * cx(i) * (double)nrmb[(size_t)(6 * a + 3) * N + y];
-        if (cy(i)) dv += gw(i) * cy(i) * (double)nrmb[(size_t)(6 * a + 4) * N + y];
-        if (cz(i)) dv += gw(i) * cz(i) * (double)nrmb[(size_t)(6 * a + 5) * N + y];
-      }
-      curv[a] = -dv;
+      curv[a] = (double)inb[(size_t)(9 + a) * N + v];
       for (int d = 0; d < 3; ++d) Fex[a][d] += kap * curv[a] * cg[a][d] * rho[a];
     }
   }
@@ -441,15 +431,13 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     to = rho[1] + (double)rres[N + v];
     Sraw = (tw / (tw + to) - mc.s_min) * ispan;
     S = Sraw < 0.0 ? 0.0 : (Sraw > 1.0 ? 1.0 : Sraw);
+    for (int d = 0; d < 3; ++d) gS[d] = (double)inb[(size_t)(6 + d) * N + v];
 #pragma unroll
-    for (int i = 1; i < Q; ++i) {
-      const bool wall = (mk >> i) & 1u;
-      const uint32_t u = 2 * (wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i)));
-      const double aw = (double)rho2[u], ao = (double)rho2[u + 1];
-      const double val = wall ? shat0 : (aw / (aw + ao) - mc.s_min) * mc.inv_span;
-      if (cx(i)) gS[0] += gw(i) * cx(i) * val;
-      if (cy(i)) gS[1] += gw(i) * cy(i) * val;
-      if (cz(i)) gS[2] += gw(i) * cz(i) * val;
+    for (int i = 1; i < Q; ++i) {  // solid links read this voxel's own S_hat
+      const double w = ((mk >> i) & 1u) ? gw(i) * shat0 : 0.0;
+      if (cx(i)) gS[0] += cx(i) * w;
+      if (cy(i)) gS[1] += cy(i) * w;
+      if (cz(i)) gS[2] += cz(i) * w;
     }
     const T *tb = tab + (size_t)ptype[v] * 3 * TABLE_N;
     const double t = S * (double)(TABLE_N - 1);
@@ -932,6 +920,62 @@ __global__ __launch_bounds__(256) void k_adj_normals(const ModelConsts mc,
   }
 }
 
+// Neighbour sums of the level that the two-component reverse step reads
+// (fluid links only; the step adds its solid links from its own values):
+// rows 0..2 and 3..5 sum_i w_i c_i rho^b(x + c_i) for the pseudo-potential
+// force of component a (b = 1 - a), rows 6..8 sum_i (w_i / cs2) c_i S_hat(x + c_i),
+// and (CSF, from the normals) rows 9, 10 curv^a = -div n^a (own normal across
+// a solid link).
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
+                                                     const T *__restrict__ rho2,
+                                                     const T *__restrict__ nrmb,
+                                                     const uint32_t *__restrict__ mask,
+                                                     T *__restrict__ inb) {
+  const long long N = mc.N;
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const uint32_t mk = mask[v];
+  if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+  double a0[3] = {0, 0, 0}, a1[3] = {0, 0, 0}, gs[3] = {0, 0, 0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const bool wall = (mk >> i) & 1u;
+    const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
+    const double rw = (double)rho2[2 * y], ro = (double)rho2[2 * y + 1];
+    const double f = wall ? 0.0 : 1.0;
+    const double sh = f * (rw / (rw + ro) - mc.s_min) * mc.inv_span;
+    const int c[3] = {cx(i), cy(i), cz(i)};
+    for (int d = 0; d < 3; ++d) {
+      if (!c[d]) continue;
+      a0[d] += f * wq(i) * c[d] * ro;  // water's force reads psi^o
+      a1[d] += f * wq(i) * c[d] * rw;
+      gs[d] += gw(i) * c[d] * sh;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    inb[(size_t)d * N + v] = (T)a0[d];
+    inb[(size_t)(3 + d) * N + v] = (T)a1[d];
+    inb[(size_t)(6 + d) * N + v] = (T)gs[d];
+  }
+  if (mc.kappa != 0.0) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double dv = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const bool wall = (mk >> i) & 1u;
+        const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
+        if (cx(i)) dv += gw(i) * cx(i) * (double)nrmb[(size_t)(6 * a + 3) * N + y];
+        if (cy(i)) dv += gw(i) * cy(i) * (double)nrmb[(size_t)(6 * a + 4) * N + y];
+        if (cz(i)) dv += gw(i) * cz(i) * (double)nrmb[(size_t)(6 * a + 5) * N + y];
+      }
+      inb[(size_t)(9 + a) * N + v] = (T)(-dv);
+    }
+  }
+}
+
 // CSF normals' reverse at a fluid voxel y: dL/dn^a(y) gathered from the
 // curvature reads of the voxels x = y - c_i (and of y itself across its solid
 // links), carried to dL/dg^a(y) through n = g / |g|, added to the force
@@ -1300,7 +1344,7 @@ void launch_adj_step_t(lbm_handle *h, const T *post, const T *lin, T *lout, doub
 // s_J and theta accumulators.
 template <typename T>
 struct Rev2 {
-  T *dens, *stash, *rnl_in, *rnl_out, *nrmb;
+  T *dens, *stash, *rnl_in, *rnl_out, *nrmb, *inb;
   const T *r;
   const uint8_t *side;
   double *gsj, *lr, *gth;
@@ -1312,7 +1356,8 @@ void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, dou
   DevState<T> &s = state<T>(h);
   const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
   hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS>), dim3(nb), dim3(256), 0, h->st, h->mc,
-                     post, (const T *)b.dens, b.r, b.side, (const T *)b.nrmb, lin,
+                     post, (const T *)b.dens, b.r, b.side, (const T *)b.nrmb,
+                     (const T *)b.inb, lin,
                      (const T *)b.rnl_in, lout,
                      b.stash, s.mask, s.K0, (const T *)s.Kinv, s.sJ, (const T *)s.thw,
                      (const T *)s.tho, s.ptype, s.tab, gk, b.gsj, b.lr, b.gth, a);
@@ -1343,10 +1388,13 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
                        h->st, (const void *)post, b.dens, (const T *)nullptr, (const T *)nullptr,
                        s.mask, h->p.nx, h->p.ny, h->p.nz, h->N);
   }
-  if (h->p.kappa != 0.0) {
+  {
     Timed tm(h, K_AUX);
-    hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
-                       (const T *)b.dens, s.mask, b.nrmb);
+    if (h->p.kappa != 0.0)
+      hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks(h->N)), dim3(256), 0, h->st,
+                         h->mc, (const T *)b.dens, s.mask, b.nrmb);
+    hipLaunchKernelGGL((adj::k_adj_inputs2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
+                       (const T *)b.dens, (const T *)b.nrmb, s.mask, b.inb);
   }
   Timed tm(h, K_ADJ);
   if (ten) {
@@ -1474,7 +1522,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   // two components: the residual amounts and side flags of every kept level
   // (checkpoints and ring, like the populations), the reverse's buffers
   T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *ckR = nullptr, *ringR = nullptr,
-    *nrmb = nullptr;
+    *nrmb = nullptr, *inb = nullptr;
   const int nstash = h->p.kappa != 0.0 ? 17 : 9;
   uint8_t *ckS = nullptr, *ringS = nullptr;
   double *gsj = nullptr, *lr = nullptr, *gth = nullptr;
@@ -1482,6 +1530,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
     dens = alloc_into<T>(h, tmp, (size_t)2 * N, &ok);
     stash = alloc_into<T>(h, tmp, (size_t)nstash * N, &ok);
     if (h->p.kappa != 0.0) nrmb = alloc_into<T>(h, tmp, (size_t)12 * N, &ok);
+    inb = alloc_into<T>(h, tmp, (size_t)11 * N, &ok);
     rnl = alloc_into<T>(h, tmp, (size_t)4 * N, &ok);
     ckR = alloc_into<T>(h, tmp, (size_t)nseg * 2 * N, &ok);
     ckS = alloc_into<uint8_t>(h, tmp, (size_t)nseg * N, &ok);
@@ -1593,6 +1642,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
         b.dens = dens;
         b.stash = stash;
         b.nrmb = nrmb;
+        b.inb = inb;
         b.rnl_in = rnl + (size_t)cl * 2 * N;
         b.rnl_out = rnl + (size_t)(1 - cl) * 2 * N;
         b.r = levelR(k);
