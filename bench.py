@@ -260,8 +260,9 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     import paper_2512_21696_amd as L
     if kind == "rock":
         wl = W.adjoint_rock(n=n, steps=steps, precision=precision)
-    elif kind == "rock2":
-        wl = W.adjoint_rock2(n=n, steps=steps, precision=precision)
+    elif kind in ("rock2", "rock2-kappa0"):
+        wl = W.adjoint_rock2(n=n, steps=steps, precision=precision,
+                             kappa=0.0 if kind == "rock2-kappa0" else None)
     else:
         wl = W.fiber_bundles(n=n, precision=precision)
         wl["params"].outlet_x = n // 2
@@ -351,7 +352,11 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
             "reverse_kernel_ms": round(adj_ms, 4),
             "reverse_kernel_launches": int(ka["adjoint_launches"]),
             "recompute_and_forward_step_launches": int(ka["step_launches"]),
-            "roofline": {"kernel": "k_adj_step", "bound": "hbm",
+            "kappa": float(wl["params"].kappa) if nc == 2 else None,
+            "roofline": {"kernel": "k_adj_step" if nc == 1 else
+                         ("k_adj_step2 + k_adj_nl2" +
+                          (" + k_adj_normals_rev" if wl["params"].kappa != 0.0 else "")),
+                         "bound": "hbm",
                          "bytes_per_fluid_update": round(b, 2),
                          "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                          "frac": round(achieved / HBM_PEAK_GBS, 4)},
@@ -455,7 +460,7 @@ def main():
                          "cwrite} into the traffic record of --precision's workload (no GPU)")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the porosity-gradient section and print its JSON, then exit")
-    ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "rock2", "both"],
+    ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "rock2", "rock2-kappa0", "both"],
                     help="with --adjoint: which workload(s) to run")
     ap.add_argument("--drift", type=int, default=0, metavar="STEPS",
                     help="only run the storage precisions side by side for STEPS steps and "
@@ -484,6 +489,8 @@ def main():
             res["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
         if args.adjoint_case in ("rock2", "both"):
             res["adjoint_gradient_two_component"] = adjoint_gradient(kind="rock2")
+        if args.adjoint_case == "rock2-kappa0":
+            res["adjoint_gradient_two_component_kappa0"] = adjoint_gradient(kind="rock2-kappa0")
         print(json.dumps(res), flush=True)
         return
 
