@@ -1631,7 +1631,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       for (int64_t k = 1; k < m && rc == LBM_OK; ++k) {
         if (nc == 2) {
           rc = copy_rs(levelR(k), levelS(k), levelR(k - 1), levelS(k - 1));
-          launch_recompute<T>(h, level(k - 1), level(k), levelR(k), levelS(k));
+          if (rc == LBM_OK) launch_recompute<T>(h, level(k - 1), level(k), levelR(k), levelS(k));
         } else {
           launch_recompute<T>(h, level(k - 1), level(k));
         }
