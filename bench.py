@@ -209,7 +209,8 @@ def rev_library(steps=400):
     (workloads.rev_domains) run together in fp32.  Fixed work first (`steps`
     steps; the per-step time is the library's HIP-event mean over the step
     launches, packing, set-up and checks excluded), then a run to convergence
-    for the K values."""
+    for the K values; then the four storage precisions side by side (the same
+    fixed work, and K after 4000 steps against fp64)."""
     import numpy as np
     import torch
     import workloads as W
@@ -229,6 +230,25 @@ def rev_library(steps=400):
     t2 = time.perf_counter() - t2
     K = np.array([r["K"] for r in conv])
     b = 2 * 19 * 4 + 4  # populations read and written, the mask word
+    # storage precisions side by side: step time of the same fixed work, and K
+    # of every domain after `kcmp` steps against the fp64 run's
+    kcmp = 4000
+    legs, Kp = {}, {}
+    for prec in ("f64", "f32", "f16", "bf16"):
+        es = {"f64": 8, "f32": 4}.get(prec, 2)
+        kp = dict(kw, precision=prec)
+        r = L.rev_permeability(doms, max_steps=steps, tol=0.0, **kp)
+        pms = r[0]["step_ms"]
+        Kp[prec] = np.array([x["K"] for x in L.rev_permeability(doms, max_steps=kcmp, tol=0.0, **kp)])
+        bp = 2 * 19 * es + 4
+        legs[prec] = {"ms_per_step": round(pms, 4),
+                      "value": round(npore / (pms * 1e-3) / 1e6, 1),
+                      "bytes_per_pore_update": bp,
+                      "frac": round(bp * npore / (pms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+    for prec in legs:
+        rel = np.abs(Kp[prec] - Kp["f64"]) / np.abs(Kp["f64"])
+        legs[prec]["K_rel_err_vs_f64_max"] = float(rel.max())
+        legs[prec]["K_rel_err_vs_f64_median"] = float(np.median(rel))
     return {"workload": f"rev_domains_{len(doms)}", "domains": len(doms), "voxels": nvox,
             "pore_voxels": npore, "storage": "f32", "collision": "regularized", "tau": 1.0,
             "steps": steps, "ms_per_step": round(ms, 4), "call_seconds": round(t1, 3),
@@ -241,7 +261,8 @@ def rev_library(steps=400):
                                "converged": int(sum(r["converged"] for r in conv)),
                                "steps_max": int(max(r["steps"] for r in conv)),
                                "K_min": float(K.min()), "K_median": float(np.median(K)),
-                               "K_max": float(K.max())}}
+                               "K_max": float(K.max())},
+            "storage_comparison": {"K_after_steps": kcmp, "legs": legs}}
 
 
 def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
@@ -458,6 +479,9 @@ def main():
     ap.add_argument("--record-traffic", metavar="PREFIX",
                     help="only turn the rocprofv3 counter passes PREFIX_{fetch,write,cfetch,"
                          "cwrite} into the traffic record of --precision's workload (no GPU)")
+    ap.add_argument("--rev", action="store_true",
+                    help="only run the batched permeability library section and print its JSON, "
+                         "then exit")
     ap.add_argument("--adjoint", action="store_true",
                     help="only run the porosity-gradient section and print its JSON, then exit")
     ap.add_argument("--adjoint-case", default="both", choices=["rock", "fiber", "rock2", "rock2-kappa0", "both"],
@@ -478,6 +502,11 @@ def main():
         return
     if args.drift:
         precision_drift(args.n, args.drift)
+        return
+    if args.rev:
+        import torch
+        torch.cuda.set_device(0)
+        print(json.dumps({"rev_library": rev_library()}), flush=True)
         return
     if args.adjoint:
         import torch

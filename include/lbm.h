@@ -299,7 +299,10 @@ typedef struct {
   double g;             /* body acceleration along axis, > 0 */
   int32_t axis;         /* 0 = x, 1 = y, 2 = z */
   int32_t collision;    /* LBM_COLL_REGULARIZED or LBM_COLL_BGK */
-  int32_t precision;    /* LBM_PREC_F64 or LBM_PREC_F32 (storage and arithmetic) */
+  int32_t precision;    /* LBM_PREC_F64 or LBM_PREC_F32 (storage and arithmetic), or
+                           LBM_PREC_F16 / LBM_PREC_BF16: 16-bit storage of the offsets
+                           h = f_i / w_i - 1 from the rest state at density 1 (round to
+                           nearest even), decoded as f_i = w_i (1 + h); fp32 arithmetic */
   int32_t side_walls;   /* 1: the four box faces parallel to the force are walls
                            (bounce-back) instead of periodic */
   int32_t mirror;       /* 1: each domain is run joined to its mirror image along the
@@ -325,7 +328,7 @@ typedef struct {
 /* Runs the domains doms[0 .. ndom-1] and writes out[0 .. ndom-1] (caller-owned
  * host arrays).  Device memory is allocated and freed inside the call, which
  * returns after the last result is on the host.  Errors: LBM_E_INVAL for an
- * argument out of range (nothing runs), LBM_E_UNSUPPORTED for another
+ * argument out of range (nothing runs), LBM_E_UNSUPPORTED for an unknown
  * precision or more than 2^31 / 19 packed voxels, LBM_E_NOMEM, LBM_E_DEVICE,
  * LBM_E_NONFINITE when a domain's mean velocity is not finite at a check.  The
  * message is lbm_last_error(NULL). */

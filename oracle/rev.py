@@ -40,12 +40,13 @@ def mirrored(cls, axis):
     return np.concatenate([cls, np.flip(cls, axis=ax)], axis=ax)
 
 
-def permeability(params, cls, steps, axis=0):
+def permeability(params, cls, steps, axis=0, with_state=False):
     """Runs the periodic box `cls` (0 pore, 1 solid) for `steps` steps with
     `params` (one component, tau, collision and the body acceleration g along
     `axis`, no gray voxels) and returns (K0, u): u is the velocity field along
     the force, (m + F/2) / rho, zero on solid voxels, and K0 = (sum of u over
-    the box / number of voxels) nu / g = phi <u> nu / g."""
+    the box / number of voxels) nu / g = phi <u> nu / g.  with_state: also the
+    final post-streaming populations f[i][z][y][x]."""
     cls = np.asarray(cls, np.uint8)
     shape = cls.shape
     o = Oracle(params)
@@ -55,4 +56,6 @@ def permeability(params, cls, steps, axis=0):
     u = np.where(cls == PORE, o.evaluate()["u"][axis], 0.0)
     g = float(params.g[0][axis])
     nu = (float(params.tau[0]) - 0.5) / 3.0
+    if with_state:
+        return u.sum() / cls.size * nu / g, u, o.f[0].copy()
     return u.sum() / cls.size * nu / g, u

@@ -11,6 +11,11 @@
 // box is just a solid neighbour), moments, the regularised or BGK collision
 // and the force term of Eq. (3) for the body force rho g, emitted as the
 // quadratic form w_i (A + B.c_i + c_i^T C c_i) like the fused step.
+//
+// Storage: the arithmetic type T (fp64 or fp32), or 16-bit offsets (fp16 or
+// bf16, SK) with fp32 arithmetic: a stored value of direction class i is
+// h = f / w_i - 1, the population's departure from the rest state at density 1
+// (single-phase flow stays near unit density), decoded as f = w_i (1 + h).
 #include <memory>
 
 namespace lbm {
@@ -69,42 +74,58 @@ __global__ __launch_bounds__(256) void k_rev_mask(const Dom *__restrict__ doms,
   mask[V] = m;
 }
 
-// rest state at density 1 on pore voxels, zeros elsewhere
-template <typename T>
-__global__ __launch_bounds__(256) void k_rev_init(T *__restrict__ f,
+// Stored slot k of direction class i (opposite directions share a weight).
+template <typename T, int SK>
+__device__ inline T rev_load(const void *__restrict__ f, uint32_t k, int i) {
+  if constexpr (SK == SK_NATIVE) return static_cast<const T *>(f)[k];
+  else return (T)wq(i) * ((T)1 + dec16<SK>((uint32_t) static_cast<const uint16_t *>(f)[k]));
+}
+// zero: a solid slot (never read), stored as zero bits
+template <typename T, int SK>
+__device__ inline void rev_store(void *__restrict__ f, size_t k, int i, T val, bool zero) {
+  if constexpr (SK == SK_NATIVE) static_cast<T *>(f)[k] = zero ? (T)0 : val;
+  else
+    static_cast<uint16_t *>(f)[k] =
+        zero ? (uint16_t)0 : enc16<SK>(val * (T)(1.0 / wq(i)) - (T)1);
+}
+
+// rest state at density 1 on pore voxels (16-bit: offset 0), zeros elsewhere
+template <typename T, int SK>
+__global__ __launch_bounds__(256) void k_rev_init(void *__restrict__ f,
                                                   const uint32_t *__restrict__ mask, int Vtot) {
   const int V = blockIdx.x * 256 + threadIdx.x;
   if (V >= Vtot) return;
   const bool pore = ((mask[V] >> CLASS_SHIFT) & 3u) != SOLID_CODE;
-  for (int i = 0; i < Q; ++i) f[(size_t)i * Vtot + V] = pore ? (T)wq(i) : (T)0;
+  for (int i = 0; i < Q; ++i) rev_store<T, SK>(f, (size_t)i * Vtot + V, i, (T)wq(i), !pore);
 }
 
 // The 19 populations voxel V pulls from the stored (post-collision) set:
 // f_i from x - c_i, or this voxel's opposite slot when x - c_i is solid.
-template <typename T>
-__device__ inline void pull19(const Dom &D, uint32_t mk, int V, const T *__restrict__ fin,
+template <typename T, int SK>
+__device__ inline void pull19(const Dom &D, uint32_t mk, int V, const void *__restrict__ fin,
                               uint32_t Vt, T (&f)[Q]) {
   int x, y, z;
   local_xyz(D, V - D.voff, x, y, z);
   const int X3[3] = {x == 0 ? D.nx - 1 : x - 1, x, x == D.nx - 1 ? 0 : x + 1};
   const int Y3[3] = {y == 0 ? D.ny - 1 : y - 1, y, y == D.ny - 1 ? 0 : y + 1};
   const int Z3[3] = {z == 0 ? D.nz - 1 : z - 1, z, z == D.nz - 1 ? 0 : z + 1};
-  f[0] = fin[V];
+  f[0] = rev_load<T, SK>(fin, (uint32_t)V, 0);
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     const uint32_t src =
         (uint32_t)(D.voff + X3[1 - cx(i)] + D.nx * (Y3[1 - cy(i)] + D.ny * Z3[1 - cz(i)]));
     const uint32_t k = ((mk >> opp(i)) & 1u) ? (uint32_t)opp(i) * Vt + (uint32_t)V
                                               : (uint32_t)i * Vt + src;
-    f[i] = fin[k];
+    f[i] = rev_load<T, SK>(fin, k, i);
   }
 }
 
 // One time step of every packed domain.
-template <typename T, bool REG>
+template <typename T, bool REG, int SK>
 __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
                                                   const int *__restrict__ blk_dom,
-                                                  const T *__restrict__ fin, T *__restrict__ fout,
+                                                  const void *__restrict__ fin,
+                                                  void *__restrict__ fout,
                                                   const uint32_t *__restrict__ mask, int Vtot,
                                                   T g0, T g1, T g2, T omega) {
   const int V = blockIdx.x * 256 + threadIdx.x;
@@ -116,14 +137,16 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
   // covers whole lines
   if (__all(solid)) return;
   // solid lanes store zeros only when their 128-byte line holds a fluid voxel
-  constexpr int LPL = 128 / (int)sizeof(T);
+  // (16-bit storage: one line per wave, which holds one here)
+  constexpr int LPL = 128 / (SK == SK_NATIVE ? (int)sizeof(T) : 2);
+  constexpr uint64_t LMASK = LPL >= 64 ? ~0ull : ((1ull << (LPL & 63)) - 1ull);
   const uint64_t live = __ballot(!solid);
   const int lane = threadIdx.x & 63;
-  const bool dead_line = solid && ((live >> (lane / LPL * LPL)) & ((1ull << LPL) - 1ull)) == 0ull;
+  const bool dead_line = solid && ((live >> (lane / LPL * LPL % 64)) & LMASK) == 0ull;
   const uint32_t Vt = (uint32_t)Vtot;
   T f[Q];  // the pulled set
   if (!solid) {
-    pull19<T>(D, mk, V, fin, Vt, f);
+    pull19<T, SK>(D, mk, V, fin, Vt, f);
   } else {
 #pragma unroll
     for (int i = 0; i < Q; ++i) f[i] = (T)0;
@@ -176,17 +199,17 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
     T val = (T)wq(i) * (A + B0 * c0 + B1 * c1 + B2 * c2 + Cxx * c0 * c0 + Cyy * c1 * c1 +
                         Czz * c2 * c2 + (T)2 * (Cxy * c0 * c1 + Cxz * c0 * c2 + Cyz * c1 * c2));
     if (!REG) val += keep * f[i];
-    if (!dead_line) fout[(size_t)i * Vtot + V] = solid ? (T)0 : val;
+    if (!dead_line) rev_store<T, SK>(fout, (size_t)i * Vtot + V, i, val, solid);
   }
 }
 
 // Velocity along the force, (m + F/2)_axis / rho, of the post-streaming set
 // (the stored set pulled as a step would): per-block fp64 sums over pore
 // voxels, and the field when uf is given.
-template <typename T>
+template <typename T, int SK>
 __global__ __launch_bounds__(256) void k_rev_velocity(const Dom *__restrict__ doms,
                                                       const int *__restrict__ blk_dom,
-                                                      const T *__restrict__ fin,
+                                                      const void *__restrict__ fin,
                                                       const uint32_t *__restrict__ mask, int Vtot,
                                                       int axis, T g, T *__restrict__ uf,
                                                       double *__restrict__ partial) {
@@ -198,7 +221,7 @@ __global__ __launch_bounds__(256) void k_rev_velocity(const Dom *__restrict__ do
   if (pore) {
     const Dom D = doms[blk_dom[blockIdx.x]];
     T f[Q];
-    pull19<T>(D, mk, V, fin, (uint32_t)Vtot, f);
+    pull19<T, SK>(D, mk, V, fin, (uint32_t)Vtot, f);
     T rho = 0, m = 0;
     for (int i = 0; i < Q; ++i) {
       const int c = axis == 0 ? cx(i) : (axis == 1 ? cy(i) : cz(i));
@@ -254,7 +277,7 @@ int check(hipError_t e, const char *what) {
   return fail(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
-template <typename T>
+template <typename T, int SK>
 int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out) {
   const hipStream_t st = (hipStream_t)p->stream;
   const int ax = p->axis;
@@ -306,8 +329,9 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   int *dblk = mem.get<int>(nblk);
   uint8_t *dcls = mem.get<uint8_t>(Vtot);
   uint32_t *dmask = mem.get<uint32_t>(Vtot);
-  T *fa = mem.get<T>((size_t)Q * Vtot);
-  T *fb = mem.get<T>((size_t)Q * Vtot);
+  const size_t es = SK == SK_NATIVE ? sizeof(T) : 2;  // bytes per stored value
+  void *fa = mem.get<uint8_t>((size_t)Q * Vtot * es);
+  void *fb = mem.get<uint8_t>((size_t)Q * Vtot * es);
   T *uf = want_u ? mem.get<T>(Vtot) : nullptr;
   double *partial = mem.get<double>(nblk);
   double *usum = mem.get<double>(ndom);
@@ -327,7 +351,7 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   if (rc != LBM_OK) return rc;
   const int wall_axes = p->side_walls ? (7 & ~(1 << ax)) : 0;
   hipLaunchKernelGGL(k_rev_mask, dim3(nblk), dim3(256), 0, st, ddom, dblk, dcls, dmask, wall_axes);
-  hipLaunchKernelGGL(k_rev_init<T>, dim3(nblk), dim3(256), 0, st, fa, dmask, Vtot);
+  hipLaunchKernelGGL((k_rev_init<T, SK>), dim3(nblk), dim3(256), 0, st, fa, dmask, Vtot);
 
   const T gv[3] = {ax == 0 ? (T)p->g : (T)0, ax == 1 ? (T)p->g : (T)0, ax == 2 ? (T)p->g : (T)0};
   const T omega = (T)(1.0 / p->tau);
@@ -338,7 +362,7 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   int64_t done = 0;
   bool have_prev = false;
   auto measure = [&](T *u_field) -> int {
-    hipLaunchKernelGGL(k_rev_velocity<T>, dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, dmask,
+    hipLaunchKernelGGL((k_rev_velocity<T, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, dmask,
                        Vtot, ax, (T)p->g, u_field, partial);
     hipLaunchKernelGGL(k_rev_reduce, dim3((ndom + 63) / 64), dim3(64), 0, st, ddom, ndom, partial,
                        usum);
@@ -370,10 +394,10 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     if (rc != LBM_OK) return rc;
     for (int64_t s = 0; s < k; ++s) {
       if (reg)
-        hipLaunchKernelGGL((k_rev_step<T, true>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, fb,
+        hipLaunchKernelGGL((k_rev_step<T, true, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, fb,
                            dmask, Vtot, gv[0], gv[1], gv[2], omega);
       else
-        hipLaunchKernelGGL((k_rev_step<T, false>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa,
+        hipLaunchKernelGGL((k_rev_step<T, false, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa,
                            fb, dmask, Vtot, gv[0], gv[1], gv[2], omega);
       std::swap(fa, fb);
     }
@@ -440,10 +464,14 @@ extern "C" int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domai
     if ((long long)doms[d].nx * doms[d].ny * doms[d].nz * (p->mirror ? 2 : 1) > 0x7fffffff / Q)
       return fail(LBM_E_UNSUPPORTED, "domain " + std::to_string(d) + " is too large");
   }
-  if (p->precision != LBM_PREC_F64 && p->precision != LBM_PREC_F32)
-    return fail(LBM_E_UNSUPPORTED, "the permeability runs support F64 and F32");
+  if (p->precision < LBM_PREC_F64 || p->precision > LBM_PREC_BF16)
+    return fail(LBM_E_UNSUPPORTED, "unknown precision");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LBM_E_DEVICE, "no HIP device");
-  return p->precision == LBM_PREC_F64 ? lbm::rev::run<double>(p, doms, ndom, out)
-                                      : lbm::rev::run<float>(p, doms, ndom, out);
+  switch (p->precision) {
+    case LBM_PREC_F64: return lbm::rev::run<double, lbm::SK_NATIVE>(p, doms, ndom, out);
+    case LBM_PREC_F32: return lbm::rev::run<float, lbm::SK_NATIVE>(p, doms, ndom, out);
+    case LBM_PREC_F16: return lbm::rev::run<float, lbm::SK_F16>(p, doms, ndom, out);
+    default: return lbm::rev::run<float, lbm::SK_BF16>(p, doms, ndom, out);
+  }
 }

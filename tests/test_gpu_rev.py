@@ -7,7 +7,14 @@ quantities of the size of the density (1) to 2^-24 relative, and the velocity
 is a small difference of them (|u| is at most a few 1e-3 here), so the bound
 is absolute: at most one ulp of the unit density, 2^-23, per step, summed
 over the n steps (errors persist for a viscous time), n 2^-23 in u and
-n 2^-23 nu / g in K."""
+n 2^-23 nu / g in K.
+
+16-bit storage (fp16, bf16): a stored value is h = f_i / w_i - 1, rounded to
+the nearest of a format with unit roundoff eps (2^-11 fp16, 2^-8 bf16), so a
+population carries an error of at most w_i eps |h| per step.  The velocity
+along an axis takes sum_i w_i c_ia^2 = 1/3 of that per step: with H the
+largest |f_i / w_i - 1| of the run (the oracle's final set, doubled, since
+the flow accelerates from rest), the bound is n (eps H / 3 + 2^-23) in u."""
 import math
 
 import numpy as np
@@ -109,3 +116,43 @@ def test_slit_converges_to_exact_permeability():
     exact = sum((y - 0.5) * (H + 0.5 - y) for y in range(1, H + 1)) / (2 * (H + 2))
     assert r["converged"] and r["steps"] < 20000
     assert abs(r["K"] - exact) < 1e-9 * exact, (r["K"], exact)
+
+
+@pytest.mark.parametrize("prec,collision,axis", [("f16", "regularized", 0), ("bf16", "bgk", 1),
+                                                 ("f16", "bgk", 2), ("bf16", "regularized", 0)])
+def test_batch_16bit_storage_matches_oracle(prec, collision, axis):
+    import paper_2512_21696_amd as L
+    from oracle.lattice import W as WQ
+    doms, tau, g, steps = batch(), 0.8, 1e-4, 60
+    announce(f"rev batch {len(doms)} domains {prec} {collision} axis {axis}, {steps} steps")
+    got = L.rev_permeability(doms, tau=tau, g=g, axis=axis, collision=collision, precision=prec,
+                             max_steps=steps, check_every=20, tol=0.0, want_u=True)
+    eps = 2.0 ** -11 if prec == "f16" else 2.0 ** -8
+    nu = (tau - 0.5) / 3
+    worst = 0.0
+    for cls, r in zip(doms, got):
+        K, u, f = rev.permeability(params(cls.shape, tau, g, axis, collision), cls, steps, axis,
+                                   with_state=True)
+        pore = cls == 0
+        H = 2.0 * max(np.abs(f[i][pore] / WQ[i] - 1.0).max() for i in range(19))
+        bound = steps * (eps * H / 3.0 + 2.0 ** -23)
+        d = np.abs(r["u"] - u).max()
+        worst = max(worst, d / bound)
+        assert d < bound, (cls.shape, d, bound)
+        assert abs(r["K"] - K) < bound * nu / g, (cls.shape, r["K"], K)
+    print(prec, collision, "worst velocity error / bound", f"{worst:.2e}")
+
+
+def test_16bit_batch_equals_single_domain_runs():
+    import paper_2512_21696_amd as L
+    doms = batch()
+    announce("rev batch vs single-domain calls, f16")
+    kw = dict(tau=0.8, g=1e-4, axis=2, precision="f16", max_steps=50, check_every=10, tol=0.0,
+              want_u=True)
+    together = L.rev_permeability(doms, **kw)
+    for cls, r in zip(doms, together):
+        alone = L.rev_permeability([cls], **kw)[0]
+        assert alone["K"] == r["K"] and np.array_equal(alone["u"], r["u"])
+    # the stored sets are rounded to 16 bits: the fp32 run differs
+    f32 = L.rev_permeability(doms[1:2], **dict(kw, precision="f32"))[0]
+    assert not np.array_equal(f32["u"], together[1]["u"])

@@ -78,13 +78,25 @@ def test_binding_refuses_without_gpu():
 @pytest.mark.parametrize("kw,code", [
     (dict(tau=0.5), L.LBM_E_INVAL), (dict(g=0.0), L.LBM_E_INVAL), (dict(axis=3), L.LBM_E_INVAL),
     (dict(check_every=0), L.LBM_E_INVAL), (dict(max_steps=-1), L.LBM_E_INVAL),
-    (dict(tol=-1.0), L.LBM_E_INVAL), (dict(precision="f16"), L.LBM_E_UNSUPPORTED)])
+    (dict(tol=-1.0), L.LBM_E_INVAL)])
 def test_rev_permeability_rejects_bad_arguments_on_host(kw, code):
     import numpy as np
     with pytest.raises(L.LbmError) as e:
         L.rev_permeability([np.zeros((4, 4, 4), np.uint8)], **kw)
     assert e.value.code == code
     assert len(L.load_library().lbm_last_error(None)) > 0
+
+
+def test_rev_permeability_rejects_unknown_precision_on_host():
+    import numpy as np
+    lib = L.load_library()
+    p = L.lbm_rev_params(tau=1.0, g=1e-5, max_steps=10, check_every=5, precision=7)
+    res = (L.lbm_rev_result * 1)()
+    doms = (L.lbm_rev_domain * 1)()
+    cls = np.zeros((2, 2, 2), np.uint8)
+    doms[0].nx = doms[0].ny = doms[0].nz = 2
+    doms[0].cls = cls.ctypes.data
+    assert lib.lbm_rev_permeability(ctypes.byref(p), doms, 1, res) == L.LBM_E_UNSUPPORTED
 
 
 def test_rev_permeability_rejects_empty_and_bad_domains_on_host():
