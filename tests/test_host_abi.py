@@ -59,6 +59,20 @@ def test_oversized_grid_unsupported():
     assert L.load_library().lbm_validate_params(ctypes.byref(p), None, 0) == L.LBM_E_UNSUPPORTED
 
 
+@pytest.mark.parametrize("prec,largest,next_up", [
+    (L.PREC["f32"], (384, 384, 383), (384, 384, 384)),   # 2*19*N below 2^31
+    (L.PREC["f16"], (384, 384, 383), (384, 384, 384)),
+    (L.PREC["f64"], (304, 304, 305), (304, 304, 306))])  # 19*N*8 bytes below 4 GiB
+def test_largest_accepted_grid(prec, largest, next_up):
+    lib = L.load_library()
+    p = L.lbm_params_default()
+    p.precision = prec
+    p.nx, p.ny, p.nz = largest
+    assert lib.lbm_validate_params(ctypes.byref(p), None, 0) == L.LBM_OK
+    p.nx, p.ny, p.nz = next_up
+    assert lib.lbm_validate_params(ctypes.byref(p), None, 0) == L.LBM_E_UNSUPPORTED
+
+
 def test_null_handle_calls_fail_cleanly():
     lib = L.load_library()
     assert lib.lbm_step(None, 1) == L.LBM_E_INVAL

@@ -173,7 +173,7 @@ def gaussian_random_field(n: tuple, corr_len: float, seed: int) -> np.ndarray:
     ky = 2 * np.pi * np.fft.fftfreq(ny)[None, :, None]
     kx = 2 * np.pi * np.fft.rfftfreq(nx)[None, None, :]
     filt = np.exp(-0.5 * s * s * (kx * kx + ky * ky + kz * kz))
-    return np.fft.irfftn(np.fft.rfftn(w) * filt, s=(nz, ny, nx))
+    return np.fft.irfftn(np.fft.rfftn(w) * filt, s=(nz, ny, nx), axes=(0, 1, 2))
 
 
 def two_phase_densities(water: np.ndarray, m: float):
