@@ -235,14 +235,24 @@ __global__ __launch_bounds__(256) void k_rev_velocity(const Dom *__restrict__ do
   block_sum<1>(val, partial + blockIdx.x, false);
 }
 
-// per-domain sums of the block partials, in block order
-__global__ void k_rev_reduce(const Dom *__restrict__ doms, int ndom,
-                             const double *__restrict__ partial, double *__restrict__ usum) {
-  const int d = blockIdx.x * blockDim.x + threadIdx.x;
-  if (d >= ndom) return;
+// per-domain sums of the block partials, one 256-thread block per domain:
+// strided partial sums, then a fixed tree (the order depends only on the
+// domain's block count, so results are reproducible and batch-independent)
+__global__ __launch_bounds__(256) void k_rev_reduce(const Dom *__restrict__ doms,
+                                                    const double *__restrict__ partial,
+                                                    double *__restrict__ usum) {
+  __shared__ double sh[256];
+  const Dom D = doms[blockIdx.x];
+  const int t = threadIdx.x;
   double s = 0.0;
-  for (int b = 0; b < doms[d].nblk; ++b) s += partial[doms[d].blk0 + b];
-  usum[d] = s;
+  for (int b = t; b < D.nblk; b += 256) s += partial[D.blk0 + b];
+  sh[t] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) sh[t] += sh[t + w];
+    __syncthreads();
+  }
+  if (t == 0) usum[blockIdx.x] = sh[0];
 }
 
 struct DevBuf {  // device allocations and events of one call, freed on every exit path
@@ -364,8 +374,7 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   auto measure = [&](T *u_field) -> int {
     hipLaunchKernelGGL((k_rev_velocity<T, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, dmask,
                        Vtot, ax, (T)p->g, u_field, partial);
-    hipLaunchKernelGGL(k_rev_reduce, dim3((ndom + 63) / 64), dim3(64), 0, st, ddom, ndom, partial,
-                       usum);
+    hipLaunchKernelGGL(k_rev_reduce, dim3(ndom), dim3(256), 0, st, ddom, partial, usum);
     int r = check(hipMemcpyAsync(hsum.data(), usum, ndom * sizeof(double), hipMemcpyDeviceToHost, st),
                   "copy sums");
     if (r == LBM_OK) r = check(hipStreamSynchronize(st), "step");
