@@ -229,7 +229,9 @@ def rev_library(steps=400):
     conv = L.rev_permeability(doms, max_steps=20000, tol=1e-6, **kw)
     t2 = time.perf_counter() - t2
     K = np.array([r["K"] for r in conv])
-    b = 2 * 19 * 4 + 4  # populations read and written, the mask word
+    # pore voxels only: populations read and written, the 18 neighbour-table
+    # entries (16-bit storage also reads and writes the writer's density)
+    b = 2 * 19 * 4 + 18 * 4
     # storage precisions side by side: step time of the same fixed work, and K
     # of every domain after `kcmp` steps against the fp64 run's
     kcmp = 4000
@@ -240,7 +242,7 @@ def rev_library(steps=400):
         r = L.rev_permeability(doms, max_steps=steps, tol=0.0, **kp)
         pms = r[0]["step_ms"]
         Kp[prec] = np.array([x["K"] for x in L.rev_permeability(doms, max_steps=kcmp, tol=0.0, **kp)])
-        bp = 2 * 19 * es + 4
+        bp = 2 * 19 * es + 18 * 4 + (8 if es == 2 else 0)
         legs[prec] = {"ms_per_step": round(pms, 4),
                       "value": round(npore / (pms * 1e-3) / 1e6, 1),
                       "bytes_per_pore_update": bp,

@@ -299,10 +299,14 @@ typedef struct {
   double g;             /* body acceleration along axis, > 0 */
   int32_t axis;         /* 0 = x, 1 = y, 2 = z */
   int32_t collision;    /* LBM_COLL_REGULARIZED or LBM_COLL_BGK */
-  int32_t precision;    /* LBM_PREC_F64 or LBM_PREC_F32 (storage and arithmetic), or
-                           LBM_PREC_F16 / LBM_PREC_BF16: 16-bit storage of the offsets
-                           h = f_i / w_i - 1 from the rest state at density 1 (round to
-                           nearest even), decoded as f_i = w_i (1 + h); fp32 arithmetic */
+  int32_t precision;    /* populations are held as offsets and the step works on offsets:
+                           LBM_PREC_F64 or LBM_PREC_F32 (storage and arithmetic) hold
+                           f_i / w_i - 1 from the rest state at density 1;
+                           LBM_PREC_F16 / LBM_PREC_BF16 hold f_i / w_i - rho_writer, the
+                           offset from the density of the voxel that wrote it, rounded to
+                           nearest even in 16 bits (fp16 scaled by 2^12 to stay in its
+                           normal range), with fp32 arithmetic and an fp32 array of the
+                           writers' densities */
   int32_t side_walls;   /* 1: the four box faces parallel to the force are walls
                            (bounce-back) instead of periodic */
   int32_t mirror;       /* 1: each domain is run joined to its mirror image along the

@@ -1,21 +1,28 @@
 // Batched single-phase permeability runs (the REV library of the paper's
-// Appendix): many small domains of different sizes packed into one voxel
-// array, one launch per time step for all of them.
+// Appendix): many small domains of different sizes, one launch per time step
+// for all of them.
 //
-// Packing: domain d occupies packed voxels [voff, voff + N) of one
-// structure-of-arrays population buffer f[i][V], padded to a multiple of 256 so
-// that a 256-thread block never straddles two domains; blk_dom maps a block to
-// its domain.  Padding voxels are marked solid and never touched by a pull.
+// Layout: only pore voxels hold populations.  Domain d's pore voxels (x
+// fastest, then y, z) occupy slots [poff, poff + npore) of one
+// structure-of-arrays population buffer f[i][P], padded to a multiple of 256
+// so that a 256-thread block never straddles two domains (blk_dom maps a
+// block to its domain).  A neighbour table nbr[i - 1][P] (i = 1..18) holds the
+// slot of the pore voxel at x - c_i (across a periodic face, or -1 beyond a
+// wall face), -1 when that voxel is solid (halfway bounce-back: the slot's own
+// opposite population), and -2 on padding slots.  Sphere packs are mostly
+// solid (about 70 % here), so a pore update moves 19 + 19 populations and 18
+// table entries instead of the populations of 3 voxels.
 // The per-voxel model is the one-component step without gray voxels: pull with
-// halfway bounce-back (resolved from the neighbour mask, so a wall face of the
-// box is just a solid neighbour), moments, the regularised or BGK collision
-// and the force term of Eq. (3) for the body force rho g, emitted as the
-// quadratic form w_i (A + B.c_i + c_i^T C c_i) like the fused step.
+// halfway bounce-back, moments, the regularised or BGK collision and the force
+// term of Eq. (3) for the body force rho g, emitted as the quadratic form
+// w_i (A + B.c_i + c_i^T C c_i) like the fused step.
 //
-// Storage: the arithmetic type T (fp64 or fp32), or 16-bit offsets (fp16 or
-// bf16, SK) with fp32 arithmetic: a stored value of direction class i is
-// h = f / w_i - 1, the population's departure from the rest state at density 1
-// (single-phase flow stays near unit density), decoded as f = w_i (1 + h).
+// Storage: every population is held as an offset, f / w_i - 1 from the rest
+// state at density 1 (single-phase flow stays near unit density) in the
+// arithmetic type T (fp64 or fp32), or f / w_i - rho_writer from the density
+// of the voxel that wrote it, rounded to bf16 or (times 2^12) fp16 (SK), with
+// fp32 arithmetic and the writers' density offsets in an fp32 array per
+// level; the step works on offsets throughout.
 #include <memory>
 
 namespace lbm {
@@ -24,138 +31,129 @@ namespace rev {
 struct Dom {
   int nx, ny, nz;  // box as run (doubled along the force when mirrored)
   int N;           // voxels of the box
-  int voff;        // first packed voxel
-  int blk0, nblk;  // its blocks of 256 packed voxels
+  int voff;        // first voxel of the box in the dense class / slot map
+  int poff;        // first slot
+  int npore;       // pore voxels (slots in use)
+  int blk0, nblk;  // its blocks of 256 slots
 };
 
-__device__ inline void local_xyz(const Dom &D, int v, int &x, int &y, int &z) {
-  const int nxy = D.nx * D.ny;
-  z = v / nxy;
-  const int r = v - z * nxy;
-  y = r / D.nx;
-  x = r - y * D.nx;
-}
-
-// Class code and neighbour-solid bits of every packed voxel.  wall_axes has
-// bit k set when the faces normal to axis k are walls (a neighbour beyond
-// them counts as solid); other faces wrap around.
-__global__ __launch_bounds__(256) void k_rev_mask(const Dom *__restrict__ doms,
-                                                  const int *__restrict__ blk_dom,
-                                                  const uint8_t *__restrict__ cls,
-                                                  uint32_t *__restrict__ mask, int wall_axes) {
-  const int V = blockIdx.x * 256 + threadIdx.x;
-  const Dom D = doms[blk_dom[blockIdx.x]];
-  const int v = V - D.voff;
-  if (v >= D.N) {
-    mask[V] = SOLID_CODE << CLASS_SHIFT;
+// Neighbour table of every slot.  wall_axes has bit k set when the faces
+// normal to axis k are walls; other faces wrap around.  slot_of[voff + v] is
+// the slot of voxel v of the box or -1 (solid); vox_of[P] the voxel of slot P
+// within its box, -1 on padding.
+__global__ __launch_bounds__(256) void k_rev_nbr(const Dom *__restrict__ doms,
+                                                 const int *__restrict__ blk_dom,
+                                                 const int *__restrict__ slot_of,
+                                                 const int *__restrict__ vox_of,
+                                                 int *__restrict__ nbr, int Ptot, int wall_axes) {
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  const int v = vox_of[P];
+  if (v < 0) {
+    for (int i = 1; i < Q; ++i) nbr[(size_t)(i - 1) * Ptot + P] = -2;
     return;
   }
-  int x, y, z;
-  local_xyz(D, v, x, y, z);
-  uint32_t m = (cls[V] == 1 ? SOLID_CODE : 0u) << CLASS_SHIFT;
+  const Dom D = doms[blk_dom[blockIdx.x]];
+  const int nxy = D.nx * D.ny;
+  const int z = v / nxy, y = (v - z * nxy) / D.nx, x = v - z * nxy - y * D.nx;
   for (int i = 1; i < Q; ++i) {
-    int xs = x + cx(i), ys = y + cy(i), zs = z + cz(i);
-    bool solid = false;
+    int xs = x - cx(i), ys = y - cy(i), zs = z - cz(i);
+    bool wall = false;
     if (xs < 0 || xs >= D.nx) {
-      if (wall_axes & 1) solid = true;
+      wall |= (wall_axes & 1) != 0;
       xs = xs < 0 ? D.nx - 1 : 0;
     }
     if (ys < 0 || ys >= D.ny) {
-      if (wall_axes & 2) solid = true;
+      wall |= (wall_axes & 2) != 0;
       ys = ys < 0 ? D.ny - 1 : 0;
     }
     if (zs < 0 || zs >= D.nz) {
-      if (wall_axes & 4) solid = true;
+      wall |= (wall_axes & 4) != 0;
       zs = zs < 0 ? D.nz - 1 : 0;
     }
-    if (!solid) solid = cls[D.voff + xs + D.nx * (ys + D.ny * zs)] == 1;
-    if (solid) m |= 1u << i;
+    nbr[(size_t)(i - 1) * Ptot + P] = wall ? -1 : slot_of[D.voff + xs + D.nx * (ys + D.ny * zs)];
   }
-  mask[V] = m;
 }
 
-// Stored slot k of direction class i (opposite directions share a weight).
+// Stored value k: the offset h = f / w_i - 1 of a population from the rest
+// state at density 1, in T or (16-bit storage) bf16, or fp16 scaled by 2^12:
+// the offsets of a slow pore (|u| ~ 1e-6, h ~ 3 c.u) would otherwise fall
+// below fp16's smallest normal number (6.1e-5) and keep only a few bits, and
+// 2^12 still leaves room for |h| up to 16.
+constexpr float kRevF16Scale = 4096.f;
 template <typename T, int SK>
-__device__ inline T rev_load(const void *__restrict__ f, uint32_t k, int i) {
+__device__ inline T rev_load(const void *__restrict__ f, uint32_t k) {
   if constexpr (SK == SK_NATIVE) return static_cast<const T *>(f)[k];
-  else return (T)wq(i) * ((T)1 + dec16<SK>((uint32_t) static_cast<const uint16_t *>(f)[k]));
+  else if constexpr (SK == SK_F16)
+    return dec16<SK>((uint32_t) static_cast<const uint16_t *>(f)[k]) * (T)(1.0f / kRevF16Scale);
+  else return dec16<SK>((uint32_t) static_cast<const uint16_t *>(f)[k]);
 }
-// zero: a solid slot (never read), stored as zero bits
 template <typename T, int SK>
-__device__ inline void rev_store(void *__restrict__ f, size_t k, int i, T val, bool zero) {
-  if constexpr (SK == SK_NATIVE) static_cast<T *>(f)[k] = zero ? (T)0 : val;
-  else
-    static_cast<uint16_t *>(f)[k] =
-        zero ? (uint16_t)0 : enc16<SK>(val * (T)(1.0 / wq(i)) - (T)1);
-}
-
-// rest state at density 1 on pore voxels (16-bit: offset 0), zeros elsewhere
-template <typename T, int SK>
-__global__ __launch_bounds__(256) void k_rev_init(void *__restrict__ f,
-                                                  const uint32_t *__restrict__ mask, int Vtot) {
-  const int V = blockIdx.x * 256 + threadIdx.x;
-  if (V >= Vtot) return;
-  const bool pore = ((mask[V] >> CLASS_SHIFT) & 3u) != SOLID_CODE;
-  for (int i = 0; i < Q; ++i) rev_store<T, SK>(f, (size_t)i * Vtot + V, i, (T)wq(i), !pore);
+__device__ inline void rev_store(void *__restrict__ f, size_t k, T h) {
+  if constexpr (SK == SK_NATIVE) static_cast<T *>(f)[k] = h;
+  else if constexpr (SK == SK_F16) static_cast<uint16_t *>(f)[k] = enc16<SK>(h * (T)kRevF16Scale);
+  else static_cast<uint16_t *>(f)[k] = enc16<SK>(h);
 }
 
-// The 19 populations voxel V pulls from the stored (post-collision) set:
-// f_i from x - c_i, or this voxel's opposite slot when x - c_i is solid.
+// rest state at density 1 (offset 0, reference 0) on every slot, padding
+// included
 template <typename T, int SK>
-__device__ inline void pull19(const Dom &D, uint32_t mk, int V, const void *__restrict__ fin,
-                              uint32_t Vt, T (&f)[Q]) {
-  int x, y, z;
-  local_xyz(D, V - D.voff, x, y, z);
-  const int X3[3] = {x == 0 ? D.nx - 1 : x - 1, x, x == D.nx - 1 ? 0 : x + 1};
-  const int Y3[3] = {y == 0 ? D.ny - 1 : y - 1, y, y == D.ny - 1 ? 0 : y + 1};
-  const int Z3[3] = {z == 0 ? D.nz - 1 : z - 1, z, z == D.nz - 1 ? 0 : z + 1};
-  f[0] = rev_load<T, SK>(fin, (uint32_t)V, 0);
+__global__ __launch_bounds__(256) void k_rev_init(void *__restrict__ f, T *__restrict__ ref,
+                                                  int Ptot) {
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  for (int i = 0; i < Q; ++i) rev_store<T, SK>(f, (size_t)i * Ptot + P, (T)0);
+  if (ref) ref[P] = (T)0;
+}
+
+// The 19 offsets f_i / w_i - 1 slot P pulls from the stored (post-collision)
+// set: from the slot at x - c_i, or this slot's opposite population when that
+// neighbour is solid or a wall (opposite directions share a weight, so the
+// offset carries over unchanged).  16-bit storage keeps each value relative
+// to its writer's density, h = f_i / w_i - rho_writer, and ref holds the
+// writers' density offsets rho - 1 of that level: the offset from the rest
+// state is ref[writer] + h.  (Relative to the rest state alone, a stored value
+// would carry the pressure field's density offsets, up to 1e-3 here, beside a
+// velocity part down to 1e-6 in a tight pore, which 16-bit rounding then
+// loses.)
+template <typename T, int SK>
+__device__ inline void pull19(const int *__restrict__ nbr, int P, const void *__restrict__ fin,
+                              const T *__restrict__ ref, uint32_t Pt, T (&h)[Q]) {
+  constexpr bool REF = SK != SK_NATIVE;
+  const T own = REF ? ref[P] : (T)0;
+  h[0] = rev_load<T, SK>(fin, (uint32_t)P) + own;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
-    const uint32_t src =
-        (uint32_t)(D.voff + X3[1 - cx(i)] + D.nx * (Y3[1 - cy(i)] + D.ny * Z3[1 - cz(i)]));
-    const uint32_t k = ((mk >> opp(i)) & 1u) ? (uint32_t)opp(i) * Vt + (uint32_t)V
-                                              : (uint32_t)i * Vt + src;
-    f[i] = rev_load<T, SK>(fin, k, i);
+    const int s = nbr[(size_t)(i - 1) * Pt + P];
+    const uint32_t k = s >= 0 ? (uint32_t)i * Pt + (uint32_t)s : (uint32_t)opp(i) * Pt + (uint32_t)P;
+    h[i] = rev_load<T, SK>(fin, k);
+    if (REF) h[i] += s >= 0 ? ref[s] : own;
   }
 }
 
-// One time step of every packed domain.
+// One time step of every packed domain, in offsets: with f_i = w_i (1 + h_i),
+// rho = 1 + d with d = sum_i w_i h_i, m = sum_i w_i c_i h_i, and the second
+// moment sum_i w_i c_i c_i (1 + h_i) = I / 3 + sum_i w_i c_i c_i h_i, so every
+// moment of the departure from rest is formed from the small offsets and the
+// new offsets f_post / w_i - 1 come out of the quadratic form with the unit
+// density already taken out (the velocity stays accurate in fp32 at the
+// 1e-5 body forces of a permeability run).
 template <typename T, bool REG, int SK>
-__global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
-                                                  const int *__restrict__ blk_dom,
+__global__ __launch_bounds__(256) void k_rev_step(const int *__restrict__ nbr,
                                                   const void *__restrict__ fin,
                                                   void *__restrict__ fout,
-                                                  const uint32_t *__restrict__ mask, int Vtot,
+                                                  const T *__restrict__ ref_in,
+                                                  T *__restrict__ ref_out, int Ptot,
                                                   T g0, T g1, T g2, T omega) {
-  const int V = blockIdx.x * 256 + threadIdx.x;
-  const Dom D = doms[blk_dom[blockIdx.x]];
-  const uint32_t mk = mask[V];
-  const bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
-  // no pull ever reads a solid slot: a wave of solid voxels (or padding) has
-  // nothing to do; solid lanes of mixed waves store zeros so that every store
-  // covers whole lines
-  if (__all(solid)) return;
-  // solid lanes store zeros only when their 128-byte line holds a fluid voxel
-  // (16-bit storage: one line per wave, which holds one here)
-  constexpr int LPL = 128 / (SK == SK_NATIVE ? (int)sizeof(T) : 2);
-  constexpr uint64_t LMASK = LPL >= 64 ? ~0ull : ((1ull << (LPL & 63)) - 1ull);
-  const uint64_t live = __ballot(!solid);
-  const int lane = threadIdx.x & 63;
-  const bool dead_line = solid && ((live >> (lane / LPL * LPL % 64)) & LMASK) == 0ull;
-  const uint32_t Vt = (uint32_t)Vtot;
-  T f[Q];  // the pulled set
-  if (!solid) {
-    pull19<T, SK>(D, mk, V, fin, Vt, f);
-  } else {
-#pragma unroll
-    for (int i = 0; i < Q; ++i) f[i] = (T)0;
-  }
-  T rho = 0, m0 = 0, m1 = 0, m2 = 0, Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  const bool pad = nbr[P] == -2;  // padding slot
+  if (__all(pad)) return;
+  if (pad) return;
+  T h[Q];  // the pulled offsets from the rest state
+  pull19<T, SK>(nbr, P, fin, ref_in, (uint32_t)Ptot, h);
+  T d = 0, m0 = 0, m1 = 0, m2 = 0, Pxx = 0, Pyy = 0, Pzz = 0, Pxy = 0, Pxz = 0, Pyz = 0;
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
-    const T v = f[i];
-    rho += v;
+    const T v = (T)wq(i) * h[i];
+    d += v;
     if (cx(i)) { m0 += cx(i) * v; Pxx += v; }
     if (cy(i)) { m1 += cy(i) * v; Pyy += v; }
     if (cz(i)) { m2 += cz(i) * v; Pzz += v; }
@@ -163,7 +161,7 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
     if (cx(i) && cz(i)) Pxz += cx(i) * cz(i) * v;
     if (cy(i) && cz(i)) Pyz += cy(i) * cz(i) * v;
   }
-  const T r = solid ? (T)1 : rho;
+  const T r = (T)1 + d;
   const T ir = (T)1 / r;
   // common velocity u' = m / rho, force F = rho g, force term at u' + F/(2 rho)
   const T u0 = m0 * ir, u1 = m1 * ir, u2 = m2 * ir;
@@ -173,7 +171,9 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
   const T uF = a0 * F0 + a1 * F1 + a2 * F2;
   const T keep = (T)1 - omega;
   const T we = REG ? r : omega * r;  // weight of the equilibrium part
-  T A = we * ((T)1 - (T)1.5 * usq) - (T)3 * uF;
+  // A - 1: regularised we - 1 = d; BGK we - 1 + keep = omega d (the keep f_i
+  // part adds keep h_i below)
+  T A = (REG ? d : omega * d) - (T)1.5 * we * usq - (T)3 * uF;
   const T B0 = (T)3 * (we * u0 + F0), B1 = (T)3 * (we * u1 + F1), B2 = (T)3 * (we * u2 + F2);
   const T er = (T)4.5 * we;
   T Cxx = er * u0 * u0 + (T)9 * a0 * F0;
@@ -183,10 +183,11 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
   T Cxz = er * u0 * u2 + (T)4.5 * (a0 * F2 + a2 * F0);
   T Cyz = er * u1 * u2 + (T)4.5 * (a1 * F2 + a2 * F1);
   if (REG) {
-    // non-equilibrium second moment; its first moment vanishes for one component
-    const T cs2 = (T)(1.0 / 3.0);
-    const T qxx = Pxx - r * (cs2 + u0 * u0), qyy = Pyy - r * (cs2 + u1 * u1);
-    const T qzz = Pzz - r * (cs2 + u2 * u2);
+    // non-equilibrium second moment Pi - rho (I/3 + u u), with the unit
+    // density's I/3 taken out; its first moment vanishes for one component
+    const T d3 = d * (T)(1.0 / 3.0);
+    const T qxx = Pxx - d3 - r * u0 * u0, qyy = Pyy - d3 - r * u1 * u1;
+    const T qzz = Pzz - d3 - r * u2 * u2;
     const T qxy = Pxy - r * u0 * u1, qxz = Pxz - r * u0 * u2, qyz = Pyz - r * u1 * u2;
     const T k45 = (T)4.5 * keep;
     A -= (T)1.5 * keep * (qxx + qyy + qzz);
@@ -196,42 +197,43 @@ __global__ __launch_bounds__(256) void k_rev_step(const Dom *__restrict__ doms,
 #pragma unroll
   for (int i = 0; i < Q; ++i) {
     const T c0 = (T)cx(i), c1 = (T)cy(i), c2 = (T)cz(i);
-    T val = (T)wq(i) * (A + B0 * c0 + B1 * c1 + B2 * c2 + Cxx * c0 * c0 + Cyy * c1 * c1 +
-                        Czz * c2 * c2 + (T)2 * (Cxy * c0 * c1 + Cxz * c0 * c2 + Cyz * c1 * c2));
-    if (!REG) val += keep * f[i];
-    if (!dead_line) rev_store<T, SK>(fout, (size_t)i * Vtot + V, i, val, solid);
+    T val = A + B0 * c0 + B1 * c1 + B2 * c2 + Cxx * c0 * c0 + Cyy * c1 * c1 + Czz * c2 * c2 +
+            (T)2 * (Cxy * c0 * c1 + Cxz * c0 * c2 + Cyz * c1 * c2);
+    if (!REG) val += keep * h[i];
+    if (SK != SK_NATIVE) val -= d;  // relative to this voxel's density (its mass is kept)
+    rev_store<T, SK>(fout, (size_t)i * Ptot + P, val);
   }
+  if (SK != SK_NATIVE) ref_out[P] = d;
 }
 
 // Velocity along the force, (m + F/2)_axis / rho, of the post-streaming set
 // (the stored set pulled as a step would): per-block fp64 sums over pore
 // voxels, and the field when uf is given.
 template <typename T, int SK>
-__global__ __launch_bounds__(256) void k_rev_velocity(const Dom *__restrict__ doms,
-                                                      const int *__restrict__ blk_dom,
+__global__ __launch_bounds__(256) void k_rev_velocity(const int *__restrict__ nbr,
                                                       const void *__restrict__ fin,
-                                                      const uint32_t *__restrict__ mask, int Vtot,
+                                                      const T *__restrict__ ref, int Ptot,
                                                       int axis, T g, T *__restrict__ uf,
                                                       double *__restrict__ partial) {
-  const int V = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t mk = mask[V];
-  const bool pore = ((mk >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+  const int P = blockIdx.x * 256 + threadIdx.x;
+  const bool pore = nbr[P] != -2;
   double val[1] = {0.0};
   T u = 0;
   if (pore) {
-    const Dom D = doms[blk_dom[blockIdx.x]];
-    T f[Q];
-    pull19<T, SK>(D, mk, V, fin, (uint32_t)Vtot, f);
-    T rho = 0, m = 0;
+    T h[Q];
+    pull19<T, SK>(nbr, P, fin, ref, (uint32_t)Ptot, h);
+    T d = 0, m = 0;
     for (int i = 0; i < Q; ++i) {
       const int c = axis == 0 ? cx(i) : (axis == 1 ? cy(i) : cz(i));
-      rho += f[i];
-      m += c * f[i];
+      const T v = (T)wq(i) * h[i];
+      d += v;
+      m += c * v;
     }
+    const T rho = (T)1 + d;
     u = (m + (T)0.5 * rho * g) / rho;
     val[0] = (double)u;
   }
-  if (uf) uf[V] = u;
+  if (uf) uf[P] = u;
   block_sum<1>(val, partial + blockIdx.x, false);
 }
 
@@ -291,28 +293,25 @@ template <typename T, int SK>
 int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out) {
   const hipStream_t st = (hipStream_t)p->stream;
   const int ax = p->axis;
-  // boxes as run, packing offsets, block table
+  // boxes as run, dense offsets, slots of the pore voxels, block table
   std::vector<Dom> hd(ndom);
   long long Vtot_ll = 0;
   for (int d = 0; d < ndom; ++d) {
     int n[3] = {doms[d].nx, doms[d].ny, doms[d].nz};
     if (p->mirror) n[ax] *= 2;
     const long long N = (long long)n[0] * n[1] * n[2];
-    const long long Npad = (N + 255) / 256 * 256;
-    if (Vtot_ll + Npad > (long long)(0x7fffffff / Q))
-      return fail(LBM_E_UNSUPPORTED, "more than 2^31 / 19 packed voxels");
-    hd[d] = Dom{n[0], n[1], n[2], (int)N, (int)Vtot_ll, (int)(Vtot_ll / 256), (int)(Npad / 256)};
-    Vtot_ll += Npad;
+    if (Vtot_ll + N > (long long)0x7fffffff) return fail(LBM_E_UNSUPPORTED, "more than 2^31 voxels");
+    hd[d] = Dom{n[0], n[1], n[2], (int)N, (int)Vtot_ll, 0, 0, 0, 0};
+    Vtot_ll += N;
   }
   const int Vtot = (int)Vtot_ll;
-  const int nblk = Vtot / 256;
-  std::vector<int> blk_dom(nblk);
-  std::vector<uint8_t> hcls((size_t)Vtot, 1);
-  std::vector<long long> npore(ndom, 0);
+  std::vector<int> slot_of((size_t)Vtot, -1), vox_of;
+  long long Ptot_ll = 0;
   for (int d = 0; d < ndom; ++d) {
-    const Dom &D = hd[d];
-    for (int b = 0; b < D.nblk; ++b) blk_dom[D.blk0 + b] = d;
+    Dom &D = hd[d];
+    D.poff = (int)Ptot_ll;
     const int bx = doms[d].nx, by = doms[d].ny;
+    int np = 0;
     for (int z = 0; z < D.nz; ++z)
       for (int y = 0; y < D.ny; ++y)
         for (int x = 0; x < D.nx; ++x) {
@@ -324,28 +323,72 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
           const uint8_t c = doms[d].cls[(size_t)s[0] + (size_t)bx * (s[1] + (size_t)by * s[2])];
           if (c != LBM_PORE && c != LBM_SOLID)
             return fail(LBM_E_INVAL, "domain classes must be LBM_PORE or LBM_SOLID");
-          hcls[(size_t)D.voff + x + (size_t)D.nx * (y + (size_t)D.ny * z)] = c;
-          npore[d] += c == LBM_PORE;
+          if (c == LBM_PORE) {
+            const int v = x + D.nx * (y + D.ny * z);
+            slot_of[(size_t)D.voff + v] = D.poff + np++;
+            vox_of.push_back(v);
+          }
         }
+    const long long ppad = ((long long)np + 255) / 256 * 256;
+    if (Ptot_ll + ppad > (long long)(0x7fffffff / Q))
+      return fail(LBM_E_UNSUPPORTED, "more than 2^31 / 19 pore voxels");
+    vox_of.resize((size_t)(Ptot_ll + ppad), -1);
+    D.npore = np;
+    D.blk0 = (int)(Ptot_ll / 256);
+    D.nblk = (int)(ppad / 256);
+    Ptot_ll += ppad;
   }
+  const int Ptot = (int)Ptot_ll;
+  const int nblk = Ptot / 256;
+  std::vector<int> blk_dom((size_t)std::max(nblk, 1), 0);
+  for (int d = 0; d < ndom; ++d)
+    for (int b = 0; b < hd[d].nblk; ++b) blk_dom[(size_t)hd[d].blk0 + b] = d;
   const bool want_u = [&] {
     for (int d = 0; d < ndom; ++d)
       if (doms[d].u_out) return true;
     return false;
   }();
+  auto write_u = [&](const std::vector<T> &hu) {  // slots back to the callers' boxes
+    for (int d = 0; d < ndom; ++d) {
+      if (!doms[d].u_out) continue;
+      const Dom &D = hd[d];
+      const int L = (&doms[d].nx)[ax];
+      std::fill(doms[d].u_out, doms[d].u_out + (size_t)doms[d].nx * doms[d].ny * doms[d].nz, 0.0);
+      for (int k = 0; k < D.npore; ++k) {
+        const int v = vox_of[(size_t)D.poff + k];
+        const int z = v / (D.nx * D.ny), y = (v / D.nx) % D.ny, x = v % D.nx;
+        const int c[3] = {x, y, z};
+        if (c[ax] >= L) continue;  // the mirrored half
+        doms[d].u_out[(size_t)x + (size_t)doms[d].nx * (y + (size_t)doms[d].ny * z)] =
+            hu.empty() ? 0.0 : (double)hu[(size_t)D.poff + k];
+      }
+    }
+  };
+  const double nu = (p->tau - 0.5) / 3.0;
+  if (nblk == 0) {  // no pore voxel anywhere: nothing flows
+    write_u({});
+    for (int d = 0; d < ndom; ++d)
+      out[d] = lbm_rev_result{0.0, 0.0, 0.0, 0, p->tol > 0 ? 1 : 0, 0, 0.0};
+    return LBM_OK;
+  }
 
   DevBuf mem;
   Dom *ddom = mem.get<Dom>(ndom);
   int *dblk = mem.get<int>(nblk);
-  uint8_t *dcls = mem.get<uint8_t>(Vtot);
-  uint32_t *dmask = mem.get<uint32_t>(Vtot);
+  int *dslot = mem.get<int>(Vtot);
+  int *dvox = mem.get<int>(Ptot);
+  int *dnbr = mem.get<int>((size_t)(Q - 1) * Ptot);
   const size_t es = SK == SK_NATIVE ? sizeof(T) : 2;  // bytes per stored value
-  void *fa = mem.get<uint8_t>((size_t)Q * Vtot * es);
-  void *fb = mem.get<uint8_t>((size_t)Q * Vtot * es);
-  T *uf = want_u ? mem.get<T>(Vtot) : nullptr;
+  void *fa = mem.get<uint8_t>((size_t)Q * Ptot * es);
+  void *fb = mem.get<uint8_t>((size_t)Q * Ptot * es);
+  T *uf = want_u ? mem.get<T>(Ptot) : nullptr;
+  // 16-bit storage: the writers' density offsets, one array per level
+  T *ra = SK != SK_NATIVE ? mem.get<T>(Ptot) : nullptr;
+  T *rb = SK != SK_NATIVE ? mem.get<T>(Ptot) : nullptr;
   double *partial = mem.get<double>(nblk);
   double *usum = mem.get<double>(ndom);
-  if (!ddom || !dblk || !dcls || !dmask || !fa || !fb || (want_u && !uf) || !partial || !usum)
+  if (!ddom || !dblk || !dslot || !dvox || !dnbr || !fa || !fb || (want_u && !uf) || !partial ||
+      !usum || (SK != SK_NATIVE && (!ra || !rb)))
     return fail(LBM_E_NOMEM, "device allocation failed");
   hipEvent_t ev0 = mem.event(), ev1 = mem.event();
   if (!ev0 || !ev1) return fail(LBM_E_DEVICE, "hipEventCreate failed");
@@ -356,24 +399,29 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     rc = check(hipMemcpyAsync(dblk, blk_dom.data(), nblk * sizeof(int), hipMemcpyHostToDevice, st),
                "copy block table");
   if (rc == LBM_OK)
-    rc = check(hipMemcpyAsync(dcls, hcls.data(), (size_t)Vtot, hipMemcpyHostToDevice, st),
-               "copy classes");
+    rc = check(hipMemcpyAsync(dslot, slot_of.data(), (size_t)Vtot * sizeof(int),
+                              hipMemcpyHostToDevice, st),
+               "copy slot map");
+  if (rc == LBM_OK)
+    rc = check(hipMemcpyAsync(dvox, vox_of.data(), (size_t)Ptot * sizeof(int),
+                              hipMemcpyHostToDevice, st),
+               "copy slot voxels");
   if (rc != LBM_OK) return rc;
   const int wall_axes = p->side_walls ? (7 & ~(1 << ax)) : 0;
-  hipLaunchKernelGGL(k_rev_mask, dim3(nblk), dim3(256), 0, st, ddom, dblk, dcls, dmask, wall_axes);
-  hipLaunchKernelGGL((k_rev_init<T, SK>), dim3(nblk), dim3(256), 0, st, fa, dmask, Vtot);
+  hipLaunchKernelGGL(k_rev_nbr, dim3(nblk), dim3(256), 0, st, ddom, dblk, dslot, dvox, dnbr, Ptot,
+                     wall_axes);
+  hipLaunchKernelGGL((k_rev_init<T, SK>), dim3(nblk), dim3(256), 0, st, fa, ra, Ptot);
 
   const T gv[3] = {ax == 0 ? (T)p->g : (T)0, ax == 1 ? (T)p->g : (T)0, ax == 2 ? (T)p->g : (T)0};
   const T omega = (T)(1.0 / p->tau);
   const bool reg = p->collision == LBM_COLL_REGULARIZED;
-  const double nu = (p->tau - 0.5) / 3.0;
   std::vector<double> hsum(ndom), prev(ndom, 0.0);
   std::vector<int64_t> conv_step(ndom, -1);
   int64_t done = 0;
   bool have_prev = false;
   auto measure = [&](T *u_field) -> int {
-    hipLaunchKernelGGL((k_rev_velocity<T, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, dmask,
-                       Vtot, ax, (T)p->g, u_field, partial);
+    hipLaunchKernelGGL((k_rev_velocity<T, SK>), dim3(nblk), dim3(256), 0, st, dnbr, fa,
+                       (const T *)ra, Ptot, ax, (T)p->g, u_field, partial);
     hipLaunchKernelGGL(k_rev_reduce, dim3(ndom), dim3(256), 0, st, ddom, partial, usum);
     int r = check(hipMemcpyAsync(hsum.data(), usum, ndom * sizeof(double), hipMemcpyDeviceToHost, st),
                   "copy sums");
@@ -403,12 +451,13 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     if (rc != LBM_OK) return rc;
     for (int64_t s = 0; s < k; ++s) {
       if (reg)
-        hipLaunchKernelGGL((k_rev_step<T, true, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa, fb,
-                           dmask, Vtot, gv[0], gv[1], gv[2], omega);
+        hipLaunchKernelGGL((k_rev_step<T, true, SK>), dim3(nblk), dim3(256), 0, st, dnbr, fa, fb,
+                           (const T *)ra, rb, Ptot, gv[0], gv[1], gv[2], omega);
       else
-        hipLaunchKernelGGL((k_rev_step<T, false, SK>), dim3(nblk), dim3(256), 0, st, ddom, dblk, fa,
-                           fb, dmask, Vtot, gv[0], gv[1], gv[2], omega);
+        hipLaunchKernelGGL((k_rev_step<T, false, SK>), dim3(nblk), dim3(256), 0, st, dnbr, fa, fb,
+                           (const T *)ra, rb, Ptot, gv[0], gv[1], gv[2], omega);
       std::swap(fa, fb);
+      std::swap(ra, rb);
     }
     rc = check(hipGetLastError(), "step launch");
     if (rc == LBM_OK) rc = check(hipEventRecord(ev1, st), "event");
@@ -422,26 +471,18 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   if (want_u) {
     rc = measure(uf);
     if (rc != LBM_OK) return rc;
-    std::vector<T> hu((size_t)Vtot);
-    rc = check(hipMemcpyAsync(hu.data(), uf, (size_t)Vtot * sizeof(T), hipMemcpyDeviceToHost, st),
+    std::vector<T> hu((size_t)Ptot);
+    rc = check(hipMemcpyAsync(hu.data(), uf, (size_t)Ptot * sizeof(T), hipMemcpyDeviceToHost, st),
                "copy velocity");
     if (rc == LBM_OK) rc = check(hipStreamSynchronize(st), "copy velocity");
     if (rc != LBM_OK) return rc;
-    for (int d = 0; d < ndom; ++d) {
-      if (!doms[d].u_out) continue;
-      const Dom &D = hd[d];
-      for (int z = 0; z < doms[d].nz; ++z)
-        for (int y = 0; y < doms[d].ny; ++y)
-          for (int x = 0; x < doms[d].nx; ++x)
-            doms[d].u_out[(size_t)x + (size_t)doms[d].nx * (y + (size_t)doms[d].ny * z)] =
-                (double)hu[(size_t)D.voff + x + (size_t)D.nx * (y + (size_t)D.ny * z)];
-    }
+    write_u(hu);
   }
   for (int d = 0; d < ndom; ++d) {
     const double N = (double)hd[d].N;
     out[d].K = hsum[d] / N * nu / p->g;
-    out[d].phi = (double)npore[d] / N;
-    out[d].u_mean = npore[d] > 0 ? hsum[d] / (double)npore[d] : 0.0;
+    out[d].phi = (double)hd[d].npore / N;
+    out[d].u_mean = hd[d].npore > 0 ? hsum[d] / (double)hd[d].npore : 0.0;
     out[d].steps = conv_step[d] >= 0 ? conv_step[d] : done;
     out[d].converged = conv_step[d] >= 0;
     out[d].pad_ = 0;

@@ -9,12 +9,16 @@ is absolute: at most one ulp of the unit density, 2^-23, per step, summed
 over the n steps (errors persist for a viscous time), n 2^-23 in u and
 n 2^-23 nu / g in K.
 
-16-bit storage (fp16, bf16): a stored value is h = f_i / w_i - 1, rounded to
-the nearest of a format with unit roundoff eps (2^-11 fp16, 2^-8 bf16), so a
-population carries an error of at most w_i eps |h| per step.  The velocity
-along an axis takes sum_i w_i c_ia^2 = 1/3 of that per step: with H the
-largest |f_i / w_i - 1| of the run (the oracle's final set, doubled, since
-the flow accelerates from rest), the bound is n (eps H / 3 + 2^-23) in u."""
+16-bit storage (fp16, bf16): a stored value is h = f_i / w_i - rho_w, the
+offset from the density of the voxel that wrote it, rounded to the nearest
+of a format with unit roundoff eps (2^-11 fp16, 2^-8 bf16; fp16 holds 2^12 h,
+an exact scaling, so offsets down to 1.5e-8 stay normal and smaller ones err
+by at most 2^-36, far below the fp32 term), so a population carries an error
+of at most w_i eps |h| per step.  The velocity along an axis takes
+sum_i w_i c_ia^2 = 1/3 of that per step.  |h| is at most the largest
+|f_i / w_i - 1| plus the largest |rho - 1| of the run; with H twice the sum of
+those two on the oracle's final set (the flow accelerates from rest), the
+bound is n (eps H / 3 + 2^-23) in u."""
 import math
 
 import numpy as np
@@ -134,7 +138,9 @@ def test_batch_16bit_storage_matches_oracle(prec, collision, axis):
         K, u, f = rev.permeability(params(cls.shape, tau, g, axis, collision), cls, steps, axis,
                                    with_state=True)
         pore = cls == 0
-        H = 2.0 * max(np.abs(f[i][pore] / WQ[i] - 1.0).max() for i in range(19))
+        rho = f.sum(axis=0)[pore]
+        H = 2.0 * (max(np.abs(f[i][pore] / WQ[i] - 1.0).max() for i in range(19)) +
+                   np.abs(rho - 1.0).max())
         bound = steps * (eps * H / 3.0 + 2.0 ** -23)
         d = np.abs(r["u"] - u).max()
         worst = max(worst, d / bound)
