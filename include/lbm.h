@@ -271,9 +271,12 @@ int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset);
  * on fully resolved sub-volumes driven by a body force, with K = phi <u> nu / g
  * (Appendix: the domain mirrored along the force and periodic in that
  * direction, the four other sides closed by walls).  lbm_rev_permeability runs
- * any number of such domains of different sizes together: their voxels are
- * packed into one array (each domain padded to a multiple of 256 voxels) and
- * one launch per time step updates all of them.  Each domain is periodic on
+ * any number of such domains of different sizes together: their pore voxels
+ * are packed into one array (each domain padded to a multiple of 256 slots,
+ * with a table of each slot's 18 pull sources; solid voxels hold nothing) and
+ * one launch per time step updates all of them.  Device memory per call:
+ * about 2 x 19 stored values + 19 x 4 bytes per pore slot, plus 8 bytes per
+ * voxel of the boxes while the table is built.  Each domain is periodic on
  * its own box (or walled on the sides and mirrored, as flags); the model is the
  * one-component case of lbm_step without gray voxels (D3Q19, halfway
  * bounce-back at solid voxels, the regularised or BGK collision, the force
