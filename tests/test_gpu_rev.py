@@ -162,3 +162,22 @@ def test_16bit_batch_equals_single_domain_runs():
     # the stored sets are rounded to 16 bits: the fp32 run differs
     f32 = L.rev_permeability(doms[1:2], **dict(kw, precision="f32"))[0]
     assert not np.array_equal(f32["u"], together[1]["u"])
+
+
+def test_solid_domains():
+    """A domain without pore voxels holds no slots: K = phi = 0 in a batch (the
+    other domains' results are unchanged) and alone (nothing is launched)."""
+    import paper_2512_21696_amd as L
+    doms = batch()
+    solid = np.ones((5, 4, 6), np.uint8)
+    announce("rev batch with an all-solid domain, and an all-solid call, f32")
+    kw = dict(tau=0.8, g=1e-4, axis=0, precision="f32", max_steps=40, check_every=10, tol=0.0,
+              want_u=True)
+    ref = L.rev_permeability(doms, **kw)
+    got = L.rev_permeability(doms[:2] + [solid] + doms[2:], **kw)
+    for r, g_ in zip(ref, got[:2] + got[3:]):
+        assert r["K"] == g_["K"] and np.array_equal(r["u"], g_["u"])
+    assert got[2]["K"] == 0.0 and got[2]["phi"] == 0.0 and not got[2]["u"].any()
+    alone = L.rev_permeability([solid, solid], **dict(kw, tol=1e-6))
+    for r in alone:
+        assert r["K"] == 0.0 and r["phi"] == 0.0 and r["converged"] and not r["u"].any()
