@@ -286,7 +286,10 @@ int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset);
  * domain (velocity (m + F/2)/rho at the post-streaming level, fp64 sums in a
  * fixed order); a domain has converged when it changed by at most tol times
  * its magnitude since the previous check.  The run stops when every domain
- * has converged or after max_steps; tol = 0 runs exactly max_steps.
+ * has converged or after max_steps; tol = 0 runs exactly max_steps.  A domain
+ * without pore voxels gives K = phi = u_mean = 0 and counts as converged from
+ * the second check (when tol > 0); if no domain has pore voxels nothing is
+ * launched and every result is zero (converged when tol > 0, steps 0).
  */
 typedef struct {
   int32_t nx, ny, nz;   /* box (each >= 1) */
