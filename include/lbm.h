@@ -5,12 +5,13 @@
  * The model (paper: "Enhanced numerical models for two-component fluid flow in
  * multiscale porous structures", Sec. II):
  *   - LB equation on D3Q19 with a collision projected on the Hermite space and
- *     the exact-difference force term, Eqs. (2)-(3);
+ *     the force term of Eq. (3): the exact-difference form in pore voxels, the
+ *     second-order (Guo) form in gray voxels (below), Eqs. (2)-(3);
  *   - Shan-Chen pseudo-potential inter-component force;
  *   - CSF surface-tension control, Eq. (4), in under-resolved (gray) voxels;
  *   - the under-resolved-region force of Eq. (1): capillary term
  *     -Pc(Sw) rho_r n H and Brinkman resistance rho nu / (K0(phi) Kr(Sw)) rho_r u,
- *     taken semi-implicitly (default) or implicitly (lbm_params.resistance);
+ *     with u from the trapezoidal rule (below);
  *   - residual-component model (Sec. II, Fig. 6): trapped water/oil amounts read
  *     off the J-scaled (Eq. (5)) Pc-Sw curve at Pc^{ref,max} / Pc^{ref,min};
  *   - tensorial resistivity, Eqs. (6)-(7), principal axes from the Hessian and
@@ -68,18 +69,19 @@ enum { LBM_PORE = 0, LBM_SOLID = 1, LBM_GRAY = 2 };
 enum { LBM_PREC_F64 = 0, LBM_PREC_F32 = 1, LBM_PREC_F16 = 2, LBM_PREC_BF16 = 3 };
 enum { LBM_COLL_REGULARIZED = 0, LBM_COLL_BGK = 1 };
 enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
-/* Time discretisation of the Brinkman resistance of Eq. (1) (paper silent).
- * SEMI_IMPLICIT: R u with u = (rho I + R/2)^-1 (m + F_ex/2), the half-force
- *   (trapezoidal) velocity: second order, the uniform Darcy state exact, and at
- *   rest a force is carried entirely by pressure; the momentum of a voxel with
- *   R >> rho reverses every step.
- * IMPLICIT: R u* with u* = (rho I + R)^-1 (m + F_ex), the velocity after the
- *   force (backward Euler): the uniform Darcy state exact and the momentum of a
- *   strongly resisting voxel decays (L-stable), first order in R/rho; at rest
- *   pressure carries only 2 rho / (2 rho + R) of a force inside a gray voxel.
- * Either way F_res^a = -(rho^a / rho) R u and the reported velocity is
- * (m + sum_a F^a / 2) / rho. */
-enum { LBM_RES_SEMI_IMPLICIT = 0, LBM_RES_IMPLICIT = 1 };
+/* Time discretisation of the Brinkman resistance of Eq. (1) (the paper is
+ * silent): the resistance acts on the velocity u = (rho I + R/2)^-1 (m + F_ex/2)
+ * (the trapezoidal rule), F_res^a = -(rho^a / rho) R u, which is also the
+ * reported velocity (m + sum_a F^a / 2) / rho.  Its steady states are exactly
+ * Darcy's law, whether a body force or a pressure gradient drives the flow, and
+ * at rest pressure carries all of a force.  Where R >> rho the gathered
+ * momentum of a voxel reverses at every step; gray voxels therefore take the
+ * force term of Eq. (3) in its second-order form, with the equilibrium, the
+ * non-equilibrium part and the force term all at ua = u' + F^a / (2 rho^a) and
+ * the force term weighted by 1 - 1/(2 tau^a), which keeps the large resistance
+ * force out of the equilibrium's quadratic terms (pore voxels keep the
+ * exact-difference form, equilibrium at u').  Both forms give every component
+ * the post-collision momentum of the exact-difference form. */
 /* Boundaries of the x faces.  PERIODIC: the grid wraps.  PRESSURE: the paper's
  * pressure inlet and outlet (Sec. III.B-D; it gives no equations): beyond
  * x = 0 and x = nx - 1 lie reservoirs of prescribed densities rho_in and
@@ -125,7 +127,6 @@ typedef struct lbm_params {
   double delta_tie;       /* tie-break: |l2| - |l1| <= delta_tie |l3| uses the gradient */
   int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
   int32_t track_flux;     /* 1: accumulate the outlet flux every step */
-  int32_t resistance;     /* LBM_RES_SEMI_IMPLICIT (default) | LBM_RES_IMPLICIT */
   int32_t bc_x;           /* LBM_BC_PERIODIC (default) | LBM_BC_PRESSURE */
   double rho_in[2];       /* LBM_BC_PRESSURE: reservoir densities (water, oil) beyond x = 0 */
   double rho_out[2];      /* LBM_BC_PRESSURE: reservoir densities beyond x = nx - 1 */
@@ -157,7 +158,7 @@ typedef struct lbm_pore_table {
  * N doubles; on_device = 1: device arrays of N values of the arithmetic type
  * (double for LBM_PREC_F64, float otherwise).  Values are at the current
  * time level: densities, the velocity u = (m + sum_a F^a / 2) / rho with the
- * total force (for the semi-implicit resistance, u = (rho I + R/2)^-1 (m + F_ex/2)),
+ * total force (u = (rho I + R/2)^-1 (m + F_ex/2) in gray voxels),
  * residual-inclusive saturation S and residual amounts; zero in solid voxels. */
 typedef struct lbm_fields {
   int32_t on_device;

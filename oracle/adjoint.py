@@ -1,7 +1,7 @@
 """Reference gradients of the outlet-flux history with respect to the gray
 porosity, for the one-component model (pore, gray and solid voxels, scalar
 K0(phi) or the tensorial resistivity of Eqs. (6)-(7), regularised or BGK
-collision, semi-implicit or implicit resistance, body force).  TEST
+collision, trapezoidal resistance, body force).  TEST
 INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline).
 
 The step is the one of model.Oracle with one component, and the tensor set-up
@@ -60,6 +60,19 @@ def _force_term(u, F):
         cu = C[i, 0] * u[0] + C[i, 1] * u[1] + C[i, 2] * u[2]
         out.append(W[i] * (cF / CS2 + (2.0 * cu * cF - 2.0 * CS2 * uF) / (2 * CS2 * CS2)))
     return torch.stack(out)
+
+
+def _collide(f, rho, up, ua, F, tau, collision, gray):
+    """Post-collision set of one component: pore voxels take the equilibrium
+    at u' and Eq. (3) at ua as the exact-difference increment; gray voxels take
+    Eq. (3) in its second-order form, equilibrium and non-equilibrium part at
+    ua and the force term weighted by 1 - 1/(2 tau)."""
+    def one(ue, kf):
+        feq = _equilibrium(rho, ue)
+        fneq = f - feq
+        f1 = _hermite(fneq) if collision == "regularized" else fneq
+        return feq + (1.0 - 1.0 / tau) * f1 + kf * _force_term(ua, F)
+    return torch.where(gray, one(ua, 1.0 - 0.5 / tau), one(up, 1.0))
 
 
 def _hermite(fneq):
@@ -162,7 +175,6 @@ class OneComponent:
         self.tables = tables
         self.tau = float(p.tau[0])
         self.g = [float(v) for v in p.g[0]]
-        self.h = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
         self.tensor = bool(getattr(p, "tensor", False))
         self.src_solid = [_sh(self.solid, C[i], -1) for i in range(Q)]
         fl = self.fluid.numpy()
@@ -201,25 +213,22 @@ class OneComponent:
         F_ex = [rho * self.g[d] for d in range(3)]
         nu = CS2 * (self.tau - 0.5)
         cR = torch.where(self.gray, rho * nu, torch.zeros_like(rho))
-        b = [mom[d] + self.h * F_ex[d] for d in range(3)]
+        b = [mom[d] + 0.5 * F_ex[d] for d in range(3)]
         if Kinv is None:
             Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
                              torch.zeros_like(rho))
-            Ru = [Rs * (b[d] / (safe + self.h * Rs)) for d in range(3)]
+            Ru = [Rs * (b[d] / (safe + 0.5 * Rs)) for d in range(3)]
         else:
             comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}
             R = [[cR * Kinv[comp[(min(a, c), max(a, c))]] for c in range(3)] for a in range(3)]
-            A = torch.stack([torch.stack([self.h * R[a][c] + (safe if a == c else 0.0)
+            A = torch.stack([torch.stack([0.5 * R[a][c] + (safe if a == c else 0.0)
                                           for c in range(3)], -1) for a in range(3)], -2)
             u = torch.linalg.solve(A, torch.stack(b, -1)[..., None])[..., 0]
             Ru = [sum(R[a][c] * u[..., c] for c in range(3)) for a in range(3)]
         F = [F_ex[d] - Ru[d] for d in range(3)]
         up = [torch.where(fl, mom[d] / safe, torch.zeros_like(rho)) for d in range(3)]
-        feq = _equilibrium(rho, up)
-        fneq = f - feq
-        f1 = _hermite(fneq) if p.collision == "regularized" else fneq
         ua = [up[d] + F[d] / (2.0 * safe) for d in range(3)]
-        post = feq + (1.0 - 1.0 / self.tau) * f1 + _force_term(ua, F)
+        post = _collide(f, rho, up, ua, F, self.tau, p.collision, self.gray)
         post = torch.where(fl, post, torch.zeros_like(post))
         Qn = (self.flux_w * post).sum()
         new = torch.stack([torch.where(self.src_solid[i], post[OPP[i]], _sh(post[i], C[i], -1))
@@ -408,15 +417,15 @@ class TwoComponent(OneComponent):
         co = torch.where(So > 0, rho_t * So * nu[1] / torch.clamp(Kro, min=p.kr_min),
                          torch.zeros_like(S))
         cR = torch.where(self.gray, cw + co, torch.zeros_like(S))
-        b = [mom[0][d] + mom[1][d] + self.h * (F_ex[0][d] + F_ex[1][d]) for d in range(3)]
+        b = [mom[0][d] + mom[1][d] + 0.5 * (F_ex[0][d] + F_ex[1][d]) for d in range(3)]
         if Kinv is None:
             Rs = torch.where(self.gray, cR / torch.where(self.gray, K0, torch.ones_like(K0)),
                              torch.zeros_like(S))
-            Ru = [Rs * (b[d] / (safe + self.h * Rs)) for d in range(3)]
+            Ru = [Rs * (b[d] / (safe + 0.5 * Rs)) for d in range(3)]
         else:
             comp = {(0, 0): 0, (1, 1): 1, (2, 2): 2, (0, 1): 3, (0, 2): 4, (1, 2): 5}
             R = [[cR * Kinv[comp[(min(a, c), max(a, c))]] for c in range(3)] for a in range(3)]
-            A = torch.stack([torch.stack([self.h * R[a][c] + (safe if a == c else 0.0)
+            A = torch.stack([torch.stack([0.5 * R[a][c] + (safe if a == c else 0.0)
                                           for c in range(3)], -1) for a in range(3)], -2)
             u = torch.linalg.solve(A, torch.stack(b, -1)[..., None])[..., 0]
             Ru = [sum(R[a][c] * u[..., c] for c in range(3)) for a in range(3)]
@@ -427,12 +436,9 @@ class TwoComponent(OneComponent):
                           torch.zeros_like(den)) for d in range(3)]
         posts = []
         for a in range(2):
-            feq = _equilibrium(rho[a], up)
-            fneq = f[a] - feq
-            f1 = _hermite(fneq) if p.collision == "regularized" else fneq
             ra = torch.where(fl, 2.0 * rho[a], torch.ones_like(rho[a]))
             ua = [up[d] + F[a][d] / ra for d in range(3)]
-            post = feq + (1.0 - 1.0 / self.taus[a]) * f1 + _force_term(ua, F[a])
+            post = _collide(f[a], rho[a], up, ua, F[a], self.taus[a], p.collision, self.gray)
             posts.append(torch.where(fl, post, torch.zeros_like(post)))
         if side is not None:
             Sd = S.detach()

@@ -21,16 +21,21 @@ post-streaming population set at time n.  One step (Eq. (2)) is:
                  coefficient c_R = sum_b rho S^b nu^b / max(Kr^b, Kr_min) and
                  resistivity R = c_R K^-1 (scalar K0 or the tensor of
                  Eqs. (6)-(7));
-4. velocity      the resistance acts on u = (rho I + h R)^-1 (m + h sum_a F_ex^a),
-                 h = 1/2 (semi-implicit, the default) or h = 1 (implicit,
-                 backward Euler); F_res^a = -(rho^a/rho) R u,
-                 F^a = F_ex^a + F_res^a; the reported velocity is
-                 (m + sum_a F^a / 2) / rho (equal to u when h = 1/2);
-5. collision     equilibrium at the Shan-Chen common velocity
-                 u' = sum(m^a/tau^a) / sum(rho^a/tau^a); non-equilibrium part
-                 projected on Hermite orders 1-2 (regularised; BGK optional);
-                 force term of Eq. (3) as the exact-difference increment of
-                 each component (Eq. (3) at u' + F^a / (2 rho^a));
+4. velocity      the resistance acts on u = (rho I + R/2)^-1 (m + sum_a F_ex^a / 2)
+                 (the trapezoidal rule: its steady states are exactly Darcy's
+                 law, under body forces and under pressure gradients alike);
+                 F_res^a = -(rho^a/rho) R u, F^a = F_ex^a + F_res^a;
+                 u = (m + sum_a F^a / 2) / rho is also the reported velocity;
+5. collision     Shan-Chen common velocity u' = sum(m^a/tau^a) / sum(rho^a/tau^a)
+                 and ua = u' + F^a / (2 rho^a); non-equilibrium part projected
+                 on Hermite orders 1-2 (regularised; BGK optional).  Pore
+                 voxels: equilibrium at u', force term of Eq. (3) as the
+                 exact-difference increment (Eq. (3) at ua).  Gray voxels:
+                 Eq. (3) in its second-order (Guo) form, equilibrium and
+                 non-equilibrium part at ua and the force term weighted by
+                 1 - 1/(2 tau^a); the post-collision momentum is the same
+                 m^a + F^a-sum either way, but the stiff resistance force no
+                 longer enters the equilibrium's quadratic terms;
 6. residual      trap / release on a saturation crossing (gray voxels);
 7. outlet flux   per-link count through the plane x_f | x_f + 1;
 8. streaming     pull with halfway bounce-back at solid neighbours, periodic.
@@ -288,13 +293,13 @@ class Oracle:
             cR = np.where(self.gray, rho_t * nu, 0.0)
             out.update(S=np.where(fl, 1.0, 0.0), S_hat=np.where(fl, 1.0, 0.0), rhoT=rho_t)
         out["cR"] = cR
-        # velocity the resistance of Eq. (1) acts on: trapezoidal (h = 1/2)
-        # or backward Euler (h = 1) in the resistance
-        h = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
-        b = mom.sum(axis=0) + h * F_ex.sum(axis=0)
+        # velocity the resistance of Eq. (1) acts on, by the trapezoidal rule:
+        # (rho I + R / 2) u = m + sum_a F_ex^a / 2, R = c_R K^-1 (or c_R / K0),
+        # F_res = -R u; the steady states are exactly Darcy's law
+        b = mom.sum(axis=0) + 0.5 * F_ex.sum(axis=0)
         if self.Kinv is None:
             Rs = np.where(self.gray, cR / np.where(self.gray, self.K0, 1.0), 0.0)
-            u = b / (safe + h * Rs)
+            u = b / (safe + 0.5 * Rs)
             Ru = Rs * u
         else:
             K = self.Kinv
@@ -303,7 +308,7 @@ class Oracle:
             for (i, j), k in idx.items():
                 Rm[i, j] = cR * K[k]
                 Rm[j, i] = cR * K[k]
-            A = h * Rm
+            A = 0.5 * Rm
             for d in range(3):
                 A[d, d] += safe
             Am = np.moveaxis(A, (0, 1), (-2, -1))
@@ -313,8 +318,6 @@ class Oracle:
         F = np.empty_like(F_ex)
         for a in range(nc):
             F[a] = F_ex[a] - (rho[a] / safe) * Ru
-        if h != 0.5:
-            u = (mom.sum(axis=0) + 0.5 * F.sum(axis=0)) / safe
         u = np.where(fl, u, 0.0)
         den = sum(rho[a] / self.tau[a] for a in range(nc))
         up = sum(mom[a] / self.tau[a] for a in range(nc)) / np.where(fl, den, 1.0)
@@ -333,14 +336,24 @@ class Oracle:
         fl = self.fluid
         post = np.empty_like(self.f)
         for a in range(self.ncomp):
+            # the velocity of component a shifted by half its force
+            ua = up + F[a] / np.where(fl, 2.0 * rho[a], 1.0)
+            # pore voxels: Eq. (3) as the exact-difference-method increment
+            # f_eq(rho^a, u' + F^a/rho^a) - f_eq(rho^a, u'), i.e. Eq. (3) at
+            # u' + F^a / (2 rho^a), on the equilibrium at u'
             feq = self.equilibrium(rho[a], up)
             fneq = self.f[a] - feq
             f1 = self.hermite_project(fneq) if p.collision == "regularized" else fneq
-            # Eq. (3) is the exact-difference-method increment of component a:
-            # f_eq(rho^a, u' + F^a/rho^a) - f_eq(rho^a, u'), i.e. Eq. (3)
-            # evaluated at u' + F^a / (2 rho^a).
-            ua = up + F[a] / np.where(fl, 2.0 * rho[a], 1.0)
-            post[a] = feq + (1.0 - 1.0 / self.tau[a]) * f1 + self.force_term(ua, F[a])
+            edm = feq + (1.0 - 1.0 / self.tau[a]) * f1 + self.force_term(ua, F[a])
+            # gray voxels: Eq. (3) in the second-order (Guo) form, with the
+            # equilibrium, the non-equilibrium part and the force term all at
+            # ua and the force term weighted by 1 - 1/(2 tau^a)
+            geq = self.equilibrium(rho[a], ua)
+            gneq = self.f[a] - geq
+            g1 = self.hermite_project(gneq) if p.collision == "regularized" else gneq
+            guo = (geq + (1.0 - 1.0 / self.tau[a]) * g1
+                   + (1.0 - 0.5 / self.tau[a]) * self.force_term(ua, F[a]))
+            post[a] = np.where(self.gray[None], guo, edm)
             post[a] = np.where(fl, post[a], 0.0)
         if self.ncomp == 2:
             self._residual(post, ev)

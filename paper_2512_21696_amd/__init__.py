@@ -25,7 +25,6 @@ PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 STORE16 = ("f16", "bf16")
 COLL = {"regularized": 0, "bgk": 1}
 REGION = {"gray": 0, "all": 1}
-RESIST = {"semi_implicit": 0, "implicit": 1}
 BCX = {"periodic": 0, "pressure": 1}
 TABLE_N = 1025
 
@@ -46,7 +45,7 @@ class lbm_params(ctypes.Structure):
         ("smooth_radius", ctypes.c_int32), ("outlet_x", ctypes.c_int32),
         ("eps_g", ctypes.c_double), ("eps_H", ctypes.c_double), ("delta_tie", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("track_flux", ctypes.c_int32),
-        ("resistance", ctypes.c_int32), ("bc_x", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32),
         ("rho_in", ctypes.c_double * 2), ("rho_out", ctypes.c_double * 2),
         ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
@@ -180,7 +179,6 @@ def to_c_params(params) -> lbm_params:
     p.G = float(params.G)
     p.kappa = float(params.kappa)
     p.csf_region = REGION[params.csf_region]
-    p.resistance = RESIST[getattr(params, "resistance", "semi_implicit")]
     p.bc_x = BCX[getattr(params, "bc_x", "periodic")]
     for a in range(2):
         p.rho_in[a] = float(getattr(params, "rho_in", (1.0, 0.0))[a])

@@ -8,16 +8,19 @@
 //   moments   rho, m = sum c_i f_i, Pi = sum c_i c_i^T f_i (Phi below is
 //             linear in Pi, so its reverse needs rho and m only);
 //   Eq. (1)   R_s = rho nu / K0 on gray voxels (0 elsewhere),
-//             u = (m + h rho g) / (rho + h R_s), F = rho g - R_s u,
-//             h = 1/2 (semi-implicit) or 1 (implicit);
+//             u = (m + h rho g) / (rho + h R_s), F = rho g - R_s u, h = 1/2
+//             (the trapezoidal rule);
 //   collision post_i = w_i (A + B.c_i + c_i^T C c_i) with u' = m / rho,
-//             ua = u' + F / (2 rho), omega = 1 / tau and
-//               equilibrium  A = e rho (1 - u'.u' / 2cs2), B = e rho u' / cs2,
-//                            C = e rho u' u'^T / 2cs4,
-//               force (Eq. (3))  A = -ua.F / cs2, B = F / cs2,
-//                            C = (ua F^T + F ua^T) / 2cs4,
-//               regularised non-equilibrium  A = -(1 - omega) tr P / 2cs2,
-//                            C = (1 - omega) P / 2cs4, P = Pi - rho cs2 I - rho u' u'^T,
+//             ua = u' + F / (2 rho), omega = 1 / tau, the equilibrium
+//             velocity ve = u' and kf = 1 in pore voxels, ve = ua and
+//             kf = 1 - omega / 2 in gray voxels, and
+//               equilibrium  A = e rho (1 - ve.ve / 2cs2), B = e rho ve / cs2,
+//                            C = e rho ve ve^T / 2cs4,
+//               force (Eq. (3))  A = -kf ua.F / cs2, B = kf F / cs2,
+//                            C = kf (ua F^T + F ua^T) / 2cs4,
+//               regularised non-equilibrium  B = (1 - omega) j / cs2,
+//                            A = -(1 - omega) tr P / 2cs2, C = (1 - omega) P / 2cs4,
+//                            j = m - rho ve, P = Pi - rho cs2 I - rho ve ve^T,
 //             e = 1 (regularised) or omega (BGK, which also keeps (1 - omega) f_i);
 //   flux      Q(n) = sum over the outlet links of post_i(x_f) (c_x = +1) minus
 //             post_i(x_f + 1) (c_x = -1), both ends fluid.
@@ -108,7 +111,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   const double cs2 = CS2;
   constexpr double ics2 = 3.0, ics4 = 9.0;  // 1 / c_s^2, 1 / c_s^4
   const double om = mc.omega[0], keep = 1.0 - om, e = REG ? 1.0 : om;
-  const double h = mc.res_implicit ? 1.0 : 0.5;
+  const double h = 0.5;
   const double g0 = mc.g[0][0], g1 = mc.g[0][1], g2 = mc.g[0][2];
   const bool tens = TENS && gray;
   const double b0 = m0 + h * rho * g0, b1 = m1 + h * rho * g1, b2 = m2 + h * rho * g2;
@@ -154,54 +157,67 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   }
   const double ir = 1.0 / rho;
   const double p0 = m0 * ir, p1 = m1 * ir, p2 = m2 * ir;  // u'
-  const double usq = p0 * p0 + p1 * p1 + p2 * p2;
   const double a0 = p0 + 0.5 * F0 * ir, a1 = p1 + 0.5 * F1 * ir, a2 = p2 + 0.5 * F2 * ir;  // ua
+  // equilibrium velocity ve (u' in pore voxels, ua in gray ones) and the
+  // force term's weight kf (1, or 1 - omega/2 in gray voxels)
+  const double v0 = gray ? a0 : p0, v1 = gray ? a1 : p1, v2 = gray ? a2 : p2;
+  const double kf = gray ? 1.0 - 0.5 * om : 1.0;
+  const double vsq = v0 * v0 + v1 * v1 + v2 * v2;
 
   // reverse sweep of Phi
   double rb = 0, pb0 = 0, pb1 = 0, pb2 = 0, Fb0 = 0, Fb1 = 0, Fb2 = 0, ab0 = 0, ab1 = 0, ab2 = 0;
+  double vb0 = 0, vb1 = 0, vb2 = 0, mb0 = 0, mb1 = 0, mb2 = 0;
   // A terms
-  rb += e * (1.0 - usq * (0.5 * ics2)) * L0;
-  const double usqb = -e * rho * (0.5 * ics2) * L0;
-  const double uFb = -L0 * ics2;
+  rb += e * (1.0 - vsq * (0.5 * ics2)) * L0;
+  const double vsqb = -e * rho * (0.5 * ics2) * L0;
+  const double uFb = -kf * L0 * ics2;
   // B terms
-  rb += e * (p0 * L1x + p1 * L1y + p2 * L1z) * ics2;
-  pb0 += e * rho * L1x * ics2; pb1 += e * rho * L1y * ics2; pb2 += e * rho * L1z * ics2;
-  Fb0 += L1x * ics2; Fb1 += L1y * ics2; Fb2 += L1z * ics2;
+  rb += e * (v0 * L1x + v1 * L1y + v2 * L1z) * ics2;
+  vb0 += e * rho * L1x * ics2; vb1 += e * rho * L1y * ics2; vb2 += e * rho * L1z * ics2;
+  Fb0 += kf * L1x * ics2; Fb1 += kf * L1y * ics2; Fb2 += kf * L1z * ics2;
   // C terms (M = Lambda2, symmetric)
-  const double Mp0 = Mxx * p0 + Mxy * p1 + Mxz * p2;
-  const double Mp1 = Mxy * p0 + Myy * p1 + Myz * p2;
-  const double Mp2 = Mxz * p0 + Myz * p1 + Mzz * p2;
-  rb += e * (p0 * Mp0 + p1 * Mp1 + p2 * Mp2) * (0.5 * ics4);
-  pb0 += e * rho * Mp0 * ics4; pb1 += e * rho * Mp1 * ics4; pb2 += e * rho * Mp2 * ics4;
-  ab0 += (Mxx * F0 + Mxy * F1 + Mxz * F2) * ics4;
-  ab1 += (Mxy * F0 + Myy * F1 + Myz * F2) * ics4;
-  ab2 += (Mxz * F0 + Myz * F1 + Mzz * F2) * ics4;
-  Fb0 += (Mxx * a0 + Mxy * a1 + Mxz * a2) * ics4;
-  Fb1 += (Mxy * a0 + Myy * a1 + Myz * a2) * ics4;
-  Fb2 += (Mxz * a0 + Myz * a1 + Mzz * a2) * ics4;
-  // regularised non-equilibrium: dPhi/dP, which is also dPhi/dPi
+  const double Mv0 = Mxx * v0 + Mxy * v1 + Mxz * v2;
+  const double Mv1 = Mxy * v0 + Myy * v1 + Myz * v2;
+  const double Mv2 = Mxz * v0 + Myz * v1 + Mzz * v2;
+  rb += e * (v0 * Mv0 + v1 * Mv1 + v2 * Mv2) * (0.5 * ics4);
+  vb0 += e * rho * Mv0 * ics4; vb1 += e * rho * Mv1 * ics4; vb2 += e * rho * Mv2 * ics4;
+  ab0 += kf * (Mxx * F0 + Mxy * F1 + Mxz * F2) * ics4;
+  ab1 += kf * (Mxy * F0 + Myy * F1 + Myz * F2) * ics4;
+  ab2 += kf * (Mxz * F0 + Myz * F1 + Mzz * F2) * ics4;
+  Fb0 += kf * (Mxx * a0 + Mxy * a1 + Mxz * a2) * ics4;
+  Fb1 += kf * (Mxy * a0 + Myy * a1 + Myz * a2) * ics4;
+  Fb2 += kf * (Mxz * a0 + Myz * a1 + Mzz * a2) * ics4;
+  // regularised non-equilibrium: first order j = m - rho ve (identically 0
+  // at ve = u'), second order P = Pi - rho cs2 I - rho ve ve; dPhi/dP is also
+  // dPhi/dPi
   double Bxx = 0, Byy = 0, Bzz = 0, Bxy = 0, Bxz = 0, Byz = 0;
   if (REG) {
+    const double kj = keep * ics2;
+    mb0 += kj * L1x; mb1 += kj * L1y; mb2 += kj * L1z;
+    rb -= kj * (v0 * L1x + v1 * L1y + v2 * L1z);
+    vb0 -= kj * rho * L1x; vb1 -= kj * rho * L1y; vb2 -= kj * rho * L1z;
     const double c = keep * (0.5 * ics4), d = -keep * (0.5 * ics2) * L0;
     Bxx = c * Mxx + d; Byy = c * Myy + d; Bzz = c * Mzz + d;
     Bxy = c * Mxy; Bxz = c * Mxz; Byz = c * Myz;
-    const double Bp0 = Bxx * p0 + Bxy * p1 + Bxz * p2;
-    const double Bp1 = Bxy * p0 + Byy * p1 + Byz * p2;
-    const double Bp2 = Bxz * p0 + Byz * p1 + Bzz * p2;
-    rb += -cs2 * (Bxx + Byy + Bzz) - (p0 * Bp0 + p1 * Bp1 + p2 * Bp2);
-    pb0 -= 2 * rho * Bp0; pb1 -= 2 * rho * Bp1; pb2 -= 2 * rho * Bp2;
+    const double Bv0 = Bxx * v0 + Bxy * v1 + Bxz * v2;
+    const double Bv1 = Bxy * v0 + Byy * v1 + Byz * v2;
+    const double Bv2 = Bxz * v0 + Byz * v1 + Bzz * v2;
+    rb += -cs2 * (Bxx + Byy + Bzz) - (v0 * Bv0 + v1 * Bv1 + v2 * Bv2);
+    vb0 -= 2 * rho * Bv0; vb1 -= 2 * rho * Bv1; vb2 -= 2 * rho * Bv2;
   }
   // ua.F
   ab0 += F0 * uFb; ab1 += F1 * uFb; ab2 += F2 * uFb;
   Fb0 += a0 * uFb; Fb1 += a1 * uFb; Fb2 += a2 * uFb;
+  // ve.ve, then ve = ua (gray) or u' (pore)
+  vb0 += 2 * v0 * vsqb; vb1 += 2 * v1 * vsqb; vb2 += 2 * v2 * vsqb;
+  if (gray) { ab0 += vb0; ab1 += vb1; ab2 += vb2; }
+  else { pb0 += vb0; pb1 += vb1; pb2 += vb2; }
   // ua = u' + F / 2rho
   pb0 += ab0; pb1 += ab1; pb2 += ab2;
   Fb0 += 0.5 * ab0 * ir; Fb1 += 0.5 * ab1 * ir; Fb2 += 0.5 * ab2 * ir;
   rb -= 0.5 * (ab0 * F0 + ab1 * F1 + ab2 * F2) * ir * ir;
-  // u'.u'
-  pb0 += 2 * p0 * usqb; pb1 += 2 * p1 * usqb; pb2 += 2 * p2 * usqb;
   // u' = m / rho
-  double mb0 = pb0 * ir, mb1 = pb1 * ir, mb2 = pb2 * ir;
+  mb0 += pb0 * ir; mb1 += pb1 * ir; mb2 += pb2 * ir;
   rb -= (pb0 * p0 + pb1 * p1 + pb2 * p2) * ir;
   rb += g0 * Fb0 + g1 * Fb1 + g2 * Fb2;
   double Rsb = 0.0;
@@ -287,12 +303,14 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
 //   S = clamp(((rho^w + r^w) / (rho_t + r^w + r^o) - s_min) / span, 0, 1),
 //   P_c = s_J P_c(S), c_R = rho_t S nu^w / max(Kr^w(S), Kr_min)
 //                         + rho_t (1 - S) nu^o / max(Kr^o(S), Kr_min),
-//   u = (rho_t I + h c_R K^-1)^-1 (m^w + m^o + h (F_ex^w + F_ex^o)),
+//   u = (rho_t I + h c_R K^-1)^-1 (m^w + m^o + h (F_ex^w + F_ex^o)), h = 1/2,
 //   F^a = F_ex^a - (rho^a / rho_t) c_R K^-1 u,
 //   u' = (omega^w m^w + omega^o m^o) / (omega^w rho^w + omega^o rho^o),
 //   post^a = w_i (A^a + B^a.c_i + c_i^T C^a c_i) as for one component, with
-//   feq(rho^a, u'), the force term at u' + F^a / (2 rho^a) and, regularised,
-//   the first-order part j^a = m^a - rho^a u' of the non-equilibrium.
+//   ua^a = u' + F^a / (2 rho^a), the force term at ua^a, the equilibrium
+//   feq(rho^a, ve^a) with ve^a = u' (pore) or ua^a and the force term weighted
+//   by 1 - omega^a / 2 (gray), and, regularised, the first-order part
+//   j^a = m^a - rho^a ve^a of the non-equilibrium.
 // The reverse of the force's neighbour reads is split off: k_adj_step2 keeps
 // dL/d(acc^a) and dL/d(grad S_hat) of each voxel (stash[9][v]), k_adj_nl2
 // gathers them into the neighbours' dL/drho^a (rnl[v][2]), which the next
@@ -387,7 +405,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   // forward quantities
   const double rt = rho[0] + rho[1], irt = 1.0 / rt;
   const double irho[2] = {1.0 / rho[0], 1.0 / rho[1]};
-  const double h = mc.res_implicit ? 1.0 : 0.5;
+  const double h = 0.5;
   const double ispan = mc.inv_span;
   double Fex[2][3], acc[2][3];
 #pragma unroll
@@ -512,7 +530,6 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   const double D = om[0] * rho[0] + om[1] * rho[1], iD = 1.0 / D;
   double up[3];
   for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) * iD;
-  const double usq = up[0] * up[0] + up[1] * up[1] + up[2] * up[2];
 
   // residual transfer: which branch, the scale factors, and dL/ds^a =
   // sum_i lam_post_i post_i of the unscaled set; the adjoint of the unscaled
@@ -545,36 +562,42 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
     for (int a = 0; a < 2; ++a) {
       const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a], ra = rho[a];
-      double ua[3];
-      for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * 0.5 * irho[a];
-      double uF = 0, pl = 0, FL = 0;
+      double ua[3], ve[3];
+      for (int d = 0; d < 3; ++d) {
+        ua[d] = up[d] + F[a][d] * 0.5 * irho[a];
+        ve[d] = gray ? ua[d] : up[d];
+      }
+      const double kf = gray ? 1.0 - 0.5 * om[a] : 1.0;
+      double uF = 0, pl = 0, FL = 0, vsq = 0;
       for (int d = 0; d < 3; ++d) {
         uF += ua[d] * F[a][d];
-        pl += up[d] * L1[a][d];
+        pl += ve[d] * L1[a][d];
         FL += F[a][d] * L1[a][d];
+        vsq += ve[d] * ve[d];
       }
       const double *Mv = M2[a];
       const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
       double uMu = 0, aMF = 0;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
-          uMu += up[i] * Mm[i][j] * up[j];
+          uMu += ve[i] * Mm[i][j] * ve[j];
           aMF += ua[i] * Mm[i][j] * F[a][j];
         }
       // equilibrium and force parts of A L0 + B.L1 + C:M
-      double phi_a = e * ra * (1.0 - usq * (0.5 * ics2)) * L0[a] - uF * ics2 * L0[a] +
-                     e * ra * pl * ics2 + FL * ics2 + e * ra * uMu * (0.5 * ics4) + aMF * ics4;
+      double phi_a = e * ra * (1.0 - vsq * (0.5 * ics2)) * L0[a] - kf * uF * ics2 * L0[a] +
+                     e * ra * pl * ics2 + kf * FL * ics2 + e * ra * uMu * (0.5 * ics4) +
+                     kf * aMF * ics4;
       if (REG) {
         const double *P = Pi[a];
         const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
         double tr = 0, PM = 0, jl = 0;
         for (int i = 0; i < 3; ++i) {
           for (int j = 0; j < 3; ++j) {
-            const double pn = Pm[i][j] - (i == j ? ra * cs2 : 0.0) - ra * up[i] * up[j];
+            const double pn = Pm[i][j] - (i == j ? ra * cs2 : 0.0) - ra * ve[i] * ve[j];
             PM += pn * Mm[i][j];
             if (i == j) tr += pn;
           }
-          jl += (m[a][i] - ra * up[i]) * L1[a][i];
+          jl += (m[a][i] - ra * ve[i]) * L1[a][i];
         }
         phi_a += keep * (-tr * (0.5 * ics2) * L0[a] + jl * ics2 + PM * (0.5 * ics4));
       } else {
@@ -589,34 +612,40 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   }
 
-  // reverse sweep
+  // reverse sweep; per component the equilibrium velocity ve is u' (pore)
+  // or ua (gray), and kf the force term's weight (1 or 1 - omega/2)
   double rb[2] = {0, 0}, mb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Pb[2][6];
-  double upb[3] = {0, 0, 0}, usqb = 0, Fb[2][3];
+  double upb[3] = {0, 0, 0}, Fb[2][3];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a];
     const double ra = rho[a], ir2 = 0.5 * irho[a];
-    double ua[3];
-    for (int d = 0; d < 3; ++d) ua[d] = up[d] + F[a][d] * ir2;
+    const double kf = gray ? 1.0 - 0.5 * om[a] : 1.0;
+    double ua[3], ve[3];
+    for (int d = 0; d < 3; ++d) {
+      ua[d] = up[d] + F[a][d] * ir2;
+      ve[d] = gray ? ua[d] : up[d];
+    }
+    const double vsq = ve[0] * ve[0] + ve[1] * ve[1] + ve[2] * ve[2];
     const double *Mv = M2[a];
     const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
-    double Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0};
-    rb[a] += e * (1.0 - usq * (0.5 * ics2)) * L0[a];
-    usqb += -e * ra * (0.5 * ics2) * L0[a];
-    const double uFb = -L0[a] * ics2;
+    double Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0}, veb[3] = {0, 0, 0};
+    rb[a] += e * (1.0 - vsq * (0.5 * ics2)) * L0[a];
+    const double vsqb = -e * ra * (0.5 * ics2) * L0[a];
+    const double uFb = -kf * L0[a] * ics2;
     double pl = 0, pMp = 0;
-    for (int d = 0; d < 3; ++d) pl += up[d] * L1[a][d];
+    for (int d = 0; d < 3; ++d) pl += ve[d] * L1[a][d];
     rb[a] += e * pl * ics2;
     for (int d = 0; d < 3; ++d) {
-      upb[d] += e * ra * L1[a][d] * ics2;
-      Fbar[d] += L1[a][d] * ics2;
+      veb[d] += e * ra * L1[a][d] * ics2;
+      Fbar[d] += kf * L1[a][d] * ics2;
     }
     for (int i = 0; i < 3; ++i) {
-      const double Mu = Mm[i][0] * up[0] + Mm[i][1] * up[1] + Mm[i][2] * up[2];
-      pMp += up[i] * Mu;
-      upb[i] += e * ra * Mu * ics4;
-      uab[i] += (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) * ics4;
-      Fbar[i] += (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) * ics4;
+      const double Mu = Mm[i][0] * ve[0] + Mm[i][1] * ve[1] + Mm[i][2] * ve[2];
+      pMp += ve[i] * Mu;
+      veb[i] += e * ra * Mu * ics4;
+      uab[i] += kf * (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) * ics4;
+      Fbar[i] += kf * (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) * ics4;
     }
     rb[a] += e * pMp * (0.5 * ics4);
     for (int d = 0; d < 6; ++d) Pb[a][d] = 0;
@@ -629,23 +658,26 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       Pb[a][3] = B[0][1]; Pb[a][4] = B[0][2]; Pb[a][5] = B[1][2];
       double pBp = 0;
       for (int i = 0; i < 3; ++i) {
-        const double Bu = B[i][0] * up[0] + B[i][1] * up[1] + B[i][2] * up[2];
-        pBp += up[i] * Bu;
-        upb[i] += -2.0 * ra * Bu;
+        const double Bu = B[i][0] * ve[0] + B[i][1] * ve[1] + B[i][2] * ve[2];
+        pBp += ve[i] * Bu;
+        veb[i] += -2.0 * ra * Bu;
       }
       rb[a] += -cs2 * (B[0][0] + B[1][1] + B[2][2]) - pBp;
-      // first-order part j^a = m^a - rho^a u'
+      // first-order part j^a = m^a - rho^a ve
       double pj = 0;
       for (int d = 0; d < 3; ++d) {
         const double jb = keep * L1[a][d] * ics2;
         mb[a][d] += jb;
-        pj += up[d] * jb;
-        upb[d] += -ra * jb;
+        pj += ve[d] * jb;
+        veb[d] += -ra * jb;
       }
       rb[a] += -pj;
     }
     double abF = 0;
     for (int d = 0; d < 3; ++d) {
+      veb[d] += 2.0 * ve[d] * vsqb;
+      if (gray) uab[d] += veb[d];
+      else upb[d] += veb[d];
       uab[d] += F[a][d] * uFb;
       Fbar[d] += ua[d] * uFb;
       upb[d] += uab[d];
@@ -655,7 +687,6 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     rb[a] += -abF * ir2 * irho[a];
     for (int d = 0; d < 3; ++d) Fb[a][d] = Fbar[d];
   }
-  for (int d = 0; d < 3; ++d) upb[d] += 2.0 * up[d] * usqb;
   {
     double pu = 0;
     for (int d = 0; d < 3; ++d) pu += upb[d] * up[d];
@@ -1474,6 +1505,8 @@ int tensor_gradient(lbm_handle *h, const double *gKi, double *gK0, double *gbase
   int rc = hip_check(h, hipMemcpyAsync(wts, w.data(), w.size() * sizeof(double),
                                        hipMemcpyHostToDevice, h->st),
                      "copy smoothing weights");
+  // w is host staging for that copy and ends with this function
+  if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "copy smoothing weights");
   if (rc != LBM_OK) return rc;
   const dim3 gr(blocks(N)), bl(256);
   double *sm2 = gbase;

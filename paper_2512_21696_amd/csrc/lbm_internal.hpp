@@ -22,7 +22,6 @@ struct ModelConsts {
   int nx, ny, nz;
   long long N;
   int ncomp, collision, csf_all, tensor;
-  int res_implicit;  // 1: backward-Euler resistance, 0: semi-implicit
   int open_x;        // 1: reservoirs beyond the x faces (pressure boundaries)
   double rho_in[2], rho_out[2];
   double tau[2], omega[2], nu[2];

@@ -702,17 +702,15 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
     cR = rt * (T)mc.nu[0];
   }
 
-  // a5: velocity the resistance acts on, u = (rho I + h R)^-1 (m + h sum F_ex)
-  // with h = 1/2 (semi-implicit) or 1 (implicit); the reported velocity is
-  // (m + sum F / 2) / rho with the total force
-  const T h = mc.res_implicit ? (T)1 : (T)0.5;
+  // a5: velocity the resistance acts on, u = (rho I + R/2)^-1 (m + sum F_ex / 2)
+  // (trapezoidal rule), which is also the reported velocity (m + sum F / 2) / rho
+  const T h = (T)0.5;
   T b0 = 0, b1 = 0, b2 = 0, e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
     b0 += mom[a][0]; b1 += mom[a][1]; b2 += mom[a][2];
     e0 += Fex[a][0]; e1 += Fex[a][1]; e2 += Fex[a][2];
   }
-  const T m0 = b0, m1 = b1, m2 = b2;
   b0 = b0 + h * e0;
   b1 = b1 + h * e1;
   b2 = b2 + h * e2;
@@ -740,11 +738,6 @@ __device__ __forceinline__ void step_voxel(const ModelConsts &mc, const T *__res
     const T den = rt + h * Rs;
     u0 = b0 / den; u1 = b1 / den; u2 = b2 / den;
     Ru0 = Rs * u0; Ru1 = Rs * u1; Ru2 = Rs * u2;
-  }
-  if (mc.res_implicit) {  // report (m + sum F / 2) / rho
-    u0 = (m0 + (T)0.5 * (e0 - Ru0)) / rt;
-    u1 = (m1 + (T)0.5 * (e1 - Ru1)) / rt;
-    u2 = (m2 + (T)0.5 * (e2 - Ru2)) / rt;
   }
 
   if (MODE == MODE_FIELDS) {

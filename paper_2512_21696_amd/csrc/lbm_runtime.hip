@@ -210,7 +210,6 @@ ModelConsts make_consts(const lbm_params &p) {
   mc.collision = p.collision;
   mc.csf_all = p.csf_region == LBM_CSF_ALL;
   mc.tensor = p.tensor;
-  mc.res_implicit = p.resistance == LBM_RES_IMPLICIT;
   mc.open_x = p.bc_x == LBM_BC_PRESSURE;
   for (int a = 0; a < 2; ++a) {
     mc.rho_in[a] = p.rho_in[a];
@@ -302,6 +301,9 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
     pt0.assign(N, 0);
     pt_src = pt0.data();
   }
+  // smoothing weights: host staging for an asynchronous copy, alive until the
+  // stream synchronisation at the end of this function
+  std::vector<double> w;
   int rc = LBM_OK;
 #define CK(x, w) \
   if (rc == LBM_OK) rc = hip_check(h, (x), w)
@@ -323,7 +325,7 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
                        s.phiT);
     if (h->p.tensor) {
       const int R = h->p.smooth_radius;
-      std::vector<double> w(2 * R + 1);
+      w.assign(2 * R + 1, 0.0);
       double sum = 0.0;
       for (int j = -R; j <= R; ++j) {
         w[j + R] = std::exp(-(double)(j * j) / (2.0 * h->p.sigma_s * h->p.sigma_s));

@@ -56,7 +56,7 @@ __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 // them as scalar operands instead of converting inside the loop.
 template <typename T>
 struct KC {
-  int nx, ny, nz, csf_all, tensor, collision, res_implicit, open_x;
+  int nx, ny, nz, csf_all, tensor, collision, open_x;
   long long N;
   T g[2][3], omega[2], nu[2], wall_dpsi[2], rho_in[2], rho_out[2];
   T G, kappa, csf_fac, s_min, inv_span, kr_min, hyst, m_minor, eps_n2;
@@ -67,7 +67,6 @@ KC<T> make_kc(const ModelConsts &m) {
   KC<T> k{};
   k.nx = m.nx; k.ny = m.ny; k.nz = m.nz; k.N = m.N;
   k.csf_all = m.csf_all; k.tensor = m.tensor; k.collision = m.collision;
-  k.res_implicit = m.res_implicit;
   k.open_x = m.open_x;
   for (int a = 0; a < 2; ++a) {
     k.rho_in[a] = (T)m.rho_in[a];
@@ -839,9 +838,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       cR = rt * mc.nu[0];
     }
 
-    // a5: velocity the resistance acts on, u = (rho I + h R)^-1 (m + h sum F_ex)
-    // with h = 1/2 (semi-implicit) or 1 (implicit)
-    const T h = mc.res_implicit ? (T)1 : (T)0.5;
+    // a5: velocity the resistance acts on, u = (rho I + R/2)^-1 (m + sum F_ex / 2)
+    // (trapezoidal rule)
+    const T h = (T)0.5;
     T b0 = 0, b1 = 0, b2 = 0, e0 = 0, e1 = 0, e2 = 0;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
@@ -920,7 +919,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
 
-    // a6: collision + exact-difference force term (Eq. (3)) as quadratic forms
+    // a6: collision + force term (Eq. (3)) as quadratic forms.  Pore voxels:
+    // equilibrium at u' and Eq. (3) at ua = u' + F^a / (2 rho^a) (the exact
+    // difference).  Gray voxels: Eq. (3) in its second-order form, the
+    // equilibrium and the non-equilibrium part at ua and the force term
+    // weighted by 1 - omega/2, so that the resistance force (R >> rho) stays
+    // out of the equilibrium's quadratic terms.
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       const T ra = rho[a];
@@ -928,31 +932,36 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       const T Fa0 = Fex[a][0] - kr * Ru0, Fa1 = Fex[a][1] - kr * Ru1, Fa2 = Fex[a][2] - kr * Ru2;
       const T ih2 = (T)0.5 * rcp(ra);
       const T ua0 = up0 + Fa0 * ih2, ua1 = up1 + Fa1 * ih2, ua2 = up2 + Fa2 * ih2;
-      const T uF = ua0 * Fa0 + ua1 * Fa1 + ua2 * Fa2;
       const T om = mc.omega[a];
       const T keep = (T)1 - om;
+      // equilibrium velocity ve and force weight kf
+      const T ve0 = gray ? ua0 : up0, ve1 = gray ? ua1 : up1, ve2 = gray ? ua2 : up2;
+      const T kf = gray ? (T)1 - (T)0.5 * om : (T)1;
+      const T vsq = gray ? ua0 * ua0 + ua1 * ua1 + ua2 * ua2 : usq;
+      const T kF0 = kf * Fa0, kF1 = kf * Fa1, kF2 = kf * Fa2;
+      const T uF = ua0 * kF0 + ua1 * kF1 + ua2 * kF2;
       const T we = REG ? (T)1 : om;  // weight of the equilibrium part
       const T wr = we * ra;
-      T A = wr * ((T)1 - (T)1.5 * usq) - (T)3 * uF;
-      T B0 = (T)3 * (wr * up0 + Fa0);
-      T B1 = (T)3 * (wr * up1 + Fa1);
-      T B2 = (T)3 * (wr * up2 + Fa2);
+      T A = wr * ((T)1 - (T)1.5 * vsq) - (T)3 * uF;
+      T B0 = (T)3 * (wr * ve0 + kF0);
+      T B1 = (T)3 * (wr * ve1 + kF1);
+      T B2 = (T)3 * (wr * ve2 + kF2);
       const T er = (T)4.5 * wr;
-      T Cxx = er * up0 * up0 + (T)9 * ua0 * Fa0;
-      T Cyy = er * up1 * up1 + (T)9 * ua1 * Fa1;
-      T Czz = er * up2 * up2 + (T)9 * ua2 * Fa2;
-      T Cxy = er * up0 * up1 + (T)4.5 * (ua0 * Fa1 + ua1 * Fa0);
-      T Cxz = er * up0 * up2 + (T)4.5 * (ua0 * Fa2 + ua2 * Fa0);
-      T Cyz = er * up1 * up2 + (T)4.5 * (ua1 * Fa2 + ua2 * Fa1);
+      T Cxx = er * ve0 * ve0 + (T)9 * ua0 * kF0;
+      T Cyy = er * ve1 * ve1 + (T)9 * ua1 * kF1;
+      T Czz = er * ve2 * ve2 + (T)9 * ua2 * kF2;
+      T Cxy = er * ve0 * ve1 + (T)4.5 * (ua0 * kF1 + ua1 * kF0);
+      T Cxz = er * ve0 * ve2 + (T)4.5 * (ua0 * kF2 + ua2 * kF0);
+      T Cyz = er * ve1 * ve2 + (T)4.5 * (ua1 * kF2 + ua2 * kF1);
       if (REG) {
-        // projected non-equilibrium part: j - rho u', Pi - rho (cs2 I + u'u')
-        const T jn0 = mom[a][0] - ra * up0, jn1 = mom[a][1] - ra * up1, jn2 = mom[a][2] - ra * up2;
-        const T qxx = P[a][0] - ra * (cs2 + up0 * up0);
-        const T qyy = P[a][1] - ra * (cs2 + up1 * up1);
-        const T qzz = P[a][2] - ra * (cs2 + up2 * up2);
-        const T qxy = P[a][3] - ra * up0 * up1;
-        const T qxz = P[a][4] - ra * up0 * up2;
-        const T qyz = P[a][5] - ra * up1 * up2;
+        // projected non-equilibrium part: j - rho ve, Pi - rho (cs2 I + ve ve)
+        const T jn0 = mom[a][0] - ra * ve0, jn1 = mom[a][1] - ra * ve1, jn2 = mom[a][2] - ra * ve2;
+        const T qxx = P[a][0] - ra * (cs2 + ve0 * ve0);
+        const T qyy = P[a][1] - ra * (cs2 + ve1 * ve1);
+        const T qzz = P[a][2] - ra * (cs2 + ve2 * ve2);
+        const T qxy = P[a][3] - ra * ve0 * ve1;
+        const T qxz = P[a][4] - ra * ve0 * ve2;
+        const T qyz = P[a][5] - ra * ve1 * ve2;
         const T k3 = (T)3 * keep, k45 = (T)4.5 * keep;
         A -= (T)1.5 * keep * (qxx + qyy + qzz);
         B0 += k3 * jn0; B1 += k3 * jn1; B2 += k3 * jn2;

@@ -105,8 +105,6 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
       return fail(msg, len, LBM_E_INVAL, "tensor thresholds must be >= 0");
   }
   if (p->diag_every < 0) return fail(msg, len, LBM_E_INVAL, "diag_every must be >= 0");
-  if (p->resistance != LBM_RES_SEMI_IMPLICIT && p->resistance != LBM_RES_IMPLICIT)
-    return fail(msg, len, LBM_E_INVAL, "unknown resistance scheme");
   if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_PRESSURE)
     return fail(msg, len, LBM_E_INVAL, "unknown x boundary");
   if (p->bc_x == LBM_BC_PRESSURE) {

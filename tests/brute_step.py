@@ -148,18 +148,24 @@ class Brute:
                 else:
                     cR = rt * cs2 * (p.tau[0] - 0.5)
                 R = cR / self.K0[z][y][x]
-            hh = 1.0 if getattr(p, "resistance", "semi_implicit") == "implicit" else 0.5
-            u = [(sum(mom[a][v][d] for a in range(nc)) + hh * sum(Fex[a][d] for a in range(nc)))
-                 / (rt + hh * R) for d in range(3)]
+            # trapezoidal rule in the resistance
+            u = [(sum(mom[a][v][d] for a in range(nc)) + 0.5 * sum(Fex[a][d] for a in range(nc)))
+                 / (rt + 0.5 * R) for d in range(3)]
             Ftot = [[Fex[a][d] - rho[a][v] / rt * R * u[d] for d in range(3)] for a in range(nc)]
             den = sum(rho[a][v] / p.tau[a] for a in range(nc))
             up = [sum(mom[a][v][d] / p.tau[a] for a in range(nc)) / den for d in range(3)]
             for a in range(nc):
                 ra = rho[a][v]
+                Fa = Ftot[a]
+                ua = [up[d] + Fa[d] / (2.0 * ra) for d in range(3)]
+                # equilibrium velocity: u' (exact-difference forcing) in pore
+                # voxels, ua with the force term's 1 - 1/(2 tau) weight in gray ones
+                ue = ua if gray else up
+                kf = 1.0 - 0.5 / p.tau[a] if gray else 1.0
                 feq = {}
                 for c in VELS:
-                    cu = sum(c[d] * up[d] for d in range(3))
-                    uu = sum(up[d] * up[d] for d in range(3))
+                    cu = sum(c[d] * ue[d] for d in range(3))
+                    uu = sum(ue[d] * ue[d] for d in range(3))
                     feq[c] = weight(c) * ra * (1 + 3 * cu + 4.5 * cu * cu - 1.5 * uu)
                 fneq = {c: pop[a][v][c] - feq[c] for c in VELS}
                 if p.collision == "regularized":
@@ -174,14 +180,12 @@ class Brute:
                         f1[c] = weight(c) * (3.0 * cj + 4.5 * (pcc - tr / 3.0))
                 else:
                     f1 = fneq
-                Fa = Ftot[a]
-                ua = [up[d] + Fa[d] / (2.0 * ra) for d in range(3)]
                 out = {}
                 for c in VELS:
                     cF = sum(c[d] * Fa[d] for d in range(3))
                     cu = sum(c[d] * ua[d] for d in range(3))
                     uF = sum(ua[d] * Fa[d] for d in range(3))
-                    force = weight(c) * (3.0 * cF + 9.0 * (cu * cF - uF / 3.0))
+                    force = kf * weight(c) * (3.0 * cF + 9.0 * (cu * cF - uF / 3.0))
                     out[c] = feq[c] + (1.0 - 1.0 / p.tau[a]) * f1[c] + force
                 post[a][v] = out
             # residual transfer

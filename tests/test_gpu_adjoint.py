@@ -16,7 +16,7 @@ from gpu_common import announce
 pytestmark = pytest.mark.gpu
 
 
-def small_case(collision="regularized", resistance="semi_implicit", precision="f64", seed=21):
+def small_case(collision="regularized", precision="f64", seed=21):
     """70 x 9 x 6 (several 64-wide rows with a ragged tail), random pore / solid /
     gray voxels, two pore types, a non-uniform start and a skewed body force."""
     rng = np.random.default_rng(seed)
@@ -29,7 +29,7 @@ def small_case(collision="regularized", resistance="semi_implicit", precision="f
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
             for lam in (1.0, 2.0)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, collision=collision,
-                 resistance=resistance, precision=precision, kappa=0.0,
+                 precision=precision, kappa=0.0,
                  g=((1e-4, 2e-5, -1e-5), (0.0, 0.0, 0.0)), outlet_x=33).filled()
     rho = 1.0 + 0.02 * rng.standard_normal(cls.shape)
     return dict(params=p, cls=cls, phi=phi, ptype=pt, tables=tabs, rho=rho)
@@ -56,12 +56,10 @@ def norm_err(a, b):
     return float(np.abs(a - b).max() / np.abs(b).max())
 
 
-@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
-                                                  ("bgk", "implicit"),
-                                                  ("regularized", "implicit")])
-def test_adjoint_matches_oracle_fp64(collision, resistance):
-    announce(f"adjoint 70x9x6 fp64 {collision} {resistance}, 12 steps, checkpoints every 5")
-    c = small_case(collision, resistance)
+@pytest.mark.parametrize("collision", ["regularized", "bgk"])
+def test_adjoint_matches_oracle_fp64(collision):
+    announce(f"adjoint 70x9x6 fp64 {collision}, 12 steps, checkpoints every 5")
+    c = small_case(collision)
     steps = 12
     a = np.linspace(1.0, -0.5, steps)
     qo, go = oracle_gradient(c, steps, a)
@@ -262,14 +260,13 @@ def test_fullsize_fp32_gradient_against_fp64():
     assert eg < 1e-2
 
 
-def fiber_case(n=14, ncyl=3, precision="f64", collision="regularized", resistance="semi_implicit"):
+def fiber_case(n=14, ncyl=3, precision="f64", collision="regularized"):
     """Gray fibre bundles, one component, tensorial resistivity (1, 0.1, 0.1),
     a few solid voxels added (seed 33), skewed body force."""
     wl = W.fiber_bundles(n=n, ncyl=ncyl, precision=precision)
     p = wl["params"]
     p.outlet_x = n // 2 - 1
     p.collision = collision
-    p.resistance = resistance
     p.g = ((1e-4, 3e-5, -2e-5), (0.0, 0.0, 0.0))
     rng = np.random.default_rng(33)
     cls = wl["cls"].copy()
@@ -279,11 +276,10 @@ def fiber_case(n=14, ncyl=3, precision="f64", collision="regularized", resistanc
                 rho=wl["rho_w"])
 
 
-@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
-                                                  ("bgk", "implicit")])
-def test_tensor_adjoint_matches_oracle_fp64(collision, resistance):
-    announce(f"tensor adjoint 14^3 fibres fp64 {collision} {resistance}, 10 steps")
-    c = fiber_case(collision=collision, resistance=resistance)
+@pytest.mark.parametrize("collision", ["regularized", "bgk"])
+def test_tensor_adjoint_matches_oracle_fp64(collision):
+    announce(f"tensor adjoint 14^3 fibres fp64 {collision}, 10 steps")
+    c = fiber_case(collision=collision)
     steps = 10
     a = np.linspace(1.0, 2.0, steps)
     qo, go = oracle_gradient(c, steps, a)
@@ -337,23 +333,22 @@ def test_tensor_gradient_against_gpu_finite_differences():
         assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
 
 
-def two_gpu_case(collision="regularized", resistance="implicit", tensor=False):
+def two_gpu_case(collision="regularized", tensor=False):
     from test_oracle_adjoint import two_case
-    p, cls, phi, pt, tabs, rw, ro = two_case(collision, resistance)
+    p, cls, phi, pt, tabs, rw, ro = two_case(collision)
     p.tensor = tensor
     return p, cls, phi, pt, tabs, rw, ro
 
 
-@pytest.mark.parametrize("collision,resistance,tensor", [("regularized", "implicit", False),
-                                                         ("bgk", "semi_implicit", False),
-                                                         ("regularized", "implicit", True)])
-def test_two_component_adjoint_matches_oracle(collision, resistance, tensor):
+@pytest.mark.parametrize("collision,tensor", [("regularized", False), ("bgk", False),
+                                              ("regularized", True)])
+def test_two_component_adjoint_matches_oracle(collision, tensor):
     """20 x 8 x 6, water and oil, pore / solid / gray voxels with two pore
     types, kappa = 0, 10 steps without residual events: dL/dphi through K0 (or
     K^-1) in the resistance and s_J in the capillary term, fp64."""
     import paper_2512_21696_amd as L
-    announce(f"two-component adjoint 20x8x6 fp64 {collision} {resistance} tensor={tensor}")
-    p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision, resistance, tensor)
+    announce(f"two-component adjoint 20x8x6 fp64 {collision} tensor={tensor}")
+    p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision, tensor)
     steps = 10
     a = np.linspace(1.0, 2.0, steps)
     o = Oracle(p)
@@ -389,12 +384,10 @@ def test_adjoint_rejects_16bit_storage():
     lb.destroy()
 
 
-@pytest.mark.parametrize("collision,resistance,kappa,region",
-                         [("regularized", "implicit", 0.0, "gray"),
-                          ("bgk", "semi_implicit", 0.0, "gray"),
-                          ("regularized", "implicit", -0.05, "gray"),
-                          ("bgk", "implicit", 0.03, "all")])
-def test_two_component_adjoint_through_residual_events(collision, resistance, kappa, region):
+@pytest.mark.parametrize("collision,kappa,region",
+                         [("regularized", 0.0, "gray"), ("bgk", 0.0, "gray"),
+                          ("regularized", -0.05, "gray"), ("bgk", 0.03, "all")])
+def test_two_component_adjoint_through_residual_events(collision, kappa, region):
     """The 20 x 8 x 6 two-component case with half of the gray voxels' side
     flags turned and some residual amounts (loaded through a state blob), so
     that trap and release fire: the gradient through the branch each voxel
@@ -402,9 +395,9 @@ def test_two_component_adjoint_through_residual_events(collision, resistance, ka
     unchanged."""
     import paper_2512_21696_amd as L
     from test_oracle_adjoint import event_state
-    announce(f"two-component adjoint with residual events 20x8x6 fp64 {collision} {resistance} "
+    announce(f"two-component adjoint with residual events 20x8x6 fp64 {collision} "
              f"kappa={kappa} region={region}")
-    p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision, resistance)
+    p, cls, phi, pt, tabs, rw, ro = two_gpu_case(collision)
     p.kappa, p.csf_region = kappa, region
     side, r = event_state(p, cls, phi, pt, tabs, rw, ro)
     steps = 10

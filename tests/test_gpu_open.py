@@ -26,8 +26,7 @@ def displacement(precision="f64"):
     K0 = W.kozeny_carman_table(2.0)
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, precision=precision, tau=(1.0, 1.2),
-                 kappa=-0.05, bc_x="pressure", rho_in=(1.02, m), rho_out=(m, 0.99),
-                 resistance="implicit").filled()
+                 kappa=-0.05, bc_x="pressure", rho_in=(1.02, m), rho_out=(m, 0.99)).filled()
     x = np.arange(nx)[None, None, :]
     prof = 0.5 * (1 - np.tanh((x - 3.0) / 1.5)) * np.ones(cls.shape)
     rw = m + (1 - m) * prof

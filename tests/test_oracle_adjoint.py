@@ -10,7 +10,7 @@ from oracle import Oracle
 from oracle import adjoint as A
 
 
-def case(collision="regularized", resistance="semi_implicit", seed=5):
+def case(collision="regularized", seed=5):
     rng = np.random.default_rng(seed)
     nz, ny, nx = 5, 6, 8
     r = rng.random((nz, ny, nx))
@@ -19,7 +19,7 @@ def case(collision="regularized", resistance="semi_implicit", seed=5):
     K0 = W.kozeny_carman_table(2.0)
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, collision=collision,
-                 resistance=resistance, g=((1e-4, 2e-5, 0.0), (0.0, 0.0, 0.0))).filled()
+                 g=((1e-4, 2e-5, 0.0), (0.0, 0.0, 0.0))).filled()
     return p, cls, phi, np.zeros(cls.shape, np.uint8), tabs
 
 
@@ -35,10 +35,9 @@ def oracle_history(p, cls, phi, pt, tabs, steps):
     return f0, np.array(qs), o.f[0]
 
 
-@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
-                                                  ("bgk", "implicit")])
-def test_torch_forward_equals_oracle(collision, resistance):
-    p, cls, phi, pt, tabs = case(collision, resistance)
+@pytest.mark.parametrize("collision", ["regularized", "bgk"])
+def test_torch_forward_equals_oracle(collision):
+    p, cls, phi, pt, tabs = case(collision)
     f0, qs, fN = oracle_history(p, cls, phi, pt, tabs, 15)
     hist, _, f_t = A.flux_gradient(p, cls, phi, pt, tabs, f0, 15, np.ones(15))
     # Q is a signed sum of O(100) populations of size ~0.1: rounding order alone
@@ -47,10 +46,9 @@ def test_torch_forward_equals_oracle(collision, resistance):
     assert np.abs(f_t - fN).max() < 1e-14
 
 
-@pytest.mark.parametrize("collision,resistance", [("regularized", "semi_implicit"),
-                                                  ("bgk", "implicit")])
-def test_gradient_matches_oracle_finite_differences(collision, resistance):
-    p, cls, phi, pt, tabs = case(collision, resistance)
+@pytest.mark.parametrize("collision", ["regularized", "bgk"])
+def test_gradient_matches_oracle_finite_differences(collision):
+    p, cls, phi, pt, tabs = case(collision)
     steps = 12
     a = np.linspace(1.0, 2.0, steps)            # L = sum_n a_n Q(n)
     f0, _, _ = oracle_history(p, cls, phi, pt, tabs, 1)
@@ -157,7 +155,7 @@ def test_tensor_gradient_matches_oracle_finite_differences():
     assert checked == 3
 
 
-def two_case(collision="regularized", resistance="implicit", seed=7):
+def two_case(collision="regularized", seed=7):
     """20 x 8 x 6, two components (water in x < 10, oil beyond), random pore /
     solid / gray voxels with two pore types, kappa = 0, skewed body forces."""
     rng = np.random.default_rng(seed)
@@ -170,7 +168,7 @@ def two_case(collision="regularized", resistance="implicit", seed=7):
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
             for lam in (1.0, 2.0)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
-                 collision=collision, resistance=resistance,
+                 collision=collision,
                  g=((1e-4, 2e-5, 0.0), (0.0, 0.0, -1e-5)), outlet_x=9).filled()
     m = p.m_minor
     x = np.arange(nx)[None, None, :]

@@ -9,13 +9,12 @@ from oracle import Oracle, C, Q
 from brute_step import Brute, VELS
 
 
-def tiny_case(ncomp=2, collision="regularized", seed=11, n=(3, 4, 5), region="gray",
-              resistance="semi_implicit"):
+def tiny_case(ncomp=2, collision="regularized", seed=11, n=(3, 4, 5), region="gray"):
     nz, ny, nx = n
     rng = np.random.default_rng(seed)
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=ncomp, tau=(0.7, 1.3), G=3.0,
                  g=((2e-4, -1e-4, 5e-5), (0.0, 1e-4, 0.0)), kappa=-0.03, collision=collision,
-                 csf_region=region, resistance=resistance).filled()
+                 csf_region=region).filled()
     cls = rng.choice([0, 0, 1, 2, 2], size=n).astype(np.uint8)
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, size=n), 1.0)
     ptype = np.where(cls == 2, rng.integers(0, 2, size=n), 0).astype(np.uint8)
@@ -70,14 +69,13 @@ def compare(o, pops, r, side, tol):
         assert side[(x, y, z)] == bool(o.side[z, y, x])
 
 
-@pytest.mark.parametrize("ncomp,collision,region,resistance",
-                         [(2, "regularized", "gray", "semi_implicit"),
-                          (2, "bgk", "all", "semi_implicit"),
-                          (1, "regularized", "gray", "semi_implicit"),
-                          (2, "regularized", "gray", "implicit")])
-def test_oracle_matches_nested_loops(ncomp, collision, region, resistance):
-    p, cls, phi, ptype, tabs, rw, ro, rng = tiny_case(ncomp, collision, region=region,
-                                                      resistance=resistance)
+@pytest.mark.parametrize("ncomp,collision,region",
+                         [(2, "regularized", "gray"),
+                          (2, "bgk", "all"),
+                          (1, "regularized", "gray"),
+                          (1, "bgk", "gray")])
+def test_oracle_matches_nested_loops(ncomp, collision, region):
+    p, cls, phi, ptype, tabs, rw, ro, rng = tiny_case(ncomp, collision, region=region)
     o = Oracle(p)
     o.set_geometry(cls, phi, ptype, tabs)
     o.init_fluid(rw, ro)

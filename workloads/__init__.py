@@ -73,7 +73,6 @@ class Params:
     g: tuple = ((0.0, 0.0, 0.0), (0.0, 0.0, 0.0))  # body acceleration per component
     kappa: float = 0.0
     csf_region: str = "gray"        # "gray" | "all"
-    resistance: str = "semi_implicit"  # "semi_implicit" | "implicit" (Brinkman term in time)
     phi_max: float = 1.0
     phi_avg: float = 0.0            # filled from m when 0
     m_minor: float = 0.0            # filled from G when 0
@@ -216,8 +215,7 @@ def droplet_slab(seed: int = 1001, n: int = 32, radius: float = 8.0, slab: int =
 def multiscale_rock(n: int = 256, seed: int = 2001, precision: str = "f32",
                     sigma_scale: float = 0.5, kappa: float = None, buffer: int = 8,
                     gw: float = 1e-5, pc_e: float = 0.05, tau: tuple = (1.0, 1.5),
-                    edge: float = 1.5, phi_range: tuple = (0.05, 0.4),
-                    resistance: str = "implicit") -> dict:
+                    edge: float = 1.5, phi_range: tuple = (0.05, 0.4)) -> dict:
     """n^3 synthetic multiscale rock: Gaussian random field (correlation length
     6 voxels) thresholded at its quantiles into 35 % solid, 20 % gray (grain
     rims) and 45 % pore; gray phi ~ U[0.05, 0.4]; pore type ~ U{0..3} with
@@ -228,14 +226,10 @@ def multiscale_rock(n: int = 256, seed: int = 2001, precision: str = "f32",
     ratio, tau_w = 0.6 or tau_o = 3, drove densities negative within ~100
     steps next to gray and solid voxels); G = 3.  Surface-tension control in
     the gray voxels at sigma_scale (0.5 or 2) times the kappa = 0 surface
-    tension, unless kappa is given.  The Brinkman resistance is taken
-    implicitly (backward Euler): with the semi-implicit rule the momentum of
-    the strongly resisting gray voxels reverses every step, and this rock goes
-    non-finite within 250-650 steps at every kappa (fp32 and fp64 alike)."""
+    tension, unless kappa is given."""
     if kappa is None:
         kappa = KAPPA_SIGMA_SCALE[float(sigma_scale)]
     p = Params(nx=n, ny=n, nz=n, ncomp=2, precision=precision, tau=tuple(tau), G=3.0,
-               resistance=resistance,
                g=((gw, 0.0, 0.0), (0.0, 0.0, 0.0)), kappa=kappa).filled()
     f = gaussian_random_field((n, n, n), 6.0, seed)
     q35, q55 = np.quantile(f, [0.35, 0.55])
@@ -397,20 +391,20 @@ def _flux_misfit(seed: int, steps: int, window: int):
 
 def adjoint_rock(n: int = 96, seed: int = 5001, precision: str = "f32", steps: int = 800,
                  window: int = 200, tau: float = 1.0, g: float = 1e-5,
-                 collision: str = "regularized", resistance: str = "implicit") -> dict:
+                 collision: str = "regularized") -> dict:
     """The porosity-gradient workload: the multiscale-rock geometry generator
     (Gaussian random field, correlation length 6, quantiles 35 % solid, 20 %
     gray, 45 % pore; gray phi ~ U[0.05, 0.4], pore type ~ U{0..3}) on an n^3
     box, run with one component (the fluid the library's adjoint covers) from
-    rest at density 1, body acceleration g along +x, tau = 1, implicit
-    resistance, outlet at x = n / 2.  Loss: L = sum over steps n >= window of
+    rest at density 1, body acceleration g along +x, tau = 1, outlet at
+    x = n / 2.  Loss: L = sum over steps n >= window of
     (Q(n) - Q*(n))^2 with a fixed seeded target: `target(q_base)` returns
     Q*(n) = 1.1 mean(q_base over the window) (1 + 0.02 xi_n), xi ~ N(0, 1)
     (seed + 1), from a base run's history; `loss_grad(q, target)` returns
     (L, dL/dQ)."""
     base = multiscale_rock(n=n, seed=seed, precision=precision, buffer=0)
     p = Params(nx=n, ny=n, nz=n, ncomp=1, precision=precision, tau=(tau, tau), G=0.0,
-               collision=collision, resistance=resistance, g=((g, 0.0, 0.0), (0.0, 0.0, 0.0)),
+               collision=collision, g=((g, 0.0, 0.0), (0.0, 0.0, 0.0)),
                kappa=0.0, outlet_x=n // 2).filled()
     target, loss_grad = _flux_misfit(seed + 1, steps, window)
     return dict(name=f"adjoint_rock_{n}", params=p, cls=base["cls"], phi=base["phi"],
