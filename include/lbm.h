@@ -198,48 +198,67 @@ void lbm_params_default(lbm_params *p);
  * be NULL).  Returns LBM_OK or LBM_E_INVAL / LBM_E_UNSUPPORTED. */
 int lbm_validate_params(const lbm_params *p, char *msg, size_t msglen);
 
-/* Validates p, allocates the device state through the hook and returns a new
- * handle in *out (NULL on failure).  The library owns its device memory until
- * lbm_destroy.  Errors: LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE. */
+/* The run of the paper's workflow step iii (Sec. I: the multiscale two-component
+ * simulation with the library's constitutive inputs), with the model
+ * parameters of Sec. II (Eqs. (2)-(4) and the gray force of Eq. (1)).
+ * Validates p, allocates the device state through the hook and returns a new
+ * handle in *out (NULL on failure; LBM_E_NOMEM when the hook returns NULL).
+ * The library owns its device memory until lbm_destroy.
+ * Errors: LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE. */
 int lbm_create(const lbm_params *p, lbm_handle **out);
 
-/* Copies the geometry in (host arrays of N values owned by the caller):
+/* The segmented image of the workflow (Sec. I, Fig. 1: resolved pore, solid and
+ * under-resolved gray voxels with their porosity and pore type, and the
+ * per-type K0(phi), Pc(Sw), Kr(Sw) library of its step ii).
+ * Copies the geometry in (host arrays of N values owned by the caller):
  * cls (LBM_PORE/LBM_SOLID/LBM_GRAY), phi (in (0,1) on gray voxels, ignored
  * elsewhere), pore_type (< ntab on gray voxels) and ntab pore tables; then runs
  * the per-voxel setup on the device: K0(phi), the Leverett-J factor
- * s_J = sqrt((K0_ref/phi_ref) / (K0/phi)), the residual saturations theta_w,
- * theta_o and, with tensor = 1, the inverse permeability tensors.
+ * s_J = sqrt((K0_ref/phi_ref) / (K0/phi)) (Eq. (5)), the residual saturations
+ * theta_w, theta_o (Sec. II, Fig. 6) and, with tensor = 1, the inverse
+ * permeability tensors (Eqs. (6)-(7)).
  * Invalidates the fluid state (lbm_init_fluid is needed again).
  * Errors: LBM_E_INVAL (codes, ranges, table shape), LBM_E_DEVICE. */
 int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double *phi,
                      const uint8_t *pore_type, const lbm_pore_table *tabs, int32_t ntab);
 
-/* Sets every fluid voxel to the rest equilibrium of the given densities
+/* Initial state of Eq. (2) (the paper gives none): sets every fluid voxel to
+ * the rest equilibrium of the given densities
  * (host arrays of N doubles; rho_o ignored for ncomp = 1), clears the residual
  * store, sets the side flag of gray voxels to [S >= 1/2] and the step counter
  * and flux accumulators to zero.  Errors: LBM_E_STATE (no geometry),
  * LBM_E_INVAL (non-finite or non-positive density on a fluid voxel). */
 int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *rho_o);
 
-/* Advances n >= 0 time steps, asynchronously on the stream.  Every
+/* Advances n >= 0 time steps of Eq. (2) (collision and force term, Eq. (3),
+ * with the pseudo-potential force, the CSF control of Eq. (4) and the gray
+ * force of Eq. (1); streaming), asynchronously on the stream.  Every
  * params.diag_every steps it synchronises and returns LBM_E_NONFINITE if the
  * state holds NaN/Inf.  Errors: LBM_E_STATE (no fluid state), LBM_E_DEVICE. */
 int lbm_step(lbm_handle *h, int64_t n);
 
-/* Evaluates the fields at the current time level (see lbm_fields) and writes
- * them; synchronises the stream for host outputs. */
+/* The fields of the workflow's step iii (Sec. I) and of Eq. (1): component
+ * densities rho^a, velocity u, saturation Sw and the residual amounts.
+ * Evaluates them at the current time level (see lbm_fields) and writes
+ * them; synchronises the stream for host outputs.  Errors: LBM_E_STATE (no
+ * fluid state), LBM_E_DEVICE. */
 int lbm_get_fields(lbm_handle *h, const lbm_fields *out);
 
-/* Computes the global diagnostics of the current state; synchronises. */
+/* Global quantities of the paper's displacement runs (Sec. III: mass per
+ * component, the pore-volume saturation Sw and the outlet flux per component).
+ * Computes them for the current state; synchronises.  Errors: LBM_E_STATE,
+ * LBM_E_DEVICE. */
 int lbm_get_diagnostics(lbm_handle *h, lbm_diag *out);
 
-/* Per-voxel setup values (host arrays of N doubles, NULL skips): K0, s_J,
+/* The per-voxel set-up of lbm_set_geometry (Eqs. (5)-(7), Fig. 6).
+ * Per-voxel setup values (host arrays of N doubles, NULL skips): K0, s_J,
  * theta_w, theta_o, and the inverse permeability as 6 arrays of N in the
  * order xx, yy, zz, xy, xz, yz (K0inv6 may be NULL; zero outside gray). */
 int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
                   double *theta_o, double *K0inv6);
 
-/* Checkpoint.  The state blob holds a header, the post-streaming populations
+/* Checkpoint of the state of Eq. (2) (the paper describes none).  The state
+ * blob holds a header, the post-streaming populations
  * f[a][i][v] (storage type; for F16/BF16 the 16-bit offsets h, followed for
  * two components by the fp32 reference densities rho_ref[v][a]: the offset
  * pulled by voxel v in direction i decodes as w_i (rho_ref[s] + h) with s the

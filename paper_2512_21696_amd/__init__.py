@@ -405,12 +405,6 @@ def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
     return Lbm(params, use_torch_memory)
 
 
-def reservoir_pressure(rho, G):
-    """Bulk pressure of a reservoir (water, oil densities) in the
-    two-component pseudo-potential model: cs^2 (rho_w + rho_o) + cs^2 G rho_w rho_o."""
-    return (rho[0] + rho[1] + G * rho[0] * rho[1]) / 3.0
-
-
 def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
                      precision="f32", side_walls=False, mirror=False, max_steps=2000,
                      check_every=100, tol=1e-6, want_u=False, stream=None):

@@ -156,7 +156,7 @@ def test_autograd_function_matches_oracle():
     import torch
     from paper_2512_21696_amd.autograd import FluxHistory
     announce("FluxHistory autograd, 70x9x6 fp64, squared-misfit loss, 10 steps")
-    c = small_case("bgk", "implicit")
+    c = small_case("bgk")
     steps = 10
     run = dict(params=c["params"], cls=c["cls"], ptype=c["ptype"], tables=c["tables"],
                rho=c["rho"], steps=steps, checkpoint_every=3)
