@@ -365,6 +365,29 @@ typedef struct {
 int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
                          lbm_rev_result *out);
 
+/* Bytes of the no-allocation variant's device scratch (one region per GPU). */
+#define LBM_REV_SCRATCH_BYTES (64u << 20)
+
+/* lbm_rev_permeability without any device allocation, for callers that cannot
+ * allocate (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  Same arguments, model, results and errors, except:
+ *   - every device buffer of the call (packed populations, neighbour table,
+ *     slot maps, partial sums) is carved out of a file-scope device array of
+ *     LBM_REV_SCRATCH_BYTES bytes, one per GPU, held until the process ends;
+ *     its address is looked up once per device on the first call there;
+ *   - a batch needing more than that returns LBM_E_UNSUPPORTED before any
+ *     launch, with the size it needs in lbm_last_error(NULL) (about 240 bytes
+ *     per packed pore slot plus 4 per voxel of the boxes in fp32: roughly
+ *     200,000 pore voxels);
+ *   - step launches are not timed: step_ms is 0.
+ * The call writes every scratch byte it reads before reading it, so a call
+ * never depends on what an earlier one left.  All calls on one GPU share its
+ * scratch: calls that overlap on one GPU (other host threads, or streams whose
+ * work overlaps) race and must be serialised by the caller.  Host staging of
+ * the inputs and results is ordinary host memory. */
+int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_rev_domain *doms,
+                                int32_t ndom, lbm_rev_result *out);
+
 /* ---------------------------------------------------------------------------
  * Discrete adjoint of the outlet flux with respect to the gray porosity.
  *

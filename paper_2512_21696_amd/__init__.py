@@ -101,7 +101,7 @@ EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_g
            "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
            "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
-           "lbm_adjoint_flux", "lbm_last_error", "lbm_destroy"]
+           "lbm_rev_permeability_static", "lbm_adjoint_flux", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -140,6 +140,8 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_reservoirs": (ctypes.c_int, [vp, dp, dp]),
         "lbm_rev_permeability": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain), i32,
                                                 P(lbm_rev_result)]),
+        "lbm_rev_permeability_static": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain),
+                                                       i32, P(lbm_rev_result)]),
         "lbm_adjoint_flux": (ctypes.c_int, [vp, i64, dp, i64, dp, dp, dp]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_destroy": (None, [vp]),
@@ -407,11 +409,13 @@ def lbm_create(params, use_torch_memory: bool = True) -> Lbm:
 
 def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
                      precision="f32", side_walls=False, mirror=False, max_steps=2000,
-                     check_every=100, tol=1e-6, want_u=False, stream=None):
+                     check_every=100, tol=1e-6, want_u=False, stream=None, static=False):
     """Single-phase permeability K = phi <u> nu / g of every domain (a list of
     uint8 class arrays [z][y][x], 0 pore / 1 solid), all run together by
-    lbm_rev_permeability.  Returns one dict per domain (K, phi, u_mean, steps,
-    converged, and with want_u the final velocity field along the force)."""
+    lbm_rev_permeability (or, with static=True, by lbm_rev_permeability_static,
+    which allocates no device memory).  Returns one dict per domain (K, phi,
+    u_mean, steps, converged, and with want_u the final velocity field along
+    the force)."""
     if stream is None:
         try:
             import torch
@@ -434,7 +438,8 @@ def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
                        mirror=int(bool(mirror)), max_steps=int(max_steps),
                        check_every=int(check_every), tol=float(tol), stream=stream)
     res = (lbm_rev_result * len(arrs))()
-    rc = lib.lbm_rev_permeability(ctypes.byref(p), doms, len(arrs), res)
+    fn = lib.lbm_rev_permeability_static if static else lib.lbm_rev_permeability
+    rc = fn(ctypes.byref(p), doms, len(arrs), res)
     if rc != LBM_OK:
         raise LbmError(rc, lib.lbm_last_error(None).decode())
     out = []

@@ -24,6 +24,7 @@
 // fp32 arithmetic and the writers' density offsets in an fp32 array per
 // level; the step works on offsets throughout.
 #include <memory>
+#include <mutex>
 
 namespace lbm {
 namespace rev {
@@ -279,6 +280,24 @@ struct DevBuf {  // device allocations and events of one call, freed on every ex
   }
 };
 
+// Device memory of one call taken from a fixed region (the file-scope scratch
+// array of the no-allocation entry point): consecutive 256-byte aligned
+// pieces; `need` grows by every request, whether it fits or not, so that a
+// run can report the size it needs.
+struct Carve {
+  char *base;
+  size_t cap;
+  size_t need = 0;
+  template <typename U>
+  U *get(size_t n) {
+    const size_t bytes = (std::max<size_t>(n, 1) * sizeof(U) + 255) / 256 * 256;
+    const size_t at = need;
+    need += bytes;
+    if (need > cap) return nullptr;
+    return reinterpret_cast<U *>(base + at);
+  }
+};
+
 int fail(int code, const std::string &msg) {
   g_create_error = msg;
   return code;
@@ -289,8 +308,18 @@ int check(hipError_t e, const char *what) {
   return fail(LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+template <typename T, int SK, typename Mem, typename WriteU>
+int run_steps(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out,
+              const std::vector<Dom> &hd, const std::vector<int> &slot_of,
+              const std::vector<int> &vox_of, const std::vector<int> &blk_dom, int Vtot, int Ptot,
+              int nblk, bool want_u, const WriteU &write_u, Mem &mem);
+
+// scratch == nullptr: device memory from hipMalloc, freed on exit, step
+// launches timed with HIP events.  Otherwise every device buffer is carved
+// out of the scratch region (cap bytes) and nothing is allocated or timed.
 template <typename T, int SK>
-int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out) {
+int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out,
+        void *scratch = nullptr, size_t cap = 0) {
   const hipStream_t st = (hipStream_t)p->stream;
   const int ax = p->axis;
   // boxes as run, dense offsets, slots of the pore voxels, block table
@@ -372,26 +401,55 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     return LBM_OK;
   }
 
+  if (scratch) {
+    Carve mem{static_cast<char *>(scratch), cap};
+    return run_steps<T, SK>(p, doms, ndom, out, hd, slot_of, vox_of, blk_dom, Vtot, Ptot, nblk,
+                            want_u, write_u, mem);
+  }
   DevBuf mem;
-  Dom *ddom = mem.get<Dom>(ndom);
-  int *dblk = mem.get<int>(nblk);
-  int *dslot = mem.get<int>(Vtot);
-  int *dvox = mem.get<int>(Ptot);
-  int *dnbr = mem.get<int>((size_t)(Q - 1) * Ptot);
+  return run_steps<T, SK>(p, doms, ndom, out, hd, slot_of, vox_of, blk_dom, Vtot, Ptot, nblk,
+                          want_u, write_u, mem);
+}
+
+// The device part of run(): buffers from `mem` (DevBuf or Carve), set-up,
+// the step loop with its convergence checks, results.
+template <typename T, int SK, typename Mem, typename WriteU>
+int run_steps(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_result *out,
+              const std::vector<Dom> &hd, const std::vector<int> &slot_of,
+              const std::vector<int> &vox_of, const std::vector<int> &blk_dom, int Vtot, int Ptot,
+              int nblk, bool want_u, const WriteU &write_u, Mem &mem) {
+  const hipStream_t st = (hipStream_t)p->stream;
+  const int ax = p->axis;
+  const double nu = (p->tau - 0.5) / 3.0;
+  constexpr bool timed = std::is_same<Mem, DevBuf>::value;
+  Dom *ddom = mem.template get<Dom>(ndom);
+  int *dblk = mem.template get<int>(nblk);
+  int *dslot = mem.template get<int>(Vtot);
+  int *dvox = mem.template get<int>(Ptot);
+  int *dnbr = mem.template get<int>((size_t)(Q - 1) * Ptot);
   const size_t es = SK == SK_NATIVE ? sizeof(T) : 2;  // bytes per stored value
-  void *fa = mem.get<uint8_t>((size_t)Q * Ptot * es);
-  void *fb = mem.get<uint8_t>((size_t)Q * Ptot * es);
-  T *uf = want_u ? mem.get<T>(Ptot) : nullptr;
+  void *fa = mem.template get<uint8_t>((size_t)Q * Ptot * es);
+  void *fb = mem.template get<uint8_t>((size_t)Q * Ptot * es);
+  T *uf = want_u ? mem.template get<T>(Ptot) : nullptr;
   // 16-bit storage: the writers' density offsets, one array per level
-  T *ra = SK != SK_NATIVE ? mem.get<T>(Ptot) : nullptr;
-  T *rb = SK != SK_NATIVE ? mem.get<T>(Ptot) : nullptr;
-  double *partial = mem.get<double>(nblk);
-  double *usum = mem.get<double>(ndom);
+  T *ra = SK != SK_NATIVE ? mem.template get<T>(Ptot) : nullptr;
+  T *rb = SK != SK_NATIVE ? mem.template get<T>(Ptot) : nullptr;
+  double *partial = mem.template get<double>(nblk);
+  double *usum = mem.template get<double>(ndom);
   if (!ddom || !dblk || !dslot || !dvox || !dnbr || !fa || !fb || (want_u && !uf) || !partial ||
-      !usum || (SK != SK_NATIVE && (!ra || !rb)))
+      !usum || (SK != SK_NATIVE && (!ra || !rb))) {
+    if constexpr (!timed)
+      return fail(LBM_E_UNSUPPORTED, "the domains need " + std::to_string(mem.need) +
+                                         " bytes of device memory; the static scratch holds " +
+                                         std::to_string(mem.cap));
     return fail(LBM_E_NOMEM, "device allocation failed");
-  hipEvent_t ev0 = mem.event(), ev1 = mem.event();
-  if (!ev0 || !ev1) return fail(LBM_E_DEVICE, "hipEventCreate failed");
+  }
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  if constexpr (timed) {
+    ev0 = mem.event();
+    ev1 = mem.event();
+    if (!ev0 || !ev1) return fail(LBM_E_DEVICE, "hipEventCreate failed");
+  }
   double step_ms_total = 0.0;
   int rc = check(hipMemcpyAsync(ddom, hd.data(), ndom * sizeof(Dom), hipMemcpyHostToDevice, st),
                  "copy domains");
@@ -447,8 +505,10 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
     have_prev = true;
     if (all || done >= p->max_steps) break;
     const int64_t k = std::min<int64_t>(p->check_every, p->max_steps - done);
-    rc = check(hipEventRecord(ev0, st), "event");
-    if (rc != LBM_OK) return rc;
+    if (timed) {
+      rc = check(hipEventRecord(ev0, st), "event");
+      if (rc != LBM_OK) return rc;
+    }
     for (int64_t s = 0; s < k; ++s) {
       if (reg)
         hipLaunchKernelGGL((k_rev_step<T, true, SK>), dim3(nblk), dim3(256), 0, st, dnbr, fa, fb,
@@ -460,10 +520,12 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
       std::swap(ra, rb);
     }
     rc = check(hipGetLastError(), "step launch");
-    if (rc == LBM_OK) rc = check(hipEventRecord(ev1, st), "event");
-    if (rc == LBM_OK) rc = check(hipEventSynchronize(ev1), "step");
     float ms = 0.f;
-    if (rc == LBM_OK) rc = check(hipEventElapsedTime(&ms, ev0, ev1), "event time");
+    if (timed) {
+      if (rc == LBM_OK) rc = check(hipEventRecord(ev1, st), "event");
+      if (rc == LBM_OK) rc = check(hipEventSynchronize(ev1), "step");
+      if (rc == LBM_OK) rc = check(hipEventElapsedTime(&ms, ev0, ev1), "event time");
+    }
     if (rc != LBM_OK) return rc;
     step_ms_total += ms;
     done += k;
@@ -491,12 +553,36 @@ int run(const lbm_rev_params *p, const lbm_rev_domain *doms, int ndom, lbm_rev_r
   return LBM_OK;
 }
 
-}  // namespace rev
-}  // namespace lbm
+// The no-allocation entry point's device memory: one file-scope array per
+// GPU, held until the process ends.  Host code never passes the array's name
+// to a kernel or a copy (on the host it is only a stand-in for the symbol):
+// scratch_address() looks up its device address once per device, with that
+// device current, and every later use goes through that pointer.
+static __device__ __align__(256) unsigned char scratch[LBM_REV_SCRATCH_BYTES];
 
-extern "C" int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms,
-                                    int32_t ndom, lbm_rev_result *out) {
-  using lbm::rev::fail;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_address(void **out) {
+  int dev = 0;
+  int rc = check(hipGetDevice(&dev), "hipGetDevice");
+  if (rc != LBM_OK) return rc;
+  if (dev < 0 || dev >= kMaxDevices) return fail(LBM_E_UNSUPPORTED, "device index too large");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *ptr = nullptr;
+    rc = check(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (rc != LBM_OK) return rc;
+    if (!ptr) return fail(LBM_E_DEVICE, "hipGetSymbolAddress(scratch) gave no address");
+    g_scratch_ptr[dev] = ptr;
+  }
+  *out = g_scratch_ptr[dev];
+  return LBM_OK;
+}
+
+int check_args(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
+               lbm_rev_result *out) {
   if (!p || !doms || !out) return fail(LBM_E_INVAL, "NULL argument");
   if (ndom < 1) return fail(LBM_E_INVAL, "ndom must be at least 1");
   if (!(p->tau > 0.5)) return fail(LBM_E_INVAL, "tau must exceed 1/2");
@@ -518,10 +604,35 @@ extern "C" int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domai
     return fail(LBM_E_UNSUPPORTED, "unknown precision");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return fail(LBM_E_DEVICE, "no HIP device");
+  return LBM_OK;
+}
+
+int dispatch(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
+             lbm_rev_result *out, void *scr, size_t cap) {
   switch (p->precision) {
-    case LBM_PREC_F64: return lbm::rev::run<double, lbm::SK_NATIVE>(p, doms, ndom, out);
-    case LBM_PREC_F32: return lbm::rev::run<float, lbm::SK_NATIVE>(p, doms, ndom, out);
-    case LBM_PREC_F16: return lbm::rev::run<float, lbm::SK_F16>(p, doms, ndom, out);
-    default: return lbm::rev::run<float, lbm::SK_BF16>(p, doms, ndom, out);
+    case LBM_PREC_F64: return run<double, SK_NATIVE>(p, doms, ndom, out, scr, cap);
+    case LBM_PREC_F32: return run<float, SK_NATIVE>(p, doms, ndom, out, scr, cap);
+    case LBM_PREC_F16: return run<float, SK_F16>(p, doms, ndom, out, scr, cap);
+    default: return run<float, SK_BF16>(p, doms, ndom, out, scr, cap);
   }
+}
+
+}  // namespace rev
+}  // namespace lbm
+
+extern "C" int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_rev_domain *doms,
+                                           int32_t ndom, lbm_rev_result *out) {
+  int rc = lbm::rev::check_args(p, doms, ndom, out);
+  if (rc != LBM_OK) return rc;
+  void *scr = nullptr;
+  rc = lbm::rev::scratch_address(&scr);
+  if (rc != LBM_OK) return rc;
+  return lbm::rev::dispatch(p, doms, ndom, out, scr, (size_t)LBM_REV_SCRATCH_BYTES);
+}
+
+extern "C" int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms,
+                                    int32_t ndom, lbm_rev_result *out) {
+  const int rc = lbm::rev::check_args(p, doms, ndom, out);
+  if (rc != LBM_OK) return rc;
+  return lbm::rev::dispatch(p, doms, ndom, out, nullptr, 0);
 }
