@@ -56,12 +56,12 @@ def test_droplet_slab_fp64_200_steps():
 
 def test_rock_mini_fp64():
     wl = W.multiscale_rock(n=48, precision="f64")
-    _check64(wl, 60, "multiscale_rock 48^3")
+    _check64(wl, 100, "multiscale_rock 48^3")
 
 
 def test_fiber_mini_fp64():
-    wl = W.fiber_bundles(n=40, ncyl=4, precision="f64")
-    _check64(wl, 60, "fiber_bundles 40^3")
+    wl = W.fiber_bundles(n=48, ncyl=5, precision="f64")
+    _check64(wl, 100, "fiber_bundles 48^3")
 
 
 def test_ragged_grid_fp64_bgk():

@@ -69,14 +69,14 @@ def test_droplet_slab_16bit(prec):
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
 def test_rock_mini_16bit(prec):
     wl = W.multiscale_rock(n=48, precision="f64")
-    _compare(wl, 60, prec, ("rho_w", "rho_o", "ux", "uy", "uz", "S"), "multiscale_rock 48^3")
+    _compare(wl, 100, prec, ("rho_w", "rho_o", "ux", "uy", "uz", "S"), "multiscale_rock 48^3")
 
 
 @pytest.mark.parametrize("prec", ["f16", "bf16"])
 def test_fiber_mini_16bit(prec):
     # one component: the reference density is the constant 1
-    wl = W.fiber_bundles(n=40, ncyl=4, precision="f64")
-    _compare(wl, 60, prec, ("rho_w", "ux", "uy", "uz"), "fiber_bundles 40^3")
+    wl = W.fiber_bundles(n=48, ncyl=5, precision="f64")
+    _compare(wl, 100, prec, ("rho_w", "ux", "uy", "uz"), "fiber_bundles 48^3")
 
 
 def test_fp16_beats_bf16_and_fp32_beats_fp16():
