@@ -21,6 +21,7 @@ times the one-component tensorial-resistivity workload (192^3 fibre bundles).
 import argparse
 import hashlib
 import json
+import re
 import os
 import platform
 import sys
@@ -97,14 +98,16 @@ def record_traffic(prefix, workload):
     rocprofv3's run_counter_collection.csv."""
     import csv
 
-    def per_dispatch(tag, name):
+    def per_dispatch(tag, name, required=True):
         vals = {}
         with open(f"{prefix}_{tag}/run_counter_collection.csv") as fh:
             for row in csv.DictReader(fh):
-                if name in row["Kernel_Name"]:
+                if re.search(r"\b" + name + r"\b", row["Kernel_Name"].replace("<", " ")):
                     vals.setdefault(row["Dispatch_Id"], 0.0)
                     vals[row["Dispatch_Id"]] += float(row["Counter_Value"])
         if not vals:
+            if not required:
+                return None, 0
             raise SystemExit(f"no dispatch of {name} in {prefix}_{tag}")
         return sum(vals.values()) / len(vals), len(vals)
 
@@ -114,15 +117,21 @@ def record_traffic(prefix, workload):
     fs, fw = gib / (cf * 1024), gib / (cw * 1024)
     sf, n_disp = per_dispatch("fetch", "k_step_zm")
     sw, _ = per_dispatch("write", "k_step_zm")
-    df, _ = per_dispatch("fetch", "k_density")
-    dw, _ = per_dispatch("write", "k_density")
+    # the density work of a step: the fix-up after the step's own push, or
+    # (storage kinds without the push) the density pass
+    aux = "k_density_fix"
+    df, nd = per_dispatch("fetch", aux, required=False)
+    if not nd:
+        aux = "k_density"
+        df, _ = per_dispatch("fetch", aux)
+    dw, _ = per_dispatch("write", aux)
     rec = {"kernel": "k_step_zm", "kernel_hash": kernel_source_hash(),
            "dispatches": n_disp,
            "fetch_size_kib_per_dispatch": round(sf, 1), "write_size_kib_per_dispatch": round(sw, 1),
            "fetch_scale": round(fs, 4), "write_scale": round(fw, 4),
            "read_bytes_per_launch": int(sf * 1024 * fs), "write_bytes_per_launch": int(sw * 1024 * fw),
            "bytes_per_launch": int(sf * 1024 * fs + sw * 1024 * fw),
-           "aux_kernel": {"name": "k_density", "read_bytes": int(df * 1024 * fs),
+           "aux_kernel": {"name": aux, "read_bytes": int(df * 1024 * fs),
                           "write_bytes": int(dw * 1024 * fw)}}
     out = {"note": "HBM bytes per launch from rocprofv3 FETCH_SIZE and WRITE_SIZE, each scaled by "
                    "what the same counter reads for k_probe_copy_b32 (libhbmprobe.so: 1 GiB read "
@@ -136,6 +145,18 @@ def record_traffic(prefix, workload):
     with open(TRAFFIC_JSON, "w") as fh:
         json.dump(out, fh, indent=1)
     print(json.dumps({workload: rec}))
+
+
+def cpu_model():
+    """The host CPU's model name (from /proc/cpuinfo where there is one)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
 
 
 def cpu_baseline(n_crop=64, steps=40):
@@ -367,7 +388,12 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
             "tensor": kind == "fiber",
             "checkpoint_every": every, "fluid_voxels": n_fluid,
             "gray_voxels": int(np.sum(cls == 2)), "loss": loss,
+            # the adjoint's forward sweep takes every level's densities from the
+            # density pass; lbm_step (fp32, two components) from its own push:
+            # equal to rounding there, bitwise otherwise
             "flux_history_equal": bool(np.array_equal(out["Q"], q)),
+            "flux_history_max_rel_diff": float(np.abs(out["Q"] - q).max() /
+                                               max(np.abs(q).max(), 1e-300)),
             "forward_seconds": round(t_fwd, 4), "gradient_seconds": round(t_adj, 4),
             "gradient_over_forward": round(t_adj / t_fwd, 2),
             "all_levels_kept": all_levels,
@@ -618,6 +644,11 @@ def main():
                      "kernel": "k_step_zm (fused collide-stream)",
                      "bytes_per_fluid_update": round(b_alg, 2),
                      "kernel_ms": round(step_ms, 4),
+                     # the whole step (fused kernel, density work, flux and
+                     # diagnostics) against the same algorithmic bytes
+                     "step_achieved": round(b_alg * n_fluid / (ms_per_step * 1e-3) / 1e9, 1),
+                     "step_frac": round(b_alg * n_fluid / (ms_per_step * 1e-3) / 1e9 /
+                                        HBM_PEAK_GBS, 4),
                      "step_time_share": round(kt["step_ms"] / total_ms, 4),
                      "aux_ms_per_step": round(kt["aux_ms"] / args.steps, 4),
                      "other_ms_per_step": round(kt["other_ms"] / args.steps, 4)},
@@ -701,7 +732,8 @@ def main():
         out["adjoint_gradient_two_component"] = adjoint_gradient(kind="rock2")
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline()
-        out["cpu_baseline"]["host"] = platform.processor() or platform.machine()
+        out["cpu_baseline"]["host"] = cpu_model()
+        out["cpu_baseline"]["nproc"] = os.cpu_count()
     print(json.dumps(out), flush=True)
 
 

@@ -1592,6 +1592,9 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
                     "copy side flags");
     return e;
   };
+  // every level's densities come from the density pass, in the forward sweep
+  // as in its recomputations, so both give the same sets
+  h->rho2_valid = false;
   // forward sweep.  The last segment keeps its levels: each of its steps but
   // the last writes its new set straight into the ring (the handle's buffer
   // pointers are swapped for it and put back at the end), so that segment is
@@ -1608,7 +1611,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
     T *const spare = s.f[1 - h->cur];
     for (int64_t k = 0; k < m && rc == LBM_OK; ++k) {
       if (keep) s.f[1 - h->cur] = k < m - 1 ? ring + k * SN : spare;
-      rc = step_t<T>(h, 1);
+      rc = step_t<T>(h, 1, false);
       if (rc != LBM_OK) break;
       Timed tm(h, K_OTHER);
       if (nc == 2)

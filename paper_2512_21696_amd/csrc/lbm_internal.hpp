@@ -49,6 +49,9 @@ struct DevState {
                      // of the stored offsets (the reader's density)
   T *rho;            // densities at the current level [a][v] (field evaluation)
   T *rho2;           // the same, interleaved [v][a] (fused step)
+  T *rho2n;          // the next level's densities, summed by the fused step
+                     // from its own post-collision values (fp32 arithmetic,
+                     // two components, periodic x), [v][a]
   T *rhoS;           // 16-bit two-component runs: sum_i w_i rho_ref(s_i) over the
                      // sources s_i of each voxel's next pulls [v][a], written by
                      // the fused step for the density pass that follows it

@@ -52,6 +52,9 @@ struct lbm_handle {
   int ntab = 0;
   bool has_geom = false, has_fluid = false, rho_valid = false, rho2_valid = false;
   bool rhoS_valid = false;  // 16-bit runs: rhoS belongs to the stored set
+  // the fused step sums the next level's densities itself (fp32 arithmetic,
+  // two components, periodic x), so no density pass reads the new set
+  bool push = false;
   int64_t step = 0;
   DevState<double> sd{};
   DevState<float> sf{};
@@ -179,6 +182,11 @@ int alloc_state(lbm_handle *h) {
   }
   s.rho = alloc_into<T>(h, L, (size_t)2 * N, &ok);
   s.rho2 = alloc_into<T>(h, L, (size_t)2 * N, &ok);
+  // (16-bit storage keeps the density pass: there it reads only the offsets,
+  // and the push's registers cost the step more than the pass)
+  h->push = std::is_same<T, float>::value && h->sk == SK_NATIVE && nc == 2 &&
+            h->p.bc_x != LBM_BC_PRESSURE;
+  s.rho2n = h->push ? alloc_into<T>(h, L, (size_t)2 * N, &ok) : nullptr;
   s.nrm = (h->p.ncomp == 2 && h->p.kappa != 0.0) ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
   s.mask = alloc_into<uint32_t>(h, L, (size_t)N, &ok);
   s.ptype = alloc_into<uint8_t>(h, L, (size_t)N, &ok);
@@ -445,44 +453,88 @@ void ensure_normals(lbm_handle *h) {
   }
 }
 
+// z chunk of the fused step: ZC planes, halved while the grid has fewer than
+// 1024 tiles (4 blocks per CU), down to 4 planes
+int tiled_chunk(const lbm_handle *h) {
+  const long long tx = (h->p.nx + zm::TX - 1) / zm::TX;
+  const long long ty = (h->p.ny + zm::TY - 1) / zm::TY;
+  int zc = zm::ZC;
+  while (zc > 4 && tx * ty * ((h->p.nz + zc - 1) / zc) < 1024) zc /= 2;
+  return zc;
+}
+
 // The fused step from the stored copy into the other one, or (native storage)
-// from fin into fout when given.
-template <typename T, int NC, bool REG>
+// from fin into fout when given.  PUSH: the step also sums the next level's
+// densities into rho2n (the links it can reach); launch_density_fix adds the
+// rest.
+template <typename T, int NC, bool REG, bool PUSH = false>
 void launch_tiled(lbm_handle *h, const T *fin_ = nullptr, T *fout_ = nullptr) {
   DevState<T> &s = state<T>(h);
   const int tx = (h->p.nx + zm::TX - 1) / zm::TX;
   const int ty = (h->p.ny + zm::TY - 1) / zm::TY;
-  // z chunks of ZC planes, halved while the grid has fewer than 1024 tiles (4
-  // blocks per CU), down to 4 planes
-  int zc = zm::ZC;
-  while (zc > 4 && (long long)tx * ty * ((h->p.nz + zc - 1) / zc) < 1024) zc /= 2;
+  const int zc = tiled_chunk(h);
   const int tz = (h->p.nz + zc - 1) / zc;
   const int nt = tx * ty * tz;
   const int grid = (nt + 7) / 8 * 8;
+  constexpr bool P = PUSH && NC == 2 && std::is_same<T, float>::value;
   if (h->sk == SK_NATIVE) {
-    const T *fin = fin_ ? fin_ : s.f[h->cur];
-    T *fout = fout_ ? fout_ : s.f[1 - h->cur];
-    hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE>), dim3(grid), dim3(zm::NT), 0, h->st,
-                       make_kc<T>(h->mc), (const void *)fin, (void *)fout, s, tx, ty, zc, nt);
+    const void *fin = fin_ ? fin_ : s.f[h->cur];
+    void *fout = fout_ ? fout_ : s.f[1 - h->cur];
+    hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE, P>), dim3(grid), dim3(zm::NT), 0, h->st,
+                       make_kc<T>(h->mc), fin, fout, s, tx, ty, zc, nt);
   } else if constexpr (std::is_same<T, float>::value) {
     const void *fin = s.fc[h->cur];
     void *fout = s.fc[1 - h->cur];
     if (h->sk == SK_F16)
-      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16>), dim3(grid), dim3(zm::NT), 0, h->st,
-                         make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16, P>), dim3(grid), dim3(zm::NT), 0,
+                         h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
     else
-      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16>), dim3(grid), dim3(zm::NT), 0,
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16, P>), dim3(grid), dim3(zm::NT), 0,
                          h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
   }
 }
 
+// After a step with the push: the links it could not sum (k_density_fix),
+// from the set just written (the stored copy the step wrote into, which
+// becomes current when the step completes).
+template <typename T>
+void launch_density_fix(lbm_handle *h) {
+  if constexpr (std::is_same<T, float>::value) {
+    DevState<T> &s = state<T>(h);
+    Timed tm(h, K_AUX);
+    const int nx = h->p.nx, ny = h->p.ny, nz = h->p.nz;
+    const int zc = tiled_chunk(h);
+    const unsigned nb = blocks(h->N);
+    const void *fnew = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur]
+                                          : (const void *)s.fc[1 - h->cur];
+    if (h->sk == SK_NATIVE)
+      hipLaunchKernelGGL((k_density_fix<float, SK_NATIVE>), dim3(nb), dim3(256), 0, h->st, fnew,
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+    else if (h->sk == SK_F16)
+      hipLaunchKernelGGL((k_density_fix<float, SK_F16>), dim3(nb), dim3(256), 0, h->st, fnew,
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+    else
+      hipLaunchKernelGGL((k_density_fix<float, SK_BF16>), dim3(nb), dim3(256), 0, h->st, fnew,
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+  }
+}
+
 template <typename T, int MODE, typename O>
-void launch_step(lbm_handle *h, const FieldsOut &fo) {
+void launch_step(lbm_handle *h, const FieldsOut &fo, bool push = false) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
   if (MODE == MODE_STEP) {
-    Timed tm(h, K_STEP);
     const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
+    if (h->p.ncomp == 2 && push) {
+      {
+        Timed tm(h, K_STEP);
+        if (reg) launch_tiled<T, 2, true, true>(h);
+        else launch_tiled<T, 2, false, true>(h);
+      }
+      launch_density_fix<T>(h);
+      return;
+    }
+    Timed tm(h, K_STEP);
     if (h->p.ncomp == 2) {
       if (reg) launch_tiled<T, 2, true>(h);
       else launch_tiled<T, 2, false>(h);
@@ -534,14 +586,17 @@ int diag_t(lbm_handle *h, lbm_diag *out) {
   return LBM_OK;
 }
 
+// allow_push = false keeps the density pass on every step (the adjoint's
+// forward sweep, whose recomputations take the densities from it).
 template <typename T>
-int step_t(lbm_handle *h, int64_t n) {
+int step_t(lbm_handle *h, int64_t n, bool allow_push) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
+  const bool push = allow_push && h->push;
   for (int64_t k = 0; k < n; ++k) {
     ensure_density<T>(h);
-    launch_step<T, MODE_STEP, T>(h, FieldsOut{});
+    launch_step<T, MODE_STEP, T>(h, FieldsOut{}, push);
     h->cur = 1 - h->cur;
     if (h->mc.open_x) {
       Timed tm(h, K_OTHER);
@@ -553,11 +608,26 @@ int step_t(lbm_handle *h, int64_t n) {
                            s.mask);
     }
     // 16-bit runs: the new offsets are relative to the densities of the level
-    // just left, which the density pass wrote into rho2
-    if (h->sk != SK_NATIVE && h->p.ncomp == 2) std::swap(s.rhoE, s.rho2);
-    h->rhoS_valid = h->sk != SK_NATIVE && h->p.ncomp == 2;
+    // just left, which the density pass (or the previous push) wrote into rho2
+    if (push) {
+      // rho2n holds the new level's densities; the level just left becomes
+      // the references (16-bit) or the spare
+      if (h->sk != SK_NATIVE) {
+        T *const spare = s.rhoE;
+        s.rhoE = s.rho2;
+        s.rho2 = s.rho2n;
+        s.rho2n = spare;
+      } else {
+        std::swap(s.rho2, s.rho2n);
+      }
+      h->rhoS_valid = false;
+      h->rho2_valid = true;
+    } else {
+      if (h->sk != SK_NATIVE && h->p.ncomp == 2) std::swap(s.rhoE, s.rho2);
+      h->rhoS_valid = h->sk != SK_NATIVE && h->p.ncomp == 2;
+      h->rho2_valid = false;
+    }
     h->rho_valid = false;
-    h->rho2_valid = false;
     h->dec_valid = false;
     h->step += 1;
     if (h->p.track_flux) {
@@ -709,9 +779,11 @@ template <typename T>
 int get_state_t(lbm_handle *h, void *buf) {
   DevState<T> &s = state<T>(h);
   const long long N = h->N;
-  // 16-bit runs: the next density pass gathers the reference sums itself, as
-  // a run resumed from this blob will, so the two continue bitwise alike
+  // the next step takes its densities from a density pass (16-bit runs:
+  // gathering the reference sums itself), as a run resumed from this blob
+  // will, so the two continue bitwise alike
   h->rhoS_valid = false;
+  h->rho2_valid = false;
   // canonical (post-streaming) order; 16-bit offsets are already relative to
   // the reader, so their gather is a plain permutation
   const void *C = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur] : (const void *)s.fc[1 - h->cur];
@@ -931,7 +1003,7 @@ extern "C" int lbm_step(lbm_handle *h, int64_t n) {
   if (!h) return LBM_E_INVAL;
   if (n < 0) return set_err(h, LBM_E_INVAL, "n must be >= 0");
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
-  return h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n) : step_t<float>(h, n);
+  return h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n, true) : step_t<float>(h, n, true);
 }
 
 extern "C" int lbm_get_fields(lbm_handle *h, const lbm_fields *out) {

@@ -187,11 +187,11 @@ __device__ inline int rslot(int z) { return (z + 10) % 5; }
 // Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus
 // keep * sc * f_i for BGK) of one component; voff is the voxel's byte offset
 // within its plane, sbase the byte offset of the plane.
-template <typename T, bool REG>
+template <typename T, bool REG, bool OUTV = false>
 __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sbase,
                                           uint32_t Nbytes, T A, T B0, T B1, T B2, T Cxx, T Cyy,
                                           T Czz, T Cxy, T Cxz, T Cyz, T sc, const T *fpop,
-                                          T keep, bool zero) {
+                                          T keep, bool zero, T *outv = nullptr) {
   const T w0 = (T)(1.0 / 3.0) * sc, w1 = (T)(1.0 / 18.0) * sc, w2 = (T)(1.0 / 36.0) * sc;
   T v[Q];
   v[0] = w0 * A;
@@ -226,6 +226,7 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
     T val = v[i];
     if (!REG) val += keep * sc * fpop[i];
     bstore(out, voff, so, zero ? (T)0 : val);
+    if (OUTV) outv[i] = zero ? (T)0 : val;  // the value its readers will pull
     so += Nbytes;
     keep_scalar(so);
   }
@@ -234,12 +235,13 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
 // 16-bit variant: stores enc((A + B.c_i + c_i^T C c_i) sc - ref) where ref
 // is the writing voxel's density (plus keep * sc * g_i, g_i = f_i / w_i, for
 // BGK).
-template <int SK, bool REG>
+template <int SK, bool REG, bool OUTV = false>
 __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t sbase,
                                             uint32_t Nbytes, float A, float B0, float B1,
                                             float B2, float Cxx, float Cyy, float Czz, float Cxy,
                                             float Cxz, float Cyz, float sc, const float *gpop,
-                                            float keep, bool zero, float ref) {
+                                            float keep, bool zero, float ref,
+                                            float *outv = nullptr) {
   float v[Q];
   v[0] = A;
   const float ax = A + Cxx, ay = A + Cyy, az = A + Czz;
@@ -273,7 +275,10 @@ __device__ __forceinline__ void emit_post16(rsrc_t out, uint32_t voff, uint32_t 
     float val = v[i] * sc;
     if (!REG) val += keep * sc * gpop[i];
     val -= ref;
-    bstore16(out, voff, so, zero ? (uint16_t)0 : enc16<SK>(val));
+    const uint16_t code = zero ? (uint16_t)0 : enc16<SK>(val);
+    bstore16(out, voff, so, code);
+    // the population its readers decode, w_i (ref + h)
+    if (OUTV) outv[i] = zero ? 0.f : (float)wq(i) * (ref + dec16<SK>(code));
     so += Nbytes;
     keep_scalar(so);
   }
@@ -349,7 +354,7 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
   out[v] = vec2<T>{r[0], r[1]};
 }
 
-template <typename T, int NC, bool REG, int SK>
+template <typename T, int NC, bool REG, int SK, bool PUSH = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
                                                  void *__restrict__ fout, const DevState<T> s,
                                                  const int tiles_x, const int tiles_y,
@@ -360,7 +365,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   using T2 = vec2<T>;
   __shared__ T2 srho[STENCIL ? RS : 1][STENCIL ? NH : 1];  // rho_w, rho_o (+inf: solid)
   __shared__ T sshat[STENCIL ? RS : 1][STENCIL ? NH : 1];  // mobile saturation S_hat
-  __shared__ T2 snrm[3][STENCIL ? NM : 1];                  // (n^w_d, n^o_d) of one plane
+  // (n^w_d, n^o_d) of one plane; the push exchange of the next level's
+  // densities reuses the space between the normals' last read and their next
+  // write (a barrier on each side)
+  constexpr int NRM_BYTES = 3 * (STENCIL ? NM : 1) * (int)sizeof(T2);
+  // rows 0 .. TY-2 send up, rows 1 .. TY-1 send down: [TY-1][TX][c_z + 1][NC] each
+  constexpr int PUSH_ROW = TX * 3 * NC;
+  constexpr int PUSH_BYTES = PUSH ? 2 * (TY - 1) * PUSH_ROW * (int)sizeof(T) : 0;
+  static_assert(PUSH_BYTES <= NRM_BYTES || !STENCIL, "the push exchange fits the normals' space");
+  __shared__ __align__(16) unsigned char snrm_raw[NRM_BYTES > PUSH_BYTES ? NRM_BYTES : PUSH_BYTES];
+  T2(*snrm)[STENCIL ? NM : 1] = reinterpret_cast<T2(*)[STENCIL ? NM : 1]>(snrm_raw);
+  T *const spush_up = reinterpret_cast<T *>(snrm_raw);
+  T *const spush_dn = spush_up + (TY - 1) * PUSH_ROW;
   __shared__ int sxw[HX], syw[HY];
   __shared__ int sxg[HX];  // open x faces: 1 beyond x = 0, 2 beyond x = nx-1 (reservoir cells)
   // 16-bit storage, two components: reference densities (the writers'
@@ -631,6 +647,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   };
   auto all_solid = [](uint32_t mkz) { return __all(((mkz >> CLASS_SHIFT) & 3u) == SOLID_CODE); };
   if (inside && !all_solid(M[0])) issue(zs, M[0]);
+  // pushed densities of planes z - 1, z, z + 1 at this thread's column
+  T Pp[NC], Pc[NC], Pn[NC];
+#pragma unroll
+  for (int a = 0; a < NC; ++a) Pp[a] = Pc[a] = Pn[a] = (T)0;
+  uint32_t Mlast = 0u;
 
   for (int z = zs; z < ze; advance(++z)) {
     if (STENCIL) {
@@ -655,7 +676,92 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (REFS) fetch_ref(z + 2);
       }
     }
-    if (!inside) continue;
+    // The push of the next level's densities: every post-collision value goes
+    // to the voxel that will pull it (x + c_i), or stays here when x + c_i is
+    // solid (bounce-back).  Links within this tile and chunk that do not wrap
+    // around the grid are summed here: along x by lane shifts, across rows
+    // through LDS, across planes in registers (Pp, Pc, Pn hold the planes
+    // z - 1, z, z + 1 of this thread's column).  k_density_fix adds the
+    // links leaving the tile or chunk, or wrapping, after the step.
+    // gself, gzp, gzm: this component's values for planes z, z + 1, z - 1
+    // from this row (after the lane shifts); the values for the rows above
+    // and below go to LDS ([row][tx][c_z + 1][a]), which reuses the normals'
+    // space: the barrier below ends every read of the normals of this plane.
+    T gself[PUSH ? NC : 1], gzp[PUSH ? NC : 1], gzm[PUSH ? NC : 1];
+    T *const my_up = spush_up + (ty < TY - 1 ? ty : 0) * PUSH_ROW + tx * 3 * NC;
+    T *const my_dn = spush_dn + (ty >= 1 ? ty - 1 : 0) * PUSH_ROW + tx * 3 * NC;
+    auto push_zero = [&]() {
+#pragma unroll
+      for (int k = 0; k < 3 * NC; ++k) {
+        if (ty < TY - 1) my_up[k] = (T)0;
+        if (ty >= 1) my_dn[k] = (T)0;
+      }
+    };
+    if constexpr (PUSH) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a) gself[a] = gzp[a] = gzm[a] = (T)0;
+      if (csf) __syncthreads();
+    }
+    auto push_comp = [&](int a, const T *pvv, uint32_t mkp) {
+      const bool ox_p = tx + 1 < TX && x + 1 < nx, ox_m = tx >= 1;
+      const bool oy_p = ty + 1 < TY && y + 1 < ny, oy_m = ty >= 1;
+      const bool oz_p = z + 1 < ze, oz_m = z - 1 >= zs;
+      T own = pvv[0];
+      auto take = [&](int i, bool ok) -> T {
+        if ((mkp >> i) & 1u) {  // x + c_i solid: it comes back here
+          own += pvv[i];
+          return (T)0;
+        }
+        return ok ? pvv[i] : (T)0;
+      };
+      // lane tx takes the +x values of lane tx - 1 and the -x values of lane
+      // tx + 1 (lanes beyond the grid's last column left the voxel work, so
+      // their lane is never read)
+      const bool rl = tx >= 1, rr = tx + 1 < TX && x + 1 < nx;
+      auto from_left = [&](T val) -> T {
+        const T r = __shfl_up(val, 1);
+        return rl ? r : (T)0;
+      };
+      auto from_right = [&](T val) -> T {
+        const T r = __shfl_down(val, 1);
+        return rr ? r : (T)0;
+      };
+      // one class (c_y, c_z) at a time: its c_x = 0 value plus the +x value
+      // of the lane to the left and the -x value of the lane to the right
+      auto cls3 = [&](int i0_, int ip, int im, bool ok) -> T {
+        const T c0 = take(i0_, ok);
+        const T l = from_left(take(ip, ok && ox_p));
+        const T r = from_right(take(im, ok && ox_m));
+        return c0 + l + r;
+      };
+      const T gyp = cls3(3, 7, 10, oy_p);  // (., +1, 0)
+      const T gym = cls3(4, 9, 8, oy_m);   // (., -1, 0)
+      if (ty < TY - 1) {  // the top row's up values are zero: they leave the tile
+        my_up[0 * NC + a] = take(17, oy_p && oz_m);  // (0, +1, -1)
+        my_up[1 * NC + a] = gyp;
+        my_up[2 * NC + a] = take(15, oy_p && oz_p);  // (0, +1, +1)
+      } else {
+        (void)take(17, false);
+        (void)take(15, false);
+      }
+      if (ty >= 1) {  // the bottom row's down values likewise
+        my_dn[0 * NC + a] = take(16, oy_m && oz_m);  // (0, -1, -1)
+        my_dn[1 * NC + a] = gym;
+        my_dn[2 * NC + a] = take(18, oy_m && oz_p);  // (0, -1, +1)
+      } else {
+        (void)take(16, false);
+        (void)take(18, false);
+      }
+      gzp[a] = cls3(5, 11, 14, oz_p);  // (., 0, +1)
+      gzm[a] = cls3(6, 13, 12, oz_m);  // (., 0, -1)
+      const T gx = from_left(take(1, ox_p)) + from_right(take(2, ox_m));  // (., 0, 0)
+      gself[a] = own + gx;
+    };
+    do {
+    if (!inside) {
+      if constexpr (PUSH) push_zero();
+      break;
+    }
     const uint32_t zoff = (uint32_t)z * nxy;
     const uint32_t v = vxy + zoff;
     const uint32_t mk = M[0];
@@ -730,7 +836,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
     }
     if (!skip_next) issue(z + 1, M[1]);
-    if (skip) continue;
+    if (skip) {
+      if constexpr (PUSH) push_zero();
+      break;
+    }
     T rt = rho[0];
     if (NC == 2) rt = rho[0] + rho[1];
     const T irt = rcp(rt);
@@ -774,12 +883,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         if (cx(i)) { aw0 += (T)(wq(i) * cx(i)) * vw; ao0 += (T)(wq(i) * cx(i)) * vo; }
         if (cy(i)) { aw1 += (T)(wq(i) * cy(i)) * vw; ao1 += (T)(wq(i) * cy(i)) * vo; }
         if (cz(i)) { aw2 += (T)(wq(i) * cz(i)) * vw; ao2 += (T)(wq(i) * cz(i)) * vo; }
-        if (S16) {
+        if (S16 && !PUSH) {
           qw += (T)wq(i) * (sol ? eown.x : e.x);
           qo += (T)wq(i) * (sol ? eown.y : e.y);
         }
       }
-      if (S16) reinterpret_cast<T2 *>(s.rhoS)[v] = T2{qw, qo};
+      if (S16 && !PUSH) reinterpret_cast<T2 *>(s.rhoS)[v] = T2{qw, qo};
       {
         const T kw = -mc.G * rho[0], ko = -mc.G * rho[1];
         Fex[0][0] += kw * ao0; Fex[0][1] += kw * ao1; Fex[0][2] += kw * ao2;
@@ -969,18 +1078,137 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         Cxy += k45 * qxy; Cxz += k45 * qxz; Cyz += k45 * qyz;
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
+      T pv[PUSH ? Q : 1];  // the values written (the push's input)
       if constexpr (!S16) {
-        emit_post<T, REG>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy, Czz,
-                          Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid);
+        emit_post<T, REG, PUSH>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy,
+                                Czz, Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, pv);
       } else {
         // reference of every outgoing slot: this voxel's density of this
         // level (exactly the value the density pass wrote, which becomes the
         // readers' reference array)
         const float ref = NC == 2 ? reinterpret_cast<const float *>(&srho[rslot(z)][c])[a] : 1.f;
-        emit_post16<SK, REG>(rout[a], vxy * 2u, zoff * 2u, N32 * 2u, A, B0, B1, B2, Cxx, Cyy, Czz,
-                             Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, ref);
+        emit_post16<SK, REG, PUSH>(rout[a], vxy * 2u, zoff * 2u, N32 * 2u, A, B0, B1, B2, Cxx,
+                                   Cyy, Czz, Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, ref,
+                                   reinterpret_cast<float *>(pv));
+      }
+      if constexpr (PUSH) push_comp(a, pv, mk);
+    }
+    } while (0);
+
+    if constexpr (PUSH) {
+      __syncthreads();
+      // row y - 1's up values and row y + 1's down values
+      const T *below = spush_up + (ty >= 1 ? ty - 1 : 0) * PUSH_ROW + tx * 3 * NC;
+      const T *above = spush_dn + (ty + 1 < TY ? ty : 0) * PUSH_ROW + tx * 3 * NC;
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        T r[3];
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+          const T ru = ty >= 1 ? below[k * NC + a] : (T)0;
+          const T rd = ty + 1 < TY ? above[k * NC + a] : (T)0;
+          r[k] = ru + rd;
+        }
+        Pc[a] += gself[a] + r[1];
+        Pn[a] += gzp[a] + r[2];
+        Pp[a] += gzm[a] + r[0];
+      }
+      const uint32_t mkp = inside ? M[0] : 0u;
+      // plane z - 1 has all its in-tile contributions now
+      if (inside && z - 1 >= zs) {
+        const bool sol = ((Mlast >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+        reinterpret_cast<T2 *>(s.rho2n)[(size_t)vxy + (size_t)(z - 1) * nxy] =
+            sol ? T2{(T)INFINITY, (T)INFINITY} : T2{Pp[0], Pp[NC - 1]};
+      }
+#pragma unroll
+      for (int a = 0; a < NC; ++a) {
+        Pp[a] = Pc[a];
+        Pc[a] = Pn[a];
+        Pn[a] = (T)0;
+      }
+      Mlast = mkp;
+    }
+  }
+  if constexpr (PUSH) {
+    if (inside) {  // the chunk's last plane: the next chunk's first plane adds to it in k_density_fix
+      const bool sol = ((Mlast >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+      reinterpret_cast<T2 *>(s.rho2n)[(size_t)vxy + (size_t)(ze - 1) * nxy] =
+          sol ? T2{(T)INFINITY, (T)INFINITY} : T2{Pp[0], Pp[NC - 1]};
+    }
+  }
+}
+
+// The next level's densities, second part.  With the push, the fused step
+// summed every link whose two ends lie in one tile and one z chunk without
+// crossing the periodic wrap; this adds the values of the other links, read
+// back from the new set exactly as the next step will pull them (16-bit
+// storage: w_i (rho_ref(s) + h), rho_ref(s) the writer's density of the
+// level just left, `rref`), so that each density is the sum of the voxel's
+// next pulls.  Only voxels on a face of a tile or chunk have such links, and
+// a solid source means bounce-back, which the step summed at the voxel itself.
+template <typename T, int SK>
+__global__ __launch_bounds__(256) void k_density_fix(const void *__restrict__ fnew,
+                                                     T *__restrict__ rho2n,
+                                                     const T *__restrict__ rref,
+                                                     const uint32_t *__restrict__ mask, int nx,
+                                                     int ny, int nz, int zc, long long N) {
+  using namespace zm;
+  const uint32_t v = blockIdx.x * 256u + threadIdx.x;
+  if (v >= (uint32_t)N) return;
+  const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
+  const int z = (int)(v / nxy);
+  const uint32_t rem = v - (uint32_t)z * nxy;
+  const int y = (int)(rem / (uint32_t)nx);
+  const int x = (int)(rem - (uint32_t)y * (uint32_t)nx);
+  const int tx = x % TX, ty = y % TY, tz = z % zc;
+  const bool face = tx == 0 || tx == TX - 1 || x == nx - 1 || ty == 0 || ty == TY - 1 ||
+                    y == ny - 1 || tz == 0 || tz == zc - 1 || z == nz - 1;
+  if (!face) return;
+  // which links leave the step's reach follows from the position alone: a
+  // source beyond the grid (the wrap) or in another tile or chunk along some
+  // axis.  Their loads, the mask and the partial density are all issued
+  // before any of them is used (one memory round trip per wave).
+  auto cut = [](int src, int dst, int n, int t) { return src < 0 || src >= n || src / t != dst / t; };
+  const uint32_t mk = mask[v];
+  const vec2<T> part = reinterpret_cast<const vec2<T> *>(rho2n)[v];
+  T val[Q - 1][2];
+  uint32_t need = 0u;
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const int xs = x - cx(i), ys = y - cy(i), zs = z - cz(i);
+    const bool cross = (cx(i) != 0 && cut(xs, x, nx, TX)) || (cy(i) != 0 && cut(ys, y, ny, TY)) ||
+                       (cz(i) != 0 && cut(zs, z, nz, zc));
+    val[i - 1][0] = val[i - 1][1] = (T)0;
+    if (!cross) continue;
+    need |= 1u << i;
+    const uint32_t sv = (uint32_t)(xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs)) +
+                        (uint32_t)(ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys)) * (uint32_t)nx +
+                        (uint32_t)(zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs)) * nxy;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const size_t k = (size_t)(a * Q + i) * (size_t)N + sv;
+      if constexpr (SK == SK_NATIVE) {
+        val[i - 1][a] = reinterpret_cast<const T *>(fnew)[k];
+      } else {
+        const uint16_t code = reinterpret_cast<const uint16_t *>(fnew)[k];
+        val[i - 1][a] = (float)wq(i) * (rref[2 * (size_t)sv + a] + dec16<SK>(code));
       }
     }
+  }
+  if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  // a solid source means bounce-back, which the step summed at the voxel itself
+  T add[2] = {(T)0, (T)0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (!((need >> i) & 1u) || ((mk >> opp(i)) & 1u)) continue;
+    add[0] += val[i - 1][0];
+    add[1] += val[i - 1][1];
+  }
+  if (need) {
+    vec2<T> r = part;
+    r.x += add[0];
+    r.y += add[1];
+    reinterpret_cast<vec2<T> *>(rho2n)[v] = r;
   }
 }
 

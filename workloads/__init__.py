@@ -431,8 +431,10 @@ def adjoint_rock2(n: int = 96, seed: int = 5001, precision: str = "f32", steps: 
     (kappa of the 0.5x surface tension unless given), water buffer and body
     force as there, outlet at x = n / 2; loss L = sum over steps n >= window
     of (Q^w(n) - Q*(n))^2 with a seeded target (`target(q_base)`,
-    `loss_grad(q, target)`, as in `adjoint_rock`)."""
-    base = multiscale_rock(n=n, seed=seed, precision=precision, kappa=kappa)
+    `loss_grad(q, target)`, as in `adjoint_rock`).  The pore buffer is the 8
+    water planes alone (no margins), so that the water meets gray voxels and
+    residual transfers fire within the first few hundred steps."""
+    base = multiscale_rock(n=n, seed=seed, precision=precision, kappa=kappa, margin=0)
     p = base["params"]
     p.outlet_x = n // 2
     target, loss_grad = _flux_misfit(seed + 1, steps, window)
