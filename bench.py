@@ -147,6 +147,38 @@ def record_traffic(prefix, workload):
     print(json.dumps({workload: rec}))
 
 
+def pc_sweep(max_edge=40, count=6):
+    """The capillary-pressure half of the library: a five-level drainage sweep
+    (workloads.pc_sweep_setup) of the first `count` sphere packs of
+    workloads.rev_domains with edge <= max_edge, fp32, 14 oil planes before
+    each domain, a 2-plane membrane, side walls; each level until Sw changes
+    by at most 1e-3 over 500 steps (20000 steps at most).  Reports every
+    domain's Pc(Sw) points and the sweep's voxel updates per second (the
+    whole box of each domain, every step, set-up and checks included)."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2512_21696_amd as L
+    doms = [d["cls"] for d in W.rev_domains() if d["edge"] <= max_edge][:count]
+    su = W.pc_sweep_setup(precision="f32")
+    kw = dict(buffer_in=14, membrane=2, buffer_out=2, side_walls=True,
+              membrane_phi=su["membrane_phi"], check_every=500, max_steps=20000, tol=1e-3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = L.rev_pc_sweep(doms, su["model"], su["membrane_table"], su["rho_nw_in"], **kw)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    updates = 0
+    for c, r in zip(doms, out):
+        nz, ny, nx = c.shape
+        updates += sum(r["steps"]) * (nx + 18) * (ny + 2) * (nz + 2)
+    return {"domains": len(doms), "edges": [int(c.shape[0]) for c in doms], "storage": "f32",
+            "levels_rho_oil_in": list(su["rho_nw_in"]), "seconds": round(dt, 2),
+            "box_voxel_mlups": round(updates / dt / 1e6, 1),
+            "curves": [{"pc": [round(v, 5) for v in r["pc"]], "sw": [round(v, 4) for v in r["sw"]],
+                        "steps": r["steps"], "converged": r["converged"]} for r in out]}
+
+
 def cpu_model():
     """The host CPU's model name (from /proc/cpuinfo where there is one)."""
     try:
@@ -534,7 +566,7 @@ def main():
     if args.rev:
         import torch
         torch.cuda.set_device(0)
-        print(json.dumps({"rev_library": rev_library()}), flush=True)
+        print(json.dumps({"rev_library": rev_library(), "pc_sweep": pc_sweep()}), flush=True)
         return
     if args.adjoint:
         import torch
@@ -727,6 +759,7 @@ def main():
             "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
     if compare:
         out["rev_library"] = rev_library()
+        out["pc_sweep"] = pc_sweep()
         out["adjoint_gradient"] = adjoint_gradient()
         out["adjoint_gradient_tensor"] = adjoint_gradient(n=192, steps=1000, kind="fiber")
         out["adjoint_gradient_two_component"] = adjoint_gradient(kind="rock2")

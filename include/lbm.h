@@ -389,6 +389,72 @@ int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_rev_domain *d
                                 int32_t ndom, lbm_rev_result *out);
 
 /* ---------------------------------------------------------------------------
+ * Capillary-pressure sweep of many small domains (the Pc(Sw) half of the
+ * library runs of the paper's Appendix: Pc measured through a two-component
+ * displacement of a resolved sub-volume, with a reservoir region of 14 cells
+ * before it and the pressure difference between the two faces changed in
+ * steps, a steady state recorded at each level; Sec. II.A describes the same
+ * stepping for its fully resolved run).
+ *
+ * Reading (the paper gives no equations for it): a drainage sweep.  Each
+ * domain (lbm_rev_domain: 0 pore, 1 solid, [z][y][x]) is run along x with
+ * open faces (LBM_BC_PRESSURE) inside a box of
+ *   buffer_in pore planes | the domain | membrane gray planes | buffer_out
+ *   pore planes,
+ * with a solid frame on the four sides when side_walls = 1 (the walls of the
+ * Appendix's runs).  The sample starts filled with water (wetting with the
+ * default wall_dpsi), the inlet buffer with oil (tanh edge of width 1.5).
+ * The outlet reservoir holds water (rho_w, rho_o) = (1, m); the inlet
+ * reservoir holds oil (m, rho_nw_in[k]) at level k, so the capillary pressure
+ * of the level is Pc_k = p(m, rho_nw_in[k]) - p(1, m), with the bulk pressure
+ * p = cs^2 (rho_w + rho_o) + cs^2 G rho_w rho_o.  The membrane is a capillary
+ * barrier of gray voxels (porosity membrane_phi, one pore table given by the
+ * caller): oil enters it only above the table's entry pressure, water passes
+ * at its K0, so with an entry pressure above the last level the sample's
+ * saturation settles at every level instead of the oil breaking through.
+ * Levels run in order from one state.  A level ends when the water
+ * saturation Sw of the sample's pore voxels (mean of S over them) changes by
+ * at most tol over check_every steps, or after max_steps steps.
+ *
+ * Every model setting comes from `model` (tau, G, wall_dpsi, m_minor,
+ * s_min/s_max, collision, kappa with LBM_CSF_GRAY, precision F64 or F32,
+ * hooks, stream); the sweep sets the grid, ncomp = 2, bc_x, the reservoirs,
+ * zero body force and no flux tracking.  Domains run one after another on
+ * the model's stream, each with its own handle (device memory through the
+ * hooks, freed before the next).  Errors: LBM_E_INVAL (arguments, levels,
+ * buffer_out < 2, membrane < 1, buffer_in < 1), LBM_E_UNSUPPORTED (16-bit
+ * storage), and whatever lbm_create and the calls it makes return; the
+ * message is in lbm_last_error(NULL).  Results of the domains before a
+ * failing one are written. */
+#define LBM_PC_MAX_LEVELS 16
+typedef struct {
+  lbm_params model;        /* two-component model and run settings (see above) */
+  int32_t buffer_in;       /* oil planes before the domain (the paper's 14), >= 1 */
+  int32_t membrane;        /* gray planes after the domain, >= 1 */
+  int32_t buffer_out;      /* pore planes between the membrane and the outlet face, >= 2 */
+  int32_t side_walls;      /* 1: solid frame on the four sides, 0: periodic in y and z */
+  int32_t nlevels;         /* 1 .. LBM_PC_MAX_LEVELS */
+  int32_t pad_;
+  double rho_nw_in[LBM_PC_MAX_LEVELS]; /* inlet oil density per level (finite, > 0) */
+  double membrane_phi;     /* porosity of the membrane's gray voxels, in (0, 1) */
+  int64_t check_every;     /* steps between saturation checks, >= 1 */
+  int64_t max_steps;       /* steps per level at most, >= check_every */
+  double tol;              /* steady when |delta Sw| <= tol over check_every steps, >= 0 */
+} lbm_pc_params;
+
+typedef struct {
+  int32_t nlevels;
+  int32_t pad_;
+  double pc[LBM_PC_MAX_LEVELS];       /* capillary pressure of the level (reservoir pressures) */
+  double sw[LBM_PC_MAX_LEVELS];       /* Sw of the sample's pore voxels at the level's end */
+  int64_t steps[LBM_PC_MAX_LEVELS];   /* steps the level took */
+  int32_t converged[LBM_PC_MAX_LEVELS];
+} lbm_pc_result;
+
+int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_table,
+                     const lbm_rev_domain *doms, int32_t ndom, lbm_pc_result *out);
+
+/* ---------------------------------------------------------------------------
  * Discrete adjoint of the outlet flux with respect to the gray porosity.
  *
  * The gray-region resistance of Eq. (1) makes the flow depend on phi through

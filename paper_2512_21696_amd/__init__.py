@@ -59,6 +59,25 @@ class lbm_pore_table(ctypes.Structure):
                 ("kd", ctypes.c_double * 3)]
 
 
+PC_MAX_LEVELS = 16
+
+
+class lbm_pc_params(ctypes.Structure):
+    _fields_ = [("model", lbm_params), ("buffer_in", ctypes.c_int32),
+                ("membrane", ctypes.c_int32), ("buffer_out", ctypes.c_int32),
+                ("side_walls", ctypes.c_int32), ("nlevels", ctypes.c_int32),
+                ("pad_", ctypes.c_int32), ("rho_nw_in", ctypes.c_double * PC_MAX_LEVELS),
+                ("membrane_phi", ctypes.c_double), ("check_every", ctypes.c_int64),
+                ("max_steps", ctypes.c_int64), ("tol", ctypes.c_double)]
+
+
+class lbm_pc_result(ctypes.Structure):
+    _fields_ = [("nlevels", ctypes.c_int32), ("pad_", ctypes.c_int32),
+                ("pc", ctypes.c_double * PC_MAX_LEVELS), ("sw", ctypes.c_double * PC_MAX_LEVELS),
+                ("steps", ctypes.c_int64 * PC_MAX_LEVELS),
+                ("converged", ctypes.c_int32 * PC_MAX_LEVELS)]
+
+
 class lbm_fields(ctypes.Structure):
     _fields_ = [("on_device", ctypes.c_int32)] + [
         (k, ctypes.c_void_p) for k in ("rho_w", "rho_o", "ux", "uy", "uz", "S", "r_w", "r_o")]
@@ -101,7 +120,8 @@ EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_g
            "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
            "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
-           "lbm_rev_permeability_static", "lbm_adjoint_flux", "lbm_last_error", "lbm_destroy"]
+           "lbm_rev_permeability_static", "lbm_rev_pc_sweep", "lbm_adjoint_flux",
+           "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -142,6 +162,8 @@ def load_library(path: str = LIB_PATH):
                                                 P(lbm_rev_result)]),
         "lbm_rev_permeability_static": (ctypes.c_int, [P(lbm_rev_params), P(lbm_rev_domain),
                                                        i32, P(lbm_rev_result)]),
+        "lbm_rev_pc_sweep": (ctypes.c_int, [P(lbm_pc_params), P(lbm_pore_table),
+                                            P(lbm_rev_domain), i32, P(lbm_pc_result)]),
         "lbm_adjoint_flux": (ctypes.c_int, [vp, i64, dp, i64, dp, dp, dp]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_destroy": (None, [vp]),
@@ -450,6 +472,68 @@ def rev_permeability(domains, tau=1.0, g=1e-5, axis=0, collision="regularized",
             r["u"] = outs[k]
         out.append(r)
     return out
+
+
+def rev_pc_sweep(domains, model, membrane_table, rho_nw_in, buffer_in=14, membrane=2,
+                 buffer_out=2, side_walls=True, membrane_phi=0.3, check_every=200,
+                 max_steps=4000, tol=1e-4, use_torch_memory=True):
+    """Capillary-pressure sweep of every domain (uint8 class arrays [z][y][x],
+    0 pore / 1 solid) by lbm_rev_pc_sweep: `model` (workloads.Params of the
+    two-component model; grid, reservoirs and forces are set per domain),
+    the membrane's pore table (a workloads.pore_table dict) and the inlet oil
+    density of every level.  Returns one dict per domain: pc, sw, steps,
+    converged (one entry per level)."""
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("no GPU: the library has no CPU path")
+    lib = load_library()
+    levels = [float(v) for v in rho_nw_in]
+    if not 1 <= len(levels) <= PC_MAX_LEVELS:
+        raise ValueError(f"1 to {PC_MAX_LEVELS} levels")
+    arrs = [np.ascontiguousarray(c, dtype=np.uint8) for c in domains]
+    doms = (lbm_rev_domain * len(arrs))()
+    for k, a in enumerate(arrs):
+        if a.ndim != 3:
+            raise ValueError("each domain is a 3-D class array [z][y][x]")
+        doms[k].nz, doms[k].ny, doms[k].nx = a.shape
+        doms[k].cls = a.ctypes.data
+        doms[k].u_out = None
+    p = lbm_pc_params()
+    p.model = to_c_params(model)
+    p.model.stream = torch.cuda.current_stream().cuda_stream
+    cbs = None
+    if use_torch_memory:
+        dev, st = torch.cuda.current_device(), p.model.stream
+
+        def _alloc(nbytes, ctx):
+            try:
+                return int(torch.cuda.caching_allocator_alloc(int(nbytes), dev, st))
+            except Exception:
+                return None
+
+        def _free(ptr, ctx):
+            try:
+                torch.cuda.caching_allocator_delete(int(ptr))
+            except Exception:
+                pass
+
+        cbs = (ALLOC_FN(_alloc), FREE_FN(_free))
+        p.model.alloc, p.model.free = cbs
+    p.buffer_in, p.membrane, p.buffer_out = int(buffer_in), int(membrane), int(buffer_out)
+    p.side_walls, p.nlevels = int(bool(side_walls)), len(levels)
+    for k, v in enumerate(levels):
+        p.rho_nw_in[k] = v
+    p.membrane_phi = float(membrane_phi)
+    p.check_every, p.max_steps, p.tol = int(check_every), int(max_steps), float(tol)
+    tab = to_c_tables([membrane_table])
+    res = (lbm_pc_result * len(arrs))()
+    rc = lib.lbm_rev_pc_sweep(ctypes.byref(p), tab, doms, len(arrs), res)
+    if rc != LBM_OK:
+        raise LbmError(rc, lib.lbm_last_error(None).decode())
+    n = len(levels)
+    return [{"pc": list(res[k].pc[:n]), "sw": list(res[k].sw[:n]),
+             "steps": list(res[k].steps[:n]), "converged": list(res[k].converged[:n])}
+            for k in range(len(arrs))]
 
 
 def make_state_blob(lbm: Lbm, f, r, side, step=0, q_last=(0.0, 0.0), q_acc=(0.0, 0.0),

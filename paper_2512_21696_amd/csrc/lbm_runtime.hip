@@ -1112,3 +1112,6 @@ extern "C" void lbm_destroy(lbm_handle *h) {
 
 // Discrete adjoint of the one-component step (own kernels and entry point).
 #include "lbm_adjoint.hip"
+
+// Capillary-pressure sweep of many small domains (host driver of the step).
+#include "lbm_pc_sweep.hip"

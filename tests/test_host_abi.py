@@ -126,3 +126,69 @@ def test_rev_permeability_rejects_empty_and_bad_domains_on_host():
     doms[0].cls = None
     assert lib.lbm_rev_permeability(ctypes.byref(p), doms, 1, res) == L.LBM_E_INVAL
     del cls
+
+
+def _pc_args(**kw):
+    import numpy as np
+    import workloads as W
+    su = W.pc_sweep_setup()
+    p = L.lbm_pc_params()
+    p.model = L.to_c_params(su["model"])
+    p.buffer_in, p.membrane, p.buffer_out, p.side_walls = 4, 2, 2, 1
+    p.nlevels = 2
+    p.rho_nw_in[0], p.rho_nw_in[1] = 1.05, 1.1
+    p.membrane_phi, p.check_every, p.max_steps, p.tol = 0.3, 10, 20, 1e-4
+    for k, v in kw.items():
+        if k == "precision":
+            p.model.precision = v
+        else:
+            setattr(p, k, v)
+    cls = np.zeros((4, 4, 4), np.uint8)
+    doms = (L.lbm_rev_domain * 1)()
+    doms[0].nz = doms[0].ny = doms[0].nx = 4
+    doms[0].cls = cls.ctypes.data
+    return p, L.to_c_tables([su["membrane_table"]]), doms, cls
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(nlevels=0), L.LBM_E_INVAL), (dict(nlevels=17), L.LBM_E_INVAL),
+    (dict(buffer_out=1), L.LBM_E_INVAL), (dict(membrane=0), L.LBM_E_INVAL),
+    (dict(buffer_in=0), L.LBM_E_INVAL), (dict(membrane_phi=1.0), L.LBM_E_INVAL),
+    (dict(check_every=0), L.LBM_E_INVAL), (dict(max_steps=5), L.LBM_E_INVAL),
+    (dict(tol=-1.0), L.LBM_E_INVAL), (dict(precision=2), L.LBM_E_UNSUPPORTED)])
+def test_pc_sweep_rejects_bad_arguments_on_host(kw, code):
+    lib = L.load_library()
+    p, tab, doms, cls = _pc_args(**kw)
+    res = (L.lbm_pc_result * 1)()
+    assert lib.lbm_rev_pc_sweep(ctypes.byref(p), tab, doms, 1, res) == code
+    assert len(lib.lbm_last_error(None)) > 0
+
+
+def test_pc_sweep_rejects_null_and_bad_levels_on_host():
+    lib = L.load_library()
+    p, tab, doms, cls = _pc_args()
+    res = (L.lbm_pc_result * 1)()
+    assert lib.lbm_rev_pc_sweep(ctypes.byref(p), None, doms, 1, res) == L.LBM_E_INVAL
+    assert lib.lbm_rev_pc_sweep(ctypes.byref(p), tab, doms, 0, res) == L.LBM_E_INVAL
+    p.rho_nw_in[1] = float("nan")
+    assert lib.lbm_rev_pc_sweep(ctypes.byref(p), tab, doms, 1, res) == L.LBM_E_INVAL
+
+
+def test_pc_structs_match_the_header():
+    """sizeof of the sweep's structs as the C compiler lays them out."""
+    import shutil
+    import subprocess
+    import tempfile
+    if shutil.which("gcc") is None:
+        pytest.skip("no C compiler")
+    src = ('#include <stdio.h>\n#include "%s"\nint main(void){printf("%%zu %%zu %%zu\\n", '
+           'sizeof(lbm_params), sizeof(lbm_pc_params), sizeof(lbm_pc_result));return 0;}\n'
+           % os.path.join(ROOT, "include", "lbm.h"))
+    with tempfile.TemporaryDirectory() as d:
+        c, exe = os.path.join(d, "s.c"), os.path.join(d, "s")
+        open(c, "w").write(src)
+        subprocess.run(["gcc", "-o", exe, c], check=True)
+        sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
+                                                 check=True).stdout.split()]
+    assert sizes == [ctypes.sizeof(L.lbm_params), ctypes.sizeof(L.lbm_pc_params),
+                     ctypes.sizeof(L.lbm_pc_result)]

@@ -383,6 +383,22 @@ def rev_domains(count: int = 96, seed: int = 4001, lmin: int = 24, lmax: int = 9
     return out
 
 
+def pc_sweep_setup(entry_pc: float = 0.3, membrane_phi: float = 0.3, K0: float = 1.0,
+                   levels: tuple = (1.05, 1.12, 1.20, 1.30, 1.42), tau: tuple = (1.0, 1.0),
+                   precision: str = "f64") -> dict:
+    """Inputs of the capillary-pressure sweep: the two-component model (G = 3,
+    water-wet walls, no CSF control), the membrane's pore table (Brooks-Corey
+    Pc with entry pressure `entry_pc`, lambda = 2, Swr = 0.05, a constant K0
+    so that water leaves through it freely, phi_ref = membrane_phi) and the
+    inlet oil density of each of the five levels."""
+    model = Params(nx=8, ny=8, nz=8, ncomp=2, precision=precision, tau=tuple(tau), G=3.0).filled()
+    pc, krw, kro = brooks_corey_tables(entry_pc, 2.0, 0.05)
+    tab = pore_table(np.full(TABLE_N, float(K0)), pc, krw, kro, phi_ref=membrane_phi,
+                     pc_pm=entry_pc)
+    return dict(model=model, membrane_table=tab, membrane_phi=membrane_phi,
+                rho_nw_in=tuple(float(v) for v in levels))
+
+
 def _flux_misfit(seed: int, steps: int, window: int):
     """(target, loss_grad) of the squared flux misfit over steps >= window:
     Q*(n) = 1.1 mean(q_base over the window) (1 + 0.02 xi_n), xi ~ N(0, 1)
