@@ -324,7 +324,7 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
 // rho_T = rho^w + r^w + rho^o + r^o.  The residual amounts are state: lr[2][v]
 // carries dL/dr from step to step (updated in place), and gth[2][v]
 // accumulates dL/dtheta_w, dL/dtheta_o.
-template <typename T, bool REG, bool TENS>
+template <typename T, bool REG, bool TENS, typename AT = double>
 __global__ __launch_bounds__(256) void k_adj_step2(
     const ModelConsts mc, const T *__restrict__ post, const T *__restrict__ rho2,
     const T *__restrict__ rres, const uint8_t *__restrict__ side, const T *__restrict__ nrmb,
@@ -335,6 +335,13 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     const uint8_t *__restrict__ ptype, const T *__restrict__ tab, double *__restrict__ gk,
     double *__restrict__ gsj, double *__restrict__ lr, double *__restrict__ gth,
     const double an) {
+  // the run's constants in the arithmetic type
+  const AT mG = (AT)mc.G, mkappa = (AT)mc.kappa, mcsf = (AT)mc.csf_scale, mminor = (AT)mc.m_minor;
+  const AT msmin = (AT)mc.s_min, mspan = (AT)mc.inv_span, mkrmin = (AT)mc.kr_min, mhyst = (AT)mc.hyst;
+  const AT mnu[2] = {(AT)mc.nu[0], (AT)mc.nu[1]}, momg[2] = {(AT)mc.omega[0], (AT)mc.omega[1]};
+  const AT mwd[2] = {(AT)mc.wall_dpsi[0], (AT)mc.wall_dpsi[1]};
+  const AT mg[2][3] = {{(AT)mc.g[0][0], (AT)mc.g[0][1], (AT)mc.g[0][2]},
+                       {(AT)mc.g[1][0], (AT)mc.g[1][1], (AT)mc.g[1][2]}};
   const long long N = mc.N;
   const int per = gridDim.x / 8;
   const long long blk = (long long)(blockIdx.x % 8) * per + blockIdx.x / 8;
@@ -348,13 +355,13 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
   const int x1 = mc.outlet_x + 1 == mc.nx ? 0 : mc.outlet_x + 1;
   const bool at0 = nb.x == mc.outlet_x, at1 = nb.x == x1;
-  const double cs2 = CS2;
-  constexpr double ics2 = 3.0, ics4 = 9.0;  // 1 / c_s^2, 1 / c_s^4
+  const AT cs2 = CS2;
+  constexpr AT ics2 = AT(3.0), ics4 = AT(9.0);  // 1 / c_s^2, 1 / c_s^4
 
   // pulls, moments and the gathered adjoint of the post-collision sets
-  double rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
-  double Pi[2][6], lf[2];  // second moments (regularised), sum_i lam_i f_i (BGK)
-  double lp[REG ? 1 : 2][REG ? 1 : Q];
+  AT rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
+  AT Pi[2][6], lf[2];  // second moments (regularised), sum_i lam_i f_i (BGK)
+  AT lp[REG ? 1 : 2][REG ? 1 : Q];
   const uint32_t N32 = (uint32_t)N, v32 = (uint32_t)v;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -368,7 +375,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       const int j = opp(i);
       const uint32_t src = ((mk >> j) & 1u) ? (uint32_t)j * N32 + v32
                                             : (uint32_t)i * N32 + (uint32_t)nb.at(-cx(i), -cy(i), -cz(i));
-      const double fi = (double)pa[src];
+      const AT fi = (AT)pa[src];
       rho[a] += fi;
       if (cx(i)) m[a][0] += cx(i) * fi;
       if (cy(i)) m[a][1] += cy(i) * fi;
@@ -384,14 +391,14 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       const bool wall = (mk >> i) & 1u;
       const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
       const uint32_t li = wall ? (uint32_t)j * N32 + v32 : (uint32_t)i * N32 + y;
-      double l = (double)la[li] + (double)rnl[2 * y + a];
+      AT l = (AT)la[li] + (AT)rnl[2 * y + a];
       if (a == 0 && cx(i) == 1 && at0 && !wall) l += an;
       if (a == 0 && cx(i) == -1 && at1 && !wall) l -= an;
       if (!REG) {
         lp[REG ? 0 : a][REG ? 0 : i] = l;
         lf[a] += l * fi;
       }
-      const double wl = wq(i) * l;
+      const AT wl = (AT)wq(i) * l;
       L0[a] += wl;
       if (cx(i)) { L1[a][0] += cx(i) * wl; M2[a][0] += wl; }
       if (cy(i)) { L1[a][1] += cy(i) * wl; M2[a][1] += wl; }
@@ -403,105 +410,105 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   }
 
   // forward quantities
-  const double rt = rho[0] + rho[1], irt = 1.0 / rt;
-  const double irho[2] = {1.0 / rho[0], 1.0 / rho[1]};
-  const double h = 0.5;
-  const double ispan = mc.inv_span;
-  double Fex[2][3], acc[2][3];
+  const AT rt = rho[0] + rho[1], irt = AT(1.0) / rt;
+  const AT irho[2] = {AT(1.0) / rho[0], AT(1.0) / rho[1]};
+  const AT h = AT(0.5);
+  const AT ispan = mspan;
+  AT Fex[2][3], acc[2][3];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int b = 1 - a;
-    double pw = rho[b] + mc.wall_dpsi[b];
-    pw = pw > 0.0 ? pw : 0.0;
+    AT pw = rho[b] + mwd[b];
+    pw = pw > AT(0.0) ? pw : AT(0.0);
     // the fluid links' sum comes from the inputs pass, the solid links read pw
-    double s0 = (double)inb[(size_t)(3 * a) * N + v], s1 = (double)inb[(size_t)(3 * a + 1) * N + v],
-           s2 = (double)inb[(size_t)(3 * a + 2) * N + v];
+    AT s0 = (AT)inb[(size_t)(3 * a) * N + v], s1 = (AT)inb[(size_t)(3 * a + 1) * N + v],
+           s2 = (AT)inb[(size_t)(3 * a + 2) * N + v];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const double w = ((mk >> i) & 1u) ? wq(i) * pw : 0.0;
+      const AT w = ((mk >> i) & 1u) ? (AT)wq(i) * pw : AT(0.0);
       if (cx(i)) s0 += cx(i) * w;
       if (cy(i)) s1 += cy(i) * w;
       if (cz(i)) s2 += cz(i) * w;
     }
     acc[a][0] = s0; acc[a][1] = s1; acc[a][2] = s2;
-    for (int d = 0; d < 3; ++d) Fex[a][d] = rho[a] * mc.g[a][d] - mc.G * rho[a] * acc[a][d];
+    for (int d = 0; d < 3; ++d) Fex[a][d] = rho[a] * mg[a][d] - mG * rho[a] * acc[a][d];
   }
   // CSF control, Eq. (4), on the region's voxels: g^a = grad rho^b and the
   // normals n^a = g^a / |g^a| of the level (nrmb rows 6a..6a+2: g, 6a+3..: n),
   // curv^a = -div n^a (own normal across a solid link), F^a += kap curv g rho^a
-  const bool csfv = mc.kappa != 0.0 && (gray || mc.csf_all);
-  const double kap = mc.kappa * mc.csf_scale;
-  double cg[2][3] = {{0, 0, 0}, {0, 0, 0}}, curv[2] = {0, 0};
+  const bool csfv = mkappa != AT(0.0) && (gray || mc.csf_all);
+  const AT kap = mkappa * mcsf;
+  AT cg[2][3] = {{0, 0, 0}, {0, 0, 0}}, curv[2] = {0, 0};
   if (csfv) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      for (int d = 0; d < 3; ++d) cg[a][d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
-      curv[a] = (double)inb[(size_t)(9 + a) * N + v];
+      for (int d = 0; d < 3; ++d) cg[a][d] = (AT)nrmb[(size_t)(6 * a + d) * N + v];
+      curv[a] = (AT)inb[(size_t)(9 + a) * N + v];
       for (int d = 0; d < 3; ++d) Fex[a][d] += kap * curv[a] * cg[a][d] * rho[a];
     }
   }
   // gray: saturation, tables, capillary force, resistance coefficient
-  double S = 0, Sraw = 0, tw = 0, to = 0, gS[3] = {0, 0, 0}, Pct = 0, dPct = 0, Krw = 0,
+  AT S = 0, Sraw = 0, tw = 0, to = 0, gS[3] = {0, 0, 0}, Pct = 0, dPct = 0, Krw = 0,
          dKrw = 0, Kro = 0, dKro = 0, sj = 0, Pc = 0, kw = 1, ko = 1, ikw = 1, iko = 1, cR = 0;
-  const double shat0 = (rho[0] * irt - mc.s_min) * ispan;
+  const AT shat0 = (rho[0] * irt - msmin) * ispan;
   if (gray) {
-    tw = rho[0] + (double)rres[v];
-    to = rho[1] + (double)rres[N + v];
-    Sraw = (tw / (tw + to) - mc.s_min) * ispan;
-    S = Sraw < 0.0 ? 0.0 : (Sraw > 1.0 ? 1.0 : Sraw);
-    for (int d = 0; d < 3; ++d) gS[d] = (double)inb[(size_t)(6 + d) * N + v];
+    tw = rho[0] + (AT)rres[v];
+    to = rho[1] + (AT)rres[N + v];
+    Sraw = (tw / (tw + to) - msmin) * ispan;
+    S = Sraw < AT(0.0) ? AT(0.0) : (Sraw > AT(1.0) ? AT(1.0) : Sraw);
+    for (int d = 0; d < 3; ++d) gS[d] = (AT)inb[(size_t)(6 + d) * N + v];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {  // solid links read this voxel's own S_hat
-      const double w = ((mk >> i) & 1u) ? gw(i) * shat0 : 0.0;
+      const AT w = ((mk >> i) & 1u) ? (AT)gw(i) * shat0 : AT(0.0);
       if (cx(i)) gS[0] += cx(i) * w;
       if (cy(i)) gS[1] += cy(i) * w;
       if (cz(i)) gS[2] += cz(i) * w;
     }
     const T *tb = tab + (size_t)ptype[v] * 3 * TABLE_N;
-    const double t = S * (double)(TABLE_N - 1);
+    const AT t = S * (AT)(TABLE_N - 1);
     int k = (int)floor(t);
     k = k > TABLE_N - 2 ? TABLE_N - 2 : (k < 0 ? 0 : k);
-    const double fr = t - (double)k;
-    auto lookup = [&](const T *c, double &val, double &slope) {
-      const double lo = (double)c[k], hi = (double)c[k + 1];
+    const AT fr = t - (AT)k;
+    auto lookup = [&](const T *c, AT &val, AT &slope) {
+      const AT lo = (AT)c[k], hi = (AT)c[k + 1];
       val = lo + fr * (hi - lo);
-      slope = (hi - lo) * (double)(TABLE_N - 1);
+      slope = (hi - lo) * (AT)(TABLE_N - 1);
     };
     lookup(tb, Pct, dPct);
     lookup(tb + TABLE_N, Krw, dKrw);
     lookup(tb + 2 * TABLE_N, Kro, dKro);
-    sj = (double)sJ[v];
+    sj = (AT)sJ[v];
     Pc = sj * Pct;
     for (int a = 0; a < 2; ++a)
       for (int d = 0; d < 3; ++d) Fex[a][d] += -Pc * (rho[a] * irt) * gS[d];
-    kw = Krw > mc.kr_min ? Krw : mc.kr_min;
-    ko = Kro > mc.kr_min ? Kro : mc.kr_min;
-    ikw = 1.0 / kw;
-    iko = 1.0 / ko;
-    const double cw = S > 0.0 ? rt * S * mc.nu[0] * ikw : 0.0;
-    const double co = 1.0 - S > 0.0 ? rt * (1.0 - S) * mc.nu[1] * iko : 0.0;
+    kw = Krw > mkrmin ? Krw : mkrmin;
+    ko = Kro > mkrmin ? Kro : mkrmin;
+    ikw = AT(1.0) / kw;
+    iko = AT(1.0) / ko;
+    const AT cw = S > AT(0.0) ? rt * S * mnu[0] * ikw : AT(0.0);
+    const AT co = AT(1.0) - S > AT(0.0) ? rt * (AT(1.0) - S) * mnu[1] * iko : AT(0.0);
     cR = cw + co;
   }
   // resistance
-  double bvec[3], u[3], Ru[3], K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
+  AT bvec[3], u[3], Ru[3], K[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}},
                                   Ai[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}}, wv[3] = {0, 0, 0};
   for (int d = 0; d < 3; ++d) bvec[d] = m[0][d] + m[1][d] + h * (Fex[0][d] + Fex[1][d]);
-  double k0 = 1.0, Rs = 0.0, den = rt;
+  AT k0 = AT(1.0), Rs = AT(0.0), den = rt;
   if (tens) {
-    K[0][0] = (double)Kinv[v];
-    K[1][1] = (double)Kinv[N + v];
-    K[2][2] = (double)Kinv[2 * N + v];
-    K[0][1] = K[1][0] = (double)Kinv[3 * N + v];
-    K[0][2] = K[2][0] = (double)Kinv[4 * N + v];
-    K[1][2] = K[2][1] = (double)Kinv[5 * N + v];
-    const double hc = h * cR;
-    const double a00 = rt + hc * K[0][0], a11 = rt + hc * K[1][1], a22 = rt + hc * K[2][2];
-    const double a01 = hc * K[0][1], a02 = hc * K[0][2], a12 = hc * K[1][2];
-    const double c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22,
+    K[0][0] = (AT)Kinv[v];
+    K[1][1] = (AT)Kinv[N + v];
+    K[2][2] = (AT)Kinv[2 * N + v];
+    K[0][1] = K[1][0] = (AT)Kinv[3 * N + v];
+    K[0][2] = K[2][0] = (AT)Kinv[4 * N + v];
+    K[1][2] = K[2][1] = (AT)Kinv[5 * N + v];
+    const AT hc = h * cR;
+    const AT a00 = rt + hc * K[0][0], a11 = rt + hc * K[1][1], a22 = rt + hc * K[2][2];
+    const AT a01 = hc * K[0][1], a02 = hc * K[0][2], a12 = hc * K[1][2];
+    const AT c00 = a11 * a22 - a12 * a12, c01 = a02 * a12 - a01 * a22,
                  c02 = a01 * a12 - a02 * a11;
-    const double c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12,
+    const AT c11 = a00 * a22 - a02 * a02, c12 = a01 * a02 - a00 * a12,
                  c22 = a00 * a11 - a01 * a01;
-    const double idet = 1.0 / (a00 * c00 + a01 * c01 + a02 * c02);
+    const AT idet = AT(1.0) / (a00 * c00 + a01 * c01 + a02 * c02);
     Ai[0][0] = c00 * idet; Ai[1][1] = c11 * idet; Ai[2][2] = c22 * idet;
     Ai[0][1] = Ai[1][0] = c01 * idet;
     Ai[0][2] = Ai[2][0] = c02 * idet;
@@ -513,93 +520,93 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   } else {
     if (gray) {
-      k0 = (double)K0[v];
+      k0 = (AT)K0[v];
       Rs = cR / k0;  // once per voxel
     }
     den = rt + h * Rs;
-    const double idn0 = 1.0 / den;
+    const AT idn0 = AT(1.0) / den;
     for (int d = 0; d < 3; ++d) {
       u[d] = bvec[d] * idn0;
       Ru[d] = Rs * u[d];
     }
   }
-  double F[2][3];
+  AT F[2][3];
   for (int a = 0; a < 2; ++a)
     for (int d = 0; d < 3; ++d) F[a][d] = Fex[a][d] - (rho[a] * irt) * Ru[d];
-  const double om[2] = {mc.omega[0], mc.omega[1]};
-  const double D = om[0] * rho[0] + om[1] * rho[1], iD = 1.0 / D;
-  double up[3];
+  const AT om[2] = {momg[0], momg[1]};
+  const AT D = om[0] * rho[0] + om[1] * rho[1], iD = AT(1.0) / D;
+  AT up[3];
   for (int d = 0; d < 3; ++d) up[d] = (om[0] * m[0][d] + om[1] * m[1][d]) * iD;
 
   // residual transfer: which branch, the scale factors, and dL/ds^a =
   // sum_i lam_post_i post_i of the unscaled set; the adjoint of the unscaled
   // set is s^a times the gathered one
   int ev = 0;  // 1: oil -> water, 2: water -> oil
-  double sc[2] = {1.0, 1.0}, scb[2] = {0.0, 0.0}, dtr = 0.0, rw0 = 0.0, ro0 = 0.0;
+  AT sc[2] = {AT(1.0), AT(1.0)}, scb[2] = {AT(0.0), AT(0.0)}, dtr = AT(0.0), rw0 = AT(0.0), ro0 = AT(0.0);
   if (gray) {
     const bool sd = side[v] != 0;
-    if (!sd && S >= 0.5 + mc.hyst) ev = 1;
-    else if (sd && S <= 0.5 - mc.hyst) ev = 2;
+    if (!sd && S >= AT(0.5) + mhyst) ev = 1;
+    else if (sd && S <= AT(0.5) - mhyst) ev = 2;
   }
   if (ev) {
-    rw0 = (double)rres[v];
-    ro0 = (double)rres[N + v];
-    const double rhoT = tw + to, mm = mc.m_minor;
+    rw0 = (AT)rres[v];
+    ro0 = (AT)rres[N + v];
+    const AT rhoT = tw + to, mm = mminor;
     if (ev == 1) {
       sc[0] = (rho[0] + rw0) * irho[0];
-      double d = (double)tho[v] * rhoT - ro0;
-      const double cap = rho[1] - mm;
+      AT d = (AT)tho[v] * rhoT - ro0;
+      const AT cap = rho[1] - mm;
       d = d < cap ? d : cap;
-      dtr = d > 0.0 ? d : 0.0;
-      sc[1] = 1.0 - dtr * irho[1];
+      dtr = d > AT(0.0) ? d : AT(0.0);
+      sc[1] = AT(1.0) - dtr * irho[1];
     } else {
       sc[1] = (rho[1] + ro0) * irho[1];
-      double d = (double)thw[v] * rhoT - rw0;
-      const double cap = rho[0] - mm;
+      AT d = (AT)thw[v] * rhoT - rw0;
+      const AT cap = rho[0] - mm;
       d = d < cap ? d : cap;
-      dtr = d > 0.0 ? d : 0.0;
-      sc[0] = 1.0 - dtr * irho[0];
+      dtr = d > AT(0.0) ? d : AT(0.0);
+      sc[0] = AT(1.0) - dtr * irho[0];
     }
     for (int a = 0; a < 2; ++a) {
-      const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a], ra = rho[a];
-      double ua[3], ve[3];
+      const AT keep = AT(1.0) - om[a], e = REG ? AT(1.0) : om[a], ra = rho[a];
+      AT ua[3], ve[3];
       for (int d = 0; d < 3; ++d) {
-        ua[d] = up[d] + F[a][d] * 0.5 * irho[a];
+        ua[d] = up[d] + F[a][d] * AT(0.5) * irho[a];
         ve[d] = gray ? ua[d] : up[d];
       }
-      const double kf = gray ? 1.0 - 0.5 * om[a] : 1.0;
-      double uF = 0, pl = 0, FL = 0, vsq = 0;
+      const AT kf = gray ? AT(1.0) - AT(0.5) * om[a] : AT(1.0);
+      AT uF = 0, pl = 0, FL = 0, vsq = 0;
       for (int d = 0; d < 3; ++d) {
         uF += ua[d] * F[a][d];
         pl += ve[d] * L1[a][d];
         FL += F[a][d] * L1[a][d];
         vsq += ve[d] * ve[d];
       }
-      const double *Mv = M2[a];
-      const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
-      double uMu = 0, aMF = 0;
+      const AT *Mv = M2[a];
+      const AT Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
+      AT uMu = 0, aMF = 0;
       for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) {
           uMu += ve[i] * Mm[i][j] * ve[j];
           aMF += ua[i] * Mm[i][j] * F[a][j];
         }
       // equilibrium and force parts of A L0 + B.L1 + C:M
-      double phi_a = e * ra * (1.0 - vsq * (0.5 * ics2)) * L0[a] - kf * uF * ics2 * L0[a] +
-                     e * ra * pl * ics2 + kf * FL * ics2 + e * ra * uMu * (0.5 * ics4) +
+      AT phi_a = e * ra * (AT(1.0) - vsq * (AT(0.5) * ics2)) * L0[a] - kf * uF * ics2 * L0[a] +
+                     e * ra * pl * ics2 + kf * FL * ics2 + e * ra * uMu * (AT(0.5) * ics4) +
                      kf * aMF * ics4;
       if (REG) {
-        const double *P = Pi[a];
-        const double Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
-        double tr = 0, PM = 0, jl = 0;
+        const AT *P = Pi[a];
+        const AT Pm[3][3] = {{P[0], P[3], P[4]}, {P[3], P[1], P[5]}, {P[4], P[5], P[2]}};
+        AT tr = 0, PM = 0, jl = 0;
         for (int i = 0; i < 3; ++i) {
           for (int j = 0; j < 3; ++j) {
-            const double pn = Pm[i][j] - (i == j ? ra * cs2 : 0.0) - ra * ve[i] * ve[j];
+            const AT pn = Pm[i][j] - (i == j ? ra * cs2 : AT(0.0)) - ra * ve[i] * ve[j];
             PM += pn * Mm[i][j];
             if (i == j) tr += pn;
           }
           jl += (m[a][i] - ra * ve[i]) * L1[a][i];
         }
-        phi_a += keep * (-tr * (0.5 * ics2) * L0[a] + jl * ics2 + PM * (0.5 * ics4));
+        phi_a += keep * (-tr * (AT(0.5) * ics2) * L0[a] + jl * ics2 + PM * (AT(0.5) * ics4));
       } else {
         phi_a += keep * lf[a];
       }
@@ -614,26 +621,26 @@ __global__ __launch_bounds__(256) void k_adj_step2(
 
   // reverse sweep; per component the equilibrium velocity ve is u' (pore)
   // or ua (gray), and kf the force term's weight (1 or 1 - omega/2)
-  double rb[2] = {0, 0}, mb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Pb[2][6];
-  double upb[3] = {0, 0, 0}, Fb[2][3];
+  AT rb[2] = {0, 0}, mb[2][3] = {{0, 0, 0}, {0, 0, 0}}, Pb[2][6];
+  AT upb[3] = {0, 0, 0}, Fb[2][3];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
-    const double keep = 1.0 - om[a], e = REG ? 1.0 : om[a];
-    const double ra = rho[a], ir2 = 0.5 * irho[a];
-    const double kf = gray ? 1.0 - 0.5 * om[a] : 1.0;
-    double ua[3], ve[3];
+    const AT keep = AT(1.0) - om[a], e = REG ? AT(1.0) : om[a];
+    const AT ra = rho[a], ir2 = AT(0.5) * irho[a];
+    const AT kf = gray ? AT(1.0) - AT(0.5) * om[a] : AT(1.0);
+    AT ua[3], ve[3];
     for (int d = 0; d < 3; ++d) {
       ua[d] = up[d] + F[a][d] * ir2;
       ve[d] = gray ? ua[d] : up[d];
     }
-    const double vsq = ve[0] * ve[0] + ve[1] * ve[1] + ve[2] * ve[2];
-    const double *Mv = M2[a];
-    const double Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
-    double Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0}, veb[3] = {0, 0, 0};
-    rb[a] += e * (1.0 - vsq * (0.5 * ics2)) * L0[a];
-    const double vsqb = -e * ra * (0.5 * ics2) * L0[a];
-    const double uFb = -kf * L0[a] * ics2;
-    double pl = 0, pMp = 0;
+    const AT vsq = ve[0] * ve[0] + ve[1] * ve[1] + ve[2] * ve[2];
+    const AT *Mv = M2[a];
+    const AT Mm[3][3] = {{Mv[0], Mv[3], Mv[4]}, {Mv[3], Mv[1], Mv[5]}, {Mv[4], Mv[5], Mv[2]}};
+    AT Fbar[3] = {0, 0, 0}, uab[3] = {0, 0, 0}, veb[3] = {0, 0, 0};
+    rb[a] += e * (AT(1.0) - vsq * (AT(0.5) * ics2)) * L0[a];
+    const AT vsqb = -e * ra * (AT(0.5) * ics2) * L0[a];
+    const AT uFb = -kf * L0[a] * ics2;
+    AT pl = 0, pMp = 0;
     for (int d = 0; d < 3; ++d) pl += ve[d] * L1[a][d];
     rb[a] += e * pl * ics2;
     for (int d = 0; d < 3; ++d) {
@@ -641,41 +648,41 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       Fbar[d] += kf * L1[a][d] * ics2;
     }
     for (int i = 0; i < 3; ++i) {
-      const double Mu = Mm[i][0] * ve[0] + Mm[i][1] * ve[1] + Mm[i][2] * ve[2];
+      const AT Mu = Mm[i][0] * ve[0] + Mm[i][1] * ve[1] + Mm[i][2] * ve[2];
       pMp += ve[i] * Mu;
       veb[i] += e * ra * Mu * ics4;
       uab[i] += kf * (Mm[i][0] * F[a][0] + Mm[i][1] * F[a][1] + Mm[i][2] * F[a][2]) * ics4;
       Fbar[i] += kf * (Mm[i][0] * ua[0] + Mm[i][1] * ua[1] + Mm[i][2] * ua[2]) * ics4;
     }
-    rb[a] += e * pMp * (0.5 * ics4);
+    rb[a] += e * pMp * (AT(0.5) * ics4);
     for (int d = 0; d < 6; ++d) Pb[a][d] = 0;
     if (REG) {
-      const double c = keep * (0.5 * ics4), dd = -keep * (0.5 * ics2) * L0[a];
-      double B[3][3];
+      const AT c = keep * (AT(0.5) * ics4), dd = -keep * (AT(0.5) * ics2) * L0[a];
+      AT B[3][3];
       for (int i = 0; i < 3; ++i)
-        for (int j = 0; j < 3; ++j) B[i][j] = c * Mm[i][j] + (i == j ? dd : 0.0);
+        for (int j = 0; j < 3; ++j) B[i][j] = c * Mm[i][j] + (i == j ? dd : AT(0.0));
       Pb[a][0] = B[0][0]; Pb[a][1] = B[1][1]; Pb[a][2] = B[2][2];
       Pb[a][3] = B[0][1]; Pb[a][4] = B[0][2]; Pb[a][5] = B[1][2];
-      double pBp = 0;
+      AT pBp = 0;
       for (int i = 0; i < 3; ++i) {
-        const double Bu = B[i][0] * ve[0] + B[i][1] * ve[1] + B[i][2] * ve[2];
+        const AT Bu = B[i][0] * ve[0] + B[i][1] * ve[1] + B[i][2] * ve[2];
         pBp += ve[i] * Bu;
-        veb[i] += -2.0 * ra * Bu;
+        veb[i] += -AT(2.0) * ra * Bu;
       }
       rb[a] += -cs2 * (B[0][0] + B[1][1] + B[2][2]) - pBp;
       // first-order part j^a = m^a - rho^a ve
-      double pj = 0;
+      AT pj = 0;
       for (int d = 0; d < 3; ++d) {
-        const double jb = keep * L1[a][d] * ics2;
+        const AT jb = keep * L1[a][d] * ics2;
         mb[a][d] += jb;
         pj += ve[d] * jb;
         veb[d] += -ra * jb;
       }
       rb[a] += -pj;
     }
-    double abF = 0;
+    AT abF = 0;
     for (int d = 0; d < 3; ++d) {
-      veb[d] += 2.0 * ve[d] * vsqb;
+      veb[d] += AT(2.0) * ve[d] * vsqb;
       if (gray) uab[d] += veb[d];
       else upb[d] += veb[d];
       uab[d] += F[a][d] * uFb;
@@ -688,7 +695,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     for (int d = 0; d < 3; ++d) Fb[a][d] = Fbar[d];
   }
   {
-    double pu = 0;
+    AT pu = 0;
     for (int d = 0; d < 3; ++d) pu += upb[d] * up[d];
     for (int a = 0; a < 2; ++a) {
       for (int d = 0; d < 3; ++d) mb[a][d] += om[a] * upb[d] * iD;
@@ -696,9 +703,9 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   }
   // F^a = F_ex^a - (rho^a / rho_t) R u
-  double Rub[3] = {0, 0, 0}, rtb = 0, Fexb[2][3], twb = 0, tob = 0;
+  AT Rub[3] = {0, 0, 0}, rtb = 0, Fexb[2][3], twb = 0, tob = 0;
   for (int a = 0; a < 2; ++a) {
-    double FR = 0;
+    AT FR = 0;
     for (int d = 0; d < 3; ++d) {
       Fexb[a][d] = Fb[a][d];
       Rub[d] += -(rho[a] * irt) * Fb[a][d];
@@ -707,20 +714,20 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     rb[a] += -FR * irt;
     rtb += rho[a] * FR * irt * irt;
   }
-  double cRb = 0, bb[3];
+  AT cRb = 0, bb[3];
   if (tens) {
     cRb = Rub[0] * wv[0] + Rub[1] * wv[1] + Rub[2] * wv[2];
-    double wb[3], ub[3], Kb[3][3];
+    AT wb[3], ub[3], Kb[3][3];
     for (int i = 0; i < 3; ++i) wb[i] = cR * Rub[i];
     for (int i = 0; i < 3; ++i) {
       ub[i] = K[i][0] * wb[0] + K[i][1] * wb[1] + K[i][2] * wb[2];
       for (int j = 0; j < 3; ++j) Kb[i][j] = wb[i] * u[j];
     }
     for (int i = 0; i < 3; ++i) bb[i] = Ai[i][0] * ub[0] + Ai[i][1] * ub[1] + Ai[i][2] * ub[2];
-    double AK = 0;
+    AT AK = 0;
     for (int i = 0; i < 3; ++i)
       for (int j = 0; j < 3; ++j) {
-        const double Ab = -bb[i] * u[j];
+        const AT Ab = -bb[i] * u[j];
         AK += Ab * K[i][j];
         Kb[i][j] += h * cR * Ab;
         if (i == j) rtb += Ab;
@@ -733,13 +740,13 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     gk[4 * N + v] += Kb[0][2] + Kb[2][0];
     gk[5 * N + v] += Kb[1][2] + Kb[2][1];
   } else {
-    double Rsb = 0, ub[3];
+    AT Rsb = 0, ub[3];
     for (int d = 0; d < 3; ++d) {
       Rsb += u[d] * Rub[d];
       ub[d] = Rs * Rub[d];
     }
-    const double idn = 1.0 / den;
-    double denb = 0;
+    const AT idn = AT(1.0) / den;
+    AT denb = 0;
     for (int d = 0; d < 3; ++d) {
       bb[d] = ub[d] * idn;
       denb += -ub[d] * u[d] * idn;
@@ -747,7 +754,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     rtb += denb;
     Rsb += h * denb;
     if (gray) {
-      const double ik0 = 1.0 / k0;
+      const AT ik0 = AT(1.0) / k0;
       cRb = Rsb * ik0;
       gk[v] += -Rsb * cR * ik0 * ik0;
     }
@@ -759,12 +766,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   // CSF: this voxel's part; dL/dcurv^a and dL/dg^a of the force term are
   // stashed (rows 9, 10 and 11..16) for the normals' and gradients' reverse
-  if (mc.kappa != 0.0) {
+  if (mkappa != AT(0.0)) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      double cb = 0.0, gb[3] = {0, 0, 0};
+      AT cb = AT(0.0), gb[3] = {0, 0, 0};
       if (csfv) {
-        const double gFc = cg[a][0] * Fexb[a][0] + cg[a][1] * Fexb[a][1] + cg[a][2] * Fexb[a][2];
+        const AT gFc = cg[a][0] * Fexb[a][0] + cg[a][1] * Fexb[a][1] + cg[a][2] * Fexb[a][2];
         rb[a] += kap * curv[a] * gFc;
         cb = kap * rho[a] * gFc;
         for (int d = 0; d < 3; ++d) gb[d] = kap * curv[a] * rho[a] * Fexb[a][d];
@@ -775,26 +782,26 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   }
   // F_ex: body force, pseudo-potential force (own part; the neighbours'
   // part is stashed), capillary term
-  double gSb[3] = {0, 0, 0}, Pcb = 0;
+  AT gSb[3] = {0, 0, 0}, Pcb = 0;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     const int b = 1 - a;
-    double gF = 0, aF = 0, gFS = 0;
+    AT gF = 0, aF = 0, gFS = 0;
     for (int d = 0; d < 3; ++d) {
-      gF += mc.g[a][d] * Fexb[a][d];
+      gF += mg[a][d] * Fexb[a][d];
       aF += acc[a][d] * Fexb[a][d];
       gFS += gS[d] * Fexb[a][d];
     }
-    rb[a] += gF - mc.G * aF;
-    const double accb[3] = {-mc.G * rho[a] * Fexb[a][0], -mc.G * rho[a] * Fexb[a][1],
-                            -mc.G * rho[a] * Fexb[a][2]};
+    rb[a] += gF - mG * aF;
+    const AT accb[3] = {-mG * rho[a] * Fexb[a][0], -mG * rho[a] * Fexb[a][1],
+                            -mG * rho[a] * Fexb[a][2]};
     for (int d = 0; d < 3; ++d) stash[(size_t)(3 * a + d) * N + v] = (T)accb[d];
-    if (rho[b] + mc.wall_dpsi[b] > 0.0) {  // solid links read max(rho^b + dpsi^b, 0)
-      double wsum = 0;
+    if (rho[b] + mwd[b] > AT(0.0)) {  // solid links read max(rho^b + dpsi^b, 0)
+      AT wsum = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        const double t = wq(i) * (cx(i) * accb[0] + cy(i) * accb[1] + cz(i) * accb[2]);
-        wsum += ((mk >> i) & 1u) ? t : 0.0;
+        const AT t = (AT)wq(i) * (cx(i) * accb[0] + cy(i) * accb[1] + cz(i) * accb[2]);
+        wsum += ((mk >> i) & 1u) ? t : AT(0.0);
       }
       rb[b] += wsum;
     }
@@ -808,31 +815,31 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   if (gray) {
     for (int d = 0; d < 3; ++d) stash[(size_t)(6 + d) * N + v] = (T)gSb[d];
     // c_R
-    double Sb = 0;
-    if (S > 0.0) {
-      rtb += cRb * S * mc.nu[0] * ikw;
-      Sb += cRb * rt * mc.nu[0] * ikw;
-      if (Krw > mc.kr_min) Sb += -cRb * rt * S * mc.nu[0] * ikw * ikw * dKrw;
+    AT Sb = 0;
+    if (S > AT(0.0)) {
+      rtb += cRb * S * mnu[0] * ikw;
+      Sb += cRb * rt * mnu[0] * ikw;
+      if (Krw > mkrmin) Sb += -cRb * rt * S * mnu[0] * ikw * ikw * dKrw;
     }
-    if (1.0 - S > 0.0) {
-      rtb += cRb * (1.0 - S) * mc.nu[1] * iko;
-      Sb += -cRb * rt * mc.nu[1] * iko;
-      if (Kro > mc.kr_min) Sb += -cRb * rt * (1.0 - S) * mc.nu[1] * iko * iko * dKro;
+    if (AT(1.0) - S > AT(0.0)) {
+      rtb += cRb * (AT(1.0) - S) * mnu[1] * iko;
+      Sb += -cRb * rt * mnu[1] * iko;
+      if (Kro > mkrmin) Sb += -cRb * rt * (AT(1.0) - S) * mnu[1] * iko * iko * dKro;
     }
     // P_c = s_J P_c(S)
     gsj[v] += Pcb * Pct;
     Sb += Pcb * sj * dPct;
-    if (Sraw > 0.0 && Sraw < 1.0) {
-      const double itt = 1.0 / (tw + to), sb = Sb * ispan;
+    if (Sraw > AT(0.0) && Sraw < AT(1.0)) {
+      const AT itt = AT(1.0) / (tw + to), sb = Sb * ispan;
       twb += sb * to * itt * itt;
       tob += -sb * tw * itt * itt;
     }
     // grad S_hat: the links to solid neighbours read this voxel's S_hat
-    double shb = 0;
+    AT shb = 0;
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
-      const double t = gw(i) * (cx(i) * gSb[0] + cy(i) * gSb[1] + cz(i) * gSb[2]);
-      shb += ((mk >> i) & 1u) ? t : 0.0;
+      const AT t = (AT)gw(i) * (cx(i) * gSb[0] + cy(i) * gSb[1] + cz(i) * gSb[2]);
+      shb += ((mk >> i) & 1u) ? t : AT(0.0);
     }
     rb[0] += shb * ispan * rho[1] * irt * irt;
     rb[1] += -shb * ispan * rho[0] * irt * irt;
@@ -841,11 +848,11 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   rb[1] += rtb;
   if (gray) {
     // residual amounts: dL/dr after the step comes in, dL/dr before it goes out
-    double rbw = 0.0, rbo = 0.0;
-    const double lw = lr[v], lo_ = lr[N + v];
+    AT rbw = AT(0.0), rbo = AT(0.0);
+    const AT lw = lr[v], lo_ = lr[N + v];
     if (ev) {
-      const double rhoT = tw + to;
-      double db = 0.0, rTb = 0.0;
+      const AT rhoT = tw + to;
+      AT db = AT(0.0), rTb = AT(0.0);
       if (ev == 1) {
         rb[0] += scb[0] * (-rw0 * irho[0] * irho[0]);
         rbw += scb[0] * irho[0];
@@ -853,12 +860,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         rb[1] += scb[1] * dtr * irho[1] * irho[1];
         rbo += lo_;  // r^o <- r^o + d; r^w <- 0
         db += lo_;
-        const double raw = (double)tho[v] * rhoT - ro0, cap = rho[1] - mc.m_minor;
-        if (raw < cap && raw > 0.0) {
+        const AT raw = (AT)tho[v] * rhoT - ro0, cap = rho[1] - mminor;
+        if (raw < cap && raw > AT(0.0)) {
           gth[N + v] += db * rhoT;
-          rTb += db * (double)tho[v];
+          rTb += db * (AT)tho[v];
           rbo -= db;
-        } else if (raw >= cap && cap > 0.0) {
+        } else if (raw >= cap && cap > AT(0.0)) {
           rb[1] += db;
         }
       } else {
@@ -868,12 +875,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         rb[0] += scb[0] * dtr * irho[0] * irho[0];
         rbw += lw;  // r^w <- r^w + d; r^o <- 0
         db += lw;
-        const double raw = (double)thw[v] * rhoT - rw0, cap = rho[0] - mc.m_minor;
-        if (raw < cap && raw > 0.0) {
+        const AT raw = (AT)thw[v] * rhoT - rw0, cap = rho[0] - mminor;
+        if (raw < cap && raw > AT(0.0)) {
           gth[v] += db * rhoT;
-          rTb += db * (double)thw[v];
+          rTb += db * (AT)thw[v];
           rbw -= db;
-        } else if (raw >= cap && cap > 0.0) {
+        } else if (raw >= cap && cap > AT(0.0)) {
           rb[0] += db;
         }
       }
@@ -895,7 +902,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     T *lo = lout + (size_t)a * Q * N;
 #pragma unroll
     for (int k = 0; k < Q; ++k) {
-      double l = rb[a];
+      AT l = rb[a];
       if (cx(k)) l += cx(k) * mb[a][0];
       if (cy(k)) l += cy(k) * mb[a][1];
       if (cz(k)) l += cz(k) * mb[a][2];
@@ -907,7 +914,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         if (cx(k) && cz(k)) l += (2 * cx(k) * cz(k)) * Pb[a][4];
         if (cy(k) && cz(k)) l += (2 * cy(k) * cz(k)) * Pb[a][5];
       } else {
-        l += (1.0 - om[a]) * lp[REG ? 0 : a][REG ? 0 : k];
+        l += (AT(1.0) - om[a]) * lp[REG ? 0 : a][REG ? 0 : k];
       }
       lo[(size_t)k * N + v] = (T)l;
     }
@@ -1386,7 +1393,8 @@ void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, dou
                         double a, const Rev2<T> &b) {
   DevState<T> &s = state<T>(h);
   const unsigned nb = (blocks(h->N) + 7) / 8 * 8;
-  hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS>), dim3(nb), dim3(256), 0, h->st, h->mc,
+  // fp32 storage reverses in fp32 arithmetic (the accumulators stay fp64)
+  hipLaunchKernelGGL((adj::k_adj_step2<T, REG, TENS, T>), dim3(nb), dim3(256), 0, h->st, h->mc,
                      post, (const T *)b.dens, b.r, b.side, (const T *)b.nrmb,
                      (const T *)b.inb, lin,
                      (const T *)b.rnl_in, lout,
