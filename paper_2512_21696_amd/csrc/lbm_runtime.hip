@@ -485,11 +485,12 @@ void launch_tiled(lbm_handle *h, const T *fin_ = nullptr, T *fout_ = nullptr) {
   } else if constexpr (std::is_same<T, float>::value) {
     const void *fin = s.fc[h->cur];
     void *fout = s.fc[1 - h->cur];
+    // (16-bit storage takes the density pass: no push)
     if (h->sk == SK_F16)
-      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16, P>), dim3(grid), dim3(zm::NT), 0,
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_F16>), dim3(grid), dim3(zm::NT), 0,
                          h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
     else
-      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16, P>), dim3(grid), dim3(zm::NT), 0,
+      hipLaunchKernelGGL((k_step_zm<float, NC, REG, SK_BF16>), dim3(grid), dim3(zm::NT), 0,
                          h->st, make_kc<float>(h->mc), fin, fout, s, tx, ty, zc, nt);
   }
 }

@@ -624,6 +624,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint32_t NE = N32 * ES;
     const uint32_t ZE[3] = {(uint32_t)zm1 * nxy * ES, zo * ES, (uint32_t)zp1 * nxy * ES};
     const uint32_t vE = vv * ES;
+    // a solid voxel's pulls are never used: its lane loads nothing
+    if (((mkz >> CLASS_SHIFT) & 3u) == SOLID_CODE) {
+#pragma unroll
+      for (int a = 0; a < NC; ++a)
+#pragma unroll
+        for (int i = 0; i < Q; ++i) pf[a][i] = (LT)0;
+      return;
+    }
 #pragma unroll
     for (int a = 0; a < NC; ++a) pf[a][0] = pull_raw_s<T, SK>(rin[a], vE, 0u);
     // pair (i, j = i + 1) of opposite directions, both addressed from the
