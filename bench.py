@@ -416,6 +416,29 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
     adj_ms = ka["adjoint_ms"] / max(ka["adjoint_launches"], 1)
     achieved = b * n_fluid / (adj_ms * 1e-3) / 1e9
     g = out["dL_dphi"]
+    # the same gradient from fp64 storage (the reference the tests hold to
+    # finite differences): its error against the largest gradient over the
+    # gray voxels
+    vs64 = None
+    if precision != "f64":
+        if kind == "rock":
+            w64 = W.adjoint_rock(n=n, steps=steps, precision="f64")
+        elif kind in ("rock2", "rock2-kappa0"):
+            w64 = W.adjoint_rock2(n=n, steps=steps, precision="f64",
+                                  kappa=0.0 if kind == "rock2-kappa0" else None)
+        else:
+            w64 = None
+        if w64 is not None:
+            l64 = L.lbm_create(w64["params"])
+            l64.set_geometry(cls, w64["phi"], w64["ptype"], w64["tables"])
+            l64.init_fluid(w64["rho_w"], w64.get("rho_o"))
+            o64 = l64.adjoint_flux(steps, dLdQ, checkpoint_every=every)
+            l64.destroy()
+            gm = cls == 2
+            d = np.abs(g[gm] - o64["dL_dphi"][gm]) / np.abs(o64["dL_dphi"][gm]).max()
+            vs64 = {"max": float(d.max()), "p99": float(np.percentile(d, 99)),
+                    "flux_history": float(np.abs(out["Q"] - o64["Q"]).max() /
+                                          np.abs(o64["Q"]).max())}
     return {"workload": wl["name"], "storage": precision, "components": nc, "steps": steps,
             "tensor": kind == "fiber",
             "checkpoint_every": every, "fluid_voxels": n_fluid,
@@ -423,6 +446,7 @@ def adjoint_gradient(n=96, steps=800, every=50, precision="f32", kind="rock"):
             # the adjoint's forward sweep takes every level's densities from the
             # density pass; lbm_step (fp32, two components) from its own push:
             # equal to rounding there, bitwise otherwise
+            "dL_dphi_vs_fp64": vs64,
             "flux_history_equal": bool(np.array_equal(out["Q"], q)),
             "flux_history_max_rel_diff": float(np.abs(out["Q"] - q).max() /
                                                max(np.abs(q).max(), 1e-300)),

@@ -440,17 +440,18 @@ def _fd_history2(L, wl, phi, steps):
 
 
 def test_fullsize_two_component_gradient_against_gpu_finite_differences():
-    """96^3 two-component rock (the benchmark's generator with its CSF control), fp64,
-    300 steps with residual transfers firing, squared water-flux misfit over
-    steps 100..300, checkpoints every 50: the adjoint's dL/dphi against
-    central differences of the GPU forward run, 3 gray voxels of large
-    gradient and 2 random (seed 5003).  With thousands of transfers a
-    perturbation can move one to another step (a switch the gradient does not
-    see; eps = 1e-4 does that at one of these voxels), so a voxel counts only
-    when its perturbed runs end with the base run's side flags and two step
-    sizes (1e-5, 5e-6) agree."""
+    """The benchmark's two-component gradient workload (96^3 rock with its CSF
+    control, 800 steps with residual transfers firing, squared water-flux
+    misfit over steps 200..800, checkpoints every 50), in fp64: the adjoint's
+    dL/dphi against central differences of the GPU forward run on 3 gray
+    voxels of large gradient and 20 random gray voxels (seed 5003).  With
+    thousands of transfers a perturbation can move one to another step (a
+    switch the gradient does not see), so a voxel counts only when its
+    perturbed runs end with the base run's side flags and two step sizes
+    (1e-5, 5e-6) agree; the voxels skipped for that are counted and
+    printed."""
     import paper_2512_21696_amd as L
-    wl = W.adjoint_rock2(n=96, precision="f64", steps=300, window=100)  # with its CSF control
+    wl = W.adjoint_rock2(n=96, precision="f64")  # with its CSF control
     steps = wl["steps"]
     announce(f"adjoint_rock2 96^3 fp64 {steps} steps: base run")
     q0, side0 = _fd_history2(L, wl, wl["phi"], steps)
@@ -472,11 +473,13 @@ def test_fullsize_two_component_gradient_against_gpu_finite_differences():
     rng = np.random.default_rng(5003)
     top = cand[np.argsort(np.abs(g[tuple(cand.T)]))[-60:]]
     gmax = np.abs(g).max()
+    want = {"top": 3, "random": 20}
     checked = {"top": 0, "random": 0}
+    skipped = {"top": 0, "random": 0}
     order = [("top", tuple(v)) for v in top[rng.permutation(60)]]
     order += [("random", tuple(v)) for v in cand[rng.permutation(len(cand))[:40]]]
     for kind, v in order:
-        if checked[kind] >= (3 if kind == "top" else 2):
+        if checked[kind] >= want[kind]:
             continue
         announce(f"adjoint_rock2 96^3 finite difference at {v} ({kind})")
         fds, same = [], True
@@ -491,14 +494,56 @@ def test_fullsize_two_component_gradient_against_gpu_finite_differences():
             fds.append((Ls[0] - Ls[1]) / (2 * eps))
         fd = fds[0]
         if not same or abs(fds[0] - fds[1]) > 1e-3 * abs(fd) + 1e-6 * gmax:
-            continue  # a residual transfer switched within reach
+            skipped[kind] += 1  # a residual transfer switched within reach
+            continue
         print(f"voxel {v}: adjoint {g[v]:.6e} fd {fd:.6e}")
         assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
         checked[kind] += 1
-        if checked["top"] >= 3 and checked["random"] >= 2:
+        if all(checked[k] >= want[k] for k in want):
             break
-    assert checked["top"] >= 3 and checked["random"] >= 2
+    print("checked", checked, "skipped for a switched transfer", skipped)
+    assert all(checked[k] >= want[k] for k in want), (checked, skipped)
 
+
+
+def test_fullsize_two_component_fp32_gradient_against_fp64():
+    """The benchmark's two-component gradient (96^3 rock with its CSF control,
+    800 steps, checkpoints every 50) from fp32 storage against fp64 (held to
+    finite differences above).  Besides the fp32 forward's drift and the fp32
+    reverse arithmetic, fp32 rounding can move a residual transfer to another
+    step at a voxel whose saturation passes its threshold slowly; such a
+    voxel's gradient is that of another branch.  The check is therefore on the
+    bulk of the gray voxels (the 99th percentile of the per-voxel error against
+    the largest gradient) and on how many voxels differ by more than 10 % of
+    it."""
+    import paper_2512_21696_amd as L
+    res = {}
+    for prec in ("f64", "f32"):
+        wl = W.adjoint_rock2(n=96, precision=prec)
+        steps = wl["steps"]
+        announce(f"adjoint_rock2 96^3 {prec} {steps} steps")
+        lb = L.lbm_create(wl["params"])
+        lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
+        lb.init_fluid(wl["rho_w"], wl["rho_o"])
+        start = lb.get_state()
+        q = lb.adjoint_flux(steps, np.zeros(steps), checkpoint_every=50)["Q"]
+        if prec == "f64":
+            tgt = wl["target"](q)
+        _, dLdQ = wl["loss_grad"](q, tgt)
+        lb.set_state(start)
+        res[prec] = lb.adjoint_flux(steps, dLdQ, checkpoint_every=50)
+        lb.destroy()
+    gray = wl["cls"] == 2
+    eq = norm_err(res["f32"]["Q"], res["f64"]["Q"])
+    g64, g32 = res["f64"]["dL_dphi"][gray], res["f32"]["dL_dphi"][gray]
+    gmax = np.abs(g64).max()
+    d = np.abs(g32 - g64) / gmax
+    p99, worst, far = float(np.percentile(d, 99)), float(d.max()), int(np.sum(d > 0.1))
+    print(f"fp32 vs fp64 two components: flux history {eq:.2e}, dL/dphi against the largest "
+          f"gradient: 99th percentile {p99:.2e}, max {worst:.2e}, voxels above 0.1: {far} of {d.size}")
+    assert eq < 1e-3
+    assert p99 < 1e-2
+    assert far <= 1e-3 * d.size
 
 
 @pytest.mark.parametrize("kappa", [0.0, None])
