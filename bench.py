@@ -147,6 +147,35 @@ def record_traffic(prefix, workload):
     print(json.dumps({workload: rec}))
 
 
+def fiber_permeability(n=192, steps=1000, g=1e-5):
+    """The 3 x 3 effective permeability of the fibre bundles, nu <u_i> / g_j
+    (mean over the fluid voxels) after `steps` steps from rest with the body
+    acceleration along each axis in turn: transient (not converged), fp32."""
+    import numpy as np
+    import torch
+    import workloads as W
+    import paper_2512_21696_amd as L
+    K = np.zeros((3, 3))
+    for j in range(3):
+        wf = W.fiber_bundles(n=n, precision="f32", direction=j, g=g)
+        p = wf["params"]
+        lb = L.lbm_create(p)
+        lb.set_geometry(wf["cls"], wf["phi"], wf["ptype"], wf["tables"])
+        lb.init_fluid(wf["rho_w"], wf["rho_o"])
+        lb.step(steps)
+        t = {k: torch.empty(wf["cls"].size, dtype=torch.float32, device="cuda")
+             for k in ("ux", "uy", "uz")}
+        lb.get_fields_device(t)
+        torch.cuda.synchronize()
+        lb.destroy()
+        fl = torch.from_numpy((wf["cls"] != 1).reshape(-1)).cuda()
+        nu = (p.tau[0] - 0.5) / 3.0
+        for i, k in enumerate(("ux", "uy", "uz")):
+            K[i, j] = nu * float(t[k][fl].double().mean()) / g
+    return {"steps": steps, "g": g, "note": "transient, nu <u_i> / g_j over fluid voxels",
+            "K": [[float(f"{v:.4e}") for v in row] for row in K]}
+
+
 def pc_sweep(max_edge=40, count=6):
     """The capillary-pressure half of the library: a five-level drainage sweep
     (workloads.pc_sweep_setup) of the first `count` sphere packs of
@@ -780,7 +809,8 @@ def main():
             "unit": "MLUPS", "ms_per_step": round(lf["total_ms"] / args.steps, 4),
             "kernel_ms": round(fms, 4), "bytes_per_fluid_update": round(bf, 2),
             "achieved_gbs": round(bf * nf_fl / (fms * 1e-3) / 1e9, 1),
-            "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+            "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "effective_permeability": fiber_permeability()}
     if compare:
         out["rev_library"] = rev_library()
         out["pc_sweep"] = pc_sweep()
