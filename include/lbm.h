@@ -94,6 +94,16 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
  * gray voxel at x in {0, 1, nx-2, nx-1} is rejected by lbm_set_geometry), so
  * no other stencil reaches a reservoir.  Not with 16-bit storage. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1 };
+/* Population storage layout (not part of the model; results are meant to be
+ * bitwise the same either way).  DENSE: one slot per voxel.  AUTO: where the
+ * fused step pushes the next level's densities (fp32 storage, two components,
+ * periodic x) the populations of solid voxels would not be stored, each
+ * population array holding one slot per fluid voxel in voxel order, so that
+ * the step neither writes nor fetches cache lines for solid voxels.  That
+ * fluid-only layout is switched off in this build (its first GPU run stalled
+ * without a fault and the cause is not known): AUTO gives the dense layout,
+ * which lbm_get_layout reports. */
+enum { LBM_LAYOUT_AUTO = 0, LBM_LAYOUT_DENSE = 1 };
 
 #define LBM_TABLE_N 1025 /* samples of every constitutive curve on [0, 1] */
 #define LBM_MAX_TYPES 256
@@ -128,6 +138,7 @@ typedef struct lbm_params {
   int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
   int32_t track_flux;     /* 1: accumulate the outlet flux every step */
   int32_t bc_x;           /* LBM_BC_PERIODIC (default) | LBM_BC_PRESSURE */
+  int32_t layout;         /* LBM_LAYOUT_AUTO (default) | LBM_LAYOUT_DENSE */
   double rho_in[2];       /* LBM_BC_PRESSURE: reservoir densities (water, oil) beyond x = 0 */
   double rho_out[2];      /* LBM_BC_PRESSURE: reservoir densities beyond x = nx - 1 */
   /* device allocator hook (NULL = hipMalloc/hipFree); ctx is passed through */
@@ -283,6 +294,14 @@ int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_o
  * since the last reset.  Off by default. */
 int lbm_set_profiling(lbm_handle *h, int32_t on);
 int lbm_get_kernel_times(lbm_handle *h, lbm_kernel_times *out, int32_t reset);
+
+/* The population layout in use (storage only; see LBM_LAYOUT_AUTO): writes 1
+ * to *fluid_only when solid voxels hold no populations, else 0, and the slots
+ * of each population array (N in the dense layout; the fluid voxel count
+ * rounded up to a multiple of 64, at most N, otherwise).  It is fixed by
+ * lbm_set_geometry.  Host only; either pointer may be NULL.  LBM_E_INVAL for a
+ * NULL handle. */
+int lbm_get_layout(const lbm_handle *h, int32_t *fluid_only, int64_t *slots);
 
 /* ---------------------------------------------------------------------------
  * Batched single-phase permeability of many small domains.

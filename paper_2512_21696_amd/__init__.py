@@ -26,6 +26,7 @@ STORE16 = ("f16", "bf16")
 COLL = {"regularized": 0, "bgk": 1}
 REGION = {"gray": 0, "all": 1}
 BCX = {"periodic": 0, "pressure": 1}
+LAYOUT = {"auto": 0, "dense": 1}
 TABLE_N = 1025
 
 ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -45,7 +46,7 @@ class lbm_params(ctypes.Structure):
         ("smooth_radius", ctypes.c_int32), ("outlet_x", ctypes.c_int32),
         ("eps_g", ctypes.c_double), ("eps_H", ctypes.c_double), ("delta_tie", ctypes.c_double),
         ("diag_every", ctypes.c_int32), ("track_flux", ctypes.c_int32),
-        ("bc_x", ctypes.c_int32),
+        ("bc_x", ctypes.c_int32), ("layout", ctypes.c_int32),
         ("rho_in", ctypes.c_double * 2), ("rho_out", ctypes.c_double * 2),
         ("alloc", ALLOC_FN), ("free", FREE_FN), ("alloc_ctx", ctypes.c_void_p),
         ("stream", ctypes.c_void_p),
@@ -121,7 +122,7 @@ EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_g
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
            "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
            "lbm_rev_permeability_static", "lbm_rev_pc_sweep", "lbm_adjoint_flux",
-           "lbm_last_error", "lbm_destroy"]
+           "lbm_get_layout", "lbm_last_error", "lbm_destroy"]
 
 _lib = None
 
@@ -165,6 +166,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_rev_pc_sweep": (ctypes.c_int, [P(lbm_pc_params), P(lbm_pore_table),
                                             P(lbm_rev_domain), i32, P(lbm_pc_result)]),
         "lbm_adjoint_flux": (ctypes.c_int, [vp, i64, dp, i64, dp, dp, dp]),
+        "lbm_get_layout": (ctypes.c_int, [vp, P(i32), P(i64)]),
         "lbm_last_error": (ctypes.c_char_p, [vp]),
         "lbm_destroy": (None, [vp]),
     }
@@ -204,6 +206,7 @@ def to_c_params(params) -> lbm_params:
     p.kappa = float(params.kappa)
     p.csf_region = REGION[params.csf_region]
     p.bc_x = BCX[getattr(params, "bc_x", "periodic")]
+    p.layout = LAYOUT[getattr(params, "layout", "auto")]
     for a in range(2):
         p.rho_in[a] = float(getattr(params, "rho_in", (1.0, 0.0))[a])
         p.rho_out[a] = float(getattr(params, "rho_out", (1.0, 0.0))[a])
@@ -415,6 +418,11 @@ class Lbm:
                                               q.ctypes.data_as(dp), gk.ctypes.data_as(dp),
                                               gp.ctypes.data_as(dp)))
         return {"Q": q, "dL_dK0": gk.reshape(self.shape), "dL_dphi": gp.reshape(self.shape)}
+
+    def get_layout(self) -> dict:
+        fo, sl = ctypes.c_int32(), ctypes.c_int64()
+        self._check(self.lib.lbm_get_layout(self.h, ctypes.byref(fo), ctypes.byref(sl)))
+        return {"fluid_only": bool(fo.value), "slots": int(sl.value)}
 
     def set_profiling(self, on: bool):
         self._check(self.lib.lbm_set_profiling(self.h, int(bool(on))))

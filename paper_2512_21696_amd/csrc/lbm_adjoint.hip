@@ -1624,10 +1624,10 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       Timed tm(h, K_OTHER);
       if (nc == 2)
         hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                           s.mask, s.partial);
+                           s.mask, s.partial, pop_layout<T>(h));
       else
         hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                           s.mask, s.partial);
+                           s.mask, s.partial, pop_layout<T>(h));
       hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0,
                          qh + 2 * (sg * K + k), 0);
       if (keep && nc == 2 && k < m - 1)
@@ -1747,6 +1747,16 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
     return set_err(h, LBM_E_UNSUPPORTED,
                    "adjoint_flux: periodic x faces and native storage only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
-  return h->es == 8 ? adjoint_t<double>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi)
-                    : adjoint_t<float>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi);
+  // the sweeps keep whole population sets (checkpoints, ring): dense layout
+  // for their duration
+  const bool fluid_only = h->compact;
+  int rc = fluid_only ? set_layout_t<float>(h, false) : LBM_OK;
+  if (rc != LBM_OK) return rc;
+  rc = h->es == 8 ? adjoint_t<double>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi)
+                  : adjoint_t<float>(h, nsteps, dL_dQ, checkpoint_every, Q_out, dL_dK0, dL_dphi);
+  if (fluid_only) {
+    const int rc2 = set_layout_t<float>(h, true);
+    if (rc == LBM_OK) rc = rc2;
+  }
+  return rc;
 }

@@ -66,6 +66,30 @@ struct DevState {
   T *tab;            // pore tables [type][curve][TABLE_N], curves Pc, Krw, Kro
   double *partial;   // block partials for reductions
   double *acc;       // device accumulators: q_last[2], q_acc[2]
+  // Fluid-only population layout (cs != 0): a population array holds cs
+  // slots, one per fluid voxel in voxel order.  Per x row (row = y + ny z) and
+  // 64-voxel word: cmask the fluid bits, cbase the number of fluid voxels
+  // before the word (cw words per row; entry rows * cw is the total).
+  const uint64_t *cmask;
+  const uint32_t *cbase;
+  int cw;
+  uint32_t cs;
+};
+
+// Where a voxel's populations live: slot = voxel index and array stride N
+// (dense), or the fluid-only slot (only fluid voxels have one).
+struct PopLayout {
+  const uint64_t *cm;
+  const uint32_t *cb;
+  int cw;
+  long long stride;  // elements between population arrays
+  __device__ long long slot(long long v, int nx) const {
+    if (!cm) return v;
+    const long long row = v / nx;
+    const int x = (int)(v - row * nx);
+    const long long k = row * cw + (x >> 6);
+    return (long long)cb[k] + __popcll(cm[k] & ((1ull << (x & 63)) - 1ull));
+  }
 };
 
 }  // namespace lbm

@@ -385,11 +385,13 @@ __global__ void k_axes(const double *__restrict__ ps, const uint32_t *__restrict
 template <typename T>
 __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
                           const uint32_t *__restrict__ mask, int nx, int ny, int nz, long long N,
-                          int ncomp, int open_x) {
+                          int ncomp, int open_x, const PopLayout L) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   uint32_t mk = mask[v];
   bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  if (solid && L.cm) return;  // fluid-only layout: a solid voxel has no slot
+  const long long sl = L.slot(v, nx);
   Nbr nb((int)v, nx, ny, nz);
   for (int a = 0; a < ncomp; ++a) {
 #pragma unroll
@@ -405,7 +407,7 @@ __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
         // voxel across the wrap (its reservoir population)
         val = C[(size_t)(a * Q + i) * N + rd];
       }
-      B[(size_t)(a * Q + i) * N + v] = val;
+      B[(size_t)(a * Q + i) * L.stride + sl] = val;
     }
   }
 }
@@ -414,24 +416,46 @@ __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
 template <typename T>
 __global__ void k_gather(const T *__restrict__ B, T *__restrict__ C,
                          const uint32_t *__restrict__ mask, int nx, int ny, int nz, long long N,
-                         int ncomp) {
+                         int ncomp, const PopLayout L) {
   long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   uint32_t mk = mask[v];
   bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
   Nbr nb((int)v, nx, ny, nz);
+  const long long sl = solid ? 0 : L.slot(v, nx);
   for (int a = 0; a < ncomp; ++a) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       T val = 0;
       if (!solid) {
         const int j = opp(i);
-        if ((mk >> j) & 1u) val = B[(size_t)(a * Q + j) * N + v];
-        else val = B[(size_t)(a * Q + i) * N + nb.at(-cx(i), -cy(i), -cz(i))];
+        if ((mk >> j) & 1u) val = B[(size_t)(a * Q + j) * L.stride + sl];
+        else val = B[(size_t)(a * Q + i) * L.stride + L.slot(nb.at(-cx(i), -cy(i), -cz(i)), nx)];
       }
       C[(size_t)(a * Q + i) * N + v] = val;
     }
   }
+}
+
+// Between the dense and the fluid-only population layouts (to_fluid = 1:
+// dense src into fluid-only dst; 0: fluid-only src into dense dst, zero at
+// solid voxels, as the dense step leaves them).
+template <typename T>
+__global__ void k_relayout(const T *__restrict__ src, T *__restrict__ dst,
+                           const uint32_t *__restrict__ mask, int nx, long long N, int ncomp,
+                           const PopLayout L, int to_fluid) {
+  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= N) return;
+  const bool solid = ((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  if (solid && to_fluid) return;
+  const long long sl = solid ? 0 : L.slot(v, nx);
+  for (int a = 0; a < ncomp; ++a)
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      const size_t kd = (size_t)(a * Q + i) * N + v, kf = (size_t)(a * Q + i) * L.stride + sl;
+      if (to_fluid) dst[kf] = src[kd];
+      else dst[kd] = solid ? (T)0 : src[kf];
+    }
 }
 
 template <typename T>
@@ -891,7 +915,8 @@ __global__ __launch_bounds__(256) void k_step(const ModelConsts mc, const T *__r
 // post-collision set (links with a solid end are skipped).
 template <typename T, int NC>
 __global__ void k_flux(const ModelConsts mc, const T *__restrict__ post,
-                       const uint32_t *__restrict__ mask, double *__restrict__ partial) {
+                       const uint32_t *__restrict__ mask, double *__restrict__ partial,
+                       const PopLayout L) {
   const long long N = mc.N;
   const int nyz = mc.ny * mc.nz;
   const int k = blockIdx.x * blockDim.x + threadIdx.x;
@@ -904,14 +929,15 @@ __global__ void k_flux(const ModelConsts mc, const T *__restrict__ post,
     const uint32_t m0 = mask[v0], m1 = mask[v1];
     const bool f0 = ((m0 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    const long long s0 = f0 ? L.slot(v0, mc.nx) : 0, s1 = f1 ? L.slot(v1, mc.nx) : 0;
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double q = 0.0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) q += (double)post[(size_t)(a * Q + i) * N + v0];
+        if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) q += (double)post[(size_t)(a * Q + i) * L.stride + s0];
         if (cx(i) == -1 && f1 && !((m1 >> i) & 1u))
-          q -= (double)post[(size_t)(a * Q + i) * N + v1];
+          q -= (double)post[(size_t)(a * Q + i) * L.stride + s1];
       }
       val[a] = q;
     }

@@ -46,7 +46,9 @@ struct lbm_handle {
   size_t es = 8;   // arithmetic type size
   size_t pes = 8;  // stored population size
   int sk = SK_NATIVE;
-  bool dec_valid = false;  // 16-bit runs: f[0] holds the decode of the stored set
+  // 16-bit runs: f[0] holds the decode of the stored set; fluid-only layout:
+  // f[1 - cur] holds its dense copy
+  bool dec_valid = false;
   long long N = 0;
   int cur = 0;
   int ntab = 0;
@@ -55,6 +57,9 @@ struct lbm_handle {
   // the fused step sums the next level's densities itself (fp32 arithmetic,
   // two components, periodic x), so no density pass reads the new set
   bool push = false;
+  // populations in the fluid-only layout (DevState cmask/cbase/cw/cs): set
+  // with a geometry where the push applies and the layout parameter allows it
+  bool compact = false;
   int64_t step = 0;
   DevState<double> sd{};
   DevState<float> sf{};
@@ -160,6 +165,13 @@ template <>
 DevState<float> &state<float>(lbm_handle *h) { return h->sf; }
 
 unsigned blocks(long long n) { return (unsigned)((n + 255) / 256); }
+
+template <typename T>
+PopLayout pop_layout(lbm_handle *h) {
+  const DevState<T> &s = state<T>(h);
+  if (h->compact) return PopLayout{s.cmask, s.cbase, s.cw, (long long)s.cs};
+  return PopLayout{nullptr, nullptr, 0, h->N};
+}
 
 template <typename T>
 int alloc_state(lbm_handle *h) {
@@ -309,9 +321,55 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
     pt0.assign(N, 0);
     pt_src = pt0.data();
   }
-  // smoothing weights: host staging for an asynchronous copy, alive until the
-  // stream synchronisation at the end of this function
+  // smoothing weights and the fluid-only layout's tables: host staging for
+  // asynchronous copies, alive until the stream synchronisation at the end of
+  // this function
   std::vector<double> w;
+  std::vector<uint64_t> hcm;
+  std::vector<uint32_t> hcb;
+  h->compact = false;
+  s.cmask = nullptr;
+  s.cbase = nullptr;
+  s.cw = 0;
+  s.cs = 0;
+  // The fluid-only layout is switched off: its first GPU test run stalled
+  // without a fault, and no cause has been found in its kernels or host code,
+  // so every run keeps the dense layout until one is.
+  constexpr bool kFluidOnlyEnabled = false;
+  const bool fluid_only = kFluidOnlyEnabled && h->push && h->p.layout == LBM_LAYOUT_AUTO;
+  if (fluid_only) {
+    const int nx = h->p.nx, W = (nx + 63) / 64;
+    const long long rows = (long long)h->p.ny * h->p.nz;
+    hcm.assign((size_t)rows * W, 0ull);
+    hcb.assign((size_t)rows * W + 1, 0u);
+    uint32_t cnt = 0;
+    for (long long r = 0; r < rows; ++r)
+      for (int wd = 0; wd < W; ++wd) {
+        hcb[(size_t)r * W + wd] = cnt;
+        uint64_t bits = 0ull;
+        for (int b = 0; b < 64; ++b) {
+          const int x = wd * 64 + b;
+          if (x < nx && cls[r * nx + x] != LBM_SOLID) {
+            bits |= 1ull << b;
+            ++cnt;
+          }
+        }
+        hcm[(size_t)r * W + wd] = bits;
+      }
+    hcb[(size_t)rows * W] = cnt;
+    uint64_t *cm_d = alloc_into<uint64_t>(h, h->geom_allocs, hcm.size(), &ok);
+    uint32_t *cb_d = alloc_into<uint32_t>(h, h->geom_allocs, hcb.size(), &ok);
+    if (!ok) {
+      cleanup();
+      return set_err(h, LBM_E_NOMEM, "device allocation failed in set_geometry");
+    }
+    s.cmask = cm_d;
+    s.cbase = cb_d;
+    s.cw = W;
+    // array stride: the fluid count rounded up to 64 slots (256-byte aligned
+    // arrays), within the dense allocation
+    s.cs = (uint32_t)std::min<long long>(((long long)cnt + 63) / 64 * 64, N);
+  }
   int rc = LBM_OK;
 #define CK(x, w) \
   if (rc == LBM_OK) rc = hip_check(h, (x), w)
@@ -324,6 +382,14 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
      "copy table metadata");
   CK(hipMemcpyAsync(s.tab, htabT.data(), htabT.size() * sizeof(T), hipMemcpyHostToDevice, st),
      "copy step tables");
+  if (fluid_only) {
+    CK(hipMemcpyAsync(const_cast<uint64_t *>(s.cmask), hcm.data(), hcm.size() * sizeof(uint64_t),
+                      hipMemcpyHostToDevice, st),
+       "copy fluid words");
+    CK(hipMemcpyAsync(const_cast<uint32_t *>(s.cbase), hcb.data(), hcb.size() * sizeof(uint32_t),
+                      hipMemcpyHostToDevice, st),
+       "copy fluid counts");
+  }
   if (rc == LBM_OK) {
     Timed tm(h, K_OTHER);
     hipLaunchKernelGGL(k_mask, dim3(blocks(N)), dim3(256), 0, st, cls_d, s.mask, h->p.nx, h->p.ny,
@@ -359,6 +425,7 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
   CK(hipStreamSynchronize(st), "setup");
 #undef CK
   cleanup();
+  if (rc == LBM_OK) h->compact = fluid_only;
   return rc;
 }
 
@@ -368,6 +435,17 @@ int set_geometry_t(lbm_handle *h, const uint8_t *cls, const double *phi, const u
 template <typename T>
 const T *eval_pops(lbm_handle *h) {
   DevState<T> &s = state<T>(h);
+  if (h->sk == SK_NATIVE && h->compact) {
+    // fluid-only layout: a dense copy in the other buffer, which the next step
+    // overwrites
+    if (!h->dec_valid) {
+      Timed tm(h, K_OTHER);
+      hipLaunchKernelGGL(k_relayout<T>, dim3(blocks(h->N)), dim3(256), 0, h->st, s.f[h->cur],
+                         s.f[1 - h->cur], s.mask, h->p.nx, h->N, h->p.ncomp, pop_layout<T>(h), 0);
+      h->dec_valid = true;
+    }
+    return s.f[1 - h->cur];
+  }
   if (h->sk == SK_NATIVE) return s.f[h->cur];
   if constexpr (std::is_same<T, float>::value) {
     if (!h->dec_valid) {
@@ -412,8 +490,9 @@ void ensure_density(lbm_handle *h) {
   if (h->p.ncomp == 2 && !h->rho2_valid) {
     Timed tm(h, K_AUX);
     if (h->sk == SK_NATIVE) {
+      const T *fin = eval_pops<T>(h);
       hipLaunchKernelGGL((k_density<T, 2, SK_NATIVE, false>), dim3(blocks(N)), dim3(256), 0, h->st,
-                         (const void *)s.f[h->cur], s.rho2, (const T *)nullptr,
+                         (const void *)fin, s.rho2, (const T *)nullptr,
                          (const T *)nullptr, s.mask, h->p.nx, h->p.ny, h->p.nz, N);
     } else if constexpr (std::is_same<T, float>::value) {
       // the reference sums of the last step, unless the stored set came from
@@ -480,8 +559,12 @@ void launch_tiled(lbm_handle *h, const T *fin_ = nullptr, T *fout_ = nullptr) {
   if (h->sk == SK_NATIVE) {
     const void *fin = fin_ ? fin_ : s.f[h->cur];
     void *fout = fout_ ? fout_ : s.f[1 - h->cur];
-    hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE, P>), dim3(grid), dim3(zm::NT), 0, h->st,
-                       make_kc<T>(h->mc), fin, fout, s, tx, ty, zc, nt);
+    if (P && h->compact)  // (the fluid-only layout exists only where the push applies)
+      hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE, P, P>), dim3(grid), dim3(zm::NT), 0,
+                         h->st, make_kc<T>(h->mc), fin, fout, s, tx, ty, zc, nt);
+    else
+      hipLaunchKernelGGL((k_step_zm<T, NC, REG, SK_NATIVE, P>), dim3(grid), dim3(zm::NT), 0, h->st,
+                         make_kc<T>(h->mc), fin, fout, s, tx, ty, zc, nt);
   } else if constexpr (std::is_same<T, float>::value) {
     const void *fin = s.fc[h->cur];
     void *fout = s.fc[1 - h->cur];
@@ -508,15 +591,22 @@ void launch_density_fix(lbm_handle *h) {
     const unsigned nb = blocks(h->N);
     const void *fnew = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur]
                                           : (const void *)s.fc[1 - h->cur];
-    if (h->sk == SK_NATIVE)
+    if (h->sk == SK_NATIVE && h->compact)
+      hipLaunchKernelGGL((k_density_fix<float, SK_NATIVE, true>), dim3(nb), dim3(256), 0, h->st,
+                         fnew, s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N,
+                         pop_layout<float>(h));
+    else if (h->sk == SK_NATIVE)
       hipLaunchKernelGGL((k_density_fix<float, SK_NATIVE>), dim3(nb), dim3(256), 0, h->st, fnew,
-                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N,
+                         pop_layout<float>(h));
     else if (h->sk == SK_F16)
       hipLaunchKernelGGL((k_density_fix<float, SK_F16>), dim3(nb), dim3(256), 0, h->st, fnew,
-                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N,
+                         pop_layout<float>(h));
     else
       hipLaunchKernelGGL((k_density_fix<float, SK_BF16>), dim3(nb), dim3(256), 0, h->st, fnew,
-                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N);
+                         s.rho2n, (const float *)s.rho2, s.mask, nx, ny, nz, zc, h->N,
+                         pop_layout<float>(h));
   }
 }
 
@@ -636,10 +726,10 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
       if (h->sk == SK_NATIVE) {
         if (h->p.ncomp == 2)
           hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                             s.mask, s.partial);
+                             s.mask, s.partial, pop_layout<T>(h));
         else
           hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                             s.mask, s.partial);
+                             s.mask, s.partial, pop_layout<T>(h));
       } else if constexpr (std::is_same<T, float>::value) {
         const uint16_t *c = s.fc[h->cur];
         if (h->sk == SK_F16) {
@@ -699,7 +789,8 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
       hipLaunchKernelGGL(k_equilibrium_rest<T>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d, ro_d,
                          C, s.mask, N, h->p.ncomp);
       hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, C, s.f[h->cur],
-                         s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp, h->mc.open_x);
+                         s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp, h->mc.open_x,
+                         pop_layout<T>(h));
     } else if constexpr (std::is_same<T, float>::value) {
       float *C = s.f[0];
       hipLaunchKernelGGL(k_equilibrium_rest<float>, dim3(blocks(N)), dim3(256), 0, h->st, rw_d,
@@ -785,6 +876,7 @@ int get_state_t(lbm_handle *h, void *buf) {
   // will, so the two continue bitwise alike
   h->rhoS_valid = false;
   h->rho2_valid = false;
+  h->dec_valid = false;  // the other buffer is the staging area below
   // canonical (post-streaming) order; 16-bit offsets are already relative to
   // the reader, so their gather is a plain permutation
   const void *C = h->sk == SK_NATIVE ? (const void *)s.f[1 - h->cur] : (const void *)s.fc[1 - h->cur];
@@ -792,10 +884,12 @@ int get_state_t(lbm_handle *h, void *buf) {
     Timed tm(h, K_OTHER);
     if (h->sk == SK_NATIVE)
       hipLaunchKernelGGL(k_gather<T>, dim3(blocks(N)), dim3(256), 0, h->st, s.f[h->cur],
-                         s.f[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+                         s.f[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp,
+                         pop_layout<T>(h));
     else
       hipLaunchKernelGGL(k_gather<uint16_t>, dim3(blocks(N)), dim3(256), 0, h->st, s.fc[h->cur],
-                         s.fc[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp);
+                         s.fc[1 - h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp,
+                         PopLayout{nullptr, nullptr, 0, N});
   }
   StateHeader hd{};
   hd.magic = kStateMagic;
@@ -876,22 +970,42 @@ int set_state_t(lbm_handle *h, const void *buf) {
     if (h->sk == SK_NATIVE)
       hipLaunchKernelGGL(k_scatter<T>, dim3(blocks(N)), dim3(256), 0, h->st, (const T *)C,
                          s.f[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N, h->p.ncomp,
-                         h->mc.open_x);
+                         h->mc.open_x, pop_layout<T>(h));
     else  // (open x faces need native storage)
       hipLaunchKernelGGL(k_scatter<uint16_t>, dim3(blocks(N)), dim3(256), 0, h->st,
                          (const uint16_t *)C, s.fc[h->cur], s.mask, h->p.nx, h->p.ny, h->p.nz, N,
-                         h->p.ncomp, 0);
+                         h->p.ncomp, 0, PopLayout{nullptr, nullptr, 0, N});
     rc = hip_check(h, hipGetLastError(), "scatter");
   }
   if (rc == LBM_OK) rc = hip_check(h, hipStreamSynchronize(h->st), "set_state");
+  h->dec_valid = false;  // the other buffer was the staging area
   if (rc == LBM_OK) {
     h->step = hd.step;
     h->rho_valid = false;
     h->rho2_valid = false;
     h->rhoS_valid = false;
-    h->dec_valid = false;
     h->has_fluid = true;
   }
+  return rc;
+}
+
+// The fluid-only layout off (dense) or back on, keeping the state: the
+// populations move into the other buffer, which becomes current.
+template <typename T>
+int set_layout_t(lbm_handle *h, bool fluid_only) {
+  DevState<T> &s = state<T>(h);
+  if (h->compact == fluid_only || (fluid_only && !s.cmask)) return LBM_OK;
+  int rc = LBM_OK;
+  if (h->has_fluid) {
+    const PopLayout L{s.cmask, s.cbase, s.cw, (long long)s.cs};
+    Timed tm(h, K_OTHER);
+    hipLaunchKernelGGL(k_relayout<T>, dim3(blocks(h->N)), dim3(256), 0, h->st, s.f[h->cur],
+                       s.f[1 - h->cur], s.mask, h->p.nx, h->N, h->p.ncomp, L, fluid_only ? 1 : 0);
+    rc = hip_check(h, hipGetLastError(), "relayout");
+    h->cur = 1 - h->cur;
+  }
+  h->compact = fluid_only;
+  h->dec_valid = false;
   return rc;
 }
 
@@ -1061,6 +1175,13 @@ extern "C" int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const d
     h->p.rho_in[a] = h->mc.rho_in[a] = rho_in[a];
     h->p.rho_out[a] = h->mc.rho_out[a] = rho_out[a];
   }
+  return LBM_OK;
+}
+
+extern "C" int lbm_get_layout(const lbm_handle *h, int32_t *fluid_only, int64_t *slots) {
+  if (!h) return LBM_E_INVAL;
+  if (fluid_only) *fluid_only = h->compact ? 1 : 0;
+  if (slots) *slots = h->compact ? (int64_t)h->sf.cs : (int64_t)h->N;
   return LBM_OK;
 }
 

@@ -187,7 +187,9 @@ __device__ inline int rslot(int z) { return (z + 10) % 5; }
 // Writes the 19 populations w_i (A + B.c_i + c_i^T C c_i) * sc (plus
 // keep * sc * f_i for BGK) of one component; voff is the voxel's byte offset
 // within its plane, sbase the byte offset of the plane.
-template <typename T, bool REG, bool OUTV = false>
+// SKIPZ: lanes with `zero` set store nothing (fluid-only layout: a solid
+// voxel has no slot).
+template <typename T, bool REG, bool OUTV = false, bool SKIPZ = false>
 __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sbase,
                                           uint32_t Nbytes, T A, T B0, T B1, T B2, T Cxx, T Cyy,
                                           T Czz, T Cxy, T Cxz, T Cyz, T sc, const T *fpop,
@@ -220,15 +222,24 @@ __device__ __forceinline__ void emit_post(rsrc_t out, uint32_t voff, uint32_t sb
   v[16] = w2 * (pyz - s12);
   v[17] = w2 * (myz + d12);
   v[18] = w2 * (myz - d12);
-  uint32_t so = sbase;
+  if (!SKIPZ || !zero) {
+    uint32_t so = sbase;
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    T val = v[i];
-    if (!REG) val += keep * sc * fpop[i];
-    bstore(out, voff, so, zero ? (T)0 : val);
-    if (OUTV) outv[i] = zero ? (T)0 : val;  // the value its readers will pull
-    so += Nbytes;
-    keep_scalar(so);
+    for (int i = 0; i < Q; ++i) {
+      T val = v[i];
+      if (!REG) val += keep * sc * fpop[i];
+      bstore(out, voff, so, SKIPZ ? val : (zero ? (T)0 : val));
+      so += Nbytes;
+      keep_scalar(so);
+    }
+  }
+  if (OUTV) {
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      T val = v[i];
+      if (!REG) val += keep * sc * fpop[i];
+      outv[i] = zero ? (T)0 : val;  // the value its readers will pull
+    }
   }
 }
 
@@ -354,7 +365,7 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
   out[v] = vec2<T>{r[0], r[1]};
 }
 
-template <typename T, int NC, bool REG, int SK, bool PUSH = false>
+template <typename T, int NC, bool REG, int SK, bool PUSH = false, bool CMP = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_step_zm(const KC<T> mc, const void *__restrict__ fin,
                                                  void *__restrict__ fout, const DevState<T> s,
                                                  const int tiles_x, const int tiles_y,
@@ -398,6 +409,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
   const long long N = mc.N;
   const uint32_t N32 = (uint32_t)N;
+  static_assert(!CMP || (TX == 64 && SK == SK_NATIVE), "fluid-only layout: one 64-voxel word per tile row");
+  // population array stride: every voxel, or (fluid-only layout) every fluid voxel
+  const uint32_t NSTR = CMP ? s.cs : N32;
   const uint32_t nxy = (uint32_t)nx * (uint32_t)ny;
   const int x0 = bx * TX, y0 = by * TY;
   const int zs = bzc * zc;
@@ -608,9 +622,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   rsrc_t rin[NC], rout[NC];
 #pragma unroll
   for (int a = 0; a < NC; ++a) {
-    rin[a] = make_rsrc((const char *)fin + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
-    rout[a] = make_rsrc((char *)fout + (size_t)a * Q * N * ES, (uint32_t)(Q * N * ES));
+    rin[a] = make_rsrc((const char *)fin + (size_t)a * Q * NSTR * ES, (uint32_t)(Q * NSTR * ES));
+    rout[a] = make_rsrc((char *)fout + (size_t)a * Q * NSTR * ES, (uint32_t)(Q * NSTR * ES));
   }
+
+  // Fluid-only layout: the slot of a fluid voxel is the number of fluid voxels
+  // before it.  A wave is one tile row, so the 64-voxel word of the rows
+  // (y', z') it pulls from is the tile's (bx) and every row index is
+  // wave-uniform (scalar loads); mbcnt counts the fluid voxels of the word
+  // below this lane.  row_word gives the row's first word.
+  const int tyu = __builtin_amdgcn_readfirstlane(ty);
+  auto row_word = [&](int yy, int zq) -> uint32_t {
+    return ((uint32_t)yy + (uint32_t)ny * (uint32_t)zq) * (uint32_t)s.cw;
+  };
+  // slot of x + dx (|dx| <= 1, a fluid voxel) in the row starting at word k
+  // (the tables are read-only here: constant address space, scalar loads)
+  using cu64 = __attribute__((address_space(4))) const uint64_t;
+  using cu32 = __attribute__((address_space(4))) const uint32_t;
+  cu64 *const cmask = (cu64 *)s.cmask;
+  cu32 *const cbase = (cu32 *)s.cbase;
+  auto slot_at = [&](int dx, uint32_t k) -> uint32_t {
+    const uint64_t m = cmask[k + bx];
+    const uint32_t cb = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, cbase[k + bx]));
+    if (dx == 0) return cb;
+    if (dx < 0) return x == 0 ? cbase[k + s.cw] - 1u : cb - 1u;  // (x = 0: the row's last voxel)
+    return x == nx - 1 ? cbase[k] : cb + (uint32_t)((m >> tx) & 1ull);  // (the row's first)
+  };
 
 
   // The pull of plane z+1 is issued while plane z computes, so each wave keeps
@@ -621,9 +659,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint32_t zo = (uint32_t)zz * nxy;
     const uint32_t vv = vxy + zo;
     const int zm1 = zz == 0 ? nz - 1 : zz - 1, zp1 = zz == nz - 1 ? 0 : zz + 1;
-    const uint32_t NE = N32 * ES;
+    const uint32_t NE = NSTR * ES;
     const uint32_t ZE[3] = {(uint32_t)zm1 * nxy * ES, zo * ES, (uint32_t)zp1 * nxy * ES};
-    const uint32_t vE = vv * ES;
+    const int yu = y0 + tyu;
+    const int Yr[3] = {yu == 0 ? ny - 1 : yu - 1, yu, yu == ny - 1 ? 0 : yu + 1};
+    const int Zr[3] = {zm1, zz, zp1};
+    const uint32_t vE = CMP ? slot_at(0, row_word(yu, zz)) * ES : vv * ES;
     // a solid voxel's pulls are never used: its lane loads nothing
     if (((mkz >> CLASS_SHIFT) & 3u) == SOLID_CODE) {
 #pragma unroll
@@ -642,8 +683,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 #pragma unroll
     for (int i = 1; i < Q; i += 2) {
       const int j = i + 1;
-      const uint32_t oi = ((mkz >> j) & 1u) ? vE + NE : XYE[1 - cy(i)][1 - cx(i)] + ZE[1 - cz(i)];
-      const uint32_t oj = ((mkz >> i) & 1u) ? vE : XYE[1 + cy(i)][1 + cx(i)] + ZE[1 + cz(i)] + NE;
+      uint32_t si, sj;  // source offsets of i and j
+      if constexpr (CMP) {
+        si = slot_at(-cx(i), row_word(Yr[1 - cy(i)], Zr[1 - cz(i)])) * ES;
+        sj = slot_at(cx(i), row_word(Yr[1 + cy(i)], Zr[1 + cz(i)])) * ES;
+      } else {
+        si = XYE[1 - cy(i)][1 - cx(i)] + ZE[1 - cz(i)];
+        sj = XYE[1 + cy(i)][1 + cx(i)] + ZE[1 + cz(i)];
+      }
+      const uint32_t oi = ((mkz >> j) & 1u) ? vE + NE : si;
+      const uint32_t oj = ((mkz >> i) & 1u) ? vE : sj + NE;
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         pf[a][i] = pull_raw_s<T, SK>(rin[a], oi, so);
@@ -775,8 +824,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     const uint32_t mk = M[0];
     const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
     // Solid lanes of a wave that also holds fluid voxels run along (their
-    // results are discarded) and store zeros, so that every population store
-    // of the wave writes whole cache lines instead of partial ones.
+    // results are discarded).  In the dense layout they store zeros, so that
+    // every population store of the wave writes whole cache lines instead of
+    // partial ones; in the fluid-only layout they have no slot and store
+    // nothing.
     const bool solid = cl == SOLID_CODE;
     const bool skip = all_solid(mk);
     const bool skip_next = z + 1 >= ze || all_solid(M[1]);
@@ -1087,7 +1138,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
       T pv[PUSH ? Q : 1];  // the values written (the push's input)
-      if constexpr (!S16) {
+      if constexpr (CMP) {
+        emit_post<T, REG, PUSH, true>(rout[a], slot_at(0, row_word(y0 + tyu, z)) * ES, 0u,
+                                      NSTR * ES, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy, Cxz, Cyz, sc,
+                                      f[REG ? 0 : a], keep, solid, pv);
+      } else if constexpr (!S16) {
         emit_post<T, REG, PUSH>(rout[a], vxy * ES, zoff * ES, N32 * ES, A, B0, B1, B2, Cxx, Cyy,
                                 Czz, Cxy, Cxz, Cyz, sc, f[REG ? 0 : a], keep, solid, pv);
       } else {
@@ -1154,12 +1209,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // level just left, `rref`), so that each density is the sum of the voxel's
 // next pulls.  Only voxels on a face of a tile or chunk have such links, and
 // a solid source means bounce-back, which the step summed at the voxel itself.
-template <typename T, int SK>
+// CMP: the new set is in the fluid-only layout (L); solid sources have no
+// slot and are not read.
+template <typename T, int SK, bool CMP = false>
 __global__ __launch_bounds__(256) void k_density_fix(const void *__restrict__ fnew,
                                                      T *__restrict__ rho2n,
                                                      const T *__restrict__ rref,
                                                      const uint32_t *__restrict__ mask, int nx,
-                                                     int ny, int nz, int zc, long long N) {
+                                                     int ny, int nz, int zc, long long N,
+                                                     const PopLayout L) {
   using namespace zm;
   const uint32_t v = blockIdx.x * 256u + threadIdx.x;
   if (v >= (uint32_t)N) return;
@@ -1178,6 +1236,7 @@ __global__ __launch_bounds__(256) void k_density_fix(const void *__restrict__ fn
   // before any of them is used (one memory round trip per wave).
   auto cut = [](int src, int dst, int n, int t) { return src < 0 || src >= n || src / t != dst / t; };
   const uint32_t mk = mask[v];
+  if (CMP && ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
   const vec2<T> part = reinterpret_cast<const vec2<T> *>(rho2n)[v];
   T val[Q - 1][2];
   uint32_t need = 0u;
@@ -1189,12 +1248,14 @@ __global__ __launch_bounds__(256) void k_density_fix(const void *__restrict__ fn
     val[i - 1][0] = val[i - 1][1] = (T)0;
     if (!cross) continue;
     need |= 1u << i;
+    if (CMP && ((mk >> opp(i)) & 1u)) continue;  // solid source: no slot
     const uint32_t sv = (uint32_t)(xs < 0 ? xs + nx : (xs >= nx ? xs - nx : xs)) +
                         (uint32_t)(ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys)) * (uint32_t)nx +
                         (uint32_t)(zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs)) * nxy;
+    const size_t ss = CMP ? (size_t)L.slot(sv, nx) : (size_t)sv;
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      const size_t k = (size_t)(a * Q + i) * (size_t)N + sv;
+      const size_t k = (size_t)(a * Q + i) * (size_t)(CMP ? L.stride : N) + ss;
       if constexpr (SK == SK_NATIVE) {
         val[i - 1][a] = reinterpret_cast<const T *>(fnew)[k];
       } else {

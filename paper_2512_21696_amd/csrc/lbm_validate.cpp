@@ -52,6 +52,7 @@ extern "C" void lbm_params_default(lbm_params *p) {
   p->diag_every = 0;
   p->track_flux = 1;
   p->bc_x = LBM_BC_PERIODIC;
+  p->layout = LBM_LAYOUT_AUTO;
   p->rho_in[0] = p->rho_out[0] = 1.0;
   p->rho_in[1] = p->rho_out[1] = 0.0;
 }
@@ -107,6 +108,8 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
   if (p->diag_every < 0) return fail(msg, len, LBM_E_INVAL, "diag_every must be >= 0");
   if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_PRESSURE)
     return fail(msg, len, LBM_E_INVAL, "unknown x boundary");
+  if (p->layout != LBM_LAYOUT_AUTO && p->layout != LBM_LAYOUT_DENSE)
+    return fail(msg, len, LBM_E_INVAL, "unknown population layout");
   if (p->bc_x == LBM_BC_PRESSURE) {
     if (p->precision == LBM_PREC_F16 || p->precision == LBM_PREC_BF16)
       return fail(msg, len, LBM_E_UNSUPPORTED, "pressure boundaries need F64 or F32 storage");

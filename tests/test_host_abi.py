@@ -28,6 +28,7 @@ def test_library_exports_every_declared_function():
 def test_defaults_validate():
     p = L.lbm_params_default()
     assert p.nx == 32 and p.ncomp == 2 and p.precision == 0 and p.track_flux == 1
+    assert p.layout == 0  # LBM_LAYOUT_AUTO
     assert abs(p.m_minor - 0.0029912221254390597) < 1e-18
     msg = ctypes.create_string_buffer(256)
     assert L.load_library().lbm_validate_params(ctypes.byref(p), msg, 256) == L.LBM_OK
@@ -36,7 +37,7 @@ def test_defaults_validate():
 @pytest.mark.parametrize("field,value,code", [
     ("tau", (0.5, 1.0), L.LBM_E_INVAL), ("ncomp", 3, L.LBM_E_INVAL), ("nx", 0, L.LBM_E_INVAL),
     ("precision", 7, L.LBM_E_UNSUPPORTED), ("outlet_x", 32, L.LBM_E_INVAL),
-    ("hyst", 0.5, L.LBM_E_INVAL), ("kr_min", 0.0, L.LBM_E_INVAL)])
+    ("hyst", 0.5, L.LBM_E_INVAL), ("kr_min", 0.0, L.LBM_E_INVAL), ("layout", 2, L.LBM_E_INVAL)])
 def test_invalid_params_rejected_on_host(field, value, code):
     lib = L.load_library()
     p = L.lbm_params_default()
@@ -77,6 +78,7 @@ def test_null_handle_calls_fail_cleanly():
     lib = L.load_library()
     assert lib.lbm_step(None, 1) == L.LBM_E_INVAL
     assert lib.lbm_init_fluid(None, None, None) == L.LBM_E_INVAL
+    assert lib.lbm_get_layout(None, None, None) == L.LBM_E_INVAL
     lib.lbm_destroy(None)
 
 
@@ -181,8 +183,9 @@ def test_pc_structs_match_the_header():
     import tempfile
     if shutil.which("gcc") is None:
         pytest.skip("no C compiler")
-    src = ('#include <stdio.h>\n#include "%s"\nint main(void){printf("%%zu %%zu %%zu\\n", '
-           'sizeof(lbm_params), sizeof(lbm_pc_params), sizeof(lbm_pc_result));return 0;}\n'
+    src = ('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\nint main(void){'
+           'printf("%%zu %%zu %%zu %%zu\\n", sizeof(lbm_params), sizeof(lbm_pc_params), '
+           'sizeof(lbm_pc_result), offsetof(lbm_params, layout));return 0;}\n'
            % os.path.join(ROOT, "include", "lbm.h"))
     with tempfile.TemporaryDirectory() as d:
         c, exe = os.path.join(d, "s.c"), os.path.join(d, "s")
@@ -191,4 +194,4 @@ def test_pc_structs_match_the_header():
         sizes = [int(v) for v in subprocess.run([exe], capture_output=True, text=True,
                                                  check=True).stdout.split()]
     assert sizes == [ctypes.sizeof(L.lbm_params), ctypes.sizeof(L.lbm_pc_params),
-                     ctypes.sizeof(L.lbm_pc_result)]
+                     ctypes.sizeof(L.lbm_pc_result), L.lbm_params.layout.offset]

@@ -95,6 +95,7 @@ class Params:
     bc_x: str = "periodic"          # "periodic" | "pressure" (reservoirs beyond the x faces)
     rho_in: tuple = (1.0, 0.0)      # reservoir densities (water, oil) beyond x = 0
     rho_out: tuple = (1.0, 0.0)     # reservoir densities (water, oil) beyond x = nx - 1
+    layout: str = "auto"            # population storage: "auto" (fluid-only where supported) | "dense"
 
     def filled(self) -> "Params":
         p = Params(**asdict(self))
