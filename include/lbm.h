@@ -441,7 +441,9 @@ int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_rev_domain *d
  * zero body force and no flux tracking.  Domains run one after another on
  * the model's stream, each with its own handle (device memory through the
  * hooks, freed before the next).  Errors: LBM_E_INVAL (arguments, levels,
- * buffer_out < 2, membrane < 1, buffer_in < 1), LBM_E_UNSUPPORTED (16-bit
+ * buffer_out < 2, membrane < 1, buffer_in < 1, a membrane table that
+ * lbm_set_geometry would reject; all checked before any device work),
+ * LBM_E_UNSUPPORTED (16-bit
  * storage), and whatever lbm_create and the calls it makes return; the
  * message is in lbm_last_error(NULL).  Results of the domains before a
  * failing one are written. */

@@ -13,10 +13,12 @@ SOURCES = ["lbm_runtime.hip", "lbm_validate.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
+LIBS = {"liblbm.so": ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]}
 
 
 def _compile(sources, out, verbose):
-    cmd = [HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", out + ".tmp"]
+    cmd = ([HIPCC] + FLAGS + [os.path.join(CSRC, s) for s in sources] + ["-o", out + ".tmp"] +
+           LIBS.get(os.path.basename(out), []))
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

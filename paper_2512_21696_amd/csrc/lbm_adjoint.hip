@@ -1737,6 +1737,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
 extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,
                                 int64_t checkpoint_every, double *Q_out, double *dL_dK0,
                                 double *dL_dphi) {
+  const Range range("lbm_adjoint_flux");
   if (!h) return LBM_E_INVAL;
   if (nsteps < 1 || !dL_dQ || checkpoint_every < 0)
     return set_err(h, LBM_E_INVAL, "adjoint_flux: need nsteps >= 1, dL_dQ, checkpoint_every >= 0");

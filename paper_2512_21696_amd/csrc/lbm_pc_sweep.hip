@@ -40,6 +40,9 @@ int check_args(const lbm_pc_params *p, const lbm_pore_table *tab, const lbm_rev_
   if (p->model.precision == LBM_PREC_F16 || p->model.precision == LBM_PREC_BF16)
     return fail(LBM_E_UNSUPPORTED, "the sweep's open faces need fp64 or fp32 storage");
   if (!(p->model.m_minor > 0.0)) return fail(LBM_E_INVAL, "model.m_minor must be positive");
+  char msg[256] = {0};
+  if (lbm::validate_tables(tab, 1, msg, sizeof msg) != LBM_OK)
+    return fail(LBM_E_INVAL, std::string("membrane table: ") + msg);
   for (int d = 0; d < ndom; ++d)
     if (doms[d].nx < 1 || doms[d].ny < 1 || doms[d].nz < 1 || !doms[d].cls)
       return fail(LBM_E_INVAL, "domain " + std::to_string(d) + ": empty or without classes");
@@ -162,6 +165,7 @@ int run_domain(const lbm_pc_params *p, const lbm_pore_table *tab, const lbm_rev_
 
 extern "C" int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_table,
                                 const lbm_rev_domain *doms, int32_t ndom, lbm_pc_result *out) {
+  const Range range("lbm_rev_pc_sweep");
   int rc = lbm::pc::check_args(p, membrane_table, doms, ndom, out);
   if (rc != LBM_OK) return rc;
   for (int d = 0; d < ndom; ++d) {

@@ -622,6 +622,7 @@ int dispatch(const lbm_rev_params *p, const lbm_rev_domain *doms, int32_t ndom,
 
 extern "C" int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_rev_domain *doms,
                                            int32_t ndom, lbm_rev_result *out) {
+  const Range range("lbm_rev_permeability_static");
   int rc = lbm::rev::check_args(p, doms, ndom, out);
   if (rc != LBM_OK) return rc;
   void *scr = nullptr;
@@ -632,6 +633,7 @@ extern "C" int lbm_rev_permeability_static(const lbm_rev_params *p, const lbm_re
 
 extern "C" int lbm_rev_permeability(const lbm_rev_params *p, const lbm_rev_domain *doms,
                                     int32_t ndom, lbm_rev_result *out) {
+  const Range range("lbm_rev_permeability");
   const int rc = lbm::rev::check_args(p, doms, ndom, out);
   if (rc != LBM_OK) return rc;
   return lbm::rev::dispatch(p, doms, ndom, out, nullptr, 0);

@@ -9,6 +9,8 @@
 #include <utility>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/lbm.h"
 #include "lbm_kernels.hip"
 #include "lbm_step_tiled.hip"
@@ -1041,8 +1043,18 @@ int get_setup_t(lbm_handle *h, double *K0, double *sJ, double *thw, double *tho,
 
 }  // namespace
 
+// roctx range around an entry point (setup, step, diagnostics, ...), seen by
+// rocprofv3 --marker-trace; without a tool attached it costs a call.
+struct Range {
+  explicit Range(const char *name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range &) = delete;
+  Range &operator=(const Range &) = delete;
+};
+
 // ====================================================================== ABI
 extern "C" int lbm_create(const lbm_params *p, lbm_handle **out) {
+  const Range range("lbm_create");
   if (!out) return LBM_E_INVAL;
   *out = nullptr;
   char msg[256] = {0};
@@ -1078,6 +1090,7 @@ extern "C" int lbm_create(const lbm_params *p, lbm_handle **out) {
 extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double *phi,
                                 const uint8_t *pore_type, const lbm_pore_table *tabs,
                                 int32_t ntab) {
+  const Range range("lbm_set_geometry");
   if (!h) return LBM_E_INVAL;
   char msg[256] = {0};
   int rc = validate_tables(tabs, ntab, msg, sizeof(msg));
@@ -1105,6 +1118,7 @@ extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double 
 }
 
 extern "C" int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *rho_o) {
+  const Range range("lbm_init_fluid");
   if (!h) return LBM_E_INVAL;
   if (!h->has_geom) return set_err(h, LBM_E_STATE, "lbm_set_geometry must come first");
   char msg[256] = {0};
@@ -1115,6 +1129,7 @@ extern "C" int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *
 }
 
 extern "C" int lbm_step(lbm_handle *h, int64_t n) {
+  const Range range("lbm_step");
   if (!h) return LBM_E_INVAL;
   if (n < 0) return set_err(h, LBM_E_INVAL, "n must be >= 0");
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
@@ -1122,12 +1137,14 @@ extern "C" int lbm_step(lbm_handle *h, int64_t n) {
 }
 
 extern "C" int lbm_get_fields(lbm_handle *h, const lbm_fields *out) {
+  const Range range("lbm_get_fields");
   if (!h || !out) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
   return h->p.precision == LBM_PREC_F64 ? fields_t<double>(h, out) : fields_t<float>(h, out);
 }
 
 extern "C" int lbm_get_diagnostics(lbm_handle *h, lbm_diag *out) {
+  const Range range("lbm_get_diagnostics");
   if (!h || !out) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
   return h->p.precision == LBM_PREC_F64 ? diag_t<double>(h, out) : diag_t<float>(h, out);
@@ -1148,6 +1165,7 @@ extern "C" int lbm_state_size(const lbm_handle *h, size_t *bytes) {
 }
 
 extern "C" int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
+  const Range range("lbm_get_state");
   if (!h || !host_buf) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
   if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
@@ -1156,6 +1174,7 @@ extern "C" int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
 }
 
 extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
+  const Range range("lbm_set_state");
   if (!h || !host_buf) return LBM_E_INVAL;
   if (!h->has_geom) return set_err(h, LBM_E_STATE, "lbm_set_geometry must come first");
   if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
