@@ -15,7 +15,9 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "liblbm.so")
+# LBM_LIBRARY selects another build of the library (the debug build,
+# liblbm_debug.so, with device-side index checks)
+LIB_PATH = os.environ.get("LBM_LIBRARY") or os.path.join(HERE, "liblbm.so")
 
 LBM_OK, LBM_E_INVAL, LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_STATE, LBM_E_NONFINITE, \
     LBM_E_UNSUPPORTED = 0, -1, -2, -3, -4, -5, -6

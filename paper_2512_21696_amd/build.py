@@ -6,6 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "liblbm.so")
+# the same library with the device-side index checks (-DLBM_DEBUG)
+DEBUG_LIB = os.path.join(HERE, "liblbm_debug.so")
 PROBE_LIB = os.path.join(HERE, "libhbmprobe.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
@@ -13,7 +15,8 @@ SOURCES = ["lbm_runtime.hip", "lbm_validate.cpp"]
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wno-unused-result"]
-LIBS = {"liblbm.so": ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]}
+_ROCTX = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx", "-Wl,-rpath,/opt/rocm/lib"]
+LIBS = {"liblbm.so": _ROCTX, "liblbm_debug.so": ["-DLBM_DEBUG"] + _ROCTX}
 
 
 def _compile(sources, out, verbose):
@@ -26,8 +29,9 @@ def _compile(sources, out, verbose):
 
 
 def build(verbose: bool = False) -> str:
-    """Compiles the method's library and the bandwidth yardstick library."""
+    """Compiles the method's library, its debug variant and the bandwidth yardstick library."""
     _compile(SOURCES, LIB, verbose)
+    _compile(SOURCES, DEBUG_LIB, verbose)
     _compile(["hbm_probe.hip"], PROBE_LIB, verbose)
     return LIB
 

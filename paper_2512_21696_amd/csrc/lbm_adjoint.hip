@@ -1759,5 +1759,5 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
     const int rc2 = set_layout_t<float>(h, true);
     if (rc == LBM_OK) rc = rc2;
   }
-  return rc;
+  return dcheck(h, rc);
 }

@@ -7,6 +7,31 @@
 
 namespace lbm {
 
+// Debug builds (-DLBM_DEBUG): device-side index checks.  A failed check sets
+// its site's bit in g_dcheck and the kernel goes on (no trap, so a bad index
+// never takes the GPU down); the entry points read the bits after their work
+// and fail with LBM_E_DEVICE.  Release builds compile the checks away.  The
+// sites matter most where the hardware would hide a bad index: population
+// accesses through buffer resources read 0 beyond their range.
+enum DcheckSite : unsigned {
+  DC_PULL = 0,      // fused step: a pulled population beyond its arrays
+  DC_STORE = 1,     // fused step: a stored population beyond its arrays
+  DC_VOXEL = 2,     // fused step: a per-voxel index beyond N
+  DC_DENSITY = 3,   // density pass: a pulled population beyond its arrays
+  DC_FIX = 4,       // density fix-up: a source beyond its arrays or the grid
+  DC_FLUX = 5,      // outlet flux: a population beyond its arrays
+  DC_SCATTER = 6,   // gather / scatter / relayout: an index beyond its arrays
+};
+#ifdef LBM_DEBUG
+__device__ unsigned int g_dcheck;
+#define LBM_DCHECK(cond, site)                                            \
+  do {                                                                    \
+    if (!(cond)) atomicOr(&::lbm::g_dcheck, 1u << (unsigned)(site));     \
+  } while (0)
+#else
+#define LBM_DCHECK(cond, site) ((void)0)
+#endif
+
 constexpr int Q = 19;
 constexpr int TABLE_N = 1025;
 

@@ -392,6 +392,7 @@ __global__ void k_scatter(const T *__restrict__ C, T *__restrict__ B,
   bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
   if (solid && L.cm) return;  // fluid-only layout: a solid voxel has no slot
   const long long sl = L.slot(v, nx);
+  LBM_DCHECK(sl >= 0 && sl < L.stride, DC_SCATTER);
   Nbr nb((int)v, nx, ny, nz);
   for (int a = 0; a < ncomp; ++a) {
 #pragma unroll
@@ -423,6 +424,7 @@ __global__ void k_gather(const T *__restrict__ B, T *__restrict__ C,
   bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
   Nbr nb((int)v, nx, ny, nz);
   const long long sl = solid ? 0 : L.slot(v, nx);
+  LBM_DCHECK(sl >= 0 && sl < L.stride, DC_SCATTER);
   for (int a = 0; a < ncomp; ++a) {
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
@@ -930,6 +932,7 @@ __global__ void k_flux(const ModelConsts mc, const T *__restrict__ post,
     const bool f0 = ((m0 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const long long s0 = f0 ? L.slot(v0, mc.nx) : 0, s1 = f1 ? L.slot(v1, mc.nx) : 0;
+    LBM_DCHECK(v0 < N && v1 < N && s0 < L.stride && s1 < L.stride, DC_FLUX);
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double q = 0.0;

@@ -90,6 +90,26 @@ int hip_check(lbm_handle *h, hipError_t e, const char *what) {
   return set_err(h, LBM_E_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
 }
 
+// Debug builds (-DLBM_DEBUG): after an entry point's work, the device-side
+// index checks (g_dcheck); a failed check turns rc into LBM_E_DEVICE.
+int dcheck(lbm_handle *h, int rc) {
+#ifdef LBM_DEBUG
+  unsigned int flags = 0;
+  if (hipStreamSynchronize(h->st) != hipSuccess) return rc;
+  if (hipMemcpyFromSymbol(&flags, HIP_SYMBOL(g_dcheck), sizeof flags, 0, hipMemcpyDeviceToHost) ==
+          hipSuccess &&
+      flags) {
+    const unsigned int zero = 0;
+    (void)hipMemcpyToSymbol(HIP_SYMBOL(g_dcheck), &zero, sizeof zero, 0, hipMemcpyHostToDevice);
+    char b[96];
+    std::snprintf(b, sizeof b, "debug index check failed (site bits 0x%x)", flags);
+    return set_err(h, LBM_E_DEVICE, b);
+  }
+#endif
+  (void)h;
+  return rc;
+}
+
 void *dev_alloc(lbm_handle *h, size_t bytes) {
   if (bytes == 0) bytes = 256;
   void *p = nullptr;
@@ -1109,6 +1129,7 @@ extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double 
   h->has_fluid = false;
   rc = h->p.precision == LBM_PREC_F64 ? set_geometry_t<double>(h, cls, phi, pore_type, tabs, ntab)
                                       : set_geometry_t<float>(h, cls, phi, pore_type, tabs, ntab);
+  rc = dcheck(h, rc);
   if (rc == LBM_OK) {
     h->has_geom = true;
     h->ntab = ntab;
@@ -1124,8 +1145,8 @@ extern "C" int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *
   char msg[256] = {0};
   int rc = validate_densities(h->N, h->geom_cls.data(), rho_w, rho_o, h->p.ncomp, msg, sizeof(msg));
   if (rc != LBM_OK) return set_err(h, rc, msg);
-  return h->p.precision == LBM_PREC_F64 ? init_t<double>(h, rho_w, rho_o)
-                                        : init_t<float>(h, rho_w, rho_o);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? init_t<double>(h, rho_w, rho_o)
+                                                  : init_t<float>(h, rho_w, rho_o));
 }
 
 extern "C" int lbm_step(lbm_handle *h, int64_t n) {
@@ -1133,21 +1154,22 @@ extern "C" int lbm_step(lbm_handle *h, int64_t n) {
   if (!h) return LBM_E_INVAL;
   if (n < 0) return set_err(h, LBM_E_INVAL, "n must be >= 0");
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
-  return h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n, true) : step_t<float>(h, n, true);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n, true)
+                                                  : step_t<float>(h, n, true));
 }
 
 extern "C" int lbm_get_fields(lbm_handle *h, const lbm_fields *out) {
   const Range range("lbm_get_fields");
   if (!h || !out) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
-  return h->p.precision == LBM_PREC_F64 ? fields_t<double>(h, out) : fields_t<float>(h, out);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? fields_t<double>(h, out) : fields_t<float>(h, out));
 }
 
 extern "C" int lbm_get_diagnostics(lbm_handle *h, lbm_diag *out) {
   const Range range("lbm_get_diagnostics");
   if (!h || !out) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
-  return h->p.precision == LBM_PREC_F64 ? diag_t<double>(h, out) : diag_t<float>(h, out);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? diag_t<double>(h, out) : diag_t<float>(h, out));
 }
 
 extern "C" int lbm_get_setup(lbm_handle *h, double *K0, double *sJ, double *theta_w,
@@ -1169,8 +1191,8 @@ extern "C" int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes) {
   if (!h || !host_buf) return LBM_E_INVAL;
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "no fluid state");
   if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
-  return h->p.precision == LBM_PREC_F64 ? get_state_t<double>(h, host_buf)
-                                        : get_state_t<float>(h, host_buf);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? get_state_t<double>(h, host_buf)
+                                                  : get_state_t<float>(h, host_buf));
 }
 
 extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) {
@@ -1178,8 +1200,8 @@ extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) 
   if (!h || !host_buf) return LBM_E_INVAL;
   if (!h->has_geom) return set_err(h, LBM_E_STATE, "lbm_set_geometry must come first");
   if (bytes != state_bytes(h)) return set_err(h, LBM_E_INVAL, "state buffer size mismatch");
-  return h->p.precision == LBM_PREC_F64 ? set_state_t<double>(h, host_buf)
-                                        : set_state_t<float>(h, host_buf);
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? set_state_t<double>(h, host_buf)
+                                                  : set_state_t<float>(h, host_buf));
 }
 
 extern "C" int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_out[2]) {

@@ -353,6 +353,7 @@ __global__ __launch_bounds__(256) void k_density(const void *__restrict__ fin,
       const uint32_t sj = bj ? v : X3[1 + cx(i)] + Y3[1 + cy(i)] + Z3[1 + cz(i)];
       const uint32_t oi = bi ? (uint32_t)j * N32 + v : (uint32_t)i * N32 + si;
       const uint32_t oj = bj ? (uint32_t)i * N32 + v : (uint32_t)j * N32 + sj;
+      LBM_DCHECK(si < N32 && sj < N32 && oi < Q * N32 && oj < Q * N32, DC_DENSITY);
       T pair = pull_value<T, SK>(rin, oi) + pull_value<T, SK>(rin, oj);
       // 16-bit: each offset decodes with its writer's reference density
       if constexpr (gather) pair += rhoE[2 * si + a] + rhoE[2 * sj + a];
@@ -673,6 +674,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
         for (int i = 0; i < Q; ++i) pf[a][i] = (LT)0;
       return;
     }
+    LBM_DCHECK((uint64_t)vE + ES <= (uint64_t)Q * NSTR * ES && vv < N32, DC_PULL);
 #pragma unroll
     for (int a = 0; a < NC; ++a) pf[a][0] = pull_raw_s<T, SK>(rin[a], vE, 0u);
     // pair (i, j = i + 1) of opposite directions, both addressed from the
@@ -693,6 +695,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       const uint32_t oi = ((mkz >> j) & 1u) ? vE + NE : si;
       const uint32_t oj = ((mkz >> i) & 1u) ? vE : sj + NE;
+      LBM_DCHECK((uint64_t)oi + so + ES <= (uint64_t)Q * NSTR * ES &&
+                     (uint64_t)oj + so + ES <= (uint64_t)Q * NSTR * ES,
+                 DC_PULL);
 #pragma unroll
       for (int a = 0; a < NC; ++a) {
         pf[a][i] = pull_raw_s<T, SK>(rin[a], oi, so);
@@ -821,6 +826,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
     }
     const uint32_t zoff = (uint32_t)z * nxy;
     const uint32_t v = vxy + zoff;
+    LBM_DCHECK(v < N32 && x < nx && y < ny, DC_VOXEL);
     const uint32_t mk = M[0];
     const uint32_t cl = (mk >> CLASS_SHIFT) & 3u;
     // Solid lanes of a wave that also holds fluid voxels run along (their
@@ -1138,6 +1144,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
       }
       const T sc = NC == 2 ? scale[a] : (T)1;
       T pv[PUSH ? Q : 1];  // the values written (the push's input)
+      LBM_DCHECK(CMP || (uint64_t)(vxy + zoff) * ES + (uint64_t)(Q - 1) * N32 * ES + ES <=
+                            (uint64_t)Q * N32 * ES,
+                 DC_STORE);
       if constexpr (CMP) {
         emit_post<T, REG, PUSH, true>(rout[a], slot_at(0, row_word(y0 + tyu, z)) * ES, 0u,
                                       NSTR * ES, A, B0, B1, B2, Cxx, Cyy, Czz, Cxy, Cxz, Cyz, sc,
@@ -1253,6 +1262,7 @@ __global__ __launch_bounds__(256) void k_density_fix(const void *__restrict__ fn
                         (uint32_t)(ys < 0 ? ys + ny : (ys >= ny ? ys - ny : ys)) * (uint32_t)nx +
                         (uint32_t)(zs < 0 ? zs + nz : (zs >= nz ? zs - nz : zs)) * nxy;
     const size_t ss = CMP ? (size_t)L.slot(sv, nx) : (size_t)sv;
+    LBM_DCHECK(sv < (uint32_t)N && ss < (size_t)(CMP ? L.stride : N), DC_FIX);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const size_t k = (size_t)(a * Q + i) * (size_t)(CMP ? L.stride : N) + ss;
