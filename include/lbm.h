@@ -92,8 +92,23 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
  * (zero next to a solid voxel).  Gray voxels and, with kappa != 0, the CSF
  * region must stay two voxels away from both faces (LBM_CSF_GRAY required; a
  * gray voxel at x in {0, 1, nx-2, nx-1} is rejected by lbm_set_geometry), so
- * no other stencil reaches a reservoir.  Not with 16-bit storage. */
-enum { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1 };
+ * no other stencil reaches a reservoir.  Not with 16-bit storage.
+ * DENSITY: exact density faces of the Zou-He type (the paper's pressure
+ * inlet and outlet read as boundaries that fix the density of each component
+ * on the face voxels).  The reservoir cells beyond the faces stay for the
+ * pseudo-potential sums, with the same restrictions, but the populations a
+ * face voxel pulls across the face are set so that its pulled set holds the
+ * prescribed density of each component (rho_in at x = 0, rho_out at
+ * x = nx - 1) and no momentum along y and z: with s = +1 at x = 0 and -1 at
+ * x = nx - 1 (the c_x of the unknown directions) and g_j the known pulled
+ * values (c_x = 0 or -s, bounce-back at solid sources),
+ *   s J = rho_b - sum_{c_x=0} g - 2 sum_{c_x=-s} g,
+ *   g_i = g_opp(i) + 6 w_i s J - c_y N_y - c_z N_z   (c_x(i) = s),
+ *   N_y = (1/2) sum_{c_x=0} c_y g,  N_z = (1/2) sum_{c_x=0} c_z g,
+ * i.e. the opposite value plus the difference of the equilibria at velocity
+ * (J / rho_b, 0, 0), with the transverse sums of the in-plane values removed.
+ * Needs nx >= 3.  Not with 16-bit storage. */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1, LBM_BC_DENSITY = 2 };
 /* Population storage layout (not part of the model; results are meant to be
  * bitwise the same either way).  DENSE: one slot per voxel.  AUTO: where the
  * fused step pushes the next level's densities (fp32 storage, two components,
@@ -137,10 +152,10 @@ typedef struct lbm_params {
   double delta_tie;       /* tie-break: |l2| - |l1| <= delta_tie |l3| uses the gradient */
   int32_t diag_every;     /* lbm_step checks for non-finite values every k steps (0 = never) */
   int32_t track_flux;     /* 1: accumulate the outlet flux every step */
-  int32_t bc_x;           /* LBM_BC_PERIODIC (default) | LBM_BC_PRESSURE */
+  int32_t bc_x;           /* LBM_BC_PERIODIC (default) | LBM_BC_PRESSURE | LBM_BC_DENSITY */
   int32_t layout;         /* LBM_LAYOUT_AUTO (default) | LBM_LAYOUT_DENSE */
-  double rho_in[2];       /* LBM_BC_PRESSURE: reservoir densities (water, oil) beyond x = 0 */
-  double rho_out[2];      /* LBM_BC_PRESSURE: reservoir densities beyond x = nx - 1 */
+  double rho_in[2];       /* open faces: densities (water, oil) of the inlet (x = 0) */
+  double rho_out[2];      /* open faces: densities of the outlet (x = nx - 1) */
   /* device allocator hook (NULL = hipMalloc/hipFree); ctx is passed through */
   void *(*alloc)(size_t bytes, void *ctx);
   void (*free)(void *ptr, void *ctx);
@@ -282,10 +297,10 @@ int lbm_state_size(const lbm_handle *h, size_t *bytes);
 int lbm_get_state(lbm_handle *h, void *host_buf, size_t bytes);
 int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes);
 
-/* Pressure boundaries (bc_x = LBM_BC_PRESSURE): replaces the reservoir densities
- * (water, oil) beyond x = 0 and x = nx - 1 from the next step on, as the
- * quasi-static capillary-pressure protocols of the paper's Appendix step the
- * reservoir pressures.  Enqueues nothing.  LBM_E_STATE on a handle with
+/* Open x faces (bc_x = LBM_BC_PRESSURE or LBM_BC_DENSITY): replaces the
+ * densities (water, oil) prescribed at x = 0 and x = nx - 1 from the next step
+ * on, as the quasi-static capillary-pressure protocols of the paper's Appendix
+ * step the reservoir pressures.  Enqueues nothing.  LBM_E_STATE on a handle with
  * periodic x faces; LBM_E_INVAL for a negative or non-finite density. */
 int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_out[2]);
 

@@ -49,6 +49,23 @@ are the equilibrium at its density and at the mixture velocity of the adjacent
 boundary voxel's post-collision set (0 next to a solid voxel).  Gray voxels
 and the CSF region must keep two voxels away from both faces, so the other
 stencils never reach a reservoir.
+
+Exact density faces (bc_x = "density"; the Zou-He-type density boundaries
+that the paper's protocols call for, again without equations there): the same
+reservoir cells enter the pseudo-potential sums, but the populations a
+boundary voxel pulls across a face are set so that, after streaming, its
+density of each component equals the prescribed one and its transverse
+momentum is zero.  With s the c_x of the unknown directions (+1 at x = 0, -1
+at x = nx - 1), the known pulled values g_j (c_x = 0 or -s, bounce-back at
+solid sources included) fix the normal momentum through
+    rho = sum_{c_x=0} g + 2 sum_{c_x=-s} g + s J,   J = rho u_x,
+and each unknown takes the non-equilibrium bounce-back of its opposite plus
+the equilibrium difference, with the transverse sums N_y, N_z of the c_x = 0
+values removed:
+    g_i = g_opp(i) + 6 w_i s J - c_y N_y - c_z N_z,
+    N_y = (1/2) sum_{c_x=0} c_y g,   N_z = (1/2) sum_{c_x=0} c_z g.
+(For the face's own plane these reproduce f_i - f_opp(i) = 2 w_i rho c_i.u /
+cs^2 of the equilibrium with u = (u_x, 0, 0).)  Needs nx >= 3.
 """
 from __future__ import annotations
 
@@ -83,7 +100,13 @@ class Oracle:
         self.Q_last = np.zeros(2)
         self.Q_acc = np.zeros(2)
         self.f = None
-        self.open_x = getattr(p, "bc_x", "periodic") == "pressure"
+        bc = getattr(p, "bc_x", "periodic")
+        if bc not in ("periodic", "pressure", "density"):
+            raise ValueError("bc_x must be periodic, pressure or density")
+        self.open_x = bc != "periodic"
+        self.exact_density = bc == "density"
+        if self.exact_density and self.nx < 3:
+            raise ValueError("exact density faces need nx >= 3")
 
     # ------------------------------------------------------------------ setup
     def set_geometry(self, cls, phi, ptype, tables):
@@ -358,7 +381,9 @@ class Oracle:
         if self.ncomp == 2:
             self._residual(post, ev)
         self._outlet_flux(post)
-        if self.open_x:
+        if self.exact_density:
+            self._density_faces(post)
+        elif self.open_x:
             self._reservoirs(post)
         new = np.empty_like(post)
         for a in range(self.ncomp):
@@ -419,6 +444,37 @@ class Oracle:
                     post[a, i][:, :, self.nx - 1] = feq_in[i]
                 elif C[i, 0] < 0:  # read by the voxels at x = nx - 1
                     post[a, i][:, :, 0] = feq_out[i]
+
+    def _pulled(self, post, a, j, xb):
+        """Value that the voxels of plane xb pull in direction j from post
+        (component a): post_j at x - c_j, or post_opp(j) at x when that source
+        is solid; [z, y].  Only for sources inside the box (c_x of j pointing
+        away from the face)."""
+        cx, cy, cz = (int(v) for v in C[j])
+        src = np.roll(post[a, j][:, :, xb - cx], (cz, cy), axis=(0, 1))
+        return np.where(self.src_solid[j][:, :, xb], post[a, OPP[j]][:, :, xb], src)
+
+    def _density_faces(self, post):
+        """Exact density faces: the populations the boundary voxels pull across
+        each x face, written into the slots they pull them from (the slots
+        across the periodic wrap)."""
+        p = self.p
+        for xb, s, rho_b, wrap in ((0, 1, p.rho_in, self.nx - 1), (self.nx - 1, -1, p.rho_out, 0)):
+            fl = self.fluid[:, :, xb]
+            for a in range(self.ncomp):
+                g = {j: self._pulled(post, a, j, xb) for j in range(Q) if C[j, 0] != s}
+                s0 = sum(g[j] for j in g if C[j, 0] == 0)
+                sm = sum(g[j] for j in g if C[j, 0] == -s)
+                sJ = rho_b[a] - s0 - 2.0 * sm  # s * rho u_x
+                Ny = 0.5 * sum(C[j, 1] * g[j] for j in g if C[j, 0] == 0)
+                Nz = 0.5 * sum(C[j, 2] * g[j] for j in g if C[j, 0] == 0)
+                for i in range(Q):
+                    if C[i, 0] != s:
+                        continue
+                    val = g[OPP[i]] + 6.0 * W[i] * sJ - C[i, 1] * Ny - C[i, 2] * Nz
+                    val = np.where(fl, val, 0.0)
+                    # the voxel (z, y) pulls direction i from (z - c_z, y - c_y) across the wrap
+                    post[a, i][:, :, wrap] = np.roll(val, (-int(C[i, 2]), -int(C[i, 1])), axis=(0, 1))
 
     def _outlet_flux(self, post):
         xf = int(self.p.outlet_x)

@@ -27,7 +27,7 @@ PREC = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 STORE16 = ("f16", "bf16")
 COLL = {"regularized": 0, "bgk": 1}
 REGION = {"gray": 0, "all": 1}
-BCX = {"periodic": 0, "pressure": 1}
+BCX = {"periodic": 0, "pressure": 1, "density": 2}
 LAYOUT = {"auto": 0, "dense": 1}
 TABLE_N = 1025
 

@@ -47,7 +47,8 @@ struct ModelConsts {
   int nx, ny, nz;
   long long N;
   int ncomp, collision, csf_all, tensor;
-  int open_x;        // 1: reservoirs beyond the x faces (pressure boundaries)
+  int open_x;        // 1: reservoirs beyond the x faces (pressure or density faces)
+  int exact_density; // 1: the faces fix each component's density (Zou-He type)
   double rho_in[2], rho_out[2];
   double tau[2], omega[2], nu[2];
   double G;

@@ -172,6 +172,66 @@ __global__ __launch_bounds__(256) void k_reservoirs(const ModelConsts mc, T *__r
   }
 }
 
+// Exact density faces (Zou-He type): for every fluid voxel on a face, the
+// populations it will pull across the face, chosen so that its pulled set
+// holds the prescribed density of each component and no momentum along y and
+// z.  With s = +1 at x = 0 and -1 at x = nx - 1 (the c_x of the unknown
+// directions) and g_j its known pulled values (c_x = 0 or -s; bounce-back at
+// a solid source): s J = rho_b - sum_{c_x=0} g - 2 sum_{c_x=-s} g and
+// g_i = g_opp(i) + 6 w_i s J - c_y N_y - c_z N_z with N_y, N_z half the
+// transverse sums of the c_x = 0 values.  Each value goes into the slot the
+// voxel pulls it from (across the periodic wrap).  One thread per face voxel;
+// the slots written (c_x = s arrays on the far plane) are never among the
+// values read (nx >= 3).
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_density_faces(const ModelConsts mc, T *__restrict__ post,
+                                                       const uint32_t *__restrict__ mask) {
+  const long long N = mc.N;
+  const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * ny * nz) return;
+  const int face = k / (ny * nz);
+  const int r = k - face * ny * nz;
+  const int y = r % ny, z = r / ny;
+  const int xb = face == 0 ? 0 : nx - 1, s = face == 0 ? 1 : -1, wrap = face == 0 ? nx - 1 : 0;
+  const long long vb = xb + (long long)nx * (y + (long long)ny * z);
+  const uint32_t mk = mask[vb];
+  const bool fluid = ((mk >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+  auto at = [&](int xx, int yy, int zz) -> long long {
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+    return xx + (long long)nx * (yy + (long long)ny * zz);
+  };
+  for (int a = 0; a < NC; ++a) {
+    T g[Q];
+    T s0 = 0, sm = 0, ny2 = 0, nz2 = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      g[j] = 0;
+      if (cx(j) == s) continue;
+      const T v = ((mk >> opp(j)) & 1u) ? post[(size_t)(a * Q + opp(j)) * N + vb]
+                                        : post[(size_t)(a * Q + j) * N +
+                                               at(xb - cx(j), y - cy(j), z - cz(j))];
+      g[j] = v;
+      if (cx(j) == 0) {
+        s0 += v;
+        ny2 += (T)cy(j) * v;
+        nz2 += (T)cz(j) * v;
+      } else {
+        sm += v;
+      }
+    }
+    const T Ny = (T)0.5 * ny2, Nz = (T)0.5 * nz2;
+    const T sJ = (T)(face == 0 ? mc.rho_in[a] : mc.rho_out[a]) - s0 - (T)2 * sm;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cx(i) != s) continue;
+      const T val = g[opp(i)] + (T)(6.0 * wq(i)) * sJ - (T)cy(i) * Ny - (T)cz(i) * Nz;
+      post[(size_t)(a * Q + i) * N + at(wrap, y - cy(i), z - cz(i))] = fluid ? val : (T)0;
+    }
+  }
+}
+
 // Per gray voxel (fp64): K0 = lerp(K0_tab, phi), s_J (Leverett-J, Eq. (5)),
 // residual saturations at the crossings of s_J Pc(S) with c Pc_PM.
 __device__ double crossing_s(const double *pc, double sj, double target, bool *found) {

@@ -219,7 +219,7 @@ int alloc_state(lbm_handle *h) {
   // (16-bit storage keeps the density pass: there it reads only the offsets,
   // and the push's registers cost the step more than the pass)
   h->push = std::is_same<T, float>::value && h->sk == SK_NATIVE && nc == 2 &&
-            h->p.bc_x != LBM_BC_PRESSURE;
+            h->p.bc_x == LBM_BC_PERIODIC;
   s.rho2n = h->push ? alloc_into<T>(h, L, (size_t)2 * N, &ok) : nullptr;
   s.nrm = (h->p.ncomp == 2 && h->p.kappa != 0.0) ? alloc_into<T>(h, L, (size_t)6 * N, &ok) : nullptr;
   s.mask = alloc_into<uint32_t>(h, L, (size_t)N, &ok);
@@ -252,7 +252,8 @@ ModelConsts make_consts(const lbm_params &p) {
   mc.collision = p.collision;
   mc.csf_all = p.csf_region == LBM_CSF_ALL;
   mc.tensor = p.tensor;
-  mc.open_x = p.bc_x == LBM_BC_PRESSURE;
+  mc.open_x = p.bc_x != LBM_BC_PERIODIC;
+  mc.exact_density = p.bc_x == LBM_BC_DENSITY;
   for (int a = 0; a < 2; ++a) {
     mc.rho_in[a] = p.rho_in[a];
     mc.rho_out[a] = p.rho_out[a];
@@ -711,7 +712,16 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
     ensure_density<T>(h);
     launch_step<T, MODE_STEP, T>(h, FieldsOut{}, push);
     h->cur = 1 - h->cur;
-    if (h->mc.open_x) {
+    if (h->mc.exact_density) {
+      Timed tm(h, K_OTHER);
+      const unsigned fb2 = blocks(2LL * h->p.ny * h->p.nz);
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL((k_density_faces<T, 2>), dim3(fb2), dim3(256), 0, h->st, h->mc,
+                           s.f[h->cur], s.mask);
+      else
+        hipLaunchKernelGGL((k_density_faces<T, 1>), dim3(fb2), dim3(256), 0, h->st, h->mc,
+                           s.f[h->cur], s.mask);
+    } else if (h->mc.open_x) {
       Timed tm(h, K_OTHER);
       if (h->p.ncomp == 2)
         hipLaunchKernelGGL((k_reservoirs<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
@@ -1116,8 +1126,8 @@ extern "C" int lbm_set_geometry(lbm_handle *h, const uint8_t *cls, const double 
   int rc = validate_tables(tabs, ntab, msg, sizeof(msg));
   if (rc == LBM_OK) rc = validate_geometry(h->N, cls, phi, pore_type, ntab, msg, sizeof(msg));
   if (rc != LBM_OK) return set_err(h, rc, msg);
-  if (h->p.bc_x == LBM_BC_PRESSURE) {
-    // reservoirs: no gray voxel within two voxels of either x face
+  if (h->p.bc_x != LBM_BC_PERIODIC) {
+    // open faces: no gray voxel within two voxels of either x face
     const int nx = h->p.nx;
     for (long long r = 0; r < (long long)h->p.ny * h->p.nz; ++r)
       for (int x : {0, 1, nx - 2, nx - 1})
@@ -1206,7 +1216,7 @@ extern "C" int lbm_set_state(lbm_handle *h, const void *host_buf, size_t bytes) 
 
 extern "C" int lbm_set_reservoirs(lbm_handle *h, const double rho_in[2], const double rho_out[2]) {
   if (!h || !rho_in || !rho_out) return LBM_E_INVAL;
-  if (h->p.bc_x != LBM_BC_PRESSURE)
+  if (h->p.bc_x == LBM_BC_PERIODIC)
     return set_err(h, LBM_E_STATE, "set_reservoirs: the x faces are periodic");
   for (int a = 0; a < 2; ++a)
     if (!(rho_in[a] >= 0) || !(rho_out[a] >= 0) || !std::isfinite(rho_in[a]) ||

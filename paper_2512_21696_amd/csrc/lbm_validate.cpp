@@ -106,17 +106,19 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
       return fail(msg, len, LBM_E_INVAL, "tensor thresholds must be >= 0");
   }
   if (p->diag_every < 0) return fail(msg, len, LBM_E_INVAL, "diag_every must be >= 0");
-  if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_PRESSURE)
+  if (p->bc_x != LBM_BC_PERIODIC && p->bc_x != LBM_BC_PRESSURE && p->bc_x != LBM_BC_DENSITY)
     return fail(msg, len, LBM_E_INVAL, "unknown x boundary");
+  if (p->bc_x == LBM_BC_DENSITY && p->nx < 3)
+    return fail(msg, len, LBM_E_INVAL, "density faces need nx >= 3");
   if (p->layout != LBM_LAYOUT_AUTO && p->layout != LBM_LAYOUT_DENSE)
     return fail(msg, len, LBM_E_INVAL, "unknown population layout");
-  if (p->bc_x == LBM_BC_PRESSURE) {
+  if (p->bc_x != LBM_BC_PERIODIC) {
     if (p->precision == LBM_PREC_F16 || p->precision == LBM_PREC_BF16)
-      return fail(msg, len, LBM_E_UNSUPPORTED, "pressure boundaries need F64 or F32 storage");
+      return fail(msg, len, LBM_E_UNSUPPORTED, "open x faces need F64 or F32 storage");
     if (p->outlet_x > p->nx - 2)
-      return fail(msg, len, LBM_E_INVAL, "with pressure boundaries outlet_x must be <= nx - 2");
+      return fail(msg, len, LBM_E_INVAL, "with open x faces outlet_x must be <= nx - 2");
     if (p->kappa != 0.0 && p->csf_region != LBM_CSF_GRAY)
-      return fail(msg, len, LBM_E_INVAL, "pressure boundaries need the CSF region in gray voxels");
+      return fail(msg, len, LBM_E_INVAL, "open x faces need the CSF region in gray voxels");
     for (int a = 0; a < 2; ++a)
       if (!(p->rho_in[a] >= 0) || !(p->rho_out[a] >= 0) || !std::isfinite(p->rho_in[a]) ||
           !std::isfinite(p->rho_out[a]))

@@ -1,8 +1,10 @@
-"""Open x faces (reservoirs beyond x = 0 and x = nx - 1) on the GPU against the
-fp64 oracle, through the C ABI: a two-component displacement with a water
-reservoir at the inlet and an oil reservoir at the outlet through a ragged box
-with solid grains, gray voxels and CSF, and a single-phase pressure-driven
-slit.  Tolerances as in test_gpu_parity: fp64 1e-12 of each field's largest
+"""Open x faces on the GPU against the fp64 oracle, through the C ABI, for
+both kinds: reservoirs beyond x = 0 and x = nx - 1 (pressure) and exact
+density faces of the Zou-He type (density): a two-component displacement with
+water entering at the inlet and oil at the outlet through a ragged box with
+solid grains, gray voxels and CSF, a single-phase pressure-driven slit, and a
+change of the prescribed densities between steps.  On density faces the
+reported densities of the face voxels equal the prescribed ones.  Tolerances as in test_gpu_parity: fp64 1e-12 of each field's largest
 value; fp32 rounding (6e-8) of O(1) densities accumulated over 60 steps stays
 below 1e-4 of each field's scale."""
 import numpy as np
@@ -14,7 +16,7 @@ from gpu_common import announce, gpu_run, oracle_run, field_errors, diag_errors
 pytestmark = pytest.mark.gpu
 
 
-def displacement(precision="f64"):
+def displacement(precision="f64", bc="pressure"):
     m = W.minority_density(3.0)
     nx, ny, nz = 21, 10, 9
     rng = np.random.default_rng(71)
@@ -26,7 +28,7 @@ def displacement(precision="f64"):
     K0 = W.kozeny_carman_table(2.0)
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, precision=precision, tau=(1.0, 1.2),
-                 kappa=-0.05, bc_x="pressure", rho_in=(1.02, m), rho_out=(m, 0.99)).filled()
+                 kappa=-0.05, bc_x=bc, rho_in=(1.02, m), rho_out=(m, 0.99)).filled()
     x = np.arange(nx)[None, None, :]
     prof = 0.5 * (1 - np.tanh((x - 3.0) / 1.5)) * np.ones(cls.shape)
     rw = m + (1 - m) * prof
@@ -34,14 +36,15 @@ def displacement(precision="f64"):
                 rho_w=rw, rho_o=1 + m - rw)
 
 
+@pytest.mark.parametrize("bc", ["pressure", "density"])
 @pytest.mark.parametrize("prec,tol", [("f64", 1e-12), ("f32", 1e-4)])
-def test_open_faces_displacement_matches_oracle(prec, tol):
-    wl = displacement()
+def test_open_faces_displacement_matches_oracle(prec, tol, bc):
+    wl = displacement(bc=bc)
     steps = 60
-    announce(f"open x faces displacement {prec}, {steps} steps")
+    announce(f"open x faces ({bc}) displacement {prec}, {steps} steps")
     lb = gpu_run(wl, steps, prec)
     got, dg = lb.get_fields(), lb.get_diagnostics()
-    wl64 = displacement()
+    wl64 = displacement(bc=bc)
     o = oracle_run(wl64, steps)
     ref = o.fields()
     names = ("rho_w", "rho_o", "ux", "uy", "uz", "S") + (("r_w", "r_o") if prec == "f64" else ())
@@ -51,19 +54,25 @@ def test_open_faces_displacement_matches_oracle(prec, tol):
     print(prec, "diag errors", {k: f"{v:.2e}" for k, v in de.items()})
     for k, v in fe.items():
         assert v < tol, (k, v)
+    if bc == "density":
+        fl = wl["cls"] != 1
+        for k, xb, val in (("rho_w", 0, 1.02), ("rho_o", -1, 0.99)):
+            err = np.abs(np.asarray(got[k])[:, :, xb][fl[:, :, xb]] - val).max()
+            assert err < (1e-13 if prec == "f64" else 1e-6), (k, err)
     lb.destroy()
 
 
-def test_open_faces_single_phase_slit_matches_oracle():
+@pytest.mark.parametrize("bc", ["pressure", "density"])
+def test_open_faces_single_phase_slit_matches_oracle(bc):
     H, L = 6, 12
-    p = W.Params(nx=L, ny=H + 2, nz=3, ncomp=1, tau=(1.0, 1.0), G=0.0, bc_x="pressure",
+    p = W.Params(nx=L, ny=H + 2, nz=3, ncomp=1, tau=(1.0, 1.0), G=0.0, bc_x=bc,
                  rho_in=(1.003, 0.0), rho_out=(0.997, 0.0)).filled()
     cls = np.zeros((3, H + 2, L), np.uint8)
     cls[:, 0, :] = 1
     cls[:, H + 1, :] = 1
     wl = dict(params=p, cls=cls, phi=np.ones(cls.shape), ptype=np.zeros(cls.shape, np.uint8),
               tables=[], rho_w=np.ones(cls.shape), rho_o=None)
-    announce("open x faces single-phase slit fp64, 300 steps")
+    announce(f"open x faces ({bc}) single-phase slit fp64, 300 steps")
     lb = gpu_run(wl, 300, "f64")
     got = lb.get_fields()
     o = oracle_run(wl, 300)
@@ -96,20 +105,21 @@ def test_open_faces_reject_gray_next_to_a_face_and_16bit():
     assert e.value.code == L.LBM_E_UNSUPPORTED
 
 
-def test_reservoir_step_matches_oracle():
+@pytest.mark.parametrize("bc", ["pressure", "density"])
+def test_reservoir_step_matches_oracle(bc):
     """lbm_set_reservoirs between steps (a pressure step of a quasi-static
     protocol) against the oracle with the same change."""
     import copy
-    wl = displacement()
-    announce("open x faces: reservoir densities stepped after 30 steps, fp64")
+    wl = displacement(bc=bc)
+    announce(f"open x faces ({bc}): densities stepped after 30 steps, fp64")
     lb = gpu_run(wl, 30, "f64")
     m = wl["params"].m_minor
     new_in, new_out = (1.05, m), (m, 0.98)
     lb.set_reservoirs(new_in, new_out)
     lb.step(30)
     got = lb.get_fields()
-    p = copy.deepcopy(displacement()["params"])
-    wl64 = displacement()
+    p = copy.deepcopy(displacement(bc=bc)["params"])
+    wl64 = displacement(bc=bc)
     wl64["params"] = p
     o = oracle_run(wl64, 30)
     p.rho_in, p.rho_out = new_in, new_out

@@ -92,7 +92,7 @@ class Params:
     delta_tie: float = 0.05
     outlet_x: int = -1              # -1: nx - 1 (periodic) or nx - 2 (pressure boundaries)
     diag_every: int = 0
-    bc_x: str = "periodic"          # "periodic" | "pressure" (reservoirs beyond the x faces)
+    bc_x: str = "periodic"          # "periodic" | "pressure" (reservoirs) | "density" (exact density faces)
     rho_in: tuple = (1.0, 0.0)      # reservoir densities (water, oil) beyond x = 0
     rho_out: tuple = (1.0, 0.0)     # reservoir densities (water, oil) beyond x = nx - 1
     layout: str = "auto"            # population storage: "auto" (fluid-only where supported) | "dense"
@@ -110,7 +110,7 @@ class Params:
         if p.eps_n == 0.0:
             p.eps_n = 1e-12 if p.precision == "f64" else 1e-7
         if p.outlet_x < 0:
-            p.outlet_x = p.nx - 2 if p.bc_x == "pressure" else p.nx - 1
+            p.outlet_x = p.nx - 2 if p.bc_x != "periodic" else p.nx - 1
         p.tau = tuple(float(t) for t in p.tau)
         p.rho_in = tuple(float(v) for v in p.rho_in)
         p.rho_out = tuple(float(v) for v in p.rho_out)
