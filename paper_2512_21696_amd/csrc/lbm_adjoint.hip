@@ -40,6 +40,16 @@
 namespace lbm {
 namespace adj {
 
+// XCD-aware voxel order of the stencil kernels: the chip hands consecutive
+// blocks to its 8 XCDs in turn, so a plain linear order spreads the
+// neighbouring planes of a voxel over all of them and each XCD's L2 re-fetches
+// the neighbours' values.  Remapped, each XCD takes one contiguous run of
+// voxels.  The grid must be a multiple of 8 blocks (blocks8).
+__device__ inline long long xcd_voxel() {
+  const long long per = gridDim.x / 8;
+  return ((long long)(blockIdx.x % 8) * per + blockIdx.x / 8) * blockDim.x + threadIdx.x;
+}
+
 // The adjoint populations are stored in the state's type (fp64 or fp32); the
 // arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.  One thread
 // per voxel; the grid is a multiple of 8 blocks and block b takes the voxel
@@ -930,7 +940,7 @@ __global__ __launch_bounds__(256) void k_adj_normals(const ModelConsts mc,
                                                      const uint32_t *__restrict__ mask,
                                                      T *__restrict__ nrmb) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = xcd_voxel();
   if (v >= N) return;
   const uint32_t mk = mask[v];
   if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
@@ -971,7 +981,7 @@ __global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
                                                      const uint32_t *__restrict__ mask,
                                                      T *__restrict__ inb) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = xcd_voxel();
   if (v >= N) return;
   const uint32_t mk = mask[v];
   if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
@@ -1024,7 +1034,7 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
                                                          const uint32_t *__restrict__ mask,
                                                          T *__restrict__ stash) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = xcd_voxel();
   if (v >= N) return;
   const uint32_t mk = mask[v];
   if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
@@ -1073,7 +1083,7 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
                                                  const uint32_t *__restrict__ mask,
                                                  T *__restrict__ rnl) {
   const long long N = mc.N;
-  const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const long long v = xcd_voxel();
   if (v >= N) return;
   if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;  // stays zero
   const uint32_t mk = mask[v];
@@ -1388,6 +1398,9 @@ struct Rev2 {
   double *gsj, *lr, *gth;
 };
 
+// blocks of 256 for n threads, rounded up to a multiple of 8 (xcd_voxel)
+unsigned blocks8(long long n) { return (blocks(n) + 7) / 8 * 8; }
+
 template <typename T, bool REG, bool TENS>
 void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk,
                         double a, const Rev2<T> &b) {
@@ -1430,9 +1443,9 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
   {
     Timed tm(h, K_AUX);
     if (h->p.kappa != 0.0)
-      hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks(h->N)), dim3(256), 0, h->st,
+      hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
                          h->mc, (const T *)b.dens, s.mask, b.nrmb);
-    hipLaunchKernelGGL((adj::k_adj_inputs2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
+    hipLaunchKernelGGL((adj::k_adj_inputs2<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st, h->mc,
                        (const T *)b.dens, (const T *)b.nrmb, s.mask, b.inb);
   }
   Timed tm(h, K_ADJ);
@@ -1444,9 +1457,9 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
     else launch_adj_step2_t<T, false, false>(h, post, lin, lout, gk, a, b);
   }
   if (h->p.kappa != 0.0)
-    hipLaunchKernelGGL((adj::k_adj_normals_rev<T>), dim3(blocks(h->N)), dim3(256), 0, h->st,
+    hipLaunchKernelGGL((adj::k_adj_normals_rev<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
                        h->mc, (const T *)b.nrmb, s.mask, b.stash);
-  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks(h->N)), dim3(256), 0, h->st, h->mc,
+  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st, h->mc,
                      (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
 }
 
