@@ -16,9 +16,9 @@ from gpu_common import announce, gpu_run, oracle_run, field_errors, diag_errors
 pytestmark = pytest.mark.gpu
 
 
-def displacement(precision="f64", bc="pressure"):
+def displacement(precision="f64", bc="pressure", shape=(9, 10, 21)):
     m = W.minority_density(3.0)
-    nx, ny, nz = 21, 10, 9
+    nz, ny, nx = shape
     rng = np.random.default_rng(71)
     cls = np.zeros((nz, ny, nx), np.uint8)
     core = (slice(None), slice(None), slice(4, nx - 4))
@@ -59,6 +59,22 @@ def test_open_faces_displacement_matches_oracle(prec, tol, bc):
         for k, xb, val in (("rho_w", 0, 1.02), ("rho_o", -1, 0.99)):
             err = np.abs(np.asarray(got[k])[:, :, xb][fl[:, :, xb]] - val).max()
             assert err < (1e-13 if prec == "f64" else 1e-6), (k, err)
+    lb.destroy()
+
+
+@pytest.mark.parametrize("bc", ["pressure", "density"])
+def test_open_faces_2d_displacement_matches_oracle(bc):
+    """nz = 1: a two-dimensional displacement (the paper's 2-D protocols run on
+    one plane) through grains and gray voxels, fp64."""
+    wl = displacement(bc=bc, shape=(1, 24, 40))
+    steps = 80
+    announce(f"open x faces ({bc}) 2-D displacement 40x24x1 fp64, {steps} steps")
+    lb = gpu_run(wl, steps, "f64")
+    got = lb.get_fields()
+    o = oracle_run(displacement(bc=bc, shape=(1, 24, 40)), steps)
+    fe = field_errors(got, o.fields(), ("rho_w", "rho_o", "ux", "uy", "S"))
+    print("2-D field errors", {k: f"{v:.2e}" for k, v in fe.items()})
+    assert max(fe.values()) < 1e-12
     lb.destroy()
 
 
