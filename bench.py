@@ -811,6 +811,34 @@ def main():
             "achieved_gbs": round(bf * nf_fl / (fms * 1e-3) / 1e9, 1),
             "frac": round(bf * nf_fl / (fms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
             "effective_permeability": fiber_permeability()}
+        # the same rock between exact density faces (open x faces: no density
+        # push, so the step takes the density pass): water enters at x = 0
+        # against oil held at x = nx - 1
+        wo = W.multiscale_rock(n=args.n, precision="f32")
+        po = wo["params"]
+        m = po.m_minor
+        po.bc_x = "density"
+        po.outlet_x = args.n - 2
+        po.rho_in, po.rho_out = (1.0 + 0.02, m), (m, 1.0)
+        for a_ in ("cls", "phi", "ptype"):
+            wo[a_] = wo[a_].copy()
+        wo["cls"][:, :, -2:] = 0          # no gray (or grain) voxel on the outlet planes
+        wo["phi"][:, :, -2:] = 1.0
+        lo = run_leg("f32", False, wl=wo)
+        ko = lo["kt"]
+        oms = ko["step_ms"] / max(ko["step_launches"], 1)
+        no_fl = int(np.sum(wo["cls"] != 1))
+        bo = algorithmic_bytes(2, 4, int(np.sum(wo["cls"] == 2)) / no_fl, False)
+        out["open_faces"] = {
+            "workload": wo["name"] + "_density_faces", "bc_x": "density", "storage": "f32",
+            "rho_in": list(po.rho_in), "rho_out": list(po.rho_out), "fluid_voxels": no_fl,
+            "value": round(no_fl * args.steps / (lo["total_ms"] * 1e-3) / 1e6, 2),
+            "unit": "MLUPS", "ms_per_step": round(lo["total_ms"] / args.steps, 4),
+            "kernel_ms": round(oms, 4), "aux_ms_per_step": round(ko["aux_ms"] / args.steps, 4),
+            "bytes_per_fluid_update": round(bo, 2),
+            "frac": round(bo * no_fl / (oms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+            "diagnostics": {k: lo["diag"][k] for k in ("mass_w", "mass_o", "q_acc_w", "q_acc_o",
+                                                       "max_u", "nonfinite")}}
     if compare:
         out["rev_library"] = rev_library()
         out["pc_sweep"] = pc_sweep()

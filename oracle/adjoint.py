@@ -1,7 +1,8 @@
 """Reference gradients of the outlet-flux history with respect to the gray
 porosity, for the one-component model (pore, gray and solid voxels, scalar
 K0(phi) or the tensorial resistivity of Eqs. (6)-(7), regularised or BGK
-collision, trapezoidal resistance, body force).  TEST
+collision, trapezoidal resistance, body force; periodic x faces or, for one
+component, exact density faces as in model.Oracle).  TEST
 INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline).
 
 The step is the one of model.Oracle with one component, and the tensor set-up
@@ -177,6 +178,19 @@ class OneComponent:
         self.g = [float(v) for v in p.g[0]]
         self.tensor = bool(getattr(p, "tensor", False))
         self.src_solid = [_sh(self.solid, C[i], -1) for i in range(Q)]
+        self.faces = getattr(p, "bc_x", "periodic") == "density"
+        if getattr(p, "bc_x", "periodic") == "pressure":
+            raise ValueError("the reference gradient takes periodic or exact density faces")
+        if self.faces:
+            # a pull across an x face reads the slot the face step wrote, never
+            # bounce-back
+            nx = self.shape[2]
+            for i in range(Q):
+                if C[i, 0] != 0:
+                    xs = 0 if C[i, 0] > 0 else nx - 1
+                    m = self.src_solid[i].clone()
+                    m[:, :, xs] = False
+                    self.src_solid[i] = m
         fl = self.fluid.numpy()
         xf = int(p.outlet_x)
         x1 = (xf + 1) % self.shape[2]
@@ -231,9 +245,43 @@ class OneComponent:
         post = _collide(f, rho, up, ua, F, self.tau, p.collision, self.gray)
         post = torch.where(fl, post, torch.zeros_like(post))
         Qn = (self.flux_w * post).sum()
+        if self.faces:
+            post = self._density_faces(post)
         new = torch.stack([torch.where(self.src_solid[i], post[OPP[i]], _sh(post[i], C[i], -1))
                            for i in range(Q)])
         return torch.where(fl, new, torch.zeros_like(new)), Qn
+
+    def _density_faces(self, post):
+        """Exact density faces (model.Oracle._density_faces, one component):
+        the populations the face voxels pull across each x face, written into
+        the slots they pull them from."""
+        p = self.p
+        nx = self.shape[2]
+        slots = [post[i] for i in range(Q)]
+        for xb, s, rho_b, wrap in ((0, 1, p.rho_in[0], nx - 1), (nx - 1, -1, p.rho_out[0], 0)):
+            fl = self.fluid[:, :, xb]
+            g = {}
+            for j in range(Q):
+                if C[j, 0] == s:
+                    continue
+                cx, cy, cz = (int(v) for v in C[j])
+                src = torch.roll(post[j][:, :, xb - cx], (cz, cy), dims=(0, 1))
+                g[j] = torch.where(self.src_solid[j][:, :, xb], post[OPP[j]][:, :, xb], src)
+            s0 = sum(g[j] for j in g if C[j, 0] == 0)
+            sm = sum(g[j] for j in g if C[j, 0] == -s)
+            sJ = rho_b - s0 - 2.0 * sm
+            Ny = 0.5 * sum(C[j, 1] * g[j] for j in g if C[j, 0] == 0)
+            Nz = 0.5 * sum(C[j, 2] * g[j] for j in g if C[j, 0] == 0)
+            for i in range(Q):
+                if C[i, 0] != s:
+                    continue
+                val = g[OPP[i]] + 6.0 * W[i] * sJ - C[i, 1] * Ny - C[i, 2] * Nz
+                val = torch.where(fl, val, torch.zeros_like(val))
+                val = torch.roll(val, (-int(C[i, 2]), -int(C[i, 1])), dims=(0, 1))
+                plane = [slots[i][:, :, x] for x in range(nx)]
+                plane[wrap] = val
+                slots[i] = torch.stack(plane, dim=-1)
+        return torch.stack(slots)
 
 
 def flux_gradient(params, cls, phi, ptype, tables, f0, steps, dL_dQ):
@@ -272,6 +320,8 @@ class TwoComponent(OneComponent):
 
     def __init__(self, params, cls, ptype, tables, r):
         super().__init__(params, cls, ptype, tables)
+        if self.faces:
+            raise ValueError("the two-component reference gradient takes periodic x faces")
         p = params
         self.region = torch.as_tensor(self.cls == GRAY) if p.csf_region == "gray" else self.fluid
         self.taus = [float(t) for t in p.tau]

@@ -50,6 +50,51 @@ __device__ inline long long xcd_voxel() {
   return ((long long)(blockIdx.x % 8) * per + blockIdx.x / 8) * blockDim.x + threadIdx.x;
 }
 
+// Exact density faces, one component: the transpose of the face step on the
+// adjoint of the next level (indexed like the pulled values: lam[i][w] is
+// dL/d of the value w pulls in direction i).  A face voxel's unknown pulls
+// g_i (c_x(i) = s) are linear in its known pulls g_j of the same level,
+//   dg_i/dg_j = [j = opp(i)] - 6 w_i - (c_y(i) c_y(j) + c_z(i) c_z(j)) / 2  (c_x(j) = 0)
+//             = [j = opp(i)] - 12 w_i                                       (c_x(j) = -s),
+// so each lam[i][v] moves onto the knowns' entries, and the unknowns' entries
+// become zero (the post-collision values the periodic pull would have brought
+// across the face are overwritten).  One thread per face voxel; it touches
+// only its own entries.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_density_faces(const ModelConsts mc,
+                                                           T *__restrict__ lam,
+                                                           const uint32_t *__restrict__ mask) {
+  const long long N = mc.N;
+  const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * ny * nz) return;
+  const int face = k / (ny * nz);
+  const int r = k - face * ny * nz;
+  const int y = r % ny, z = r / ny;
+  const int xb = face == 0 ? 0 : nx - 1, s = face == 0 ? 1 : -1;
+  const long long v = xb + (long long)nx * (y + (long long)ny * z);
+  if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  double l[Q];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) l[i] = (double)lam[(size_t)i * N + v];
+#pragma unroll
+  for (int i = 0; i < Q; ++i) {
+    if (cx(i) != s) continue;
+    const double li = l[i];
+    l[i] = 0.0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      if (cx(j) == s) continue;
+      double c = j == opp(i) ? 1.0 : 0.0;
+      if (cx(j) == 0) c -= 6.0 * wq(i) + 0.5 * (double)(cy(i) * cy(j) + cz(i) * cz(j));
+      else c -= 12.0 * wq(i);
+      l[j] += c * li;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < Q; ++i) lam[(size_t)i * N + v] = (T)l[i];
+}
+
 // The adjoint populations are stored in the state's type (fp64 or fp32); the
 // arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.  One thread
 // per voxel; the grid is a multiple of 8 blocks and block b takes the voxel
@@ -1425,6 +1470,9 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
   const bool ten = h->p.tensor != 0;
   if (h->p.ncomp == 1) {
     Timed tm(h, K_ADJ);
+    if (h->mc.exact_density)
+      hipLaunchKernelGGL((adj::k_adj_density_faces<T>), dim3(blocks(2LL * h->p.ny * h->p.nz)),
+                         dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), s.mask);
     if (ten) {
       if (reg) launch_adj_step_t<T, true, true>(h, post, lin, lout, gk, a);
       else launch_adj_step_t<T, false, true>(h, post, lin, lout, gk, a);
@@ -1496,6 +1544,9 @@ void launch_recompute(lbm_handle *h, const T *fin, T *fout, T *rout = nullptr,
   Timed tm(h, K_STEP);
   if (reg) launch_tiled<T, 1, true>(h, fin, fout);
   else launch_tiled<T, 1, false>(h, fin, fout);
+  if (h->mc.exact_density)  // the face populations, as the step applies them
+    hipLaunchKernelGGL((k_density_faces<T, 1>), dim3(blocks(2LL * h->p.ny * h->p.nz)), dim3(256), 0,
+                       h->st, h->mc, fout, s.mask);
 }
 
 // dL/dK^-1 (tensor runs) back to dL/dK0 and to the porosity through the
@@ -1757,9 +1808,10 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
   for (int64_t k = 0; k < nsteps; ++k)
     if (!std::isfinite(dL_dQ[k]))
       return set_err(h, LBM_E_INVAL, "adjoint_flux: non-finite dL_dQ");
-  if (h->mc.open_x || h->sk != SK_NATIVE)
+  if ((h->mc.open_x && !(h->mc.exact_density && h->p.ncomp == 1)) || h->sk != SK_NATIVE)
     return set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: periodic x faces and native storage only");
+                   "adjoint_flux: periodic x faces (or exact density faces with one "
+                   "component) and native storage only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
   // the sweeps keep whole population sets (checkpoints, ring): dense layout
   // for their duration

@@ -137,7 +137,8 @@ def test_adjoint_rejects_unsupported_runs():
         lb.adjoint_flux(3, np.ones(3), checkpoint_every=-1)
     assert ei.value.code == L.LBM_E_INVAL
     lb.destroy()
-    # open x faces (pressure reservoirs) have no adjoint
+    # open x faces with reservoirs have no adjoint (exact density faces with
+    # one component do)
     p = W.Params(nx=16, ny=6, nz=4, ncomp=1, tau=(0.8, 0.8), G=0.0, kappa=0.0,
                  bc_x="pressure", rho_in=(1.01, 0.0), rho_out=(1.0, 0.0)).filled()
     shape = (4, 6, 16)
@@ -150,6 +151,49 @@ def test_adjoint_rejects_unsupported_runs():
         lb.adjoint_flux(2, np.ones(2))
     assert ei.value.code == L.LBM_E_UNSUPPORTED
     lb.destroy()
+
+
+def faces_case(precision="f64", seed=23):
+    """One component between exact density faces (70 x 9 x 6, ragged x tile): a
+    gray band x = 20..49 with solid grains, no body force; the flow is driven by
+    the faces' densities, so the gradient reaches the gray voxels only through
+    the face step."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 6, 9, 70
+    r = rng.random((nz, ny, nx))
+    cls = np.zeros((nz, ny, nx), np.uint8)
+    band = (slice(None), slice(None), slice(20, 50))
+    cls[band] = np.where(r[band] < 0.6, 2, np.where(r[band] > 0.92, 1, 0))
+    phi = np.where(cls == 2, rng.uniform(0.05, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
+    pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
+    K0 = W.kozeny_carman_table(2.0)
+    tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
+            for lam in (1.0, 2.0)]
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, precision=precision,
+                 kappa=0.0, bc_x="density", rho_in=(1.01, 0.0), rho_out=(0.99, 0.0),
+                 outlet_x=60).filled()
+    rho = 1.0 + 0.01 * rng.standard_normal(cls.shape)
+    return dict(params=p, cls=cls, phi=phi, ptype=pt, tables=tabs, rho=rho)
+
+
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-4)])
+def test_adjoint_with_density_faces_matches_oracle(precision, tol):
+    """Exact density faces with one component: the reverse sweep runs the
+    transpose of the face step on the adjoint of every level."""
+    announce(f"adjoint with density faces 70x9x6 {precision}, 40 steps, checkpoints every 15")
+    c = faces_case(precision)
+    steps = 40
+    a = np.linspace(1.0, 2.0, steps)
+    qo, go = oracle_gradient(faces_case("f64"), steps, a)
+    lb = gpu_handle(c)
+    out = lb.adjoint_flux(steps, a, checkpoint_every=15)
+    lb.destroy()
+    gray = c["cls"] == 2
+    assert np.count_nonzero(go[gray]) > 0.25 * gray.sum()
+    assert np.abs(out["Q"] - qo).max() < (1e-13 if precision == "f64" else 1e-5)
+    e = norm_err(out["dL_dphi"], go)
+    print(f"{precision} dL/dphi normalised error {e:.2e}")
+    assert e < tol
 
 
 def test_autograd_function_matches_oracle():

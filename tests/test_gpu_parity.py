@@ -171,6 +171,25 @@ def test_checkpoint_resume_bitwise():
     b.destroy()
 
 
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_two_runs_are_bitwise_equal(prec):
+    """Determinism: two runs of the droplet slab from the same input, on fresh
+    handles, end in the same state bit for bit, diagnostics included (every
+    reduction has a fixed order, and an LDS race in the fused step would show
+    up as a run-to-run difference).  fp32 takes the step with the density
+    push and its fix-up."""
+    import paper_2512_21696_amd as L
+    announce(f"determinism: droplet_slab {prec}, 50 steps twice")
+    out = []
+    for _ in range(2):
+        wl = W.droplet_slab()
+        lb = gpu_run(wl, 50, prec)
+        out.append((lb.get_state(), lb.get_diagnostics()))
+        lb.destroy()
+    assert out[0][0] == out[1][0], "runs differ"
+    assert out[0][1] == out[1][1]
+
+
 def test_poiseuille_bgk_exact_on_gpu():
     import math
     tau = 0.5 + math.sqrt(3) / 4

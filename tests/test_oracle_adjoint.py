@@ -310,3 +310,64 @@ def test_two_component_with_residual_events(kappa, region):
         if checked == 3:
             break
     assert checked == 3
+
+
+def faces_case(seed=11):
+    """One component between exact density faces: a gray slab (x = 4..6) with
+    solid grains, no body force, the flow driven by rho_in > rho_out."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 4, 6, 11
+    cls = np.zeros((nz, ny, nx), np.uint8)
+    r = rng.random((nz, ny, nx))
+    cls[:, :, 4:7] = np.where(r[:, :, 4:7] < 0.7, 2, 0)
+    cls[:, :, 2:9] = np.where(r[:, :, 2:9] > 0.9, 1, cls[:, :, 2:9])
+    phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
+    K0 = W.kozeny_carman_table(2.0)
+    tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, bc_x="density",
+                 rho_in=(1.01, 0.0), rho_out=(0.99, 0.0), outlet_x=7).filled()
+    return p, cls, phi, np.zeros(cls.shape, np.uint8), tabs
+
+
+def test_torch_forward_with_density_faces_equals_oracle():
+    p, cls, phi, pt, tabs = faces_case()
+    f0, qs, fN = oracle_history(p, cls, phi, pt, tabs, 15)
+    hist, _, f_t = A.flux_gradient(p, cls, phi, pt, tabs, f0, 15, np.ones(15))
+    assert np.abs(hist - qs).max() < 1e-14
+    assert np.abs(f_t - fN).max() < 1e-14
+
+
+def test_gradient_with_density_faces_matches_oracle_finite_differences():
+    p, cls, phi, pt, tabs = faces_case()
+    steps = 12
+    a = np.linspace(1.0, 2.0, steps)
+    f0, _, _ = oracle_history(p, cls, phi, pt, tabs, 1)
+    _, grad, _ = A.flux_gradient(p, cls, phi, pt, tabs, f0, steps, a)
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(3)
+    eps = 1e-4
+    checked = 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue
+        Ls = []
+        for s in (1, -1):
+            ph = phi.copy()
+            ph[v] += s * eps
+            _, qs, _ = oracle_history(p, cls, ph, pt, tabs, steps)
+            Ls.append(float((a * qs).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        assert abs(grad[v] - fd) < 2e-5 * abs(fd) + 1e-12, (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
+
+
+def test_reference_gradient_rejects_reservoir_faces():
+    p, cls, phi, pt, tabs = faces_case()
+    p.bc_x = "pressure"
+    with pytest.raises(ValueError):
+        A.OneComponent(p, cls, pt, tabs)
