@@ -500,9 +500,9 @@ int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_tabl
  * s_J(phi) (Eq. (5)).  Calibrating phi (or the tables) against an observed flux
  * needs dL/dphi.  For one or two components (with the CSF control of Eq. (4)
  * and the residual transfer; scalar K0 or tensor = 1; periodic x faces, or
- * exact density faces (LBM_BC_DENSITY) with one component, whose face step is
- * linear in the face voxels' known pulls and is reversed by its transpose;
- * native fp64 or fp32 storage) and a loss
+ * exact density faces (LBM_BC_DENSITY), whose face step is linear in the face
+ * voxels' known pulls and is reversed by its transpose; native fp64 or fp32
+ * storage) and a loss
  * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
  * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
  * first component's post-collision populations of step n crossing
@@ -553,8 +553,7 @@ int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_tabl
  * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
  * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
- * fluid state), LBM_E_UNSUPPORTED (reservoir x faces, density faces with two
- * components, 16-bit storage),
+ * fluid state), LBM_E_UNSUPPORTED (reservoir x faces, 16-bit storage),
  * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,

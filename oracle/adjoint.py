@@ -1,8 +1,8 @@
 """Reference gradients of the outlet-flux history with respect to the gray
 porosity, for the one-component model (pore, gray and solid voxels, scalar
 K0(phi) or the tensorial resistivity of Eqs. (6)-(7), regularised or BGK
-collision, trapezoidal resistance, body force; periodic x faces or, for one
-component, exact density faces as in model.Oracle).  TEST
+collision, trapezoidal resistance, body force; periodic x faces or exact
+density faces as in model.Oracle).  TEST
 INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline).
 
 The step is the one of model.Oracle with one component, and the tensor set-up
@@ -246,19 +246,19 @@ class OneComponent:
         post = torch.where(fl, post, torch.zeros_like(post))
         Qn = (self.flux_w * post).sum()
         if self.faces:
-            post = self._density_faces(post)
+            post = self._density_faces(post, 0)
         new = torch.stack([torch.where(self.src_solid[i], post[OPP[i]], _sh(post[i], C[i], -1))
                            for i in range(Q)])
         return torch.where(fl, new, torch.zeros_like(new)), Qn
 
-    def _density_faces(self, post):
-        """Exact density faces (model.Oracle._density_faces, one component):
+    def _density_faces(self, post, a):
+        """Exact density faces (model.Oracle._density_faces) for component a:
         the populations the face voxels pull across each x face, written into
         the slots they pull them from."""
         p = self.p
         nx = self.shape[2]
         slots = [post[i] for i in range(Q)]
-        for xb, s, rho_b, wrap in ((0, 1, p.rho_in[0], nx - 1), (nx - 1, -1, p.rho_out[0], 0)):
+        for xb, s, rho_b, wrap in ((0, 1, p.rho_in[a], nx - 1), (nx - 1, -1, p.rho_out[a], 0)):
             fl = self.fluid[:, :, xb]
             g = {}
             for j in range(Q):
@@ -320,14 +320,24 @@ class TwoComponent(OneComponent):
 
     def __init__(self, params, cls, ptype, tables, r):
         super().__init__(params, cls, ptype, tables)
-        if self.faces:
-            raise ValueError("the two-component reference gradient takes periodic x faces")
         p = params
         self.region = torch.as_tensor(self.cls == GRAY) if p.csf_region == "gray" else self.fluid
         self.taus = [float(t) for t in p.tau]
         self.gs = [[float(v) for v in p.g[a]] for a in range(2)]
         self.r = torch.as_tensor(np.asarray(r, np.float64))
         self.nb_solid = [_sh(self.solid, C[i]) for i in range(Q)]
+        # density faces: a neighbour across an x face is the reservoir cell
+        # (fluid, at the face's prescribed density), as in model.Oracle
+        self.cross_nb = [None] * Q
+        if self.faces:
+            nx = self.shape[2]
+            for i in range(1, Q):
+                if C[i, 0] != 0:
+                    xb = nx - 1 if C[i, 0] > 0 else 0
+                    m = torch.zeros(self.shape, dtype=torch.bool)
+                    m[:, :, xb] = True
+                    self.cross_nb[i] = m
+                    self.nb_solid[i] = self.nb_solid[i] & ~m
 
     def sJ(self, phi, K0):
         out = torch.zeros(self.shape, dtype=torch.float64)
@@ -419,6 +429,9 @@ class TwoComponent(OneComponent):
             acc = [0.0, 0.0, 0.0]
             for i in range(1, Q):
                 psi = torch.where(self.nb_solid[i], wall, _sh(rho[b], C[i]))
+                if self.cross_nb[i] is not None:
+                    ghost = p.rho_out[b] if C[i, 0] > 0 else p.rho_in[b]
+                    psi = torch.where(self.cross_nb[i], torch.full_like(psi, ghost), psi)
                 for d in range(3):
                     if C[i, d]:
                         acc[d] = acc[d] + W[i] * C[i, d] * psi
@@ -517,6 +530,8 @@ class TwoComponent(OneComponent):
             side = torch.where(to_w, torch.ones_like(side), torch.where(to_o, torch.zeros_like(side),
                                                                         side))
         Qn = (self.flux_w * posts[0]).sum()
+        if self.faces:
+            posts = [self._density_faces(posts[a], a) for a in range(2)]
         new = []
         for a in range(2):
             na = torch.stack([torch.where(self.src_solid[i], posts[a][OPP[i]],

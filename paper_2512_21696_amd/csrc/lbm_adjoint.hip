@@ -50,19 +50,23 @@ __device__ inline long long xcd_voxel() {
   return ((long long)(blockIdx.x % 8) * per + blockIdx.x / 8) * blockDim.x + threadIdx.x;
 }
 
-// Exact density faces, one component: the transpose of the face step on the
-// adjoint of the next level (indexed like the pulled values: lam[i][w] is
-// dL/d of the value w pulls in direction i).  A face voxel's unknown pulls
+// Exact density faces: the transpose of the face step on the adjoint of the
+// next level (indexed like the pulled values: lam[a][i][w] is dL/d of the
+// value w pulls in direction i, component a).  A face voxel's unknown pulls
 // g_i (c_x(i) = s) are linear in its known pulls g_j of the same level,
 //   dg_i/dg_j = [j = opp(i)] - 6 w_i - (c_y(i) c_y(j) + c_z(i) c_z(j)) / 2  (c_x(j) = 0)
 //             = [j = opp(i)] - 12 w_i                                       (c_x(j) = -s),
 // so each lam[i][v] moves onto the knowns' entries, and the unknowns' entries
 // become zero (the post-collision values the periodic pull would have brought
-// across the face are overwritten).  One thread per face voxel; it touches
-// only its own entries.
+// across the face are overwritten).  Two components: the density of a fluid
+// face voxel is the prescribed one whatever the level's values (the sum of
+// its pulls' derivatives vanishes), so the adjoint of the next level's density
+// there (rnl, added to every pull of the voxel by the reverse step) is zeroed.
+// One thread per face voxel; it touches only its own entries.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_density_faces(const ModelConsts mc,
                                                            T *__restrict__ lam,
+                                                           T *__restrict__ rnl,
                                                            const uint32_t *__restrict__ mask) {
   const long long N = mc.N;
   const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
@@ -74,25 +78,29 @@ __global__ __launch_bounds__(256) void k_adj_density_faces(const ModelConsts mc,
   const int xb = face == 0 ? 0 : nx - 1, s = face == 0 ? 1 : -1;
   const long long v = xb + (long long)nx * (y + (long long)ny * z);
   if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
-  double l[Q];
+  for (int a = 0; a < mc.ncomp; ++a) {
+    T *const la = lam + (size_t)a * Q * N;
+    double l[Q];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) l[i] = (double)lam[(size_t)i * N + v];
+    for (int i = 0; i < Q; ++i) l[i] = (double)la[(size_t)i * N + v];
 #pragma unroll
-  for (int i = 0; i < Q; ++i) {
-    if (cx(i) != s) continue;
-    const double li = l[i];
-    l[i] = 0.0;
+    for (int i = 0; i < Q; ++i) {
+      if (cx(i) != s) continue;
+      const double li = l[i];
+      l[i] = 0.0;
 #pragma unroll
-    for (int j = 0; j < Q; ++j) {
-      if (cx(j) == s) continue;
-      double c = j == opp(i) ? 1.0 : 0.0;
-      if (cx(j) == 0) c -= 6.0 * wq(i) + 0.5 * (double)(cy(i) * cy(j) + cz(i) * cz(j));
-      else c -= 12.0 * wq(i);
-      l[j] += c * li;
+      for (int j = 0; j < Q; ++j) {
+        if (cx(j) == s) continue;
+        double c = j == opp(i) ? 1.0 : 0.0;
+        if (cx(j) == 0) c -= 6.0 * wq(i) + 0.5 * (double)(cy(i) * cy(j) + cz(i) * cz(j));
+        else c -= 12.0 * wq(i);
+        l[j] += c * li;
+      }
     }
-  }
 #pragma unroll
-  for (int i = 0; i < Q; ++i) lam[(size_t)i * N + v] = (T)l[i];
+    for (int i = 0; i < Q; ++i) la[(size_t)i * N + v] = (T)l[i];
+    if (rnl) rnl[2 * v + a] = (T)0;
+  }
 }
 
 // The adjoint populations are stored in the state's type (fp64 or fp32); the
@@ -1036,7 +1044,13 @@ __global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
   for (int i = 1; i < Q; ++i) {
     const bool wall = (mk >> i) & 1u;
     const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
-    const double rw = (double)rho2[2 * y], ro = (double)rho2[2 * y + 1];
+    double rw = (double)rho2[2 * y], ro = (double)rho2[2 * y + 1];
+    // open x faces: a neighbour beyond a face is the reservoir cell at the
+    // face's prescribed densities (as in the forward step)
+    if (mc.open_x && cx(i) != 0 && (nb.x + cx(i) < 0 || nb.x + cx(i) >= mc.nx)) {
+      rw = cx(i) > 0 ? mc.rho_out[0] : mc.rho_in[0];
+      ro = cx(i) > 0 ? mc.rho_out[1] : mc.rho_in[1];
+    }
     const double f = wall ? 0.0 : 1.0;
     const double sh = f * (rw / (rw + ro) - mc.s_min) * mc.inv_span;
     const int c[3] = {cx(i), cy(i), cz(i)};
@@ -1137,6 +1151,8 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
   double r0 = 0, r1 = 0, shb = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
+    // open x faces: the voxel x - c_i across a face read a reservoir cell, not x
+    if (mc.open_x && cx(i) != 0 && (nb.x - cx(i) < 0 || nb.x - cx(i) >= mc.nx)) continue;
     const size_t x = (size_t)nb.at(-cx(i), -cy(i), -cz(i));
     auto dot = [&](int c0, size_t at) {
       double s = 0;
@@ -1472,7 +1488,7 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
     Timed tm(h, K_ADJ);
     if (h->mc.exact_density)
       hipLaunchKernelGGL((adj::k_adj_density_faces<T>), dim3(blocks(2LL * h->p.ny * h->p.nz)),
-                         dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), s.mask);
+                         dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), (T *)nullptr, s.mask);
     if (ten) {
       if (reg) launch_adj_step_t<T, true, true>(h, post, lin, lout, gk, a);
       else launch_adj_step_t<T, false, true>(h, post, lin, lout, gk, a);
@@ -1481,6 +1497,11 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
       else launch_adj_step_t<T, false, false>(h, post, lin, lout, gk, a);
     }
     return;
+  }
+  if (h->mc.exact_density) {
+    Timed tm(h, K_ADJ);
+    hipLaunchKernelGGL((adj::k_adj_density_faces<T>), dim3(blocks(2LL * h->p.ny * h->p.nz)),
+                       dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), b.rnl_in, s.mask);
   }
   {
     Timed tm(h, K_AUX);
@@ -1539,6 +1560,9 @@ void launch_recompute(lbm_handle *h, const T *fin, T *fout, T *rout = nullptr,
     }
     s.r = r_own;
     s.side = s_own;
+    if (h->mc.exact_density)
+      hipLaunchKernelGGL((k_density_faces<T, 2>), dim3(blocks(2LL * h->p.ny * h->p.nz)), dim3(256),
+                         0, h->st, h->mc, fout, s.mask);
     return;
   }
   Timed tm(h, K_STEP);
@@ -1808,10 +1832,9 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
   for (int64_t k = 0; k < nsteps; ++k)
     if (!std::isfinite(dL_dQ[k]))
       return set_err(h, LBM_E_INVAL, "adjoint_flux: non-finite dL_dQ");
-  if ((h->mc.open_x && !(h->mc.exact_density && h->p.ncomp == 1)) || h->sk != SK_NATIVE)
+  if ((h->mc.open_x && !h->mc.exact_density) || h->sk != SK_NATIVE)
     return set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: periodic x faces (or exact density faces with one "
-                   "component) and native storage only");
+                   "adjoint_flux: periodic x faces or exact density faces, and native storage only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
   // the sweeps keep whole population sets (checkpoints, ring): dense layout
   // for their duration

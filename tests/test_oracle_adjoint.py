@@ -371,3 +371,67 @@ def test_reference_gradient_rejects_reservoir_faces():
     p.bc_x = "pressure"
     with pytest.raises(ValueError):
         A.OneComponent(p, cls, pt, tabs)
+
+
+def two_faces_case(seed=13):
+    """Two components between exact density faces (22 x 8 x 6): water enters at
+    x = 0 (rho_in = (1.02, m)) against oil held at x = nx - 1 (rho_out =
+    (m, 1.0)); grains and gray voxels (two pore types) keep two planes away
+    from both faces; no body force, kappa = 0."""
+    rng = np.random.default_rng(seed)
+    nz, ny, nx = 6, 8, 22
+    r = rng.random((nz, ny, nx))
+    cls = np.where(r < 0.15, 1, np.where(r < 0.5, 2, 0)).astype(np.uint8)
+    cls[:, :, :2] = 0
+    cls[:, :, -2:] = 0
+    phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
+    pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
+    K0 = W.kozeny_carman_table(2.0)
+    tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
+            for lam in (1.0, 2.0)]
+    m = W.minority_density(3.0)
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
+                 bc_x="density", rho_in=(1.02, m), rho_out=(m, 1.0), outlet_x=12).filled()
+    x = np.arange(nx)[None, None, :]
+    noise = 0.005 * rng.random(cls.shape)
+    rw = np.where(x < 6, 1.0 - noise, m + noise)
+    return p, cls, phi, pt, tabs, rw, 1.0 + m - rw
+
+
+def test_two_component_forward_with_density_faces_equals_oracle():
+    p, cls, phi, pt, tabs, rw, ro = two_faces_case()
+    f0, r0, q, fN, events = _two_history(p, cls, phi, pt, tabs, rw, ro, 10)
+    assert events == 0
+    hist, _, f_t = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r0, 10, np.ones(10))
+    assert np.abs(hist - q).max() < 1e-14
+    assert np.abs(f_t - fN).max() < 1e-14
+
+
+def test_two_component_gradient_with_density_faces_matches_finite_differences():
+    p, cls, phi, pt, tabs, rw, ro = two_faces_case()
+    steps = 10
+    a = np.linspace(1.0, 2.0, steps)
+    f0, r0, _, _, _ = _two_history(p, cls, phi, pt, tabs, rw, ro, 1)
+    _, grad, _ = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r0, steps, a)
+    gray = np.argwhere(cls == 2)
+    rng = np.random.default_rng(5)
+    eps = 1e-4
+    checked = 0
+    for k in rng.permutation(len(gray)):
+        v = tuple(gray[k])
+        t = phi[v] * 1024
+        if min(t - np.floor(t), np.ceil(t) - t) < 0.2:
+            continue
+        Ls = []
+        for s in (1, -1):
+            ph = phi.copy()
+            ph[v] += s * eps
+            _, _, q, _, ev = _two_history(p, cls, ph, pt, tabs, rw, ro, steps)
+            assert ev == 0
+            Ls.append(float((a * q).sum()))
+        fd = (Ls[0] - Ls[1]) / (2 * eps)
+        assert abs(grad[v] - fd) < 1e-4 * abs(fd) + 1e-12, (v, grad[v], fd)
+        checked += 1
+        if checked == 3:
+            break
+    assert checked == 3
