@@ -92,7 +92,9 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
  * (zero next to a solid voxel).  Gray voxels and, with kappa != 0, the CSF
  * region must stay two voxels away from both faces (LBM_CSF_GRAY required; a
  * gray voxel at x in {0, 1, nx-2, nx-1} is rejected by lbm_set_geometry), so
- * no other stencil reaches a reservoir.  Not with 16-bit storage.
+ * no other stencil reaches a reservoir.  With 16-bit storage the populations
+ * written across a face are offsets against their slot owner's reference,
+ * like every other slot.
  * DENSITY: exact density faces of the Zou-He type (the paper's pressure
  * inlet and outlet read as boundaries that fix the density of each component
  * on the face voxels).  The reservoir cells beyond the faces stay for the
@@ -107,7 +109,7 @@ enum { LBM_CSF_GRAY = 0, LBM_CSF_ALL = 1 };
  *   N_y = (1/2) sum_{c_x=0} c_y g,  N_z = (1/2) sum_{c_x=0} c_z g,
  * i.e. the opposite value plus the difference of the equilibria at velocity
  * (J / rho_b, 0, 0), with the transverse sums of the in-plane values removed.
- * Needs nx >= 3.  Not with 16-bit storage. */
+ * Needs nx >= 3. */
 enum { LBM_BC_PERIODIC = 0, LBM_BC_PRESSURE = 1, LBM_BC_DENSITY = 2 };
 /* Population storage layout (not part of the model; results are meant to be
  * bitwise the same either way).  DENSE: one slot per voxel.  AUTO: where the

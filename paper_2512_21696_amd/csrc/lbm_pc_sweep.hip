@@ -38,7 +38,7 @@ int check_args(const lbm_pc_params *p, const lbm_pore_table *tab, const lbm_rev_
     return fail(LBM_E_INVAL, "need check_every >= 1 and max_steps >= check_every");
   if (!(p->tol >= 0.0)) return fail(LBM_E_INVAL, "tol must be non-negative");
   if (p->model.precision == LBM_PREC_F16 || p->model.precision == LBM_PREC_BF16)
-    return fail(LBM_E_UNSUPPORTED, "the sweep's open faces need fp64 or fp32 storage");
+    return fail(LBM_E_UNSUPPORTED, "the capillary-pressure sweep runs in fp64 or fp32 storage");
   if (!(p->model.m_minor > 0.0)) return fail(LBM_E_INVAL, "model.m_minor must be positive");
   char msg[256] = {0};
   if (lbm::validate_tables(tab, 1, msg, sizeof msg) != LBM_OK)

@@ -476,11 +476,11 @@ const T *eval_pops(lbm_handle *h) {
       if (h->sk == SK_F16)
         hipLaunchKernelGGL(k_decode<SK_F16>, dim3(blocks(h->N)), dim3(256), 0, h->st,
                            s.fc[h->cur], s.rhoE, s.mask, s.f[0], h->p.nx, h->p.ny, h->p.nz, h->N,
-                           h->p.ncomp);
+                           h->p.ncomp, h->mc.open_x);
       else
         hipLaunchKernelGGL(k_decode<SK_BF16>, dim3(blocks(h->N)), dim3(256), 0, h->st,
                            s.fc[h->cur], s.rhoE, s.mask, s.f[0], h->p.nx, h->p.ny, h->p.nz, h->N,
-                           h->p.ncomp);
+                           h->p.ncomp, h->mc.open_x);
       h->dec_valid = true;
     }
   }
@@ -700,6 +700,32 @@ int diag_t(lbm_handle *h, lbm_diag *out) {
   return LBM_OK;
 }
 
+// Open x faces with 16-bit storage, after a step (before the references
+// rotate): the face values encoded against their slots' owners, whose
+// references are the densities of the level just left (rho2), and, with two
+// components, the face voxels' reference sums corrected to those owners.
+void open_faces16(lbm_handle *h) {
+  DevState<float> &s = h->sf;
+  Timed tm(h, K_OTHER);
+  uint16_t *c = s.fc[h->cur];
+  const float *refs = h->p.ncomp == 2 ? s.rho2 : nullptr;
+  const unsigned fb = blocks((long long)h->p.ny * h->p.nz), fb2 = blocks(2LL * h->p.ny * h->p.nz);
+  const bool f16 = h->sk == SK_F16, two = h->p.ncomp == 2;
+  if (h->mc.exact_density) {
+    if (f16 && two) hipLaunchKernelGGL((k_density_faces16<SK_F16, 2>), dim3(fb2), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else if (f16) hipLaunchKernelGGL((k_density_faces16<SK_F16, 1>), dim3(fb2), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else if (two) hipLaunchKernelGGL((k_density_faces16<SK_BF16, 2>), dim3(fb2), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else hipLaunchKernelGGL((k_density_faces16<SK_BF16, 1>), dim3(fb2), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+  } else {
+    if (f16 && two) hipLaunchKernelGGL((k_reservoirs16<SK_F16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else if (f16) hipLaunchKernelGGL((k_reservoirs16<SK_F16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else if (two) hipLaunchKernelGGL((k_reservoirs16<SK_BF16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+    else hipLaunchKernelGGL((k_reservoirs16<SK_BF16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c, refs, s.mask);
+  }
+  if (two)
+    hipLaunchKernelGGL(k_rhoS_faces, dim3(fb2), dim3(256), 0, h->st, h->mc, s.rhoS, refs, s.mask);
+}
+
 // allow_push = false keeps the density pass on every step (the adjoint's
 // forward sweep, whose recomputations take the densities from it).
 template <typename T>
@@ -712,7 +738,9 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
     ensure_density<T>(h);
     launch_step<T, MODE_STEP, T>(h, FieldsOut{}, push);
     h->cur = 1 - h->cur;
-    if (h->mc.exact_density) {
+    if (h->mc.open_x && h->sk != SK_NATIVE) {
+      if constexpr (std::is_same<T, float>::value) open_faces16(h);
+    } else if (h->mc.exact_density) {
       Timed tm(h, K_OTHER);
       const unsigned fb2 = blocks(2LL * h->p.ny * h->p.nz);
       if (h->p.ncomp == 2)
@@ -833,11 +861,11 @@ int init_t(lbm_handle *h, const double *rw, const double *ro) {
       if (h->sk == SK_F16)
         hipLaunchKernelGGL(k_scatter_enc<SK_F16>, dim3(blocks(N)), dim3(256), 0, h->st, C,
                            s.fc[h->cur], s.rhoE, s.mask, h->p.nx, h->p.ny, h->p.nz, N,
-                           h->p.ncomp);
+                           h->p.ncomp, h->mc.open_x);
       else
         hipLaunchKernelGGL(k_scatter_enc<SK_BF16>, dim3(blocks(N)), dim3(256), 0, h->st, C,
                            s.fc[h->cur], s.rhoE, s.mask, h->p.nx, h->p.ny, h->p.nz, N,
-                           h->p.ncomp);
+                           h->p.ncomp, h->mc.open_x);
     }
   }
   h->rho_valid = false;

@@ -1302,23 +1302,27 @@ __device__ inline float writer_ref(const float *rhoE, long long v, int a, int nc
 }
 
 // stored offsets (slot layout) -> fp32 populations f = w_i (rho_ref + h)
+// (open x faces: a solid voxel on a face also decodes its slots that the
+// voxels across the face pull)
 template <int SK>
 __global__ __launch_bounds__(256) void k_decode(const uint16_t *__restrict__ codes,
                                                 const float *__restrict__ rhoE,
                                                 const uint32_t *__restrict__ mask,
                                                 float *__restrict__ out, int nx, int ny, int nz,
-                                                long long N, int nc) {
+                                                long long N, int nc, int open_x) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const uint32_t mk = mask[v];
   const bool solid = ((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE;
+  const int x = (int)(v % nx);
   for (int a = 0; a < nc; ++a) {
-    const float ref = solid ? 0.f : writer_ref(rhoE, v, a, nc);
+    const float ref = writer_ref(rhoE, v, a, nc);
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       const size_t k = (size_t)(a * Q + i) * N + v;
+      const bool crossing = open_x && cx(i) != 0 && (x + cx(i) < 0 || x + cx(i) >= nx);
       float val = 0.f;
-      if (!solid) val = (float)wq(i) * (ref + dec16<SK>(codes[k]));
+      if (!solid || crossing) val = (float)wq(i) * (ref + dec16<SK>(codes[k]));
       out[k] = val;
     }
   }
@@ -1344,12 +1348,15 @@ __global__ __launch_bounds__(256) void k_ref_canonical(const float *__restrict__
 
 // canonical fp32 set -> stored offsets (the streaming of k_scatter, encoded
 // against the reader's reference)
+// (open x faces: a solid voxel on a face also stores the slots that a fluid
+// voxel across the face pulls, as k_scatter does)
 template <int SK>
 __global__ __launch_bounds__(256) void k_scatter_enc(const float *__restrict__ C,
                                                      uint16_t *__restrict__ codes,
                                                      const float *__restrict__ rhoE,
                                                      const uint32_t *__restrict__ mask, int nx,
-                                                     int ny, int nz, long long N, int nc) {
+                                                     int ny, int nz, long long N, int nc,
+                                                     int open_x) {
   const long long v = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (v >= N) return;
   const uint32_t mk = mask[v];
@@ -1359,16 +1366,166 @@ __global__ __launch_bounds__(256) void k_scatter_enc(const float *__restrict__ C
 #pragma unroll
     for (int i = 0; i < Q; ++i) {
       uint16_t code = 0;
+      const float inv_w = i == 0 ? 3.f : (i < 7 ? 18.f : 36.f);
       if (!solid) {
         const bool bb = i > 0 && ((mk >> i) & 1u);
         const float val = bb ? C[(size_t)(a * Q + opp(i)) * N + v]
                              : C[(size_t)(a * Q + i) * N + nb.at(cx(i), cy(i), cz(i))];
-        const float inv_w = i == 0 ? 3.f : (i < 7 ? 18.f : 36.f);
         code = enc16<SK>(val * inv_w - writer_ref(rhoE, v, a, nc));
+      } else if (open_x && cx(i) != 0 && (nb.x + cx(i) < 0 || nb.x + cx(i) >= nx)) {
+        const int rd = nb.at(cx(i), cy(i), cz(i));
+        if (((mask[rd] >> CLASS_SHIFT) & 3u) != SOLID_CODE)
+          code = enc16<SK>(C[(size_t)(a * Q + i) * N + rd] * inv_w - writer_ref(rhoE, v, a, nc));
       }
       codes[(size_t)(a * Q + i) * N + v] = code;
     }
   }
+}
+
+// Open x faces with 16-bit storage.  A pulled value decodes as
+// w_i (rho_ref + h) with the reference of the slot's owner (refs [v][a], the
+// densities of the level the set was written at; 1 for one component), and
+// the face kernels encode what they write against the same owner's
+// reference, so every reader (the step, the density pass, the decode)
+// decodes the face values unchanged.
+template <int SK>
+__device__ inline float pulled16(const uint16_t *codes, const float *refs, long long N, int nc,
+                                 int a, int i, long long owner) {
+  return (float)wq(i) * (writer_ref(refs, owner, a, nc) + dec16<SK>(codes[(size_t)(a * Q + i) * N + owner]));
+}
+
+// Exact density faces (the formula of k_density_faces) on 16-bit offsets.
+template <int SK, int NC>
+__global__ __launch_bounds__(256) void k_density_faces16(const ModelConsts mc,
+                                                         uint16_t *__restrict__ codes,
+                                                         const float *__restrict__ refs,
+                                                         const uint32_t *__restrict__ mask) {
+  const long long N = mc.N;
+  const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * ny * nz) return;
+  const int face = k / (ny * nz);
+  const int r = k - face * ny * nz;
+  const int y = r % ny, z = r / ny;
+  const int xb = face == 0 ? 0 : nx - 1, s = face == 0 ? 1 : -1, wrap = face == 0 ? nx - 1 : 0;
+  const long long vb = xb + (long long)nx * (y + (long long)ny * z);
+  const uint32_t mk = mask[vb];
+  const bool fluid = ((mk >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+  auto at = [&](int xx, int yy, int zz) -> long long {
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+    return xx + (long long)nx * (yy + (long long)ny * zz);
+  };
+  for (int a = 0; a < NC; ++a) {
+    float g[Q];
+    float s0 = 0, sm = 0, ny2 = 0, nz2 = 0;
+#pragma unroll
+    for (int j = 0; j < Q; ++j) {
+      g[j] = 0;
+      if (cx(j) == s) continue;
+      const float v = ((mk >> opp(j)) & 1u)
+                          ? pulled16<SK>(codes, refs, N, NC, a, opp(j), vb)
+                          : pulled16<SK>(codes, refs, N, NC, a, j, at(xb - cx(j), y - cy(j), z - cz(j)));
+      g[j] = v;
+      if (cx(j) == 0) {
+        s0 += v;
+        ny2 += (float)cy(j) * v;
+        nz2 += (float)cz(j) * v;
+      } else {
+        sm += v;
+      }
+    }
+    const float Ny = 0.5f * ny2, Nz = 0.5f * nz2;
+    const float sJ = (float)(face == 0 ? mc.rho_in[a] : mc.rho_out[a]) - s0 - 2.f * sm;
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+      if (cx(i) != s) continue;
+      const float val = g[opp(i)] + (float)(6.0 * wq(i)) * sJ - (float)cy(i) * Ny - (float)cz(i) * Nz;
+      const long long owner = at(wrap, y - cy(i), z - cz(i));
+      const float inv_w = i < 7 ? 18.f : 36.f;
+      codes[(size_t)(a * Q + i) * N + owner] =
+          fluid ? enc16<SK>(val * inv_w - writer_ref(refs, owner, a, NC)) : (uint16_t)0;
+    }
+  }
+}
+
+// Reservoir faces (the reading of k_reservoirs) on 16-bit offsets.
+template <int SK, int NC>
+__global__ __launch_bounds__(256) void k_reservoirs16(const ModelConsts mc,
+                                                      uint16_t *__restrict__ codes,
+                                                      const float *__restrict__ refs,
+                                                      const uint32_t *__restrict__ mask) {
+  const long long N = mc.N;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mc.ny * mc.nz) return;
+  const long long v0 = (long long)k * mc.nx, v1 = v0 + mc.nx - 1;
+  float u[2][3];
+  const long long vb[2] = {v0, v1};
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const bool fluid = ((mask[vb[e]] >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    float rho = 0, m0 = 0, m1 = 0, m2 = 0;
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const float f = pulled16<SK>(codes, refs, N, NC, a, i, vb[e]);
+        rho += f;
+        m0 += (float)cx(i) * f;
+        m1 += (float)cy(i) * f;
+        m2 += (float)cz(i) * f;
+      }
+    const float ir = fluid ? 1.f / rho : 0.f;
+    u[e][0] = m0 * ir;
+    u[e][1] = m1 * ir;
+    u[e][2] = m2 * ir;
+  }
+  for (int a = 0; a < NC; ++a) {
+#pragma unroll
+    for (int i = 1; i < Q; ++i) {
+      if (cx(i) == 0) continue;
+      const int e = cx(i) > 0 ? 0 : 1;  // inlet reservoir sends c_x = +1, outlet c_x = -1
+      const float r = (float)(e == 0 ? mc.rho_in[a] : mc.rho_out[a]);
+      const float cu = (float)cx(i) * u[e][0] + (float)cy(i) * u[e][1] + (float)cz(i) * u[e][2];
+      const float usq = u[e][0] * u[e][0] + u[e][1] * u[e][1] + u[e][2] * u[e][2];
+      const float geq = r * (1.f + 3.f * cu + 4.5f * cu * cu - 1.5f * usq);  // f_eq / w_i
+      const long long owner = e == 0 ? v1 : v0;
+      codes[(size_t)(a * Q + i) * N + owner] = enc16<SK>(geq - writer_ref(refs, owner, a, NC));
+    }
+  }
+}
+
+// Two components: the fused step wrote rhoS[v] = sum_i w_i rho_ref(s_i) over
+// the sources s_i of v's next pulls with the reservoir densities for the
+// sources beyond an open face; those pulls read slots whose reference is their
+// owner's (the voxel across the wrap), so a face voxel's sum takes the
+// difference.  One thread per face voxel.
+__global__ __launch_bounds__(256) void k_rhoS_faces(const ModelConsts mc, float *__restrict__ rhoS,
+                                                    const float *__restrict__ refs,
+                                                    const uint32_t *__restrict__ mask) {
+  const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 2 * ny * nz) return;
+  const int face = k / (ny * nz);
+  const int r = k - face * ny * nz;
+  const int y = r % ny, z = r / ny;
+  const int xb = face == 0 ? 0 : nx - 1, out = face == 0 ? -1 : 1, wrap = face == 0 ? nx - 1 : 0;
+  const long long v = xb + (long long)nx * (y + (long long)ny * z);
+  if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
+  float add[2] = {0.f, 0.f};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    if (cx(i) != out) continue;  // x + c_i beyond the face
+    int yy = y + cy(i), zz = z + cz(i);
+    yy = yy < 0 ? yy + ny : (yy >= ny ? yy - ny : yy);
+    zz = zz < 0 ? zz + nz : (zz >= nz ? zz - nz : zz);
+    const long long owner = wrap + (long long)nx * (yy + (long long)ny * zz);
+    for (int a = 0; a < 2; ++a) {
+      const float res = (float)(face == 0 ? mc.rho_in[a] : mc.rho_out[a]);
+      add[a] += (float)wq(i) * (refs[2 * owner + a] - res);
+    }
+  }
+  rhoS[2 * v] += add[0];
+  rhoS[2 * v + 1] += add[1];
 }
 
 // per-link outlet flux through the plane x_f | x_f + 1 from the stored offsets

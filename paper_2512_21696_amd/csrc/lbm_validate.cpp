@@ -113,8 +113,6 @@ extern "C" int lbm_validate_params(const lbm_params *p, char *msg, size_t len) {
   if (p->layout != LBM_LAYOUT_AUTO && p->layout != LBM_LAYOUT_DENSE)
     return fail(msg, len, LBM_E_INVAL, "unknown population layout");
   if (p->bc_x != LBM_BC_PERIODIC) {
-    if (p->precision == LBM_PREC_F16 || p->precision == LBM_PREC_BF16)
-      return fail(msg, len, LBM_E_UNSUPPORTED, "open x faces need F64 or F32 storage");
     if (p->outlet_x > p->nx - 2)
       return fail(msg, len, LBM_E_INVAL, "with open x faces outlet_x must be <= nx - 2");
     if (p->kappa != 0.0 && p->csf_region != LBM_CSF_GRAY)

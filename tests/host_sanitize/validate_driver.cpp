@@ -80,7 +80,7 @@ int main() {
       {"diag_every", [](lbm_params &q) { q.diag_every = -1; }, LBM_E_INVAL},
       {"bc_x", [](lbm_params &q) { q.bc_x = 4; }, LBM_E_INVAL},
       {"layout", [](lbm_params &q) { q.layout = 3; }, LBM_E_INVAL},
-      {"pressure f16", [](lbm_params &q) { q.bc_x = LBM_BC_PRESSURE; q.precision = LBM_PREC_F16; }, LBM_E_UNSUPPORTED},
+      {"density faces nx 2", [](lbm_params &q) { q.bc_x = LBM_BC_DENSITY; q.nx = 2; q.outlet_x = 0; }, LBM_E_INVAL},
       {"pressure outlet", [](lbm_params &q) { q.bc_x = LBM_BC_PRESSURE; q.outlet_x = q.nx - 1; }, LBM_E_INVAL},
       {"pressure csf", [](lbm_params &q) { q.bc_x = LBM_BC_PRESSURE; q.outlet_x = 1; q.kappa = 0.1; q.csf_region = LBM_CSF_ALL; }, LBM_E_INVAL},
       {"reservoir nan", [](lbm_params &q) { q.bc_x = LBM_BC_PRESSURE; q.outlet_x = 1; q.rho_in[1] = std::nan(""); }, LBM_E_INVAL},

@@ -103,7 +103,7 @@ def test_open_faces_single_phase_slit_matches_oracle(bc):
     lb.destroy()
 
 
-def test_open_faces_reject_gray_next_to_a_face_and_16bit():
+def test_open_faces_reject_gray_next_to_a_face():
     import paper_2512_21696_amd as L
     wl = displacement()
     wl["cls"][:, :, 1] = 2
@@ -114,11 +114,38 @@ def test_open_faces_reject_gray_next_to_a_face_and_16bit():
         lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
     assert e.value.code == L.LBM_E_INVAL
     lb.destroy()
-    p = displacement()["params"]
-    p.precision = "f16"
-    with pytest.raises(L.LbmError) as e:
-        L.lbm_create(p)
-    assert e.value.code == L.LBM_E_UNSUPPORTED
+
+
+@pytest.mark.parametrize("bc", ["pressure", "density"])
+@pytest.mark.parametrize("prec", ["f16", "bf16"])
+def test_open_faces_16bit_displacement_within_rounding_of_oracle(prec, bc):
+    """16-bit storage between open faces: the face values are offsets against
+    their slot owner's reference like every other slot, and the face voxels'
+    reference sums are corrected to those owners.  Against the fp64 oracle
+    within the rounding bounds of the 16-bit tests (density 2 * 2^-p sqrt(n),
+    velocity 2^-p sqrt(n) / 3); on density faces the face voxels hold the
+    prescribed densities to the rounding of their five face values."""
+    from test_gpu_store16 import bound, abs_errors, BITS
+    steps = 60
+    announce(f"open x faces ({bc}) displacement {prec}, {steps} steps")
+    wl = displacement(bc=bc)
+    lb = gpu_run(wl, steps, prec)
+    got, dg = lb.get_fields(), lb.get_diagnostics()
+    lb.destroy()
+    o = oracle_run(displacement(bc=bc), steps)
+    ref = o.fields()
+    names = ("rho_w", "rho_o", "ux", "uy", "uz", "S")
+    ae = abs_errors(got, ref, names)
+    print(prec, bc, "absolute field errors", {k: f"{v:.2e}" for k, v in ae.items()})
+    assert dg["nonfinite"] == 0
+    for k, v in ae.items():
+        assert v < bound(prec, steps, k), (k, v, bound(prec, steps, k))
+    if bc == "density":
+        fl = wl["cls"] != 1
+        tol = 2.0 ** -BITS[prec] * 2.0
+        for k, xb, val in (("rho_w", 0, 1.02), ("rho_o", -1, 0.99)):
+            err = np.abs(np.asarray(got[k])[:, :, xb][fl[:, :, xb]] - val).max()
+            assert err < tol, (k, err, tol)
 
 
 @pytest.mark.parametrize("bc", ["pressure", "density"])
