@@ -2,7 +2,7 @@
 //
 // A block owns a column of 64 x 4 voxels (one wavefront per x-row, so every
 // population load and store of a wave covers 256 contiguous bytes) and
-// marches along z through a chunk of ZC planes.  A rolling window in LDS holds
+// marches along z through a chunk of planes.  A rolling window in LDS holds
 // five planes of (rho_w, rho_o) on the column plus a radius-2 halo (periodic
 // wrap; +inf marks a solid cell) with the mobile saturation S_hat of each
 // cell, and one plane of the CSF normals
@@ -47,7 +47,7 @@ constexpr int NH = HX * HY;  // density plane cells
 constexpr int MX = TX + 2, MY = TY + 2;
 constexpr int NM = MX * MY;  // normal plane cells
 constexpr int RS = 5;        // density planes z-2 .. z+2
-constexpr int ZC = 32;       // planes per block (fewer on grids too small to fill the chip)
+constexpr int ZC = 32;       // planes per block without an occupancy figure (halved on small grids)
 __host__ __device__ constexpr int hoff(int i) { return cx(i) + HX * cy(i); }
 __host__ __device__ constexpr int moff(int i) { return cx(i) + MX * cy(i); }
 }  // namespace zm
