@@ -58,7 +58,7 @@ def algorithmic_bytes(ncomp, es, gray_frac, tensor, pop_es=None):
 
 def kernel_source_hash():
     """Hash of what decides the step kernels' traffic: their sources and the
-    runtime's launch functions for them (launch_tiled, ensure_density)."""
+    runtime's functions that launch them or set their z chunk."""
     import re
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2512_21696_amd", "csrc")
@@ -67,7 +67,7 @@ def kernel_source_hash():
             h.update(fh.read())
     with open(os.path.join(csrc, "lbm_runtime.hip")) as fh:
         rt = fh.read()
-    for name in ("ensure_density", "launch_tiled"):
+    for name in ("ensure_density", "tiled_chunk", "launch_tiled", "launch_density_fix"):
         m = re.search(r"\n[^\n]*\b" + name + r"\(lbm_handle \*h[^{]*\{.*?\n\}\n", rt, re.S)
         if m is None:
             raise RuntimeError(f"{name} not found in lbm_runtime.hip")
