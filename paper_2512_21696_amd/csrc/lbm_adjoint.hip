@@ -421,6 +421,53 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   const AT cs2 = CS2;
   constexpr AT ics2 = AT(3.0), ics4 = AT(9.0);  // 1 / c_s^2, 1 / c_s^4
 
+  // a gray voxel's inputs and accumulators, none of which depends on the
+  // gathers below, loaded ahead of them so that their latency overlaps the
+  // gathers' (the updates further down add to these values)
+  AT p_rres[2] = {0, 0}, p_gS[3] = {0, 0, 0}, p_sj = 0, p_k0 = 1, p_thw = 0, p_tho = 0;
+  AT p_K[6] = {0, 0, 0, 0, 0, 0};
+  double p_lr[2] = {0, 0}, p_gsj = 0, p_gk[6] = {0, 0, 0, 0, 0, 0};
+  const T *p_tb = tab;
+  bool p_side = false;
+  // the level's neighbour sums of every fluid voxel, and (CSF region) its
+  // density gradients and curvatures
+  AT p_inb[6], p_cg[2][3] = {{0, 0, 0}, {0, 0, 0}}, p_curv[2] = {0, 0};
+#pragma unroll
+  for (int q = 0; q < 6; ++q) p_inb[q] = (AT)inb[(size_t)q * N + v];
+  const bool csfv = (AT)mc.kappa != AT(0.0) && (gray || mc.csf_all);
+  if (csfv) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int d = 0; d < 3; ++d) p_cg[a][d] = (AT)nrmb[(size_t)(6 * a + d) * N + v];
+      p_curv[a] = (AT)inb[(size_t)(9 + a) * N + v];
+    }
+  }
+  if (gray) {
+    p_rres[0] = (AT)rres[v];
+    p_rres[1] = (AT)rres[N + v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) p_gS[d] = (AT)inb[(size_t)(6 + d) * N + v];
+    p_tb = tab + (size_t)ptype[v] * 3 * TABLE_N;
+    p_sj = (AT)sJ[v];
+    p_thw = (AT)thw[v];
+    p_tho = (AT)tho[v];
+    p_side = side[v] != 0;
+    p_lr[0] = lr[v];
+    p_lr[1] = lr[N + v];
+    p_gsj = gsj[v];
+    if (TENS) {
+#pragma unroll
+      for (int q = 0; q < 6; ++q) {
+        p_K[q] = (AT)Kinv[(size_t)q * N + v];
+        p_gk[q] = gk[(size_t)q * N + v];
+      }
+    } else {
+      p_k0 = (AT)K0[v];
+      p_gk[0] = gk[v];
+    }
+  }
+
   // pulls, moments and the gathered adjoint of the post-collision sets
   AT rho[2], m[2][3], L0[2], L1[2][3], M2[2][6];  // M2: xx, yy, zz, xy, xz, yz
   AT Pi[2][6], lf[2];  // second moments (regularised), sum_i lam_i f_i (BGK)
@@ -484,8 +531,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     AT pw = rho[b] + mwd[b];
     pw = pw > AT(0.0) ? pw : AT(0.0);
     // the fluid links' sum comes from the inputs pass, the solid links read pw
-    AT s0 = (AT)inb[(size_t)(3 * a) * N + v], s1 = (AT)inb[(size_t)(3 * a + 1) * N + v],
-           s2 = (AT)inb[(size_t)(3 * a + 2) * N + v];
+    AT s0 = p_inb[3 * a], s1 = p_inb[3 * a + 1], s2 = p_inb[3 * a + 2];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const AT w = ((mk >> i) & 1u) ? (AT)wq(i) * pw : AT(0.0);
@@ -499,14 +545,15 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   // CSF control, Eq. (4), on the region's voxels: g^a = grad rho^b and the
   // normals n^a = g^a / |g^a| of the level (nrmb rows 6a..6a+2: g, 6a+3..: n),
   // curv^a = -div n^a (own normal across a solid link), F^a += kap curv g rho^a
-  const bool csfv = mkappa != AT(0.0) && (gray || mc.csf_all);
   const AT kap = mkappa * mcsf;
   AT cg[2][3] = {{0, 0, 0}, {0, 0, 0}}, curv[2] = {0, 0};
   if (csfv) {
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
-      for (int d = 0; d < 3; ++d) cg[a][d] = (AT)nrmb[(size_t)(6 * a + d) * N + v];
-      curv[a] = (AT)inb[(size_t)(9 + a) * N + v];
+#pragma unroll
+      for (int d = 0; d < 3; ++d) cg[a][d] = p_cg[a][d];
+      curv[a] = p_curv[a];
+#pragma unroll
       for (int d = 0; d < 3; ++d) Fex[a][d] += kap * curv[a] * cg[a][d] * rho[a];
     }
   }
@@ -515,11 +562,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
          dKrw = 0, Kro = 0, dKro = 0, sj = 0, Pc = 0, kw = 1, ko = 1, ikw = 1, iko = 1, cR = 0;
   const AT shat0 = (rho[0] * irt - msmin) * ispan;
   if (gray) {
-    tw = rho[0] + (AT)rres[v];
-    to = rho[1] + (AT)rres[N + v];
+    tw = rho[0] + p_rres[0];
+    to = rho[1] + p_rres[1];
     Sraw = (tw / (tw + to) - msmin) * ispan;
     S = Sraw < AT(0.0) ? AT(0.0) : (Sraw > AT(1.0) ? AT(1.0) : Sraw);
-    for (int d = 0; d < 3; ++d) gS[d] = (AT)inb[(size_t)(6 + d) * N + v];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) gS[d] = p_gS[d];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {  // solid links read this voxel's own S_hat
       const AT w = ((mk >> i) & 1u) ? (AT)gw(i) * shat0 : AT(0.0);
@@ -527,7 +575,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       if (cy(i)) gS[1] += cy(i) * w;
       if (cz(i)) gS[2] += cz(i) * w;
     }
-    const T *tb = tab + (size_t)ptype[v] * 3 * TABLE_N;
+    const T *tb = p_tb;
     const AT t = S * (AT)(TABLE_N - 1);
     int k = (int)floor(t);
     k = k > TABLE_N - 2 ? TABLE_N - 2 : (k < 0 ? 0 : k);
@@ -540,7 +588,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     lookup(tb, Pct, dPct);
     lookup(tb + TABLE_N, Krw, dKrw);
     lookup(tb + 2 * TABLE_N, Kro, dKro);
-    sj = (AT)sJ[v];
+    sj = p_sj;
     Pc = sj * Pct;
     for (int a = 0; a < 2; ++a)
       for (int d = 0; d < 3; ++d) Fex[a][d] += -Pc * (rho[a] * irt) * gS[d];
@@ -558,12 +606,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   for (int d = 0; d < 3; ++d) bvec[d] = m[0][d] + m[1][d] + h * (Fex[0][d] + Fex[1][d]);
   AT k0 = AT(1.0), Rs = AT(0.0), den = rt;
   if (tens) {
-    K[0][0] = (AT)Kinv[v];
-    K[1][1] = (AT)Kinv[N + v];
-    K[2][2] = (AT)Kinv[2 * N + v];
-    K[0][1] = K[1][0] = (AT)Kinv[3 * N + v];
-    K[0][2] = K[2][0] = (AT)Kinv[4 * N + v];
-    K[1][2] = K[2][1] = (AT)Kinv[5 * N + v];
+    K[0][0] = p_K[0];
+    K[1][1] = p_K[1];
+    K[2][2] = p_K[2];
+    K[0][1] = K[1][0] = p_K[3];
+    K[0][2] = K[2][0] = p_K[4];
+    K[1][2] = K[2][1] = p_K[5];
     const AT hc = h * cR;
     const AT a00 = rt + hc * K[0][0], a11 = rt + hc * K[1][1], a22 = rt + hc * K[2][2];
     const AT a01 = hc * K[0][1], a02 = hc * K[0][2], a12 = hc * K[1][2];
@@ -583,7 +631,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     }
   } else {
     if (gray) {
-      k0 = (AT)K0[v];
+      k0 = p_k0;
       Rs = cR / k0;  // once per voxel
     }
     den = rt + h * Rs;
@@ -607,24 +655,24 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   int ev = 0;  // 1: oil -> water, 2: water -> oil
   AT sc[2] = {AT(1.0), AT(1.0)}, scb[2] = {AT(0.0), AT(0.0)}, dtr = AT(0.0), rw0 = AT(0.0), ro0 = AT(0.0);
   if (gray) {
-    const bool sd = side[v] != 0;
+    const bool sd = p_side;
     if (!sd && S >= AT(0.5) + mhyst) ev = 1;
     else if (sd && S <= AT(0.5) - mhyst) ev = 2;
   }
   if (ev) {
-    rw0 = (AT)rres[v];
-    ro0 = (AT)rres[N + v];
+    rw0 = p_rres[0];
+    ro0 = p_rres[1];
     const AT rhoT = tw + to, mm = mminor;
     if (ev == 1) {
       sc[0] = (rho[0] + rw0) * irho[0];
-      AT d = (AT)tho[v] * rhoT - ro0;
+      AT d = p_tho * rhoT - ro0;
       const AT cap = rho[1] - mm;
       d = d < cap ? d : cap;
       dtr = d > AT(0.0) ? d : AT(0.0);
       sc[1] = AT(1.0) - dtr * irho[1];
     } else {
       sc[1] = (rho[1] + ro0) * irho[1];
-      AT d = (AT)thw[v] * rhoT - rw0;
+      AT d = p_thw * rhoT - rw0;
       const AT cap = rho[0] - mm;
       d = d < cap ? d : cap;
       dtr = d > AT(0.0) ? d : AT(0.0);
@@ -796,12 +844,12 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         if (i == j) rtb += Ab;
       }
     cRb += h * AK;
-    gk[v] += Kb[0][0];
-    gk[N + v] += Kb[1][1];
-    gk[2 * N + v] += Kb[2][2];
-    gk[3 * N + v] += Kb[0][1] + Kb[1][0];
-    gk[4 * N + v] += Kb[0][2] + Kb[2][0];
-    gk[5 * N + v] += Kb[1][2] + Kb[2][1];
+    gk[v] = p_gk[0] + Kb[0][0];
+    gk[N + v] = p_gk[1] + Kb[1][1];
+    gk[2 * N + v] = p_gk[2] + Kb[2][2];
+    gk[3 * N + v] = p_gk[3] + (Kb[0][1] + Kb[1][0]);
+    gk[4 * N + v] = p_gk[4] + (Kb[0][2] + Kb[2][0]);
+    gk[5 * N + v] = p_gk[5] + (Kb[1][2] + Kb[2][1]);
   } else {
     AT Rsb = 0, ub[3];
     for (int d = 0; d < 3; ++d) {
@@ -819,7 +867,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
     if (gray) {
       const AT ik0 = AT(1.0) / k0;
       cRb = Rsb * ik0;
-      gk[v] += -Rsb * cR * ik0 * ik0;
+      gk[v] = p_gk[0] + -Rsb * cR * ik0 * ik0;
     }
   }
   for (int a = 0; a < 2; ++a)
@@ -890,7 +938,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
       if (Kro > mkrmin) Sb += -cRb * rt * (AT(1.0) - S) * mnu[1] * iko * iko * dKro;
     }
     // P_c = s_J P_c(S)
-    gsj[v] += Pcb * Pct;
+    gsj[v] = p_gsj + Pcb * Pct;
     Sb += Pcb * sj * dPct;
     if (Sraw > AT(0.0) && Sraw < AT(1.0)) {
       const AT itt = AT(1.0) / (tw + to), sb = Sb * ispan;
@@ -912,7 +960,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   if (gray) {
     // residual amounts: dL/dr after the step comes in, dL/dr before it goes out
     AT rbw = AT(0.0), rbo = AT(0.0);
-    const AT lw = lr[v], lo_ = lr[N + v];
+    const AT lw = (AT)p_lr[0], lo_ = (AT)p_lr[1];
     if (ev) {
       const AT rhoT = tw + to;
       AT db = AT(0.0), rTb = AT(0.0);
@@ -923,10 +971,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         rb[1] += scb[1] * dtr * irho[1] * irho[1];
         rbo += lo_;  // r^o <- r^o + d; r^w <- 0
         db += lo_;
-        const AT raw = (AT)tho[v] * rhoT - ro0, cap = rho[1] - mminor;
+        const AT raw = p_tho * rhoT - ro0, cap = rho[1] - mminor;
         if (raw < cap && raw > AT(0.0)) {
           gth[N + v] += db * rhoT;
-          rTb += db * (AT)tho[v];
+          rTb += db * p_tho;
           rbo -= db;
         } else if (raw >= cap && cap > AT(0.0)) {
           rb[1] += db;
@@ -938,10 +986,10 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         rb[0] += scb[0] * dtr * irho[0] * irho[0];
         rbw += lw;  // r^w <- r^w + d; r^o <- 0
         db += lw;
-        const AT raw = (AT)thw[v] * rhoT - rw0, cap = rho[0] - mminor;
+        const AT raw = p_thw * rhoT - rw0, cap = rho[0] - mminor;
         if (raw < cap && raw > AT(0.0)) {
           gth[v] += db * rhoT;
-          rTb += db * (AT)thw[v];
+          rTb += db * p_thw;
           rbw -= db;
         } else if (raw >= cap && cap > AT(0.0)) {
           rb[0] += db;
@@ -1027,7 +1075,7 @@ __global__ __launch_bounds__(256) void k_adj_normals(const ModelConsts mc,
 // force of component a (b = 1 - a), rows 6..8 sum_i (w_i / cs2) c_i S_hat(x + c_i),
 // and (CSF, from the normals) rows 9, 10 curv^a = -div n^a (own normal across
 // a solid link).
-template <typename T>
+template <typename T, bool CSF>
 __global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
                                                      const T *__restrict__ rho2,
                                                      const T *__restrict__ nrmb,
@@ -1061,25 +1109,30 @@ __global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
       gs[d] += gw(i) * c[d] * sh;
     }
   }
+  // (CSF a template switch and every store last: no branch or store between
+  // the two groups of gathers)
+  double dv[2] = {0, 0};
+  if (CSF) {
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        const bool wall = (mk >> i) & 1u;
+        const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
+        if (cx(i)) dv[a] += gw(i) * cx(i) * (double)nrmb[(size_t)(6 * a + 3) * N + y];
+        if (cy(i)) dv[a] += gw(i) * cy(i) * (double)nrmb[(size_t)(6 * a + 4) * N + y];
+        if (cz(i)) dv[a] += gw(i) * cz(i) * (double)nrmb[(size_t)(6 * a + 5) * N + y];
+      }
+    }
+  }
   for (int d = 0; d < 3; ++d) {
     inb[(size_t)d * N + v] = (T)a0[d];
     inb[(size_t)(3 + d) * N + v] = (T)a1[d];
     inb[(size_t)(6 + d) * N + v] = (T)gs[d];
   }
-  if (mc.kappa != 0.0) {
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      double dv = 0;
-#pragma unroll
-      for (int i = 1; i < Q; ++i) {
-        const bool wall = (mk >> i) & 1u;
-        const size_t y = wall ? (size_t)v : (size_t)nb.at(cx(i), cy(i), cz(i));
-        if (cx(i)) dv += gw(i) * cx(i) * (double)nrmb[(size_t)(6 * a + 3) * N + y];
-        if (cy(i)) dv += gw(i) * cy(i) * (double)nrmb[(size_t)(6 * a + 4) * N + y];
-        if (cz(i)) dv += gw(i) * cz(i) * (double)nrmb[(size_t)(6 * a + 5) * N + y];
-      }
-      inb[(size_t)(9 + a) * N + v] = (T)(-dv);
-    }
+  if (CSF) {
+    inb[(size_t)9 * N + v] = (T)(-dv[0]);
+    inb[(size_t)10 * N + v] = (T)(-dv[1]);
   }
 }
 
@@ -1098,34 +1151,42 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
   const uint32_t mk = mask[v];
   if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
+  // every load of both components before the first store: the stores go to
+  // the same array (rows 11..16), so loads after them could not move ahead
+  T cb[2][Q];  // [a][0]: this voxel's curvature adjoint, [a][i]: x = y - c_i's
+  double g[2][3], n[2][3], sg[2][3];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    cb[a][0] = stash[(size_t)(9 + a) * N + v];
+#pragma unroll
+    for (int i = 1; i < Q; ++i) cb[a][i] = stash[(size_t)(9 + a) * N + nb.at(-cx(i), -cy(i), -cz(i))];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      g[a][d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
+      n[a][d] = (double)nrmb[(size_t)(6 * a + 3 + d) * N + v];
+      sg[a][d] = (double)stash[(size_t)(11 + 3 * a + d) * N + v];
+    }
+  }
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     double nbar[3] = {0, 0, 0};
-    const double cbv = (double)stash[(size_t)(9 + a) * N + v];
+    const double cbv = (double)cb[a][0];
 #pragma unroll
     for (int i = 1; i < Q; ++i) {
       const bool wall = (mk >> i) & 1u;
       // the voxel x = y - c_i read n(y) through its link i; y's own solid
       // links read its own normal
-      const double cb_nb = (double)stash[(size_t)(9 + a) * N + nb.at(-cx(i), -cy(i), -cz(i))];
-      const double c = cb_nb + (wall ? cbv : 0.0);
+      const double c = (double)cb[a][i] + (wall ? cbv : 0.0);
       if (cx(i)) nbar[0] += -gw(i) * cx(i) * c;
       if (cy(i)) nbar[1] += -gw(i) * cy(i) * c;
       if (cz(i)) nbar[2] += -gw(i) * cz(i) * c;
     }
-    double g[3], n[3];
-    for (int d = 0; d < 3; ++d) {
-      g[d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
-      n[d] = (double)nrmb[(size_t)(6 * a + 3 + d) * N + v];
-    }
-    const double n2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+    const double n2 = g[a][0] * g[a][0] + g[a][1] * g[a][1] + g[a][2] * g[a][2];
     if (n2 > mc.eps_n * mc.eps_n) {
       const double in = 1.0 / sqrt(n2);
-      const double nn = n[0] * nbar[0] + n[1] * nbar[1] + n[2] * nbar[2];
-      for (int d = 0; d < 3; ++d) {
-        T *sg = stash + (size_t)(11 + 3 * a + d) * N + v;
-        *sg = (T)((double)*sg + (nbar[d] - nn * n[d]) * in);
-      }
+      const double nn = n[a][0] * nbar[0] + n[a][1] * nbar[1] + n[a][2] * nbar[2];
+      for (int d = 0; d < 3; ++d)
+        stash[(size_t)(11 + 3 * a + d) * N + v] = (T)(sg[a][d] + (nbar[d] - nn * n[a][d]) * in);
     }
   }
 }
@@ -1135,7 +1196,10 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
 // through S_hat(y) from the saturation-gradient reads of gray voxels, and
 // (CSF) dL/drho^b(y) from the density-gradient reads behind the normals and
 // the force term (own value across a solid link).
-template <typename T>
+// Every neighbour value is loaded without a branch between the loads (the
+// open-face and solid-link cases select their terms afterwards), so a wave
+// keeps all its gathers in flight instead of waiting on each direction's.
+template <typename T, bool CSF>
 __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
                                                  const T *__restrict__ rho2,
                                                  const T *__restrict__ stash,
@@ -1147,12 +1211,20 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
   if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;  // stays zero
   const uint32_t mk = mask[v];
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
-  const bool csf = mc.kappa != 0.0;
+  // (CSF) this voxel's own density-gradient adjoints, which its solid links read
+  double own[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  if (CSF) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      own[0][d] = (double)stash[(size_t)(11 + d) * N + v];
+      own[1][d] = (double)stash[(size_t)(14 + d) * N + v];
+    }
+  }
   double r0 = 0, r1 = 0, shb = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
     // open x faces: the voxel x - c_i across a face read a reservoir cell, not x
-    if (mc.open_x && cx(i) != 0 && (nb.x - cx(i) < 0 || nb.x - cx(i) >= mc.nx)) continue;
+    const bool across = mc.open_x && cx(i) != 0 && (nb.x - cx(i) < 0 || nb.x - cx(i) >= mc.nx);
     const size_t x = (size_t)nb.at(-cx(i), -cy(i), -cz(i));
     auto dot = [&](int c0, size_t at) {
       double s = 0;
@@ -1161,15 +1233,25 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
       if (cz(i)) s += cz(i) * (double)stash[(size_t)(c0 + 2) * N + at];
       return s;
     };
-    r1 += wq(i) * dot(0, x);  // water's force reads psi^o
-    r0 += wq(i) * dot(3, x);  // oil's force reads psi^w
-    shb += gw(i) * dot(6, x);
-    if (csf) {
+    auto dot_own = [&](int a) {
+      double s = 0;
+      if (cx(i)) s += cx(i) * own[a][0];
+      if (cy(i)) s += cy(i) * own[a][1];
+      if (cz(i)) s += cz(i) * own[a][2];
+      return s;
+    };
+    const double d0 = dot(0, x), d3 = dot(3, x), d6 = dot(6, x);
+    r1 = across ? r1 : r1 + wq(i) * d0;  // water's force reads psi^o
+    r0 = across ? r0 : r0 + wq(i) * d3;  // oil's force reads psi^w
+    shb = across ? shb : shb + gw(i) * d6;
+    if (CSF) {
       // g^w = grad rho^o, g^o = grad rho^w; a solid link of this voxel reads
       // its own density
       const bool wall = (mk >> i) & 1u;
-      r1 += gw(i) * (dot(11, x) + (wall ? dot(11, (size_t)v) : 0.0));
-      r0 += gw(i) * (dot(14, x) + (wall ? dot(14, (size_t)v) : 0.0));
+      const double d11 = dot(11, x), d14 = dot(14, x);
+      const double w11 = wall ? dot_own(0) : 0.0, w14 = wall ? dot_own(1) : 0.0;
+      r1 = across ? r1 : r1 + gw(i) * (d11 + w11);
+      r0 = across ? r0 : r0 + gw(i) * (d14 + w14);
     }
   }
   const double aw = (double)rho2[2 * v], ao = (double)rho2[2 * v + 1];
@@ -1514,8 +1596,12 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
     if (h->p.kappa != 0.0)
       hipLaunchKernelGGL((adj::k_adj_normals<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
                          h->mc, (const T *)b.dens, s.mask, b.nrmb);
-    hipLaunchKernelGGL((adj::k_adj_inputs2<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st, h->mc,
-                       (const T *)b.dens, (const T *)b.nrmb, s.mask, b.inb);
+    if (h->p.kappa != 0.0)
+      hipLaunchKernelGGL((adj::k_adj_inputs2<T, true>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
+                         h->mc, (const T *)b.dens, (const T *)b.nrmb, s.mask, b.inb);
+    else
+      hipLaunchKernelGGL((adj::k_adj_inputs2<T, false>), dim3(blocks8(h->N)), dim3(256), 0,
+                         h->st, h->mc, (const T *)b.dens, (const T *)b.nrmb, s.mask, b.inb);
   }
   Timed tm(h, K_ADJ);
   if (ten) {
@@ -1528,8 +1614,12 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
   if (h->p.kappa != 0.0)
     hipLaunchKernelGGL((adj::k_adj_normals_rev<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
                        h->mc, (const T *)b.nrmb, s.mask, b.stash);
-  hipLaunchKernelGGL((adj::k_adj_nl2<T>), dim3(blocks8(h->N)), dim3(256), 0, h->st, h->mc,
-                     (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
+  if (h->p.kappa != 0.0)
+    hipLaunchKernelGGL((adj::k_adj_nl2<T, true>), dim3(blocks8(h->N)), dim3(256), 0, h->st, h->mc,
+                       (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
+  else
+    hipLaunchKernelGGL((adj::k_adj_nl2<T, false>), dim3(blocks8(h->N)), dim3(256), 0, h->st,
+                       h->mc, (const T *)b.dens, (const T *)b.stash, s.mask, b.rnl_out);
 }
 
 // The fused step from fin into fout (two components: after the density pass
