@@ -137,6 +137,18 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
   const int x1 = mc.outlet_x + 1 == mc.nx ? 0 : mc.outlet_x + 1;
   const bool at0 = nb.x == mc.outlet_x, at1 = nb.x == x1;
+  // (tensor) a gray voxel's K^-1 and its dL/dK^-1 accumulators, loaded ahead
+  // of the gathers so that their latency overlaps them (the updates at the
+  // end add to these values; their six read-after-write round trips would
+  // otherwise follow one another)
+  double p_K[6] = {0, 0, 0, 0, 0, 0}, p_gk[6] = {0, 0, 0, 0, 0, 0};
+  if (TENS && gray) {
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      p_K[q] = (double)Kinv[(size_t)q * N + v];
+      p_gk[q] = gk[(size_t)q * N + v];
+    }
+  }
 
   double lp[Q];
   double rho = 0, m0 = 0, m1 = 0, m2 = 0;
@@ -183,12 +195,12 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
   double u0, u1, u2, F0, F1, F2, w0 = 0, w1 = 0, w2 = 0;
   if (tens) {
     cR = rho * mc.nu[0];
-    K[0][0] = (double)Kinv[v];
-    K[1][1] = (double)Kinv[N + v];
-    K[2][2] = (double)Kinv[2 * N + v];
-    K[0][1] = K[1][0] = (double)Kinv[3 * N + v];
-    K[0][2] = K[2][0] = (double)Kinv[4 * N + v];
-    K[1][2] = K[2][1] = (double)Kinv[5 * N + v];
+    K[0][0] = p_K[0];
+    K[1][1] = p_K[1];
+    K[2][2] = p_K[2];
+    K[0][1] = K[1][0] = p_K[3];
+    K[0][2] = K[2][0] = p_K[4];
+    K[1][2] = K[2][1] = p_K[5];
     const double hc = h * cR;
     const double a00 = rho + hc * K[0][0], a11 = rho + hc * K[1][1], a22 = rho + hc * K[2][2];
     const double a01 = hc * K[0][1], a02 = hc * K[0][2], a12 = hc * K[1][2];
@@ -312,12 +324,12 @@ __global__ __launch_bounds__(256) void k_adj_step(const ModelConsts mc,
     // c_R = rho nu
     rb += mc.nu[0] * cRb;
     const long long NN = N;
-    gk[v] += Kb[0][0];
-    gk[NN + v] += Kb[1][1];
-    gk[2 * NN + v] += Kb[2][2];
-    gk[3 * NN + v] += Kb[0][1] + Kb[1][0];
-    gk[4 * NN + v] += Kb[0][2] + Kb[2][0];
-    gk[5 * NN + v] += Kb[1][2] + Kb[2][1];
+    gk[v] = p_gk[0] + Kb[0][0];
+    gk[NN + v] = p_gk[1] + Kb[1][1];
+    gk[2 * NN + v] = p_gk[2] + Kb[2][2];
+    gk[3 * NN + v] = p_gk[3] + (Kb[0][1] + Kb[1][0]);
+    gk[4 * NN + v] = p_gk[4] + (Kb[0][2] + Kb[2][0]);
+    gk[5 * NN + v] = p_gk[5] + (Kb[1][2] + Kb[2][1]);
   } else {
     // F = rho g - R_s u
     Rsb = -(u0 * Fb0 + u1 * Fb1 + u2 * Fb2);
