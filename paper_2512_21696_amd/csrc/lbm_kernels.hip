@@ -993,14 +993,26 @@ __global__ void k_flux(const ModelConsts mc, const T *__restrict__ post,
     const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const long long s0 = f0 ? L.slot(v0, mc.nx) : 0, s1 = f1 ? L.slot(v1, mc.nx) : 0;
     LBM_DCHECK(v0 < N && v1 < N && s0 < L.stride && s1 < L.stride, DC_FLUX);
+    // every value is loaded (the slots are valid for any voxel) and the
+    // links taken afterwards, so all loads of a thread are in flight at once
+    T p[NC][10];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      int n = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (cx(i) != 0) p[a][n++] = post[(size_t)(a * Q + i) * L.stride + (cx(i) == 1 ? s0 : s1)];
+    }
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double q = 0.0;
+      int n = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) q += (double)post[(size_t)(a * Q + i) * L.stride + s0];
-        if (cx(i) == -1 && f1 && !((m1 >> i) & 1u))
-          q -= (double)post[(size_t)(a * Q + i) * L.stride + s1];
+        if (cx(i) == 0) continue;
+        const double pv = (double)p[a][n++];
+        if (cx(i) == 1) q = f0 && !((m0 >> i) & 1u) ? q + pv : q;
+        else q = f1 && !((m1 >> i) & 1u) ? q - pv : q;
       }
       val[a] = q;
     }

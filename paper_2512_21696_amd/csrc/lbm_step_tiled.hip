@@ -1545,18 +1545,33 @@ __global__ void k_flux16(const ModelConsts mc, const uint16_t *__restrict__ code
     const uint32_t m0 = mask[v0], m1 = mask[v1];
     const bool f0 = ((m0 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
     const bool f1 = ((m1 >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    // every offset and reference is loaded (any voxel's slots are valid) and
+    // the links taken afterwards, so all loads of a thread are in flight at once
+    uint16_t cd[NC][10];
+    float ref[2][NC];
+#pragma unroll
+    for (int a = 0; a < NC; ++a) {
+      ref[0][a] = writer_ref(rhoE, v0, a, NC);
+      ref[1][a] = writer_ref(rhoE, v1, a, NC);
+      int n = 0;
+#pragma unroll
+      for (int i = 1; i < Q; ++i)
+        if (cx(i) != 0) cd[a][n++] = codes[(size_t)(a * Q + i) * N + (cx(i) == 1 ? v0 : v1)];
+    }
 #pragma unroll
     for (int a = 0; a < NC; ++a) {
       double q = 0.0;
+      int n = 0;
 #pragma unroll
       for (int i = 1; i < Q; ++i) {
-        if (cx(i) == 1 && f0 && !((m0 >> i) & 1u)) {
-          const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v0]);
-          q += (double)((float)wq(i) * (writer_ref(rhoE, v0, a, NC) + h));
-        }
-        if (cx(i) == -1 && f1 && !((m1 >> i) & 1u)) {
-          const float h = dec16<SK>(codes[(size_t)(a * Q + i) * N + v1]);
-          q -= (double)((float)wq(i) * (writer_ref(rhoE, v1, a, NC) + h));
+        if (cx(i) == 0) continue;
+        const float h = dec16<SK>(cd[a][n++]);
+        if (cx(i) == 1) {
+          const double pv = (double)((float)wq(i) * (ref[0][a] + h));
+          q = f0 && !((m0 >> i) & 1u) ? q + pv : q;
+        } else {
+          const double pv = (double)((float)wq(i) * (ref[1][a] + h));
+          q = f1 && !((m1 >> i) & 1u) ? q - pv : q;
         }
       }
       val[a] = q;
