@@ -265,6 +265,19 @@ int lbm_init_fluid(lbm_handle *h, const double *rho_w, const double *rho_o);
  * state holds NaN/Inf.  Errors: LBM_E_STATE (no fluid state), LBM_E_DEVICE. */
 int lbm_step(lbm_handle *h, int64_t n);
 
+/* lbm_step's n steps with the outlet flux of each step recorded: q_out (host,
+ * 2 n doubles, owned by the caller) receives Q^w and Q^o of step k at
+ * q_out[2k] and q_out[2k + 1] (Q^o = 0 with one component), the per-link
+ * count through the plane x_f | x_f + 1 that lbm_get_diagnostics reports as
+ * q_w, q_o (the outlet flux of the paper's displacement runs, Sec. III).  The
+ * steps run asynchronously; the call synchronises once, at the end, instead
+ * of once per step.  With params.track_flux the accumulated flux advances as
+ * with lbm_step; without it, it does not.  Errors: LBM_E_INVAL (n < 0, q_out
+ * NULL with n > 0), LBM_E_STATE (no fluid state), LBM_E_NOMEM (the device
+ * history of 2 n doubles), LBM_E_DEVICE, LBM_E_NONFINITE (as lbm_step; q_out
+ * is then not written). */
+int lbm_step_flux(lbm_handle *h, int64_t n, double *q_out);
+
 /* The fields of the workflow's step iii (Sec. I) and of Eq. (1): component
  * densities rho^a, velocity u, saturation Sw and the residual amounts.
  * Evaluates them at the current time level (see lbm_fields) and writes

@@ -120,7 +120,7 @@ class lbm_kernel_times(ctypes.Structure):
 
 
 EXPORTS = ["lbm_params_default", "lbm_validate_params", "lbm_create", "lbm_set_geometry",
-           "lbm_init_fluid", "lbm_step", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
+           "lbm_init_fluid", "lbm_step", "lbm_step_flux", "lbm_get_fields", "lbm_get_diagnostics", "lbm_get_setup",
            "lbm_state_size", "lbm_get_state", "lbm_set_state", "lbm_set_profiling",
            "lbm_get_kernel_times", "lbm_set_reservoirs", "lbm_rev_permeability",
            "lbm_rev_permeability_static", "lbm_rev_pc_sweep", "lbm_adjoint_flux",
@@ -152,6 +152,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_set_geometry": (ctypes.c_int, [vp, u8p, dp, u8p, P(lbm_pore_table), i32]),
         "lbm_init_fluid": (ctypes.c_int, [vp, dp, dp]),
         "lbm_step": (ctypes.c_int, [vp, i64]),
+        "lbm_step_flux": (ctypes.c_int, [vp, i64, ctypes.POINTER(ctypes.c_double)]),
         "lbm_get_fields": (ctypes.c_int, [vp, P(lbm_fields)]),
         "lbm_get_diagnostics": (ctypes.c_int, [vp, P(lbm_diag)]),
         "lbm_get_setup": (ctypes.c_int, [vp, dp, dp, dp, dp, dp]),
@@ -317,6 +318,14 @@ class Lbm:
 
     def step(self, n=1):
         self._check(self.lib.lbm_step(self.h, int(n)))
+
+    def step_flux(self, n) -> np.ndarray:
+        """n steps; the outlet flux of each, shape (n, 2): Q^w, Q^o per step
+        (one synchronisation for all of them)."""
+        q = np.zeros((int(n), 2), np.float64)
+        self._check(self.lib.lbm_step_flux(self.h, int(n),
+                                           q.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return q
 
     FIELD_NAMES = ("rho_w", "rho_o", "ux", "uy", "uz", "S", "r_w", "r_o")
 

@@ -28,10 +28,7 @@ class FluxHistory(torch.autograd.Function):
             if run.get("start_state") is not None:
                 lb.set_state(run["start_state"])
             start = lb.get_state()
-            q = np.zeros(int(run["steps"]), np.float64)
-            for n in range(q.size):
-                lb.step(1)
-                q[n] = lb.get_diagnostics()["q_w"]
+            q = lb.step_flux(int(run["steps"]))[:, 0].copy()
         except Exception:
             lb.destroy()
             raise

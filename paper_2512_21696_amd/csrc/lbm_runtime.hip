@@ -756,6 +756,43 @@ void open_faces16(lbm_handle *h) {
 
 // allow_push = false keeps the density pass on every step (the adjoint's
 // forward sweep, whose recomputations take the densities from it).
+// The outlet flux of the stored set (the step just taken): per-block partials,
+// then out[0..2) = the step's flux per component and, with accumulate,
+// out[2..4) += it.
+template <typename T>
+void launch_flux(lbm_handle *h, double *out, int accumulate) {
+  DevState<T> &s = state<T>(h);
+  const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
+  Timed tm(h, K_OTHER);
+  if (h->sk == SK_NATIVE) {
+    if (h->p.ncomp == 2)
+      hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                         s.mask, s.partial, pop_layout<T>(h));
+    else
+      hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
+                         s.mask, s.partial, pop_layout<T>(h));
+  } else if constexpr (std::is_same<T, float>::value) {
+    const uint16_t *c = s.fc[h->cur];
+    if (h->sk == SK_F16) {
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL((k_flux16<SK_F16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                           s.rhoE, s.mask, s.partial);
+      else
+        hipLaunchKernelGGL((k_flux16<SK_F16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                           s.rhoE, s.mask, s.partial);
+    } else {
+      if (h->p.ncomp == 2)
+        hipLaunchKernelGGL((k_flux16<SK_BF16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                           s.rhoE, s.mask, s.partial);
+      else
+        hipLaunchKernelGGL((k_flux16<SK_BF16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
+                           s.rhoE, s.mask, s.partial);
+    }
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0, out,
+                     accumulate);
+}
+
 template <typename T>
 int step_t(lbm_handle *h, int64_t n, bool allow_push) {
   DevState<T> &s = state<T>(h);
@@ -809,36 +846,7 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
     h->rho_valid = false;
     h->dec_valid = false;
     h->step += 1;
-    if (h->p.track_flux) {
-      Timed tm(h, K_OTHER);
-      if (h->sk == SK_NATIVE) {
-        if (h->p.ncomp == 2)
-          hipLaunchKernelGGL((k_flux<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                             s.mask, s.partial, pop_layout<T>(h));
-        else
-          hipLaunchKernelGGL((k_flux<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
-                             s.mask, s.partial, pop_layout<T>(h));
-      } else if constexpr (std::is_same<T, float>::value) {
-        const uint16_t *c = s.fc[h->cur];
-        if (h->sk == SK_F16) {
-          if (h->p.ncomp == 2)
-            hipLaunchKernelGGL((k_flux16<SK_F16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
-                               s.rhoE, s.mask, s.partial);
-          else
-            hipLaunchKernelGGL((k_flux16<SK_F16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
-                               s.rhoE, s.mask, s.partial);
-        } else {
-          if (h->p.ncomp == 2)
-            hipLaunchKernelGGL((k_flux16<SK_BF16, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
-                               s.rhoE, s.mask, s.partial);
-          else
-            hipLaunchKernelGGL((k_flux16<SK_BF16, 1>), dim3(fb), dim3(256), 0, h->st, h->mc, c,
-                               s.rhoE, s.mask, s.partial);
-        }
-      }
-      hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, h->st, s.partial, (int)fb, 2, 0, s.acc,
-                         1);
-    }
+    if (h->p.track_flux) launch_flux<T>(h, s.acc, 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return hip_check(h, e, "step launch");
     if (h->p.diag_every > 0 && h->step % h->p.diag_every == 0) {
@@ -852,6 +860,39 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
   }
   (void)N;
   return LBM_OK;
+}
+
+// n steps with the outlet flux of each recorded on the device (from the
+// accumulators when the handle tracks the flux, else by its own flux launch),
+// copied to the host once at the end.
+template <typename T>
+int step_flux_t(lbm_handle *h, int64_t n, double *q_out) {
+  DevState<T> &s = state<T>(h);
+  std::vector<void *> tmp;
+  bool ok = true;
+  double *hist = alloc_into<double>(h, tmp, (size_t)2 * (size_t)(n > 0 ? n : 1), &ok);
+  if (!ok) return set_err(h, LBM_E_NOMEM, "device allocation failed in lbm_step_flux");
+  int rc = LBM_OK;
+  for (int64_t k = 0; k < n && rc == LBM_OK; ++k) {
+    rc = step_t<T>(h, 1, true);
+    if (rc != LBM_OK) break;
+    if (h->p.track_flux)
+      rc = hip_check(h, hipMemcpyAsync(hist + 2 * k, s.acc, 2 * sizeof(double),
+                                       hipMemcpyDeviceToDevice, h->st),
+                     "copy step flux");
+    else
+      launch_flux<T>(h, hist + 2 * k, 0);
+  }
+  if (rc == LBM_OK) rc = hip_check(h, hipGetLastError(), "flux launch");
+  if (rc == LBM_OK && n > 0)
+    rc = hip_check(h, hipMemcpyAsync(q_out, hist, (size_t)2 * n * sizeof(double),
+                                     hipMemcpyDeviceToHost, h->st),
+                   "copy flux history");
+  // the history and the host copy complete before the buffer goes back
+  const int rs = hip_check(h, hipStreamSynchronize(h->st), "step_flux");
+  if (rc == LBM_OK) rc = rs;
+  for (void *p : tmp) dev_free(h, p);
+  return rc;
 }
 
 template <typename T>
@@ -1222,6 +1263,16 @@ extern "C" int lbm_step(lbm_handle *h, int64_t n) {
   if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
   return dcheck(h, h->p.precision == LBM_PREC_F64 ? step_t<double>(h, n, true)
                                                   : step_t<float>(h, n, true));
+}
+
+extern "C" int lbm_step_flux(lbm_handle *h, int64_t n, double *q_out) {
+  const Range range("lbm_step_flux");
+  if (!h) return LBM_E_INVAL;
+  if (n < 0) return set_err(h, LBM_E_INVAL, "n must be >= 0");
+  if (n > 0 && !q_out) return set_err(h, LBM_E_INVAL, "q_out is NULL");
+  if (!h->has_fluid) return set_err(h, LBM_E_STATE, "lbm_init_fluid must come first");
+  return dcheck(h, h->p.precision == LBM_PREC_F64 ? step_flux_t<double>(h, n, q_out)
+                                                  : step_flux_t<float>(h, n, q_out));
 }
 
 extern "C" int lbm_get_fields(lbm_handle *h, const lbm_fields *out) {

@@ -80,6 +80,8 @@ int main(void) {
   expect(lbm_set_geometry(NULL, cls, NULL, NULL, NULL, 0), LBM_E_INVAL, "geometry NULL");
   expect(lbm_init_fluid(NULL, rho, rho), LBM_E_INVAL, "init NULL");
   expect(lbm_step(NULL, 1), LBM_E_INVAL, "step NULL");
+  double qf[4];
+  expect(lbm_step_flux(NULL, 1, qf), LBM_E_INVAL, "step flux NULL");
   expect(lbm_get_fields(NULL, &fo), LBM_E_INVAL, "fields NULL");
   expect(lbm_get_diagnostics(NULL, &d), LBM_E_INVAL, "diagnostics NULL");
   expect(lbm_get_setup(NULL, rho, NULL, NULL, NULL, NULL), LBM_E_INVAL, "setup NULL");
@@ -105,8 +107,12 @@ int main(void) {
     cls[3] = 0;
     expect(lbm_set_geometry(h, cls, NULL, NULL, NULL, 0), LBM_OK, "geometry");
     expect(lbm_step(h, 1), LBM_E_STATE, "step before fluid");
+    expect(lbm_step_flux(h, 1, qf), LBM_E_STATE, "step flux before fluid");
     expect(lbm_init_fluid(h, rho, rho), LBM_OK, "init");
     expect(lbm_step(h, 2), LBM_OK, "step");
+    expect(lbm_step_flux(h, -1, qf), LBM_E_INVAL, "step flux n < 0");
+    expect(lbm_step_flux(h, 1, NULL), LBM_E_INVAL, "step flux NULL output");
+    expect(lbm_step_flux(h, 2, qf), LBM_OK, "step flux");
     expect(lbm_get_diagnostics(h, &d), LBM_OK, "diagnostics");
     expect(lbm_state_size(h, &bytes), LBM_OK, "state size");
     expect(lbm_get_state(h, buf, sizeof buf), LBM_E_INVAL, "state buffer too small");
