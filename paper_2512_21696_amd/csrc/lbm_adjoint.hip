@@ -1166,7 +1166,7 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
   // every load of both components before the first store: the stores go to
   // the same array (rows 11..16), so loads after them could not move ahead
   T cb[2][Q];  // [a][0]: this voxel's curvature adjoint, [a][i]: x = y - c_i's
-  double g[2][3], n[2][3], sg[2][3];
+  double g[2][3], n[2][3], sg[2][3], sp[2][3];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
     cb[a][0] = stash[(size_t)(9 + a) * N + v];
@@ -1177,6 +1177,7 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
       g[a][d] = (double)nrmb[(size_t)(6 * a + d) * N + v];
       n[a][d] = (double)nrmb[(size_t)(6 * a + 3 + d) * N + v];
       sg[a][d] = (double)stash[(size_t)(11 + 3 * a + d) * N + v];
+      sp[a][d] = (double)stash[(size_t)(3 * a + d) * N + v];  // pseudo-potential rows
     }
   }
 #pragma unroll
@@ -1197,9 +1198,36 @@ __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
     if (n2 > mc.eps_n * mc.eps_n) {
       const double in = 1.0 / sqrt(n2);
       const double nn = n[a][0] * nbar[0] + n[a][1] * nbar[1] + n[a][2] * nbar[2];
-      for (int d = 0; d < 3; ++d)
-        stash[(size_t)(11 + 3 * a + d) * N + v] = (T)(sg[a][d] + (nbar[d] - nn * n[a][d]) * in);
+#pragma unroll
+      for (int d = 0; d < 3; ++d) sg[a][d] = (double)(T)(sg[a][d] + (nbar[d] - nn * n[a][d]) * in);
     }
+  }
+  // The neighbours' part reads, per link, the pseudo-potential row and the
+  // density-gradient row of the same component with weights w_i and
+  // w_i / cs2 = 3 w_i: it gets their sum (rows 0..5 <- rows 0..5 + 3 rows
+  // 11..16) and, in rows 11 and 12, this voxel's own part, the sum over its
+  // solid links (the gradient's read of its own density; links whose other
+  // end lies across an open face are not taken) of (w_i / cs2) c_i . row.
+  double own[2] = {0.0, 0.0};
+#pragma unroll
+  for (int i = 1; i < Q; ++i) {
+    const bool across = mc.open_x && cx(i) != 0 && (nb.x - cx(i) < 0 || nb.x - cx(i) >= mc.nx);
+    if (!((mk >> i) & 1u) || across) continue;
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double t = 0;
+      if (cx(i)) t += cx(i) * sg[a][0];
+      if (cy(i)) t += cy(i) * sg[a][1];
+      if (cz(i)) t += cz(i) * sg[a][2];
+      own[a] += gw(i) * t;
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int d = 0; d < 3; ++d)
+      stash[(size_t)(3 * a + d) * N + v] = (T)(sp[a][d] + 3.0 * sg[a][d]);
+    stash[(size_t)(11 + a) * N + v] = (T)own[a];
   }
 }
 
@@ -1221,17 +1249,12 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
   const long long v = xcd_voxel();
   if (v >= N) return;
   if (((mask[v] >> CLASS_SHIFT) & 3u) == SOLID_CODE) return;  // stays zero
-  const uint32_t mk = mask[v];
   const Nbr nb((int)v, mc.nx, mc.ny, mc.nz);
-  // (CSF) this voxel's own density-gradient adjoints, which its solid links read
-  double own[2][3] = {{0, 0, 0}, {0, 0, 0}};
-  if (CSF) {
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      own[0][d] = (double)stash[(size_t)(11 + d) * N + v];
-      own[1][d] = (double)stash[(size_t)(14 + d) * N + v];
-    }
-  }
+  // (CSF) the normals' reverse has added 3 x the density-gradient rows to the
+  // pseudo-potential rows (both read with w_i and w_i / cs2 = 3 w_i) and left
+  // this voxel's solid-link part in rows 11 and 12
+  const double own1 = CSF ? (double)stash[(size_t)11 * N + v] : 0.0;
+  const double own0 = CSF ? (double)stash[(size_t)12 * N + v] : 0.0;
   double r0 = 0, r1 = 0, shb = 0;
 #pragma unroll
   for (int i = 1; i < Q; ++i) {
@@ -1245,27 +1268,15 @@ __global__ __launch_bounds__(256) void k_adj_nl2(const ModelConsts mc,
       if (cz(i)) s += cz(i) * (double)stash[(size_t)(c0 + 2) * N + at];
       return s;
     };
-    auto dot_own = [&](int a) {
-      double s = 0;
-      if (cx(i)) s += cx(i) * own[a][0];
-      if (cy(i)) s += cy(i) * own[a][1];
-      if (cz(i)) s += cz(i) * own[a][2];
-      return s;
-    };
     const double d0 = dot(0, x), d3 = dot(3, x), d6 = dot(6, x);
-    r1 = across ? r1 : r1 + wq(i) * d0;  // water's force reads psi^o
-    r0 = across ? r0 : r0 + wq(i) * d3;  // oil's force reads psi^w
+    // water's force reads psi^o (and, CSF, g^w = grad rho^o), oil's psi^w
+    // (g^o = grad rho^w)
+    r1 = across ? r1 : r1 + wq(i) * d0;
+    r0 = across ? r0 : r0 + wq(i) * d3;
     shb = across ? shb : shb + gw(i) * d6;
-    if (CSF) {
-      // g^w = grad rho^o, g^o = grad rho^w; a solid link of this voxel reads
-      // its own density
-      const bool wall = (mk >> i) & 1u;
-      const double d11 = dot(11, x), d14 = dot(14, x);
-      const double w11 = wall ? dot_own(0) : 0.0, w14 = wall ? dot_own(1) : 0.0;
-      r1 = across ? r1 : r1 + gw(i) * (d11 + w11);
-      r0 = across ? r0 : r0 + gw(i) * (d14 + w14);
-    }
   }
+  r1 += own1;
+  r0 += own0;
   const double aw = (double)rho2[2 * v], ao = (double)rho2[2 * v + 1];
   const double tt = aw + ao, span = 1.0 / mc.inv_span;
   rnl[2 * v] = (T)(r0 + shb / span * ao / (tt * tt));
