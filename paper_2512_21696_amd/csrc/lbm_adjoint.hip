@@ -487,16 +487,27 @@ __global__ __launch_bounds__(256) void k_adj_step2(
   const uint32_t N32 = (uint32_t)N, v32 = (uint32_t)v;
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
-    const T *pa = post + (size_t)a * Q * N;
-    const T *la = lin + (size_t)a * Q * N;
     rho[a] = 0; L0[a] = 0; lf[a] = 0;
     for (int d = 0; d < 3; ++d) { m[a][d] = 0; L1[a][d] = 0; }
     for (int d = 0; d < 6; ++d) { M2[a][d] = 0; Pi[a][d] = 0; }
+  }
+  // one direction at a time for both components (each component's sums keep
+  // their order): the addresses serve both, and the neighbour's dL/drho pair
+  // is one load
+  const vec2<T> *rnl2 = reinterpret_cast<const vec2<T> *>(rnl);
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-      const int j = opp(i);
-      const uint32_t src = ((mk >> j) & 1u) ? (uint32_t)j * N32 + v32
-                                            : (uint32_t)i * N32 + (uint32_t)nb.at(-cx(i), -cy(i), -cz(i));
+  for (int i = 0; i < Q; ++i) {
+    const int j = opp(i);
+    const uint32_t src = ((mk >> j) & 1u) ? (uint32_t)j * N32 + v32
+                                          : (uint32_t)i * N32 + (uint32_t)nb.at(-cx(i), -cy(i), -cz(i));
+    const bool wall = (mk >> i) & 1u;
+    const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
+    const uint32_t li = wall ? (uint32_t)j * N32 + v32 : (uint32_t)i * N32 + y;
+    const vec2<T> rn = rnl2[y];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const T *pa = post + (size_t)a * Q * N;
+      const T *la = lin + (size_t)a * Q * N;
       const AT fi = (AT)pa[src];
       rho[a] += fi;
       if (cx(i)) m[a][0] += cx(i) * fi;
@@ -510,10 +521,7 @@ __global__ __launch_bounds__(256) void k_adj_step2(
         if (cx(i) && cz(i)) Pi[a][4] += (cx(i) * cz(i)) * fi;
         if (cy(i) && cz(i)) Pi[a][5] += (cy(i) * cz(i)) * fi;
       }
-      const bool wall = (mk >> i) & 1u;
-      const uint32_t y = wall ? v32 : (uint32_t)nb.at(cx(i), cy(i), cz(i));
-      const uint32_t li = wall ? (uint32_t)j * N32 + v32 : (uint32_t)i * N32 + y;
-      AT l = (AT)la[li] + (AT)rnl[2 * y + a];
+      AT l = (AT)la[li] + (AT)(a == 0 ? rn.x : rn.y);
       if (a == 0 && cx(i) == 1 && at0 && !wall) l += an;
       if (a == 0 && cx(i) == -1 && at1 && !wall) l -= an;
       if (!REG) {
