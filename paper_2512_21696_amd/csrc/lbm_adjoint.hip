@@ -1159,7 +1159,9 @@ __global__ __launch_bounds__(256) void k_adj_inputs2(const ModelConsts mc,
 // CSF normals' reverse at a fluid voxel y: dL/dn^a(y) gathered from the
 // curvature reads of the voxels x = y - c_i (and of y itself across its solid
 // links), carried to dL/dg^a(y) through n = g / |g|, added to the force
-// term's own dL/dg^a(y) (stash rows 11..16, updated in place).
+// term's own dL/dg^a(y) (stash rows 11..16).  It then leaves the neighbour
+// part what it reads: rows 0..5 become rows 0..5 + 3 x rows 11..16, and rows
+// 11, 12 this voxel's own solid-link part of each component's sum.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_normals_rev(const ModelConsts mc,
                                                          const T *__restrict__ nrmb,
