@@ -1,8 +1,8 @@
 """Reference gradients of the outlet-flux history with respect to the gray
 porosity, for the one-component model (pore, gray and solid voxels, scalar
 K0(phi) or the tensorial resistivity of Eqs. (6)-(7), regularised or BGK
-collision, trapezoidal resistance, body force; periodic x faces or exact
-density faces as in model.Oracle).  TEST
+collision, trapezoidal resistance, body force; periodic x faces, pressure
+reservoirs or exact density faces as in model.Oracle).  TEST
 INFRASTRUCTURE ONLY (tests, smoke check, benchmark baseline).
 
 The step is the one of model.Oracle with one component, and the tensor set-up
@@ -178,10 +178,11 @@ class OneComponent:
         self.g = [float(v) for v in p.g[0]]
         self.tensor = bool(getattr(p, "tensor", False))
         self.src_solid = [_sh(self.solid, C[i], -1) for i in range(Q)]
-        self.faces = getattr(p, "bc_x", "periodic") == "density"
-        if getattr(p, "bc_x", "periodic") == "pressure":
-            raise ValueError("the reference gradient takes periodic or exact density faces")
-        if self.faces:
+        bc = getattr(p, "bc_x", "periodic")
+        self.faces = bc == "density"
+        self.res = bc == "pressure"
+        self.open_x = self.faces or self.res
+        if self.open_x:
             # a pull across an x face reads the slot the face step wrote, never
             # bounce-back
             nx = self.shape[2]
@@ -247,9 +248,42 @@ class OneComponent:
         Qn = (self.flux_w * post).sum()
         if self.faces:
             post = self._density_faces(post, 0)
+        elif self.res:
+            post = self._reservoirs([post])[0]
         new = torch.stack([torch.where(self.src_solid[i], post[OPP[i]], _sh(post[i], C[i], -1))
                            for i in range(Q)])
         return torch.where(fl, new, torch.zeros_like(new)), Qn
+
+    def _reservoirs(self, posts):
+        """Pressure reservoirs (model.Oracle._reservoirs) on the post sets of
+        all components: the slots across the periodic wrap that the boundary
+        voxels pull take the equilibrium at the reservoir density and at the
+        mixture velocity of the boundary voxel of the same (y, z) row (zero
+        when it is solid); the inlet sends c_x = +1, the outlet c_x = -1."""
+        p = self.p
+        nx = self.shape[2]
+        ends = []
+        for x in (0, nx - 1):
+            rho = sum(post[:, :, :, x].sum(0) for post in posts)
+            mom = [sum(C[i, d] * post[i][:, :, x] for post in posts for i in range(Q) if C[i, d])
+                   for d in range(3)]
+            fl = self.fluid[:, :, x]
+            safe = torch.where(fl, rho, torch.ones_like(rho))
+            ends.append([torch.where(fl, mom[d] / safe, torch.zeros_like(rho)) for d in range(3)])
+        out = []
+        for a, post in enumerate(posts):
+            feq = [_equilibrium(torch.full_like(ends[0][0], float(r)), u)
+                   for r, u in ((p.rho_in[a], ends[0]), (p.rho_out[a], ends[1]))]
+            slots = [post[i] for i in range(Q)]
+            for i in range(Q):
+                if C[i, 0] == 0:
+                    continue
+                e, col = (0, nx - 1) if C[i, 0] > 0 else (1, 0)
+                plane = [slots[i][:, :, x] for x in range(nx)]
+                plane[col] = feq[e][i]
+                slots[i] = torch.stack(plane, dim=-1)
+            out.append(torch.stack(slots))
+        return out
 
     def _density_faces(self, post, a):
         """Exact density faces (model.Oracle._density_faces) for component a:
@@ -326,10 +360,10 @@ class TwoComponent(OneComponent):
         self.gs = [[float(v) for v in p.g[a]] for a in range(2)]
         self.r = torch.as_tensor(np.asarray(r, np.float64))
         self.nb_solid = [_sh(self.solid, C[i]) for i in range(Q)]
-        # density faces: a neighbour across an x face is the reservoir cell
+        # open faces: a neighbour across an x face is the reservoir cell
         # (fluid, at the face's prescribed density), as in model.Oracle
         self.cross_nb = [None] * Q
-        if self.faces:
+        if self.open_x:
             nx = self.shape[2]
             for i in range(1, Q):
                 if C[i, 0] != 0:
@@ -532,6 +566,8 @@ class TwoComponent(OneComponent):
         Qn = (self.flux_w * posts[0]).sum()
         if self.faces:
             posts = [self._density_faces(posts[a], a) for a in range(2)]
+        elif self.res:
+            posts = self._reservoirs(posts)
         new = []
         for a in range(2):
             na = torch.stack([torch.where(self.src_solid[i], posts[a][OPP[i]],

@@ -312,9 +312,10 @@ def test_two_component_with_residual_events(kappa, region):
     assert checked == 3
 
 
-def faces_case(seed=11):
-    """One component between exact density faces: a gray slab (x = 4..6) with
-    solid grains, no body force, the flow driven by rho_in > rho_out."""
+def faces_case(seed=11, bc="density"):
+    """One component between open x faces (exact density faces or pressure
+    reservoirs): a gray slab (x = 4..6) with solid grains, no body force, the
+    flow driven by rho_in > rho_out."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = 4, 6, 11
     cls = np.zeros((nz, ny, nx), np.uint8)
@@ -324,21 +325,23 @@ def faces_case(seed=11):
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
     K0 = W.kozeny_carman_table(2.0)
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
-    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, bc_x="density",
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, bc_x=bc,
                  rho_in=(1.01, 0.0), rho_out=(0.99, 0.0), outlet_x=7).filled()
     return p, cls, phi, np.zeros(cls.shape, np.uint8), tabs
 
 
-def test_torch_forward_with_density_faces_equals_oracle():
-    p, cls, phi, pt, tabs = faces_case()
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+def test_torch_forward_with_open_faces_equals_oracle(bc):
+    p, cls, phi, pt, tabs = faces_case(bc=bc)
     f0, qs, fN = oracle_history(p, cls, phi, pt, tabs, 15)
     hist, _, f_t = A.flux_gradient(p, cls, phi, pt, tabs, f0, 15, np.ones(15))
     assert np.abs(hist - qs).max() < 1e-14
     assert np.abs(f_t - fN).max() < 1e-14
 
 
-def test_gradient_with_density_faces_matches_oracle_finite_differences():
-    p, cls, phi, pt, tabs = faces_case()
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+def test_gradient_with_open_faces_matches_oracle_finite_differences(bc):
+    p, cls, phi, pt, tabs = faces_case(bc=bc)
     steps = 12
     a = np.linspace(1.0, 2.0, steps)
     f0, _, _ = oracle_history(p, cls, phi, pt, tabs, 1)
@@ -366,15 +369,9 @@ def test_gradient_with_density_faces_matches_oracle_finite_differences():
     assert checked == 3
 
 
-def test_reference_gradient_rejects_reservoir_faces():
-    p, cls, phi, pt, tabs = faces_case()
-    p.bc_x = "pressure"
-    with pytest.raises(ValueError):
-        A.OneComponent(p, cls, pt, tabs)
-
-
-def two_faces_case(seed=13):
-    """Two components between exact density faces (22 x 8 x 6): water enters at
+def two_faces_case(seed=13, bc="density"):
+    """Two components between open x faces (exact density faces or pressure
+    reservoirs; 22 x 8 x 6): water enters at
     x = 0 (rho_in = (1.02, m)) against oil held at x = nx - 1 (rho_out =
     (m, 1.0)); grains and gray voxels (two pore types) keep two planes away
     from both faces; no body force, kappa = 0."""
@@ -391,15 +388,16 @@ def two_faces_case(seed=13):
             for lam in (1.0, 2.0)]
     m = W.minority_density(3.0)
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
-                 bc_x="density", rho_in=(1.02, m), rho_out=(m, 1.0), outlet_x=12).filled()
+                 bc_x=bc, rho_in=(1.02, m), rho_out=(m, 1.0), outlet_x=12).filled()
     x = np.arange(nx)[None, None, :]
     noise = 0.005 * rng.random(cls.shape)
     rw = np.where(x < 6, 1.0 - noise, m + noise)
     return p, cls, phi, pt, tabs, rw, 1.0 + m - rw
 
 
-def test_two_component_forward_with_density_faces_equals_oracle():
-    p, cls, phi, pt, tabs, rw, ro = two_faces_case()
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+def test_two_component_forward_with_open_faces_equals_oracle(bc):
+    p, cls, phi, pt, tabs, rw, ro = two_faces_case(bc=bc)
     f0, r0, q, fN, events = _two_history(p, cls, phi, pt, tabs, rw, ro, 10)
     assert events == 0
     hist, _, f_t = A.flux_gradient2(p, cls, phi, pt, tabs, f0, r0, 10, np.ones(10))
@@ -407,8 +405,9 @@ def test_two_component_forward_with_density_faces_equals_oracle():
     assert np.abs(f_t - fN).max() < 1e-14
 
 
-def test_two_component_gradient_with_density_faces_matches_finite_differences():
-    p, cls, phi, pt, tabs, rw, ro = two_faces_case()
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+def test_two_component_gradient_with_open_faces_matches_finite_differences(bc):
+    p, cls, phi, pt, tabs, rw, ro = two_faces_case(bc=bc)
     steps = 10
     a = np.linspace(1.0, 2.0, steps)
     f0, r0, _, _, _ = _two_history(p, cls, phi, pt, tabs, rw, ro, 1)
