@@ -514,10 +514,12 @@ int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_tabl
  * components phi also enters the capillary term through the Leverett-J factor
  * s_J(phi) (Eq. (5)).  Calibrating phi (or the tables) against an observed flux
  * needs dL/dphi.  For one or two components (with the CSF control of Eq. (4)
- * and the residual transfer; scalar K0 or tensor = 1; periodic x faces, or
- * exact density faces (LBM_BC_DENSITY), whose face step is linear in the face
- * voxels' known pulls and is reversed by its transpose; native fp64 or fp32
- * storage) and a loss
+ * and the residual transfer; scalar K0 or tensor = 1; periodic x faces, exact
+ * density faces (LBM_BC_DENSITY), whose face step is linear in the face
+ * voxels' known pulls and is reversed by its transpose, or pressure reservoirs
+ * (LBM_BC_PRESSURE), whose equilibrium at the boundary voxel's mixture
+ * velocity is differentiated at the velocity each forward step recorded;
+ * native fp64 or fp32 storage) and a loss
  * L = sum_n dL_dQ[n] Q(n) over the outlet fluxes Q(1..nsteps) of the next
  * nsteps steps from the current state (Q(n) is lbm_diag.q_w after step n: the
  * first component's post-collision populations of step n crossing
@@ -562,13 +564,14 @@ int lbm_rev_pc_sweep(const lbm_pc_params *p, const lbm_pore_table *membrane_tabl
  * K0) or 20 N doubles (tensor), and for two components, per kept level, the
  * residual amounts and side flags (2 N values of the storage type and N
  * bytes), plus 15 N (kappa != 0: 35 N) values of the storage type and 5 N
- * doubles.  The adjoint populations are kept
+ * doubles; with pressure reservoirs also 8 ny nz doubles per step (the
+ * boundary voxels' densities and velocities).  The adjoint populations are kept
  * in the storage type, the reverse arithmetic and the gradient accumulation in
  * fp64.
  * The handle ends nsteps steps on, exactly as after lbm_step(nsteps) (step
  * counter and flux accumulators included).  Synchronises the stream.
  * Errors: LBM_E_INVAL (argument out of range; nothing runs), LBM_E_STATE (no
- * fluid state), LBM_E_UNSUPPORTED (reservoir x faces, 16-bit storage),
+ * fluid state), LBM_E_UNSUPPORTED (16-bit storage),
  * LBM_E_NOMEM, LBM_E_DEVICE, LBM_E_NONFINITE (from a forward step's diagnostics; a failure inside the last
  * segment's forward steps leaves the handle without a fluid state). */
 int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_dQ,

@@ -103,6 +103,83 @@ __global__ __launch_bounds__(256) void k_adj_density_faces(const ModelConsts mc,
   }
 }
 
+// Pressure reservoirs: the transpose of the reservoir face step on the
+// adjoint of the next level (lam, indexed like the pulled values).  The step
+// wrote, into the slots across the periodic wrap that the boundary voxels
+// pull, f_i = w_i rho_res (1 + 3 c_i.u + 4.5 (c_i.u)^2 - 1.5 u.u) with u the
+// mixture velocity m / rho of the post-collision sets (both components) of
+// the boundary voxel of the same (y, z) row (zero when it is solid); rec holds
+// that rho and u per step (k_res_record).  Reverse, per row end: dL/du is the
+// sum over the written slots of their adjoint times
+// w_i rho_res (3 c_i + 9 (c_i.u) c_i - 3 u); the written slots' adjoint
+// becomes zero (the values they held reach nothing); then every post-collision
+// value f_j^b of a fluid boundary voxel gets (c_j - u).dL/du / rho.  The
+// adjoint of a post-collision value is the entry of the voxel that pulls it
+// (x + c_j in direction j, or the voxel's own entry in direction opp(j) across
+// a solid link; a link across an x face is never one) plus, with two
+// components, that puller's rnl (the adjoint of its next density, which the
+// reverse step adds to each of its pulls): a zeroed slot takes -rnl.  Both
+// ends' dL/du are taken before any value gets its share, since each end's
+// written slots are values of the other end.  One thread per (y, z) row; it
+// touches only the entries of its row's two boundary voxels, so rows do not
+// overlap.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_reservoirs(const ModelConsts mc,
+                                                        T *__restrict__ lam,
+                                                        const T *__restrict__ rnl,
+                                                        const uint32_t *__restrict__ mask,
+                                                        const double *__restrict__ rec) {
+  const long long N = mc.N;
+  const int nx = mc.nx, ny = mc.ny, nz = mc.nz;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= ny * nz) return;
+  const int y = k % ny, z = k / ny;
+  const double *const rk = rec + 8LL * k;
+  double ub[2][3] = {{0, 0, 0}, {0, 0, 0}};
+  for (int e = 0; e < 2; ++e) {
+    const int s = e == 0 ? 1 : -1;          // c_x of the directions the reservoir sends
+    const int xp = e == 0 ? 0 : nx - 1;     // the plane that pulls them
+    const double *const u = rk + 4 * e + 1;
+    for (int a = 0; a < mc.ncomp; ++a) {
+      // the reservoir density and the weights as the forward rounds them
+      const double r = (double)(T)(e == 0 ? mc.rho_in[a] : mc.rho_out[a]);
+#pragma unroll
+      for (int i = 1; i < Q; ++i) {
+        if (cx(i) != s) continue;
+        const int yy = (y + cy(i) + ny) % ny, zz = (z + cz(i) + nz) % nz;
+        const long long w = xp + (long long)nx * (yy + (long long)ny * zz);
+        T *const li = lam + ((size_t)a * Q + i) * N + w;
+        const T rn = rnl ? rnl[2 * w + a] : (T)0;
+        const double pb = (double)*li + (double)rn;
+        const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];
+        const double sc = pb * (double)(T)wq(i) * r;
+        ub[e][0] += sc * (3.0 * cx(i) + 9.0 * cu * cx(i) - 3.0 * u[0]);
+        ub[e][1] += sc * (3.0 * cy(i) + 9.0 * cu * cy(i) - 3.0 * u[1]);
+        ub[e][2] += sc * (3.0 * cz(i) + 9.0 * cu * cz(i) - 3.0 * u[2]);
+        *li = -rn;
+      }
+    }
+  }
+  for (int e = 0; e < 2; ++e) {
+    const long long vb = (e == 0 ? 0 : nx - 1) + (long long)nx * (y + (long long)ny * z);
+    const uint32_t mk = mask[vb];
+    if (((mk >> CLASS_SHIFT) & 3u) == SOLID_CODE) continue;  // u = 0 whatever its values
+    const double rho = rk[4 * e];
+    const double *const u = rk + 4 * e + 1;
+    const double base = -(u[0] * ub[e][0] + u[1] * ub[e][1] + u[2] * ub[e][2]) / rho;
+    const Nbr nb((int)vb, nx, ny, nz);
+    for (int b = 0; b < mc.ncomp; ++b)
+#pragma unroll
+      for (int j = 0; j < Q; ++j) {
+        const bool wall = (mk >> j) & 1u;
+        const size_t t = wall ? ((size_t)b * Q + opp(j)) * N + vb
+                              : ((size_t)b * Q + j) * N + nb.at(cx(j), cy(j), cz(j));
+        const double add = (cx(j) * ub[e][0] + cy(j) * ub[e][1] + cz(j) * ub[e][2]) / rho + base;
+        lam[t] = (T)((double)lam[t] + add);
+      }
+  }
+}
+
 // The adjoint populations are stored in the state's type (fp64 or fp32); the
 // arithmetic is fp64 throughout and dL/dK0 accumulates in fp64.  One thread
 // per voxel; the grid is a multiple of 8 blocks and block b takes the voxel
@@ -1593,17 +1670,23 @@ void launch_adj_step2_t(lbm_handle *h, const T *post, const T *lin, T *lout, dou
 
 // One reverse step: one component, or (two components) the density pass of
 // the level, the local reverse and the gather of the neighbours' part.
+// With pressure reservoirs, res holds the step's boundary densities and
+// velocities (k_res_record).
 template <typename T>
 void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double *gk, double a,
-                    const Rev2<T> &b) {
+                    const Rev2<T> &b, const double *res) {
   DevState<T> &s = state<T>(h);
   const bool reg = h->p.collision == LBM_COLL_REGULARIZED;
   const bool ten = h->p.tensor != 0;
+  const unsigned rb = blocks((long long)h->p.ny * h->p.nz);
   if (h->p.ncomp == 1) {
     Timed tm(h, K_ADJ);
     if (h->mc.exact_density)
       hipLaunchKernelGGL((adj::k_adj_density_faces<T>), dim3(blocks(2LL * h->p.ny * h->p.nz)),
                          dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), (T *)nullptr, s.mask);
+    else if (res)
+      hipLaunchKernelGGL((adj::k_adj_reservoirs<T>), dim3(rb), dim3(256), 0, h->st, h->mc,
+                         const_cast<T *>(lin), (const T *)nullptr, s.mask, res);
     if (ten) {
       if (reg) launch_adj_step_t<T, true, true>(h, post, lin, lout, gk, a);
       else launch_adj_step_t<T, false, true>(h, post, lin, lout, gk, a);
@@ -1617,6 +1700,10 @@ void launch_reverse(lbm_handle *h, const T *post, const T *lin, T *lout, double 
     Timed tm(h, K_ADJ);
     hipLaunchKernelGGL((adj::k_adj_density_faces<T>), dim3(blocks(2LL * h->p.ny * h->p.nz)),
                        dim3(256), 0, h->st, h->mc, const_cast<T *>(lin), b.rnl_in, s.mask);
+  } else if (res) {
+    Timed tm(h, K_ADJ);
+    hipLaunchKernelGGL((adj::k_adj_reservoirs<T>), dim3(rb), dim3(256), 0, h->st, h->mc,
+                       const_cast<T *>(lin), (const T *)b.rnl_in, s.mask, res);
   }
   {
     Timed tm(h, K_AUX);
@@ -1686,6 +1773,9 @@ void launch_recompute(lbm_handle *h, const T *fin, T *fout, T *rout = nullptr,
     if (h->mc.exact_density)
       hipLaunchKernelGGL((k_density_faces<T, 2>), dim3(blocks(2LL * h->p.ny * h->p.nz)), dim3(256),
                          0, h->st, h->mc, fout, s.mask);
+    else if (h->mc.open_x)
+      hipLaunchKernelGGL((k_reservoirs<T, 2>), dim3(blocks((long long)h->p.ny * h->p.nz)),
+                         dim3(256), 0, h->st, h->mc, fout, s.mask);
     return;
   }
   Timed tm(h, K_STEP);
@@ -1694,6 +1784,9 @@ void launch_recompute(lbm_handle *h, const T *fin, T *fout, T *rout = nullptr,
   if (h->mc.exact_density)  // the face populations, as the step applies them
     hipLaunchKernelGGL((k_density_faces<T, 1>), dim3(blocks(2LL * h->p.ny * h->p.nz)), dim3(256), 0,
                        h->st, h->mc, fout, s.mask);
+  else if (h->mc.open_x)
+    hipLaunchKernelGGL((k_reservoirs<T, 1>), dim3(blocks((long long)h->p.ny * h->p.nz)),
+                       dim3(256), 0, h->st, h->mc, fout, s.mask);
 }
 
 // dL/dK^-1 (tensor runs) back to dL/dK0 and to the porosity through the
@@ -1771,6 +1864,10 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   double *gbase = h->p.tensor ? alloc_into<double>(h, tmp, (size_t)N, &ok) : nullptr;
   double *gp = alloc_into<double>(h, tmp, (size_t)N, &ok);
   double *qh = alloc_into<double>(h, tmp, (size_t)2 * n, &ok);
+  // pressure reservoirs: every step's boundary densities and velocities
+  const size_t RR = (size_t)8 * h->p.ny * h->p.nz;
+  double *resv = h->mc.open_x && !h->mc.exact_density
+                     ? alloc_into<double>(h, tmp, (size_t)n * RR, &ok) : nullptr;
   // two components: the residual amounts and side flags of every kept level
   // (checkpoints and ring, like the populations), the reverse's buffers
   T *dens = nullptr, *stash = nullptr, *rnl = nullptr, *ckR = nullptr, *ringR = nullptr,
@@ -1795,6 +1892,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
     gth = alloc_into<double>(h, tmp, (size_t)2 * N, &ok);
   }
   auto finish = [&](int rc) {
+    h->res_rec = nullptr;
     (void)hipStreamSynchronize(h->st);
     for (void *p : tmp) dev_free(h, p);
     return rc;
@@ -1819,6 +1917,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   // pointers are swapped for it and put back at the end), so that segment is
   // not recomputed, and checkpoint_every = nsteps recomputes nothing.
   T *const own0 = s.f[0], *const own1 = s.f[1];
+  h->res_rec = resv;
   for (int64_t sg = 0; sg < nseg && rc == LBM_OK; ++sg) {
     rc = hip_check(h, hipMemcpyAsync(ck + sg * SN, s.f[h->cur], SN * sizeof(T),
                                      hipMemcpyDeviceToDevice, h->st),
@@ -1854,6 +1953,7 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
       }
     }
   }
+  h->res_rec = nullptr;
   // reverse sweep; the loss does not depend on the set after the last step
   if (rc == LBM_OK)
     rc = hip_check(h, hipMemsetAsync(lam, 0, 2 * SN * sizeof(T), h->st), "clear adjoint");
@@ -1906,7 +2006,8 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
         b.lr = lr;
         b.gth = gth;
       }
-      launch_reverse<T>(h, level(k), lam + cl * SN, lam + (1 - cl) * SN, gk, dLdQ[sg * K + k], b);
+      launch_reverse<T>(h, level(k), lam + cl * SN, lam + (1 - cl) * SN, gk, dLdQ[sg * K + k], b,
+                        resv ? resv + (size_t)(sg * K + k) * RR : nullptr);
       cl = 1 - cl;
     }
     rc = hip_check(h, hipGetLastError(), "adjoint launches");
@@ -1955,9 +2056,8 @@ extern "C" int lbm_adjoint_flux(lbm_handle *h, int64_t nsteps, const double *dL_
   for (int64_t k = 0; k < nsteps; ++k)
     if (!std::isfinite(dL_dQ[k]))
       return set_err(h, LBM_E_INVAL, "adjoint_flux: non-finite dL_dQ");
-  if ((h->mc.open_x && !h->mc.exact_density) || h->sk != SK_NATIVE)
-    return set_err(h, LBM_E_UNSUPPORTED,
-                   "adjoint_flux: periodic x faces or exact density faces, and native storage only");
+  if (h->sk != SK_NATIVE)
+    return set_err(h, LBM_E_UNSUPPORTED, "adjoint_flux: native fp64 or fp32 storage only");
   if (!h->has_geom || !h->has_fluid) return set_err(h, LBM_E_STATE, "adjoint_flux: no fluid state");
   // the sweeps keep whole population sets (checkpoints, ring): dense layout
   // for their duration

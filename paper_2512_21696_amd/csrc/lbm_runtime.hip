@@ -48,6 +48,10 @@ struct lbm_handle {
   size_t es = 8;   // arithmetic type size
   size_t pes = 8;  // stored population size
   int sk = SK_NATIVE;
+  // pressure reservoirs under the adjoint's forward sweep: when set, every
+  // step records its boundary voxels' densities and velocities here (8 ny nz
+  // doubles, k_res_record) and advances the pointer
+  double *res_rec = nullptr;
   // 16-bit runs: f[0] holds the decode of the stored set; fluid-only layout:
   // f[1 - cur] holds its dense copy
   bool dec_valid = false;
@@ -793,6 +797,42 @@ void launch_flux(lbm_handle *h, double *out, int accumulate) {
                      accumulate);
 }
 
+// Pressure reservoirs, for the adjoint: the density and mixture velocity of
+// each (y, z) row's two boundary voxels' post-collision sets, computed as
+// k_reservoirs computes them (same type, same order) before it overwrites the
+// slots leaving the domain.  rec[8 k + 4 e] = rho (0 for a solid voxel) and
+// rec[8 k + 4 e + 1 + d] = u_d, e = 0 at x = 0 and 1 at x = nx - 1.
+template <typename T, int NC>
+__global__ __launch_bounds__(256) void k_res_record(const ModelConsts mc,
+                                                    const T *__restrict__ post,
+                                                    const uint32_t *__restrict__ mask,
+                                                    double *__restrict__ rec) {
+  const long long N = mc.N;
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= mc.ny * mc.nz) return;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    const long long vb = (long long)k * mc.nx + (e == 0 ? 0 : mc.nx - 1);
+    const bool fluid = ((mask[vb] >> CLASS_SHIFT) & 3u) != SOLID_CODE;
+    T rho = 0, m0 = 0, m1 = 0, m2 = 0;
+    for (int a = 0; a < NC; ++a)
+#pragma unroll
+      for (int i = 0; i < Q; ++i) {
+        const T f = post[(size_t)(a * Q + i) * N + vb];
+        rho += f;
+        m0 += (T)cx(i) * f;
+        m1 += (T)cy(i) * f;
+        m2 += (T)cz(i) * f;
+      }
+    const T ir = fluid ? (T)1 / rho : (T)0;
+    double *const o = rec + 8LL * k + 4 * e;
+    o[0] = fluid ? (double)rho : 0.0;
+    o[1] = (double)(m0 * ir);
+    o[2] = (double)(m1 * ir);
+    o[3] = (double)(m2 * ir);
+  }
+}
+
 template <typename T>
 int step_t(lbm_handle *h, int64_t n, bool allow_push) {
   DevState<T> &s = state<T>(h);
@@ -816,6 +856,15 @@ int step_t(lbm_handle *h, int64_t n, bool allow_push) {
                            s.f[h->cur], s.mask);
     } else if (h->mc.open_x) {
       Timed tm(h, K_OTHER);
+      if (h->res_rec) {
+        if (h->p.ncomp == 2)
+          hipLaunchKernelGGL((k_res_record<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc,
+                             s.f[h->cur], s.mask, h->res_rec);
+        else
+          hipLaunchKernelGGL((k_res_record<T, 1>), dim3(fb), dim3(256), 0, h->st, h->mc,
+                             s.f[h->cur], s.mask, h->res_rec);
+        h->res_rec += (size_t)8 * h->p.ny * h->p.nz;
+      }
       if (h->p.ncomp == 2)
         hipLaunchKernelGGL((k_reservoirs<T, 2>), dim3(fb), dim3(256), 0, h->st, h->mc, s.f[h->cur],
                            s.mask);

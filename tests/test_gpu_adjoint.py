@@ -137,27 +137,13 @@ def test_adjoint_rejects_unsupported_runs():
         lb.adjoint_flux(3, np.ones(3), checkpoint_every=-1)
     assert ei.value.code == L.LBM_E_INVAL
     lb.destroy()
-    # open x faces with reservoirs have no adjoint (exact density faces with
-    # one component do)
-    p = W.Params(nx=16, ny=6, nz=4, ncomp=1, tau=(0.8, 0.8), G=0.0, kappa=0.0,
-                 bc_x="pressure", rho_in=(1.01, 0.0), rho_out=(1.0, 0.0)).filled()
-    shape = (4, 6, 16)
-    tabs = [W.pore_table(W.kozeny_carman_table(2.0), *W.brooks_corey_tables(0.05, 2.0, 0.1),
-                         phi_ref=0.225, pc_pm=0.05)]
-    lb = L.lbm_create(p)
-    lb.set_geometry(np.zeros(shape, np.uint8), np.ones(shape), np.zeros(shape, np.uint8), tabs)
-    lb.init_fluid(np.ones(shape))
-    with pytest.raises(L.LbmError) as ei:
-        lb.adjoint_flux(2, np.ones(2))
-    assert ei.value.code == L.LBM_E_UNSUPPORTED
-    lb.destroy()
 
 
-def faces_case(precision="f64", seed=23):
-    """One component between exact density faces (70 x 9 x 6, ragged x tile): a
-    gray band x = 20..49 with solid grains, no body force; the flow is driven by
-    the faces' densities, so the gradient reaches the gray voxels only through
-    the face step."""
+def faces_case(precision="f64", seed=23, bc="density"):
+    """One component between open x faces (exact density faces or pressure
+    reservoirs; 70 x 9 x 6, ragged x tile): a gray band x = 20..49 with solid
+    grains, no body force; the flow is driven by the faces' densities, so the
+    gradient reaches the gray voxels only through the face step."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = 6, 9, 70
     r = rng.random((nz, ny, nx))
@@ -170,21 +156,25 @@ def faces_case(precision="f64", seed=23):
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
             for lam in (1.0, 2.0)]
     p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=1, tau=(0.8, 0.8), G=0.0, precision=precision,
-                 kappa=0.0, bc_x="density", rho_in=(1.01, 0.0), rho_out=(0.99, 0.0),
+                 kappa=0.0, bc_x=bc, rho_in=(1.01, 0.0), rho_out=(0.99, 0.0),
                  outlet_x=60).filled()
     rho = 1.0 + 0.01 * rng.standard_normal(cls.shape)
     return dict(params=p, cls=cls, phi=phi, ptype=pt, tables=tabs, rho=rho)
 
 
+@pytest.mark.parametrize("bc", ["density", "pressure"])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-10), ("f32", 2e-4)])
-def test_adjoint_with_density_faces_matches_oracle(precision, tol):
-    """Exact density faces with one component: the reverse sweep runs the
-    transpose of the face step on the adjoint of every level."""
-    announce(f"adjoint with density faces 70x9x6 {precision}, 40 steps, checkpoints every 15")
-    c = faces_case(precision)
+def test_adjoint_with_open_faces_matches_oracle(precision, tol, bc):
+    """Open x faces with one component: the reverse sweep runs the transpose
+    of the face step (exact density faces, or pressure reservoirs with the
+    boundary velocities the forward recorded) on the adjoint of every level;
+    40 steps in three segments, so recomputed levels and kept ones both
+    meet it."""
+    announce(f"adjoint with {bc} faces 70x9x6 {precision}, 40 steps, checkpoints every 15")
+    c = faces_case(precision, bc=bc)
     steps = 40
     a = np.linspace(1.0, 2.0, steps)
-    qo, go = oracle_gradient(faces_case("f64"), steps, a)
+    qo, go = oracle_gradient(faces_case("f64", bc=bc), steps, a)
     lb = gpu_handle(c)
     out = lb.adjoint_flux(steps, a, checkpoint_every=15)
     lb.destroy()
@@ -192,7 +182,7 @@ def test_adjoint_with_density_faces_matches_oracle(precision, tol):
     assert np.count_nonzero(go[gray]) > 0.25 * gray.sum()
     assert np.abs(out["Q"] - qo).max() < (1e-13 if precision == "f64" else 1e-5)
     e = norm_err(out["dL_dphi"], go)
-    print(f"{precision} dL/dphi normalised error {e:.2e}")
+    print(f"{bc} faces {precision} dL/dphi normalised error {e:.2e}")
     assert e < tol
 
 
@@ -412,16 +402,18 @@ def test_two_component_adjoint_matches_oracle(collision, tensor):
     assert e < 1e-9
 
 
+@pytest.mark.parametrize("bc", ["density", "pressure"])
 @pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-3)])
-def test_two_component_adjoint_with_density_faces_matches_oracle(precision, tol):
-    """Water entering at x = 0 against oil held at x = nx - 1 between exact
-    density faces (70 x 8 x 6: a ragged x tile), grains and gray voxels two
-    planes away from both faces, 12 steps without residual events: the face
-    transpose on both components, the zeroed density adjoint of the face
-    voxels, and the reservoir cells as constants in the pseudo-potential
-    reverse."""
+def test_two_component_adjoint_with_open_faces_matches_oracle(precision, tol, bc):
+    """Water entering at x = 0 against oil held at x = nx - 1 between open x
+    faces (70 x 8 x 6: a ragged x tile), grains and gray voxels two planes away
+    from both faces, 12 steps without residual events: the face transpose on
+    both components (exact density faces: with the zeroed density adjoint of
+    the face voxels; pressure reservoirs: through the mixture velocity of both
+    components, with the pullers' density adjoint), and the reservoir cells as
+    constants in the pseudo-potential reverse."""
     import paper_2512_21696_amd as L
-    announce(f"two-component adjoint with density faces 70x8x6 {precision}")
+    announce(f"two-component adjoint with {bc} faces 70x8x6 {precision}")
     rng = np.random.default_rng(29)
     nz, ny, nx = 6, 8, 70
     r = rng.random((nz, ny, nx))
@@ -437,7 +429,7 @@ def test_two_component_adjoint_with_density_faces_matches_oracle(precision, tol)
 
     def params(prec):
         return W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
-                        precision=prec, bc_x="density", rho_in=(1.02, m), rho_out=(m, 1.0),
+                        precision=prec, bc_x=bc, rho_in=(1.02, m), rho_out=(m, 1.0),
                         outlet_x=40).filled()
     x = np.arange(nx)[None, None, :]
     noise = 0.005 * rng.random(cls.shape)
@@ -459,7 +451,7 @@ def test_two_component_adjoint_with_density_faces_matches_oracle(precision, tol)
     assert np.count_nonzero(go[gray]) > 0.25 * gray.sum()
     assert np.abs(out["Q"] - qo).max() < (1e-12 if precision == "f64" else 1e-4)
     e = norm_err(out["dL_dphi"], go)
-    print(f"{precision} two-component dL/dphi with density faces normalised error {e:.2e}")
+    print(f"{precision} two-component dL/dphi with {bc} faces normalised error {e:.2e}")
     assert e < tol
 
 
