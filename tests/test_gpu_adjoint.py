@@ -402,18 +402,12 @@ def test_two_component_adjoint_matches_oracle(collision, tensor):
     assert e < 1e-9
 
 
-@pytest.mark.parametrize("bc", ["density", "pressure"])
-@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-3)])
-def test_two_component_adjoint_with_open_faces_matches_oracle(precision, tol, bc):
+def two_faces_case(bc, precision="f64"):
     """Water entering at x = 0 against oil held at x = nx - 1 between open x
     faces (70 x 8 x 6: a ragged x tile), grains and gray voxels two planes away
-    from both faces, 12 steps without residual events: the face transpose on
-    both components (exact density faces: with the zeroed density adjoint of
-    the face voxels; pressure reservoirs: through the mixture velocity of both
-    components, with the pullers' density adjoint), and the reservoir cells as
-    constants in the pseudo-potential reverse."""
-    import paper_2512_21696_amd as L
-    announce(f"two-component adjoint with {bc} faces 70x8x6 {precision}")
+    from both faces, the outlet plane 64 | 65 five planes from the far face, so
+    that within 12 steps the flux depends on gray voxels through the face step.
+    Returns (params, cls, phi, ptype, tables, rho_w, rho_o, steps)."""
     rng = np.random.default_rng(29)
     nz, ny, nx = 6, 8, 70
     r = rng.random((nz, ny, nx))
@@ -426,29 +420,39 @@ def test_two_component_adjoint_with_open_faces_matches_oracle(precision, tol, bc
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, lam, 0.1), phi_ref=0.225, pc_pm=0.05)
             for lam in (1.0, 2.0)]
     m = W.minority_density(3.0)
-
-    def params(prec):
-        return W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
-                        precision=prec, bc_x=bc, rho_in=(1.02, m), rho_out=(m, 1.0),
-                        outlet_x=40).filled()
+    p = W.Params(nx=nx, ny=ny, nz=nz, ncomp=2, tau=(0.8, 1.2), G=3.0, kappa=0.0,
+                 precision=precision, bc_x=bc, rho_in=(1.02, m), rho_out=(m, 1.0),
+                 outlet_x=64).filled()
     x = np.arange(nx)[None, None, :]
     noise = 0.005 * rng.random(cls.shape)
     rw = np.where(x < 10, 1.0 - noise, m + noise)
-    ro = 1.0 + m - rw
-    steps = 12
+    return p, cls, phi, pt, tabs, rw, 1.0 + m - rw, 12
+
+
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+@pytest.mark.parametrize("precision,tol", [("f64", 1e-9), ("f32", 1e-3)])
+def test_two_component_adjoint_with_open_faces_matches_oracle(precision, tol, bc):
+    """Two components between open x faces (two_faces_case), 12 steps without
+    residual events: the face transpose on both components (exact density
+    faces: with the zeroed density adjoint of the face voxels; pressure
+    reservoirs: through the mixture velocity of both components, with the
+    pullers' density adjoint), and the reservoir cells as constants in the
+    pseudo-potential reverse."""
+    import paper_2512_21696_amd as L
+    announce(f"two-component adjoint with {bc} faces 70x8x6 {precision}")
+    p64, cls, phi, pt, tabs, rw, ro, steps = two_faces_case(bc)
     a = np.linspace(1.0, 2.0, steps)
-    p64 = params("f64")
     o = Oracle(p64)
     o.set_geometry(cls, phi, pt, tabs)
     o.init_fluid(rw, ro)
     qo, go, _ = A.flux_gradient2(p64, cls, phi, pt, tabs, o.f.copy(), o.r.copy(), steps, a)
-    lb = L.lbm_create(params(precision))
+    lb = L.lbm_create(two_faces_case(bc, precision)[0])
     lb.set_geometry(cls, phi, pt, tabs)
     lb.init_fluid(rw, ro)
     out = lb.adjoint_flux(steps, a, checkpoint_every=5)
     lb.destroy()
     gray = cls == 2
-    assert np.count_nonzero(go[gray]) > 0.25 * gray.sum()
+    assert np.count_nonzero(go[gray]) > 0.1 * gray.sum()
     assert np.abs(out["Q"] - qo).max() < (1e-12 if precision == "f64" else 1e-4)
     e = norm_err(out["dL_dphi"], go)
     print(f"{precision} two-component dL/dphi with {bc} faces normalised error {e:.2e}")

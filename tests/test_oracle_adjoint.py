@@ -4,10 +4,12 @@ autograd gradient of L = sum_n a_n Q(n) with respect to the gray porosity
 matches central finite differences of model.Oracle itself."""
 import numpy as np
 import pytest
+import torch
 
 import workloads as W
 from oracle import Oracle
 from oracle import adjoint as A
+from oracle.lattice import C, Q
 
 
 def case(collision="regularized", seed=5):
@@ -434,3 +436,57 @@ def test_two_component_gradient_with_open_faces_matches_finite_differences(bc):
         if checked == 3:
             break
     assert checked == 3
+
+
+def _faces_as_constants(monkeypatch):
+    """Plants a mistake in the reference gradient: the populations the face
+    step writes (the slots across the periodic wrap) are taken as constants."""
+    orig_r, orig_d = A.OneComponent._reservoirs, A.OneComponent._density_faces
+
+    def written(self, like):
+        m = torch.zeros_like(like, dtype=torch.bool)
+        for i in range(Q):
+            if C[i, 0] > 0:
+                m[i, :, :, -1] = True
+            elif C[i, 0] < 0:
+                m[i, :, :, 0] = True
+        return m
+
+    def res(self, posts):
+        return [torch.where(written(self, o), o.detach(), o) for o in orig_r(self, posts)]
+
+    def den(self, post, a):
+        o = orig_d(self, post, a)
+        return torch.where(written(self, o), o.detach(), o)
+    monkeypatch.setattr(A.OneComponent, "_reservoirs", res)
+    monkeypatch.setattr(A.OneComponent, "_density_faces", den)
+
+
+@pytest.mark.parametrize("bc", ["density", "pressure"])
+def test_gpu_face_cases_depend_on_the_face_step(bc, monkeypatch):
+    """The GPU adjoint's open-face parity cases (faces_case and two_faces_case
+    of test_gpu_adjoint) reach gray voxels through the face step within their
+    step counts: with the face-written populations taken as constants the
+    reference gradient moves by more than ten times those tests' fp32
+    tolerances (2e-4 and 1e-3), so a GPU face transpose that dropped its
+    dependence would fail them."""
+    from test_gpu_adjoint import faces_case, two_faces_case, oracle_gradient
+
+    def ne(x, ref):
+        return np.abs(x - ref).max() / np.abs(ref).max()
+    c = faces_case("f64", bc=bc)
+    a = np.linspace(1.0, 2.0, 40)
+    g = oracle_gradient(c, 40, a)[1]
+    p, cls, phi, pt, tabs, rw, ro, steps = two_faces_case(bc)
+    o = Oracle(p)
+    o.set_geometry(cls, phi, pt, tabs)
+    o.init_fluid(rw, ro)
+    a2 = np.linspace(1.0, 2.0, steps)
+    g2 = A.flux_gradient2(p, cls, phi, pt, tabs, o.f.copy(), o.r.copy(), steps, a2)[1]
+    gray = cls == 2
+    assert np.count_nonzero(g2[gray]) > 0.1 * gray.sum()
+    _faces_as_constants(monkeypatch)
+    d1 = ne(oracle_gradient(c, 40, a)[1], g)
+    d2 = ne(A.flux_gradient2(p, cls, phi, pt, tabs, o.f.copy(), o.r.copy(), steps, a2)[1], g2)
+    print(f"{bc}: planted-mistake change {d1:.2e} (one component), {d2:.2e} (two)")
+    assert d1 > 10 * 2e-4 and d2 > 10 * 1e-3
