@@ -120,9 +120,13 @@ __global__ __launch_bounds__(256) void k_adj_density_faces(const ModelConsts mc,
 // components, that puller's rnl (the adjoint of its next density, which the
 // reverse step adds to each of its pulls): a zeroed slot takes -rnl.  Both
 // ends' dL/du are taken before any value gets its share, since each end's
-// written slots are values of the other end.  One thread per (y, z) row; it
-// touches only the entries of its row's two boundary voxels, so rows do not
-// overlap.
+// written slots are values of the other end.  A written slot whose puller is
+// solid has no reader and adds nothing; its entry is cleared, because it can
+// hold the share a fluid boundary voxel across the face gave it two reverse
+// steps earlier (the two adjoint sets alternate and the reverse step never
+// writes a solid voxel's entries), and then gets this step's share, which the
+// boundary voxel's gather reads there.  One thread per (y, z) row; it touches
+// only the entries of its row's two boundary voxels, so rows do not overlap.
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_reservoirs(const ModelConsts mc,
                                                         T *__restrict__ lam,
@@ -149,6 +153,10 @@ __global__ __launch_bounds__(256) void k_adj_reservoirs(const ModelConsts mc,
         const int yy = (y + cy(i) + ny) % ny, zz = (z + cz(i) + nz) % nz;
         const long long w = xp + (long long)nx * (yy + (long long)ny * zz);
         T *const li = lam + ((size_t)a * Q + i) * N + w;
+        if (((mask[w] >> CLASS_SHIFT) & 3u) == SOLID_CODE) {
+          *li = (T)0;  // no reader; the entry may hold a value left two steps back
+          continue;
+        }
         const T rn = rnl ? rnl[2 * w + a] : (T)0;
         const double pb = (double)*li + (double)rn;
         const double cu = cx(i) * u[0] + cy(i) * u[1] + cz(i) * u[2];

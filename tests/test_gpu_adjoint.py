@@ -142,7 +142,7 @@ def test_adjoint_rejects_unsupported_runs():
 def faces_case(precision="f64", seed=23, bc="density"):
     """One component between open x faces (exact density faces or pressure
     reservoirs; 70 x 9 x 6, ragged x tile): a gray band x = 20..49 with solid
-    grains, no body force; the flow is driven by the faces' densities, so the
+    grains, grains on and next to both face planes, no body force; the flow is driven by the faces' densities, so the
     gradient reaches the gray voxels only through the face step."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = 6, 9, 70
@@ -150,6 +150,10 @@ def faces_case(precision="f64", seed=23, bc="density"):
     cls = np.zeros((nz, ny, nx), np.uint8)
     band = (slice(None), slice(None), slice(20, 50))
     cls[band] = np.where(r[band] < 0.6, 2, np.where(r[band] > 0.92, 1, 0))
+    # solid grains on the face planes and next to them (solid boundary voxels,
+    # solid links of fluid ones)
+    for x in (0, 1, nx - 2, nx - 1):
+        cls[:, :, x] = np.where(r[:, :, x] < 0.15, 1, 0)
     phi = np.where(cls == 2, rng.uniform(0.05, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
     pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
     K0 = W.kozeny_carman_table(2.0)
@@ -404,16 +408,17 @@ def test_two_component_adjoint_matches_oracle(collision, tensor):
 
 def two_faces_case(bc, precision="f64"):
     """Water entering at x = 0 against oil held at x = nx - 1 between open x
-    faces (70 x 8 x 6: a ragged x tile), grains and gray voxels two planes away
-    from both faces, the outlet plane 64 | 65 five planes from the far face, so
+    faces (70 x 8 x 6: a ragged x tile), grains everywhere (face planes
+    included), gray voxels two planes away from both faces, the outlet plane 64 | 65 five planes from the far face, so
     that within 12 steps the flux depends on gray voxels through the face step.
     Returns (params, cls, phi, ptype, tables, rho_w, rho_o, steps)."""
     rng = np.random.default_rng(29)
     nz, ny, nx = 6, 8, 70
     r = rng.random((nz, ny, nx))
     cls = np.where(r < 0.12, 1, np.where(r < 0.45, 2, 0)).astype(np.uint8)
-    cls[:, :, :2] = 0
-    cls[:, :, -2:] = 0
+    # no gray voxel within two planes of a face; grains there stay
+    cls[:, :, :2] = np.where(cls[:, :, :2] == 1, 1, 0)
+    cls[:, :, -2:] = np.where(cls[:, :, -2:] == 1, 1, 0)
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
     pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
     K0 = W.kozeny_carman_table(2.0)

@@ -316,14 +316,16 @@ def test_two_component_with_residual_events(kappa, region):
 
 def faces_case(seed=11, bc="density"):
     """One component between open x faces (exact density faces or pressure
-    reservoirs): a gray slab (x = 4..6) with solid grains, no body force, the
-    flow driven by rho_in > rho_out."""
+    reservoirs): a gray slab (x = 4..6) with solid grains, grains on and next
+    to both face planes, no body force, the flow driven by rho_in > rho_out."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = 4, 6, 11
     cls = np.zeros((nz, ny, nx), np.uint8)
     r = rng.random((nz, ny, nx))
     cls[:, :, 4:7] = np.where(r[:, :, 4:7] < 0.7, 2, 0)
     cls[:, :, 2:9] = np.where(r[:, :, 2:9] > 0.9, 1, cls[:, :, 2:9])
+    for x in (0, 1, nx - 2, nx - 1):  # grains on and next to the face planes
+        cls[:, :, x] = np.where(r[:, :, x] > 0.85, 1, 0)
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
     K0 = W.kozeny_carman_table(2.0)
     tabs = [W.pore_table(K0, *W.brooks_corey_tables(0.05, 2.0, 0.1), phi_ref=0.3, pc_pm=0.05)]
@@ -375,14 +377,15 @@ def two_faces_case(seed=13, bc="density"):
     """Two components between open x faces (exact density faces or pressure
     reservoirs; 22 x 8 x 6): water enters at
     x = 0 (rho_in = (1.02, m)) against oil held at x = nx - 1 (rho_out =
-    (m, 1.0)); grains and gray voxels (two pore types) keep two planes away
+    (m, 1.0)); grains everywhere (face planes included), gray voxels (two pore
+    types) two planes away
     from both faces; no body force, kappa = 0."""
     rng = np.random.default_rng(seed)
     nz, ny, nx = 6, 8, 22
     r = rng.random((nz, ny, nx))
     cls = np.where(r < 0.15, 1, np.where(r < 0.5, 2, 0)).astype(np.uint8)
-    cls[:, :, :2] = 0
-    cls[:, :, -2:] = 0
+    cls[:, :, :2] = np.where(cls[:, :, :2] == 1, 1, 0)  # grains stay, no gray
+    cls[:, :, -2:] = np.where(cls[:, :, -2:] == 1, 1, 0)
     phi = np.where(cls == 2, rng.uniform(0.1, 0.4, cls.shape), np.where(cls == 0, 1.0, 0.0))
     pt = np.where(cls == 2, rng.integers(0, 2, cls.shape), 0).astype(np.uint8)
     K0 = W.kozeny_carman_table(2.0)
