@@ -223,16 +223,35 @@ def _fd_history(L, wl, phi, steps):
     return q
 
 
-def test_fullsize_gradient_against_gpu_finite_differences():
+def _with_reservoirs(wl):
+    """The workload between pressure reservoirs (densities 1 +- 5e-4 besides
+    the body force); gray voxels within two planes of a face become pore."""
+    p = wl["params"]
+    p.bc_x = "pressure"
+    p.rho_in = (1.0005, 0.0)
+    p.rho_out = (0.9995, 0.0)
+    cls, phi = wl["cls"].copy(), wl["phi"].copy()
+    near = np.zeros(cls.shape, bool)
+    near[:, :, :2] = near[:, :, -2:] = True
+    phi[near & (cls == 2)] = 1.0
+    cls[near & (cls == 2)] = 0
+    return dict(wl, params=p, cls=cls, phi=phi)
+
+
+@pytest.mark.parametrize("bc", ["periodic", "pressure"])
+def test_fullsize_gradient_against_gpu_finite_differences(bc):
     """96^3 from the multiscale-rock generator, one component, fp64, 800 steps,
-    squared misfit over steps 200..800, checkpoints every 50: the adjoint's
-    dL/dphi against central differences (eps = 1e-4, a tenth of a table cell)
-    of the GPU forward run on 3 of the largest-gradient gray voxels and 3
-    random gray voxels (seed 5003), none within reach of a table knot."""
+    squared misfit over steps 200..800, checkpoints every 50, periodic or
+    between pressure reservoirs: the adjoint's dL/dphi against central
+    differences (eps = 1e-4, a tenth of a table cell) of the GPU forward run
+    on 3 of the largest-gradient gray voxels and 3 random gray voxels (seed
+    5003), none within reach of a table knot."""
     import paper_2512_21696_amd as L
     wl = W.adjoint_rock(n=96, precision="f64")
+    if bc == "pressure":
+        wl = _with_reservoirs(wl)
     steps = wl["steps"]
-    announce(f"adjoint_rock 96^3 fp64 {steps} steps: base run")
+    announce(f"adjoint_rock 96^3 fp64 {bc} {steps} steps: base run")
     q0 = _fd_history(L, wl, wl["phi"], steps)
     tgt = wl["target"](q0)
     _, dLdQ = wl["loss_grad"](q0, tgt)
