@@ -1908,6 +1908,13 @@ int adjoint_t(lbm_handle *h, int64_t n, const double *dLdQ, int64_t K, double *Q
   if (!ok) return finish(set_err(h, LBM_E_NOMEM, "device allocation failed in adjoint_flux"));
   const unsigned fb = blocks((long long)h->p.ny * h->p.nz);
   int rc = LBM_OK;
+  // the step stores nothing for a wave of solid voxels, so the ring's slots
+  // of those voxels keep what the allocation held; the reservoirs read a solid
+  // boundary voxel's set (its velocity is m * 0), so with them the ring starts
+  // at zero, like the handle's own sets
+  if (resv && ring)
+    rc = hip_check(h, hipMemsetAsync(ring, 0, (size_t)(K - 1) * SN * sizeof(T), h->st),
+                   "clear the ring");
   const size_t RB = (size_t)2 * N * sizeof(T);  // residual amounts of one level
   auto copy_rs = [&](T *rdst, uint8_t *sdst, const T *rsrc, const uint8_t *ssrc) {
     int e = hip_check(h, hipMemcpyAsync(rdst, rsrc, RB, hipMemcpyDeviceToDevice, h->st),

@@ -286,16 +286,20 @@ def test_fullsize_gradient_against_gpu_finite_differences(bc):
         assert abs(g[v] - fd) <= 1e-3 * abs(fd) + 1e-6 * gmax, (v, g[v], fd)
 
 
-def test_fullsize_fp32_gradient_against_fp64():
-    """The same 96^3 / 800-step gradient from fp32 storage (the benchmarked
-    configuration) against fp64 storage (held to finite differences above):
-    the fp32 run's flux history and gradient carry the fp32 forward's drift."""
+@pytest.mark.parametrize("bc", ["periodic", "pressure"])
+def test_fullsize_fp32_gradient_against_fp64(bc):
+    """The same 96^3 / 800-step gradient (periodic, or between the pressure
+    reservoirs above) from fp32 storage (the benchmarked configuration)
+    against fp64 storage (held to finite differences above): the fp32 run's
+    flux history and gradient carry the fp32 forward's drift."""
     import paper_2512_21696_amd as L
     res = {}
     for prec in ("f64", "f32"):
         wl = W.adjoint_rock(n=96, precision=prec)
+        if bc == "pressure":
+            wl = _with_reservoirs(wl)
         steps = wl["steps"]
-        announce(f"adjoint_rock 96^3 {prec} {steps} steps")
+        announce(f"adjoint_rock 96^3 {prec} {bc} {steps} steps")
         lb = L.lbm_create(wl["params"])
         lb.set_geometry(wl["cls"], wl["phi"], wl["ptype"], wl["tables"])
         lb.init_fluid(wl["rho_w"])
@@ -309,7 +313,7 @@ def test_fullsize_fp32_gradient_against_fp64():
         lb.destroy()
     eq = norm_err(res["f32"]["Q"], res["f64"]["Q"])
     eg = norm_err(res["f32"]["dL_dphi"], res["f64"]["dL_dphi"])
-    print(f"fp32 vs fp64: flux history {eq:.2e}, dL/dphi {eg:.2e}")
+    print(f"{bc} fp32 vs fp64: flux history {eq:.2e}, dL/dphi {eg:.2e}")
     # Q is a net sum of ~2e4 link populations of size ~w_i, ~1e-2 of their sum:
     # the fp32 forward's drift over 800 steps (1e-5 relative in the fields)
     # shows at a few 1e-4 in it; the gradient is of the same order
